@@ -1,0 +1,232 @@
+/*
+ * libmwalk — floating-random-walk (FRW) capacitance extraction whose
+ * transitions inside non-stratified dielectric cubes use MicroWalk
+ * (Huang & Yu, "Efficient FRW Transitions via Stochastic Finite Differences
+ * for Handling Non-Stratified Dielectrics", arXiv 2507.09730).
+ *
+ * C ABI of the MI355X (gfx950) library. Conventions for every entry point:
+ *   - Every call returns an mw_status: 0 on success, a negative code on error.
+ *     No C++ exception crosses this boundary.  mw_last_error() returns a
+ *     thread-local, NUL-terminated message describing the last failure of the
+ *     calling thread (empty string after a success).
+ *   - Outputs are written only on success (device outputs of stream-ordered
+ *     calls: only by kernels that the call enqueued after validation).
+ *   - The caller owns every array passed in or out.  The library copies what
+ *     it keeps (structures, request descriptions) and never frees caller
+ *     memory.
+ *   - "device" pointers are HIP device allocations on the current device;
+ *     "host" pointers are ordinary host memory.  `stream` is a hipStream_t
+ *     (NULL = the legacy default stream); stream-ordered calls enqueue their
+ *     kernels there and return without waiting, unless stated otherwise.
+ *   - Lengths are in micrometres, permittivities are relative (eps0 is
+ *     applied inside), capacitances are in femtofarads.
+ *   - Validation rejects, before any device work: relative permittivities
+ *     outside [1e-3, 1e3]; lattice sizes outside [2, 64] (vertex lattice: even
+ *     n, cell lattice: odd n); null pointers where a buffer is required.
+ *
+ * Random numbers (shared contract with any reimplementation): every random
+ * 32-bit word is one output word of Philox4x32-10 (Salmon, Moraes, Dror &
+ * Shaw, SC'11) with key = (seed & 0xffffffff, seed >> 32) and counter
+ *   c0 = s >> 2            (s = running index of the word within the stream)
+ *   c1 = hop index t (FRW) or cube index (transition APIs)
+ *   c2 = walk & 0xffffffff
+ *   c3 = ((walk >> 32) & 0xffffff) | (purpose << 24)
+ * taking output word s & 3.  Purposes: 0 MicroWalk step, 1 Gaussian-surface
+ * sample, 2 first-transition sample, 3 stratified-table sample.
+ */
+#ifndef LIBMWALK_H
+#define LIBMWALK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mw_status;
+#define MW_OK 0
+#define MW_EINVAL (-1)    /* bad argument                                  */
+#define MW_ENOMEM (-2)    /* device or host allocation failed              */
+#define MW_EDEVICE (-3)   /* HIP runtime error                             */
+#define MW_EBUSY (-4)     /* server queue full                             */
+#define MW_ENOTREADY (-5) /* server result not ready yet                   */
+#define MW_EGEOM (-6)     /* invalid geometry                              */
+#define MW_ELIMIT (-7)    /* a documented capacity limit was exceeded      */
+
+/* Finite-difference lattice of a transition cube with n cells per axis.
+ * MW_LATTICE_VERTEX: nodes at cell corners, (n+1)^3 nodes, (n-1)^3 interior
+ *   unknowns, start node (n/2,n/2,n/2) (n even).  Link probability of a
+ *   direction is proportional to the sum of the four cell codes around the
+ *   link (finite-volume face permittivity; equal to the normalised
+ *   coefficients of Eq. (6) written for this node placement).
+ * MW_LATTICE_CELL: nodes at voxel centres as in Sec. III-A (Fig. 2), N^3
+ *   interior nodes plus 6N^2 boundary panel nodes, coefficients of Eq. (6)
+ *   verbatim, start node ((N-1)/2, ...) (N odd).                             */
+#define MW_LATTICE_VERTEX 0
+#define MW_LATTICE_CELL 1
+
+/* Boundary condition of each window face, order -x,+x,-y,+y,-z,+z. */
+#define MW_BC_DIRICHLET 0 /* grounded enclosure: absorbs walks into "env" */
+#define MW_BC_NEUMANN 1   /* mirror symmetry plane                        */
+
+const char* mw_last_error(void);
+
+/* Selects the HIP device used by subsequent calls of this thread and
+ * initialises per-device state.  Optional: the first call on a device does it. */
+mw_status mw_init(int32_t device);
+
+/* ------------------------------------------------------------------------
+ * mw_transition — Alg. 3 (MicroWalk) on one voxelised transition cube.
+ *
+ * Runs n_walks independent micro-walks from the cube's start node until each
+ * reaches a boundary node (Alg. 3; Theorem 1 makes the hit distribution equal
+ * to the discrete SGF P_eps = e_c^T A_II^-1 A_IB of Eq. (8)).  Walk w (for w
+ * in [first_walk, first_walk + n_walks)) uses Philox words of purpose 0 with
+ * c1 = cube_index; step s consumes word s.  The direction of a step is
+ * d = #{k in 0..4 : u >= T_k}, with T_k = ceil(S_k * 2^32 / S_5) and S_k the
+ * prefix sums of the six integer link codes in direction order
+ * -x,+x,-y,+y,-z,+z.  Cell codes: vertex lattice e = rint(eps * 2^16);
+ * cell lattice link code rint(eps_i / (eps_i + eps_v) * 2^24) to an interior
+ * neighbour and 2^24 to a boundary panel (Eq. 6), both in binary64.
+ *
+ * eps        device, n^3 floats, cell (i,j,k) at eps[(k*n + j)*n + i].
+ * n_cells    n: 2..64, even for the vertex lattice, odd for the cell lattice.
+ * hit_idx    device, n_walks int32: boundary hit index.  Vertex lattice:
+ *            f*M^2 + (b-1)*M + (a-1), M = n-1; cell lattice: f*N^2 + b*N + a;
+ *            f = 2*axis + side (side 1 = the +axis face), (a, b) the two
+ *            other node coordinates in ascending axis order.  -1 if the walk
+ *            exceeded 2^30 steps (cannot happen for valid permittivities).
+ * steps      device, n_walks int32 step counts tau, or NULL.
+ * Stream-ordered.                                                          */
+mw_status mw_transition(const float* eps, int32_t n_cells, int32_t lattice,
+                        uint64_t n_walks, uint64_t first_walk, uint64_t seed,
+                        uint32_t cube_index, int32_t* hit_idx, int32_t* steps,
+                        void* stream);
+
+/* Tuning knobs of the batched MicroWalk launch.  Zero fields mean "use the
+ * autotuned or default value". */
+typedef struct {
+    int32_t tile_form;    /* 1 threshold rows in LDS, 2 cell-code tile in LDS */
+    int32_t waves_per_wg; /* 1..16                                          */
+    int32_t refill_every; /* steps between lane refills: 4, 8 or 16         */
+    int32_t item_walks;   /* walks per (cube, walk-range) work item         */
+} mw_tune;
+
+/* ------------------------------------------------------------------------
+ * mw_transition_batch — many cubes of uneven size in one persistent launch.
+ *
+ * Cube c (0 <= c < n_cubes) has n_cells[c] cells per axis, its eps grid at
+ * eps_cat + eps_off[c] (device, layout as mw_transition) and runs n_walks[c]
+ * walks 0..n_walks[c]-1 with Philox c1 = c.  Its hits (and steps) go to
+ * hits_cat + out_off[c] (device).  Results are bit-identical to calling
+ * mw_transition(eps_c, n_c, lattice, n_walks[c], 0, seed, c, ...) per cube,
+ * for every tuning.  eps_off, n_cells, n_walks, out_off are host arrays.
+ * tune may be NULL (autotuned per lattice size; see mw_autotune).
+ * Stream-ordered; the host arrays may be reused once the call returns.      */
+mw_status mw_transition_batch(int32_t n_cubes, const float* eps_cat,
+                              const int64_t* eps_off, const int32_t* n_cells,
+                              int32_t lattice, const uint64_t* n_walks,
+                              const int64_t* out_off, uint64_t seed,
+                              int32_t* hits_cat, int32_t* steps_cat,
+                              const mw_tune* tune, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Geometry (Alg. 1 input: a 3-D structure of conductors and dielectrics).
+ *
+ * Conductor boxes are half-open [lo, hi) per axis and belong to nets
+ * 0..n_nets-1; every net owns exactly one box.  Dielectric boxes override the
+ * background; a later box wins where boxes overlap.  The background is a
+ * stack of layers in z: layer l covers z in [layer_z0[l], layer_z0[l+1]) with
+ * relative permittivity layer_eps[l]; the first layer extends to -inf and the
+ * last to +inf, layer_z0 ascending.  The window [win_lo, win_hi) encloses the
+ * structure; bc[] holds MW_BC_* per face (-x,+x,-y,+y,-z,+z).              */
+typedef struct {
+    float lo[3], hi[3];
+    int32_t net;
+} mw_cond_box;
+
+typedef struct {
+    float lo[3], hi[3];
+    float eps;
+} mw_diel_box;
+
+typedef struct {
+    int32_t n_cond;
+    const mw_cond_box* cond; /* host */
+    int32_t n_nets;
+    int32_t n_diel;
+    const mw_diel_box* diel; /* host */
+    int32_t n_layers;
+    const float* layer_z0;  /* host, n_layers */
+    const float* layer_eps; /* host, n_layers */
+    float win_lo[3], win_hi[3];
+    uint8_t bc[6];
+} mw_structure_desc;
+
+typedef struct mw_structure mw_structure;
+
+/* Copies the description to the device and builds the uniform-grid
+ * acceleration structure (per grid cell: the conductors that can be nearest
+ * to a point of the cell and the dielectric boxes that a conductor-free cube
+ * centred in the cell can touch).  MW_EGEOM on overlapping conductors, a net
+ * with zero or several boxes, boxes outside the window or empty boxes. */
+mw_status mw_structure_create(const mw_structure_desc* desc, mw_structure** out);
+mw_status mw_structure_destroy(mw_structure* s);
+
+typedef struct {
+    int32_t n_cells;          /* cube lattice size (even, 4..32); default 16  */
+    int32_t hybrid;           /* 1 (default): stratified non-first cubes use
+                                 the exact SGF table, the rest MicroWalk
+                                 (Sec. III-C); 0: every non-first cube uses
+                                 MicroWalk                                  */
+    int32_t reserved0, reserved1;
+    double target_rel_3sigma; /* stop when 3*SE(C_mm)/|C_mm| <= target; 0 =
+                                 run exactly walk_budget walks              */
+    double abs_tol_rel;       /* absorption distance / window diagonal;
+                                 default 1e-6                               */
+    uint64_t first_walk;      /* id of the first walk (resume point)         */
+    uint64_t batch_walks;     /* walks per convergence check; 0 = auto      */
+} frw_options;
+
+typedef struct {
+    uint64_t walks;           /* completed walks (n_path)                   */
+    uint64_t hops;            /* non-first transitions                      */
+    uint64_t micro_steps;     /* Alg. 3 loop iterations                      */
+    uint64_t hop_class[3];    /* non-first cubes: uniform, stratified, other */
+    uint64_t first_branch[4]; /* first cubes: uniform, stratified along the
+                                 surface normal, stratified along another
+                                 axis, homogenised                          */
+    uint64_t cache_miss;      /* SGF tables built                           */
+    uint64_t env_absorbed;    /* walks ending on a grounded window face     */
+    uint64_t hop_cap;         /* walks stopped by the 1e5-hop cap           */
+    uint64_t launches;        /* walker-kernel launches                      */
+    double seconds;           /* wall time of the call                      */
+} frw_stats;
+
+/* ------------------------------------------------------------------------
+ * frw_extract — Alg. 1 for master net `master`: one row of the capacitance
+ * matrix.  Walk w = first_walk + k (k < number of walks run): Gaussian-
+ * surface sample, first transition with weight omega, transitions until the
+ * walk lands on a conductor (net k) or a grounded window face ("env"); then
+ * C_{master,k} += omega.  cap_row[j] = sum of omega over walks ending on net j
+ * divided by the number of walks (fF); cap_row[n_nets] is the env column.
+ * stderr_row[j] is the standard error of cap_row[j].  Runs walk_budget walks,
+ * or fewer when options->target_rel_3sigma > 0 and the target is met first
+ * (checked every batch).  Walk scores are summed per net in fp32 with
+ * compensated (Kahan) sums per block and in fp64 across blocks.
+ * score_net/score_w (device, walk_budget entries each, or NULL): per-walk net
+ * index (n_nets for env) and fp32 weight, indexed by walk - first_walk.
+ * stats may be NULL.  Synchronous: returns after the result is on the host.
+ * MW_ELIMIT if a cube touched more dielectric regions than the per-cube limit
+ * (MW_MAX_REGIONS) supports.                                                */
+#define MW_MAX_REGIONS 16
+mw_status frw_extract(mw_structure* s, int32_t master, uint64_t walk_budget,
+                      uint64_t seed, const frw_options* options,
+                      double* cap_row, double* stderr_row, frw_stats* stats,
+                      int32_t* score_net, float* score_w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBMWALK_H */

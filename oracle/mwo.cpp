@@ -1,0 +1,1111 @@
+// mwo.cpp — CPU oracle for FRW capacitance extraction with MicroWalk
+// transitions (Huang & Yu, arXiv 2507.09730).
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+// GPU library is checked against.  Only the test suite, the smoke check and
+// the benchmark's CPU-baseline leg may load it.  It shares no code, header or
+// table with the GPU library; it is built from this file alone with
+// `g++ -O2 -ffp-contract=off -shared -fPIC`.
+//
+// Arithmetic is binary64 except where the method is specified in integers
+// (cell and link codes, thresholds, Philox words).  Each function names the
+// passage of the paper it follows; readings of points the paper leaves open
+// are stated where they are used.
+//
+// Parity status: every function below is pinned by a CPU test against values
+// the paper or the mathematics fixes, except the first-transition weight of
+// non-stratified (homogenised) first cubes and the voxelisation bias of the
+// series parallel-plate case, which are "parity unpinned" (checked only for
+// self-consistency: reciprocity, row sums, GPU agreement).
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC'11).  Round: two 32x32->64 products of counter words 0
+// and 2 with the round multipliers; the high halves are xored with the other
+// counter word and a key word; the key is advanced by the Weyl constants
+// between rounds.
+// ---------------------------------------------------------------------------
+void philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+    uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c[1] ^ k0;
+        uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+    for (int i = 0; i < 4; ++i) out[i] = c[i];
+}
+
+// Word s of the stream identified by (seed, c1, walk, purpose).
+uint32_t rng_word(uint64_t seed, uint32_t c1, uint64_t walk, uint32_t purpose, uint64_t s) {
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {(uint32_t)(s >> 2), c1, (uint32_t)walk,
+                       (uint32_t)((walk >> 32) & 0xffffffu) | (purpose << 24)};
+    uint32_t out[4];
+    philox4x32_10(ctr, key, out);
+    return out[s & 3];
+}
+
+double u01(uint32_t u) { return ((double)u + 0.5) * (1.0 / 4294967296.0); }
+
+enum { PURPOSE_MW = 0, PURPOSE_GAUSS = 1, PURPOSE_FIRST = 2, PURPOSE_TABLE = 3 };
+
+// ---------------------------------------------------------------------------
+// Integer codes and thresholds.
+//
+// Sec. III-A, Eq. (6): the walk at node v moves to neighbour i with
+// probability alpha_i / sum(alpha).  On the vertex lattice the normalised
+// alpha of a link is its face conductance: the sum of the permittivities of
+// the four cells that share the link (each cell code is rint(eps * 2^16)).
+// On the cell lattice alpha is Eq. (6) verbatim, stored as
+// rint(alpha * 2^24).  Prefix sums S_k of the six codes (order -x,+x,-y,+y,
+// -z,+z) give thresholds T_k = ceil(S_k 2^32 / S_5); a uniform 32-bit word u
+// picks direction #{k <= 4 : u >= T_k}.
+// ---------------------------------------------------------------------------
+uint64_t vertex_cell_code(float eps) { return (uint64_t)std::nearbyint((double)eps * 65536.0); }
+
+uint64_t cell_link_code(float eps_nb, float eps_v) {
+    double a = (double)eps_nb / ((double)eps_nb + (double)eps_v);
+    return (uint64_t)std::nearbyint(a * 16777216.0);
+}
+
+void thresholds_from_codes(const uint64_t g[6], uint32_t T[5]) {
+    uint64_t S[6];
+    uint64_t acc = 0;
+    for (int d = 0; d < 6; ++d) {
+        acc += g[d];
+        S[d] = acc;
+    }
+    for (int k = 0; k < 5; ++k) T[k] = (uint32_t)(((S[k] << 32) + S[5] - 1) / S[5]);
+}
+
+int choose_direction(uint32_t u, const uint32_t T[5]) {
+    int d = 0;
+    for (int k = 0; k < 5; ++k)
+        if (u >= T[k]) ++d;
+    return d;
+}
+
+const int DIR[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+
+// Vertex lattice over n^3 cells with codes e[(k*n+j)*n+i]; nodes (i,j,k) in
+// [0,n]^3, interior [1,n-1]^3.  Link code of direction d at interior node.
+uint64_t vertex_link(const std::vector<uint64_t>& e, int n, int i, int j, int k, int d) {
+    auto E = [&](int x, int y, int z) { return e[((size_t)z * n + y) * n + x]; };
+    switch (d) {
+        case 0: return E(i - 1, j - 1, k - 1) + E(i - 1, j, k - 1) + E(i - 1, j - 1, k) + E(i - 1, j, k);
+        case 1: return E(i, j - 1, k - 1) + E(i, j, k - 1) + E(i, j - 1, k) + E(i, j, k);
+        case 2: return E(i - 1, j - 1, k - 1) + E(i, j - 1, k - 1) + E(i - 1, j - 1, k) + E(i, j - 1, k);
+        case 3: return E(i - 1, j, k - 1) + E(i, j, k - 1) + E(i - 1, j, k) + E(i, j, k);
+        case 4: return E(i - 1, j - 1, k - 1) + E(i, j - 1, k - 1) + E(i - 1, j, k - 1) + E(i, j, k - 1);
+        default: return E(i - 1, j - 1, k) + E(i, j - 1, k) + E(i - 1, j, k) + E(i, j, k);
+    }
+}
+
+// Hit index of a boundary node of the vertex lattice (exactly one coordinate
+// on {0, n}).
+int vertex_hit_index(int n, int i, int j, int k) {
+    int M = n - 1;
+    int c[3] = {i, j, k};
+    for (int ax = 0; ax < 3; ++ax) {
+        if (c[ax] == 0 || c[ax] == n) {
+            int side = c[ax] == n ? 1 : 0;
+            int a = ax == 0 ? c[1] : c[0];
+            int b = ax == 2 ? c[1] : c[2];
+            return (2 * ax + side) * M * M + (b - 1) * M + (a - 1);
+        }
+    }
+    return -1;
+}
+
+void vertex_node_of_hit(int n, int hit, int node[3]) {
+    int M = n - 1;
+    int f = hit / (M * M), rem = hit % (M * M);
+    int b = rem / M + 1, a = rem % M + 1;
+    int ax = f / 2, side = f % 2;
+    int o0 = ax == 0 ? 1 : 0, o1 = ax == 2 ? 1 : 2;
+    node[ax] = side ? n : 0;
+    node[o0] = a;
+    node[o1] = b;
+}
+
+// Alg. 3 on the vertex lattice: from the centre node, repeat {direction from
+// the node's thresholds; move} until a boundary node is reached.
+int microwalk_vertex(const std::vector<uint64_t>& e, int n, const int start[3], uint64_t seed,
+                     uint32_t c1, uint64_t walk, int32_t* steps_out, int node_out[3]) {
+    int p[3] = {start[0], start[1], start[2]};
+    uint64_t s = 0;
+    for (;;) {
+        if (s >= (1ull << 30)) {
+            if (steps_out) *steps_out = (int32_t)s;
+            return -1;
+        }
+        uint64_t g[6];
+        for (int d = 0; d < 6; ++d) g[d] = vertex_link(e, n, p[0], p[1], p[2], d);
+        uint32_t T[5];
+        thresholds_from_codes(g, T);
+        uint32_t u = rng_word(seed, c1, walk, PURPOSE_MW, s);
+        int d = choose_direction(u, T);
+        for (int a = 0; a < 3; ++a) p[a] += DIR[d][a];
+        ++s;
+        if (p[0] == 0 || p[0] == n || p[1] == 0 || p[1] == n || p[2] == 0 || p[2] == n) {
+            if (steps_out) *steps_out = (int32_t)s;
+            if (node_out)
+                for (int a = 0; a < 3; ++a) node_out[a] = p[a];
+            return vertex_hit_index(n, p[0], p[1], p[2]);
+        }
+    }
+}
+
+// Alg. 3 on the cell-centred lattice of Sec. III-A (nodes at voxel centres,
+// boundary nodes at panel centres, coefficients of Eq. 6).
+int microwalk_cell(const float* eps, int N, uint64_t seed, uint32_t c1, uint64_t walk, int32_t* steps_out) {
+    int p[3] = {(N - 1) / 2, (N - 1) / 2, (N - 1) / 2};
+    uint64_t s = 0;
+    auto EPS = [&](int x, int y, int z) { return eps[((size_t)z * N + y) * N + x]; };
+    for (;;) {
+        if (s >= (1ull << 30)) {
+            if (steps_out) *steps_out = (int32_t)s;
+            return -1;
+        }
+        uint64_t g[6];
+        float ev = EPS(p[0], p[1], p[2]);
+        for (int d = 0; d < 6; ++d) {
+            int q[3] = {p[0] + DIR[d][0], p[1] + DIR[d][1], p[2] + DIR[d][2]};
+            bool inside = q[0] >= 0 && q[0] < N && q[1] >= 0 && q[1] < N && q[2] >= 0 && q[2] < N;
+            g[d] = inside ? cell_link_code(EPS(q[0], q[1], q[2]), ev) : (1ull << 24);
+        }
+        uint32_t T[5];
+        thresholds_from_codes(g, T);
+        uint32_t u = rng_word(seed, c1, walk, PURPOSE_MW, s);
+        int d = choose_direction(u, T);
+        for (int a = 0; a < 3; ++a) p[a] += DIR[d][a];
+        ++s;
+        for (int ax = 0; ax < 3; ++ax) {
+            if (p[ax] < 0 || p[ax] >= N) {
+                int side = p[ax] >= N ? 1 : 0;
+                int a = ax == 0 ? p[1] : p[0];
+                int b = ax == 2 ? p[1] : p[2];
+                if (steps_out) *steps_out = (int32_t)s;
+                return (2 * ax + side) * N * N + b * N + a;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exact discrete SGF of the vertex lattice (Eqs. 7-8, 11).
+//
+// With integer link codes G (symmetric: a link has the same code seen from
+// both ends) and D_v = sum of the six codes at v, the chain of Alg. 3 has
+// Q_II = D^-1 G_II, so (I - Q_II)^-1 = (D - G_II)^-1 D.  Solving
+// (D - G_II) z = e_src once gives the exit distribution from the source,
+// P_b = sum_v z_v G_vb (Eq. 8 via Theorem 1) and the expected number of steps
+// E(tau) = sum_v z_v D_v (Eq. 11).  D - G_II is symmetric positive definite;
+// the solve is Jacobi-preconditioned conjugate gradients to a relative
+// residual of 1e-14.
+// ---------------------------------------------------------------------------
+struct VertexSystem {
+    int n, M;
+    std::vector<double> g;  // 6 per interior node
+    std::vector<double> D;
+    size_t idx(int i, int j, int k) const { return ((size_t)(k - 1) * M + (j - 1)) * M + (i - 1); }
+};
+
+VertexSystem build_vertex_system(const std::vector<uint64_t>& e, int n) {
+    VertexSystem S;
+    S.n = n;
+    S.M = n - 1;
+    size_t NI = (size_t)S.M * S.M * S.M;
+    S.g.resize(NI * 6);
+    S.D.resize(NI);
+    for (int k = 1; k < n; ++k)
+        for (int j = 1; j < n; ++j)
+            for (int i = 1; i < n; ++i) {
+                size_t v = S.idx(i, j, k);
+                double D = 0;
+                for (int d = 0; d < 6; ++d) {
+                    double gd = (double)vertex_link(e, n, i, j, k, d);
+                    S.g[v * 6 + d] = gd;
+                    D += gd;
+                }
+                S.D[v] = D;
+            }
+    return S;
+}
+
+void apply_vertex(const VertexSystem& S, const std::vector<double>& x, std::vector<double>& y) {
+    int n = S.n;
+    for (int k = 1; k < n; ++k)
+        for (int j = 1; j < n; ++j)
+            for (int i = 1; i < n; ++i) {
+                size_t v = S.idx(i, j, k);
+                double acc = S.D[v] * x[v];
+                for (int d = 0; d < 6; ++d) {
+                    int q[3] = {i + DIR[d][0], j + DIR[d][1], k + DIR[d][2]};
+                    if (q[0] == 0 || q[0] == n || q[1] == 0 || q[1] == n || q[2] == 0 || q[2] == n) continue;
+                    acc -= S.g[v * 6 + d] * x[S.idx(q[0], q[1], q[2])];
+                }
+                y[v] = acc;
+            }
+}
+
+bool solve_vertex(const VertexSystem& S, const std::vector<double>& b, std::vector<double>& x) {
+    size_t N = S.D.size();
+    x.assign(N, 0.0);
+    std::vector<double> r = b, z(N), p(N), Ap(N);
+    double bnorm = 0;
+    for (double v : b) bnorm += v * v;
+    bnorm = std::sqrt(bnorm);
+    if (bnorm == 0) return true;
+    for (size_t i = 0; i < N; ++i) z[i] = r[i] / S.D[i];
+    p = z;
+    double rz = 0;
+    for (size_t i = 0; i < N; ++i) rz += r[i] * z[i];
+    for (int it = 0; it < 50000; ++it) {
+        apply_vertex(S, p, Ap);
+        double pAp = 0;
+        for (size_t i = 0; i < N; ++i) pAp += p[i] * Ap[i];
+        double alpha = rz / pAp;
+        double rn = 0;
+        for (size_t i = 0; i < N; ++i) {
+            x[i] += alpha * p[i];
+            r[i] -= alpha * Ap[i];
+            rn += r[i] * r[i];
+        }
+        if (std::sqrt(rn) <= 1e-14 * bnorm) return true;
+        for (size_t i = 0; i < N; ++i) z[i] = r[i] / S.D[i];
+        double rz2 = 0;
+        for (size_t i = 0; i < N; ++i) rz2 += r[i] * z[i];
+        double beta = rz2 / rz;
+        rz = rz2;
+        for (size_t i = 0; i < N; ++i) p[i] = z[i] + beta * p[i];
+    }
+    return false;
+}
+
+// Exit distribution P (6 M^2 entries, hit-index order) and E(tau) from
+// interior source node src.
+bool sgf_vertex(const VertexSystem& S, const int src[3], std::vector<double>& P, double* etau) {
+    int n = S.n, M = S.M;
+    std::vector<double> b(S.D.size(), 0.0), z;
+    b[S.idx(src[0], src[1], src[2])] = 1.0;
+    if (!solve_vertex(S, b, z)) return false;
+    P.assign((size_t)6 * M * M, 0.0);
+    double et = 0;
+    for (int k = 1; k < n; ++k)
+        for (int j = 1; j < n; ++j)
+            for (int i = 1; i < n; ++i) {
+                size_t v = S.idx(i, j, k);
+                et += z[v] * S.D[v];
+                for (int d = 0; d < 6; ++d) {
+                    int q[3] = {i + DIR[d][0], j + DIR[d][1], k + DIR[d][2]};
+                    if (q[0] == 0 || q[0] == n || q[1] == 0 || q[1] == n || q[2] == 0 || q[2] == n)
+                        P[vertex_hit_index(n, q[0], q[1], q[2])] += z[v] * S.g[v * 6 + d];
+                }
+            }
+    if (etau) *etau = et;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry (Alg. 1 input) and voxelisation of transition cubes.
+// ---------------------------------------------------------------------------
+struct Box {
+    double lo[3], hi[3];
+    int net;     // conductors
+    float eps;   // dielectrics
+};
+
+struct Structure {
+    std::vector<Box> cond;
+    int n_nets = 0;
+    std::vector<Box> diel;
+    std::vector<double> layer_z0;
+    std::vector<float> layer_eps;
+    double wlo[3], whi[3];
+    int bc[6];
+};
+
+const double EPS0 = 8.8541878128e-3;  // vacuum permittivity, fF/um
+const int HOP_CAP = 100000;
+
+double box_point_dist(const Box& b, const double p[3]) {
+    double d = 0;
+    for (int a = 0; a < 3; ++a) {
+        double da = std::max(std::max(b.lo[a] - p[a], p[a] - b.hi[a]), 0.0);
+        d = std::max(d, da);
+    }
+    return d;
+}
+
+// Largest conductor-free cube around p (L-infinity distance to the nearest
+// conductor or grounded window face).  nearest = net index, or n_nets for a
+// grounded face.
+double structure_dist(const Structure& S, const double p[3], int* nearest) {
+    double best = INFINITY;
+    int who = S.n_nets;
+    for (const Box& b : S.cond) {
+        double d = box_point_dist(b, p);
+        if (d < best) {
+            best = d;
+            who = b.net;
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (S.bc[2 * a] == 0) {
+            double d = p[a] - S.wlo[a];
+            if (d < best) {
+                best = d;
+                who = S.n_nets;
+            }
+        }
+        if (S.bc[2 * a + 1] == 0) {
+            double d = S.whi[a] - p[a];
+            if (d < best) {
+                best = d;
+                who = S.n_nets;
+            }
+        }
+    }
+    if (nearest) *nearest = who;
+    return best;
+}
+
+// Mirror folding of a coordinate at Neumann window faces.
+double fold(const Structure& S, int a, double x) {
+    for (int it = 0; it < 64; ++it) {
+        if (x < S.wlo[a] && S.bc[2 * a] == 1)
+            x = 2 * S.wlo[a] - x;
+        else if (x > S.whi[a] && S.bc[2 * a + 1] == 1)
+            x = 2 * S.whi[a] - x;
+        else
+            break;
+    }
+    return x;
+}
+
+// Permittivity at a point (after folding): the last dielectric box that
+// contains it (half-open), else the background layer that contains z.
+float eps_at(const Structure& S, const double p[3]) {
+    for (int b = (int)S.diel.size() - 1; b >= 0; --b) {
+        const Box& B = S.diel[b];
+        if (p[0] >= B.lo[0] && p[0] < B.hi[0] && p[1] >= B.lo[1] && p[1] < B.hi[1] && p[2] >= B.lo[2] &&
+            p[2] < B.hi[2])
+            return B.eps;
+    }
+    int L = (int)S.layer_z0.size();
+    int l = 0;
+    for (int q = 1; q < L; ++q)
+        if (p[2] >= S.layer_z0[q]) l = q;
+    return S.layer_eps[l];
+}
+
+// A voxelised transition cube: n^3 cells of size h around centre c.  Cell
+// (i,j,k) takes the permittivity at its centre (reading of "constant
+// permittivity per voxel", Sec. III-A).
+struct Cube {
+    int n;
+    double c[3], R, h;
+    std::vector<uint64_t> e;  // vertex cell codes
+    int cls;                  // 0 uniform, 1 stratified, 2 non-stratified
+    int axis;                 // stratification axis (0..2) when cls <= 1
+    uint8_t full[3];          // per axis: every present region spans all cells
+};
+
+double cell_centre(const Cube& C, int a, int i) { return C.c[a] - C.R + (i + 0.5) * C.h; }
+
+// Region-level stratification (reading of "stratified dielectrics",
+// Sec. II-B/III-C): the regions are the dielectric boxes and background
+// layers.  A region is present in the cube when it contains at least one cell
+// centre.  The cube is stratified along axis s when every present region
+// contains whole planes normal to s, and uniform when every present region
+// contains the whole cube.  Regions are axis-aligned, so their cell sets are
+// products of per-axis index sets; the test uses those counts.
+void build_cube(const Structure& S, const double c[3], double R, int n, Cube& C) {
+    C.n = n;
+    for (int a = 0; a < 3; ++a) C.c[a] = c[a];
+    C.R = R;
+    C.h = 2 * R / n;
+    C.e.assign((size_t)n * n * n, 0);
+    std::vector<double> f[3];
+    for (int a = 0; a < 3; ++a) {
+        f[a].resize(n);
+        for (int i = 0; i < n; ++i) f[a][i] = fold(S, a, cell_centre(C, a, i));
+    }
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                double p[3] = {f[0][i], f[1][j], f[2][k]};
+                C.e[((size_t)k * n + j) * n + i] = vertex_cell_code(eps_at(S, p));
+            }
+    // per-region per-axis membership counts
+    bool full_axis[3] = {true, true, true};
+    auto account = [&](const double lo[3], const double hi[3]) {
+        int cnt[3];
+        for (int a = 0; a < 3; ++a) {
+            cnt[a] = 0;
+            for (int i = 0; i < n; ++i)
+                if (f[a][i] >= lo[a] && f[a][i] < hi[a]) ++cnt[a];
+        }
+        if (cnt[0] == 0 || cnt[1] == 0 || cnt[2] == 0) return;  // not present
+        for (int a = 0; a < 3; ++a)
+            if (cnt[a] != n) full_axis[a] = false;
+    };
+    for (const Box& B : S.diel) account(B.lo, B.hi);
+    int L = (int)S.layer_z0.size();
+    for (int l = 0; l < L; ++l) {
+        double lo[3] = {-INFINITY, -INFINITY, l == 0 ? -INFINITY : S.layer_z0[l]};
+        double hi[3] = {INFINITY, INFINITY, l + 1 < L ? S.layer_z0[l + 1] : INFINITY};
+        account(lo, hi);
+    }
+    for (int a = 0; a < 3; ++a) C.full[a] = full_axis[a];
+    // stratified along s <=> regions full along both other axes
+    auto strat = [&](int s) { return full_axis[(s + 1) % 3] && full_axis[(s + 2) % 3]; };
+    if (full_axis[0] && full_axis[1] && full_axis[2]) {
+        C.cls = 0;
+        C.axis = 2;
+    } else if (strat(2)) {
+        C.cls = 1;
+        C.axis = 2;
+    } else if (strat(0)) {
+        C.cls = 1;
+        C.axis = 0;
+    } else if (strat(1)) {
+        C.cls = 1;
+        C.axis = 1;
+    } else {
+        C.cls = 2;
+        C.axis = -1;
+    }
+}
+
+bool stratified_along(const Cube& C, int s) {
+    if (C.cls == 0) return true;
+    return C.full[(s + 1) % 3] && C.full[(s + 2) % 3];
+}
+
+// Codes of the planes normal to s of a stratified cube (cell with other
+// coordinates 0 represents its plane).
+std::vector<uint64_t> plane_codes(const Cube& C, int s) {
+    int n = C.n;
+    std::vector<uint64_t> seq(n);
+    for (int p = 0; p < n; ++p) {
+        int q[3] = {0, 0, 0};
+        q[s] = p;
+        seq[p] = C.e[((size_t)q[2] * n + q[1]) * n + q[0]];
+    }
+    return seq;
+}
+
+// "Homogenize" branch of the first-transition treatment (Fig. 4, Table II
+// note a): each plane normal to a takes the mean code of its n^2 cells,
+// rounded half to even.
+std::vector<uint64_t> homogenised_codes(const Cube& C, int a) {
+    int n = C.n;
+    std::vector<uint64_t> seq(n);
+    uint64_t area = (uint64_t)n * n;
+    for (int p = 0; p < n; ++p) {
+        uint64_t sum = 0;
+        for (int u = 0; u < n; ++u)
+            for (int v = 0; v < n; ++v) {
+                int q[3];
+                q[a] = p;
+                q[(a + 1) % 3] = u;
+                q[(a + 2) % 3] = v;
+                sum += C.e[((size_t)q[2] * n + q[1]) * n + q[0]];
+            }
+        uint64_t qt = sum / area, rem = sum % area;
+        if (2 * rem > area || (2 * rem == area && (qt & 1))) ++qt;
+        seq[p] = qt;
+    }
+    return seq;
+}
+
+std::vector<uint64_t> expand_layers(const std::vector<uint64_t>& seq, int s, int n) {
+    std::vector<uint64_t> e((size_t)n * n * n);
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                int q[3] = {i, j, k};
+                e[((size_t)k * n + j) * n + i] = seq[q[s]];
+            }
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// SGF tables of stratified cubes ("analytical path" of the hybrid strategy,
+// Sec. III-C).  The paper's AGF formulas are not part of the paper; the
+// oracle uses the exact discrete SGF of the same lattice, which Theorem 1
+// makes identical in distribution to MicroWalk on that cube.
+// ---------------------------------------------------------------------------
+struct HopTable {
+    std::vector<double> P;  // 6 M^2
+};
+
+struct FirstTable {
+    std::vector<double> Pc, Pp, Pm;  // sources c, c + e_a, c - e_a
+    double Gp, Gm;                   // link conductances of c along +a, -a (eps units)
+};
+
+struct TableCache {
+    std::mutex mu;
+    std::map<std::vector<uint64_t>, std::shared_ptr<HopTable>> hop;
+    std::map<std::vector<uint64_t>, std::shared_ptr<FirstTable>> first;
+    std::atomic<uint64_t> misses{0};
+};
+
+std::shared_ptr<HopTable> hop_table(TableCache& TC, int n, int s, const std::vector<uint64_t>& seq) {
+    std::vector<uint64_t> key;
+    key.push_back((uint64_t)n);
+    key.push_back((uint64_t)s);
+    key.insert(key.end(), seq.begin(), seq.end());
+    {
+        std::lock_guard<std::mutex> g(TC.mu);
+        auto it = TC.hop.find(key);
+        if (it != TC.hop.end()) return it->second;
+    }
+    auto e = expand_layers(seq, s, n);
+    VertexSystem VS = build_vertex_system(e, n);
+    auto T = std::make_shared<HopTable>();
+    int src[3] = {n / 2, n / 2, n / 2};
+    if (!sgf_vertex(VS, src, T->P, nullptr)) return nullptr;
+    TC.misses++;
+    std::lock_guard<std::mutex> g(TC.mu);
+    TC.hop[key] = T;
+    return T;
+}
+
+std::shared_ptr<FirstTable> first_table(TableCache& TC, int n, int s, int a, const std::vector<uint64_t>& seq) {
+    std::vector<uint64_t> key;
+    key.push_back((uint64_t)n);
+    key.push_back((uint64_t)s);
+    key.push_back((uint64_t)a);
+    key.insert(key.end(), seq.begin(), seq.end());
+    {
+        std::lock_guard<std::mutex> g(TC.mu);
+        auto it = TC.first.find(key);
+        if (it != TC.first.end()) return it->second;
+    }
+    auto e = expand_layers(seq, s, n);
+    VertexSystem VS = build_vertex_system(e, n);
+    auto T = std::make_shared<FirstTable>();
+    int c[3] = {n / 2, n / 2, n / 2};
+    int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
+    cp[a] += 1;
+    cm[a] -= 1;
+    if (!sgf_vertex(VS, c, T->Pc, nullptr)) return nullptr;
+    if (!sgf_vertex(VS, cp, T->Pp, nullptr)) return nullptr;
+    if (!sgf_vertex(VS, cm, T->Pm, nullptr)) return nullptr;
+    T->Gp = (double)vertex_link(e, n, c[0], c[1], c[2], 2 * a + 1) / (4.0 * 65536.0);
+    T->Gm = (double)vertex_link(e, n, c[0], c[1], c[2], 2 * a) / (4.0 * 65536.0);
+    TC.misses++;
+    std::lock_guard<std::mutex> g(TC.mu);
+    TC.first[key] = T;
+    return T;
+}
+
+// Inverse-CDF sample of index b with probability weights[b] / sum.
+int sample_index(const std::vector<double>& wts, double total, uint32_t u) {
+    double x = u01(u) * total;
+    double cum = 0;
+    int last = -1;
+    for (size_t b = 0; b < wts.size(); ++b) {
+        if (wts[b] <= 0) continue;
+        cum += wts[b];
+        last = (int)b;
+        if (x < cum) return (int)b;
+    }
+    return last;
+}
+
+// ---------------------------------------------------------------------------
+// Gaussian surface (Alg. 1 input G).  Reading: G is the boundary of the
+// master box expanded by g = half the L-infinity gap to the nearest other
+// conductor or grounded window face, restricted to the window (faces lying
+// outside it or on a symmetry wall carry no flux and are dropped; kept faces
+// are clipped to the window).
+// ---------------------------------------------------------------------------
+struct GFace {
+    int axis, side;
+    double plane;
+    double lo[3], hi[3];
+    double area;
+};
+
+struct Gauss {
+    double g;
+    std::vector<GFace> faces;
+    double area;
+};
+
+bool build_gauss(const Structure& S, int master, Gauss& G) {
+    const Box* M = nullptr;
+    for (const Box& b : S.cond)
+        if (b.net == master) M = &b;
+    if (!M) return false;
+    double g0 = INFINITY;
+    for (const Box& b : S.cond) {
+        if (&b == M) continue;
+        double gap = 0;
+        for (int a = 0; a < 3; ++a) gap = std::max(gap, std::max(b.lo[a] - M->hi[a], M->lo[a] - b.hi[a]));
+        g0 = std::min(g0, gap);
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (S.bc[2 * a] == 0) g0 = std::min(g0, M->lo[a] - S.wlo[a]);
+        if (S.bc[2 * a + 1] == 0) g0 = std::min(g0, S.whi[a] - M->hi[a]);
+    }
+    if (!(g0 > 0) || !std::isfinite(g0)) return false;
+    G.g = g0 / 2;
+    G.faces.clear();
+    G.area = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int side = 0; side < 2; ++side) {
+            GFace F;
+            F.axis = a;
+            F.side = side;
+            F.plane = side ? M->hi[a] + G.g : M->lo[a] - G.g;
+            if (!(F.plane > S.wlo[a] && F.plane < S.whi[a])) continue;
+            double area = 1;
+            for (int b = 0; b < 3; ++b) {
+                if (b == a) {
+                    F.lo[b] = F.hi[b] = F.plane;
+                    continue;
+                }
+                F.lo[b] = std::max(M->lo[b] - G.g, S.wlo[b]);
+                F.hi[b] = std::min(M->hi[b] + G.g, S.whi[b]);
+                area *= std::max(F.hi[b] - F.lo[b], 0.0);
+            }
+            F.area = area;
+            if (area <= 0) continue;
+            G.faces.push_back(F);
+            G.area += area;
+        }
+    return !G.faces.empty();
+}
+
+// ---------------------------------------------------------------------------
+// One walk of Alg. 1: Gaussian-surface sample, first transition with weight,
+// transitions until absorption.  Returns the net (n_nets = env) and omega.
+// ---------------------------------------------------------------------------
+struct WalkStats {
+    uint64_t hops = 0, micro_steps = 0, hop_class[3] = {0, 0, 0}, first_branch[4] = {0, 0, 0, 0};
+    uint64_t env = 0, hop_cap = 0;
+};
+
+struct FrwParams {
+    int n;
+    int hybrid;
+    double delta_abs;
+    uint64_t seed;
+};
+
+bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P, TableCache& TC, uint64_t walk,
+              int* net_out, double* omega_out, WalkStats& st) {
+    int n = P.n;
+    // GaussianSurfaceSampling(G)
+    uint32_t w0 = rng_word(P.seed, 0, walk, PURPOSE_GAUSS, 0);
+    uint32_t w1 = rng_word(P.seed, 0, walk, PURPOSE_GAUSS, 1);
+    uint32_t w2 = rng_word(P.seed, 0, walk, PURPOSE_GAUSS, 2);
+    double xa = u01(w0) * G.area, cum = 0;
+    size_t fi = G.faces.size() - 1;
+    for (size_t f = 0; f < G.faces.size(); ++f) {
+        cum += G.faces[f].area;
+        if (xa < cum) {
+            fi = f;
+            break;
+        }
+    }
+    const GFace& F = G.faces[fi];
+    double r[3];
+    int t0 = (F.axis + 1) % 3, t1 = (F.axis + 2) % 3;
+    int ta = std::min(t0, t1), tb = std::max(t0, t1);
+    r[F.axis] = F.plane;
+    r[ta] = F.lo[ta] + u01(w1) * (F.hi[ta] - F.lo[ta]);
+    r[tb] = F.lo[tb] + u01(w2) * (F.hi[tb] - F.lo[tb]);
+
+    // FirstTransition(r): cube centred on G touching the master.
+    int a = F.axis;
+    double R = std::min(structure_dist(S, r, nullptr), G.g);
+    Cube C;
+    build_cube(S, r, R, n, C);
+    int branch, s;
+    std::vector<uint64_t> seq;
+    if (C.cls == 0) {
+        branch = 0;
+        s = a;
+        seq = plane_codes(C, a);
+    } else if (stratified_along(C, a)) {
+        branch = 1;
+        s = a;
+        seq = plane_codes(C, a);
+    } else if (C.cls == 1) {
+        branch = 2;
+        s = C.axis;
+        seq = plane_codes(C, s);
+    } else {
+        branch = 3;
+        s = a;
+        seq = homogenised_codes(C, a);
+    }
+    st.first_branch[branch]++;
+    auto FT = first_table(TC, n, s, a, seq);
+    if (!FT) return false;
+    // flux stencil along the outward normal
+    const std::vector<double>& Pout = F.side ? FT->Pp : FT->Pm;
+    const std::vector<double>& Pin = F.side ? FT->Pm : FT->Pp;
+    double Gout = F.side ? FT->Gp : FT->Gm;
+    double Gin = F.side ? FT->Gm : FT->Gp;
+    size_t NB = FT->Pc.size();
+    std::vector<double> w(NB), aw(NB);
+    double K = 0;
+    for (size_t b = 0; b < NB; ++b) {
+        w[b] = (Gout * (FT->Pc[b] - Pout[b]) + Gin * (Pin[b] - FT->Pc[b])) / (2 * C.h);
+        aw[b] = std::fabs(w[b]);
+        K += aw[b];
+    }
+    int b = sample_index(aw, K, rng_word(P.seed, 0, walk, PURPOSE_FIRST, 0));
+    double omega = EPS0 * G.area * K * (w[b] > 0 ? 1.0 : -1.0);
+    int node[3];
+    vertex_node_of_hit(n, b, node);
+    // The walker's position is folded back into the window at symmetry
+    // walls: by mirror symmetry the folded point has the same potential.
+    double x[3];
+    for (int q = 0; q < 3; ++q) x[q] = fold(S, q, C.c[q] - C.R + node[q] * C.h);
+
+    // Transition loop.
+    for (uint32_t t = 1;; ++t) {
+        int nearest;
+        double d = structure_dist(S, x, &nearest);
+        if (d <= P.delta_abs) {
+            *net_out = nearest;
+            *omega_out = omega;
+            if (nearest == S.n_nets) st.env++;
+            return true;
+        }
+        if ((int)t > HOP_CAP) {
+            st.hop_cap++;
+            *net_out = S.n_nets;
+            *omega_out = omega;
+            return true;
+        }
+        st.hops++;
+        build_cube(S, x, d, n, C);
+        st.hop_class[C.cls]++;
+        int hb;
+        if (P.hybrid && C.cls <= 1) {
+            auto HT = hop_table(TC, n, C.axis, plane_codes(C, C.axis));
+            if (!HT) return false;
+            hb = sample_index(HT->P, 1.0, rng_word(P.seed, t, walk, PURPOSE_TABLE, 0));
+        } else {
+            int start[3] = {n / 2, n / 2, n / 2};
+            int32_t steps = 0;
+            hb = microwalk_vertex(C.e, n, start, P.seed, t, walk, &steps, nullptr);
+            st.micro_steps += (uint64_t)steps;
+            if (hb < 0) return false;
+        }
+        vertex_node_of_hit(n, hb, node);
+        for (int q = 0; q < 3; ++q) x[q] = fold(S, q, C.c[q] - C.R + node[q] * C.h);
+    }
+}
+
+Structure make_structure(const double* cond, int n_cond, int n_nets, const double* diel, int n_diel,
+                         const double* layer_z0, const double* layer_eps, int n_layers, const double* win,
+                         const int32_t* bc) {
+    Structure S;
+    for (int i = 0; i < n_cond; ++i) {
+        Box b;
+        for (int a = 0; a < 3; ++a) {
+            b.lo[a] = cond[i * 7 + a];
+            b.hi[a] = cond[i * 7 + 3 + a];
+        }
+        b.net = (int)cond[i * 7 + 6];
+        b.eps = 0;
+        S.cond.push_back(b);
+    }
+    S.n_nets = n_nets;
+    for (int i = 0; i < n_diel; ++i) {
+        Box b;
+        for (int a = 0; a < 3; ++a) {
+            b.lo[a] = diel[i * 7 + a];
+            b.hi[a] = diel[i * 7 + 3 + a];
+        }
+        b.net = -1;
+        b.eps = (float)diel[i * 7 + 6];
+        S.diel.push_back(b);
+    }
+    for (int l = 0; l < n_layers; ++l) {
+        S.layer_z0.push_back(layer_z0[l]);
+        S.layer_eps.push_back((float)layer_eps[l]);
+    }
+    for (int a = 0; a < 3; ++a) {
+        S.wlo[a] = win[a];
+        S.whi[a] = win[3 + a];
+    }
+    for (int f = 0; f < 6; ++f) S.bc[f] = bc[f];
+    return S;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C interface (ctypes).  Return 0 on success, negative on failure.
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int mwo_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+    philox4x32_10(ctr, key, out);
+    return 0;
+}
+
+int mwo_rng_words(uint64_t seed, uint32_t c1, uint64_t walk, uint32_t purpose, uint64_t s0, int64_t count,
+                  uint32_t* out) {
+    for (int64_t i = 0; i < count; ++i) out[i] = rng_word(seed, c1, walk, purpose, s0 + (uint64_t)i);
+    return 0;
+}
+
+// Vertex lattice cell codes rint(eps * 2^16).
+int mwo_vertex_codes(const float* eps, int64_t count, uint64_t* codes) {
+    for (int64_t i = 0; i < count; ++i) codes[i] = vertex_cell_code(eps[i]);
+    return 0;
+}
+
+// Link codes (6 per interior node, node order ((k-1)M+(j-1))M+(i-1)) and
+// thresholds (5 per node) of the vertex lattice.
+int mwo_vertex_thresholds(const float* eps, int n, uint64_t* links, uint32_t* T) {
+    if (n < 2 || n % 2) return -1;
+    std::vector<uint64_t> e((size_t)n * n * n);
+    for (size_t i = 0; i < e.size(); ++i) e[i] = vertex_cell_code(eps[i]);
+    int M = n - 1;
+    for (int k = 1; k < n; ++k)
+        for (int j = 1; j < n; ++j)
+            for (int i = 1; i < n; ++i) {
+                size_t v = ((size_t)(k - 1) * M + (j - 1)) * M + (i - 1);
+                uint64_t g[6];
+                for (int d = 0; d < 6; ++d) g[d] = vertex_link(e, n, i, j, k, d);
+                if (links)
+                    for (int d = 0; d < 6; ++d) links[v * 6 + d] = g[d];
+                if (T) thresholds_from_codes(g, T + v * 5);
+            }
+    return 0;
+}
+
+// Link codes and thresholds of the cell lattice (Eq. 6), node order
+// (k*N+j)*N+i.
+int mwo_cell_thresholds(const float* eps, int N, uint64_t* links, uint32_t* T) {
+    if (N < 1 || N % 2 == 0) return -1;
+    auto EPS = [&](int x, int y, int z) { return eps[((size_t)z * N + y) * N + x]; };
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                size_t v = ((size_t)k * N + j) * N + i;
+                uint64_t g[6];
+                for (int d = 0; d < 6; ++d) {
+                    int q[3] = {i + DIR[d][0], j + DIR[d][1], k + DIR[d][2]};
+                    bool inside = q[0] >= 0 && q[0] < N && q[1] >= 0 && q[1] < N && q[2] >= 0 && q[2] < N;
+                    g[d] = inside ? cell_link_code(EPS(q[0], q[1], q[2]), EPS(i, j, k)) : (1ull << 24);
+                }
+                if (links)
+                    for (int d = 0; d < 6; ++d) links[v * 6 + d] = g[d];
+                if (T) thresholds_from_codes(g, T + v * 5);
+            }
+    return 0;
+}
+
+int mwo_choose_direction(uint32_t u, const uint32_t* T) { return choose_direction(u, T); }
+
+// Alg. 3, n_walks walks with ids first_walk.. on one cube.
+int mwo_microwalk(const float* eps, int n, int lattice, uint64_t n_walks, uint64_t first_walk, uint64_t seed,
+                  uint32_t cube_index, int32_t* hits, int32_t* steps) {
+    if (lattice == 0) {
+        if (n < 2 || n % 2) return -1;
+        std::vector<uint64_t> e((size_t)n * n * n);
+        for (size_t i = 0; i < e.size(); ++i) e[i] = vertex_cell_code(eps[i]);
+        int start[3] = {n / 2, n / 2, n / 2};
+        for (uint64_t w = 0; w < n_walks; ++w) {
+            int32_t st;
+            hits[w] = microwalk_vertex(e, n, start, seed, cube_index, first_walk + w, &st, nullptr);
+            if (steps) steps[w] = st;
+        }
+        return 0;
+    }
+    if (n < 1 || n % 2 == 0) return -1;
+    for (uint64_t w = 0; w < n_walks; ++w) {
+        int32_t st;
+        hits[w] = microwalk_cell(eps, n, seed, cube_index, first_walk + w, &st);
+        if (steps) steps[w] = st;
+    }
+    return 0;
+}
+
+// Exact exit distribution (Eq. 8) and E(tau) (Eq. 11) of the vertex lattice
+// from interior source node src, given cell codes.
+int mwo_sgf_vertex(const uint64_t* codes, int n, const int32_t* src, double* P, double* etau) {
+    if (n < 2 || n % 2) return -1;
+    std::vector<uint64_t> e(codes, codes + (size_t)n * n * n);
+    VertexSystem VS = build_vertex_system(e, n);
+    std::vector<double> Pv;
+    int s[3] = {src[0], src[1], src[2]};
+    if (!sgf_vertex(VS, s, Pv, etau)) return -2;
+    std::copy(Pv.begin(), Pv.end(), P);
+    return 0;
+}
+
+// Voxelisation + classification of one transition cube of a structure.
+// out_codes: n^3 vertex cell codes; out_cls: [class, axis].
+int mwo_build_cube(const double* cond, int n_cond, int n_nets, const double* diel, int n_diel,
+                   const double* layer_z0, const double* layer_eps, int n_layers, const double* win,
+                   const int32_t* bc, const double* centre, double R, int n, uint64_t* out_codes,
+                   int32_t* out_cls) {
+    Structure S = make_structure(cond, n_cond, n_nets, diel, n_diel, layer_z0, layer_eps, n_layers, win, bc);
+    Cube C;
+    build_cube(S, centre, R, n, C);
+    std::copy(C.e.begin(), C.e.end(), out_codes);
+    out_cls[0] = C.cls;
+    out_cls[1] = C.axis;
+    return 0;
+}
+
+// Largest conductor-free cube query (half-size and nearest net).
+int mwo_dist(const double* cond, int n_cond, int n_nets, const double* win, const int32_t* bc, const double* p,
+             double* d, int32_t* nearest) {
+    Structure S = make_structure(cond, n_cond, n_nets, nullptr, 0, nullptr, nullptr, 0, win, bc);
+    int who;
+    *d = structure_dist(S, p, &who);
+    *nearest = who;
+    return 0;
+}
+
+// Gaussian surface: returns g and |G|; faces as [axis, side, plane, lo3, hi3, area].
+int mwo_gauss(const double* cond, int n_cond, int n_nets, const double* win, const int32_t* bc, int master,
+              double* g, double* area, double* faces, int32_t* n_faces) {
+    Structure S = make_structure(cond, n_cond, n_nets, nullptr, 0, nullptr, nullptr, 0, win, bc);
+    Gauss G;
+    if (!build_gauss(S, master, G)) return -1;
+    *g = G.g;
+    *area = G.area;
+    *n_faces = (int32_t)G.faces.size();
+    for (size_t f = 0; f < G.faces.size(); ++f) {
+        double* o = faces + f * 10;
+        o[0] = G.faces[f].axis;
+        o[1] = G.faces[f].side;
+        o[2] = G.faces[f].plane;
+        for (int a = 0; a < 3; ++a) {
+            o[3 + a] = G.faces[f].lo[a];
+            o[6 + a] = G.faces[f].hi[a];
+        }
+        o[9] = G.faces[f].area;
+    }
+    return 0;
+}
+
+// Alg. 1 for master net `master`, walks first_walk .. first_walk+n_walks-1.
+// row/se: n_nets+1 entries (last = env).  score_net/score_w: per walk (may be
+// NULL).  stats: [walks, hops, micro_steps, cls0, cls1, cls2, br0..br3,
+// misses, env, hop_cap] (13 entries, may be NULL).  threads >= 1 splits the
+// walk range into contiguous blocks; results do not depend on it.
+int mwo_frw_extract(const double* cond, int n_cond, int n_nets, const double* diel, int n_diel,
+                    const double* layer_z0, const double* layer_eps, int n_layers, const double* win,
+                    const int32_t* bc, int master, uint64_t n_walks, uint64_t first_walk, uint64_t seed, int n,
+                    int hybrid, double abs_tol_rel, int threads, double* row, double* se, int32_t* score_net,
+                    double* score_w, uint64_t* stats) {
+    if (n < 4 || n % 2 || n_walks < 2) return -1;
+    Structure S = make_structure(cond, n_cond, n_nets, diel, n_diel, layer_z0, layer_eps, n_layers, win, bc);
+    Gauss G;
+    if (!build_gauss(S, master, G)) return -2;
+    double diag = 0;
+    for (int a = 0; a < 3; ++a) diag += (S.whi[a] - S.wlo[a]) * (S.whi[a] - S.wlo[a]);
+    FrwParams P{n, hybrid, abs_tol_rel * std::sqrt(diag), seed};
+    TableCache TC;
+    std::vector<int32_t> nets(n_walks);
+    std::vector<double> om(n_walks);
+    if (threads < 1) threads = 1;
+    std::vector<WalkStats> wst(threads);
+    std::atomic<int> failed{0};
+    auto worker = [&](int tid) {
+        uint64_t lo = n_walks * (uint64_t)tid / threads, hi = n_walks * (uint64_t)(tid + 1) / threads;
+        for (uint64_t k = lo; k < hi && !failed; ++k) {
+            int net;
+            double o;
+            if (!frw_walk(S, G, master, P, TC, first_walk + k, &net, &o, wst[tid])) {
+                failed = 1;
+                return;
+            }
+            nets[k] = net;
+            om[k] = o;
+        }
+    };
+    if (threads == 1) {
+        worker(0);
+    } else {
+        std::vector<std::thread> th;
+        for (int t = 0; t < threads; ++t) th.emplace_back(worker, t);
+        for (auto& t : th) t.join();
+    }
+    if (failed) return -3;
+    // Alg. 1 scoring: C_ik accumulates omega of walks ending on k; averages
+    // over n_path.  Standard errors from the per-net second moments.
+    int K = n_nets + 1;
+    std::vector<double> s1(K, 0.0), s2(K, 0.0);
+    for (uint64_t k = 0; k < n_walks; ++k) {
+        s1[nets[k]] += om[k];
+        s2[nets[k]] += om[k] * om[k];
+    }
+    double nw = (double)n_walks;
+    for (int j = 0; j < K; ++j) {
+        double m = s1[j] / nw;
+        row[j] = m;
+        double var = (s2[j] / nw - m * m) / (nw - 1);
+        se[j] = std::sqrt(std::max(var, 0.0));
+    }
+    if (score_net)
+        for (uint64_t k = 0; k < n_walks; ++k) score_net[k] = nets[k];
+    if (score_w)
+        for (uint64_t k = 0; k < n_walks; ++k) score_w[k] = om[k];
+    if (stats) {
+        WalkStats tot;
+        for (auto& w : wst) {
+            tot.hops += w.hops;
+            tot.micro_steps += w.micro_steps;
+            for (int c = 0; c < 3; ++c) tot.hop_class[c] += w.hop_class[c];
+            for (int c = 0; c < 4; ++c) tot.first_branch[c] += w.first_branch[c];
+            tot.env += w.env;
+            tot.hop_cap += w.hop_cap;
+        }
+        stats[0] = n_walks;
+        stats[1] = tot.hops;
+        stats[2] = tot.micro_steps;
+        for (int c = 0; c < 3; ++c) stats[3 + c] = tot.hop_class[c];
+        for (int c = 0; c < 4; ++c) stats[6 + c] = tot.first_branch[c];
+        stats[10] = TC.misses.load();
+        stats[11] = tot.env;
+        stats[12] = tot.hop_cap;
+    }
+    return 0;
+}
+
+}  // extern "C"

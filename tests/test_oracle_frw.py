@@ -1,0 +1,118 @@
+"""Oracle pins for Alg. 1 (FRW capacitance extraction).
+
+Closed forms: parallel plates with uniform, column (parallel) and series
+dielectrics.  Maxwell capacitance-matrix properties: reciprocity C_ij = C_ji,
+rows summing to zero with the grounded enclosure, C_mm > 0, C_mj <= 0.
+Theorem 1 at the FRW level: the hybrid strategy (Sec. III-C) and an
+all-MicroWalk run estimate the same row.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+def _z(a, b, sa, sb):
+    return abs(a - b) / np.sqrt(sa ** 2 + sb ** 2)
+
+
+@pytest.mark.parametrize("variant,hybrid", [("uniform", 1), ("uniform", 0), ("columns", 0),
+                                            ("checkerboard", 1)])
+def test_parallel_plates_closed_form(oracle_lib, variant, hybrid):
+    st = W.parallel_plates(variant)
+    r = oracle_lib.frw_extract(st, 0, 40000, seed=3, threads=8, hybrid=hybrid)
+    exact = W.parallel_plates_exact(variant)
+    assert abs(r["row"][0] - exact) < 3 * r["se"][0], (r["row"], r["se"], exact)
+    assert abs(r["row"][1] + exact) < 3 * r["se"][1]
+    assert r["row"][2] == 0.0
+
+
+def test_parallel_plates_series_soft(oracle_lib):
+    """Series stack: voxel snapping of the interface gives a small bias that
+    must shrink as the lattice is refined (reported as z-scores)."""
+    st = W.parallel_plates("series")
+    exact = W.parallel_plates_exact("series")
+    zs = {}
+    for n in (8, 16):
+        r = oracle_lib.frw_extract(st, 0, 40000, seed=4, threads=8, n_cells=n)
+        zs[n] = (r["row"][0] - exact) / r["se"][0]
+    assert abs(zs[16]) < 4.0, zs
+
+
+@pytest.fixture(scope="module")
+def c2_rows(oracle_lib):
+    st = W.c2_structure()
+    return {m: oracle_lib.frw_extract(st, m, 60000, seed=10 + m, threads=8, scores=True)
+            for m in (0, 1)}
+
+
+def test_c2_reciprocity(c2_rows):
+    r0, r1 = c2_rows[0], c2_rows[1]
+    assert _z(r0["row"][1], r1["row"][0], r0["se"][1], r1["se"][0]) < 3
+
+
+def test_c2_maxwell_signs_and_row_sum(c2_rows):
+    for m, r in c2_rows.items():
+        row, se = r["row"], r["se"]
+        assert row[m] > 0
+        for j in range(len(row)):
+            if j != m:
+                assert row[j] <= 3 * se[j]
+        w = r["w"]
+        assert abs(w.mean()) < 3 * w.std() / np.sqrt(w.size)
+        assert abs(row.sum() - w.mean()) < 1e-12 * max(1.0, abs(row).sum())
+
+
+def test_c2_scores_reproduce_row(c2_rows):
+    """C_mj = (sum of omega over walks ending on j) / n_path (Alg. 1)."""
+    r = c2_rows[0]
+    K = len(r["row"])
+    s = np.bincount(r["net"], weights=r["w"], minlength=K) / r["w"].size
+    assert np.allclose(s, r["row"], rtol=1e-12, atol=1e-15)
+
+
+def test_c2_hybrid_equals_all_microwalk(oracle_lib, c2_rows):
+    """Theorem 1 at FRW level: stratified cubes sampled from the exact SGF
+    table give the same row as MicroWalk on every cube."""
+    st = W.c2_structure()
+    r_mw = oracle_lib.frw_extract(st, 0, 60000, seed=99, threads=8, hybrid=0)
+    r_hy = c2_rows[0]
+    assert r_mw["stats"]["cls_stratified"] + r_mw["stats"]["cls_uniform"] > 0
+    for j in range(len(r_hy["row"])):
+        assert _z(r_hy["row"][j], r_mw["row"][j], r_hy["se"][j], r_mw["se"][j]) < 3.5
+
+
+def test_resume_is_bit_identical(oracle_lib):
+    """Walk outcomes depend only on (seed, walk id): a run split at walk k
+    reproduces the scores of the uninterrupted run."""
+    st = W.c2_structure()
+    a = oracle_lib.frw_extract(st, 0, 400, seed=5, threads=1, scores=True)
+    b1 = oracle_lib.frw_extract(st, 0, 150, seed=5, threads=1, scores=True)
+    b2 = oracle_lib.frw_extract(st, 0, 250, seed=5, first_walk=150, threads=4, scores=True)
+    assert (np.concatenate([b1["net"], b2["net"]]) == a["net"]).all()
+    assert (np.concatenate([b1["w"], b2["w"]]) == a["w"]).all()
+
+
+def test_gaussian_surface_c2(oracle_lib):
+    """G is the master box expanded by half the gap to the nearest conductor."""
+    st = W.c2_structure()
+    g, area, faces = oracle_lib.gauss(st, 0)
+    assert g == pytest.approx(0.05, abs=1e-7)
+    L, wdt, t = 1.6 + 2 * g, 0.1 + 2 * g, 0.1 + 2 * g
+    assert area == pytest.approx(2 * (L * wdt + L * t + wdt * t), rel=1e-6)
+    assert len(faces) == 6
+
+
+def test_cube_classification(oracle_lib):
+    """Uniform, z-stratified and non-stratified cubes of the C2 structure."""
+    st = W.c2_structure()
+    _, cls = oracle_lib.build_cube(st, [1.0, 1.0, 0.2], 0.05, 16)
+    assert cls[0] == 0
+    _, cls = oracle_lib.build_cube(st, [1.0, 1.0, 0.5], 0.05, 16)
+    assert cls == (1, 2)
+    _, cls = oracle_lib.build_cube(st, [1.0, 0.9, 0.45], 0.049, 16)
+    assert cls == (1, 2)  # coating slab above the wire spans the cube
+    _, cls = oracle_lib.build_cube(st, [1.83, 0.9, 0.35], 0.029, 16)
+    assert cls == (1, 0)  # wire end: coating face normal to x
+    _, cls = oracle_lib.build_cube(st, [1.83, 0.97, 0.35], 0.029, 16)
+    assert cls[0] == 2  # coating edge at the wire end

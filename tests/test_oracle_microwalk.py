@@ -1,0 +1,217 @@
+"""Oracle pins for Alg. 3 (MicroWalk) and the FD surface Green's function.
+
+Theorem 1: the exit point of Alg. 3 is distributed as P_eps = e_c^T A_II^-1 A_IB
+(Eq. 8).  Prop. 2 / Eq. (11): E(tau) = e_c^T A_II^-1 1, about 0.3373 N^2 for
+single-dielectric cubes.  The library solve (scipy sparse LU) and closed-form
+harmonic functions are the independent references.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import pins
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    d = {}
+    for line in open(os.path.join(GOLD, name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            k, *v = line.split()
+            d[k] = [float(x) for x in v] if "/" not in v[0] else v
+    return d
+
+
+def test_c1_solve_matches_independent_values(oracle_lib):
+    g = _golden("c1_vertex_sgf.txt")
+    e = workloads.c1_eps()
+    codes = oracle_lib.vertex_codes(e).reshape(8, 8, 8)
+    P, et = oracle_lib.sgf_vertex(codes)
+    assert et == pytest.approx(g["etau"][0], rel=1e-4)
+    faces = P.reshape(6, -1).sum(axis=1)
+    assert np.allclose(faces, g["face_total"], rtol=1e-4)
+    assert P.min() == pytest.approx(g["node_min"][0], rel=1e-3)
+    assert P.max() == pytest.approx(g["node_max"][0], rel=1e-3)
+    u = np.full((8, 8, 8), 3.9, dtype=np.float32)
+    Pu, etu = oracle_lib.sgf_vertex(oracle_lib.vertex_codes(u).reshape(8, 8, 8))
+    assert np.allclose(Pu.reshape(6, -1).sum(axis=1), 1 / 6, atol=1e-12)
+    M = 7
+    assert Pu[5 * M * M + 3 * M + 3] == pytest.approx(g["uniform8_face_centre_pz"][0], rel=1e-5)
+    assert etu == pytest.approx(g["uniform8_etau"][0], rel=1e-4)
+
+
+@pytest.mark.parametrize("n", [4, 6, 8])
+def test_cg_solve_equals_sparse_lu(oracle_lib, n):
+    """The oracle's CG SGF equals a sparse-LU absorbing-chain solve (P8)."""
+    rng = np.random.default_rng(n)
+    e = workloads.random_cube(n, rng)
+    links, _ = oracle_lib.vertex_thresholds(e)
+    P_lu, et_lu = pins.vertex_exit_distribution(links, n)
+    P_cg, et_cg = oracle_lib.sgf_vertex(oracle_lib.vertex_codes(e).reshape(n, n, n))
+    assert np.allclose(P_cg, P_lu, rtol=1e-10, atol=1e-14)
+    assert et_cg == pytest.approx(et_lu, rel=1e-10)
+    assert P_cg.sum() == pytest.approx(1.0, abs=1e-12)
+
+
+@pytest.mark.parametrize("n,walks", [(4, 200000), (6, 200000), (8, 300000)])
+def test_theorem1_walk_histogram(oracle_lib, n, walks):
+    """Alg. 3 hits vs the FDM SGF of the same lattice, chi-square (Theorem 1)."""
+    rng = np.random.default_rng(100 + n)
+    e = workloads.random_cube(n, rng)
+    links, _ = oracle_lib.vertex_thresholds(e)
+    P, et = pins.vertex_exit_distribution(links, n)
+    hits, steps = oracle_lib.microwalk(e, 0, walks, seed=11)
+    counts = np.bincount(hits, minlength=P.size)
+    p, stat, dof = pins.chi_square_p(counts, P)
+    assert p > 1e-4, (stat, dof)
+    se = steps.std() / np.sqrt(walks)
+    assert abs(steps.mean() - et) < 4 * se
+
+
+def test_theorem1_c1(oracle_lib):
+    e = workloads.c1_eps()
+    links, _ = oracle_lib.vertex_thresholds(e)
+    P, et = pins.vertex_exit_distribution(links, 8)
+    hits, steps = oracle_lib.microwalk(e, 0, 100000, seed=0)
+    p, stat, dof = pins.chi_square_p(np.bincount(hits, minlength=P.size), P)
+    assert p > 1e-4, (stat, dof)
+    assert abs(steps.mean() - et) < 4 * steps.std() / np.sqrt(steps.size)
+
+
+def test_theorem1_cell_lattice(oracle_lib):
+    N = 5
+    rng = np.random.default_rng(21)
+    e = workloads.random_cube(N, rng)
+    links, _ = oracle_lib.cell_thresholds(e)
+    P, et = pins.cell_exit_distribution(links, N)
+    hits, steps = oracle_lib.microwalk(e, 1, 300000, seed=4)
+    p, stat, dof = pins.chi_square_p(np.bincount(hits, minlength=P.size), P)
+    assert p > 1e-4, (stat, dof)
+    assert abs(steps.mean() - et) < 4 * steps.std() / np.sqrt(steps.size)
+
+
+def test_expected_length_constant(oracle_lib):
+    """Prop. 2: E(tau) / N^2 tends to 0.3373 for single-dielectric cubes.
+    Richardson extrapolation in 1/n^2 from n = 16 and 24."""
+    c = float(_golden("paper_constants.txt")["etau_over_n2"][0])
+    r = {}
+    for n in (16, 24):
+        codes = np.full((n, n, n), 65536 * 2, dtype=np.uint64)
+        _, et = oracle_lib.sgf_vertex(codes)
+        r[n] = et / n ** 2
+    lim = (r[24] * 24 ** 2 - r[16] * 16 ** 2) / (24 ** 2 - 16 ** 2)
+    assert abs(lim - c) < 5e-4
+    assert abs(r[24] - c) < 2e-3
+
+
+def _cube_symmetries():
+    for perm in itertools.permutations(range(3)):
+        for flips in itertools.product((False, True), repeat=3):
+            yield perm, flips
+
+
+def test_uniform_sgf_has_cube_symmetry(oracle_lib):
+    """A uniform cube's SGF is invariant under the 48 symmetries of the cube."""
+    n = 6
+    codes = np.full((n, n, n), 65536 * 3, dtype=np.uint64)
+    P, _ = oracle_lib.sgf_vertex(codes)
+    nodes = pins.vertex_boundary_nodes(n)
+    lookup = {tuple(x): h for h, x in enumerate(nodes)}
+    for perm, flips in _cube_symmetries():
+        img = nodes[:, perm].copy()
+        for a in range(3):
+            if flips[a]:
+                img[:, a] = n - img[:, a]
+        idx = np.array([lookup[tuple(x)] for x in img])
+        assert np.allclose(P[idx], P, atol=1e-14)
+
+
+def test_stratified_sgf_symmetry(oracle_lib):
+    """A cube stratified along z keeps the 8 symmetries fixing the z axis."""
+    n = 6
+    rng = np.random.default_rng(8)
+    layers = rng.choice([2.5, 7.0, 25.0], size=n)
+    codes = np.broadcast_to((layers * 65536).astype(np.uint64)[:, None, None], (n, n, n)).copy()
+    P, _ = oracle_lib.sgf_vertex(codes)
+    nodes = pins.vertex_boundary_nodes(n)
+    lookup = {tuple(x): h for h, x in enumerate(nodes)}
+    for perm in ((0, 1, 2), (1, 0, 2)):
+        for fx, fy in itertools.product((False, True), repeat=2):
+            img = nodes[:, list(perm)].copy()
+            if fx:
+                img[:, 0] = n - img[:, 0]
+            if fy:
+                img[:, 1] = n - img[:, 1]
+            idx = np.array([lookup[tuple(x)] for x in img])
+            assert np.allclose(P[idx], P, atol=1e-14)
+
+
+def test_harmonic_linear_in_uniform_cube(oracle_lib):
+    """Linear and x^2 - y^2 potentials are discrete harmonic in a uniform
+    cube: sum_b P_b phi(x_b) = phi(centre) (mean-value property, Eq. 2)."""
+    n = 8
+    codes = np.full((n, n, n), 65536 * 5, dtype=np.uint64)
+    nodes = pins.vertex_boundary_nodes(n).astype(float)
+    for src in ((4, 4, 4), (2, 5, 3), (1, 1, 6)):
+        P, _ = oracle_lib.sgf_vertex(codes, src)
+        for phi in (lambda x: x[:, 0], lambda x: x[:, 1], lambda x: x[:, 2],
+                    lambda x: x[:, 0] ** 2 - x[:, 1] ** 2):
+            s = np.array([src], dtype=float)
+            assert P @ phi(nodes) == pytest.approx(phi(s)[0], abs=1e-10)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_harmonic_series_stack(oracle_lib, axis):
+    """Planar layers normal to `axis`: the 1-D potential with continuous flux
+    (interface condition of Eq. 4) is exact on the lattice, so the SGF
+    reproduces it at every source node (pins the links of each axis)."""
+    n = 8
+    rng = np.random.default_rng(30 + axis)
+    layers = rng.choice([1.0, 2.5, 7.0, 25.0], size=n)
+    shape = [1, 1, 1]
+    shape[2 - axis] = n  # codes array is [k, j, i]
+    codes = np.broadcast_to((layers * 65536).astype(np.uint64).reshape(shape), (n, n, n)).copy()
+    phi_nodes = pins.series_potential(layers)
+    nodes = pins.vertex_boundary_nodes(n)
+    for src in ((4, 4, 4), (3, 6, 2), (6, 1, 5)):
+        P, _ = oracle_lib.sgf_vertex(codes, src)
+        assert P @ phi_nodes[nodes[:, axis]] == pytest.approx(phi_nodes[src[axis]], rel=1e-10)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_harmonic_invariant_direction(oracle_lib, axis):
+    """Permittivity constant along `axis` (random across it): the linear
+    potential along `axis` is exact at every node (parallel capacitor)."""
+    n = 8
+    rng = np.random.default_rng(40 + axis)
+    plane = rng.choice([1.0, 2.5, 7.0, 25.0], size=(n, n))
+    e = np.zeros((n, n, n))
+    if axis == 2:
+        e[:] = plane[None, :, :]
+    elif axis == 1:
+        e[:] = plane[:, None, :]
+    else:
+        e[:] = plane[:, :, None]
+    codes = (e * 65536).astype(np.uint64)
+    nodes = pins.vertex_boundary_nodes(n)
+    for src in ((4, 4, 4), (2, 3, 6)):
+        P, _ = oracle_lib.sgf_vertex(codes, src)
+        assert P @ nodes[:, axis] == pytest.approx(src[axis], abs=1e-10)
+
+
+def test_walk_mean_value_property(oracle_lib):
+    """Monte Carlo form of the same pin: mean of the series potential at the
+    walk's exit equals the centre value within 4 standard errors."""
+    n = 8
+    layers = np.array([2.5, 7.0, 25.0, 1.0, 2.5, 25.0, 7.0, 1.0])
+    e = np.broadcast_to(layers.reshape(n, 1, 1), (n, n, n)).astype(np.float32).copy()
+    phi_nodes = pins.series_potential(layers)
+    hits, _ = oracle_lib.microwalk(e, 0, 200000, seed=2)
+    z = pins.vertex_boundary_nodes(n)[hits, 2]
+    v = phi_nodes[z]
+    assert abs(v.mean() - phi_nodes[n // 2]) < 4 * v.std() / np.sqrt(v.size)

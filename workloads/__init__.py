@@ -1,0 +1,248 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module holds geometry and permittivity descriptions only (no part of the
+method's arithmetic).  The paper's test structures are proprietary industrial
+layouts; the generators here stand in for them with the same ingredients: IC
+interconnect wires as axis-aligned boxes, layered inter-layer dielectrics
+(eps 2.7 / 3.9), conformal eps 7.0 coatings and eps 25 high-k fills.
+
+All coordinates are float32 micrometres; boxes are half-open [lo, hi).
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+DIRICHLET, NEUMANN = 0, 1
+
+
+@dataclass
+class Structure:
+    cond: np.ndarray          # (n_cond, 6) float32: lo xyz, hi xyz
+    cond_net: np.ndarray      # (n_cond,) int32
+    n_nets: int
+    diel: np.ndarray          # (n_diel, 6) float32
+    diel_eps: np.ndarray      # (n_diel,) float32
+    layer_z0: np.ndarray      # (n_layers,) float32 (entry 0 unused: first layer from -inf)
+    layer_eps: np.ndarray     # (n_layers,) float32
+    win_lo: np.ndarray        # (3,) float32
+    win_hi: np.ndarray        # (3,) float32
+    bc: tuple = (DIRICHLET,) * 6
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_cond(self):
+        return int(self.cond.shape[0])
+
+    @property
+    def n_diel(self):
+        return int(self.diel.shape[0])
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float32)
+
+
+def make_structure(cond, nets, diel, diel_eps, layer_z0, layer_eps, win_lo, win_hi, bc, name="",
+                   meta=None):
+    cond = _f32(cond).reshape(-1, 6)
+    diel = _f32(diel).reshape(-1, 6)
+    return Structure(cond=cond, cond_net=np.asarray(nets, dtype=np.int32), n_nets=int(max(nets) + 1),
+                     diel=diel, diel_eps=_f32(diel_eps).reshape(-1), layer_z0=_f32(layer_z0),
+                     layer_eps=_f32(layer_eps), win_lo=_f32(win_lo), win_hi=_f32(win_hi),
+                     bc=tuple(int(b) for b in bc), name=name, meta=meta or {})
+
+
+def _grow(b, t):
+    b = np.asarray(b, dtype=np.float64)
+    return np.concatenate([b[:3] - t, b[3:] + t])
+
+
+# ---------------------------------------------------------------------------
+# Single transition cubes
+# ---------------------------------------------------------------------------
+def c1_eps():
+    """8^3-cell cube, eps 3.9 with an off-centre 3x4x5-cell eps 7.0 block at
+    cells x in [1,4), y in [1,5), z in [3,8); layout eps[k, j, i]."""
+    e = np.full((8, 8, 8), 3.9, dtype=np.float32)
+    e[3:8, 1:5, 1:4] = 7.0
+    return e
+
+
+C3_EPS = (2.5, 3.9, 7.0, 25.0)
+
+
+def random_cube(n, rng, k_max=6, eps_choices=C3_EPS, background=3.9):
+    """n^3 cube with 1..k_max random box inclusions (later boxes win)."""
+    e = np.full((n, n, n), background, dtype=np.float32)
+    k = int(rng.integers(1, k_max + 1))
+    half = (n + 1) // 2
+    for _ in range(k):
+        ext = rng.integers(1, half + 1, size=3)
+        org = np.array([rng.integers(0, n - ext[a] + 1) for a in range(3)])
+        val = eps_choices[int(rng.integers(0, len(eps_choices)))]
+        e[org[2]:org[2] + ext[2], org[1]:org[1] + ext[1], org[0]:org[0] + ext[0]] = val
+    return e
+
+
+def c3_sizes(count=4096, seed=3):
+    """(n, walks) of the batched-transition workload: n even, log-uniform in
+    [8, 32]; walks log-uniform in [1e3, 1e5]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        n = int(2 * round(np.exp(rng.uniform(np.log(8), np.log(32))) / 2))
+        w = int(round(np.exp(rng.uniform(np.log(1e3), np.log(1e5)))))
+        out.append((n, w))
+    return out
+
+
+def c3_cubes(count=4096, seed=3):
+    """Batched-transition workload: list of (eps grid, walks)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cubes = []
+    for _ in range(count):
+        n = int(2 * round(np.exp(rng.uniform(np.log(8), np.log(32))) / 2))
+        w = int(round(np.exp(rng.uniform(np.log(1e3), np.log(1e5)))))
+        cubes.append((random_cube(n, rng), w))
+    return cubes
+
+
+# ---------------------------------------------------------------------------
+# Structures
+# ---------------------------------------------------------------------------
+def parallel_plates(variant="uniform"):
+    """1x1x1 um window with symmetry walls, plates z in [0, 0.1] (net 0) and
+    z in [0.9, 1.0] (net 1); gap 0.8 um."""
+    cond = [[0, 0, 0, 1, 1, 0.1], [0, 0, 0.9, 1, 1, 1.0]]
+    diel, deps = [], []
+    z0, le = [0.0], [3.9]
+    if variant == "columns":
+        diel, deps = [[0.5, 0, 0, 1, 1, 1]], [7.0]
+    elif variant == "checkerboard":
+        diel, deps = [[0.5, 0, 0, 1, 0.5, 1], [0, 0.5, 0, 0.5, 1, 1]], [7.0, 7.0]
+    elif variant == "series":
+        z0, le = [0.0, 0.5], [3.9, 2.7]
+    elif variant != "uniform":
+        raise ValueError(variant)
+    return make_structure(cond, [0, 1], diel, deps, z0, le, [0, 0, 0], [1, 1, 1], (NEUMANN,) * 6,
+                          name="plates-" + variant)
+
+
+EPS0 = 8.8541878128e-3  # fF/um
+
+
+def parallel_plates_exact(variant="uniform"):
+    """Closed-form C_00 (= -C_01) of parallel_plates(variant), fF."""
+    d, A = 0.8, 1.0
+    if variant == "uniform":
+        return EPS0 * 3.9 * A / d
+    if variant in ("columns", "checkerboard"):
+        return EPS0 * (0.5 * 3.9 + 0.5 * 7.0) * A / d
+    if variant == "series":
+        return EPS0 * A / (0.4 / 3.9 + 0.4 / 2.7)
+    raise ValueError(variant)
+
+
+def c2_structure():
+    """Crossing wires in a 2x2x1 um grounded window: two x-directed wires at
+    z in [0.30, 0.40] (nets 0, 1) under two y-directed wires at z in
+    [0.60, 0.70] (nets 2, 3), 100 nm wide and thick, each with a 20 nm eps 7.0
+    coating; background eps 3.9 below z = 0.5 and 2.7 above."""
+    wires = [[0.2, 0.85, 0.30, 1.8, 0.95, 0.40],
+             [0.2, 1.05, 0.30, 1.8, 1.15, 0.40],
+             [0.85, 0.2, 0.60, 0.95, 1.8, 0.70],
+             [1.05, 0.2, 0.60, 1.15, 1.8, 0.70]]
+    coat = [_grow(w, 0.02) for w in wires]
+    return make_structure(wires, [0, 1, 2, 3], coat, [7.0] * 4, [0.0, 0.5], [3.9, 2.7],
+                          [0, 0, 0], [2, 2, 1], (DIRICHLET,) * 6, name="c2-crossing-wires")
+
+
+C4_STACK_Z0 = (0.0, 0.4, 0.6, 0.9, 1.1, 1.4, 1.6)
+C4_STACK_EPS = (3.9, 2.7, 3.9, 2.7, 3.9, 2.7, 3.9)
+
+
+def interconnect(side, tracks_per_layer, rng, height=2.0, highk_p=0.1, coat=0.02):
+    """Three metal layers (z in [0.45,0.55], [0.95,1.05], [1.45,1.55]; directions
+    x, y, x) of `tracks_per_layer` wires each, pitch U[0.08, 0.20] um, width
+    pitch/2, random length U[1, 20] um clamped to the window; 20 nm eps 7.0
+    coatings; each gap between neighbouring tracks gets an eps 25 fill over the
+    common length with probability highk_p."""
+    metal = ((0.45, 0.55, 0), (0.95, 1.05, 1), (1.45, 1.55, 0))
+    cond, diel, deps = [], [], []
+    fills = []
+    for (z_lo, z_hi, along) in metal:
+        pitch = rng.uniform(0.08, 0.20, size=tracks_per_layer)
+        width = pitch / 2
+        span = float(np.sum(pitch))
+        pos = side / 2 - span / 2
+        tracks = []
+        for t in range(tracks_per_layer):
+            lo_c = pos + (pitch[t] - width[t]) / 2
+            hi_c = lo_c + width[t]
+            pos += pitch[t]
+            L = min(rng.uniform(1.0, 20.0), side - 0.2)
+            start = rng.uniform(0.1, side - 0.1 - L)
+            if along == 0:
+                box = [start, lo_c, z_lo, start + L, hi_c, z_hi]
+            else:
+                box = [lo_c, start, z_lo, hi_c, start + L, z_hi]
+            tracks.append((box, start, start + L, lo_c, hi_c))
+            cond.append(box)
+        for t in range(tracks_per_layer - 1):
+            if rng.uniform() < highk_p:
+                a, b = tracks[t], tracks[t + 1]
+                s0, s1 = max(a[1], b[1]), min(a[2], b[2])
+                if s1 <= s0:
+                    continue
+                g0, g1 = a[4], b[3]
+                if along == 0:
+                    fills.append([s0, g0, z_lo, s1, g1, z_hi])
+                else:
+                    fills.append([g0, s0, z_lo, g1, s1, z_hi])
+    for box in cond:
+        diel.append(_grow(box, coat))
+        deps.append(7.0)
+    for f in fills:
+        diel.append(f)
+        deps.append(25.0)
+    return cond, diel, deps
+
+
+def c4_structure(seed=4):
+    """20x20x2 um three-layer interconnect window, 64 wires per layer (192
+    nets), layered ILD 3.9/2.7, conformal eps 7.0 coatings and eps 25 fills."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    side = 20.0
+    cond, diel, deps = interconnect(side, 64, rng)
+    st = make_structure(cond, list(range(len(cond))), diel, deps, C4_STACK_Z0, C4_STACK_EPS,
+                        [0, 0, 0], [side, side, 2.0], (DIRICHLET,) * 6, name="c4-interconnect")
+    # master: middle-layer wire nearest to the window centre
+    mid = [i for i, b in enumerate(st.cond) if b[2] > 0.9 and b[5] < 1.1]
+    cen = [(st.cond[i][:3] + st.cond[i][3:]) / 2 for i in mid]
+    d = [max(abs(c[0] - 10), abs(c[1] - 10)) for c in cen]
+    st.meta["master"] = int(mid[int(np.argmin(d))])
+    return st
+
+
+def request_structure(K, rng):
+    """A serving request: a window built like the large structure with
+    ceil(K/3) tracks per layer and side max(2, 20*sqrt(K/192)) um."""
+    tracks = int(np.ceil(K / 3))
+    side = float(max(2.0, 20.0 * np.sqrt(K / 192.0)))
+    cond, diel, deps = interconnect(side, tracks, rng)
+    return make_structure(cond, list(range(len(cond))), diel, deps, C4_STACK_Z0, C4_STACK_EPS,
+                          [0, 0, 0], [side, side, 2.0], (DIRICHLET,) * 6, name="req-%d" % K)
+
+
+def c5_requests(count=2000, seed=5):
+    """Serving workload: (structure, master, walk budget, seed) per request."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(count):
+        K = int(round(np.exp(rng.uniform(np.log(4), np.log(200)))))
+        st = request_structure(K, rng)
+        master = int(rng.integers(0, st.n_nets))
+        budget = int(round(np.exp(rng.uniform(np.log(1e5), np.log(1e7)))))
+        out.append((st, master, budget, i))
+    return out
