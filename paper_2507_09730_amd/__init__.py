@@ -1,0 +1,136 @@
+"""libmwalk: FRW capacitance extraction with MicroWalk transitions on MI355X.
+
+Thin ctypes binding of the C ABI declared in ``include/libmwalk.h`` (same
+names, argument marshalling only).  Device memory and streams come from
+PyTorch; every step of the method runs in the library's HIP kernels.  Importing
+this package raises ImportError when the built library is missing: there is
+no fallback implementation.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmwalk.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libmwalk.so is not built (run __graft_entry__.build() or "
+                      "python paper_2507_09730_amd/build.py)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MW_OK, MW_EINVAL, MW_ENOMEM, MW_EDEVICE, MW_EBUSY, MW_ENOTREADY, MW_EGEOM, MW_ELIMIT = \
+    0, -1, -2, -3, -4, -5, -6, -7
+MW_LATTICE_VERTEX, MW_LATTICE_CELL = 0, 1
+MW_MAX_REGIONS = 16
+_NAMES = {-1: "MW_EINVAL", -2: "MW_ENOMEM", -3: "MW_EDEVICE", -4: "MW_EBUSY",
+          -5: "MW_ENOTREADY", -6: "MW_EGEOM", -7: "MW_ELIMIT"}
+
+
+class MWError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_NAMES.get(status, status), msg))
+        self.status = status
+
+
+_lib.mw_last_error.restype = ctypes.c_char_p
+
+
+def mw_last_error():
+    return _lib.mw_last_error().decode()
+
+
+def _check(rc):
+    if rc != MW_OK:
+        raise MWError(rc, mw_last_error())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+U64, I32, U32 = ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32
+
+
+def mw_init(device=0):
+    _check(_lib.mw_init(I32(device)))
+
+
+class mw_tune(ctypes.Structure):
+    _fields_ = [("tile_form", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32),
+                ("refill_every", ctypes.c_int32), ("item_walks", ctypes.c_int32)]
+
+
+def mw_transition(eps, n_walks, lattice=MW_LATTICE_VERTEX, first_walk=0, seed=0, cube_index=0,
+                  hits=None, steps=None, want_steps=True, stream=None):
+    """Alg. 3 on one cube.  eps: CUDA float32 tensor (n, n, n) indexed
+    [k, j, i].  Returns (hits, steps) int32 CUDA tensors."""
+    import torch
+    assert eps.is_cuda and eps.dtype == torch.float32 and eps.is_contiguous()
+    n = int(eps.shape[0])
+    assert eps.shape == (n, n, n)
+    if hits is None:
+        hits = torch.empty(n_walks, dtype=torch.int32, device=eps.device)
+    if steps is None and want_steps:
+        steps = torch.empty(n_walks, dtype=torch.int32, device=eps.device)
+    _check(_lib.mw_transition(_ptr(eps), I32(n), I32(lattice), U64(n_walks), U64(first_walk),
+                              U64(seed), U32(cube_index), _ptr(hits), _ptr(steps), _stream(stream)))
+    return hits, steps
+
+
+def pack_cubes(eps_list, device="cuda"):
+    """Concatenates cube grids into one device buffer: (eps_cat, n_cells, eps_off)."""
+    import torch
+    ns = np.array([int(e.shape[0]) for e in eps_list], dtype=np.int32)
+    cells = ns.astype(np.int64) ** 3
+    eps_off = np.zeros(len(eps_list), dtype=np.int64)
+    if len(eps_list):
+        eps_off[1:] = np.cumsum(cells)[:-1]
+        flat = np.concatenate([np.asarray(e, dtype=np.float32).reshape(-1) for e in eps_list])
+        eps_cat = torch.from_numpy(flat).to(device)
+    else:
+        eps_cat = torch.empty(1, device=device)
+    return eps_cat, ns, eps_off
+
+
+def mw_transition_batch(eps_list, walks, lattice=MW_LATTICE_VERTEX, seed=0, tune=None,
+                        want_steps=True, device="cuda", stream=None, packed=None, out=None):
+    """Many cubes in one persistent launch.  eps_list: list of (n, n, n)
+    float32 arrays (or packed=(eps_cat, n_cells, eps_off) from pack_cubes);
+    walks: walks per cube.  Returns (hits_cat, steps_cat, out_off) with cube
+    c's results at out_off[c]."""
+    import torch
+    eps_cat, ns, eps_off = packed if packed is not None else pack_cubes(eps_list, device)
+    n_cubes = len(ns)
+    walks = np.asarray(walks, dtype=np.uint64)
+    out_off = np.zeros(n_cubes, dtype=np.int64)
+    if n_cubes:
+        out_off[1:] = np.cumsum(walks.astype(np.int64))[:-1]
+    total = int(walks.sum())
+    if out is not None:
+        hits, steps = out
+    else:
+        hits = torch.empty(max(total, 1), dtype=torch.int32, device=eps_cat.device)
+        steps = (torch.empty(max(total, 1), dtype=torch.int32, device=eps_cat.device)
+                 if want_steps else None)
+    t = None
+    if tune is not None:
+        t = mw_tune(*[int(tune.get(k, 0)) for k in ("tile_form", "waves_per_wg", "refill_every",
+                                                    "item_walks")])
+    _check(_lib.mw_transition_batch(
+        I32(n_cubes), _ptr(eps_cat), eps_off.ctypes.data_as(ctypes.c_void_p),
+        ns.ctypes.data_as(ctypes.c_void_p), I32(lattice), walks.ctypes.data_as(ctypes.c_void_p),
+        out_off.ctypes.data_as(ctypes.c_void_p), U64(seed), _ptr(hits), _ptr(steps),
+        ctypes.byref(t) if t is not None else None, _stream(stream)))
+    return hits[:total], (steps[:total] if steps is not None else None), out_off
+
+
+EXPORTS = ("mw_last_error", "mw_init", "mw_transition", "mw_transition_batch",
+           "mw_structure_create", "mw_structure_destroy", "frw_extract")

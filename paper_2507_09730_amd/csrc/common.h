@@ -1,0 +1,112 @@
+// common.h — status handling, HIP checks and small device helpers shared by
+// the libmwalk translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "../../include/libmwalk.h"
+
+namespace mw {
+
+// Thread-local message of the last failure (mw_last_error).
+void set_error(const char* fmt, ...);
+void clear_error();
+
+struct Fail {
+    mw_status code;
+};
+
+#define MW_REQUIRE(cond, code, ...)          \
+    do {                                     \
+        if (!(cond)) {                       \
+            ::mw::set_error(__VA_ARGS__);    \
+            throw ::mw::Fail{code};          \
+        }                                    \
+    } while (0)
+
+#define MW_HIP(call)                                                                             \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) {                                                                  \
+            ::mw::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__,     \
+                            __LINE__);                                                           \
+            throw ::mw::Fail{e_ == hipErrorOutOfMemory ? MW_ENOMEM : MW_EDEVICE};                \
+        }                                                                                        \
+    } while (0)
+
+// Runs body, maps failures to status codes; nothing escapes the C ABI.
+template <class F>
+mw_status guarded(F&& body) {
+    try {
+        clear_error();
+        body();
+        return MW_OK;
+    } catch (const Fail& f) {
+        return f.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return MW_ENOMEM;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return MW_EDEVICE;
+    }
+}
+
+// Optional fault injection for allocation-failure tests:
+// MWALK_FAULT=alloc:<k> makes the k-th device allocation (1-based) fail.
+bool inject_alloc_failure();
+
+// Device allocation helpers (throw Fail on error).
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Ten rounds; each
+// round multiplies counter words 0 and 2 by the round multipliers, mixes the
+// high products with the other two words and the round key, and the key
+// advances by the Weyl increments.  Key words are wave-uniform, so the key
+// schedule runs on the scalar unit.
+struct Rand4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ Rand4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                          uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t m2 = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t n0 = (uint32_t)(m2 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)m2;
+        c3 = (uint32_t)m0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Rand4{c0, c1, c2, c3};
+}
+
+enum : uint32_t { PURPOSE_MICROWALK = 0, PURPOSE_GAUSS = 1, PURPOSE_FIRST = 2, PURPOSE_TABLE = 3 };
+
+__device__ __forceinline__ uint32_t ctr_hi(uint64_t walk, uint32_t purpose) {
+    return (uint32_t)((walk >> 32) & 0xffffffu) | (purpose << 24);
+}
+
+// Exact T = ceil(S * 2^32 / S5) for 0 < S <= S5 < 2^32 (no 64-bit division):
+// binary64 estimate, then an integer correction.
+__device__ __forceinline__ uint32_t ceil_threshold(uint64_t S, uint64_t S5) {
+    double q = (double)(S << 32) / (double)S5;
+    uint64_t t = (uint64_t)ceil(q);
+    const uint64_t num = S << 32;
+    if (t * S5 < num) ++t;
+    if (t > 0 && (t - 1) * S5 >= num) --t;
+    return (uint32_t)t;
+}
+
+}  // namespace mw

@@ -1,0 +1,594 @@
+// microwalk.hip — Alg. 3 (MicroWalk) on explicit voxelised transition cubes:
+// mw_transition (one cube) and mw_transition_batch (many cubes of uneven
+// size in one persistent launch).
+//
+// Per cube a prep kernel turns the eps grid into one of three tables; the
+// walk kernel stages it in LDS and runs walks lane-parallel.  Every step is
+// integer work: one Philox word, five compares against the node's
+// thresholds (or against prefix sums with mulhi(u, S5), which selects the
+// same direction), one index update and one LDS load.  Walks are refilled
+// wave-wide (ballot + one LDS atomic) at group boundaries, so each walk's
+// Philox words are word-aligned (group g uses counter c0 = g).
+//
+// Tile forms (all use a padded node grid so that reaching the cube boundary
+// is detected by a sentinel in the loaded data, not by coordinate tests):
+//   1 thresholds in LDS: T4[P^3] then T0..T3[P^3] as uint4; boundary nodes
+//     have T4 = 0 (an interior node always has T4 >= 1).
+//   2 cell codes in LDS (vertex lattice, large n): (n+2)^3 codes with a
+//     border of sentinel cells 2^29; the six link codes of a node are sums of
+//     its eight surrounding cells, recomputed per step.
+//   3 thresholds as form 1, read from global memory (cubes too large for
+//     LDS).
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+
+namespace mw {
+namespace {
+
+constexpr int FORM_TLDS = 1, FORM_CODES = 2, FORM_TGLOBAL = 3;
+constexpr uint32_t SENTINEL_CELL = 1u << 29;
+constexpr uint32_t LDS_TABLE_WORDS = 40704;  // 159 KiB of the 160 KiB LDS
+
+struct CubeDev {
+    const float* eps;
+    uint32_t* table;
+    int32_t* hits;
+    int32_t* steps;
+    uint64_t walk0;
+    uint64_t n_walks;
+    int32_t n, lattice, form, P;
+    uint32_t table_words;  // multiple of 4
+    uint32_t t4_words;     // forms 1/3: words before the uint4 block
+    uint32_t c1;
+    int32_t start;
+};
+
+struct Item {
+    int32_t cube;
+    int32_t pad;
+    uint64_t w_begin, w_end;
+};
+
+// -------------------------------------------------------------------------
+// Table preparation.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t vcode(const float* eps, int n, int i, int j, int k) {
+    return (uint32_t)rintf(eps[((size_t)k * n + j) * n + i] * 65536.0f);
+}
+
+// Five thresholds from six link codes.
+__device__ __forceinline__ void thresholds6(const uint32_t g[6], uint32_t T[5]) {
+    uint64_t S = 0, S5 = 0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) S5 += g[d];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        S += g[k];
+        T[k] = ceil_threshold(S, S5);
+    }
+}
+
+__global__ void prep_kernel(const CubeDev* __restrict__ cubes, int* bad) {
+    const CubeDev C = cubes[blockIdx.y];
+    const int P = C.P, n = C.n;
+    const uint32_t nodes = (uint32_t)P * P * P;
+    const uint32_t cells = (uint32_t)n * n * n;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < cells; v += gridDim.x * blockDim.x) {
+        const float e = C.eps[v];
+        if (!(e >= 1e-3f && e <= 1e3f)) atomicOr(bad, 1);
+    }
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nodes; v += gridDim.x * blockDim.x) {
+        const int i = v % P, j = (v / P) % P, k = v / (P * P);
+        if (C.form == FORM_CODES) {
+            // padded cell (i,j,k) = real cell (i-1, j-1, k-1)
+            const bool real = i >= 1 && i <= n && j >= 1 && j <= n && k >= 1 && k <= n;
+            C.table[v] = real ? vcode(C.eps, n, i - 1, j - 1, k - 1) : SENTINEL_CELL;
+            continue;
+        }
+        uint32_t T[5] = {0, 0, 0, 0, 0};
+        if (C.lattice == MW_LATTICE_VERTEX) {
+            if (i >= 1 && i < n && j >= 1 && j < n && k >= 1 && k < n) {
+                uint32_t c[2][2][2];
+#pragma unroll
+                for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+                    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                        for (int dx = 0; dx < 2; ++dx) c[dz][dy][dx] = vcode(C.eps, n, i - 1 + dx, j - 1 + dy, k - 1 + dz);
+                uint32_t g[6];
+                g[0] = c[0][0][0] + c[0][1][0] + c[1][0][0] + c[1][1][0];
+                g[1] = c[0][0][1] + c[0][1][1] + c[1][0][1] + c[1][1][1];
+                g[2] = c[0][0][0] + c[0][0][1] + c[1][0][0] + c[1][0][1];
+                g[3] = c[0][1][0] + c[0][1][1] + c[1][1][0] + c[1][1][1];
+                g[4] = c[0][0][0] + c[0][0][1] + c[0][1][0] + c[0][1][1];
+                g[5] = c[1][0][0] + c[1][0][1] + c[1][1][0] + c[1][1][1];
+                thresholds6(g, T);
+            }
+        } else {
+            // cell lattice: padded index (x+1) for node coordinate x in [-1, N]
+            const int x = i - 1, y = j - 1, z = k - 1;
+            if (x >= 0 && x < n && y >= 0 && y < n && z >= 0 && z < n) {
+                const double ev = (double)C.eps[((size_t)z * n + y) * n + x];
+                const int q[6][3] = {{x - 1, y, z}, {x + 1, y, z}, {x, y - 1, z},
+                                     {x, y + 1, z}, {x, y, z - 1}, {x, y, z + 1}};
+                uint32_t g[6];
+#pragma unroll
+                for (int d = 0; d < 6; ++d) {
+                    const int a = q[d][0], b = q[d][1], cc = q[d][2];
+                    if (a >= 0 && a < n && b >= 0 && b < n && cc >= 0 && cc < n) {
+                        const double ei = (double)C.eps[((size_t)cc * n + b) * n + a];
+                        g[d] = (uint32_t)rint(ei / (ei + ev) * 16777216.0);
+                    } else {
+                        g[d] = 1u << 24;
+                    }
+                }
+                thresholds6(g, T);
+            }
+        }
+        C.table[v] = T[4];
+        uint4* q4 = reinterpret_cast<uint4*>(C.table + C.t4_words);
+        q4[v] = make_uint4(T[0], T[1], T[2], T[3]);
+    }
+}
+
+// -------------------------------------------------------------------------
+// Boundary hit index of the final (padded) node.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ int32_t hit_index(const CubeDev& C, int node) {
+    const int P = C.P;
+    int c[3] = {node % P, (node / P) % P, node / (P * P)};
+    if (C.lattice == MW_LATTICE_VERTEX) {
+        const int n = C.n, M = n - 1;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            if (c[ax] == 0 || c[ax] == n) {
+                const int side = c[ax] == n;
+                const int a = ax == 0 ? c[1] : c[0];
+                const int b = ax == 2 ? c[1] : c[2];
+                return (2 * ax + side) * M * M + (b - 1) * M + (a - 1);
+            }
+        }
+        return -1;
+    }
+    const int N = C.n;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) c[ax] -= 1;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        if (c[ax] < 0 || c[ax] >= N) {
+            const int side = c[ax] >= N;
+            const int a = ax == 0 ? c[1] : c[0];
+            const int b = ax == 2 ? c[1] : c[2];
+            return (2 * ax + side) * N * N + b * N + a;
+        }
+    }
+    return -1;
+}
+
+constexpr uint32_t STEP_CAP = 1u << 30;
+
+// Node data cached in registers between steps.
+struct NodeT {
+    uint32_t t0, t1, t2, t3, t4;
+};
+
+__device__ __forceinline__ NodeT load_t(const uint32_t* base, uint32_t t4_words, int node) {
+    NodeT r;
+    r.t4 = base[node];
+    const uint4 q = reinterpret_cast<const uint4*>(base + t4_words)[node];
+    r.t0 = q.x;
+    r.t1 = q.y;
+    r.t2 = q.z;
+    r.t3 = q.w;
+    return r;
+}
+
+// Form 2: prefix sums S0..S4 and S5 of the node's links from its 8 cells;
+// returns false at a boundary node (a sentinel cell among the eight).
+struct NodeS {
+    uint32_t s0, s1, s2, s3, s4, s5;
+};
+
+__device__ __forceinline__ bool load_s(const uint32_t* lds, int P, int node, NodeS& r) {
+    const uint32_t* b0 = lds + node;
+    const uint32_t* b1 = b0 + P * P;
+    const uint32_t c000 = b0[0], c001 = b0[1], c010 = b0[P], c011 = b0[P + 1];
+    const uint32_t c100 = b1[0], c101 = b1[1], c110 = b1[P], c111 = b1[P + 1];
+    // c[dz][dy][dx] named c<dz><dy><dx>
+    const uint32_t a0 = c000 + c100, a1 = c010 + c110;  // dx = 0, dy = 0/1, summed over dz
+    const uint32_t b0s = c001 + c101, b1s = c011 + c111;  // dx = 1
+    const uint32_t gmx = a0 + a1, gpx = b0s + b1s;
+    const uint32_t total = gmx + gpx;
+    const uint32_t gmy = a0 + b0s;
+    const uint32_t gmz = c000 + c001 + c010 + c011;
+    r.s0 = gmx;
+    r.s1 = total;
+    r.s2 = total + gmy;
+    r.s3 = total + total;
+    r.s4 = r.s3 + gmz;
+    r.s5 = r.s3 + total;
+    return total < SENTINEL_CELL;
+}
+
+__device__ __forceinline__ int select_delta(uint32_t u, uint32_t t0, uint32_t t1, uint32_t t2, uint32_t t3,
+                                            uint32_t t4, int P, int P2) {
+    int delta = -1;
+    delta = u >= t0 ? 1 : delta;
+    delta = u >= t1 ? -P : delta;
+    delta = u >= t2 ? P : delta;
+    delta = u >= t3 ? -P2 : delta;
+    delta = u >= t4 ? P2 : delta;
+    return delta;
+}
+
+template <int FORM>
+__device__ void run_item(const CubeDev& C, const uint32_t* tab, uint64_t wb, uint64_t we, uint32_t* s_next,
+                         uint32_t k0, uint32_t k1, int groups_per_refill, unsigned long long& my_steps) {
+    const int lane = threadIdx.x & 63;
+    const int P = C.P, P2 = C.P * C.P;
+    const uint64_t cnt = we - wb;
+    bool active = false;
+    int node = 0;
+    uint32_t s = 0;
+    uint64_t rel = 0;
+    NodeT T{};
+    NodeS S{};
+    for (;;) {
+        const bool want = !active;
+        const uint64_t bal = __ballot(want);
+        if (bal) {
+            const int leader = __ffsll((unsigned long long)bal) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(s_next, (uint32_t)__popcll(bal));
+            base = __shfl(base, leader);
+            const uint32_t rank = __popcll(bal & ((1ull << lane) - 1ull));
+            if (want && (uint64_t)base + rank < cnt) {
+                active = true;
+                rel = wb + base + rank;
+                s = 0;
+                node = C.start;
+                if (FORM == FORM_CODES)
+                    load_s(tab, P, node, S);
+                else
+                    T = load_t(tab, C.t4_words, node);
+            }
+        }
+        if (!__any(active)) break;
+        for (int g = 0; g < groups_per_refill; ++g) {
+            if (active) {
+                const uint64_t walk = C.walk0 + rel;
+                const Rand4 r = philox10(s >> 2, C.c1, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), k0, k1);
+                const uint32_t us[4] = {r.x, r.y, r.z, r.w};
+                bool alive = true;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (alive) {
+                        int delta;
+                        if (FORM == FORM_CODES) {
+                            const uint32_t x = __umulhi(us[q], S.s5);
+                            delta = select_delta(x, S.s0, S.s1, S.s2, S.s3, S.s4, P, P2);
+                        } else {
+                            delta = select_delta(us[q], T.t0, T.t1, T.t2, T.t3, T.t4, P, P2);
+                        }
+                        node += delta;
+                        ++s;
+                        if (FORM == FORM_CODES) {
+                            alive = load_s(tab, P, node, S);
+                        } else {
+                            T = load_t(tab, C.t4_words, node);
+                            alive = T.t4 != 0;
+                        }
+                    }
+                }
+                if (!alive || s >= STEP_CAP) {
+                    C.hits[rel] = alive ? -1 : hit_index(C, node);
+                    if (C.steps) C.steps[rel] = (int32_t)s;
+                    my_steps += s;
+                    active = false;
+                }
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024) walk_kernel(const CubeDev* __restrict__ cubes, const Item* __restrict__ items,
+                                                    int32_t n_items, uint64_t item_walks, int32_t* item_counter,
+                                                    uint32_t k0, uint32_t k1, int32_t groups_per_refill,
+                                                    unsigned long long* step_total) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    __shared__ int32_t s_item;
+    __shared__ uint32_t s_next;
+    int cur_cube = -1;
+    unsigned long long my_steps = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_item = atomicAdd(item_counter, 1);
+            s_next = 0;
+        }
+        __syncthreads();
+        const int it = s_item;
+        if (it >= n_items) break;
+        Item I;
+        if (items) {
+            I = items[it];
+        } else {
+            I.cube = 0;
+            I.w_begin = (uint64_t)it * item_walks;
+            const uint64_t e = I.w_begin + item_walks, nw = cubes[0].n_walks;
+            I.w_end = e < nw ? e : nw;
+        }
+        const CubeDev C = cubes[I.cube];
+        if (C.form != FORM_TGLOBAL && I.cube != cur_cube) {
+            const uint4* src = reinterpret_cast<const uint4*>(C.table);
+            uint4* dst = reinterpret_cast<uint4*>(lds);
+            for (uint32_t q = threadIdx.x; q < C.table_words / 4; q += blockDim.x) dst[q] = src[q];
+            cur_cube = I.cube;
+            __syncthreads();
+        }
+        // separate call sites keep the LDS table in the LDS address space
+        if (C.form == FORM_CODES)
+            run_item<FORM_CODES>(C, lds, I.w_begin, I.w_end, &s_next, k0, k1, groups_per_refill, my_steps);
+        else if (C.form == FORM_TLDS)
+            run_item<FORM_TLDS>(C, lds, I.w_begin, I.w_end, &s_next, k0, k1, groups_per_refill, my_steps);
+        else
+            run_item<FORM_TGLOBAL>(C, C.table, I.w_begin, I.w_end, &s_next, k0, k1, groups_per_refill, my_steps);
+        __syncthreads();
+    }
+    // device-counted micro-steps
+    for (int off = 32; off > 0; off >>= 1) my_steps += __shfl_down(my_steps, off);
+    if ((threadIdx.x & 63) == 0 && my_steps) atomicAdd(step_total, my_steps);
+}
+
+// -------------------------------------------------------------------------
+// Host planning.
+// -------------------------------------------------------------------------
+struct Plan {
+    int form;
+    int P;
+    uint32_t t4_words, table_words;
+};
+
+Plan plan_cube(int n, int lattice, int want_form) {
+    Plan p{};
+    auto tplan = [&](int P) {
+        p.P = P;
+        uint32_t nodes = (uint32_t)P * P * P;
+        p.t4_words = (nodes + 3) / 4 * 4;
+        p.table_words = p.t4_words + 4 * nodes;
+    };
+    if (lattice == MW_LATTICE_VERTEX) {
+        const int Pc = n + 2;
+        const uint32_t code_words = ((uint32_t)Pc * Pc * Pc + 3) / 4 * 4;
+        tplan(n + 1);
+        const bool t_fits = p.table_words <= LDS_TABLE_WORDS;
+        const bool c_fits = code_words <= LDS_TABLE_WORDS;
+        int form = want_form;
+        if (form < 0 || form > FORM_TGLOBAL) form = 0;
+        if (form == FORM_TLDS && !t_fits) form = 0;
+        if (form == FORM_CODES && !c_fits) form = 0;
+        if (form == 0) form = t_fits && n <= 16 ? FORM_TLDS : (c_fits ? FORM_CODES : (t_fits ? FORM_TLDS : FORM_TGLOBAL));
+        p.form = form;
+        if (form == FORM_CODES) {
+            p.P = Pc;
+            p.t4_words = 0;
+            p.table_words = code_words;
+        }
+    } else {
+        tplan(n + 2);
+        p.form = p.table_words <= LDS_TABLE_WORDS && want_form != FORM_TGLOBAL ? FORM_TLDS : FORM_TGLOBAL;
+    }
+    return p;
+}
+
+void validate_cube(int n, int lattice) {
+    MW_REQUIRE(lattice == MW_LATTICE_VERTEX || lattice == MW_LATTICE_CELL, MW_EINVAL, "unknown lattice %d", lattice);
+    MW_REQUIRE(n >= 2 && n <= 64, MW_EINVAL, "n_cells %d outside [2, 64]", n);
+    if (lattice == MW_LATTICE_VERTEX)
+        MW_REQUIRE(n % 2 == 0, MW_EINVAL, "vertex lattice needs an even n_cells (got %d)", n);
+    else
+        MW_REQUIRE(n % 2 == 1, MW_EINVAL, "cell lattice needs an odd n_cells (got %d)", n);
+}
+
+void allow_large_lds() {
+    static bool done = false;
+    if (!done) {
+        MW_HIP(hipFuncSetAttribute((const void*)walk_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(LDS_TABLE_WORDS * 4)));
+        done = true;
+    }
+}
+
+int blocks_per_cu(size_t lds_bytes) {
+    return std::max(1, std::min(2, (int)(163840 / (lds_bytes + 1024))));
+}
+
+int num_cus() {
+    int dev = 0, cus = 0;
+    MW_HIP(hipGetDevice(&dev));
+    MW_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    return cus;
+}
+
+struct Launch {
+    int waves;
+    int groups;
+    uint64_t item_walks;
+};
+
+Launch default_launch(const mw_tune* t, uint64_t total_walks) {
+    Launch L{16, 2, 0};
+    if (t) {
+        if (t->waves_per_wg > 0) L.waves = std::min(16, std::max(1, (int)t->waves_per_wg));
+        if (t->refill_every > 0) L.groups = std::max(1, (int)t->refill_every / 4);
+        if (t->item_walks > 0) L.item_walks = (uint64_t)t->item_walks;
+    }
+    (void)total_walks;
+    return L;
+}
+
+}  // namespace
+}  // namespace mw
+
+using namespace mw;
+
+extern "C" mw_status mw_transition(const float* eps, int32_t n_cells, int32_t lattice, uint64_t n_walks,
+                                   uint64_t first_walk, uint64_t seed, uint32_t cube_index, int32_t* hit_idx,
+                                   int32_t* steps, void* stream) {
+    return guarded([&] {
+        validate_cube(n_cells, lattice);
+        if (n_walks == 0) return;
+        MW_REQUIRE(eps && hit_idx, MW_EINVAL, "eps and hit_idx are required");
+        hipStream_t st = (hipStream_t)stream;
+        const Plan p = plan_cube(n_cells, lattice, 0);
+        // scratch: [bad flag | step counter | item counter | cube desc | table]
+        const size_t hdr = 256;
+        const size_t bytes = hdr + (size_t)p.table_words * 4;
+        char* scratch = nullptr;
+        MW_REQUIRE(!inject_alloc_failure(), MW_ENOMEM, "injected device allocation failure");
+        MW_HIP(hipMallocAsync((void**)&scratch, bytes, st));
+        int* bad = (int*)scratch;
+        unsigned long long* step_total = (unsigned long long*)(scratch + 8);
+        int32_t* item_counter = (int32_t*)(scratch + 16);
+        CubeDev* dcube = (CubeDev*)(scratch + 64);
+        CubeDev C{};
+        C.eps = eps;
+        C.table = (uint32_t*)(scratch + hdr);
+        C.hits = hit_idx;
+        C.steps = steps;
+        C.walk0 = first_walk;
+        C.n_walks = n_walks;
+        C.n = n_cells;
+        C.lattice = lattice;
+        C.form = p.form;
+        C.P = p.P;
+        C.table_words = p.table_words;
+        C.t4_words = p.t4_words;
+        C.c1 = cube_index;
+        const int cen = lattice == MW_LATTICE_VERTEX ? n_cells / 2 : (n_cells - 1) / 2 + 1;
+        C.start = cen * (p.P * p.P + p.P + 1);
+        MW_HIP(hipMemsetAsync(scratch, 0, 64, st));
+        MW_HIP(hipMemcpyAsync(dcube, &C, sizeof C, hipMemcpyHostToDevice, st));
+        const uint32_t nodes = (uint32_t)p.P * p.P * p.P;
+        prep_kernel<<<dim3(std::min<uint32_t>((nodes + 255) / 256, 1024), 1), 256, 0, st>>>(dcube, bad);
+        MW_HIP(hipGetLastError());
+        // eps is device memory: its range check needs one device round trip
+        int h_bad = 0;
+        MW_HIP(hipMemcpyAsync(&h_bad, bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
+        MW_HIP(hipStreamSynchronize(st));
+        if (h_bad) {
+            (void)hipFreeAsync(scratch, st);
+            MW_REQUIRE(false, MW_EINVAL, "permittivity outside [1e-3, 1e3]");
+        }
+        const Launch L = default_launch(nullptr, n_walks);
+        const int threads = 64 * L.waves;
+        uint64_t iw = L.item_walks ? L.item_walks : std::max<uint64_t>(threads * 4, 4096);
+        const int cus = num_cus();
+        // enough items to keep every CU busy
+        while (iw > (uint64_t)threads && (n_walks + iw - 1) / iw < (uint64_t)cus * 2) iw /= 2;
+        const int64_t n_items = (int64_t)((n_walks + iw - 1) / iw);
+        MW_REQUIRE(n_items < (1ll << 31), MW_ELIMIT, "too many walks for one launch");
+        const size_t lds = p.form == FORM_TGLOBAL ? 16 : (size_t)p.table_words * 4;
+        const int blocks = (int)std::min<int64_t>(n_items, (int64_t)cus * blocks_per_cu(lds));
+        allow_large_lds();
+        walk_kernel<<<blocks, threads, lds, st>>>(dcube, nullptr, (int32_t)n_items, iw, item_counter,
+                                                   (uint32_t)seed, (uint32_t)(seed >> 32), L.groups, step_total);
+        MW_HIP(hipGetLastError());
+        MW_HIP(hipFreeAsync(scratch, st));
+    });
+}
+
+extern "C" mw_status mw_transition_batch(int32_t n_cubes, const float* eps_cat, const int64_t* eps_off,
+                                         const int32_t* n_cells, int32_t lattice, const uint64_t* n_walks,
+                                         const int64_t* out_off, uint64_t seed, int32_t* hits_cat,
+                                         int32_t* steps_cat, const mw_tune* tune, void* stream) {
+    return guarded([&] {
+        MW_REQUIRE(n_cubes >= 0, MW_EINVAL, "n_cubes < 0");
+        MW_REQUIRE(n_cubes <= 65535, MW_ELIMIT, "at most 65535 cubes per batch (got %d)", n_cubes);
+        if (n_cubes == 0) return;
+        MW_REQUIRE(eps_cat && eps_off && n_cells && n_walks && out_off && hits_cat, MW_EINVAL,
+                   "null argument to mw_transition_batch");
+        hipStream_t st = (hipStream_t)stream;
+        const Launch L = default_launch(tune, 0);
+        const int threads = 64 * L.waves;
+        const int want_form = tune ? tune->tile_form : 0;
+        std::vector<CubeDev> cubes(n_cubes);
+        std::vector<Plan> plans(n_cubes);
+        size_t table_total = 0;
+        uint64_t total_walks = 0;
+        uint32_t max_lds_words = 4;
+        for (int c = 0; c < n_cubes; ++c) {
+            validate_cube(n_cells[c], lattice);
+            MW_REQUIRE(eps_off[c] >= 0 && out_off[c] >= 0, MW_EINVAL, "negative offset for cube %d", c);
+            plans[c] = plan_cube(n_cells[c], lattice, want_form);
+            table_total += (size_t)plans[c].table_words * 4;
+            total_walks += n_walks[c];
+            if (plans[c].form != FORM_TGLOBAL) max_lds_words = std::max(max_lds_words, plans[c].table_words);
+        }
+        // order cubes by cost (n^2 * walks), largest first; items contiguous per cube
+        std::vector<int> order(n_cubes);
+        for (int c = 0; c < n_cubes; ++c) order[c] = c;
+        std::sort(order.begin(), order.end(), [&](int a, int b) {
+            double ca = (double)n_cells[a] * n_cells[a] * n_walks[a], cb = (double)n_cells[b] * n_cells[b] * n_walks[b];
+            return ca > cb;
+        });
+        uint64_t iw = L.item_walks ? L.item_walks : (uint64_t)threads * 16;
+        std::vector<Item> items;
+        for (int c : order)
+            for (uint64_t w = 0; w < n_walks[c]; w += iw) items.push_back(Item{c, 0, w, std::min(w + iw, n_walks[c])});
+        MW_REQUIRE(items.size() < (1ull << 31), MW_ELIMIT, "too many work items");
+        const size_t hdr = 256;
+        const size_t cubes_bytes = (sizeof(CubeDev) * n_cubes + 255) / 256 * 256;
+        const size_t items_bytes = (sizeof(Item) * items.size() + 255) / 256 * 256;
+        char* scratch = (char*)dev_alloc(hdr + cubes_bytes + items_bytes + table_total + 256);
+        struct Guard {
+            char* p;
+            ~Guard() { dev_free(p); }
+        } guard{scratch};
+        int* bad = (int*)scratch;
+        unsigned long long* step_total = (unsigned long long*)(scratch + 8);
+        int32_t* item_counter = (int32_t*)(scratch + 16);
+        CubeDev* dcubes = (CubeDev*)(scratch + hdr);
+        Item* ditems = (Item*)(scratch + hdr + cubes_bytes);
+        char* tables = scratch + hdr + cubes_bytes + items_bytes;
+        size_t toff = 0;
+        for (int c = 0; c < n_cubes; ++c) {
+            const Plan& p = plans[c];
+            CubeDev& C = cubes[c];
+            C.eps = eps_cat + eps_off[c];
+            C.table = (uint32_t*)(tables + toff);
+            toff += (size_t)p.table_words * 4;
+            C.hits = hits_cat + out_off[c];
+            C.steps = steps_cat ? steps_cat + out_off[c] : nullptr;
+            C.walk0 = 0;
+            C.n_walks = n_walks[c];
+            C.n = n_cells[c];
+            C.lattice = lattice;
+            C.form = p.form;
+            C.P = p.P;
+            C.table_words = p.table_words;
+            C.t4_words = p.t4_words;
+            C.c1 = (uint32_t)c;
+            const int cen = lattice == MW_LATTICE_VERTEX ? n_cells[c] / 2 : (n_cells[c] - 1) / 2 + 1;
+            C.start = cen * (p.P * p.P + p.P + 1);
+        }
+        MW_HIP(hipMemsetAsync(scratch, 0, 64, st));
+        MW_HIP(hipMemcpyAsync(dcubes, cubes.data(), sizeof(CubeDev) * n_cubes, hipMemcpyHostToDevice, st));
+        MW_HIP(hipMemcpyAsync(ditems, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, st));
+        prep_kernel<<<dim3(64, n_cubes), 256, 0, st>>>(dcubes, bad);
+        MW_HIP(hipGetLastError());
+        int h_bad = 0;
+        MW_HIP(hipMemcpyAsync(&h_bad, bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
+        MW_HIP(hipStreamSynchronize(st));
+        MW_REQUIRE(!h_bad, MW_EINVAL, "permittivity outside [1e-3, 1e3]");
+        const size_t lds = (size_t)max_lds_words * 4;
+        const int cus = num_cus();
+        const int blocks = (int)std::min<size_t>(items.size(), (size_t)cus * blocks_per_cu(lds));
+        allow_large_lds();
+        walk_kernel<<<blocks, threads, lds, st>>>(dcubes, ditems, (int32_t)items.size(), 0, item_counter,
+                                                   (uint32_t)seed, (uint32_t)(seed >> 32), L.groups, step_total);
+        MW_HIP(hipGetLastError());
+        MW_HIP(hipStreamSynchronize(st));
+    });
+}
