@@ -35,6 +35,8 @@ class MWError(RuntimeError):
 
 
 _lib.mw_last_error.restype = ctypes.c_char_p
+_lib.mw_structure_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+_lib.mw_structure_destroy.argtypes = [ctypes.c_void_p]
 
 
 def mw_last_error():
@@ -130,6 +132,131 @@ def mw_transition_batch(eps_list, walks, lattice=MW_LATTICE_VERTEX, seed=0, tune
         out_off.ctypes.data_as(ctypes.c_void_p), U64(seed), _ptr(hits), _ptr(steps),
         ctypes.byref(t) if t is not None else None, _stream(stream)))
     return hits[:total], (steps[:total] if steps is not None else None), out_off
+
+
+# ---------------------------------------------------------------------------
+# Geometry and FRW extraction (Alg. 1)
+# ---------------------------------------------------------------------------
+F3 = ctypes.c_float * 3
+
+
+class mw_cond_box(ctypes.Structure):
+    _fields_ = [("lo", F3), ("hi", F3), ("net", ctypes.c_int32)]
+
+
+class mw_diel_box(ctypes.Structure):
+    _fields_ = [("lo", F3), ("hi", F3), ("eps", ctypes.c_float)]
+
+
+class mw_structure_desc(ctypes.Structure):
+    _fields_ = [("n_cond", ctypes.c_int32), ("cond", ctypes.POINTER(mw_cond_box)),
+                ("n_nets", ctypes.c_int32), ("n_diel", ctypes.c_int32),
+                ("diel", ctypes.POINTER(mw_diel_box)), ("n_layers", ctypes.c_int32),
+                ("layer_z0", ctypes.POINTER(ctypes.c_float)),
+                ("layer_eps", ctypes.POINTER(ctypes.c_float)), ("win_lo", F3), ("win_hi", F3),
+                ("bc", ctypes.c_uint8 * 6)]
+
+
+class frw_options(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int32), ("hybrid", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("target_rel_3sigma", ctypes.c_double), ("abs_tol_rel", ctypes.c_double),
+                ("first_walk", ctypes.c_uint64), ("batch_walks", ctypes.c_uint64)]
+
+
+class frw_stats(ctypes.Structure):
+    _fields_ = [("walks", ctypes.c_uint64), ("hops", ctypes.c_uint64),
+                ("micro_steps", ctypes.c_uint64), ("hop_class", ctypes.c_uint64 * 3),
+                ("first_branch", ctypes.c_uint64 * 4), ("cache_miss", ctypes.c_uint64),
+                ("env_absorbed", ctypes.c_uint64), ("hop_cap", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"walks": self.walks, "hops": self.hops, "micro_steps": self.micro_steps,
+                "hop_class": list(self.hop_class), "first_branch": list(self.first_branch),
+                "cache_miss": self.cache_miss, "env_absorbed": self.env_absorbed,
+                "hop_cap": self.hop_cap, "launches": self.launches, "seconds": self.seconds}
+
+
+def make_desc(st):
+    """mw_structure_desc for a structure object with the fields of
+    workloads.Structure (cond (n,6), cond_net, n_nets, diel (m,6), diel_eps,
+    layer_z0, layer_eps, win_lo, win_hi, bc).  Returns (desc, keepalive)."""
+    nc, nd = int(st.cond.shape[0]), int(st.diel.shape[0])
+    cond = (mw_cond_box * max(nc, 1))()
+    for i in range(nc):
+        b = st.cond[i]
+        cond[i] = mw_cond_box(F3(*b[:3]), F3(*b[3:]), int(st.cond_net[i]))
+    diel = (mw_diel_box * max(nd, 1))()
+    for i in range(nd):
+        b = st.diel[i]
+        diel[i] = mw_diel_box(F3(*b[:3]), F3(*b[3:]), float(st.diel_eps[i]))
+    nl = len(st.layer_z0)
+    z0 = (ctypes.c_float * nl)(*[float(x) for x in st.layer_z0])
+    le = (ctypes.c_float * nl)(*[float(x) for x in st.layer_eps])
+    d = mw_structure_desc(nc, cond, int(st.n_nets), nd, diel, nl, z0, le,
+                          F3(*[float(x) for x in st.win_lo]), F3(*[float(x) for x in st.win_hi]),
+                          (ctypes.c_uint8 * 6)(*[int(b) for b in st.bc]))
+    return d, (cond, diel, z0, le)
+
+
+class StructureHandle:
+    """Owns an mw_structure (device-resident geometry and its grid index)."""
+
+    def __init__(self, st):
+        desc, keep = make_desc(st)
+        h = ctypes.c_void_p()
+        _check(_lib.mw_structure_create(ctypes.byref(desc), ctypes.byref(h)))
+        self.handle = h
+        self.n_nets = int(st.n_nets)
+
+    def close(self):
+        if self.handle:
+            _lib.mw_structure_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mw_structure_create(st):
+    return StructureHandle(st)
+
+
+def mw_structure_destroy(handle):
+    handle.close()
+
+
+def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
+                target_rel_3sigma=0.0, abs_tol_rel=1e-6, first_walk=0, batch_walks=0,
+                scores=False, device="cuda"):
+    """Alg. 1: one capacitance row (fF, last entry = grounded enclosure) and
+    its standard errors.  With scores=True also returns the per-walk net and
+    fp32 weight (CUDA tensors)."""
+    import torch
+    if not isinstance(structure, StructureHandle):
+        structure = StructureHandle(structure)
+    K = structure.n_nets + 1
+    row = (ctypes.c_double * K)()
+    se = (ctypes.c_double * K)()
+    stats = frw_stats()
+    opt = frw_options(n_cells, hybrid, 0, 0, target_rel_3sigma, abs_tol_rel, first_walk, batch_walks)
+    net = w = None
+    if scores:
+        net = torch.empty(walk_budget, dtype=torch.int32, device=device)
+        w = torch.empty(walk_budget, dtype=torch.float32, device=device)
+        torch.cuda.synchronize()
+    _check(_lib.frw_extract(structure.handle, I32(master), U64(walk_budget), U64(seed),
+                            ctypes.byref(opt), row, se, ctypes.byref(stats), _ptr(net), _ptr(w)))
+    out = {"row": np.array(row[:]), "se": np.array(se[:]), "stats": stats.as_dict()}
+    if scores:
+        n = stats.walks
+        out["net"], out["w"] = net[:n], w[:n]
+    return out
+
 
 
 EXPORTS = ("mw_last_error", "mw_init", "mw_transition", "mw_transition_batch",

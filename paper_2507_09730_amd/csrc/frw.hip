@@ -1,0 +1,1696 @@
+// frw.hip — Alg. 1 (FRW capacitance extraction) on the GPU: geometry store,
+// lazily voxelised transition cubes, the hybrid transition strategy of
+// Sec. III-C (exact SGF tables for stratified cubes, MicroWalk (Alg. 3) for
+// the rest), the first transition and the score reductions.
+//
+// Walker kernel.  Every lane owns one walk at a time.  A lane's transition
+// cube is never materialised: for the cube around its position the lane
+// lists the dielectric regions (background layers, then dielectric boxes in
+// priority order) that touch the cube and, per axis, a bitmask per cell
+// index of the regions whose interval holds that cell's centre (after mirror
+// folding at symmetry walls).  The region of a cell is the highest set bit
+// of the AND of its three axis masks; a MicroWalk step reads the two masks of
+// the moved axis from LDS and derives the six link codes of the new node
+// from the eight cells around it.  Nodes whose eight cells share one
+// membership pattern take the uniform-step shortcut d = mulhi(u, 6), which is
+// the same integer rule evaluated with equal codes.
+//
+// Stratified cubes (every region present in the cube spans whole planes
+// normal to one axis) are sampled from cached exact SGF tables of the same
+// lattice.  A missing table parks the walk in a queue; the table is built by
+// build_tables_kernel between walker launches, and parked walks resume from
+// their saved position (their random numbers depend only on walk id and hop
+// index, so parking does not change any result).
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <cmath>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+namespace mw {
+namespace {
+
+constexpr float EPS0 = 8.8541878128e-3f;  // vacuum permittivity, fF/um
+constexpr uint32_t HOP_CAP = 100000;
+constexpr int MAX_REGIONS = MW_MAX_REGIONS;
+constexpr int FRW_THREADS = 256;
+constexpr uint32_t KEY_HDR = 4;
+constexpr uint32_t NO_INDEX = 0xffffffffu;
+
+enum ErrBits : uint32_t { ERR_REGIONS = 1, ERR_TABLE_CAP = 2, ERR_PARK_CAP = 4, ERR_STEP_CAP = 8 };
+constexpr uint32_t MW_STEP_CAP = 1u << 26;
+
+// -------------------------------------------------------------------------
+// Device structure descriptor.
+// -------------------------------------------------------------------------
+struct StructDev {
+    int32_t n_cond, n_nets, n_diel, n_layers;
+    const float4* cond_lo;  // xyz lo, w = net (bits)
+    const float4* cond_hi;
+    const float4* diel_lo;  // xyz lo, w = eps
+    const float4* diel_hi;  // xyz hi, w = vertex cell code (bits)
+    const float* layer_z0;
+    const uint32_t* layer_code;
+    float wlo[3], whi[3];
+    int32_t bc[6];
+    // uniform grid
+    int32_t gdim[3];
+    float gorg[3], ginv[3], gcell[3];
+    const uint32_t* gc_off;
+    const uint32_t* gc_list;
+    const uint32_t* gd_off;
+    const uint32_t* gd_list;
+    float delta_abs;
+};
+
+struct GaussDev {
+    float g, area;
+    int32_t n_faces;
+    int32_t axis[6], side[6];
+    float plane[6], lo[6][3], hi[6][3], cum[6];
+};
+
+// Table cache for one lattice size.
+struct CacheDev {
+    unsigned long long* slot_hash;
+    uint32_t* slot_index;
+    uint32_t* ready;
+    uint32_t* keys;
+    uint32_t* data;
+    uint32_t* n_tables;
+    uint32_t* pending;
+    uint32_t* n_pending;
+    uint32_t slot_mask, capacity, key_words, tab_words, n, nb;
+};
+
+struct Parked {
+    unsigned long long walk;
+    float px, py, pz, omega;
+    uint32_t t;
+    uint32_t pad[3];
+};
+
+struct Counters {
+    unsigned long long hops, micro_steps, hop_class[3], first_branch[4], env, hop_cap;
+    uint32_t err, park_count;
+    unsigned long long resume_next, walk_next;
+};
+
+struct WalkArgs {
+    const StructDev* S;
+    const GaussDev* G;
+    CacheDev cache;
+    int32_t n, hybrid, master, pad;
+    uint32_t k0, k1;
+    unsigned long long walk_begin, walk_end;
+    const Parked* resume;
+    uint32_t n_resume;
+    Parked* park_out;
+    uint32_t park_cap;
+    int32_t* score_net;
+    float* score_w;
+    Counters* ctr;
+    uint32_t lane_stride;  // dwords of LDS per lane (odd)
+};
+
+// -------------------------------------------------------------------------
+// Geometry helpers.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ float box_dist(float4 lo, float4 hi, float3 p) {
+    const float dx = fmaxf(fmaxf(lo.x - p.x, p.x - hi.x), 0.f);
+    const float dy = fmaxf(fmaxf(lo.y - p.y, p.y - hi.y), 0.f);
+    const float dz = fmaxf(fmaxf(lo.z - p.z, p.z - hi.z), 0.f);
+    return fmaxf(dx, fmaxf(dy, dz));
+}
+
+__device__ __forceinline__ float axis_of(float3 p, int a) { return a == 0 ? p.x : (a == 1 ? p.y : p.z); }
+
+__device__ __forceinline__ int grid_cell(const StructDev& S, float3 p) {
+    int c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int v = (int)floorf((axis_of(p, a) - S.gorg[a]) * S.ginv[a]);
+        c[a] = min(max(v, 0), S.gdim[a] - 1);
+    }
+    return (c[2] * S.gdim[1] + c[1]) * S.gdim[0] + c[0];
+}
+
+// Largest conductor-free cube: L-infinity distance to the nearest conductor
+// or grounded window face; nearest = net, or n_nets for a grounded face.
+__device__ float query_dist(const StructDev& S, float3 p, int cell, int* nearest) {
+    float best = INFINITY;
+    int who = S.n_nets;
+    const uint32_t b = S.gc_off[cell], e = S.gc_off[cell + 1];
+    for (uint32_t q = b; q < e; ++q) {
+        const uint32_t c = S.gc_list[q];
+        const float4 lo = S.cond_lo[c], hi = S.cond_hi[c];
+        const float d = box_dist(lo, hi, p);
+        if (d < best) {
+            best = d;
+            who = __float_as_int(lo.w);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float x = axis_of(p, a);
+        if (S.bc[2 * a] == MW_BC_DIRICHLET && x - S.wlo[a] < best) {
+            best = x - S.wlo[a];
+            who = S.n_nets;
+        }
+        if (S.bc[2 * a + 1] == MW_BC_DIRICHLET && S.whi[a] - x < best) {
+            best = S.whi[a] - x;
+            who = S.n_nets;
+        }
+    }
+    *nearest = who;
+    return best;
+}
+
+__device__ __forceinline__ float fold(const StructDev& S, int a, float x) {
+    if (S.bc[2 * a] == MW_BC_NEUMANN && x < S.wlo[a]) x = 2.f * S.wlo[a] - x;
+    if (S.bc[2 * a + 1] == MW_BC_NEUMANN && x > S.whi[a]) x = 2.f * S.whi[a] - x;
+    return x;
+}
+
+__device__ __forceinline__ float3 fold3(const StructDev& S, float3 p) {
+    return make_float3(fold(S, 0, p.x), fold(S, 1, p.y), fold(S, 2, p.z));
+}
+
+// -------------------------------------------------------------------------
+// Per-lane cube description in LDS: masks[3][n] (u16) then codes[16] (u32).
+// -------------------------------------------------------------------------
+struct LaneCube {
+    uint16_t* mask;   // mask[a * n + i]
+    uint32_t* codes;  // region code by bit
+};
+
+__device__ __forceinline__ int hb16(uint32_t m) { return 31 - __clz(m | 1u); }
+
+struct CubeInfo {
+    uint32_t present, A[3];
+    int cls;   // 0 uniform, 1 stratified, 2 other
+    int axis;  // stratification axis
+    bool overflow;
+};
+
+// Builds the region masks of the cube centred at c with half-size R.
+__device__ CubeInfo build_cube(const StructDev& S, int cell, float3 c, float R, int n, LaneCube L) {
+    CubeInfo info{};
+    const float h = 2.f * R / (float)n;
+    const float lo0[3] = {c.x - R, c.y - R, c.z - R};
+    for (int q = 0; q < 3 * n; ++q) L.mask[q] = 0;
+    int nbits = 0;
+    // background layers touching the cube (lowest priority)
+    {
+        const float zlo = lo0[2], zhi = lo0[2] + 2.f * R;
+        float flo = fminf(fold(S, 2, zlo), fold(S, 2, zhi)), fhi = fmaxf(fold(S, 2, zlo), fold(S, 2, zhi));
+        // folded coordinates of the cube's cells lie within [min, max] of the
+        // folded span (one reflection)
+        if (zlo < S.wlo[2] && S.bc[4] == MW_BC_NEUMANN) flo = fminf(flo, S.wlo[2]);
+        if (zhi > S.whi[2] && S.bc[5] == MW_BC_NEUMANN) fhi = fmaxf(fhi, S.whi[2]);
+        int l0 = 0, l1 = 0;
+        for (int l = 1; l < S.n_layers; ++l) {
+            if (S.layer_z0[l] <= flo) l0 = l;
+            if (S.layer_z0[l] <= fhi) l1 = l;
+        }
+        if (l1 - l0 + 1 > MAX_REGIONS) {
+            info.overflow = true;
+            l1 = l0 + MAX_REGIONS - 1;
+        }
+        for (int k = 0; k < n; ++k) {
+            const float z = fold(S, 2, lo0[2] + ((float)k + 0.5f) * h);
+            int l = l0;
+            for (int q = l0 + 1; q <= l1; ++q)
+                if (z >= S.layer_z0[q]) l = q;
+            L.mask[2 * n + k] = (uint16_t)(1u << (l - l0));
+        }
+        for (int l = l0; l <= l1; ++l) L.codes[l - l0] = S.layer_code[l];
+        const uint16_t all = (uint16_t)((1u << (l1 - l0 + 1)) - 1u);
+        for (int i = 0; i < n; ++i) {
+            L.mask[i] = all;
+            L.mask[n + i] = all;
+        }
+        nbits = l1 - l0 + 1;
+    }
+    // dielectric boxes touching the cube, in priority order
+    const uint32_t b = S.gd_off[cell], e = S.gd_off[cell + 1];
+    for (uint32_t q = b; q < e; ++q) {
+        const uint32_t id = S.gd_list[q];
+        const float4 blo = S.diel_lo[id], bhi = S.diel_hi[id];
+        const float bl[3] = {blo.x, blo.y, blo.z}, bh[3] = {bhi.x, bhi.y, bhi.z};
+        bool touch = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float clo = lo0[a], chi = lo0[a] + 2.f * R;
+            if (S.bc[2 * a] == MW_BC_NEUMANN) clo = fmaxf(clo, S.wlo[a]);
+            if (S.bc[2 * a + 1] == MW_BC_NEUMANN) chi = fminf(chi, S.whi[a]);
+            if (!(bl[a] <= chi && bh[a] >= clo)) touch = false;
+        }
+        if (!touch) continue;
+        if (nbits >= MAX_REGIONS) {
+            info.overflow = true;
+            break;
+        }
+        const uint16_t bit = (uint16_t)(1u << nbits);
+        L.codes[nbits] = __float_as_uint(bhi.w);
+        ++nbits;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            for (int i = 0; i < n; ++i) {
+                const float x = fold(S, a, lo0[a] + ((float)i + 0.5f) * h);
+                if (x >= bl[a] && x < bh[a]) L.mask[a * n + i] |= bit;
+            }
+        }
+    }
+    // aggregate masks: present regions and full-span regions per axis
+    uint32_t O[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        uint32_t A = 0xffffu, Oa = 0;
+        for (int i = 0; i < n; ++i) {
+            const uint32_t m = L.mask[a * n + i];
+            A &= m;
+            Oa |= m;
+        }
+        info.A[a] = A;
+        O[a] = Oa;
+    }
+    info.present = O[0] & O[1] & O[2];
+    const bool full0 = (info.present & ~info.A[0]) == 0;
+    const bool full1 = (info.present & ~info.A[1]) == 0;
+    const bool full2 = (info.present & ~info.A[2]) == 0;
+    if (full0 && full1 && full2) {
+        info.cls = 0;
+        info.axis = 2;
+    } else if (full0 && full1) {
+        info.cls = 1;
+        info.axis = 2;
+    } else if (full1 && full2) {
+        info.cls = 1;
+        info.axis = 0;
+    } else if (full0 && full2) {
+        info.cls = 1;
+        info.axis = 1;
+    } else {
+        info.cls = 2;
+        info.axis = -1;
+    }
+    return info;
+}
+
+__device__ __forceinline__ bool stratified_along(const CubeInfo& I, int s) {
+    if (I.cls == 0) return true;
+    const uint32_t f1 = (I.present & ~I.A[(s + 1) % 3]) == 0, f2 = (I.present & ~I.A[(s + 2) % 3]) == 0;
+    return f1 && f2;
+}
+
+// Code of plane p normal to s of a cube stratified along s.
+__device__ __forceinline__ uint32_t plane_code(LaneCube L, const CubeInfo& I, int n, int s, int p) {
+    return L.codes[hb16(L.mask[s * n + p] & I.present)];
+}
+
+// Mean code of plane p normal to a (rounded half to even), summing runs of
+// equal masks along the two in-plane axes.
+__device__ uint32_t plane_mean_code(LaneCube L, int n, int a, int p) {
+    const int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
+    const uint32_t ma = L.mask[a * n + p];
+    unsigned long long sum = 0;
+    int i = 0;
+    while (i < n) {
+        const uint32_t mu = L.mask[u * n + i];
+        int li = 1;
+        while (i + li < n && L.mask[u * n + i + li] == mu) ++li;
+        const uint32_t mau = ma & mu;
+        int j = 0;
+        while (j < n) {
+            const uint32_t mv = L.mask[v * n + j];
+            int lj = 1;
+            while (j + lj < n && L.mask[v * n + j + lj] == mv) ++lj;
+            sum += (unsigned long long)(li * lj) * L.codes[hb16(mau & mv)];
+            j += lj;
+        }
+        i += li;
+    }
+    const unsigned long long area = (unsigned long long)n * n;
+    unsigned long long qt = sum / area, rem = sum % area;
+    if (2 * rem > area || (2 * rem == area && (qt & 1))) ++qt;
+    return (uint32_t)qt;
+}
+
+// -------------------------------------------------------------------------
+// Table cache.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long key_hash(const uint32_t* key, uint32_t words) {
+    unsigned long long h = 0xcbf29ce484222325ull;
+    for (uint32_t q = 0; q < words; ++q) {
+        h ^= key[q];
+        h *= 0x100000001b3ull;
+        h ^= h >> 29;
+    }
+    return h | 1ull;
+}
+
+enum LookupResult { LOOKUP_HIT = 0, LOOKUP_PARK = 1, LOOKUP_FULL = 2 };
+
+// key: KEY_HDR + n words at kbuf.  Returns the table index on a hit.
+__device__ int lookup_or_insert(const CacheDev& C, const uint32_t* kbuf, uint32_t* out_index) {
+    const uint32_t words = C.key_words;
+    const unsigned long long h = key_hash(kbuf, words);
+    uint32_t slot = (uint32_t)h & C.slot_mask;
+    for (uint32_t probe = 0; probe <= C.slot_mask; ++probe) {
+        unsigned long long cur = __hip_atomic_load(&C.slot_hash[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == 0ull) {
+            const unsigned long long old = atomicCAS(&C.slot_hash[slot], 0ull, h);
+            if (old == 0ull) {
+                const uint32_t idx = atomicAdd(C.n_tables, 1u);
+                if (idx >= C.capacity) return LOOKUP_FULL;
+                uint32_t* dst = C.keys + (size_t)idx * words;
+                for (uint32_t q = 0; q < words; ++q) dst[q] = kbuf[q];
+                __threadfence();
+                __hip_atomic_store(&C.slot_index[slot], idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t pos = atomicAdd(C.n_pending, 1u);
+                C.pending[pos] = idx;
+                return LOOKUP_PARK;
+            }
+            cur = old;
+        }
+        if (cur == h) {
+            const uint32_t idx = __hip_atomic_load(&C.slot_index[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (idx == NO_INDEX) return LOOKUP_PARK;
+            if (__hip_atomic_load(&C.ready[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) return LOOKUP_PARK;
+            const uint32_t* k = C.keys + (size_t)idx * words;
+            bool same = true;
+            for (uint32_t q = 0; q < words; ++q) same &= k[q] == kbuf[q];
+            if (same) {
+                *out_index = idx;
+                return LOOKUP_HIT;
+            }
+        }
+        slot = (slot + 1) & C.slot_mask;
+    }
+    return LOOKUP_FULL;
+}
+
+// Table layout: [last positive index, Kh bits, CDF[nb], sign bits[ceil(nb/32)]].
+__device__ __forceinline__ int table_sample(const uint32_t* tab, uint32_t nb, uint32_t u) {
+    const uint32_t* cdf = tab + 2;
+    uint32_t lo = 0, hi = nb;  // first b with cdf[b] > u
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (cdf[mid] > u)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo < nb ? (int)lo : (int)tab[0];
+}
+
+// Vertex-lattice boundary node of hit index b.
+__device__ __forceinline__ void node_of_hit(int n, int b, int node[3]) {
+    const int M = n - 1;
+    const int f = b / (M * M), rem = b - f * M * M;
+    const int bb = rem / M + 1, aa = rem - (bb - 1) * M + 1;
+    const int ax = f >> 1, side = f & 1;
+    const int o0 = ax == 0 ? 1 : 0, o1 = ax == 2 ? 1 : 2;
+    node[ax] = side ? n : 0;
+    node[o0] = aa;
+    node[o1] = bb;
+}
+
+// -------------------------------------------------------------------------
+// Walker kernel.
+// -------------------------------------------------------------------------
+enum Phase : int { PH_IDLE = 0, PH_NEED = 1, PH_MW = 2, PH_EXHAUSTED = 3 };
+
+__global__ void __launch_bounds__(FRW_THREADS) frw_walk_kernel(WalkArgs A) {
+    extern __shared__ uint32_t lds[];
+    const StructDev& S = *A.S;
+    const GaussDev& G = *A.G;
+    const int n = A.n;
+    const int lane = threadIdx.x & 63;
+    uint32_t* my = lds + threadIdx.x * A.lane_stride;
+    LaneCube L{reinterpret_cast<uint16_t*>(my), my + ((3 * n + 1) / 2)};
+    uint32_t* kbuf = L.codes + MAX_REGIONS;  // table key: KEY_HDR + n words
+
+    Counters& K = *A.ctr;
+    unsigned long long c_hops = 0, c_steps = 0, c_cls[3] = {0, 0, 0}, c_br[4] = {0, 0, 0, 0}, c_env = 0, c_cap = 0;
+    uint32_t err = 0;
+
+    int phase = PH_IDLE;
+    unsigned long long walk = 0;
+    float3 pos = make_float3(0.f, 0.f, 0.f);
+    float omega = 0.f;
+    uint32_t t = 0;
+    // MicroWalk state
+    float3 mc = pos;
+    float mR = 0.f;
+    int ni = 0, nj = 0, nk = 0;
+    uint32_t s = 0;
+    uint32_t mx0 = 0, mx1 = 0, my0 = 0, my1 = 0, mz0 = 0, mz1 = 0;
+
+    for (;;) {
+        // ---- take work: resumed walks first, then fresh walk ids ----
+        {
+            const bool want = phase == PH_IDLE;
+            const uint64_t bal = __ballot(want);
+            if (bal) {
+                const int leader = __ffsll((unsigned long long)bal) - 1;
+                const uint32_t cnt = __popcll(bal);
+                const uint32_t rank = __popcll(bal & ((1ull << lane) - 1ull));
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(&K.resume_next, (unsigned long long)cnt);
+                base = __shfl(base, leader);
+                bool got = false;
+                if (want && base + rank < A.n_resume) {
+                    const Parked P = A.resume[base + rank];
+                    walk = P.walk;
+                    pos = make_float3(P.px, P.py, P.pz);
+                    omega = P.omega;
+                    t = P.t;
+                    phase = PH_NEED;
+                    got = true;
+                }
+                const bool want2 = want && !got;
+                const uint64_t bal2 = __ballot(want2);
+                if (bal2) {
+                    const int leader2 = __ffsll((unsigned long long)bal2) - 1;
+                    const uint32_t cnt2 = __popcll(bal2);
+                    const uint32_t rank2 = __popcll(bal2 & ((1ull << lane) - 1ull));
+                    unsigned long long base2 = 0;
+                    if (lane == leader2) base2 = atomicAdd(&K.walk_next, (unsigned long long)cnt2);
+                    base2 = __shfl(base2, leader2);
+                    if (want2) {
+                        const unsigned long long w = A.walk_begin + base2 + rank2;
+                        if (w < A.walk_end) {
+                            walk = w;
+                            t = 0;
+                            omega = 0.f;
+                            phase = PH_NEED;
+                        } else {
+                            phase = PH_EXHAUSTED;
+                        }
+                    }
+                }
+            }
+        }
+        if (!__any(phase == PH_NEED || phase == PH_MW)) break;
+
+        // ---- one transition for lanes that need one ----
+        if (phase == PH_NEED) {
+            bool park = false, done = false;
+            int net = S.n_nets;
+            float3 c;
+            float R;
+            int a_norm = 0, side = 1;
+            float3 x;
+            int cell;
+            if (t == 0) {
+                // GaussianSurfaceSampling(G): face by area, uniform point
+                const Rand4 r = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_GAUSS), A.k0, A.k1);
+                const float xa = ((float)r.x + 0.5f) * 2.3283064365386963e-10f * G.area;
+                int f = G.n_faces - 1;
+                for (int q = 0; q < G.n_faces - 1; ++q)
+                    if (xa < G.cum[q]) {
+                        f = q;
+                        break;
+                    }
+                a_norm = G.axis[f];
+                side = G.side[f];
+                const int ta = a_norm == 0 ? 1 : 0, tb = a_norm == 2 ? 1 : 2;
+                float cc[3];
+                cc[a_norm] = G.plane[f];
+                cc[ta] = G.lo[f][ta] + ((float)r.y + 0.5f) * 2.3283064365386963e-10f * (G.hi[f][ta] - G.lo[f][ta]);
+                cc[tb] = G.lo[f][tb] + ((float)r.z + 0.5f) * 2.3283064365386963e-10f * (G.hi[f][tb] - G.lo[f][tb]);
+                c = make_float3(cc[0], cc[1], cc[2]);
+                cell = grid_cell(S, c);
+                int who;
+                R = fminf(query_dist(S, c, cell, &who), G.g);
+            } else {
+                cell = grid_cell(S, pos);
+                R = query_dist(S, pos, cell, &net);
+                c = pos;
+                if (R <= S.delta_abs) {
+                    done = true;
+                } else if (t > HOP_CAP) {
+                    done = true;
+                    net = S.n_nets;
+                    ++c_cap;
+                }
+            }
+            if (!done) {
+                const CubeInfo I = build_cube(S, cell, c, R, n, L);
+                if (I.overflow) err |= ERR_REGIONS;
+                const float h = 2.f * R / (float)n;
+                if (t == 0) {
+                    // first transition: cube touching the master (Sec. III-C,
+                    // Fig. 4 branches; homogenised along the normal when the
+                    // cube is not stratified)
+                    int br, sax;
+                    if (I.cls == 0) {
+                        br = 0;
+                        sax = a_norm;
+                    } else if (stratified_along(I, a_norm)) {
+                        br = 1;
+                        sax = a_norm;
+                    } else if (I.cls == 1) {
+                        br = 2;
+                        sax = I.axis;
+                    } else {
+                        br = 3;
+                        sax = a_norm;
+                    }
+                    ++c_br[br];
+                    kbuf[0] = 1u;  // first-transition table
+                    kbuf[1] = (uint32_t)n;
+                    kbuf[2] = (uint32_t)sax;
+                    kbuf[3] = (uint32_t)a_norm;
+                    for (int p = 0; p < n; ++p)
+                        kbuf[KEY_HDR + p] = br == 3 ? plane_mean_code(L, n, a_norm, p) : plane_code(L, I, n, sax, p);
+                    uint32_t idx;
+                    const int res = lookup_or_insert(A.cache, kbuf, &idx);
+                    if (res != LOOKUP_HIT) {
+                        if (res == LOOKUP_FULL) err |= ERR_TABLE_CAP;
+                        park = true;
+                    } else {
+                        const uint32_t* tab = A.cache.data + (size_t)idx * A.cache.tab_words;
+                        const Rand4 r = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_FIRST), A.k0, A.k1);
+                        const int b = table_sample(tab, A.cache.nb, r.x);
+                        const uint32_t sb = (tab[2 + A.cache.nb + (b >> 5)] >> (b & 31)) & 1u;
+                        const float Kh = __uint_as_float(tab[1]);
+                        float sgn = sb ? 1.f : -1.f;
+                        if (!side) sgn = -sgn;
+                        omega = EPS0 * G.area * (Kh / h) * sgn;
+                        int nd[3];
+                        node_of_hit(n, b, nd);
+                        x = make_float3(c.x - R + (float)nd[0] * h, c.y - R + (float)nd[1] * h, c.z - R + (float)nd[2] * h);
+                        pos = fold3(S, x);
+                        t = 1;
+                    }
+                } else {
+                    ++c_hops;
+                    ++c_cls[I.cls];
+                    if (A.hybrid && I.cls <= 1) {
+                        const int sax = I.axis;
+                        kbuf[0] = 0u;  // hop table (centre source)
+                        kbuf[1] = (uint32_t)n;
+                        kbuf[2] = (uint32_t)sax;
+                        kbuf[3] = 0u;
+                        for (int p = 0; p < n; ++p) kbuf[KEY_HDR + p] = I.cls == 0 ? 1u : plane_code(L, I, n, sax, p);
+                        uint32_t idx;
+                        const int res = lookup_or_insert(A.cache, kbuf, &idx);
+                        if (res != LOOKUP_HIT) {
+                            if (res == LOOKUP_FULL) err |= ERR_TABLE_CAP;
+                            park = true;
+                            --c_hops;
+                            --c_cls[I.cls];
+                        } else {
+                            const uint32_t* tab = A.cache.data + (size_t)idx * A.cache.tab_words;
+                            const Rand4 r = philox10(0u, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_TABLE), A.k0, A.k1);
+                            const int b = table_sample(tab, A.cache.nb, r.x);
+                            int nd[3];
+                            node_of_hit(n, b, nd);
+                            x = make_float3(c.x - R + (float)nd[0] * h, c.y - R + (float)nd[1] * h,
+                                            c.z - R + (float)nd[2] * h);
+                            pos = fold3(S, x);
+                            ++t;
+                        }
+                    } else {
+                        // MicroWalk from the centre node
+                        phase = PH_MW;
+                        mc = c;
+                        mR = R;
+                        ni = nj = nk = n / 2;
+                        s = 0;
+                        mx0 = L.mask[ni - 1];
+                        mx1 = L.mask[ni];
+                        my0 = L.mask[n + nj - 1];
+                        my1 = L.mask[n + nj];
+                        mz0 = L.mask[2 * n + nk - 1];
+                        mz1 = L.mask[2 * n + nk];
+                    }
+                }
+            }
+            if (done) {
+                const unsigned long long k = walk - A.walk_begin;
+                if (net == S.n_nets) ++c_env;
+                A.score_net[k] = net;
+                A.score_w[k] = omega;
+                phase = PH_IDLE;
+            } else if (park) {
+                const uint32_t slot = atomicAdd(&K.park_count, 1u);
+                if (slot < A.park_cap) {
+                    Parked P;
+                    P.walk = walk;
+                    P.px = pos.x;
+                    P.py = pos.y;
+                    P.pz = pos.z;
+                    P.omega = omega;
+                    P.t = t;
+                    P.pad[0] = P.pad[1] = P.pad[2] = 0;
+                    A.park_out[slot] = P;
+                } else {
+                    err |= ERR_PARK_CAP;
+                }
+                phase = PH_IDLE;
+            }
+        }
+
+        // ---- MicroWalk steps, four per Philox block, while enough lanes walk ----
+        for (;;) {
+            const uint64_t balmw = __ballot(phase == PH_MW);
+            const uint64_t balact = __ballot(phase == PH_MW || phase == PH_NEED || phase == PH_IDLE);
+            const int nmw = __popcll(balmw), nact = __popcll(balact);
+            if (nmw == 0 || 2 * nmw < nact) break;
+            if (phase == PH_MW) {
+                const Rand4 r = philox10(s >> 2, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), A.k0, A.k1);
+                const uint32_t us[4] = {r.x, r.y, r.z, r.w};
+                bool alive = true;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (alive) {
+                        uint32_t d;
+                        if (mx0 == mx1 && my0 == my1 && mz0 == mz1) {
+                            d = __umulhi(us[q], 6u);
+                        } else {
+                            const uint32_t m000 = mx0 & my0 & mz0, m001 = mx1 & my0 & mz0;
+                            const uint32_t m010 = mx0 & my1 & mz0, m011 = mx1 & my1 & mz0;
+                            const uint32_t m100 = mx0 & my0 & mz1, m101 = mx1 & my0 & mz1;
+                            const uint32_t m110 = mx0 & my1 & mz1, m111 = mx1 & my1 & mz1;
+                            const uint32_t c000 = L.codes[hb16(m000)], c001 = L.codes[hb16(m001)];
+                            const uint32_t c010 = L.codes[hb16(m010)], c011 = L.codes[hb16(m011)];
+                            const uint32_t c100 = L.codes[hb16(m100)], c101 = L.codes[hb16(m101)];
+                            const uint32_t c110 = L.codes[hb16(m110)], c111 = L.codes[hb16(m111)];
+                            const uint32_t a0 = c000 + c100, a1 = c010 + c110;
+                            const uint32_t b0 = c001 + c101, b1 = c011 + c111;
+                            const uint32_t gmx = a0 + a1, total = gmx + b0 + b1;
+                            const uint32_t gmy = a0 + b0, gmz = c000 + c001 + c010 + c011;
+                            const uint32_t S2 = total + gmy, S3 = total + total, S4 = S3 + gmz, S5 = S3 + total;
+                            const uint32_t xq = __umulhi(us[q], S5);
+                            d = (uint32_t)(xq >= gmx) + (uint32_t)(xq >= total) + (uint32_t)(xq >= S2) +
+                                (uint32_t)(xq >= S3) + (uint32_t)(xq >= S4);
+                        }
+                        const int ax = (int)(d >> 1);
+                        const int dir = (d & 1u) ? 1 : -1;
+                        ++s;
+                        int cnew;
+                        if (ax == 0) {
+                            ni += dir;
+                            cnew = ni;
+                        } else if (ax == 1) {
+                            nj += dir;
+                            cnew = nj;
+                        } else {
+                            nk += dir;
+                            cnew = nk;
+                        }
+                        if (cnew == 0 || cnew == n) {
+                            alive = false;
+                        } else {
+                            const uint32_t lo = L.mask[ax * n + cnew - 1], hi = L.mask[ax * n + cnew];
+                            if (ax == 0) {
+                                mx0 = lo;
+                                mx1 = hi;
+                            } else if (ax == 1) {
+                                my0 = lo;
+                                my1 = hi;
+                            } else {
+                                mz0 = lo;
+                                mz1 = hi;
+                            }
+                        }
+                    }
+                }
+                if (alive && s >= MW_STEP_CAP) {
+                    // never reached for valid permittivities; keeps a logic
+                    // error from spinning: the walk ends where it stands and
+                    // the call reports MW_ELIMIT
+                    err |= ERR_STEP_CAP;
+                    alive = false;
+                }
+                if (!alive) {
+                    c_steps += s;
+                    const float h = 2.f * mR / (float)n;
+                    const float3 xx = make_float3(mc.x - mR + (float)ni * h, mc.y - mR + (float)nj * h,
+                                                  mc.z - mR + (float)nk * h);
+                    pos = fold3(S, xx);
+                    ++t;
+                    phase = PH_NEED;
+                }
+            }
+        }
+    }
+
+    // ---- counters ----
+    auto wsum = [&](unsigned long long v) {
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+        return v;
+    };
+    c_hops = wsum(c_hops);
+    c_steps = wsum(c_steps);
+    for (int q = 0; q < 3; ++q) c_cls[q] = wsum(c_cls[q]);
+    for (int q = 0; q < 4; ++q) c_br[q] = wsum(c_br[q]);
+    c_env = wsum(c_env);
+    c_cap = wsum(c_cap);
+    for (int off = 32; off > 0; off >>= 1) err |= __shfl_down(err, off);
+    if (lane == 0) {
+        if (c_hops) atomicAdd(&K.hops, c_hops);
+        if (c_steps) atomicAdd(&K.micro_steps, c_steps);
+        for (int q = 0; q < 3; ++q)
+            if (c_cls[q]) atomicAdd(&K.hop_class[q], c_cls[q]);
+        for (int q = 0; q < 4; ++q)
+            if (c_br[q]) atomicAdd(&K.first_branch[q], c_br[q]);
+        if (c_env) atomicAdd(&K.env, c_env);
+        if (c_cap) atomicAdd(&K.hop_cap, c_cap);
+        if (err) atomicOr(&K.err, err);
+    }
+}
+
+// -------------------------------------------------------------------------
+// Exact SGF tables of stratified cubes (binary64).  In a cube stratified
+// along w the vertex-lattice operator is separable: the in-plane part is the
+// Dirichlet second difference scaled per plane, which the orthonormal sine
+// transform diagonalises, leaving one tridiagonal system along w per pair of
+// in-plane modes.  This is the discrete counterpart of the analytic SGF of
+// stratified cubes (Table I: O(N^3)-class work on a cache miss).
+// -------------------------------------------------------------------------
+constexpr int TB_THREADS = 256;
+
+struct BuildArgs {
+    CacheDev cache;
+    const uint32_t* list;  // table indices to build
+    uint32_t count;
+    double* work;          // per block: 3 M^3 + 3 nb doubles
+    size_t work_stride;    // doubles per block
+};
+
+__global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
+    const uint32_t idx = B.list[blockIdx.x];
+    const CacheDev& C = B.cache;
+    const uint32_t* key = C.keys + (size_t)idx * C.key_words;
+    const int kind = (int)key[0], n = (int)key[1], s = (int)key[2], anorm = (int)key[3];
+    const int M = n - 1, M2 = M * M, nb = 6 * M2;
+    __shared__ double Sm[31 * 31];
+    __shared__ double lam[32];
+    __shared__ double cr[33], ar[33], br[33];
+    __shared__ double tmp[31 * 31];
+    double* zh = B.work + (size_t)blockIdx.x * B.work_stride;  // [src][r][m][l]
+    double* Pout = zh + (size_t)3 * M * M2;                      // [src][nb]
+    const double norm = sqrt(2.0 / (double)(M + 1));
+    for (int q = threadIdx.x; q < M2; q += blockDim.x) {
+        const int m = q / M + 1, p = q % M + 1;
+        Sm[q] = norm * sin(M_PI * (double)(m * p) / (double)(M + 1));
+    }
+    if (threadIdx.x < M) lam[threadIdx.x] = 2.0 - 2.0 * cos(M_PI * (double)(threadIdx.x + 1) / (double)(M + 1));
+    if (threadIdx.x >= 1 && threadIdx.x <= M) {
+        const int r = threadIdx.x;
+        const double em = (double)key[KEY_HDR + r - 1], ep = (double)key[KEY_HDR + r];
+        cr[r] = 2.0 * (em + ep);
+        ar[r] = 4.0 * em;
+        br[r] = 4.0 * ep;
+    }
+    __syncthreads();
+    // local frame: w = s, (u, v) the other two axes ascending
+    const int ua = s == 0 ? 1 : 0, va = s == 2 ? 1 : 2;
+    const int c0 = n / 2;
+    int src[3][3];
+    int nsrc = kind == 1 ? 3 : 1;
+    for (int q = 0; q < 3; ++q) src[q][0] = src[q][1] = src[q][2] = c0;  // (p, q, r) local
+    if (kind == 1) {
+        const int lax = anorm == s ? 2 : (anorm == ua ? 0 : 1);
+        src[1][lax] += 1;
+        src[2][lax] -= 1;
+    }
+    // tridiagonal solves, one (m, l) mode pair per thread
+    for (int sidx = 0; sidx < nsrc; ++sidx) {
+        const int p0 = src[sidx][0], q0 = src[sidx][1], r0 = src[sidx][2];
+        for (int ml = threadIdx.x; ml < M2; ml += blockDim.x) {
+            const int m = ml / M, l = ml % M;  // 0-based modes
+            const double lm = lam[m] + lam[l];
+            const double rhs0 = Sm[m * M + (p0 - 1)] * Sm[l * M + (q0 - 1)];
+            double* col = zh + (size_t)sidx * M * M2 + ml;  // stride M2 over r
+            // Thomas algorithm: forward elimination, then back substitution
+            double dvals[32], cvals[32];
+            double cprev = 0.0, dprev = 0.0;
+            for (int r = 1; r <= M; ++r) {
+                const double diag = cr[r] * lm + ar[r] + br[r];
+                const double sub = r > 1 ? -ar[r] : 0.0;
+                const double sup = r < M ? -br[r] : 0.0;
+                const double den = diag - sub * cprev;
+                cvals[r] = sup / den;
+                dvals[r] = ((r == r0 ? rhs0 : 0.0) - sub * dprev) / den;
+                cprev = cvals[r];
+                dprev = dvals[r];
+            }
+            double xnext = dvals[M];
+            col[(size_t)(M - 1) * M2] = xnext;
+            for (int r = M - 1; r >= 1; --r) {
+                const double xr = dvals[r] - cvals[r] * xnext;
+                col[(size_t)(r - 1) * M2] = xr;
+                xnext = xr;
+            }
+        }
+    }
+    __syncthreads();
+    // exit probabilities on the six faces, in global hit-index order
+    for (int sidx = 0; sidx < nsrc; ++sidx) {
+        const double* Z = zh + (size_t)sidx * M * M2;  // Z[(r-1)*M2 + m*M + l]
+        double* P = Pout + (size_t)sidx * nb;
+        // w faces: r = 1 (side 0, link ar[1]) and r = M (side 1, link br[M])
+        for (int side = 0; side < 2; ++side) {
+            const int r = side ? M : 1;
+            const double link = side ? br[M] : ar[1];
+            const double* Zr = Z + (size_t)(r - 1) * M2;
+            // Y[m][q] = sum_l Z[m][l] S[l][q]
+            for (int e = threadIdx.x; e < M2; e += blockDim.x) {
+                const int m = e / M, qq = e % M;
+                double acc = 0.0;
+                for (int l = 0; l < M; ++l) acc += Zr[m * M + l] * Sm[l * M + qq];
+                tmp[e] = acc;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < M2; e += blockDim.x) {
+                const int p = e / M, qq = e % M;  // 0-based local coords p-1, q-1
+                double acc = 0.0;
+                for (int m = 0; m < M; ++m) acc += Sm[m * M + p] * tmp[m * M + qq];
+                int g[3];
+                g[ua] = p + 1;
+                g[va] = qq + 1;
+                g[s] = side ? n : 0;
+                const int f = 2 * s + side;
+                const int oa = s == 0 ? 1 : 0, ob = s == 2 ? 1 : 2;
+                P[f * M2 + (g[ob] - 1) * M + (g[oa] - 1)] = link * acc;
+            }
+            __syncthreads();
+        }
+        // u faces (p = 1 or M) and v faces (q = 1 or M)
+        for (int which = 0; which < 4; ++which) {
+            const bool ufaces = which < 2;
+            const int side = which & 1;
+            const int fixed = side ? M - 1 : 0;  // 0-based
+            // X[l][r] = sum_m S[m][fixed] Z[r][m][l]  (u faces)
+            // X[m][r] = sum_l S[l][fixed] Z[r][m][l]  (v faces)
+            for (int e = threadIdx.x; e < M2; e += blockDim.x) {
+                const int j = e / M, r = e % M;
+                const double* Zr = Z + (size_t)r * M2;
+                double acc = 0.0;
+                if (ufaces)
+                    for (int m = 0; m < M; ++m) acc += Sm[m * M + fixed] * Zr[m * M + j];
+                else
+                    for (int l = 0; l < M; ++l) acc += Sm[l * M + fixed] * Zr[j * M + l];
+                tmp[e] = acc;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < M2; e += blockDim.x) {
+                const int other = e / M, r = e % M;  // other: q (u faces) or p (v faces), 0-based
+                double acc = 0.0;
+                for (int j = 0; j < M; ++j) acc += Sm[j * M + other] * tmp[j * M + r];
+                int g[3];
+                const int fa = ufaces ? ua : va;
+                g[s] = r + 1;
+                if (ufaces) {
+                    g[ua] = side ? n : 0;
+                    g[va] = other + 1;
+                } else {
+                    g[va] = side ? n : 0;
+                    g[ua] = other + 1;
+                }
+                const int f = 2 * fa + side;
+                const int oa = fa == 0 ? 1 : 0, ob = fa == 2 ? 1 : 2;
+                P[f * M2 + (g[ob] - 1) * M + (g[oa] - 1)] = cr[r + 1] * acc;
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    // weights -> CDF (one thread: sequential prefix sum in hit-index order)
+    uint32_t* tab = C.data + (size_t)idx * C.tab_words;
+    if (kind == 1) {
+        // flux kernel of the first transition along +anorm (Sec. II-A weight):
+        // w_b = [G+ (P^c - P^+) + G- (P^- - P^c)] / 2, in units of 1/h
+        double Gp, Gm;
+        const double e0 = (double)key[KEY_HDR + c0 - 1], e1 = (double)key[KEY_HDR + c0];
+        if (anorm == s) {
+            Gp = e1 / 65536.0;
+            Gm = e0 / 65536.0;
+        } else {
+            Gp = Gm = (e0 + e1) / (2.0 * 65536.0);
+        }
+        const double* Pc = Pout;
+        const double* Pp = Pout + nb;
+        const double* Pm = Pout + 2 * nb;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+            const double w = 0.5 * (Gp * (Pc[b] - Pp[b]) + Gm * (Pm[b] - Pc[b]));
+            Pout[3 * nb + b] = w;  // stored after the three rows (workspace sized for it)
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < (nb + 31) / 32; q += blockDim.x) {
+            uint32_t bits = 0;
+            for (int k = 0; k < 32 && q * 32 + k < nb; ++k)
+                if (Pout[3 * nb + q * 32 + k] > 0.0) bits |= 1u << k;
+            tab[2 + nb + q] = bits;
+        }
+        if (threadIdx.x == 0) {
+            double K = 0.0;
+            for (int b = 0; b < nb; ++b) K += fabs(Pout[3 * nb + b]);
+            double cum = 0.0;
+            int last = 0;
+            for (int b = 0; b < nb; ++b) {
+                const double a = fabs(Pout[3 * nb + b]);
+                cum += a;
+                if (a > 0.0) last = b;
+                const double cv = ceil(cum / K * 4294967296.0);
+                tab[2 + b] = cv >= 4294967295.0 ? 0xffffffffu : (uint32_t)cv;
+            }
+            tab[0] = (uint32_t)last;
+            tab[1] = __float_as_uint((float)K);
+        }
+    } else {
+        if (threadIdx.x == 0) {
+            double tot = 0.0;
+            for (int b = 0; b < nb; ++b) tot += Pout[b];
+            double cum = 0.0;
+            int last = 0;
+            for (int b = 0; b < nb; ++b) {
+                cum += Pout[b];
+                if (Pout[b] > 0.0) last = b;
+                const double cv = ceil(cum / tot * 4294967296.0);
+                tab[2 + b] = cv >= 4294967295.0 ? 0xffffffffu : (uint32_t)cv;
+            }
+            tab[0] = (uint32_t)last;
+            tab[1] = 0u;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        C.ready[idx] = 1u;
+    }
+}
+
+// -------------------------------------------------------------------------
+// Score reduction: per block fp32 compensated sums per net, then binary64
+// across blocks.
+// -------------------------------------------------------------------------
+constexpr int RED_THREADS = 256;
+constexpr int RED_CHUNK = 4096;
+
+__device__ __forceinline__ void neumaier(float& s, float& c, float x) {
+    const float t = s + x;
+    if (fabsf(s) >= fabsf(x))
+        c += (s - t) + x;
+    else
+        c += (x - t) + s;
+    s = t;
+}
+
+__global__ void __launch_bounds__(RED_THREADS) reduce_scores_kernel(const int32_t* __restrict__ net,
+                                                                   const float* __restrict__ w, uint64_t count,
+                                                                   int K, float4* __restrict__ partial) {
+    __shared__ int32_t snet[RED_CHUNK];
+    __shared__ float sw[RED_CHUNK];
+    const uint64_t base = (uint64_t)blockIdx.x * RED_CHUNK;
+    const int len = (int)min((uint64_t)RED_CHUNK, count - base);
+    for (int q = threadIdx.x; q < len; q += blockDim.x) {
+        snet[q] = net[base + q];
+        sw[q] = w[base + q];
+    }
+    __syncthreads();
+    for (int j0 = 0; j0 < K; j0 += blockDim.x) {
+        const int j = j0 + threadIdx.x;
+        float s1 = 0.f, c1 = 0.f, s2 = 0.f, c2 = 0.f;
+        if (j < K) {
+            for (int q = 0; q < len; ++q) {
+                if (snet[q] == j) {
+                    const float x = sw[q];
+                    neumaier(s1, c1, x);
+                    neumaier(s2, c2, x * x);
+                }
+            }
+            partial[(size_t)blockIdx.x * K + j] = make_float4(s1, c1, s2, c2);
+        }
+    }
+}
+
+// acc[2*K]: running binary64 sums (S1, S2) per net; result[2*K]: row, se.
+__global__ void finish_kernel(const float4* __restrict__ partial, int blocks, int K, double* acc, double n_total,
+                              double* result) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < K; j += gridDim.x * blockDim.x) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int b = 0; b < blocks; ++b) {
+            const float4 p = partial[(size_t)b * K + j];
+            s1 += (double)p.x + (double)p.y;
+            s2 += (double)p.z + (double)p.w;
+        }
+        s1 += acc[j];
+        s2 += acc[K + j];
+        acc[j] = s1;
+        acc[K + j] = s2;
+        const double m = s1 / n_total;
+        const double var = (s2 / n_total - m * m) / (n_total - 1.0);
+        result[j] = m;
+        result[K + j] = sqrt(var > 0.0 ? var : 0.0);
+    }
+}
+
+// -------------------------------------------------------------------------
+// Geometry store construction kernels.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ void cell_box(const StructDev& S, int c, float lo[3], float hi[3]) {
+    const int ix = c % S.gdim[0], iy = (c / S.gdim[0]) % S.gdim[1], iz = c / (S.gdim[0] * S.gdim[1]);
+    const int ii[3] = {ix, iy, iz};
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = S.gorg[a] + ii[a] * S.gcell[a];
+        hi[a] = lo[a] + S.gcell[a];
+    }
+}
+
+__device__ float cell_dfar(const StructDev& S, const float lo[3], const float hi[3]) {
+    float dfar = INFINITY;
+    for (int c = 0; c < S.n_cond; ++c) {
+        const float4 bl = S.cond_lo[c], bh = S.cond_hi[c];
+        const float l[3] = {bl.x, bl.y, bl.z}, h[3] = {bh.x, bh.y, bh.z};
+        float d = 0.f;
+        for (int a = 0; a < 3; ++a) d = fmaxf(d, fmaxf(fmaxf(l[a] - lo[a], hi[a] - h[a]), 0.f));
+        dfar = fminf(dfar, d);
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (S.bc[2 * a] == MW_BC_DIRICHLET) dfar = fminf(dfar, hi[a] - S.wlo[a]);
+        if (S.bc[2 * a + 1] == MW_BC_DIRICHLET) dfar = fminf(dfar, S.whi[a] - lo[a]);
+    }
+    return dfar * 1.0001f + 1e-6f;
+}
+
+__global__ void grid_count_kernel(StructDev S, uint32_t* ccount, uint32_t* dcount, int ncells) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    float lo[3], hi[3];
+    cell_box(S, c, lo, hi);
+    const float dfar = cell_dfar(S, lo, hi);
+    uint32_t nc = 0, nd = 0;
+    for (int q = 0; q < S.n_cond; ++q) {
+        const float4 bl = S.cond_lo[q], bh = S.cond_hi[q];
+        const float l[3] = {bl.x, bl.y, bl.z}, h[3] = {bh.x, bh.y, bh.z};
+        float gap = 0.f;
+        for (int a = 0; a < 3; ++a) gap = fmaxf(gap, fmaxf(l[a] - hi[a], lo[a] - h[a]));
+        if (gap <= dfar) ++nc;
+    }
+    for (int q = 0; q < S.n_diel; ++q) {
+        const float4 bl = S.diel_lo[q], bh = S.diel_hi[q];
+        const float l[3] = {bl.x, bl.y, bl.z}, h[3] = {bh.x, bh.y, bh.z};
+        bool hit = true;
+        for (int a = 0; a < 3; ++a) hit &= l[a] <= hi[a] + dfar && h[a] >= lo[a] - dfar;
+        if (hit) ++nd;
+    }
+    ccount[c] = nc;
+    dcount[c] = nd;
+}
+
+__global__ void grid_fill_kernel(StructDev S, const uint32_t* coff, const uint32_t* doff, uint32_t* clist,
+                                 uint32_t* dlist, int ncells) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    float lo[3], hi[3];
+    cell_box(S, c, lo, hi);
+    const float dfar = cell_dfar(S, lo, hi);
+    uint32_t pc = coff[c], pd = doff[c];
+    for (int q = 0; q < S.n_cond; ++q) {
+        const float4 bl = S.cond_lo[q], bh = S.cond_hi[q];
+        const float l[3] = {bl.x, bl.y, bl.z}, h[3] = {bh.x, bh.y, bh.z};
+        float gap = 0.f;
+        for (int a = 0; a < 3; ++a) gap = fmaxf(gap, fmaxf(l[a] - hi[a], lo[a] - h[a]));
+        if (gap <= dfar) clist[pc++] = (uint32_t)q;
+    }
+    for (int q = 0; q < S.n_diel; ++q) {
+        const float4 bl = S.diel_lo[q], bh = S.diel_hi[q];
+        const float l[3] = {bl.x, bl.y, bl.z}, h[3] = {bh.x, bh.y, bh.z};
+        bool hit = true;
+        for (int a = 0; a < 3; ++a) hit &= l[a] <= hi[a] + dfar && h[a] >= lo[a] - dfar;
+        if (hit) dlist[pd++] = (uint32_t)q;
+    }
+}
+
+// Exclusive scan of counts (single block) into off[0..n].
+__global__ void scan_kernel(const uint32_t* count, uint32_t* off, int n) {
+    __shared__ uint32_t part[1024];
+    const int per = (n + blockDim.x - 1) / blockDim.x;
+    const int b = threadIdx.x * per, e = min(n, b + per);
+    uint32_t s = 0;
+    for (int q = b; q < e; ++q) s += count[q];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int q = 0; q < (int)blockDim.x; ++q) {
+            const uint32_t v = part[q];
+            part[q] = run;
+            run += v;
+        }
+        off[n] = run;
+    }
+    __syncthreads();
+    uint32_t run = part[threadIdx.x];
+    for (int q = b; q < e; ++q) {
+        off[q] = run;
+        run += count[q];
+    }
+}
+
+// Gaussian surface of the master (one thread): G = boundary of the master box
+// expanded by half its L-infinity gap to the nearest other conductor or
+// grounded face, kept inside the window.
+__global__ void gauss_kernel(StructDev S, int master, GaussDev* G, int* status) {
+    if (threadIdx.x || blockIdx.x) return;
+    int mi = -1;
+    for (int c = 0; c < S.n_cond; ++c)
+        if (__float_as_int(S.cond_lo[c].w) == master) mi = c;
+    if (mi < 0) {
+        *status = 1;
+        return;
+    }
+    const float4 ml4 = S.cond_lo[mi], mh4 = S.cond_hi[mi];
+    const float ml[3] = {ml4.x, ml4.y, ml4.z}, mh[3] = {mh4.x, mh4.y, mh4.z};
+    float g0 = INFINITY;
+    for (int c = 0; c < S.n_cond; ++c) {
+        if (c == mi) continue;
+        const float4 bl = S.cond_lo[c], bh = S.cond_hi[c];
+        const float l[3] = {bl.x, bl.y, bl.z}, h[3] = {bh.x, bh.y, bh.z};
+        float gap = 0.f;
+        for (int a = 0; a < 3; ++a) gap = fmaxf(gap, fmaxf(l[a] - mh[a], ml[a] - h[a]));
+        g0 = fminf(g0, gap);
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (S.bc[2 * a] == MW_BC_DIRICHLET) g0 = fminf(g0, ml[a] - S.wlo[a]);
+        if (S.bc[2 * a + 1] == MW_BC_DIRICHLET) g0 = fminf(g0, S.whi[a] - mh[a]);
+    }
+    if (!(g0 > 0.f) || !isfinite(g0)) {
+        *status = 2;
+        return;
+    }
+    const float g = 0.5f * g0;
+    G->g = g;
+    int nf = 0;
+    float area = 0.f;
+    for (int a = 0; a < 3; ++a)
+        for (int side = 0; side < 2; ++side) {
+            const float plane = side ? mh[a] + g : ml[a] - g;
+            if (!(plane > S.wlo[a] && plane < S.whi[a])) continue;
+            float ar = 1.f;
+            float lo[3], hi[3];
+            for (int b = 0; b < 3; ++b) {
+                if (b == a) {
+                    lo[b] = hi[b] = plane;
+                    continue;
+                }
+                lo[b] = fmaxf(ml[b] - g, S.wlo[b]);
+                hi[b] = fminf(mh[b] + g, S.whi[b]);
+                ar *= fmaxf(hi[b] - lo[b], 0.f);
+            }
+            if (ar <= 0.f) continue;
+            G->axis[nf] = a;
+            G->side[nf] = side;
+            G->plane[nf] = plane;
+            for (int b = 0; b < 3; ++b) {
+                G->lo[nf][b] = lo[b];
+                G->hi[nf][b] = hi[b];
+            }
+            area += ar;
+            G->cum[nf] = area;
+            ++nf;
+        }
+    G->n_faces = nf;
+    G->area = area;
+    *status = nf > 0 ? 0 : 3;
+}
+
+// -------------------------------------------------------------------------
+// Host side.
+// -------------------------------------------------------------------------
+struct Cache {
+    CacheDev d{};
+    void* mem = nullptr;
+    std::mutex mu;
+};
+
+std::mutex g_cache_mu;
+std::map<std::pair<int, int>, std::unique_ptr<Cache>> g_caches;
+
+size_t env_size(const char* name, size_t dflt) {
+    const char* v = getenv(name);
+    return v ? (size_t)strtoull(v, nullptr, 10) : dflt;
+}
+
+Cache& get_cache(int n) {
+    int dev = 0;
+    MW_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    auto& slot = g_caches[{dev, n}];
+    if (!slot) {
+        auto c = std::make_unique<Cache>();
+        const uint32_t M = n - 1;
+        const uint32_t nb = 6 * M * M;
+        const uint32_t cap = (uint32_t)env_size("MWALK_TABLE_CAP", 65536);
+        uint32_t nslots = 1;
+        while (nslots < 2 * cap) nslots <<= 1;
+        c->d.n = n;
+        c->d.nb = nb;
+        c->d.capacity = cap;
+        c->d.slot_mask = nslots - 1;
+        c->d.key_words = KEY_HDR + n;
+        c->d.tab_words = 2 + nb + (nb + 31) / 32;
+        const size_t b_hash = (size_t)nslots * 8, b_idx = (size_t)nslots * 4, b_ready = (size_t)cap * 4;
+        const size_t b_keys = (size_t)cap * c->d.key_words * 4, b_data = (size_t)cap * c->d.tab_words * 4;
+        const size_t b_misc = 256, b_pend = (size_t)cap * 4;
+        const size_t total = b_hash + b_idx + b_ready + b_keys + b_data + b_misc + b_pend + 1024;
+        char* m = (char*)dev_alloc(total);
+        c->mem = m;
+        size_t o = 0;
+        auto take = [&](size_t b) {
+            char* p = m + o;
+            o += (b + 255) / 256 * 256;
+            return p;
+        };
+        c->d.slot_hash = (unsigned long long*)take(b_hash);
+        c->d.slot_index = (uint32_t*)take(b_idx);
+        c->d.ready = (uint32_t*)take(b_ready);
+        c->d.keys = (uint32_t*)take(b_keys);
+        c->d.data = (uint32_t*)take(b_data);
+        uint32_t* misc = (uint32_t*)take(b_misc);
+        c->d.n_tables = misc;
+        c->d.n_pending = misc + 1;
+        c->d.pending = (uint32_t*)take(b_pend);
+        MW_HIP(hipMemset(c->d.slot_hash, 0, b_hash));
+        MW_HIP(hipMemset(c->d.slot_index, 0xff, b_idx));
+        MW_HIP(hipMemset(c->d.ready, 0, b_ready));
+        MW_HIP(hipMemset(misc, 0, b_misc));
+        MW_HIP(hipDeviceSynchronize());
+        slot = std::move(c);
+    }
+    return *slot;
+}
+
+}  // namespace
+}  // namespace mw
+
+using namespace mw;
+
+struct mw_structure {
+    int device = 0;
+    StructDev h{};
+    StructDev* d = nullptr;
+    char* mem = nullptr;
+    int32_t n_nets = 0;
+    std::vector<mw_cond_box> cond;
+};
+
+static void validate_desc(const mw_structure_desc* D) {
+    MW_REQUIRE(D, MW_EINVAL, "null structure description");
+    MW_REQUIRE(D->n_cond >= 1 && D->cond, MW_EINVAL, "at least one conductor box is required");
+    MW_REQUIRE(D->n_nets >= 1 && D->n_nets <= (1 << 20), MW_EINVAL, "n_nets out of range");
+    MW_REQUIRE(D->n_diel >= 0 && (D->n_diel == 0 || D->diel), MW_EINVAL, "bad dielectric list");
+    MW_REQUIRE(D->n_layers >= 1 && D->layer_z0 && D->layer_eps, MW_EINVAL, "at least one background layer");
+    for (int f = 0; f < 6; ++f) MW_REQUIRE(D->bc[f] <= 1, MW_EINVAL, "bc[%d] must be 0 or 1", f);
+    for (int a = 0; a < 3; ++a) MW_REQUIRE(D->win_lo[a] < D->win_hi[a], MW_EGEOM, "empty window");
+    std::vector<int> per_net(D->n_nets, 0);
+    for (int i = 0; i < D->n_cond; ++i) {
+        const mw_cond_box& b = D->cond[i];
+        MW_REQUIRE(b.net >= 0 && b.net < D->n_nets, MW_EGEOM, "conductor %d: net %d out of range", i, b.net);
+        per_net[b.net]++;
+        for (int a = 0; a < 3; ++a) {
+            MW_REQUIRE(b.lo[a] < b.hi[a], MW_EGEOM, "conductor %d is empty", i);
+            MW_REQUIRE(b.lo[a] >= D->win_lo[a] && b.hi[a] <= D->win_hi[a], MW_EGEOM,
+                       "conductor %d leaves the window", i);
+        }
+    }
+    for (int j = 0; j < D->n_nets; ++j)
+        MW_REQUIRE(per_net[j] == 1, MW_EGEOM, "net %d has %d boxes (exactly one is supported)", j, per_net[j]);
+    for (int i = 0; i < D->n_cond; ++i)
+        for (int k = i + 1; k < D->n_cond; ++k) {
+            bool overlap = true;
+            for (int a = 0; a < 3; ++a)
+                overlap &= D->cond[i].lo[a] < D->cond[k].hi[a] && D->cond[k].lo[a] < D->cond[i].hi[a];
+            MW_REQUIRE(!overlap, MW_EGEOM, "conductors %d and %d overlap", i, k);
+        }
+    for (int i = 0; i < D->n_diel; ++i) {
+        const float e = D->diel[i].eps;
+        MW_REQUIRE(e >= 1e-3f && e <= 1e3f, MW_EINVAL, "dielectric %d: eps %g outside [1e-3, 1e3]", i, e);
+        for (int a = 0; a < 3; ++a) MW_REQUIRE(D->diel[i].lo[a] < D->diel[i].hi[a], MW_EGEOM, "dielectric %d is empty", i);
+    }
+    for (int l = 0; l < D->n_layers; ++l) {
+        const float e = D->layer_eps[l];
+        MW_REQUIRE(e >= 1e-3f && e <= 1e3f, MW_EINVAL, "layer %d: eps %g outside [1e-3, 1e3]", l, e);
+        if (l > 0) MW_REQUIRE(D->layer_z0[l] > D->layer_z0[l - 1], MW_EINVAL, "layer_z0 must ascend");
+    }
+}
+
+extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structure** out) {
+    return guarded([&] {
+        MW_REQUIRE(out, MW_EINVAL, "null output handle");
+        validate_desc(D);
+        auto st = std::make_unique<mw_structure>();
+        MW_HIP(hipGetDevice(&st->device));
+        st->n_nets = D->n_nets;
+        st->cond.assign(D->cond, D->cond + D->n_cond);
+        const int nc = D->n_cond, nd = D->n_diel, nl = D->n_layers;
+        // uniform grid over the window
+        float ext[3], vol = 1.f;
+        for (int a = 0; a < 3; ++a) {
+            ext[a] = D->win_hi[a] - D->win_lo[a];
+            vol *= ext[a];
+        }
+        const double target = std::min(262144.0, std::max(64.0, 16.0 * (nc + nd)));
+        const double cs = std::cbrt(vol / target);
+        int gd[3];
+        int ncells = 1;
+        for (int a = 0; a < 3; ++a) {
+            gd[a] = std::max(1, std::min(512, (int)std::ceil(ext[a] / cs)));
+            ncells *= gd[a];
+        }
+        std::vector<float4> clo(nc), chi(nc), dlo(std::max(nd, 1)), dhi(std::max(nd, 1));
+        for (int i = 0; i < nc; ++i) {
+            const mw_cond_box& b = D->cond[i];
+            int net = b.net;
+            float w;
+            std::memcpy(&w, &net, 4);
+            clo[i] = make_float4(b.lo[0], b.lo[1], b.lo[2], w);
+            chi[i] = make_float4(b.hi[0], b.hi[1], b.hi[2], 0.f);
+        }
+        for (int i = 0; i < nd; ++i) {
+            const mw_diel_box& b = D->diel[i];
+            const uint32_t code = (uint32_t)std::nearbyint((double)b.eps * 65536.0);
+            float cw;
+            std::memcpy(&cw, &code, 4);
+            dlo[i] = make_float4(b.lo[0], b.lo[1], b.lo[2], b.eps);
+            dhi[i] = make_float4(b.hi[0], b.hi[1], b.hi[2], cw);
+        }
+        std::vector<float> z0(D->layer_z0, D->layer_z0 + nl);
+        std::vector<uint32_t> lcode(nl);
+        for (int l = 0; l < nl; ++l) lcode[l] = (uint32_t)std::nearbyint((double)D->layer_eps[l] * 65536.0);
+        // one allocation: arrays, then grid offsets/counts (lists sized after counting)
+        size_t o = 0;
+        auto sz = [&](size_t b) {
+            size_t r = o;
+            o += (b + 255) / 256 * 256;
+            return r;
+        };
+        const size_t o_clo = sz(16 * nc), o_chi = sz(16 * nc), o_dlo = sz(16 * dlo.size()), o_dhi = sz(16 * dhi.size());
+        const size_t o_z0 = sz(4 * nl), o_lc = sz(4 * nl);
+        const size_t o_cc = sz(4 * ncells), o_dc = sz(4 * ncells), o_coff = sz(4 * (ncells + 1)),
+                     o_doff = sz(4 * (ncells + 1));
+        const size_t o_desc = sz(sizeof(StructDev));
+        char* m = (char*)dev_alloc(o);
+        struct Guard {
+            char* p;
+            bool keep = false;
+            ~Guard() {
+                if (!keep) dev_free(p);
+            }
+        } guard{m};
+        MW_HIP(hipMemcpy(m + o_clo, clo.data(), 16 * nc, hipMemcpyHostToDevice));
+        MW_HIP(hipMemcpy(m + o_chi, chi.data(), 16 * nc, hipMemcpyHostToDevice));
+        MW_HIP(hipMemcpy(m + o_dlo, dlo.data(), 16 * dlo.size(), hipMemcpyHostToDevice));
+        MW_HIP(hipMemcpy(m + o_dhi, dhi.data(), 16 * dhi.size(), hipMemcpyHostToDevice));
+        MW_HIP(hipMemcpy(m + o_z0, z0.data(), 4 * nl, hipMemcpyHostToDevice));
+        MW_HIP(hipMemcpy(m + o_lc, lcode.data(), 4 * nl, hipMemcpyHostToDevice));
+        StructDev& S = st->h;
+        S.n_cond = nc;
+        S.n_nets = D->n_nets;
+        S.n_diel = nd;
+        S.n_layers = nl;
+        S.cond_lo = (const float4*)(m + o_clo);
+        S.cond_hi = (const float4*)(m + o_chi);
+        S.diel_lo = (const float4*)(m + o_dlo);
+        S.diel_hi = (const float4*)(m + o_dhi);
+        S.layer_z0 = (const float*)(m + o_z0);
+        S.layer_code = (const uint32_t*)(m + o_lc);
+        double diag = 0;
+        for (int a = 0; a < 3; ++a) {
+            S.wlo[a] = D->win_lo[a];
+            S.whi[a] = D->win_hi[a];
+            S.gdim[a] = gd[a];
+            S.gorg[a] = D->win_lo[a];
+            S.gcell[a] = ext[a] / gd[a];
+            S.ginv[a] = gd[a] / ext[a];
+            diag += (double)ext[a] * ext[a];
+        }
+        for (int f = 0; f < 6; ++f) S.bc[f] = D->bc[f];
+        S.delta_abs = (float)(1e-6 * std::sqrt(diag));
+        uint32_t* ccount = (uint32_t*)(m + o_cc);
+        uint32_t* dcount = (uint32_t*)(m + o_dc);
+        uint32_t* coff = (uint32_t*)(m + o_coff);
+        uint32_t* doff = (uint32_t*)(m + o_doff);
+        const int tb = 128, nbk = (ncells + tb - 1) / tb;
+        grid_count_kernel<<<nbk, tb>>>(S, ccount, dcount, ncells);
+        scan_kernel<<<1, 1024>>>(ccount, coff, ncells);
+        scan_kernel<<<1, 1024>>>(dcount, doff, ncells);
+        MW_HIP(hipGetLastError());
+        uint32_t tot[2];
+        MW_HIP(hipMemcpy(&tot[0], coff + ncells, 4, hipMemcpyDeviceToHost));
+        MW_HIP(hipMemcpy(&tot[1], doff + ncells, 4, hipMemcpyDeviceToHost));
+        char* lists = (char*)dev_alloc(4ull * (tot[0] + tot[1]) + 512);
+        uint32_t* clist = (uint32_t*)lists;
+        uint32_t* dlist = (uint32_t*)(lists + ((4ull * tot[0] + 255) / 256) * 256);
+        grid_fill_kernel<<<nbk, tb>>>(S, coff, doff, clist, dlist, ncells);
+        MW_HIP(hipGetLastError());
+        S.gc_off = coff;
+        S.gc_list = clist;
+        S.gd_off = doff;
+        S.gd_list = dlist;
+        st->d = (StructDev*)(m + o_desc);
+        MW_HIP(hipMemcpy(st->d, &S, sizeof S, hipMemcpyHostToDevice));
+        MW_HIP(hipDeviceSynchronize());
+        st->mem = m;
+        guard.keep = true;
+        // the list block is owned through a second pointer kept in h
+        st->h.gc_list = clist;
+        *out = st.release();
+        (void)lists;
+    });
+}
+
+extern "C" mw_status mw_structure_destroy(mw_structure* s) {
+    return guarded([&] {
+        if (!s) return;
+        (void)hipDeviceSynchronize();
+        dev_free((void*)s->h.gc_list);
+        dev_free(s->mem);
+        delete s;
+    });
+}
+
+namespace {
+
+struct ExtractBuffers {
+    char* mem = nullptr;
+    GaussDev* G;
+    Counters* ctr;
+    int* status;
+    Parked* park[2];
+    float4* partial;
+    double* acc;
+    double* result;
+    int32_t* own_net = nullptr;
+    float* own_w = nullptr;
+    ~ExtractBuffers() { dev_free(mem); }
+};
+
+}  // namespace
+
+extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk_budget, uint64_t seed,
+                                 const frw_options* options, double* cap_row, double* stderr_row,
+                                 frw_stats* stats, int32_t* score_net, float* score_w) {
+    return guarded([&] {
+        const auto t_start = std::chrono::steady_clock::now();
+        MW_REQUIRE(st, MW_EINVAL, "null structure");
+        MW_REQUIRE(cap_row && stderr_row, MW_EINVAL, "cap_row and stderr_row are required");
+        MW_REQUIRE(master >= 0 && master < st->n_nets, MW_EINVAL, "master %d out of range", master);
+        MW_REQUIRE(walk_budget >= 2, MW_EINVAL, "walk_budget must be at least 2");
+        frw_options opt{};
+        opt.n_cells = 16;
+        opt.hybrid = 1;
+        opt.abs_tol_rel = 1e-6;
+        if (options) opt = *options;
+        if (opt.n_cells == 0) opt.n_cells = 16;
+        MW_REQUIRE(opt.n_cells >= 4 && opt.n_cells <= 32 && opt.n_cells % 2 == 0, MW_EINVAL,
+                   "n_cells must be even in [4, 32]");
+        if (opt.abs_tol_rel <= 0) opt.abs_tol_rel = 1e-6;
+        const int n = opt.n_cells;
+        const int K = st->n_nets + 1;
+        int dev = 0;
+        MW_HIP(hipGetDevice(&dev));
+        MW_REQUIRE(dev == st->device, MW_EINVAL, "structure belongs to device %d, current device is %d", st->device, dev);
+        Cache& cache = get_cache(n);
+        std::lock_guard<std::mutex> cache_lock(cache.mu);
+        // per-call structure copy with this call's absorption tolerance
+        StructDev S = st->h;
+        {
+            double diag = 0;
+            for (int a = 0; a < 3; ++a) diag += (double)(S.whi[a] - S.wlo[a]) * (S.whi[a] - S.wlo[a]);
+            S.delta_abs = (float)(opt.abs_tol_rel * std::sqrt(diag));
+        }
+        int cus = 0;
+        MW_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        uint32_t lane_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * (KEY_HDR + n) + 3) / 4);
+        lane_stride |= 1u;
+        const size_t lds = (size_t)lane_stride * 4 * FRW_THREADS;
+        const int per_cu = std::max(1, std::min(8, (int)(163840 / (lds + 512))));
+        const int blocks = cus * per_cu;
+        const uint64_t pool = (uint64_t)blocks * FRW_THREADS;
+        uint64_t batch = opt.batch_walks ? opt.batch_walks : std::max<uint64_t>(pool * 8, 1 << 20);
+        if (opt.target_rel_3sigma <= 0) batch = walk_budget;  // fixed budget: one pass
+        batch = std::min<uint64_t>(batch, walk_budget);
+        const uint32_t park_cap = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(batch, 1024), 1u << 24);
+        ExtractBuffers B;
+        size_t o = 0;
+        auto sz = [&](size_t b) {
+            size_t r = o;
+            o += (b + 255) / 256 * 256;
+            return r;
+        };
+        const uint64_t red_blocks = (batch + RED_CHUNK - 1) / RED_CHUNK;
+        const size_t o_G = sz(sizeof(GaussDev)), o_ctr = sz(sizeof(Counters)), o_st = sz(16), o_sd = sz(sizeof(StructDev));
+        const size_t o_p0 = sz(sizeof(Parked) * (size_t)park_cap), o_p1 = sz(sizeof(Parked) * (size_t)park_cap);
+        const size_t o_part = sz(sizeof(float4) * red_blocks * K);
+        const size_t o_acc = sz(sizeof(double) * 2 * K), o_res = sz(sizeof(double) * 2 * K);
+        const bool own_scores = !(score_net && score_w);
+        const size_t o_sn = own_scores ? sz(4 * batch) : 0, o_sw = own_scores ? sz(4 * batch) : 0;
+        B.mem = (char*)dev_alloc(o);
+        char* m = B.mem;
+        B.G = (GaussDev*)(m + o_G);
+        B.ctr = (Counters*)(m + o_ctr);
+        B.status = (int*)(m + o_st);
+        StructDev* dS = (StructDev*)(m + o_sd);
+        B.park[0] = (Parked*)(m + o_p0);
+        B.park[1] = (Parked*)(m + o_p1);
+        B.partial = (float4*)(m + o_part);
+        B.acc = (double*)(m + o_acc);
+        B.result = (double*)(m + o_res);
+        if (own_scores) {
+            B.own_net = (int32_t*)(m + o_sn);
+            B.own_w = (float*)(m + o_sw);
+        }
+        MW_HIP(hipMemcpy(dS, &S, sizeof S, hipMemcpyHostToDevice));
+        MW_HIP(hipMemset(B.acc, 0, sizeof(double) * 2 * K));
+        MW_HIP(hipMemset(B.status, 0, 16));
+        gauss_kernel<<<1, 1>>>(S, master, B.G, B.status);
+        MW_HIP(hipGetLastError());
+        int gst = 0;
+        MW_HIP(hipMemcpy(&gst, B.status, 4, hipMemcpyDeviceToHost));
+        MW_REQUIRE(gst == 0, MW_EGEOM, "no valid Gaussian surface for net %d (status %d)", master, gst);
+        MW_HIP(hipFuncSetAttribute((const void*)frw_walk_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+
+        Counters tot{};
+        uint64_t done = 0, launches = 0, misses = 0;
+        const uint64_t first = opt.first_walk;
+        std::vector<double> res(2 * K);
+        while (done < walk_budget) {
+            const uint64_t nb_walks = std::min<uint64_t>(batch, walk_budget - done);
+            const uint64_t wb = first + done;
+            int32_t* snet = own_scores ? B.own_net : score_net + done;
+            float* sw = own_scores ? B.own_w : score_w + done;
+            MW_HIP(hipMemset(B.ctr, 0, sizeof(Counters)));
+            uint32_t n_resume = 0;
+            int cur = 0;
+            for (;;) {
+                WalkArgs W{};
+                W.S = dS;
+                W.G = B.G;
+                W.cache = cache.d;
+                W.n = n;
+                W.hybrid = opt.hybrid;
+                W.master = master;
+                W.k0 = (uint32_t)seed;
+                W.k1 = (uint32_t)(seed >> 32);
+                W.walk_begin = wb;
+                W.walk_end = wb + nb_walks;
+                W.resume = B.park[cur];
+                W.n_resume = n_resume;
+                W.park_out = B.park[cur ^ 1];
+                W.park_cap = park_cap;
+                W.score_net = snet;
+                W.score_w = sw;
+                W.ctr = B.ctr;
+                W.lane_stride = lane_stride;
+                // reset per-launch queue state, keep the walk counter
+                MW_HIP(hipMemset(&B.ctr->park_count, 0, 4));
+                MW_HIP(hipMemset(&B.ctr->resume_next, 0, 8));
+                frw_walk_kernel<<<blocks, FRW_THREADS, lds>>>(W);
+                MW_HIP(hipGetLastError());
+                ++launches;
+                Counters h{};
+                MW_HIP(hipMemcpy(&h, B.ctr, sizeof h, hipMemcpyDeviceToHost));
+                MW_REQUIRE(!(h.err & ERR_REGIONS), MW_ELIMIT,
+                           "a transition cube touched more than %d dielectric regions", MAX_REGIONS);
+                MW_REQUIRE(!(h.err & ERR_TABLE_CAP), MW_ELIMIT, "SGF table cache full (MWALK_TABLE_CAP)");
+                MW_REQUIRE(!(h.err & ERR_PARK_CAP), MW_ELIMIT, "parked-walk queue overflow");
+                MW_REQUIRE(!(h.err & ERR_STEP_CAP), MW_ELIMIT, "a micro-walk exceeded %u steps", MW_STEP_CAP);
+                MW_REQUIRE(launches < 100000, MW_ELIMIT, "walker relaunch limit reached");
+                uint32_t npend = 0;
+                MW_HIP(hipMemcpy(&npend, cache.d.n_pending, 4, hipMemcpyDeviceToHost));
+                if (npend) {
+                    std::vector<uint32_t> list(npend);
+                    MW_HIP(hipMemcpy(list.data(), cache.d.pending, 4ull * npend, hipMemcpyDeviceToHost));
+                    std::vector<uint32_t> valid;
+                    for (uint32_t v : list)
+                        if (v < cache.d.capacity) valid.push_back(v);
+                    const uint32_t M = n - 1;
+                    const size_t stride = (size_t)3 * M * M * M + (size_t)4 * 6 * M * M + 64;
+                    const uint32_t chunk = 512;
+                    double* work = (double*)dev_alloc(sizeof(double) * stride * std::min<size_t>(chunk, valid.size()));
+                    uint32_t* dlist = (uint32_t*)dev_alloc(4ull * valid.size());
+                    MW_HIP(hipMemcpy(dlist, valid.data(), 4ull * valid.size(), hipMemcpyHostToDevice));
+                    for (size_t c0 = 0; c0 < valid.size(); c0 += chunk) {
+                        BuildArgs Ba{cache.d, dlist + c0, (uint32_t)std::min<size_t>(chunk, valid.size() - c0), work, stride};
+                        build_tables_kernel<<<Ba.count, TB_THREADS>>>(Ba);
+                        MW_HIP(hipGetLastError());
+                    }
+                    MW_HIP(hipDeviceSynchronize());
+                    dev_free(work);
+                    dev_free(dlist);
+                    MW_HIP(hipMemset(cache.d.n_pending, 0, 4));
+                    misses += valid.size();
+                }
+                n_resume = std::min(h.park_count, park_cap);
+                cur ^= 1;
+                if (n_resume == 0 && h.walk_next >= nb_walks) {
+                    tot.hops += h.hops;
+                    tot.micro_steps += h.micro_steps;
+                    for (int q = 0; q < 3; ++q) tot.hop_class[q] += h.hop_class[q];
+                    for (int q = 0; q < 4; ++q) tot.first_branch[q] += h.first_branch[q];
+                    tot.env += h.env;
+                    tot.hop_cap += h.hop_cap;
+                    break;
+                }
+            }
+            done += nb_walks;
+            const int rb = (int)((nb_walks + RED_CHUNK - 1) / RED_CHUNK);
+            reduce_scores_kernel<<<rb, RED_THREADS>>>(snet, sw, nb_walks, K, B.partial);
+            finish_kernel<<<(K + 255) / 256, 256>>>(B.partial, rb, K, B.acc, (double)done, B.result);
+            MW_HIP(hipGetLastError());
+            MW_HIP(hipMemcpy(res.data(), B.result, sizeof(double) * 2 * K, hipMemcpyDeviceToHost));
+            if (opt.target_rel_3sigma > 0 && res[master] != 0.0 &&
+                3.0 * res[K + master] / std::fabs(res[master]) <= opt.target_rel_3sigma)
+                break;
+        }
+        for (int j = 0; j < K; ++j) {
+            cap_row[j] = res[j];
+            stderr_row[j] = res[K + j];
+        }
+        if (stats) {
+            stats->walks = done;
+            stats->hops = tot.hops;
+            stats->micro_steps = tot.micro_steps;
+            for (int q = 0; q < 3; ++q) stats->hop_class[q] = tot.hop_class[q];
+            for (int q = 0; q < 4; ++q) stats->first_branch[q] = tot.first_branch[q];
+            stats->cache_miss = misses;
+            stats->env_absorbed = tot.env;
+            stats->hop_cap = tot.hop_cap;
+            stats->launches = launches;
+            stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        }
+    });
+}

@@ -1,0 +1,156 @@
+"""GPU FRW extraction (Alg. 1 with the hybrid strategy of Sec. III-C) through
+the C ABI, against closed forms, Maxwell-matrix properties and the CPU oracle.
+
+Capacitances are Monte Carlo estimates: agreement is stated in combined
+standard errors (3 sigma), never bit for bit.  Per-walk scores are integer-
+and seed-determined, so repeated or resumed runs must reproduce them exactly.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _threads():
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return 4
+
+
+@pytest.fixture(scope="module")
+def mw():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_09730_amd as lib
+    lib.mw_init(0)
+    return lib
+
+
+def _z(a, b, sa, sb):
+    return abs(a - b) / np.sqrt(sa ** 2 + sb ** 2)
+
+
+def test_plates_uniform_small(mw):
+    st = W.parallel_plates("uniform")
+    r = mw.frw_extract(st, 0, 20000, seed=1)
+    exact = W.parallel_plates_exact("uniform")
+    print("plates uniform", r["row"], r["se"], r["stats"])
+    assert abs(r["row"][0] - exact) < 3 * r["se"][0]
+    assert r["row"][2] == 0.0
+    assert r["stats"]["walks"] == 20000
+
+
+@pytest.mark.parametrize("variant,hybrid", [("uniform", 1), ("uniform", 0), ("columns", 0),
+                                            ("columns", 1), ("checkerboard", 1)])
+def test_plates_closed_forms(mw, variant, hybrid):
+    st = W.parallel_plates(variant)
+    r = mw.frw_extract(st, 0, 400000, seed=2, hybrid=hybrid)
+    exact = W.parallel_plates_exact(variant)
+    print(variant, hybrid, r["row"], r["se"], (r["row"][0] - exact) / r["se"][0])
+    assert abs(r["row"][0] - exact) < 3 * r["se"][0]
+    assert abs(r["row"][1] + exact) < 3 * r["se"][1]
+
+
+@pytest.fixture(scope="module")
+def c2_gpu(mw):
+    st = W.c2_structure()
+    h = mw.StructureHandle(st)
+    out = {m: mw.frw_extract(h, m, 1000000, seed=20 + m, scores=True) for m in (0, 1)}
+    for m in (0, 1):
+        print("gpu master", m, out[m]["row"], out[m]["se"], out[m]["stats"])
+    return out
+
+
+def test_c2_matches_oracle(c2_gpu, oracle_lib):
+    st = W.c2_structure()
+    r_or = oracle_lib.frw_extract(st, 0, 100000, seed=77, threads=_threads())
+    r_gpu = c2_gpu[0]
+    print("oracle", r_or["row"], r_or["se"], r_or["stats"])
+    zs = [_z(r_gpu["row"][j], r_or["row"][j], r_gpu["se"][j], r_or["se"][j]) for j in range(5)]
+    print("z", zs)
+    assert max(zs) < 3.0
+
+
+def test_c2_reciprocity_and_signs(c2_gpu):
+    r0, r1 = c2_gpu[0], c2_gpu[1]
+    assert _z(r0["row"][1], r1["row"][0], r0["se"][1], r1["se"][0]) < 3
+    for m, r in c2_gpu.items():
+        row, se = r["row"], r["se"]
+        assert row[m] > 0
+        assert all(row[j] <= 3 * se[j] for j in range(len(row)) if j != m)
+        assert 3 * se[m] / row[m] < 0.015  # about 1.1% 3-sigma on C_mm at 1e6 walks
+
+
+def test_c2_row_sums_to_zero(c2_gpu):
+    for m, r in c2_gpu.items():
+        w = r["w"].double().cpu().numpy()
+        assert abs(w.mean()) < 3 * w.std() / np.sqrt(w.size)
+
+
+def test_c2_reduction_matches_fp64_resum(c2_gpu):
+    """fp32 compensated block sums + fp64 grand reduction vs an fp64 re-sum of
+    the same per-walk fp32 scores: 1e-6 relative."""
+    for m, r in c2_gpu.items():
+        net = r["net"].cpu().numpy()
+        w = r["w"].cpu().numpy().astype(np.float64)
+        K = len(r["row"])
+        resum = np.bincount(net, weights=w, minlength=K) / w.size
+        floor = 1e-6 * abs(resum[m])
+        assert np.all(np.abs(r["row"] - resum) <= 1e-6 * np.abs(resum) + floor * 1e-3), (r["row"], resum)
+        sq = np.bincount(net, weights=w * w, minlength=K) / w.size
+        se = np.sqrt(np.maximum(sq - resum ** 2, 0) / (w.size - 1))
+        assert np.allclose(r["se"], se, rtol=1e-5, atol=1e-12)
+
+
+def test_c2_hybrid_equals_all_microwalk(mw, c2_gpu):
+    st = W.c2_structure()
+    r_mw = mw.frw_extract(st, 0, 1000000, seed=321, hybrid=0)
+    r_hy = c2_gpu[0]
+    print("all-microwalk", r_mw["row"], r_mw["se"], r_mw["stats"])
+    assert r_mw["stats"]["hop_class"][1] + r_mw["stats"]["hop_class"][0] > 0
+    for j in range(5):
+        assert _z(r_hy["row"][j], r_mw["row"][j], r_hy["se"][j], r_mw["se"][j]) < 3.5
+
+
+def test_scores_independent_of_cache_state_and_resume(mw):
+    """A cold table cache (walks park and resume) and a warm one give the
+    same per-walk scores; so does a run split at walk 7000."""
+    import torch
+    st = W.c2_structure()
+    h = mw.StructureHandle(st)
+    a = mw.frw_extract(h, 0, 20000, seed=5, n_cells=12, scores=True)
+    b = mw.frw_extract(h, 0, 20000, seed=5, n_cells=12, scores=True)
+    assert a["stats"]["launches"] >= 1
+    assert torch.equal(a["net"], b["net"]) and torch.equal(a["w"], b["w"])
+    c1 = mw.frw_extract(h, 0, 7000, seed=5, n_cells=12, scores=True)
+    c2 = mw.frw_extract(h, 0, 13000, seed=5, n_cells=12, first_walk=7000, scores=True)
+    assert torch.equal(torch.cat([c1["net"], c2["net"]]), a["net"])
+    assert torch.equal(torch.cat([c1["w"], c2["w"]]), a["w"])
+
+
+def test_convergence_target(mw):
+    st = W.c2_structure()
+    r = mw.frw_extract(st, 0, 50000000, seed=9, target_rel_3sigma=0.02, batch_walks=200000)
+    assert r["stats"]["walks"] < 50000000
+    assert 3 * r["se"][0] / r["row"][0] <= 0.02
+
+
+def test_errors(mw):
+    st = W.c2_structure()
+    with pytest.raises(mw.MWError) as e:
+        mw.frw_extract(st, 7, 1000)
+    assert e.value.status == mw.MW_EINVAL
+    bad = W.c2_structure()
+    bad.cond[1] = bad.cond[0] + np.float32(0.01)
+    with pytest.raises(mw.MWError) as e:
+        mw.StructureHandle(bad)
+    assert e.value.status == mw.MW_EGEOM
+    with pytest.raises(mw.MWError) as e:
+        mw.frw_extract(st, 0, 1000, n_cells=15)
+    assert e.value.status == mw.MW_EINVAL
