@@ -202,6 +202,8 @@ typedef struct {
     uint64_t hop_cap;         /* walks stopped by the 1e5-hop cap           */
     uint64_t launches;        /* walker-kernel launches                      */
     double seconds;           /* wall time of the call                      */
+    double walker_seconds;    /* summed duration of the walker-kernel launches
+                                 (HIP events on the launch stream)          */
 } frw_stats;
 
 /* ------------------------------------------------------------------------

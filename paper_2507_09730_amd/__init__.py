@@ -169,13 +169,15 @@ class frw_stats(ctypes.Structure):
                 ("micro_steps", ctypes.c_uint64), ("hop_class", ctypes.c_uint64 * 3),
                 ("first_branch", ctypes.c_uint64 * 4), ("cache_miss", ctypes.c_uint64),
                 ("env_absorbed", ctypes.c_uint64), ("hop_cap", ctypes.c_uint64),
-                ("launches", ctypes.c_uint64), ("seconds", ctypes.c_double)]
+                ("launches", ctypes.c_uint64), ("seconds", ctypes.c_double),
+                ("walker_seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {"walks": self.walks, "hops": self.hops, "micro_steps": self.micro_steps,
                 "hop_class": list(self.hop_class), "first_branch": list(self.first_branch),
                 "cache_miss": self.cache_miss, "env_absorbed": self.env_absorbed,
-                "hop_cap": self.hop_cap, "launches": self.launches, "seconds": self.seconds}
+                "hop_cap": self.hop_cap, "launches": self.launches, "seconds": self.seconds,
+                "walker_seconds": self.walker_seconds}
 
 
 def make_desc(st):

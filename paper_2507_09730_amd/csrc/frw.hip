@@ -1585,6 +1585,17 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
 
         Counters tot{};
         uint64_t done = 0, launches = 0, misses = 0;
+        double walker_ms = 0.0;
+        hipEvent_t ev0, ev1;
+        MW_HIP(hipEventCreate(&ev0));
+        MW_HIP(hipEventCreate(&ev1));
+        struct EvGuard {
+            hipEvent_t a, b;
+            ~EvGuard() {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+            }
+        } evguard{ev0, ev1};
         const uint64_t first = opt.first_walk;
         std::vector<double> res(2 * K);
         while (done < walk_budget) {
@@ -1618,11 +1629,16 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
                 // reset per-launch queue state, keep the walk counter
                 MW_HIP(hipMemset(&B.ctr->park_count, 0, 4));
                 MW_HIP(hipMemset(&B.ctr->resume_next, 0, 8));
+                MW_HIP(hipEventRecord(ev0, 0));
                 frw_walk_kernel<<<blocks, FRW_THREADS, lds>>>(W);
                 MW_HIP(hipGetLastError());
+                MW_HIP(hipEventRecord(ev1, 0));
                 ++launches;
                 Counters h{};
                 MW_HIP(hipMemcpy(&h, B.ctr, sizeof h, hipMemcpyDeviceToHost));
+                float ms = 0.f;
+                MW_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+                walker_ms += ms;
                 MW_REQUIRE(!(h.err & ERR_REGIONS), MW_ELIMIT,
                            "a transition cube touched more than %d dielectric regions", MAX_REGIONS);
                 MW_REQUIRE(!(h.err & ERR_TABLE_CAP), MW_ELIMIT, "SGF table cache full (MWALK_TABLE_CAP)");
@@ -1691,6 +1707,7 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
             stats->hop_cap = tot.hop_cap;
             stats->launches = launches;
             stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+            stats->walker_seconds = walker_ms * 1e-3;
         }
     });
 }
