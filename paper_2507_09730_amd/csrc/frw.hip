@@ -259,11 +259,22 @@ __device__ CubeInfo build_cube(const StructDev& S, int cell, float3 c, float R, 
         const uint16_t bit = (uint16_t)(1u << nbits);
         L.codes[nbits] = __float_as_uint(bhi.w);
         ++nbits;
+        const float inv_h = (float)n / (2.f * R);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            for (int i = 0; i < n; ++i) {
-                const float x = fold(S, a, lo0[a] + ((float)i + 0.5f) * h);
-                if (x >= bl[a] && x < bh[a]) L.mask[a * n + i] |= bit;
+            const bool crosses = (S.bc[2 * a] == MW_BC_NEUMANN && lo0[a] < S.wlo[a]) ||
+                                 (S.bc[2 * a + 1] == MW_BC_NEUMANN && lo0[a] + 2.f * R > S.whi[a]);
+            if (!crosses) {
+                // cells whose centre lo0 + (i + 1/2) h lies in [bl, bh)
+                const float f0 = fminf(fmaxf((bl[a] - lo0[a]) * inv_h - 0.5f, -1.f), (float)n + 1.f);
+                const float f1 = fminf(fmaxf((bh[a] - lo0[a]) * inv_h - 0.5f, -1.f), (float)n + 1.f);
+                const int i0 = max((int)ceilf(f0), 0), i1 = min((int)ceilf(f1), n);
+                for (int i = i0; i < i1; ++i) L.mask[a * n + i] |= bit;
+            } else {
+                for (int i = 0; i < n; ++i) {
+                    const float x = fold(S, a, lo0[a] + ((float)i + 0.5f) * h);
+                    if (x >= bl[a] && x < bh[a]) L.mask[a * n + i] |= bit;
+                }
             }
         }
     }
@@ -314,32 +325,42 @@ __device__ __forceinline__ uint32_t plane_code(LaneCube L, const CubeInfo& I, in
     return L.codes[hb16(L.mask[s * n + p] & I.present)];
 }
 
-// Mean code of plane p normal to a (rounded half to even), summing runs of
-// equal masks along the two in-plane axes.
-__device__ uint32_t plane_mean_code(LaneCube L, int n, int a, int p) {
+// Mean codes of the planes normal to a (rounded half to even) written to
+// out[0..n): each plane sums its cells by runs of equal masks along the two
+// in-plane axes; planes whose own mask equals the previous plane's repeat it.
+__device__ void plane_mean_codes(LaneCube L, int n, int a, uint32_t* out) {
     const int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
-    const uint32_t ma = L.mask[a * n + p];
-    unsigned long long sum = 0;
-    int i = 0;
-    while (i < n) {
-        const uint32_t mu = L.mask[u * n + i];
-        int li = 1;
-        while (i + li < n && L.mask[u * n + i + li] == mu) ++li;
-        const uint32_t mau = ma & mu;
-        int j = 0;
-        while (j < n) {
-            const uint32_t mv = L.mask[v * n + j];
-            int lj = 1;
-            while (j + lj < n && L.mask[v * n + j + lj] == mv) ++lj;
-            sum += (unsigned long long)(li * lj) * L.codes[hb16(mau & mv)];
-            j += lj;
-        }
-        i += li;
-    }
     const unsigned long long area = (unsigned long long)n * n;
-    unsigned long long qt = sum / area, rem = sum % area;
-    if (2 * rem > area || (2 * rem == area && (qt & 1))) ++qt;
-    return (uint32_t)qt;
+    uint32_t prev_ma = 0xffffffffu, prev = 0;
+    for (int p = 0; p < n; ++p) {
+        const uint32_t ma = L.mask[a * n + p];
+        if (ma == prev_ma) {
+            out[p] = prev;
+            continue;
+        }
+        unsigned long long sum = 0;
+        int i = 0;
+        while (i < n) {
+            const uint32_t mu = L.mask[u * n + i];
+            int li = 1;
+            while (i + li < n && L.mask[u * n + i + li] == mu) ++li;
+            const uint32_t mau = ma & mu;
+            int j = 0;
+            while (j < n) {
+                const uint32_t mv = L.mask[v * n + j];
+                int lj = 1;
+                while (j + lj < n && L.mask[v * n + j + lj] == mv) ++lj;
+                sum += (unsigned long long)(li * lj) * L.codes[hb16(mau & mv)];
+                j += lj;
+            }
+            i += li;
+        }
+        unsigned long long qt = sum / area, rem = sum % area;
+        if (2 * rem > area || (2 * rem == area && (qt & 1))) ++qt;
+        prev_ma = ma;
+        prev = (uint32_t)qt;
+        out[p] = prev;
+    }
 }
 
 // -------------------------------------------------------------------------
@@ -396,10 +417,16 @@ __device__ int lookup_or_insert(const CacheDev& C, const uint32_t* kbuf, uint32_
     return LOOKUP_FULL;
 }
 
-// Table layout: [last positive index, Kh bits, CDF[nb], sign bits[ceil(nb/32)]].
+// Table layout: [last positive index, Kh bits, guide[257], CDF[nb],
+// sign bits[ceil(nb/32)]].  guide[g] = first b with CDF[b] > g * 2^24, so the
+// answer for a word u lies in [guide[u>>24], guide[(u>>24)+1]].
+constexpr uint32_t TAB_GUIDE = 2, TAB_CDF = 2 + 257;
+
 __device__ __forceinline__ int table_sample(const uint32_t* tab, uint32_t nb, uint32_t u) {
-    const uint32_t* cdf = tab + 2;
-    uint32_t lo = 0, hi = nb;  // first b with cdf[b] > u
+    const uint32_t* cdf = tab + TAB_CDF;
+    const uint32_t g = u >> 24;
+    uint32_t lo = tab[TAB_GUIDE + g], hi = tab[TAB_GUIDE + g + 1];
+    if (hi < nb) ++hi;  // first b with cdf[b] > u lies in [lo, hi)
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
         if (cdf[mid] > u)
@@ -463,10 +490,12 @@ __global__ void __launch_bounds__(FRW_THREADS) frw_walk_kernel(WalkArgs A) {
                 const uint32_t cnt = __popcll(bal);
                 const uint32_t rank = __popcll(bal & ((1ull << lane) - 1ull));
                 unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(&K.resume_next, (unsigned long long)cnt);
-                base = __shfl(base, leader);
+                if (A.n_resume) {
+                    if (lane == leader) base = atomicAdd(&K.resume_next, (unsigned long long)cnt);
+                    base = __shfl(base, leader);
+                }
                 bool got = false;
-                if (want && base + rank < A.n_resume) {
+                if (want && A.n_resume && base + rank < A.n_resume) {
                     const Parked P = A.resume[base + rank];
                     walk = P.walk;
                     pos = make_float3(P.px, P.py, P.pz);
@@ -564,23 +593,25 @@ __global__ void __launch_bounds__(FRW_THREADS) frw_walk_kernel(WalkArgs A) {
                         br = 3;
                         sax = a_norm;
                     }
-                    ++c_br[br];
                     kbuf[0] = 1u;  // first-transition table
                     kbuf[1] = (uint32_t)n;
                     kbuf[2] = (uint32_t)sax;
                     kbuf[3] = (uint32_t)a_norm;
-                    for (int p = 0; p < n; ++p)
-                        kbuf[KEY_HDR + p] = br == 3 ? plane_mean_code(L, n, a_norm, p) : plane_code(L, I, n, sax, p);
+                    if (br == 3)
+                        plane_mean_codes(L, n, a_norm, kbuf + KEY_HDR);
+                    else
+                        for (int p = 0; p < n; ++p) kbuf[KEY_HDR + p] = plane_code(L, I, n, sax, p);
                     uint32_t idx;
                     const int res = lookup_or_insert(A.cache, kbuf, &idx);
                     if (res != LOOKUP_HIT) {
                         if (res == LOOKUP_FULL) err |= ERR_TABLE_CAP;
                         park = true;
                     } else {
+                        ++c_br[br];
                         const uint32_t* tab = A.cache.data + (size_t)idx * A.cache.tab_words;
                         const Rand4 r = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_FIRST), A.k0, A.k1);
                         const int b = table_sample(tab, A.cache.nb, r.x);
-                        const uint32_t sb = (tab[2 + A.cache.nb + (b >> 5)] >> (b & 31)) & 1u;
+                        const uint32_t sb = (tab[TAB_CDF + A.cache.nb + (b >> 5)] >> (b & 31)) & 1u;
                         const float Kh = __uint_as_float(tab[1]);
                         float sgn = sb ? 1.f : -1.f;
                         if (!side) sgn = -sgn;
@@ -952,7 +983,7 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
             uint32_t bits = 0;
             for (int k = 0; k < 32 && q * 32 + k < nb; ++k)
                 if (Pout[3 * nb + q * 32 + k] > 0.0) bits |= 1u << k;
-            tab[2 + nb + q] = bits;
+            tab[TAB_CDF + nb + q] = bits;
         }
         if (threadIdx.x == 0) {
             double K = 0.0;
@@ -964,7 +995,7 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
                 cum += a;
                 if (a > 0.0) last = b;
                 const double cv = ceil(cum / K * 4294967296.0);
-                tab[2 + b] = cv >= 4294967295.0 ? 0xffffffffu : (uint32_t)cv;
+                tab[TAB_CDF + b] = cv >= 4294967295.0 ? 0xffffffffu : (uint32_t)cv;
             }
             tab[0] = (uint32_t)last;
             tab[1] = __float_as_uint((float)K);
@@ -979,7 +1010,7 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
                 cum += Pout[b];
                 if (Pout[b] > 0.0) last = b;
                 const double cv = ceil(cum / tot * 4294967296.0);
-                tab[2 + b] = cv >= 4294967295.0 ? 0xffffffffu : (uint32_t)cv;
+                tab[TAB_CDF + b] = cv >= 4294967295.0 ? 0xffffffffu : (uint32_t)cv;
             }
             tab[0] = (uint32_t)last;
             tab[1] = 0u;
@@ -987,6 +1018,12 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        uint32_t b = 0;
+        for (uint32_t g = 0; g <= 256; ++g) {
+            const unsigned long long thr = (unsigned long long)g << 24;
+            while (b < (uint32_t)nb && (unsigned long long)tab[TAB_CDF + b] <= thr) ++b;
+            tab[TAB_GUIDE + g] = b;
+        }
         __threadfence();
         C.ready[idx] = 1u;
     }
@@ -1013,6 +1050,7 @@ __global__ void __launch_bounds__(RED_THREADS) reduce_scores_kernel(const int32_
                                                                    int K, float4* __restrict__ partial) {
     __shared__ int32_t snet[RED_CHUNK];
     __shared__ float sw[RED_CHUNK];
+    __shared__ float4 part[RED_THREADS];
     const uint64_t base = (uint64_t)blockIdx.x * RED_CHUNK;
     const int len = (int)min((uint64_t)RED_CHUNK, count - base);
     for (int q = threadIdx.x; q < len; q += blockDim.x) {
@@ -1020,19 +1058,39 @@ __global__ void __launch_bounds__(RED_THREADS) reduce_scores_kernel(const int32_
         sw[q] = w[base + q];
     }
     __syncthreads();
-    for (int j0 = 0; j0 < K; j0 += blockDim.x) {
-        const int j = j0 + threadIdx.x;
-        float s1 = 0.f, c1 = 0.f, s2 = 0.f, c2 = 0.f;
-        if (j < K) {
-            for (int q = 0; q < len; ++q) {
+    // nets in groups of up to RED_THREADS; each net's entries are split into
+    // `parts` contiguous slices summed by different threads, then combined in
+    // slice order (deterministic)
+    for (int j0 = 0; j0 < K; j0 += RED_THREADS) {
+        const int kn = min(K - j0, RED_THREADS);
+        const int parts = RED_THREADS / kn;
+        const int t = threadIdx.x;
+        if (t < kn * parts) {
+            const int j = j0 + t / parts, pi = t % parts;
+            const int q0 = (int)((long long)len * pi / parts), q1 = (int)((long long)len * (pi + 1) / parts);
+            float s1 = 0.f, c1 = 0.f, s2 = 0.f, c2 = 0.f;
+            for (int q = q0; q < q1; ++q) {
                 if (snet[q] == j) {
                     const float x = sw[q];
                     neumaier(s1, c1, x);
                     neumaier(s2, c2, x * x);
                 }
             }
-            partial[(size_t)blockIdx.x * K + j] = make_float4(s1, c1, s2, c2);
+            part[t] = make_float4(s1, c1, s2, c2);
         }
+        __syncthreads();
+        if (t < kn) {
+            float s1 = 0.f, c1 = 0.f, s2 = 0.f, c2 = 0.f;
+            for (int pi = 0; pi < parts; ++pi) {
+                const float4 v = part[t * parts + pi];
+                neumaier(s1, c1, v.x);
+                neumaier(s1, c1, v.y);
+                neumaier(s2, c2, v.z);
+                neumaier(s2, c2, v.w);
+            }
+            partial[(size_t)blockIdx.x * K + j0 + t] = make_float4(s1, c1, s2, c2);
+        }
+        __syncthreads();
     }
 }
 
@@ -1261,7 +1319,7 @@ Cache& get_cache(int n) {
         c->d.capacity = cap;
         c->d.slot_mask = nslots - 1;
         c->d.key_words = KEY_HDR + n;
-        c->d.tab_words = 2 + nb + (nb + 31) / 32;
+        c->d.tab_words = TAB_CDF + nb + (nb + 31) / 32;
         const size_t b_hash = (size_t)nslots * 8, b_idx = (size_t)nslots * 4, b_ready = (size_t)cap * 4;
         const size_t b_keys = (size_t)cap * c->d.key_words * 4, b_data = (size_t)cap * c->d.tab_words * 4;
         const size_t b_misc = 256, b_pend = (size_t)cap * 4;
