@@ -97,13 +97,12 @@ struct Parked {
 
 struct Counters {
     unsigned long long hops, micro_steps, hop_class[3], first_branch[4], env, hop_cap;
-    uint32_t err, park_count;
+    uint32_t err, park_count, first_missing, pad;
     unsigned long long resume_next, walk_next;
 };
 
 struct WalkArgs {
     const StructDev* S;
-    const GaussDev* G;
     CacheDev cache;
     int32_t n, hybrid, master, pad;
     uint32_t k0, k1;
@@ -116,6 +115,21 @@ struct WalkArgs {
     float* score_w;
     Counters* ctr;
     uint32_t lane_stride;  // dwords of LDS per lane (odd)
+    const float4* first_state;  // per walk of the batch: exit point of the first transition, omega
+};
+
+// First transitions of a batch of walks (one lane per walk).
+struct FirstArgs {
+    const StructDev* S;
+    const GaussDev* G;
+    CacheDev cache;
+    int32_t n;
+    uint32_t k0, k1;
+    unsigned long long walk_begin, count;
+    float4* state;     // exit point (folded) and omega per walk
+    uint32_t* done;    // 1 once the walk's first transition is stored
+    Counters* ctr;
+    uint32_t lane_stride;
 };
 
 // -------------------------------------------------------------------------
@@ -450,14 +464,112 @@ __device__ __forceinline__ void node_of_hit(int n, int b, int node[3]) {
 }
 
 // -------------------------------------------------------------------------
-// Walker kernel.
+// First transitions (Alg. 1: GaussianSurfaceSampling + FirstTransition).
+// Every walk of a batch starts here, one lane per walk, so the per-walk work
+// (Gaussian-surface sample, first cube, homogenisation, weight) runs with
+// full lanes.  A walk whose first-cube table is missing is retried after the
+// table is built.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ float sel3(float3 v, int a) { return a == 0 ? v.x : (a == 1 ? v.y : v.z); }
+
+__global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
+    extern __shared__ uint32_t lds[];
+    const StructDev& S = *A.S;
+    const GaussDev& G = *A.G;
+    const int n = A.n;
+    uint32_t* my = lds + threadIdx.x * A.lane_stride;
+    LaneCube L{reinterpret_cast<uint16_t*>(my), my + ((3 * n + 1) / 2)};
+    uint32_t* kbuf = L.codes + MAX_REGIONS;
+    unsigned long long c_br[4] = {0, 0, 0, 0};
+    uint32_t err = 0, missing = 0;
+    for (unsigned long long k = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; k < A.count;
+         k += (unsigned long long)gridDim.x * blockDim.x) {
+        if (A.done[k]) continue;
+        const unsigned long long walk = A.walk_begin + k;
+        // GaussianSurfaceSampling(G): face by area, uniform point on it
+        const Rand4 r = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_GAUSS), A.k0, A.k1);
+        const float xa = ((float)r.x + 0.5f) * 2.3283064365386963e-10f * G.area;
+        int f = G.n_faces - 1;
+        for (int q = 0; q < G.n_faces - 1; ++q)
+            if (xa < G.cum[q]) {
+                f = q;
+                break;
+            }
+        const int a_norm = G.axis[f], side = G.side[f];
+        const int ta = a_norm == 0 ? 1 : 0, tb = a_norm == 2 ? 1 : 2;
+        const float ua = G.lo[f][ta] + ((float)r.y + 0.5f) * 2.3283064365386963e-10f * (G.hi[f][ta] - G.lo[f][ta]);
+        const float ub = G.lo[f][tb] + ((float)r.z + 0.5f) * 2.3283064365386963e-10f * (G.hi[f][tb] - G.lo[f][tb]);
+        const float pl = G.plane[f];
+        const float3 c = make_float3(a_norm == 0 ? pl : ua, a_norm == 1 ? pl : (a_norm == 0 ? ua : ub),
+                                     a_norm == 2 ? pl : ub);
+        const int cell = grid_cell(S, c);
+        int who;
+        const float R = fminf(query_dist(S, c, cell, &who), G.g);
+        // FirstTransition: cube touching the master (Sec. III-C, Fig. 4
+        // branches; homogenised along the normal when not stratified)
+        const CubeInfo I = build_cube(S, cell, c, R, n, L);
+        if (I.overflow) err |= ERR_REGIONS;
+        const float h = 2.f * R / (float)n;
+        int br, sax;
+        if (I.cls == 0) {
+            br = 0;
+            sax = a_norm;
+        } else if (stratified_along(I, a_norm)) {
+            br = 1;
+            sax = a_norm;
+        } else if (I.cls == 1) {
+            br = 2;
+            sax = I.axis;
+        } else {
+            br = 3;
+            sax = a_norm;
+        }
+        kbuf[0] = 1u;  // first-transition table
+        kbuf[1] = (uint32_t)n;
+        kbuf[2] = (uint32_t)sax;
+        kbuf[3] = (uint32_t)a_norm;
+        if (br == 3)
+            plane_mean_codes(L, n, a_norm, kbuf + KEY_HDR);
+        else
+            for (int p = 0; p < n; ++p) kbuf[KEY_HDR + p] = plane_code(L, I, n, sax, p);
+        uint32_t idx;
+        const int res = lookup_or_insert(A.cache, kbuf, &idx);
+        if (res != LOOKUP_HIT) {
+            if (res == LOOKUP_FULL) err |= ERR_TABLE_CAP;
+            ++missing;
+            continue;
+        }
+        ++c_br[br];
+        const uint32_t* tab = A.cache.data + (size_t)idx * A.cache.tab_words;
+        const Rand4 r2 = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_FIRST), A.k0, A.k1);
+        const int b = table_sample(tab, A.cache.nb, r2.x);
+        const uint32_t sb = (tab[TAB_CDF + A.cache.nb + (b >> 5)] >> (b & 31)) & 1u;
+        const float Kh = __uint_as_float(tab[1]);
+        float sgn = sb ? 1.f : -1.f;
+        if (!side) sgn = -sgn;
+        const float omega = EPS0 * G.area * (Kh / h) * sgn;
+        int nd[3];
+        node_of_hit(n, b, nd);
+        const float3 x = make_float3(c.x - R + (float)nd[0] * h, c.y - R + (float)nd[1] * h, c.z - R + (float)nd[2] * h);
+        const float3 xf = fold3(S, x);
+        A.state[k] = make_float4(xf.x, xf.y, xf.z, omega);
+        A.done[k] = 1u;
+    }
+    Counters& K = *A.ctr;
+    for (int q = 0; q < 4; ++q)
+        if (c_br[q]) atomicAdd(&K.first_branch[q], c_br[q]);
+    if (err) atomicOr(&K.err, err);
+    if (missing) atomicAdd(&K.first_missing, missing);
+}
+
+// -------------------------------------------------------------------------
+// Walker kernel: transitions after the first, until absorption.
 // -------------------------------------------------------------------------
 enum Phase : int { PH_IDLE = 0, PH_NEED = 1, PH_MW = 2, PH_EXHAUSTED = 3 };
 
 __global__ void __launch_bounds__(FRW_THREADS) frw_walk_kernel(WalkArgs A) {
     extern __shared__ uint32_t lds[];
     const StructDev& S = *A.S;
-    const GaussDev& G = *A.G;
     const int n = A.n;
     const int lane = threadIdx.x & 63;
     uint32_t* my = lds + threadIdx.x * A.lane_stride;
@@ -465,7 +577,7 @@ __global__ void __launch_bounds__(FRW_THREADS) frw_walk_kernel(WalkArgs A) {
     uint32_t* kbuf = L.codes + MAX_REGIONS;  // table key: KEY_HDR + n words
 
     Counters& K = *A.ctr;
-    unsigned long long c_hops = 0, c_steps = 0, c_cls[3] = {0, 0, 0}, c_br[4] = {0, 0, 0, 0}, c_env = 0, c_cap = 0;
+    unsigned long long c_hops = 0, c_steps = 0, c_cls[3] = {0, 0, 0}, c_env = 0, c_cap = 0;
     uint32_t err = 0;
 
     int phase = PH_IDLE;
@@ -516,9 +628,11 @@ __global__ void __launch_bounds__(FRW_THREADS) frw_walk_kernel(WalkArgs A) {
                     if (want2) {
                         const unsigned long long w = A.walk_begin + base2 + rank2;
                         if (w < A.walk_end) {
+                            const float4 f = A.first_state[base2 + rank2];
                             walk = w;
-                            t = 0;
-                            omega = 0.f;
+                            pos = make_float3(f.x, f.y, f.z);
+                            omega = f.w;
+                            t = 1;
                             phase = PH_NEED;
                         } else {
                             phase = PH_EXHAUSTED;
@@ -535,31 +649,9 @@ __global__ void __launch_bounds__(FRW_THREADS) frw_walk_kernel(WalkArgs A) {
             int net = S.n_nets;
             float3 c;
             float R;
-            int a_norm = 0, side = 1;
             float3 x;
             int cell;
-            if (t == 0) {
-                // GaussianSurfaceSampling(G): face by area, uniform point
-                const Rand4 r = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_GAUSS), A.k0, A.k1);
-                const float xa = ((float)r.x + 0.5f) * 2.3283064365386963e-10f * G.area;
-                int f = G.n_faces - 1;
-                for (int q = 0; q < G.n_faces - 1; ++q)
-                    if (xa < G.cum[q]) {
-                        f = q;
-                        break;
-                    }
-                a_norm = G.axis[f];
-                side = G.side[f];
-                const int ta = a_norm == 0 ? 1 : 0, tb = a_norm == 2 ? 1 : 2;
-                float cc[3];
-                cc[a_norm] = G.plane[f];
-                cc[ta] = G.lo[f][ta] + ((float)r.y + 0.5f) * 2.3283064365386963e-10f * (G.hi[f][ta] - G.lo[f][ta]);
-                cc[tb] = G.lo[f][tb] + ((float)r.z + 0.5f) * 2.3283064365386963e-10f * (G.hi[f][tb] - G.lo[f][tb]);
-                c = make_float3(cc[0], cc[1], cc[2]);
-                cell = grid_cell(S, c);
-                int who;
-                R = fminf(query_dist(S, c, cell, &who), G.g);
-            } else {
+            {
                 cell = grid_cell(S, pos);
                 R = query_dist(S, pos, cell, &net);
                 c = pos;
@@ -575,54 +667,7 @@ __global__ void __launch_bounds__(FRW_THREADS) frw_walk_kernel(WalkArgs A) {
                 const CubeInfo I = build_cube(S, cell, c, R, n, L);
                 if (I.overflow) err |= ERR_REGIONS;
                 const float h = 2.f * R / (float)n;
-                if (t == 0) {
-                    // first transition: cube touching the master (Sec. III-C,
-                    // Fig. 4 branches; homogenised along the normal when the
-                    // cube is not stratified)
-                    int br, sax;
-                    if (I.cls == 0) {
-                        br = 0;
-                        sax = a_norm;
-                    } else if (stratified_along(I, a_norm)) {
-                        br = 1;
-                        sax = a_norm;
-                    } else if (I.cls == 1) {
-                        br = 2;
-                        sax = I.axis;
-                    } else {
-                        br = 3;
-                        sax = a_norm;
-                    }
-                    kbuf[0] = 1u;  // first-transition table
-                    kbuf[1] = (uint32_t)n;
-                    kbuf[2] = (uint32_t)sax;
-                    kbuf[3] = (uint32_t)a_norm;
-                    if (br == 3)
-                        plane_mean_codes(L, n, a_norm, kbuf + KEY_HDR);
-                    else
-                        for (int p = 0; p < n; ++p) kbuf[KEY_HDR + p] = plane_code(L, I, n, sax, p);
-                    uint32_t idx;
-                    const int res = lookup_or_insert(A.cache, kbuf, &idx);
-                    if (res != LOOKUP_HIT) {
-                        if (res == LOOKUP_FULL) err |= ERR_TABLE_CAP;
-                        park = true;
-                    } else {
-                        ++c_br[br];
-                        const uint32_t* tab = A.cache.data + (size_t)idx * A.cache.tab_words;
-                        const Rand4 r = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_FIRST), A.k0, A.k1);
-                        const int b = table_sample(tab, A.cache.nb, r.x);
-                        const uint32_t sb = (tab[TAB_CDF + A.cache.nb + (b >> 5)] >> (b & 31)) & 1u;
-                        const float Kh = __uint_as_float(tab[1]);
-                        float sgn = sb ? 1.f : -1.f;
-                        if (!side) sgn = -sgn;
-                        omega = EPS0 * G.area * (Kh / h) * sgn;
-                        int nd[3];
-                        node_of_hit(n, b, nd);
-                        x = make_float3(c.x - R + (float)nd[0] * h, c.y - R + (float)nd[1] * h, c.z - R + (float)nd[2] * h);
-                        pos = fold3(S, x);
-                        t = 1;
-                    }
-                } else {
+                {
                     ++c_hops;
                     ++c_cls[I.cls];
                     if (A.hybrid && I.cls <= 1) {
@@ -784,7 +829,6 @@ __global__ void __launch_bounds__(FRW_THREADS) frw_walk_kernel(WalkArgs A) {
     c_hops = wsum(c_hops);
     c_steps = wsum(c_steps);
     for (int q = 0; q < 3; ++q) c_cls[q] = wsum(c_cls[q]);
-    for (int q = 0; q < 4; ++q) c_br[q] = wsum(c_br[q]);
     c_env = wsum(c_env);
     c_cap = wsum(c_cap);
     for (int off = 32; off > 0; off >>= 1) err |= __shfl_down(err, off);
@@ -793,8 +837,6 @@ __global__ void __launch_bounds__(FRW_THREADS) frw_walk_kernel(WalkArgs A) {
         if (c_steps) atomicAdd(&K.micro_steps, c_steps);
         for (int q = 0; q < 3; ++q)
             if (c_cls[q]) atomicAdd(&K.hop_class[q], c_cls[q]);
-        for (int q = 0; q < 4; ++q)
-            if (c_br[q]) atomicAdd(&K.first_branch[q], c_br[q]);
         if (c_env) atomicAdd(&K.env, c_env);
         if (c_cap) atomicAdd(&K.hop_cap, c_cap);
         if (err) atomicOr(&K.err, err);
@@ -1614,6 +1656,7 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         const size_t o_p0 = sz(sizeof(Parked) * (size_t)park_cap), o_p1 = sz(sizeof(Parked) * (size_t)park_cap);
         const size_t o_part = sz(sizeof(float4) * red_blocks * K);
         const size_t o_acc = sz(sizeof(double) * 2 * K), o_res = sz(sizeof(double) * 2 * K);
+        const size_t o_fs = sz(sizeof(float4) * batch), o_fd = sz(sizeof(uint32_t) * batch);
         const bool own_scores = !(score_net && score_w);
         const size_t o_sn = own_scores ? sz(4 * batch) : 0, o_sw = own_scores ? sz(4 * batch) : 0;
         B.mem = (char*)dev_alloc(o);
@@ -1627,6 +1670,8 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         B.partial = (float4*)(m + o_part);
         B.acc = (double*)(m + o_acc);
         B.result = (double*)(m + o_res);
+        float4* fstate = (float4*)(m + o_fs);
+        uint32_t* fdone = (uint32_t*)(m + o_fd);
         if (own_scores) {
             B.own_net = (int32_t*)(m + o_sn);
             B.own_w = (float*)(m + o_sw);
@@ -1640,9 +1685,43 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         MW_HIP(hipMemcpy(&gst, B.status, 4, hipMemcpyDeviceToHost));
         MW_REQUIRE(gst == 0, MW_EGEOM, "no valid Gaussian surface for net %d (status %d)", master, gst);
         MW_HIP(hipFuncSetAttribute((const void*)frw_walk_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        MW_HIP(hipFuncSetAttribute((const void*)first_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        uint64_t misses = 0;
+        // builds every table queued by the last launch (binary64 solves)
+        auto build_pending = [&]() {
+            uint32_t npend = 0;
+            MW_HIP(hipMemcpy(&npend, cache.d.n_pending, 4, hipMemcpyDeviceToHost));
+            if (!npend) return;
+            std::vector<uint32_t> list(npend);
+            MW_HIP(hipMemcpy(list.data(), cache.d.pending, 4ull * npend, hipMemcpyDeviceToHost));
+            std::vector<uint32_t> valid;
+            for (uint32_t v : list)
+                if (v < cache.d.capacity) valid.push_back(v);
+            const uint32_t M = n - 1;
+            const size_t stride = (size_t)3 * M * M * M + (size_t)4 * 6 * M * M + 64;
+            const uint32_t chunk = 512;
+            double* work = (double*)dev_alloc(sizeof(double) * stride * std::min<size_t>(chunk, valid.size()));
+            uint32_t* dlist = (uint32_t*)dev_alloc(4ull * valid.size());
+            struct G2 {
+                void *a, *b;
+                ~G2() {
+                    dev_free(a);
+                    dev_free(b);
+                }
+            } g2{work, dlist};
+            MW_HIP(hipMemcpy(dlist, valid.data(), 4ull * valid.size(), hipMemcpyHostToDevice));
+            for (size_t c0 = 0; c0 < valid.size(); c0 += chunk) {
+                BuildArgs Ba{cache.d, dlist + c0, (uint32_t)std::min<size_t>(chunk, valid.size() - c0), work, stride};
+                build_tables_kernel<<<Ba.count, TB_THREADS>>>(Ba);
+                MW_HIP(hipGetLastError());
+            }
+            MW_HIP(hipDeviceSynchronize());
+            MW_HIP(hipMemset(cache.d.n_pending, 0, 4));
+            misses += valid.size();
+        };
 
         Counters tot{};
-        uint64_t done = 0, launches = 0, misses = 0;
+        uint64_t done = 0, launches = 0;
         double walker_ms = 0.0;
         hipEvent_t ev0, ev1;
         MW_HIP(hipEventCreate(&ev0));
@@ -1662,12 +1741,39 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
             int32_t* snet = own_scores ? B.own_net : score_net + done;
             float* sw = own_scores ? B.own_w : score_w + done;
             MW_HIP(hipMemset(B.ctr, 0, sizeof(Counters)));
+            MW_HIP(hipMemset(fdone, 0, sizeof(uint32_t) * nb_walks));
+            for (int round = 0;; ++round) {
+                FirstArgs F{};
+                F.S = dS;
+                F.G = B.G;
+                F.cache = cache.d;
+                F.n = n;
+                F.k0 = (uint32_t)seed;
+                F.k1 = (uint32_t)(seed >> 32);
+                F.walk_begin = wb;
+                F.count = nb_walks;
+                F.state = fstate;
+                F.done = fdone;
+                F.ctr = B.ctr;
+                F.lane_stride = lane_stride;
+                MW_HIP(hipMemset(&B.ctr->first_missing, 0, 4));
+                const int fblocks = (int)std::min<uint64_t>((nb_walks + FRW_THREADS - 1) / FRW_THREADS, (uint64_t)blocks);
+                first_kernel<<<fblocks, FRW_THREADS, lds>>>(F);
+                MW_HIP(hipGetLastError());
+                Counters h{};
+                MW_HIP(hipMemcpy(&h, B.ctr, sizeof h, hipMemcpyDeviceToHost));
+                MW_REQUIRE(!(h.err & ERR_REGIONS), MW_ELIMIT,
+                           "a transition cube touched more than %d dielectric regions", MAX_REGIONS);
+                MW_REQUIRE(!(h.err & ERR_TABLE_CAP), MW_ELIMIT, "SGF table cache full (MWALK_TABLE_CAP)");
+                MW_REQUIRE(round < 1000, MW_ELIMIT, "first-transition retry limit reached");
+                build_pending();
+                if (h.first_missing == 0) break;
+            }
             uint32_t n_resume = 0;
             int cur = 0;
             for (;;) {
                 WalkArgs W{};
                 W.S = dS;
-                W.G = B.G;
                 W.cache = cache.d;
                 W.n = n;
                 W.hybrid = opt.hybrid;
@@ -1684,6 +1790,7 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
                 W.score_w = sw;
                 W.ctr = B.ctr;
                 W.lane_stride = lane_stride;
+                W.first_state = fstate;
                 // reset per-launch queue state, keep the walk counter
                 MW_HIP(hipMemset(&B.ctr->park_count, 0, 4));
                 MW_HIP(hipMemset(&B.ctr->resume_next, 0, 8));
@@ -1703,31 +1810,7 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
                 MW_REQUIRE(!(h.err & ERR_PARK_CAP), MW_ELIMIT, "parked-walk queue overflow");
                 MW_REQUIRE(!(h.err & ERR_STEP_CAP), MW_ELIMIT, "a micro-walk exceeded %u steps", MW_STEP_CAP);
                 MW_REQUIRE(launches < 100000, MW_ELIMIT, "walker relaunch limit reached");
-                uint32_t npend = 0;
-                MW_HIP(hipMemcpy(&npend, cache.d.n_pending, 4, hipMemcpyDeviceToHost));
-                if (npend) {
-                    std::vector<uint32_t> list(npend);
-                    MW_HIP(hipMemcpy(list.data(), cache.d.pending, 4ull * npend, hipMemcpyDeviceToHost));
-                    std::vector<uint32_t> valid;
-                    for (uint32_t v : list)
-                        if (v < cache.d.capacity) valid.push_back(v);
-                    const uint32_t M = n - 1;
-                    const size_t stride = (size_t)3 * M * M * M + (size_t)4 * 6 * M * M + 64;
-                    const uint32_t chunk = 512;
-                    double* work = (double*)dev_alloc(sizeof(double) * stride * std::min<size_t>(chunk, valid.size()));
-                    uint32_t* dlist = (uint32_t*)dev_alloc(4ull * valid.size());
-                    MW_HIP(hipMemcpy(dlist, valid.data(), 4ull * valid.size(), hipMemcpyHostToDevice));
-                    for (size_t c0 = 0; c0 < valid.size(); c0 += chunk) {
-                        BuildArgs Ba{cache.d, dlist + c0, (uint32_t)std::min<size_t>(chunk, valid.size() - c0), work, stride};
-                        build_tables_kernel<<<Ba.count, TB_THREADS>>>(Ba);
-                        MW_HIP(hipGetLastError());
-                    }
-                    MW_HIP(hipDeviceSynchronize());
-                    dev_free(work);
-                    dev_free(dlist);
-                    MW_HIP(hipMemset(cache.d.n_pending, 0, 4));
-                    misses += valid.size();
-                }
+                build_pending();
                 n_resume = std::min(h.park_count, park_cap);
                 cur ^= 1;
                 if (n_resume == 0 && h.walk_next >= nb_walks) {
