@@ -38,7 +38,8 @@ namespace {
 constexpr float EPS0 = 8.8541878128e-3f;  // vacuum permittivity, fF/um
 constexpr uint32_t HOP_CAP = 100000;
 constexpr int MAX_REGIONS = MW_MAX_REGIONS;
-constexpr int FRW_THREADS = 256;
+constexpr int FRW_THREADS = 256;   // first-transition kernel
+constexpr int WALK_THREADS = 192;  // walker kernel: 5 blocks of 3 waves fit one CU's LDS
 constexpr uint32_t KEY_HDR = 4;
 constexpr uint32_t NO_INDEX = 0xffffffffu;
 
@@ -77,8 +78,7 @@ struct GaussDev {
 
 // Table cache for one lattice size.
 struct CacheDev {
-    unsigned long long* slot_hash;
-    uint32_t* slot_index;
+    unsigned long long* slot;  // (hash32 << 32) | table index; 0 = empty
     uint32_t* ready;
     uint32_t* keys;
     uint32_t* data;
@@ -116,6 +116,7 @@ struct WalkArgs {
     Counters* ctr;
     uint32_t lane_stride;  // dwords of LDS per lane (odd)
     const float4* first_state;  // per walk of the batch: exit point of the first transition, omega
+    uint32_t uniform_index;     // table of the uniform cube
 };
 
 // First transitions of a batch of walks (one lane per walk).
@@ -380,48 +381,50 @@ __device__ void plane_mean_codes(LaneCube L, int n, int a, uint32_t* out) {
 // -------------------------------------------------------------------------
 // Table cache.
 // -------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long key_hash(const uint32_t* key, uint32_t words) {
-    unsigned long long h = 0xcbf29ce484222325ull;
-    for (uint32_t q = 0; q < words; ++q) {
-        h ^= key[q];
-        h *= 0x100000001b3ull;
-        h ^= h >> 29;
-    }
-    return h | 1ull;
-}
-
 enum LookupResult { LOOKUP_HIT = 0, LOOKUP_PARK = 1, LOOKUP_FULL = 2 };
+constexpr unsigned long long SLOT_HASH_MASK = 0xffffffff00000000ull;
 
-// key: KEY_HDR + n words at kbuf.  Returns the table index on a hit.
-__device__ int lookup_or_insert(const CacheDev& C, const uint32_t* kbuf, uint32_t* out_index) {
+// Finds the table of a key (words produced by key(q), q < key_words) or
+// queues it for building.  Slot words pack a 32-bit key hash with the table
+// index; the full key is compared before a hit is reported.
+template <class KeyF>
+__device__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t* out_index) {
     const uint32_t words = C.key_words;
-    const unsigned long long h = key_hash(kbuf, words);
-    uint32_t slot = (uint32_t)h & C.slot_mask;
+    uint32_t h = 0x811c9dc5u;
+    for (uint32_t q = 0; q < words; ++q) {
+        h ^= key(q);
+        h *= 0x01000193u;
+        h ^= h >> 15;
+    }
+    if (h == 0u) h = 1u;
+    const unsigned long long hh = (unsigned long long)h << 32;
+    uint32_t slot = (h * 0x9E3779B1u) & C.slot_mask;
     for (uint32_t probe = 0; probe <= C.slot_mask; ++probe) {
-        unsigned long long cur = __hip_atomic_load(&C.slot_hash[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long cur = __hip_atomic_load(&C.slot[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cur == 0ull) {
-            const unsigned long long old = atomicCAS(&C.slot_hash[slot], 0ull, h);
+            const unsigned long long old = atomicCAS(&C.slot[slot], 0ull, hh | NO_INDEX);
             if (old == 0ull) {
                 const uint32_t idx = atomicAdd(C.n_tables, 1u);
                 if (idx >= C.capacity) return LOOKUP_FULL;
                 uint32_t* dst = C.keys + (size_t)idx * words;
-                for (uint32_t q = 0; q < words; ++q) dst[q] = kbuf[q];
+                for (uint32_t q = 0; q < words; ++q) dst[q] = key(q);
                 __threadfence();
-                __hip_atomic_store(&C.slot_index[slot], idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&C.slot[slot], hh | idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t pos = atomicAdd(C.n_pending, 1u);
                 C.pending[pos] = idx;
                 return LOOKUP_PARK;
             }
             cur = old;
         }
-        if (cur == h) {
-            const uint32_t idx = __hip_atomic_load(&C.slot_index[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((cur & SLOT_HASH_MASK) == hh) {
+            const uint32_t idx = (uint32_t)cur;
             if (idx == NO_INDEX) return LOOKUP_PARK;
-            if (__hip_atomic_load(&C.ready[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) return LOOKUP_PARK;
+            const uint32_t rdy = __hip_atomic_load(&C.ready[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t* k = C.keys + (size_t)idx * words;
             bool same = true;
-            for (uint32_t q = 0; q < words; ++q) same &= k[q] == kbuf[q];
+            for (uint32_t q = 0; q < words; ++q) same &= k[q] == key(q);
             if (same) {
+                if (!rdy) return LOOKUP_PARK;
                 *out_index = idx;
                 return LOOKUP_HIT;
             }
@@ -461,6 +464,17 @@ __device__ __forceinline__ void node_of_hit(int n, int b, int node[3]) {
     node[ax] = side ? n : 0;
     node[o0] = aa;
     node[o1] = bb;
+}
+
+// Looks up (or queues) the hop table of the uniform cube; out[0] = status,
+// out[1] = table index.
+__global__ void uniform_table_kernel(CacheDev C, int n, uint32_t* out) {
+    if (threadIdx.x || blockIdx.x) return;
+    uint32_t idx = NO_INDEX;
+    const int res = lookup_or_insert(
+        C, [&](uint32_t q) { return q == 1 ? (uint32_t)n : (q == 2 ? 2u : (q < KEY_HDR ? 0u : 1u)); }, &idx);
+    out[0] = (uint32_t)res;
+    out[1] = idx;
 }
 
 // -------------------------------------------------------------------------
@@ -533,7 +547,7 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         else
             for (int p = 0; p < n; ++p) kbuf[KEY_HDR + p] = plane_code(L, I, n, sax, p);
         uint32_t idx;
-        const int res = lookup_or_insert(A.cache, kbuf, &idx);
+        const int res = lookup_or_insert(A.cache, [&](uint32_t q) { return kbuf[q]; }, &idx);
         if (res != LOOKUP_HIT) {
             if (res == LOOKUP_FULL) err |= ERR_TABLE_CAP;
             ++missing;
@@ -567,14 +581,13 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
 // -------------------------------------------------------------------------
 enum Phase : int { PH_IDLE = 0, PH_NEED = 1, PH_MW = 2, PH_EXHAUSTED = 3 };
 
-__global__ void __launch_bounds__(FRW_THREADS) frw_walk_kernel(WalkArgs A) {
+__global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     extern __shared__ uint32_t lds[];
     const StructDev& S = *A.S;
     const int n = A.n;
     const int lane = threadIdx.x & 63;
     uint32_t* my = lds + threadIdx.x * A.lane_stride;
     LaneCube L{reinterpret_cast<uint16_t*>(my), my + ((3 * n + 1) / 2)};
-    uint32_t* kbuf = L.codes + MAX_REGIONS;  // table key: KEY_HDR + n words
 
     Counters& K = *A.ctr;
     unsigned long long c_hops = 0, c_steps = 0, c_cls[3] = {0, 0, 0}, c_env = 0, c_cap = 0;
@@ -672,13 +685,19 @@ __global__ void __launch_bounds__(FRW_THREADS) frw_walk_kernel(WalkArgs A) {
                     ++c_cls[I.cls];
                     if (A.hybrid && I.cls <= 1) {
                         const int sax = I.axis;
-                        kbuf[0] = 0u;  // hop table (centre source)
-                        kbuf[1] = (uint32_t)n;
-                        kbuf[2] = (uint32_t)sax;
-                        kbuf[3] = 0u;
-                        for (int p = 0; p < n; ++p) kbuf[KEY_HDR + p] = I.cls == 0 ? 1u : plane_code(L, I, n, sax, p);
-                        uint32_t idx;
-                        const int res = lookup_or_insert(A.cache, kbuf, &idx);
+                        // hop table key: (0, n, axis, 0, plane codes); every
+                        // uniform cube shares one table
+                        uint32_t idx = A.uniform_index;
+                        int res = LOOKUP_HIT;
+                        if (I.cls != 0)
+                            res = lookup_or_insert(
+                                A.cache,
+                                [&](uint32_t q) {
+                                    return q == 1 ? (uint32_t)n
+                                                  : (q == 2 ? (uint32_t)sax
+                                                            : (q < KEY_HDR ? 0u : plane_code(L, I, n, sax, (int)q - KEY_HDR)));
+                                },
+                                &idx);
                         if (res != LOOKUP_HIT) {
                             if (res == LOOKUP_FULL) err |= ERR_TABLE_CAP;
                             park = true;
@@ -1362,10 +1381,10 @@ Cache& get_cache(int n) {
         c->d.slot_mask = nslots - 1;
         c->d.key_words = KEY_HDR + n;
         c->d.tab_words = TAB_CDF + nb + (nb + 31) / 32;
-        const size_t b_hash = (size_t)nslots * 8, b_idx = (size_t)nslots * 4, b_ready = (size_t)cap * 4;
+        const size_t b_hash = (size_t)nslots * 8, b_ready = (size_t)cap * 4;
         const size_t b_keys = (size_t)cap * c->d.key_words * 4, b_data = (size_t)cap * c->d.tab_words * 4;
         const size_t b_misc = 256, b_pend = (size_t)cap * 4;
-        const size_t total = b_hash + b_idx + b_ready + b_keys + b_data + b_misc + b_pend + 1024;
+        const size_t total = b_hash + b_ready + b_keys + b_data + b_misc + b_pend + 2048;
         char* m = (char*)dev_alloc(total);
         c->mem = m;
         size_t o = 0;
@@ -1374,8 +1393,7 @@ Cache& get_cache(int n) {
             o += (b + 255) / 256 * 256;
             return p;
         };
-        c->d.slot_hash = (unsigned long long*)take(b_hash);
-        c->d.slot_index = (uint32_t*)take(b_idx);
+        c->d.slot = (unsigned long long*)take(b_hash);
         c->d.ready = (uint32_t*)take(b_ready);
         c->d.keys = (uint32_t*)take(b_keys);
         c->d.data = (uint32_t*)take(b_data);
@@ -1383,8 +1401,7 @@ Cache& get_cache(int n) {
         c->d.n_tables = misc;
         c->d.n_pending = misc + 1;
         c->d.pending = (uint32_t*)take(b_pend);
-        MW_HIP(hipMemset(c->d.slot_hash, 0, b_hash));
-        MW_HIP(hipMemset(c->d.slot_index, 0xff, b_idx));
+        MW_HIP(hipMemset(c->d.slot, 0, b_hash));
         MW_HIP(hipMemset(c->d.ready, 0, b_ready));
         MW_HIP(hipMemset(misc, 0, b_misc));
         MW_HIP(hipDeviceSynchronize());
@@ -1634,12 +1651,16 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         }
         int cus = 0;
         MW_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        uint32_t lane_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * (KEY_HDR + n) + 3) / 4);
-        lane_stride |= 1u;
-        const size_t lds = (size_t)lane_stride * 4 * FRW_THREADS;
+        // LDS per lane: axis masks + region codes (+ a key buffer for first
+        // transitions); odd dword strides spread lanes over the banks
+        uint32_t lane_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 3) / 4) | 1u;
+        uint32_t first_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * (KEY_HDR + n) + 3) / 4) | 1u;
+        const size_t lds = (size_t)lane_stride * 4 * WALK_THREADS;
+        const size_t first_lds = (size_t)first_stride * 4 * FRW_THREADS;
         const int per_cu = std::max(1, std::min(8, (int)(163840 / (lds + 512))));
         const int blocks = cus * per_cu;
-        const uint64_t pool = (uint64_t)blocks * FRW_THREADS;
+        const int first_per_cu = std::max(1, std::min(8, (int)(163840 / (first_lds + 512))));
+        const uint64_t pool = (uint64_t)blocks * WALK_THREADS;
         uint64_t batch = opt.batch_walks ? opt.batch_walks : std::max<uint64_t>(pool * 8, 1 << 20);
         if (opt.target_rel_3sigma <= 0) batch = walk_budget;  // fixed budget: one pass
         batch = std::min<uint64_t>(batch, walk_budget);
@@ -1685,7 +1706,7 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         MW_HIP(hipMemcpy(&gst, B.status, 4, hipMemcpyDeviceToHost));
         MW_REQUIRE(gst == 0, MW_EGEOM, "no valid Gaussian surface for net %d (status %d)", master, gst);
         MW_HIP(hipFuncSetAttribute((const void*)frw_walk_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        MW_HIP(hipFuncSetAttribute((const void*)first_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        MW_HIP(hipFuncSetAttribute((const void*)first_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)first_lds));
         uint64_t misses = 0;
         // builds every table queued by the last launch (binary64 solves)
         auto build_pending = [&]() {
@@ -1720,6 +1741,18 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
             misses += valid.size();
         };
 
+        // the uniform cube's hop table is used without a hash lookup
+        uint32_t uniform_index = NO_INDEX;
+        for (int it = 0; it < 3 && uniform_index == NO_INDEX; ++it) {
+            uniform_table_kernel<<<1, 1>>>(cache.d, n, (uint32_t*)B.status);
+            MW_HIP(hipGetLastError());
+            uint32_t res[2];
+            MW_HIP(hipMemcpy(res, B.status, 8, hipMemcpyDeviceToHost));
+            if (res[0] == LOOKUP_HIT) uniform_index = res[1];
+            else if (res[0] == LOOKUP_FULL) MW_REQUIRE(false, MW_ELIMIT, "SGF table cache full (MWALK_TABLE_CAP)");
+            else build_pending();
+        }
+        MW_REQUIRE(uniform_index != NO_INDEX, MW_EDEVICE, "uniform SGF table could not be built");
         Counters tot{};
         uint64_t done = 0, launches = 0;
         double walker_ms = 0.0;
@@ -1755,10 +1788,11 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
                 F.state = fstate;
                 F.done = fdone;
                 F.ctr = B.ctr;
-                F.lane_stride = lane_stride;
+                F.lane_stride = first_stride;
                 MW_HIP(hipMemset(&B.ctr->first_missing, 0, 4));
-                const int fblocks = (int)std::min<uint64_t>((nb_walks + FRW_THREADS - 1) / FRW_THREADS, (uint64_t)blocks);
-                first_kernel<<<fblocks, FRW_THREADS, lds>>>(F);
+                const int fblocks = (int)std::min<uint64_t>((nb_walks + FRW_THREADS - 1) / FRW_THREADS,
+                                                            (uint64_t)cus * first_per_cu);
+                first_kernel<<<fblocks, FRW_THREADS, first_lds>>>(F);
                 MW_HIP(hipGetLastError());
                 Counters h{};
                 MW_HIP(hipMemcpy(&h, B.ctr, sizeof h, hipMemcpyDeviceToHost));
@@ -1791,11 +1825,12 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
                 W.ctr = B.ctr;
                 W.lane_stride = lane_stride;
                 W.first_state = fstate;
+                W.uniform_index = uniform_index;
                 // reset per-launch queue state, keep the walk counter
                 MW_HIP(hipMemset(&B.ctr->park_count, 0, 4));
                 MW_HIP(hipMemset(&B.ctr->resume_next, 0, 8));
                 MW_HIP(hipEventRecord(ev0, 0));
-                frw_walk_kernel<<<blocks, FRW_THREADS, lds>>>(W);
+                frw_walk_kernel<<<blocks, WALK_THREADS, lds>>>(W);
                 MW_HIP(hipGetLastError());
                 MW_HIP(hipEventRecord(ev1, 0));
                 ++launches;
