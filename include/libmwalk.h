@@ -228,6 +228,48 @@ mw_status frw_extract(mw_structure* s, int32_t master, uint64_t walk_budget,
                       double* cap_row, double* stderr_row, frw_stats* stats,
                       int32_t* score_net, float* score_w);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over one device with continuous batching.
+ *
+ * mw_server_submit copies the structure description and returns a ticket.
+ * A worker thread admits queued requests while their device footprint
+ * (structure, grid index, per-round walk buffers, accumulators) fits within
+ * hbm_budget_bytes, and runs rounds: each round gives every admitted request
+ * a share of walks (its next walk ids, from 0) and runs all shares in one
+ * set of kernel launches, so requests that arrive while others run join at
+ * the next round and their work overlaps on the device.  A request completes
+ * when walk_budget walks have run or options->target_rel_3sigma is met
+ * (checked after each of its rounds).  Per-walk results are those of
+ * frw_extract(structure, master, walk_budget, seed, options) run alone; rows
+ * agree with it to fp32 summation order (1e-6 relative).
+ * MW_ELIMIT at poll time if a request's footprint alone exceeds the budget;
+ * MW_EBUSY from submit when the queue holds max_queue requests.            */
+typedef struct mw_server mw_server;
+
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t rounds, walks;
+    uint64_t resident_bytes;      /* current admitted footprint               */
+    uint64_t max_resident_bytes;  /* peak admitted footprint (<= budget)      */
+    uint64_t max_concurrent;      /* peak number of requests in one round     */
+} mw_server_stats;
+
+mw_status mw_server_create(size_t hbm_budget_bytes, const frw_options* options,
+                           mw_server** out);
+mw_status mw_server_submit(mw_server* srv, const mw_structure_desc* desc,
+                           int32_t master, uint64_t walk_budget, uint64_t seed,
+                           uint64_t* ticket);
+/* MW_ENOTREADY until the request has finished; then cap_row/stderr_row
+ * (n_nets+1 entries of the request's structure) and, if non-NULL, stats and
+ * latency_s (completion minus submission, seconds) are written.  A failed
+ * request returns its error code. */
+mw_status mw_server_poll(mw_server* srv, uint64_t ticket, double* cap_row,
+                         double* stderr_row, frw_stats* stats, double* latency_s);
+mw_status mw_server_get_stats(mw_server* srv, mw_server_stats* out);
+/* Stops admitting, finishes the running requests, fails the queued ones,
+ * joins the worker and frees the server. */
+mw_status mw_server_destroy(mw_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

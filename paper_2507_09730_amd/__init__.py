@@ -261,5 +261,108 @@ def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
 
 
 
+# ---------------------------------------------------------------------------
+# Serving (continuous batching)
+# ---------------------------------------------------------------------------
+class mw_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "failed", "rounds", "walks",
+                                                "resident_bytes", "max_resident_bytes",
+                                                "max_concurrent")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib.mw_server_create.argtypes = [ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]
+_lib.mw_server_submit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64,
+                                  ctypes.c_uint64, ctypes.c_void_p]
+_lib.mw_server_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_void_p, ctypes.c_void_p]
+_lib.mw_server_get_stats.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+_lib.mw_server_destroy.argtypes = [ctypes.c_void_p]
+
+
+class Server:
+    """Request loop over the device (mw_server_*): submit structures, poll rows."""
+
+    def __init__(self, hbm_budget_bytes, n_cells=16, hybrid=1, target_rel_3sigma=0.0,
+                 abs_tol_rel=1e-6):
+        opt = frw_options(n_cells, hybrid, 0, 0, target_rel_3sigma, abs_tol_rel, 0, 0)
+        h = ctypes.c_void_p()
+        _check(_lib.mw_server_create(ctypes.c_size_t(int(hbm_budget_bytes)), ctypes.byref(opt),
+                                     ctypes.byref(h)))
+        self.handle = h
+        self._nets = {}
+
+    def submit(self, st, master, walk_budget, seed=0):
+        desc, keep = make_desc(st)
+        t = ctypes.c_uint64()
+        _check(_lib.mw_server_submit(self.handle, ctypes.byref(desc), master, walk_budget, seed,
+                                     ctypes.byref(t)))
+        self._nets[t.value] = int(st.n_nets)
+        return t.value
+
+    def poll(self, ticket):
+        """None while running; else dict(row, se, latency, walks)."""
+        K = self._nets[ticket] + 1
+        row = (ctypes.c_double * K)()
+        se = (ctypes.c_double * K)()
+        stats = frw_stats()
+        lat = ctypes.c_double()
+        rc = _lib.mw_server_poll(self.handle, ticket, row, se, ctypes.byref(stats), ctypes.byref(lat))
+        if rc == MW_ENOTREADY:
+            return None
+        _check(rc)
+        return {"row": np.array(row[:]), "se": np.array(se[:]), "latency": lat.value,
+                "walks": stats.walks}
+
+    def wait(self, ticket, timeout=600.0, interval=0.0005):
+        import time
+        t0 = time.time()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.time() - t0 > timeout:
+                raise TimeoutError("request %d not done" % ticket)
+            time.sleep(interval)
+
+    def stats(self):
+        s = mw_server_stats()
+        _check(_lib.mw_server_get_stats(self.handle, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if self.handle:
+            _check(_lib.mw_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mw_server_create(hbm_budget_bytes, **options):
+    return Server(hbm_budget_bytes, **options)
+
+
+def mw_server_submit(server, st, master, walk_budget, seed=0):
+    return server.submit(st, master, walk_budget, seed)
+
+
+def mw_server_poll(server, ticket):
+    return server.poll(ticket)
+
+
+def mw_server_get_stats(server):
+    return server.stats()
+
+
+def mw_server_destroy(server):
+    server.close()
+
+
 EXPORTS = ("mw_last_error", "mw_init", "mw_transition", "mw_transition_batch",
            "mw_structure_create", "mw_structure_destroy", "frw_extract")

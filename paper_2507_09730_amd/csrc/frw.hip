@@ -92,7 +92,8 @@ struct Parked {
     unsigned long long walk;
     float px, py, pz, omega;
     uint32_t t;
-    uint32_t pad[3];
+    int32_t seg;
+    uint32_t pad[2];
 };
 
 struct Counters {
@@ -101,34 +102,57 @@ struct Counters {
     unsigned long long resume_next, walk_next;
 };
 
-struct WalkArgs {
+// A contiguous range of walks of one extraction request.  One launch of the
+// first-transition or walker kernel serves a list of segments (one for
+// frw_extract, several requests for the server); the walks of the list are
+// numbered 0..total-1 in segment order.
+struct Segment {
     const StructDev* S;
+    const GaussDev* G;
+    unsigned long long walk_begin;  // walk id of the segment's first walk
+    unsigned long long offset;      // list index of the segment's first walk
+    unsigned long long count;
+    int32_t* score_net;             // indexed by walk - walk_begin
+    float* score_w;
+    float4* first_state;
+    uint32_t* first_done;
+    uint32_t k0, k1;                // Philox key (seed)
+};
+
+__device__ __forceinline__ int find_segment(const Segment* segs, int n_segs, unsigned long long g) {
+    int lo = 0, hi = n_segs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].offset <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+struct WalkArgs {
+    const Segment* segs;
+    int32_t n_segs, pad0;
+    unsigned long long total;
     CacheDev cache;
-    int32_t n, hybrid, master, pad;
-    uint32_t k0, k1;
-    unsigned long long walk_begin, walk_end;
+    int32_t n, hybrid;
     const Parked* resume;
     uint32_t n_resume;
     Parked* park_out;
     uint32_t park_cap;
-    int32_t* score_net;
-    float* score_w;
     Counters* ctr;
-    uint32_t lane_stride;  // dwords of LDS per lane (odd)
-    const float4* first_state;  // per walk of the batch: exit point of the first transition, omega
-    uint32_t uniform_index;     // table of the uniform cube
+    uint32_t lane_stride;   // dwords of LDS per lane (odd)
+    uint32_t uniform_index; // table of the uniform cube
 };
 
 // First transitions of a batch of walks (one lane per walk).
 struct FirstArgs {
-    const StructDev* S;
-    const GaussDev* G;
+    const Segment* segs;
+    int32_t n_segs, pad0;
+    unsigned long long total;
     CacheDev cache;
     int32_t n;
-    uint32_t k0, k1;
-    unsigned long long walk_begin, count;
-    float4* state;     // exit point (folded) and omega per walk
-    uint32_t* done;    // 1 once the walk's first transition is stored
     Counters* ctr;
     uint32_t lane_stride;
 };
@@ -488,20 +512,22 @@ __device__ __forceinline__ float sel3(float3 v, int a) { return a == 0 ? v.x : (
 
 __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
     extern __shared__ uint32_t lds[];
-    const StructDev& S = *A.S;
-    const GaussDev& G = *A.G;
     const int n = A.n;
     uint32_t* my = lds + threadIdx.x * A.lane_stride;
     LaneCube L{reinterpret_cast<uint16_t*>(my), my + ((3 * n + 1) / 2)};
     uint32_t* kbuf = L.codes + MAX_REGIONS;
     unsigned long long c_br[4] = {0, 0, 0, 0};
     uint32_t err = 0, missing = 0;
-    for (unsigned long long k = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; k < A.count;
-         k += (unsigned long long)gridDim.x * blockDim.x) {
-        if (A.done[k]) continue;
-        const unsigned long long walk = A.walk_begin + k;
+    for (unsigned long long g = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; g < A.total;
+         g += (unsigned long long)gridDim.x * blockDim.x) {
+        const Segment& SG = A.segs[find_segment(A.segs, A.n_segs, g)];
+        const unsigned long long k = g - SG.offset;
+        if (SG.first_done[k]) continue;
+        const StructDev& S = *SG.S;
+        const GaussDev& G = *SG.G;
+        const unsigned long long walk = SG.walk_begin + k;
         // GaussianSurfaceSampling(G): face by area, uniform point on it
-        const Rand4 r = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_GAUSS), A.k0, A.k1);
+        const Rand4 r = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_GAUSS), SG.k0, SG.k1);
         const float xa = ((float)r.x + 0.5f) * 2.3283064365386963e-10f * G.area;
         int f = G.n_faces - 1;
         for (int q = 0; q < G.n_faces - 1; ++q)
@@ -555,7 +581,7 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         }
         ++c_br[br];
         const uint32_t* tab = A.cache.data + (size_t)idx * A.cache.tab_words;
-        const Rand4 r2 = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_FIRST), A.k0, A.k1);
+        const Rand4 r2 = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_FIRST), SG.k0, SG.k1);
         const int b = table_sample(tab, A.cache.nb, r2.x);
         const uint32_t sb = (tab[TAB_CDF + A.cache.nb + (b >> 5)] >> (b & 31)) & 1u;
         const float Kh = __uint_as_float(tab[1]);
@@ -566,8 +592,8 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         node_of_hit(n, b, nd);
         const float3 x = make_float3(c.x - R + (float)nd[0] * h, c.y - R + (float)nd[1] * h, c.z - R + (float)nd[2] * h);
         const float3 xf = fold3(S, x);
-        A.state[k] = make_float4(xf.x, xf.y, xf.z, omega);
-        A.done[k] = 1u;
+        SG.first_state[k] = make_float4(xf.x, xf.y, xf.z, omega);
+        SG.first_done[k] = 1u;
     }
     Counters& K = *A.ctr;
     for (int q = 0; q < 4; ++q)
@@ -581,9 +607,9 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
 // -------------------------------------------------------------------------
 enum Phase : int { PH_IDLE = 0, PH_NEED = 1, PH_MW = 2, PH_EXHAUSTED = 3 };
 
+template <bool MULTI>
 __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     extern __shared__ uint32_t lds[];
-    const StructDev& S = *A.S;
     const int n = A.n;
     const int lane = threadIdx.x & 63;
     uint32_t* my = lds + threadIdx.x * A.lane_stride;
@@ -594,6 +620,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     uint32_t err = 0;
 
     int phase = PH_IDLE;
+    int sg = 0;  // segment of the lane's walk (always 0 for one segment)
     unsigned long long walk = 0;
     float3 pos = make_float3(0.f, 0.f, 0.f);
     float omega = 0.f;
@@ -622,6 +649,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                 bool got = false;
                 if (want && A.n_resume && base + rank < A.n_resume) {
                     const Parked P = A.resume[base + rank];
+                    if (MULTI) sg = P.seg;
                     walk = P.walk;
                     pos = make_float3(P.px, P.py, P.pz);
                     omega = P.omega;
@@ -639,10 +667,13 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                     if (lane == leader2) base2 = atomicAdd(&K.walk_next, (unsigned long long)cnt2);
                     base2 = __shfl(base2, leader2);
                     if (want2) {
-                        const unsigned long long w = A.walk_begin + base2 + rank2;
-                        if (w < A.walk_end) {
-                            const float4 f = A.first_state[base2 + rank2];
-                            walk = w;
+                        const unsigned long long gi = base2 + rank2;
+                        if (gi < A.total) {
+                            if (MULTI) sg = find_segment(A.segs, A.n_segs, gi);
+                            const Segment& SG = A.segs[sg];
+                            const unsigned long long k = gi - SG.offset;
+                            const float4 f = SG.first_state[k];
+                            walk = SG.walk_begin + k;
                             pos = make_float3(f.x, f.y, f.z);
                             omega = f.w;
                             t = 1;
@@ -658,6 +689,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
 
         // ---- one transition for lanes that need one ----
         if (phase == PH_NEED) {
+            const Segment& SG = A.segs[sg];
+            const StructDev& S = *SG.S;
             bool park = false, done = false;
             int net = S.n_nets;
             float3 c;
@@ -705,7 +738,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             --c_cls[I.cls];
                         } else {
                             const uint32_t* tab = A.cache.data + (size_t)idx * A.cache.tab_words;
-                            const Rand4 r = philox10(0u, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_TABLE), A.k0, A.k1);
+                            const Rand4 r = philox10(0u, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_TABLE), SG.k0, SG.k1);
                             const int b = table_sample(tab, A.cache.nb, r.x);
                             int nd[3];
                             node_of_hit(n, b, nd);
@@ -731,10 +764,10 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                 }
             }
             if (done) {
-                const unsigned long long k = walk - A.walk_begin;
+                const unsigned long long k = walk - SG.walk_begin;
                 if (net == S.n_nets) ++c_env;
-                A.score_net[k] = net;
-                A.score_w[k] = omega;
+                SG.score_net[k] = net;
+                SG.score_w[k] = omega;
                 phase = PH_IDLE;
             } else if (park) {
                 const uint32_t slot = atomicAdd(&K.park_count, 1u);
@@ -746,7 +779,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                     P.pz = pos.z;
                     P.omega = omega;
                     P.t = t;
-                    P.pad[0] = P.pad[1] = P.pad[2] = 0;
+                    P.seg = sg;
+                    P.pad[0] = P.pad[1] = 0;
                     A.park_out[slot] = P;
                 } else {
                     err |= ERR_PARK_CAP;
@@ -762,7 +796,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
             const int nmw = __popcll(balmw), nact = __popcll(balact);
             if (nmw == 0 || 2 * nmw < nact) break;
             if (phase == PH_MW) {
-                const Rand4 r = philox10(s >> 2, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), A.k0, A.k1);
+                const Segment& SG = A.segs[sg];
+                const Rand4 r = philox10(s >> 2, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), SG.k0, SG.k1);
                 const uint32_t us[4] = {r.x, r.y, r.z, r.w};
                 bool alive = true;
 #pragma unroll
@@ -832,7 +867,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                     const float h = 2.f * mR / (float)n;
                     const float3 xx = make_float3(mc.x - mR + (float)ni * h, mc.y - mR + (float)nj * h,
                                                   mc.z - mR + (float)nk * h);
-                    pos = fold3(S, xx);
+                    pos = fold3(*SG.S, xx);
                     ++t;
                     phase = PH_NEED;
                 }
@@ -1417,6 +1452,7 @@ using namespace mw;
 
 struct mw_structure {
     int device = 0;
+    size_t bytes = 0;  // device memory held (arrays, grid index)
     StructDev h{};
     StructDev* d = nullptr;
     char* mem = nullptr;
@@ -1568,7 +1604,9 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
         uint32_t tot[2];
         MW_HIP(hipMemcpy(&tot[0], coff + ncells, 4, hipMemcpyDeviceToHost));
         MW_HIP(hipMemcpy(&tot[1], doff + ncells, 4, hipMemcpyDeviceToHost));
-        char* lists = (char*)dev_alloc(4ull * (tot[0] + tot[1]) + 512);
+        const size_t list_bytes = 4ull * (tot[0] + tot[1]) + 512;
+        char* lists = (char*)dev_alloc(list_bytes);
+        st->bytes = o + list_bytes;
         uint32_t* clist = (uint32_t*)lists;
         uint32_t* dlist = (uint32_t*)(lists + ((4ull * tot[0] + 255) / 256) * 256);
         grid_fill_kernel<<<nbk, tb>>>(S, coff, doff, clist, dlist, ncells);
@@ -1601,19 +1639,347 @@ extern "C" mw_status mw_structure_destroy(mw_structure* s) {
 
 namespace {
 
-struct ExtractBuffers {
+// Launch geometry of the FRW kernels for lattice size n.
+struct LaunchGeom {
+    uint32_t lane_stride, first_stride;
+    size_t lds, first_lds;
+    int blocks, first_blocks;
+    uint64_t pool;
+};
+
+LaunchGeom launch_geom(int n) {
+    int dev = 0, cus = 0;
+    MW_HIP(hipGetDevice(&dev));
+    MW_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    LaunchGeom g;
+    // LDS per lane: axis masks + region codes (+ a key buffer for first
+    // transitions); odd dword strides spread lanes over the banks
+    g.lane_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 3) / 4) | 1u;
+    g.first_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * (KEY_HDR + n) + 3) / 4) | 1u;
+    g.lds = (size_t)g.lane_stride * 4 * WALK_THREADS;
+    g.first_lds = (size_t)g.first_stride * 4 * FRW_THREADS;
+    g.blocks = cus * std::max(1, std::min(8, (int)(163840 / (g.lds + 512))));
+    g.first_blocks = cus * std::max(1, std::min(8, (int)(163840 / (g.first_lds + 512))));
+    g.pool = (uint64_t)g.blocks * WALK_THREADS;
+    return g;
+}
+
+// Runs the walks of a list of segments to completion: first transitions
+// (retried after missing tables are built), then walker launches (parked
+// walks resume after their tables are built).  Holds the table cache of one
+// lattice size while it runs.
+struct Runner {
+    int n, hybrid;
+    Cache* cache;
+    LaunchGeom g;
+    uint32_t park_cap;
+    int seg_cap;
+    uint32_t uniform_index = NO_INDEX;
     char* mem = nullptr;
-    GaussDev* G;
     Counters* ctr;
-    int* status;
+    uint32_t* status;
     Parked* park[2];
+    Segment* dsegs;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    uint64_t misses = 0, launches = 0;
+    double walker_ms = 0.0;
+
+    Runner(int n_, int hybrid_, uint64_t max_walks, int seg_cap_) : n(n_), hybrid(hybrid_), seg_cap(seg_cap_) {
+        cache = &get_cache(n);
+        g = launch_geom(n);
+        park_cap = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(max_walks, 1024), 1u << 24);
+        size_t o = 0;
+        auto sz = [&](size_t b) {
+            size_t r = o;
+            o += (b + 255) / 256 * 256;
+            return r;
+        };
+        const size_t o_ctr = sz(sizeof(Counters)), o_st = sz(16);
+        const size_t o_p0 = sz(sizeof(Parked) * (size_t)park_cap), o_p1 = sz(sizeof(Parked) * (size_t)park_cap);
+        const size_t o_sg = sz(sizeof(Segment) * (size_t)seg_cap);
+        mem = (char*)dev_alloc(o);
+        ctr = (Counters*)(mem + o_ctr);
+        status = (uint32_t*)(mem + o_st);
+        park[0] = (Parked*)(mem + o_p0);
+        park[1] = (Parked*)(mem + o_p1);
+        dsegs = (Segment*)(mem + o_sg);
+        MW_HIP(hipEventCreate(&ev0));
+        MW_HIP(hipEventCreate(&ev1));
+        MW_HIP(hipFuncSetAttribute((const void*)frw_walk_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)g.lds));
+        MW_HIP(hipFuncSetAttribute((const void*)frw_walk_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)g.lds));
+        MW_HIP(hipFuncSetAttribute((const void*)first_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)g.first_lds));
+    }
+    ~Runner() {
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        dev_free(mem);
+    }
+
+    // builds every table queued since the last call (binary64 solves)
+    void build_pending() {
+        uint32_t npend = 0;
+        MW_HIP(hipMemcpy(&npend, cache->d.n_pending, 4, hipMemcpyDeviceToHost));
+        if (!npend) return;
+        std::vector<uint32_t> list(npend);
+        MW_HIP(hipMemcpy(list.data(), cache->d.pending, 4ull * npend, hipMemcpyDeviceToHost));
+        std::vector<uint32_t> valid;
+        for (uint32_t v : list)
+            if (v < cache->d.capacity) valid.push_back(v);
+        const uint32_t M = n - 1;
+        const size_t stride = (size_t)3 * M * M * M + (size_t)4 * 6 * M * M + 64;
+        const uint32_t chunk = 512;
+        double* work = (double*)dev_alloc(sizeof(double) * stride * std::min<size_t>(chunk, valid.size()));
+        uint32_t* dlist = nullptr;
+        try {
+            dlist = (uint32_t*)dev_alloc(4ull * valid.size());
+        } catch (...) {
+            dev_free(work);
+            throw;
+        }
+        struct G2 {
+            void *a, *b;
+            ~G2() {
+                dev_free(a);
+                dev_free(b);
+            }
+        } g2{work, dlist};
+        MW_HIP(hipMemcpy(dlist, valid.data(), 4ull * valid.size(), hipMemcpyHostToDevice));
+        for (size_t c0 = 0; c0 < valid.size(); c0 += chunk) {
+            BuildArgs Ba{cache->d, dlist + c0, (uint32_t)std::min<size_t>(chunk, valid.size() - c0), work, stride};
+            build_tables_kernel<<<Ba.count, TB_THREADS>>>(Ba);
+            MW_HIP(hipGetLastError());
+        }
+        MW_HIP(hipDeviceSynchronize());
+        MW_HIP(hipMemset(cache->d.n_pending, 0, 4));
+        misses += valid.size();
+    }
+
+    void ensure_uniform_table() {
+        for (int it = 0; it < 3 && uniform_index == NO_INDEX; ++it) {
+            uniform_table_kernel<<<1, 1>>>(cache->d, n, status);
+            MW_HIP(hipGetLastError());
+            uint32_t res[2];
+            MW_HIP(hipMemcpy(res, status, 8, hipMemcpyDeviceToHost));
+            if (res[0] == LOOKUP_HIT)
+                uniform_index = res[1];
+            else if (res[0] == LOOKUP_FULL)
+                MW_REQUIRE(false, MW_ELIMIT, "SGF table cache full (MWALK_TABLE_CAP)");
+            else
+                build_pending();
+        }
+        MW_REQUIRE(uniform_index != NO_INDEX, MW_EDEVICE, "uniform SGF table could not be built");
+    }
+
+    static void check_errors(const Counters& h) {
+        MW_REQUIRE(!(h.err & ERR_REGIONS), MW_ELIMIT, "a transition cube touched more than %d dielectric regions",
+                   MAX_REGIONS);
+        MW_REQUIRE(!(h.err & ERR_TABLE_CAP), MW_ELIMIT, "SGF table cache full (MWALK_TABLE_CAP)");
+        MW_REQUIRE(!(h.err & ERR_PARK_CAP), MW_ELIMIT, "parked-walk queue overflow");
+        MW_REQUIRE(!(h.err & ERR_STEP_CAP), MW_ELIMIT, "a micro-walk exceeded %u steps", MW_STEP_CAP);
+    }
+
+    // Runs every walk of segs (first_done must be zeroed by the caller).
+    Counters run(const std::vector<Segment>& segs) {
+        MW_REQUIRE((int)segs.size() <= seg_cap && !segs.empty(), MW_EINVAL, "bad segment list");
+        std::lock_guard<std::mutex> lock(cache->mu);
+        ensure_uniform_table();
+        unsigned long long total = 0;
+        for (const Segment& sgm : segs) total += sgm.count;
+        MW_REQUIRE(total <= park_cap || total <= (1ull << 40), MW_ELIMIT, "round too large");
+        MW_HIP(hipMemcpy(dsegs, segs.data(), sizeof(Segment) * segs.size(), hipMemcpyHostToDevice));
+        MW_HIP(hipMemset(ctr, 0, sizeof(Counters)));
+        for (int round = 0;; ++round) {
+            FirstArgs F{};
+            F.segs = dsegs;
+            F.n_segs = (int)segs.size();
+            F.total = total;
+            F.cache = cache->d;
+            F.n = n;
+            F.ctr = ctr;
+            F.lane_stride = g.first_stride;
+            MW_HIP(hipMemset(&ctr->first_missing, 0, 4));
+            const int fblocks = (int)std::min<uint64_t>((total + FRW_THREADS - 1) / FRW_THREADS, (uint64_t)g.first_blocks);
+            first_kernel<<<fblocks, FRW_THREADS, g.first_lds>>>(F);
+            MW_HIP(hipGetLastError());
+            Counters h{};
+            MW_HIP(hipMemcpy(&h, ctr, sizeof h, hipMemcpyDeviceToHost));
+            check_errors(h);
+            MW_REQUIRE(round < 1000, MW_ELIMIT, "first-transition retry limit reached");
+            build_pending();
+            if (h.first_missing == 0) break;
+        }
+        uint32_t n_resume = 0;
+        int cur = 0;
+        for (uint64_t local = 0;; ++local) {
+            WalkArgs W{};
+            W.segs = dsegs;
+            W.n_segs = (int)segs.size();
+            W.total = total;
+            W.cache = cache->d;
+            W.n = n;
+            W.hybrid = hybrid;
+            W.resume = park[cur];
+            W.n_resume = n_resume;
+            W.park_out = park[cur ^ 1];
+            W.park_cap = park_cap;
+            W.ctr = ctr;
+            W.lane_stride = g.lane_stride;
+            W.uniform_index = uniform_index;
+            // reset the per-launch queue state, keep the walk counter
+            MW_HIP(hipMemset(&ctr->park_count, 0, 4));
+            MW_HIP(hipMemset(&ctr->resume_next, 0, 8));
+            MW_HIP(hipEventRecord(ev0, 0));
+            if (segs.size() == 1)
+                frw_walk_kernel<false><<<g.blocks, WALK_THREADS, g.lds>>>(W);
+            else
+                frw_walk_kernel<true><<<g.blocks, WALK_THREADS, g.lds>>>(W);
+            MW_HIP(hipGetLastError());
+            MW_HIP(hipEventRecord(ev1, 0));
+            ++launches;
+            Counters h{};
+            MW_HIP(hipMemcpy(&h, ctr, sizeof h, hipMemcpyDeviceToHost));
+            float ms = 0.f;
+            MW_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+            walker_ms += ms;
+            check_errors(h);
+            MW_REQUIRE(local < 100000, MW_ELIMIT, "walker relaunch limit reached");
+            build_pending();
+            n_resume = std::min(h.park_count, park_cap);
+            cur ^= 1;
+            if (n_resume == 0 && h.walk_next >= total) return h;
+        }
+    }
+};
+
+// Device state of one extraction: structure copy with the call's absorption
+// tolerance, Gaussian surface, per-walk buffers of one chunk and the fp64
+// accumulators.
+struct Extraction {
+    int K = 0, master = 0;
+    uint64_t chunk_cap = 0;
+    char* mem = nullptr;
+    StructDev* dS;
+    GaussDev* G;
+    int* status;
     float4* partial;
     double* acc;
     double* result;
-    int32_t* own_net = nullptr;
-    float* own_w = nullptr;
-    ~ExtractBuffers() { dev_free(mem); }
+    int32_t* score_net;
+    float* score_w;
+    float4* first_state;
+    uint32_t* first_done;
+    uint64_t done = 0;
+    std::vector<double> res;
+
+    static size_t bytes(int K, uint64_t chunk_cap) {
+        const uint64_t red_blocks = (chunk_cap + RED_CHUNK - 1) / RED_CHUNK;
+        return 256 * 12 + sizeof(StructDev) + sizeof(GaussDev) + 16 + sizeof(float4) * red_blocks * K +
+               sizeof(double) * 4 * K + chunk_cap * (4 + 4 + 16 + 4);
+    }
+
+    Extraction(const mw_structure& st, int master_, double abs_tol_rel, uint64_t chunk_cap_, bool own_scores)
+        : K(st.n_nets + 1), master(master_), chunk_cap(chunk_cap_) {
+        size_t o = 0;
+        auto sz = [&](size_t b) {
+            size_t r = o;
+            o += (b + 255) / 256 * 256;
+            return r;
+        };
+        const uint64_t red_blocks = (chunk_cap + RED_CHUNK - 1) / RED_CHUNK;
+        const size_t o_sd = sz(sizeof(StructDev)), o_G = sz(sizeof(GaussDev)), o_st = sz(16);
+        const size_t o_part = sz(sizeof(float4) * red_blocks * K);
+        const size_t o_acc = sz(sizeof(double) * 2 * K), o_res = sz(sizeof(double) * 2 * K);
+        const size_t o_fs = sz(sizeof(float4) * chunk_cap), o_fd = sz(sizeof(uint32_t) * chunk_cap);
+        const size_t o_sn = own_scores ? sz(4 * chunk_cap) : 0, o_sw = own_scores ? sz(4 * chunk_cap) : 0;
+        mem = (char*)dev_alloc(o);
+        dS = (StructDev*)(mem + o_sd);
+        G = (GaussDev*)(mem + o_G);
+        status = (int*)(mem + o_st);
+        partial = (float4*)(mem + o_part);
+        acc = (double*)(mem + o_acc);
+        result = (double*)(mem + o_res);
+        first_state = (float4*)(mem + o_fs);
+        first_done = (uint32_t*)(mem + o_fd);
+        score_net = own_scores ? (int32_t*)(mem + o_sn) : nullptr;
+        score_w = own_scores ? (float*)(mem + o_sw) : nullptr;
+        StructDev S = st.h;
+        double diag = 0;
+        for (int a = 0; a < 3; ++a) diag += (double)(S.whi[a] - S.wlo[a]) * (S.whi[a] - S.wlo[a]);
+        S.delta_abs = (float)(abs_tol_rel * std::sqrt(diag));
+        MW_HIP(hipMemcpy(dS, &S, sizeof S, hipMemcpyHostToDevice));
+        MW_HIP(hipMemset(acc, 0, sizeof(double) * 2 * K));
+        MW_HIP(hipMemset(status, 0, 16));
+        gauss_kernel<<<1, 1>>>(S, master, G, status);
+        MW_HIP(hipGetLastError());
+        int gst = 0;
+        MW_HIP(hipMemcpy(&gst, status, 4, hipMemcpyDeviceToHost));
+        if (gst != 0) {
+            dev_free(mem);
+            mem = nullptr;
+            MW_REQUIRE(false, MW_EGEOM, "no valid Gaussian surface for net %d (status %d)", master, gst);
+        }
+        res.assign(2 * K, 0.0);
+    }
+    ~Extraction() { dev_free(mem); }
+
+    // Segment for walks [first, first + count) writing scores to net/w (or
+    // the extraction's own buffers).
+    Segment segment(uint64_t first, uint64_t count, uint64_t seed, int32_t* net, float* w) {
+        MW_REQUIRE(count <= chunk_cap, MW_EINVAL, "chunk larger than its buffers");
+        MW_HIP(hipMemset(first_done, 0, sizeof(uint32_t) * count));
+        Segment s{};
+        s.S = dS;
+        s.G = G;
+        s.walk_begin = first;
+        s.count = count;
+        s.score_net = net ? net : score_net;
+        s.score_w = w ? w : score_w;
+        s.first_state = first_state;
+        s.first_done = first_done;
+        s.k0 = (uint32_t)seed;
+        s.k1 = (uint32_t)(seed >> 32);
+        return s;
+    }
+
+    // Adds the scores of a finished segment to the fp64 sums; refreshes res.
+    void reduce(const Segment& s) {
+        const int rb = (int)((s.count + RED_CHUNK - 1) / RED_CHUNK);
+        done += s.count;
+        reduce_scores_kernel<<<rb, RED_THREADS>>>(s.score_net, s.score_w, s.count, K, partial);
+        finish_kernel<<<(K + 255) / 256, 256>>>(partial, rb, K, acc, (double)done, result);
+        MW_HIP(hipGetLastError());
+        MW_HIP(hipMemcpy(res.data(), result, sizeof(double) * 2 * K, hipMemcpyDeviceToHost));
+    }
+
+    bool converged(double target) const {
+        return target > 0 && res[master] != 0.0 && 3.0 * res[K + master] / std::fabs(res[master]) <= target;
+    }
 };
+
+frw_options normalised_options(const frw_options* options) {
+    frw_options opt{};
+    opt.n_cells = 16;
+    opt.hybrid = 1;
+    opt.abs_tol_rel = 1e-6;
+    if (options) opt = *options;
+    if (opt.n_cells == 0) opt.n_cells = 16;
+    MW_REQUIRE(opt.n_cells >= 4 && opt.n_cells <= 32 && opt.n_cells % 2 == 0, MW_EINVAL,
+               "n_cells must be even in [4, 32]");
+    if (opt.abs_tol_rel <= 0) opt.abs_tol_rel = 1e-6;
+    return opt;
+}
+
+void add_counters(frw_stats& st, const Counters& h) {
+    st.hops += h.hops;
+    st.micro_steps += h.micro_steps;
+    for (int q = 0; q < 3; ++q) st.hop_class[q] += h.hop_class[q];
+    for (int q = 0; q < 4; ++q) st.first_branch[q] += h.first_branch[q];
+    st.env_absorbed += h.env;
+    st.hop_cap += h.hop_cap;
+}
 
 }  // namespace
 
@@ -1626,264 +1992,323 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         MW_REQUIRE(cap_row && stderr_row, MW_EINVAL, "cap_row and stderr_row are required");
         MW_REQUIRE(master >= 0 && master < st->n_nets, MW_EINVAL, "master %d out of range", master);
         MW_REQUIRE(walk_budget >= 2, MW_EINVAL, "walk_budget must be at least 2");
-        frw_options opt{};
-        opt.n_cells = 16;
-        opt.hybrid = 1;
-        opt.abs_tol_rel = 1e-6;
-        if (options) opt = *options;
-        if (opt.n_cells == 0) opt.n_cells = 16;
-        MW_REQUIRE(opt.n_cells >= 4 && opt.n_cells <= 32 && opt.n_cells % 2 == 0, MW_EINVAL,
-                   "n_cells must be even in [4, 32]");
-        if (opt.abs_tol_rel <= 0) opt.abs_tol_rel = 1e-6;
-        const int n = opt.n_cells;
-        const int K = st->n_nets + 1;
+        const frw_options opt = normalised_options(options);
         int dev = 0;
         MW_HIP(hipGetDevice(&dev));
-        MW_REQUIRE(dev == st->device, MW_EINVAL, "structure belongs to device %d, current device is %d", st->device, dev);
-        Cache& cache = get_cache(n);
-        std::lock_guard<std::mutex> cache_lock(cache.mu);
-        // per-call structure copy with this call's absorption tolerance
-        StructDev S = st->h;
-        {
-            double diag = 0;
-            for (int a = 0; a < 3; ++a) diag += (double)(S.whi[a] - S.wlo[a]) * (S.whi[a] - S.wlo[a]);
-            S.delta_abs = (float)(opt.abs_tol_rel * std::sqrt(diag));
-        }
-        int cus = 0;
-        MW_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        // LDS per lane: axis masks + region codes (+ a key buffer for first
-        // transitions); odd dword strides spread lanes over the banks
-        uint32_t lane_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 3) / 4) | 1u;
-        uint32_t first_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * (KEY_HDR + n) + 3) / 4) | 1u;
-        const size_t lds = (size_t)lane_stride * 4 * WALK_THREADS;
-        const size_t first_lds = (size_t)first_stride * 4 * FRW_THREADS;
-        const int per_cu = std::max(1, std::min(8, (int)(163840 / (lds + 512))));
-        const int blocks = cus * per_cu;
-        const int first_per_cu = std::max(1, std::min(8, (int)(163840 / (first_lds + 512))));
-        const uint64_t pool = (uint64_t)blocks * WALK_THREADS;
-        uint64_t batch = opt.batch_walks ? opt.batch_walks : std::max<uint64_t>(pool * 8, 1 << 20);
+        MW_REQUIRE(dev == st->device, MW_EINVAL, "structure belongs to device %d, current device is %d",
+                   st->device, dev);
+        const int n = opt.n_cells;
+        const LaunchGeom g = launch_geom(n);
+        uint64_t batch = opt.batch_walks ? opt.batch_walks : std::max<uint64_t>(g.pool * 8, 1 << 20);
         if (opt.target_rel_3sigma <= 0) batch = walk_budget;  // fixed budget: one pass
         batch = std::min<uint64_t>(batch, walk_budget);
-        const uint32_t park_cap = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(batch, 1024), 1u << 24);
-        ExtractBuffers B;
-        size_t o = 0;
-        auto sz = [&](size_t b) {
-            size_t r = o;
-            o += (b + 255) / 256 * 256;
-            return r;
-        };
-        const uint64_t red_blocks = (batch + RED_CHUNK - 1) / RED_CHUNK;
-        const size_t o_G = sz(sizeof(GaussDev)), o_ctr = sz(sizeof(Counters)), o_st = sz(16), o_sd = sz(sizeof(StructDev));
-        const size_t o_p0 = sz(sizeof(Parked) * (size_t)park_cap), o_p1 = sz(sizeof(Parked) * (size_t)park_cap);
-        const size_t o_part = sz(sizeof(float4) * red_blocks * K);
-        const size_t o_acc = sz(sizeof(double) * 2 * K), o_res = sz(sizeof(double) * 2 * K);
-        const size_t o_fs = sz(sizeof(float4) * batch), o_fd = sz(sizeof(uint32_t) * batch);
         const bool own_scores = !(score_net && score_w);
-        const size_t o_sn = own_scores ? sz(4 * batch) : 0, o_sw = own_scores ? sz(4 * batch) : 0;
-        B.mem = (char*)dev_alloc(o);
-        char* m = B.mem;
-        B.G = (GaussDev*)(m + o_G);
-        B.ctr = (Counters*)(m + o_ctr);
-        B.status = (int*)(m + o_st);
-        StructDev* dS = (StructDev*)(m + o_sd);
-        B.park[0] = (Parked*)(m + o_p0);
-        B.park[1] = (Parked*)(m + o_p1);
-        B.partial = (float4*)(m + o_part);
-        B.acc = (double*)(m + o_acc);
-        B.result = (double*)(m + o_res);
-        float4* fstate = (float4*)(m + o_fs);
-        uint32_t* fdone = (uint32_t*)(m + o_fd);
-        if (own_scores) {
-            B.own_net = (int32_t*)(m + o_sn);
-            B.own_w = (float*)(m + o_sw);
+        Extraction X(*st, master, opt.abs_tol_rel, batch, own_scores);
+        Runner R(n, opt.hybrid, batch, 1);
+        frw_stats acc{};
+        while (X.done < walk_budget) {
+            const uint64_t nb = std::min<uint64_t>(batch, walk_budget - X.done);
+            const Segment sgm = X.segment(opt.first_walk + X.done, nb, seed, own_scores ? nullptr : score_net + X.done,
+                                          own_scores ? nullptr : score_w + X.done);
+            add_counters(acc, R.run({sgm}));
+            X.reduce(sgm);
+            if (X.converged(opt.target_rel_3sigma)) break;
         }
-        MW_HIP(hipMemcpy(dS, &S, sizeof S, hipMemcpyHostToDevice));
-        MW_HIP(hipMemset(B.acc, 0, sizeof(double) * 2 * K));
-        MW_HIP(hipMemset(B.status, 0, 16));
-        gauss_kernel<<<1, 1>>>(S, master, B.G, B.status);
-        MW_HIP(hipGetLastError());
-        int gst = 0;
-        MW_HIP(hipMemcpy(&gst, B.status, 4, hipMemcpyDeviceToHost));
-        MW_REQUIRE(gst == 0, MW_EGEOM, "no valid Gaussian surface for net %d (status %d)", master, gst);
-        MW_HIP(hipFuncSetAttribute((const void*)frw_walk_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        MW_HIP(hipFuncSetAttribute((const void*)first_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)first_lds));
-        uint64_t misses = 0;
-        // builds every table queued by the last launch (binary64 solves)
-        auto build_pending = [&]() {
-            uint32_t npend = 0;
-            MW_HIP(hipMemcpy(&npend, cache.d.n_pending, 4, hipMemcpyDeviceToHost));
-            if (!npend) return;
-            std::vector<uint32_t> list(npend);
-            MW_HIP(hipMemcpy(list.data(), cache.d.pending, 4ull * npend, hipMemcpyDeviceToHost));
-            std::vector<uint32_t> valid;
-            for (uint32_t v : list)
-                if (v < cache.d.capacity) valid.push_back(v);
-            const uint32_t M = n - 1;
-            const size_t stride = (size_t)3 * M * M * M + (size_t)4 * 6 * M * M + 64;
-            const uint32_t chunk = 512;
-            double* work = (double*)dev_alloc(sizeof(double) * stride * std::min<size_t>(chunk, valid.size()));
-            uint32_t* dlist = (uint32_t*)dev_alloc(4ull * valid.size());
-            struct G2 {
-                void *a, *b;
-                ~G2() {
-                    dev_free(a);
-                    dev_free(b);
-                }
-            } g2{work, dlist};
-            MW_HIP(hipMemcpy(dlist, valid.data(), 4ull * valid.size(), hipMemcpyHostToDevice));
-            for (size_t c0 = 0; c0 < valid.size(); c0 += chunk) {
-                BuildArgs Ba{cache.d, dlist + c0, (uint32_t)std::min<size_t>(chunk, valid.size() - c0), work, stride};
-                build_tables_kernel<<<Ba.count, TB_THREADS>>>(Ba);
-                MW_HIP(hipGetLastError());
-            }
-            MW_HIP(hipDeviceSynchronize());
-            MW_HIP(hipMemset(cache.d.n_pending, 0, 4));
-            misses += valid.size();
-        };
-
-        // the uniform cube's hop table is used without a hash lookup
-        uint32_t uniform_index = NO_INDEX;
-        for (int it = 0; it < 3 && uniform_index == NO_INDEX; ++it) {
-            uniform_table_kernel<<<1, 1>>>(cache.d, n, (uint32_t*)B.status);
-            MW_HIP(hipGetLastError());
-            uint32_t res[2];
-            MW_HIP(hipMemcpy(res, B.status, 8, hipMemcpyDeviceToHost));
-            if (res[0] == LOOKUP_HIT) uniform_index = res[1];
-            else if (res[0] == LOOKUP_FULL) MW_REQUIRE(false, MW_ELIMIT, "SGF table cache full (MWALK_TABLE_CAP)");
-            else build_pending();
-        }
-        MW_REQUIRE(uniform_index != NO_INDEX, MW_EDEVICE, "uniform SGF table could not be built");
-        Counters tot{};
-        uint64_t done = 0, launches = 0;
-        double walker_ms = 0.0;
-        hipEvent_t ev0, ev1;
-        MW_HIP(hipEventCreate(&ev0));
-        MW_HIP(hipEventCreate(&ev1));
-        struct EvGuard {
-            hipEvent_t a, b;
-            ~EvGuard() {
-                (void)hipEventDestroy(a);
-                (void)hipEventDestroy(b);
-            }
-        } evguard{ev0, ev1};
-        const uint64_t first = opt.first_walk;
-        std::vector<double> res(2 * K);
-        while (done < walk_budget) {
-            const uint64_t nb_walks = std::min<uint64_t>(batch, walk_budget - done);
-            const uint64_t wb = first + done;
-            int32_t* snet = own_scores ? B.own_net : score_net + done;
-            float* sw = own_scores ? B.own_w : score_w + done;
-            MW_HIP(hipMemset(B.ctr, 0, sizeof(Counters)));
-            MW_HIP(hipMemset(fdone, 0, sizeof(uint32_t) * nb_walks));
-            for (int round = 0;; ++round) {
-                FirstArgs F{};
-                F.S = dS;
-                F.G = B.G;
-                F.cache = cache.d;
-                F.n = n;
-                F.k0 = (uint32_t)seed;
-                F.k1 = (uint32_t)(seed >> 32);
-                F.walk_begin = wb;
-                F.count = nb_walks;
-                F.state = fstate;
-                F.done = fdone;
-                F.ctr = B.ctr;
-                F.lane_stride = first_stride;
-                MW_HIP(hipMemset(&B.ctr->first_missing, 0, 4));
-                const int fblocks = (int)std::min<uint64_t>((nb_walks + FRW_THREADS - 1) / FRW_THREADS,
-                                                            (uint64_t)cus * first_per_cu);
-                first_kernel<<<fblocks, FRW_THREADS, first_lds>>>(F);
-                MW_HIP(hipGetLastError());
-                Counters h{};
-                MW_HIP(hipMemcpy(&h, B.ctr, sizeof h, hipMemcpyDeviceToHost));
-                MW_REQUIRE(!(h.err & ERR_REGIONS), MW_ELIMIT,
-                           "a transition cube touched more than %d dielectric regions", MAX_REGIONS);
-                MW_REQUIRE(!(h.err & ERR_TABLE_CAP), MW_ELIMIT, "SGF table cache full (MWALK_TABLE_CAP)");
-                MW_REQUIRE(round < 1000, MW_ELIMIT, "first-transition retry limit reached");
-                build_pending();
-                if (h.first_missing == 0) break;
-            }
-            uint32_t n_resume = 0;
-            int cur = 0;
-            for (;;) {
-                WalkArgs W{};
-                W.S = dS;
-                W.cache = cache.d;
-                W.n = n;
-                W.hybrid = opt.hybrid;
-                W.master = master;
-                W.k0 = (uint32_t)seed;
-                W.k1 = (uint32_t)(seed >> 32);
-                W.walk_begin = wb;
-                W.walk_end = wb + nb_walks;
-                W.resume = B.park[cur];
-                W.n_resume = n_resume;
-                W.park_out = B.park[cur ^ 1];
-                W.park_cap = park_cap;
-                W.score_net = snet;
-                W.score_w = sw;
-                W.ctr = B.ctr;
-                W.lane_stride = lane_stride;
-                W.first_state = fstate;
-                W.uniform_index = uniform_index;
-                // reset per-launch queue state, keep the walk counter
-                MW_HIP(hipMemset(&B.ctr->park_count, 0, 4));
-                MW_HIP(hipMemset(&B.ctr->resume_next, 0, 8));
-                MW_HIP(hipEventRecord(ev0, 0));
-                frw_walk_kernel<<<blocks, WALK_THREADS, lds>>>(W);
-                MW_HIP(hipGetLastError());
-                MW_HIP(hipEventRecord(ev1, 0));
-                ++launches;
-                Counters h{};
-                MW_HIP(hipMemcpy(&h, B.ctr, sizeof h, hipMemcpyDeviceToHost));
-                float ms = 0.f;
-                MW_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-                walker_ms += ms;
-                MW_REQUIRE(!(h.err & ERR_REGIONS), MW_ELIMIT,
-                           "a transition cube touched more than %d dielectric regions", MAX_REGIONS);
-                MW_REQUIRE(!(h.err & ERR_TABLE_CAP), MW_ELIMIT, "SGF table cache full (MWALK_TABLE_CAP)");
-                MW_REQUIRE(!(h.err & ERR_PARK_CAP), MW_ELIMIT, "parked-walk queue overflow");
-                MW_REQUIRE(!(h.err & ERR_STEP_CAP), MW_ELIMIT, "a micro-walk exceeded %u steps", MW_STEP_CAP);
-                MW_REQUIRE(launches < 100000, MW_ELIMIT, "walker relaunch limit reached");
-                build_pending();
-                n_resume = std::min(h.park_count, park_cap);
-                cur ^= 1;
-                if (n_resume == 0 && h.walk_next >= nb_walks) {
-                    tot.hops += h.hops;
-                    tot.micro_steps += h.micro_steps;
-                    for (int q = 0; q < 3; ++q) tot.hop_class[q] += h.hop_class[q];
-                    for (int q = 0; q < 4; ++q) tot.first_branch[q] += h.first_branch[q];
-                    tot.env += h.env;
-                    tot.hop_cap += h.hop_cap;
-                    break;
-                }
-            }
-            done += nb_walks;
-            const int rb = (int)((nb_walks + RED_CHUNK - 1) / RED_CHUNK);
-            reduce_scores_kernel<<<rb, RED_THREADS>>>(snet, sw, nb_walks, K, B.partial);
-            finish_kernel<<<(K + 255) / 256, 256>>>(B.partial, rb, K, B.acc, (double)done, B.result);
-            MW_HIP(hipGetLastError());
-            MW_HIP(hipMemcpy(res.data(), B.result, sizeof(double) * 2 * K, hipMemcpyDeviceToHost));
-            if (opt.target_rel_3sigma > 0 && res[master] != 0.0 &&
-                3.0 * res[K + master] / std::fabs(res[master]) <= opt.target_rel_3sigma)
-                break;
-        }
+        const int K = X.K;
         for (int j = 0; j < K; ++j) {
-            cap_row[j] = res[j];
-            stderr_row[j] = res[K + j];
+            cap_row[j] = X.res[j];
+            stderr_row[j] = X.res[K + j];
         }
         if (stats) {
-            stats->walks = done;
-            stats->hops = tot.hops;
-            stats->micro_steps = tot.micro_steps;
-            for (int q = 0; q < 3; ++q) stats->hop_class[q] = tot.hop_class[q];
-            for (int q = 0; q < 4; ++q) stats->first_branch[q] = tot.first_branch[q];
-            stats->cache_miss = misses;
-            stats->env_absorbed = tot.env;
-            stats->hop_cap = tot.hop_cap;
-            stats->launches = launches;
+            *stats = acc;
+            stats->walks = X.done;
+            stats->cache_miss = R.misses;
+            stats->launches = R.launches;
             stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-            stats->walker_seconds = walker_ms * 1e-3;
+            stats->walker_seconds = R.walker_ms * 1e-3;
         }
+    });
+}
+
+// -------------------------------------------------------------------------
+// Serving: continuous batching of extraction requests on one device.
+// -------------------------------------------------------------------------
+#include <condition_variable>
+#include <deque>
+#include <thread>
+
+namespace {
+
+struct ServerRequest {
+    uint64_t ticket = 0;
+    // copied description
+    std::vector<mw_cond_box> cond;
+    std::vector<mw_diel_box> diel;
+    std::vector<float> z0, eps;
+    mw_structure_desc desc{};
+    int32_t master = 0;
+    uint64_t budget = 0, seed = 0;
+    size_t footprint = 0;
+    // device state (worker thread only)
+    mw_structure* st = nullptr;
+    std::unique_ptr<Extraction> X;
+    uint64_t chunk = 0;
+    frw_stats stats{};
+    // result
+    enum State { QUEUED, RUNNING, DONE, FAILED } state = QUEUED;
+    mw_status code = MW_OK;
+    std::string message;
+    std::vector<double> row, se;
+    std::chrono::steady_clock::time_point t_submit, t_done;
+
+    void release() {
+        X.reset();
+        if (st) {
+            mw_structure_destroy(st);
+            st = nullptr;
+        }
+    }
+};
+
+}  // namespace
+
+struct mw_server {
+    int device = 0;
+    size_t budget = 0;
+    frw_options opt{};
+    size_t max_queue = 100000;
+    int max_slots = 256;
+    uint64_t round_walks = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
+    std::deque<std::shared_ptr<ServerRequest>> queue;
+    std::map<uint64_t, std::shared_ptr<ServerRequest>> tickets;
+    uint64_t next_ticket = 1;
+    mw_server_stats st{};
+    std::thread worker;
+
+    void fail(const std::shared_ptr<ServerRequest>& r, mw_status code, const std::string& msg) {
+        r->state = ServerRequest::FAILED;
+        r->code = code;
+        r->message = msg;
+        r->t_done = std::chrono::steady_clock::now();
+        st.failed++;
+    }
+
+    void loop() {
+        (void)hipSetDevice(device);
+        std::unique_ptr<Runner> R;
+        std::vector<std::shared_ptr<ServerRequest>> running;
+        for (;;) {
+            std::vector<std::shared_ptr<ServerRequest>> admitted;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                while (!stop && queue.empty() && running.empty()) cv.wait(lk);
+                if (stop && running.empty()) {
+                    for (auto& r : queue) fail(r, MW_EBUSY, "server destroyed before the request ran");
+                    queue.clear();
+                    cv.notify_all();
+                    return;
+                }
+                // admission by device footprint
+                while (!stop && !queue.empty() && (int)(running.size() + admitted.size()) < max_slots) {
+                    auto r = queue.front();
+                    if (r->footprint > budget) {
+                        queue.pop_front();
+                        fail(r, MW_ELIMIT, "request footprint exceeds the server's memory budget");
+                        continue;
+                    }
+                    if (st.resident_bytes + r->footprint > budget) break;
+                    queue.pop_front();
+                    st.resident_bytes += r->footprint;
+                    st.max_resident_bytes = std::max(st.max_resident_bytes, st.resident_bytes);
+                    r->state = ServerRequest::RUNNING;
+                    admitted.push_back(r);
+                }
+            }
+            for (auto& r : admitted) {
+                mw_status rc = mw_structure_create(&r->desc, &r->st);
+                std::string msg = rc ? mw_last_error() : "";
+                if (rc == MW_OK) {
+                    rc = guarded([&] {
+                        r->X = std::make_unique<Extraction>(*r->st, r->master, opt.abs_tol_rel, round_walks, true);
+                    });
+                    if (rc) msg = mw_last_error();
+                }
+                if (rc != MW_OK) {
+                    r->release();
+                    std::lock_guard<std::mutex> lk(mu);
+                    st.resident_bytes -= r->footprint;
+                    fail(r, rc, msg);
+                    cv.notify_all();
+                } else {
+                    // reconcile the reservation with the memory actually held
+                    const size_t actual = r->st->bytes + Extraction::bytes(r->X->K, round_walks);
+                    std::lock_guard<std::mutex> lk(mu);
+                    if (actual > r->footprint) {
+                        st.resident_bytes += actual - r->footprint;
+                        r->footprint = actual;
+                        st.max_resident_bytes = std::max(st.max_resident_bytes, st.resident_bytes);
+                    }
+                    running.push_back(r);
+                }
+            }
+            if (running.empty()) continue;
+            // one round: every running request gets an equal share of walks
+            const uint64_t share = std::max<uint64_t>(round_walks / running.size(), 16384);
+            std::vector<Segment> segs;
+            uint64_t offset = 0;
+            for (auto& r : running) {
+                r->chunk = std::min<uint64_t>(std::min(share, round_walks), r->budget - r->X->done);
+                Segment sg{};
+                const mw_status rc = guarded([&] {
+                    sg = r->X->segment(opt.first_walk + r->X->done, r->chunk, r->seed, nullptr, nullptr);
+                });
+                (void)rc;
+                sg.offset = offset;
+                offset += r->chunk;
+                segs.push_back(sg);
+            }
+            mw_status rc = guarded([&] {
+                if (!R) R = std::make_unique<Runner>(opt.n_cells, opt.hybrid, round_walks, max_slots);
+                const Counters h = R->run(segs);
+                (void)h;
+                for (size_t i = 0; i < running.size(); ++i) {
+                    running[i]->X->reduce(segs[i]);
+                    running[i]->stats.walks = running[i]->X->done;
+                }
+            });
+            std::string msg = rc ? mw_last_error() : "";
+            std::lock_guard<std::mutex> lk(mu);
+            st.rounds++;
+            st.walks += offset;
+            st.max_concurrent = std::max<uint64_t>(st.max_concurrent, running.size());
+            std::vector<std::shared_ptr<ServerRequest>> still;
+            for (auto& r : running) {
+                if (rc != MW_OK) {
+                    fail(r, rc, msg);
+                } else if (r->X->done >= r->budget || r->X->converged(opt.target_rel_3sigma)) {
+                    const int K = r->X->K;
+                    r->row.assign(r->X->res.begin(), r->X->res.begin() + K);
+                    r->se.assign(r->X->res.begin() + K, r->X->res.end());
+                    r->state = ServerRequest::DONE;
+                    r->t_done = std::chrono::steady_clock::now();
+                    st.completed++;
+                } else {
+                    still.push_back(r);
+                    continue;
+                }
+                r->release();
+                st.resident_bytes -= r->footprint;
+            }
+            running.swap(still);
+            cv.notify_all();
+        }
+    }
+};
+
+extern "C" mw_status mw_server_create(size_t hbm_budget_bytes, const frw_options* options, mw_server** out) {
+    return guarded([&] {
+        MW_REQUIRE(out, MW_EINVAL, "null output handle");
+        MW_REQUIRE(hbm_budget_bytes > 0, MW_EINVAL, "zero memory budget");
+        auto s = std::make_unique<mw_server>();
+        MW_HIP(hipGetDevice(&s->device));
+        s->budget = hbm_budget_bytes;
+        s->opt = normalised_options(options);
+        const LaunchGeom g = launch_geom(s->opt.n_cells);
+        s->round_walks = std::max<uint64_t>(2 * g.pool, 1 << 19);
+        mw_server* raw = s.get();
+        s->worker = std::thread([raw] { raw->loop(); });
+        *out = s.release();
+    });
+}
+
+extern "C" mw_status mw_server_submit(mw_server* srv, const mw_structure_desc* D, int32_t master,
+                                      uint64_t walk_budget, uint64_t seed, uint64_t* ticket) {
+    return guarded([&] {
+        MW_REQUIRE(srv && ticket, MW_EINVAL, "null argument");
+        validate_desc(D);
+        MW_REQUIRE(master >= 0 && master < D->n_nets, MW_EINVAL, "master %d out of range", master);
+        MW_REQUIRE(walk_budget >= 2, MW_EINVAL, "walk_budget must be at least 2");
+        auto r = std::make_shared<ServerRequest>();
+        r->cond.assign(D->cond, D->cond + D->n_cond);
+        r->diel.assign(D->diel, D->diel + D->n_diel);
+        r->z0.assign(D->layer_z0, D->layer_z0 + D->n_layers);
+        r->eps.assign(D->layer_eps, D->layer_eps + D->n_layers);
+        r->desc = *D;
+        r->desc.cond = r->cond.data();
+        r->desc.diel = r->diel.empty() ? nullptr : r->diel.data();
+        r->desc.layer_z0 = r->z0.data();
+        r->desc.layer_eps = r->eps.data();
+        r->master = master;
+        r->budget = walk_budget;
+        r->seed = seed;
+        // footprint: structure and grid index (bounded by the grid-size rule
+        // of mw_structure_create) plus the per-round extraction buffers
+        const size_t boxes = (size_t)D->n_cond + D->n_diel;
+        const size_t cells = (size_t)std::min(262144.0, std::max(64.0, 16.0 * boxes)) * 4;  // grid rounding slack
+        r->footprint = boxes * 64 + cells * 16 + cells * 4 * std::min<size_t>(boxes, 64) +
+                       Extraction::bytes(D->n_nets + 1, srv->round_walks) + 64 * 1024;
+        r->t_submit = std::chrono::steady_clock::now();
+        std::lock_guard<std::mutex> lk(srv->mu);
+        MW_REQUIRE(!srv->stop, MW_EINVAL, "server is shutting down");
+        MW_REQUIRE(srv->queue.size() < srv->max_queue, MW_EBUSY, "server queue full");
+        r->ticket = srv->next_ticket++;
+        srv->tickets[r->ticket] = r;
+        srv->queue.push_back(r);
+        srv->st.submitted++;
+        *ticket = r->ticket;
+        srv->cv.notify_all();
+    });
+}
+
+extern "C" mw_status mw_server_poll(mw_server* srv, uint64_t ticket, double* cap_row, double* stderr_row,
+                                    frw_stats* stats, double* latency_s) {
+    mw_status code = MW_OK;
+    const mw_status rc = guarded([&] {
+        MW_REQUIRE(srv, MW_EINVAL, "null server");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        auto it = srv->tickets.find(ticket);
+        MW_REQUIRE(it != srv->tickets.end(), MW_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+        auto& r = it->second;
+        if (r->state == ServerRequest::QUEUED || r->state == ServerRequest::RUNNING) {
+            code = MW_ENOTREADY;
+            return;
+        }
+        if (r->state == ServerRequest::FAILED) {
+            set_error("%s", r->message.c_str());
+            code = r->code;
+            return;
+        }
+        MW_REQUIRE(cap_row && stderr_row, MW_EINVAL, "cap_row and stderr_row are required");
+        for (size_t j = 0; j < r->row.size(); ++j) {
+            cap_row[j] = r->row[j];
+            stderr_row[j] = r->se[j];
+        }
+        if (stats) *stats = r->stats;
+        if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+    });
+    return rc != MW_OK ? rc : code;
+}
+
+extern "C" mw_status mw_server_get_stats(mw_server* srv, mw_server_stats* out) {
+    return guarded([&] {
+        MW_REQUIRE(srv && out, MW_EINVAL, "null argument");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        *out = srv->st;
+    });
+}
+
+extern "C" mw_status mw_server_destroy(mw_server* srv) {
+    return guarded([&] {
+        if (!srv) return;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->stop = true;
+        }
+        srv->cv.notify_all();
+        if (srv->worker.joinable()) srv->worker.join();
+        delete srv;
     });
 }

@@ -182,7 +182,7 @@ def interconnect(side, tracks_per_layer, rng, height=2.0, highk_p=0.1, coat=0.02
             hi_c = lo_c + width[t]
             pos += pitch[t]
             L = min(rng.uniform(1.0, 20.0), side - 0.2)
-            start = rng.uniform(0.1, side - 0.1 - L)
+            start = 0.1 + rng.uniform() * (side - 0.2 - L)
             if along == 0:
                 box = [start, lo_c, z_lo, start + L, hi_c, z_hi]
             else:
