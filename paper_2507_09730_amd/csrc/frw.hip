@@ -39,7 +39,7 @@ constexpr float EPS0 = 8.8541878128e-3f;  // vacuum permittivity, fF/um
 constexpr uint32_t HOP_CAP = 100000;
 constexpr int MAX_REGIONS = MW_MAX_REGIONS;
 constexpr int FRW_THREADS = 256;   // first-transition kernel
-constexpr int WALK_THREADS = 192;  // walker kernel: 5 blocks of 3 waves fit one CU's LDS
+constexpr int WALK_THREADS = 128;  // walker kernel: small blocks pack the LDS of a CU
 constexpr uint32_t KEY_HDR = 4;
 constexpr uint32_t NO_INDEX = 0xffffffffu;
 
@@ -221,62 +221,61 @@ __device__ __forceinline__ float3 fold3(const StructDev& S, float3 p) {
 }
 
 // -------------------------------------------------------------------------
-// Per-lane cube description in LDS: masks[3][n] (u16) then codes[16] (u32).
+// Per-lane cube description in LDS: masks[3][n] (u16, dielectric boxes),
+// box codes[16] (u32), background codes bz[n] (u32, per z cell).
 // -------------------------------------------------------------------------
 struct LaneCube {
-    uint16_t* mask;   // mask[a * n + i]
-    uint32_t* codes;  // region code by bit
+    uint16_t* mask;   // mask[a * n + i]: bit b = box b's interval holds cell i's centre
+    uint32_t* codes;  // code of box bit b
+    uint32_t* bz;     // background (layer) code of z cell k
 };
+
+__device__ __forceinline__ LaneCube lane_cube(uint32_t* my, int n) {
+    LaneCube L;
+    L.mask = reinterpret_cast<uint16_t*>(my);
+    L.codes = my + ((3 * n + 1) / 2);
+    L.bz = L.codes + MAX_REGIONS;
+    return L;
+}
 
 __device__ __forceinline__ int hb16(uint32_t m) { return 31 - __clz(m | 1u); }
 
+// Code of a cell with box-membership m and background code b.
+__device__ __forceinline__ uint32_t cell_code(LaneCube L, uint32_t m, uint32_t b) {
+    return m ? L.codes[hb16(m)] : b;
+}
+
 struct CubeInfo {
     uint32_t present, A[3];
-    int cls;   // 0 uniform, 1 stratified, 2 other
-    int axis;  // stratification axis
+    int n_layers;  // background layers holding at least one cell centre
+    int cls;       // 0 uniform, 1 stratified, 2 other
+    int axis;      // stratification axis
     bool overflow;
 };
 
-// Builds the region masks of the cube centred at c with half-size R.
+// Builds the region description of the cube centred at c with half-size R.
+// Regions are the dielectric boxes (bits, priority = list order) and the
+// background layers (per-z-cell codes); a region is present when it holds at
+// least one cell centre.
 __device__ CubeInfo build_cube(const StructDev& S, int cell, float3 c, float R, int n, LaneCube L) {
     CubeInfo info{};
     const float h = 2.f * R / (float)n;
     const float lo0[3] = {c.x - R, c.y - R, c.z - R};
     for (int q = 0; q < 3 * n; ++q) L.mask[q] = 0;
-    int nbits = 0;
-    // background layers touching the cube (lowest priority)
-    {
-        const float zlo = lo0[2], zhi = lo0[2] + 2.f * R;
-        float flo = fminf(fold(S, 2, zlo), fold(S, 2, zhi)), fhi = fmaxf(fold(S, 2, zlo), fold(S, 2, zhi));
-        // folded coordinates of the cube's cells lie within [min, max] of the
-        // folded span (one reflection)
-        if (zlo < S.wlo[2] && S.bc[4] == MW_BC_NEUMANN) flo = fminf(flo, S.wlo[2]);
-        if (zhi > S.whi[2] && S.bc[5] == MW_BC_NEUMANN) fhi = fmaxf(fhi, S.whi[2]);
-        int l0 = 0, l1 = 0;
-        for (int l = 1; l < S.n_layers; ++l) {
-            if (S.layer_z0[l] <= flo) l0 = l;
-            if (S.layer_z0[l] <= fhi) l1 = l;
-        }
-        if (l1 - l0 + 1 > MAX_REGIONS) {
-            info.overflow = true;
-            l1 = l0 + MAX_REGIONS - 1;
-        }
-        for (int k = 0; k < n; ++k) {
-            const float z = fold(S, 2, lo0[2] + ((float)k + 0.5f) * h);
-            int l = l0;
-            for (int q = l0 + 1; q <= l1; ++q)
-                if (z >= S.layer_z0[q]) l = q;
-            L.mask[2 * n + k] = (uint16_t)(1u << (l - l0));
-        }
-        for (int l = l0; l <= l1; ++l) L.codes[l - l0] = S.layer_code[l];
-        const uint16_t all = (uint16_t)((1u << (l1 - l0 + 1)) - 1u);
-        for (int i = 0; i < n; ++i) {
-            L.mask[i] = all;
-            L.mask[n + i] = all;
-        }
-        nbits = l1 - l0 + 1;
+    // background layer of every z cell
+    int lmin = 1 << 30, lmax = -1;
+    for (int k = 0; k < n; ++k) {
+        const float z = fold(S, 2, lo0[2] + ((float)k + 0.5f) * h);
+        int l = 0;
+        for (int q = 1; q < S.n_layers; ++q)
+            if (z >= S.layer_z0[q]) l = q;
+        lmin = min(lmin, l);
+        lmax = max(lmax, l);
+        L.bz[k] = S.layer_code[l];
     }
+    info.n_layers = lmax - lmin + 1;
     // dielectric boxes touching the cube, in priority order
+    int nbits = 0;
     const uint32_t b = S.gd_off[cell], e = S.gd_off[cell + 1];
     for (uint32_t q = b; q < e; ++q) {
         const uint32_t id = S.gd_list[q];
@@ -317,7 +316,7 @@ __device__ CubeInfo build_cube(const StructDev& S, int cell, float3 c, float R, 
             }
         }
     }
-    // aggregate masks: present regions and full-span regions per axis
+    // aggregate masks: present boxes and boxes spanning all cells per axis
     uint32_t O[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -331,9 +330,12 @@ __device__ CubeInfo build_cube(const StructDev& S, int cell, float3 c, float R, 
         O[a] = Oa;
     }
     info.present = O[0] & O[1] & O[2];
+    // layers span every x and y cell; they span every z cell only when a
+    // single layer is present
+    const bool one_layer = info.n_layers == 1;
     const bool full0 = (info.present & ~info.A[0]) == 0;
     const bool full1 = (info.present & ~info.A[1]) == 0;
-    const bool full2 = (info.present & ~info.A[2]) == 0;
+    const bool full2 = (info.present & ~info.A[2]) == 0 && one_layer;
     if (full0 && full1 && full2) {
         info.cls = 0;
         info.axis = 2;
@@ -355,25 +357,30 @@ __device__ CubeInfo build_cube(const StructDev& S, int cell, float3 c, float R, 
 
 __device__ __forceinline__ bool stratified_along(const CubeInfo& I, int s) {
     if (I.cls == 0) return true;
-    const uint32_t f1 = (I.present & ~I.A[(s + 1) % 3]) == 0, f2 = (I.present & ~I.A[(s + 2) % 3]) == 0;
+    const int a1 = (s + 1) % 3, a2 = (s + 2) % 3;
+    const bool f1 = (I.present & ~I.A[a1]) == 0 && (a1 != 2 || I.n_layers == 1);
+    const bool f2 = (I.present & ~I.A[a2]) == 0 && (a2 != 2 || I.n_layers == 1);
     return f1 && f2;
 }
 
 // Code of plane p normal to s of a cube stratified along s.
 __device__ __forceinline__ uint32_t plane_code(LaneCube L, const CubeInfo& I, int n, int s, int p) {
-    return L.codes[hb16(L.mask[s * n + p] & I.present)];
+    return cell_code(L, L.mask[s * n + p] & I.present, L.bz[s == 2 ? p : 0]);
 }
 
 // Mean codes of the planes normal to a (rounded half to even) written to
-// out[0..n): each plane sums its cells by runs of equal masks along the two
-// in-plane axes; planes whose own mask equals the previous plane's repeat it.
+// out[0..n): each plane sums its cells by runs of equal masks (and
+// background codes) along the two in-plane axes; planes whose own mask and
+// background equal the previous plane's repeat it.  When a is not z, the
+// second in-plane axis v is z.
 __device__ void plane_mean_codes(LaneCube L, int n, int a, uint32_t* out) {
     const int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
     const unsigned long long area = (unsigned long long)n * n;
-    uint32_t prev_ma = 0xffffffffu, prev = 0;
+    uint32_t prev_ma = 0xffffffffu, prev_b = 0, prev = 0;
     for (int p = 0; p < n; ++p) {
         const uint32_t ma = L.mask[a * n + p];
-        if (ma == prev_ma) {
+        const uint32_t bp = a == 2 ? L.bz[p] : 0u;
+        if (ma == prev_ma && bp == prev_b) {
             out[p] = prev;
             continue;
         }
@@ -387,9 +394,10 @@ __device__ void plane_mean_codes(LaneCube L, int n, int a, uint32_t* out) {
             int j = 0;
             while (j < n) {
                 const uint32_t mv = L.mask[v * n + j];
+                const uint32_t bv = a == 2 ? bp : L.bz[j];
                 int lj = 1;
-                while (j + lj < n && L.mask[v * n + j + lj] == mv) ++lj;
-                sum += (unsigned long long)(li * lj) * L.codes[hb16(mau & mv)];
+                while (j + lj < n && L.mask[v * n + j + lj] == mv && (a == 2 || L.bz[j + lj] == bv)) ++lj;
+                sum += (unsigned long long)(li * lj) * cell_code(L, mau & mv, bv);
                 j += lj;
             }
             i += li;
@@ -397,6 +405,7 @@ __device__ void plane_mean_codes(LaneCube L, int n, int a, uint32_t* out) {
         unsigned long long qt = sum / area, rem = sum % area;
         if (2 * rem > area || (2 * rem == area && (qt & 1))) ++qt;
         prev_ma = ma;
+        prev_b = bp;
         prev = (uint32_t)qt;
         out[p] = prev;
     }
@@ -514,8 +523,8 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
     extern __shared__ uint32_t lds[];
     const int n = A.n;
     uint32_t* my = lds + threadIdx.x * A.lane_stride;
-    LaneCube L{reinterpret_cast<uint16_t*>(my), my + ((3 * n + 1) / 2)};
-    uint32_t* kbuf = L.codes + MAX_REGIONS;
+    const LaneCube L = lane_cube(my, n);
+    uint32_t* kbuf = L.bz + n;
     unsigned long long c_br[4] = {0, 0, 0, 0};
     uint32_t err = 0, missing = 0;
     for (unsigned long long g = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; g < A.total;
@@ -613,7 +622,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     const int n = A.n;
     const int lane = threadIdx.x & 63;
     uint32_t* my = lds + threadIdx.x * A.lane_stride;
-    LaneCube L{reinterpret_cast<uint16_t*>(my), my + ((3 * n + 1) / 2)};
+    const LaneCube L = lane_cube(my, n);
 
     Counters& K = *A.ctr;
     unsigned long long c_hops = 0, c_steps = 0, c_cls[3] = {0, 0, 0}, c_env = 0, c_cap = 0;
@@ -630,7 +639,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     float mR = 0.f;
     int ni = 0, nj = 0, nk = 0;
     uint32_t s = 0;
-    uint32_t mx0 = 0, mx1 = 0, my0 = 0, my1 = 0, mz0 = 0, mz1 = 0;
+    uint32_t mx0 = 0, mx1 = 0, my0 = 0, my1 = 0, mz0 = 0, mz1 = 0, bz0 = 0, bz1 = 0;
 
     for (;;) {
         // ---- take work: resumed walks first, then fresh walk ids ----
@@ -760,6 +769,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                         my1 = L.mask[n + nj];
                         mz0 = L.mask[2 * n + nk - 1];
                         mz1 = L.mask[2 * n + nk];
+                        bz0 = L.bz[nk - 1];
+                        bz1 = L.bz[nk];
                     }
                 }
             }
@@ -804,17 +815,17 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                 for (int q = 0; q < 4; ++q) {
                     if (alive) {
                         uint32_t d;
-                        if (mx0 == mx1 && my0 == my1 && mz0 == mz1) {
+                        if (mx0 == mx1 && my0 == my1 && mz0 == mz1 && bz0 == bz1) {
                             d = __umulhi(us[q], 6u);
                         } else {
                             const uint32_t m000 = mx0 & my0 & mz0, m001 = mx1 & my0 & mz0;
                             const uint32_t m010 = mx0 & my1 & mz0, m011 = mx1 & my1 & mz0;
                             const uint32_t m100 = mx0 & my0 & mz1, m101 = mx1 & my0 & mz1;
                             const uint32_t m110 = mx0 & my1 & mz1, m111 = mx1 & my1 & mz1;
-                            const uint32_t c000 = L.codes[hb16(m000)], c001 = L.codes[hb16(m001)];
-                            const uint32_t c010 = L.codes[hb16(m010)], c011 = L.codes[hb16(m011)];
-                            const uint32_t c100 = L.codes[hb16(m100)], c101 = L.codes[hb16(m101)];
-                            const uint32_t c110 = L.codes[hb16(m110)], c111 = L.codes[hb16(m111)];
+                            const uint32_t c000 = cell_code(L, m000, bz0), c001 = cell_code(L, m001, bz0);
+                            const uint32_t c010 = cell_code(L, m010, bz0), c011 = cell_code(L, m011, bz0);
+                            const uint32_t c100 = cell_code(L, m100, bz1), c101 = cell_code(L, m101, bz1);
+                            const uint32_t c110 = cell_code(L, m110, bz1), c111 = cell_code(L, m111, bz1);
                             const uint32_t a0 = c000 + c100, a1 = c010 + c110;
                             const uint32_t b0 = c001 + c101, b1 = c011 + c111;
                             const uint32_t gmx = a0 + a1, total = gmx + b0 + b1;
@@ -851,6 +862,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             } else {
                                 mz0 = lo;
                                 mz1 = hi;
+                                bz0 = L.bz[cnew - 1];
+                                bz1 = L.bz[cnew];
                             }
                         }
                     }
@@ -1654,11 +1667,11 @@ LaunchGeom launch_geom(int n) {
     LaunchGeom g;
     // LDS per lane: axis masks + region codes (+ a key buffer for first
     // transitions); odd dword strides spread lanes over the banks
-    g.lane_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 3) / 4) | 1u;
-    g.first_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * (KEY_HDR + n) + 3) / 4) | 1u;
+    g.lane_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * n + 3) / 4) | 1u;
+    g.first_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * n + 4 * (KEY_HDR + n) + 3) / 4) | 1u;
     g.lds = (size_t)g.lane_stride * 4 * WALK_THREADS;
     g.first_lds = (size_t)g.first_stride * 4 * FRW_THREADS;
-    g.blocks = cus * std::max(1, std::min(8, (int)(163840 / (g.lds + 512))));
+    g.blocks = cus * std::max(1, std::min(16, (int)(163840 / (g.lds + 512))));
     g.first_blocks = cus * std::max(1, std::min(8, (int)(163840 / (g.first_lds + 512))));
     g.pool = (uint64_t)g.blocks * WALK_THREADS;
     return g;
@@ -2072,6 +2085,8 @@ struct ServerRequest {
 
 }  // namespace
 
+constexpr uint64_t MIN_SHARE = 4096;  // walks per request and round, at least
+
 struct mw_server {
     int device = 0;
     size_t budget = 0;
@@ -2156,7 +2171,7 @@ struct mw_server {
             }
             if (running.empty()) continue;
             // one round: every running request gets an equal share of walks
-            const uint64_t share = std::max<uint64_t>(round_walks / running.size(), 16384);
+            const uint64_t share = std::max<uint64_t>(round_walks / running.size(), MIN_SHARE);
             std::vector<Segment> segs;
             uint64_t offset = 0;
             for (auto& r : running) {
@@ -2171,7 +2186,10 @@ struct mw_server {
                 segs.push_back(sg);
             }
             mw_status rc = guarded([&] {
-                if (!R) R = std::make_unique<Runner>(opt.n_cells, opt.hybrid, round_walks, max_slots);
+                if (!R)
+                    R = std::make_unique<Runner>(opt.n_cells, opt.hybrid,
+                                                 std::max<uint64_t>(round_walks, MIN_SHARE * (uint64_t)max_slots),
+                                                 max_slots);
                 const Counters h = R->run(segs);
                 (void)h;
                 for (size_t i = 0; i < running.size(); ++i) {
