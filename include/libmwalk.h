@@ -122,7 +122,8 @@ typedef struct {
  * hits_cat + out_off[c] (device).  Results are bit-identical to calling
  * mw_transition(eps_c, n_c, lattice, n_walks[c], 0, seed, c, ...) per cube,
  * for every tuning.  eps_off, n_cells, n_walks, out_off are host arrays.
- * tune may be NULL (autotuned per lattice size; see mw_autotune).
+ * tune may be NULL (the setting mw_autotune_batch found for a batch of the
+ * same shape, else defaults).
  * Stream-ordered; the host arrays may be reused once the call returns.      */
 mw_status mw_transition_batch(int32_t n_cubes, const float* eps_cat,
                               const int64_t* eps_off, const int32_t* n_cells,
@@ -130,6 +131,36 @@ mw_status mw_transition_batch(int32_t n_cubes, const float* eps_cat,
                               const int64_t* out_off, uint64_t seed,
                               int32_t* hits_cat, int32_t* steps_cat,
                               const mw_tune* tune, void* stream);
+
+/* Autotuner of the batched launch: times the batch's walk kernel under
+ * candidate tunings (tile form, waves per workgroup, refill interval, walks
+ * per work item; coordinate search) and writes the fastest to *best.  Later
+ * mw_transition_batch calls with tune == NULL on a batch of the same shape
+ * (cube-size histogram and walk-count scale) use it.  Writes hits/steps as a
+ * side effect (with an internal seed).  Synchronous.                        */
+mw_status mw_autotune_batch(int32_t n_cubes, const float* eps_cat,
+                            const int64_t* eps_off, const int32_t* n_cells,
+                            int32_t lattice, const uint64_t* n_walks,
+                            const int64_t* out_off, int32_t* hits_cat,
+                            int32_t* steps_cat, mw_tune* best, void* stream);
+
+/* A batch prepared once (cube descriptors, work items, table buffers) and
+ * captured as a HIP graph (counter reset, table preparation, walk kernels).
+ * mw_batch_plan_run replays it on `stream` with a new seed; results equal
+ * mw_transition_batch with the same arguments and seed.  The plan keeps the
+ * device pointers given at creation: eps_cat may change between runs (its
+ * values must stay in [1e-3, 1e3]; the range is checked at creation only),
+ * outputs are rewritten by every run.  Runs on one plan are serialised by the
+ * plan (each run waits for the previous run's seed upload).                */
+typedef struct mw_batch_plan mw_batch_plan;
+mw_status mw_batch_plan_create(int32_t n_cubes, const float* eps_cat,
+                               const int64_t* eps_off, const int32_t* n_cells,
+                               int32_t lattice, const uint64_t* n_walks,
+                               const int64_t* out_off, int32_t* hits_cat,
+                               int32_t* steps_cat, const mw_tune* tune,
+                               mw_batch_plan** out);
+mw_status mw_batch_plan_run(mw_batch_plan* plan, uint64_t seed, void* stream);
+mw_status mw_batch_plan_destroy(mw_batch_plan* plan);
 
 /* ------------------------------------------------------------------------
  * Geometry (Alg. 1 input: a 3-D structure of conductors and dielectrics).

@@ -36,6 +36,8 @@ class MWError(RuntimeError):
 
 _lib.mw_last_error.restype = ctypes.c_char_p
 _lib.mw_structure_create.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+_lib.mw_batch_plan_run.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+_lib.mw_batch_plan_destroy.argtypes = [ctypes.c_void_p]
 _lib.mw_structure_destroy.argtypes = [ctypes.c_void_p]
 
 
@@ -132,6 +134,86 @@ def mw_transition_batch(eps_list, walks, lattice=MW_LATTICE_VERTEX, seed=0, tune
         out_off.ctypes.data_as(ctypes.c_void_p), U64(seed), _ptr(hits), _ptr(steps),
         ctypes.byref(t) if t is not None else None, _stream(stream)))
     return hits[:total], (steps[:total] if steps is not None else None), out_off
+
+
+def _batch_arrays(eps_list, walks, device, packed):
+    eps_cat, ns, eps_off = packed if packed is not None else pack_cubes(eps_list, device)
+    walks = np.asarray(walks, dtype=np.uint64)
+    out_off = np.zeros(len(ns), dtype=np.int64)
+    if len(ns):
+        out_off[1:] = np.cumsum(walks.astype(np.int64))[:-1]
+    return eps_cat, ns, eps_off, walks, out_off
+
+
+def _vp(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def mw_autotune_batch(eps_list, walks, lattice=MW_LATTICE_VERTEX, device="cuda", packed=None,
+                      stream=None):
+    """Times candidate launch settings on this batch; returns the fastest as a
+    dict (also remembered for later untuned batches of the same shape)."""
+    import torch
+    eps_cat, ns, eps_off, walks, out_off = _batch_arrays(eps_list, walks, device, packed)
+    total = int(walks.sum())
+    hits = torch.empty(max(total, 1), dtype=torch.int32, device=eps_cat.device)
+    steps = torch.empty(max(total, 1), dtype=torch.int32, device=eps_cat.device)
+    best = mw_tune()
+    _check(_lib.mw_autotune_batch(I32(len(ns)), _ptr(eps_cat), _vp(eps_off), _vp(ns), I32(lattice),
+                                  _vp(walks), _vp(out_off), _ptr(hits), _ptr(steps),
+                                  ctypes.byref(best), _stream(stream)))
+    return {k: int(getattr(best, k)) for k, _ in mw_tune._fields_}
+
+
+class BatchPlan:
+    """mw_batch_plan_*: a batch captured as a HIP graph, replayed per seed."""
+
+    def __init__(self, eps_list, walks, lattice=MW_LATTICE_VERTEX, tune=None, device="cuda",
+                 packed=None, want_steps=True):
+        import torch
+        self.eps_cat, ns, eps_off, walks, self.out_off = _batch_arrays(eps_list, walks, device, packed)
+        total = int(walks.sum())
+        self.hits = torch.empty(max(total, 1), dtype=torch.int32, device=self.eps_cat.device)
+        self.steps = (torch.empty(max(total, 1), dtype=torch.int32, device=self.eps_cat.device)
+                      if want_steps else None)
+        self.total = total
+        t = None
+        if tune is not None:
+            t = mw_tune(*[int(tune.get(k, 0)) for k in ("tile_form", "waves_per_wg", "refill_every",
+                                                        "item_walks")])
+        h = ctypes.c_void_p()
+        _check(_lib.mw_batch_plan_create(I32(len(ns)), _ptr(self.eps_cat), _vp(eps_off), _vp(ns),
+                                         I32(lattice), _vp(walks), _vp(self.out_off), _ptr(self.hits),
+                                         _ptr(self.steps), ctypes.byref(t) if t is not None else None,
+                                         ctypes.byref(h)))
+        self.handle = h
+
+    def run(self, seed, stream=None):
+        _check(_lib.mw_batch_plan_run(self.handle, U64(seed), _stream(stream)))
+        return self.hits[:self.total], (self.steps[:self.total] if self.steps is not None else None)
+
+    def close(self):
+        if self.handle:
+            _check(_lib.mw_batch_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mw_batch_plan_create(eps_list, walks, **kw):
+    return BatchPlan(eps_list, walks, **kw)
+
+
+def mw_batch_plan_run(plan, seed, stream=None):
+    return plan.run(seed, stream)
+
+
+def mw_batch_plan_destroy(plan):
+    plan.close()
 
 
 # ---------------------------------------------------------------------------

@@ -20,6 +20,10 @@
 //   3 thresholds as form 1, read from global memory (cubes too large for
 //     LDS).
 #include <algorithm>
+#include <cmath>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -295,9 +299,11 @@ __device__ void run_item(const CubeDev& C, const uint32_t* tab, uint64_t wb, uin
 
 __global__ void __launch_bounds__(1024) walk_kernel(const CubeDev* __restrict__ cubes, const Item* __restrict__ items,
                                                     int32_t n_items, uint64_t item_walks, int32_t* item_counter,
-                                                    uint32_t k0, uint32_t k1, int32_t groups_per_refill,
-                                                    unsigned long long* step_total) {
+                                                    const unsigned long long* __restrict__ seed_dev,
+                                                    int32_t groups_per_refill, unsigned long long* step_total) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    const unsigned long long seed = *seed_dev;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     __shared__ int32_t s_item;
     __shared__ uint32_t s_next;
     int cur_cube = -1;
@@ -339,6 +345,21 @@ __global__ void __launch_bounds__(1024) walk_kernel(const CubeDev* __restrict__ 
     // device-counted micro-steps
     for (int off = 32; off > 0; off >>= 1) my_steps += __shfl_down(my_steps, off);
     if ((threadIdx.x & 63) == 0 && my_steps) atomicAdd(step_total, my_steps);
+}
+
+// Clears the per-launch counters (a kernel, so that launches captured in a
+// graph need no memset nodes).
+__global__ void reset_kernel(int* bad, unsigned long long* step_total, int32_t* item_counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *bad = 0;
+        *step_total = 0ull;
+        *item_counter = 0;
+    }
+}
+
+// Writes the seed into device memory (single-cube path).
+__global__ void seed_kernel(unsigned long long* seed_dev, unsigned long long seed) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *seed_dev = seed;
 }
 
 // -------------------------------------------------------------------------
@@ -451,6 +472,7 @@ extern "C" mw_status mw_transition(const float* eps, int32_t n_cells, int32_t la
         int* bad = (int*)scratch;
         unsigned long long* step_total = (unsigned long long*)(scratch + 8);
         int32_t* item_counter = (int32_t*)(scratch + 16);
+        unsigned long long* seed_dev = (unsigned long long*)(scratch + 24);
         CubeDev* dcube = (CubeDev*)(scratch + 64);
         CubeDev C{};
         C.eps = eps;
@@ -492,31 +514,50 @@ extern "C" mw_status mw_transition(const float* eps, int32_t n_cells, int32_t la
         const size_t lds = p.form == FORM_TGLOBAL ? 16 : (size_t)p.table_words * 4;
         const int blocks = (int)std::min<int64_t>(n_items, (int64_t)cus * blocks_per_cu(lds));
         allow_large_lds();
-        walk_kernel<<<blocks, threads, lds, st>>>(dcube, nullptr, (int32_t)n_items, iw, item_counter,
-                                                   (uint32_t)seed, (uint32_t)(seed >> 32), L.groups, step_total);
+        seed_kernel<<<1, 1, 0, st>>>(seed_dev, seed);
+        walk_kernel<<<blocks, threads, lds, st>>>(dcube, nullptr, (int32_t)n_items, iw, item_counter, seed_dev,
+                                                   L.groups, step_total);
         MW_HIP(hipGetLastError());
         MW_HIP(hipFreeAsync(scratch, st));
     });
 }
 
-extern "C" mw_status mw_transition_batch(int32_t n_cubes, const float* eps_cat, const int64_t* eps_off,
-                                         const int32_t* n_cells, int32_t lattice, const uint64_t* n_walks,
-                                         const int64_t* out_off, uint64_t seed, int32_t* hits_cat,
-                                         int32_t* steps_cat, const mw_tune* tune, void* stream) {
-    return guarded([&] {
-        MW_REQUIRE(n_cubes >= 0, MW_EINVAL, "n_cubes < 0");
-        MW_REQUIRE(n_cubes <= 65535, MW_ELIMIT, "at most 65535 cubes per batch (got %d)", n_cubes);
-        if (n_cubes == 0) return;
-        MW_REQUIRE(eps_cat && eps_off && n_cells && n_walks && out_off && hits_cat, MW_EINVAL,
-                   "null argument to mw_transition_batch");
-        hipStream_t st = (hipStream_t)stream;
-        const Launch L = default_launch(tune, 0);
-        const int threads = 64 * L.waves;
+namespace mw {
+namespace {
+
+// Device state of one batch: cube descriptors, work items (cubes in
+// decreasing cost n^2 * walks, each cube's walk ranges contiguous), prepared
+// tables and counters.  enqueue() issues reset + prep + walk kernels only, so
+// the sequence can be captured in a graph and replayed.
+struct BatchState {
+    int n_cubes = 0;
+    Launch L{};
+    int threads = 0, blocks = 0;
+    size_t lds = 0;
+    uint32_t n_items = 0;
+    uint64_t total_walks = 0;
+    char* scratch = nullptr;
+    int* bad = nullptr;
+    unsigned long long* step_total = nullptr;
+    int32_t* item_counter = nullptr;
+    unsigned long long* seed_dev = nullptr;
+    CubeDev* dcubes = nullptr;
+    Item* ditems = nullptr;
+
+    BatchState() = default;
+    BatchState(const BatchState&) = delete;
+    ~BatchState() { dev_free(scratch); }
+
+    void build(int32_t n, const float* eps_cat, const int64_t* eps_off, const int32_t* n_cells, int32_t lattice,
+               const uint64_t* n_walks, const int64_t* out_off, int32_t* hits_cat, int32_t* steps_cat,
+               const mw_tune* tune) {
+        n_cubes = n;
+        L = default_launch(tune, 0);
+        threads = 64 * L.waves;
         const int want_form = tune ? tune->tile_form : 0;
         std::vector<CubeDev> cubes(n_cubes);
         std::vector<Plan> plans(n_cubes);
         size_t table_total = 0;
-        uint64_t total_walks = 0;
         uint32_t max_lds_words = 4;
         for (int c = 0; c < n_cubes; ++c) {
             validate_cube(n_cells[c], lattice);
@@ -526,31 +567,29 @@ extern "C" mw_status mw_transition_batch(int32_t n_cubes, const float* eps_cat, 
             total_walks += n_walks[c];
             if (plans[c].form != FORM_TGLOBAL) max_lds_words = std::max(max_lds_words, plans[c].table_words);
         }
-        // order cubes by cost (n^2 * walks), largest first; items contiguous per cube
         std::vector<int> order(n_cubes);
         for (int c = 0; c < n_cubes; ++c) order[c] = c;
-        std::sort(order.begin(), order.end(), [&](int a, int b) {
-            double ca = (double)n_cells[a] * n_cells[a] * n_walks[a], cb = (double)n_cells[b] * n_cells[b] * n_walks[b];
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            const double ca = (double)n_cells[a] * n_cells[a] * n_walks[a];
+            const double cb = (double)n_cells[b] * n_cells[b] * n_walks[b];
             return ca > cb;
         });
-        uint64_t iw = L.item_walks ? L.item_walks : (uint64_t)threads * 16;
+        const uint64_t iw = L.item_walks ? L.item_walks : (uint64_t)threads * 16;
         std::vector<Item> items;
         for (int c : order)
             for (uint64_t w = 0; w < n_walks[c]; w += iw) items.push_back(Item{c, 0, w, std::min(w + iw, n_walks[c])});
         MW_REQUIRE(items.size() < (1ull << 31), MW_ELIMIT, "too many work items");
+        n_items = (uint32_t)items.size();
         const size_t hdr = 256;
         const size_t cubes_bytes = (sizeof(CubeDev) * n_cubes + 255) / 256 * 256;
-        const size_t items_bytes = (sizeof(Item) * items.size() + 255) / 256 * 256;
-        char* scratch = (char*)dev_alloc(hdr + cubes_bytes + items_bytes + table_total + 256);
-        struct Guard {
-            char* p;
-            ~Guard() { dev_free(p); }
-        } guard{scratch};
-        int* bad = (int*)scratch;
-        unsigned long long* step_total = (unsigned long long*)(scratch + 8);
-        int32_t* item_counter = (int32_t*)(scratch + 16);
-        CubeDev* dcubes = (CubeDev*)(scratch + hdr);
-        Item* ditems = (Item*)(scratch + hdr + cubes_bytes);
+        const size_t items_bytes = (sizeof(Item) * std::max<size_t>(items.size(), 1) + 255) / 256 * 256;
+        scratch = (char*)dev_alloc(hdr + cubes_bytes + items_bytes + table_total + 256);
+        bad = (int*)scratch;
+        step_total = (unsigned long long*)(scratch + 8);
+        item_counter = (int32_t*)(scratch + 16);
+        seed_dev = (unsigned long long*)(scratch + 24);
+        dcubes = (CubeDev*)(scratch + hdr);
+        ditems = (Item*)(scratch + hdr + cubes_bytes);
         char* tables = scratch + hdr + cubes_bytes + items_bytes;
         size_t toff = 0;
         for (int c = 0; c < n_cubes; ++c) {
@@ -573,22 +612,223 @@ extern "C" mw_status mw_transition_batch(int32_t n_cubes, const float* eps_cat, 
             const int cen = lattice == MW_LATTICE_VERTEX ? n_cells[c] / 2 : (n_cells[c] - 1) / 2 + 1;
             C.start = cen * (p.P * p.P + p.P + 1);
         }
-        MW_HIP(hipMemsetAsync(scratch, 0, 64, st));
-        MW_HIP(hipMemcpyAsync(dcubes, cubes.data(), sizeof(CubeDev) * n_cubes, hipMemcpyHostToDevice, st));
-        MW_HIP(hipMemcpyAsync(ditems, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, st));
+        MW_HIP(hipMemcpy(dcubes, cubes.data(), sizeof(CubeDev) * n_cubes, hipMemcpyHostToDevice));
+        if (!items.empty())
+            MW_HIP(hipMemcpy(ditems, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
+        lds = (size_t)max_lds_words * 4;
+        blocks = (int)std::max<size_t>(1, std::min<size_t>(items.size(), (size_t)num_cus() * blocks_per_cu(lds)));
+        allow_large_lds();
+    }
+
+    // reset + prep + walk; the seed is read from seed_dev
+    void enqueue(hipStream_t st, bool with_walk = true) const {
+        reset_kernel<<<1, 1, 0, st>>>(bad, step_total, item_counter);
         prep_kernel<<<dim3(64, n_cubes), 256, 0, st>>>(dcubes, bad);
-        MW_HIP(hipGetLastError());
+        if (with_walk && n_items)
+            walk_kernel<<<blocks, threads, lds, st>>>(dcubes, ditems, (int32_t)n_items, 0, item_counter, seed_dev,
+                                                       L.groups, step_total);
+    }
+};
+
+void check_batch_args(int32_t n_cubes, const float* eps_cat, const int64_t* eps_off, const int32_t* n_cells,
+                      const uint64_t* n_walks, const int64_t* out_off, int32_t* hits_cat) {
+    MW_REQUIRE(n_cubes >= 0, MW_EINVAL, "n_cubes < 0");
+    MW_REQUIRE(n_cubes <= 65535, MW_ELIMIT, "at most 65535 cubes per batch (got %d)", n_cubes);
+    if (n_cubes == 0) return;
+    MW_REQUIRE(eps_cat && eps_off && n_cells && n_walks && out_off && hits_cat, MW_EINVAL,
+               "null argument to a batch call");
+}
+
+// Tuned launch settings keyed by the batch's shape (cube-size histogram and
+// walk-count scale); filled by mw_autotune_batch.
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, mw_tune> g_tuned;
+
+std::vector<int64_t> batch_signature(int32_t n_cubes, const int32_t* n_cells, const uint64_t* n_walks,
+                                     int32_t lattice) {
+    std::vector<int64_t> sig(18, 0);
+    sig[0] = lattice;
+    uint64_t tot = 0;
+    for (int c = 0; c < n_cubes; ++c) {
+        sig[1 + std::min(15, n_cells[c] / 4)] += 1;
+        tot += n_walks[c];
+    }
+    sig[17] = (int64_t)std::log2((double)tot + 1.0);
+    for (int b = 1; b <= 16; ++b) sig[b] = (int64_t)std::log2((double)sig[b] + 1.0);
+    return sig;
+}
+
+}  // namespace
+}  // namespace mw
+
+using namespace mw;
+
+extern "C" mw_status mw_transition_batch(int32_t n_cubes, const float* eps_cat, const int64_t* eps_off,
+                                         const int32_t* n_cells, int32_t lattice, const uint64_t* n_walks,
+                                         const int64_t* out_off, uint64_t seed, int32_t* hits_cat,
+                                         int32_t* steps_cat, const mw_tune* tune, void* stream) {
+    return guarded([&] {
+        check_batch_args(n_cubes, eps_cat, eps_off, n_cells, n_walks, out_off, hits_cat);
+        if (n_cubes == 0) return;
+        hipStream_t st = (hipStream_t)stream;
+        mw_tune tuned{};
+        if (!tune) {
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            auto it = g_tuned.find(batch_signature(n_cubes, n_cells, n_walks, lattice));
+            if (it != g_tuned.end()) {
+                tuned = it->second;
+                tune = &tuned;
+            }
+        }
+        BatchState B;
+        B.build(n_cubes, eps_cat, eps_off, n_cells, lattice, n_walks, out_off, hits_cat, steps_cat, tune);
+        seed_kernel<<<1, 1, 0, st>>>(B.seed_dev, seed);
+        B.enqueue(st, false);
         int h_bad = 0;
-        MW_HIP(hipMemcpyAsync(&h_bad, bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
+        MW_HIP(hipMemcpyAsync(&h_bad, B.bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
         MW_HIP(hipStreamSynchronize(st));
         MW_REQUIRE(!h_bad, MW_EINVAL, "permittivity outside [1e-3, 1e3]");
-        const size_t lds = (size_t)max_lds_words * 4;
-        const int cus = num_cus();
-        const int blocks = (int)std::min<size_t>(items.size(), (size_t)cus * blocks_per_cu(lds));
-        allow_large_lds();
-        walk_kernel<<<blocks, threads, lds, st>>>(dcubes, ditems, (int32_t)items.size(), 0, item_counter,
-                                                   (uint32_t)seed, (uint32_t)(seed >> 32), L.groups, step_total);
+        if (B.n_items)
+            walk_kernel<<<B.blocks, B.threads, B.lds, st>>>(B.dcubes, B.ditems, (int32_t)B.n_items, 0, B.item_counter,
+                                                             B.seed_dev, B.L.groups, B.step_total);
         MW_HIP(hipGetLastError());
         MW_HIP(hipStreamSynchronize(st));
+    });
+}
+
+extern "C" mw_status mw_autotune_batch(int32_t n_cubes, const float* eps_cat, const int64_t* eps_off,
+                                       const int32_t* n_cells, int32_t lattice, const uint64_t* n_walks,
+                                       const int64_t* out_off, int32_t* hits_cat, int32_t* steps_cat,
+                                       mw_tune* best, void* stream) {
+    return guarded([&] {
+        check_batch_args(n_cubes, eps_cat, eps_off, n_cells, n_walks, out_off, hits_cat);
+        MW_REQUIRE(best, MW_EINVAL, "null output");
+        *best = mw_tune{0, 16, 8, 0};
+        if (n_cubes == 0) return;
+        hipStream_t st = (hipStream_t)stream;
+        hipEvent_t e0, e1;
+        MW_HIP(hipEventCreate(&e0));
+        MW_HIP(hipEventCreate(&e1));
+        struct EG {
+            hipEvent_t a, b;
+            ~EG() {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+            }
+        } eg{e0, e1};
+        auto time_of = [&](const mw_tune& t) {
+            BatchState B;
+            B.build(n_cubes, eps_cat, eps_off, n_cells, lattice, n_walks, out_off, hits_cat, steps_cat, &t);
+            seed_kernel<<<1, 1, 0, st>>>(B.seed_dev, 0x5eedull);
+            B.enqueue(st, false);
+            int h_bad = 0;
+            MW_HIP(hipMemcpyAsync(&h_bad, B.bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
+            MW_HIP(hipStreamSynchronize(st));
+            MW_REQUIRE(!h_bad, MW_EINVAL, "permittivity outside [1e-3, 1e3]");
+            float best_ms = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                reset_kernel<<<1, 1, 0, st>>>(B.bad, B.step_total, B.item_counter);
+                MW_HIP(hipEventRecord(e0, st));
+                walk_kernel<<<B.blocks, B.threads, B.lds, st>>>(B.dcubes, B.ditems, (int32_t)B.n_items, 0,
+                                                                 B.item_counter, B.seed_dev, B.L.groups, B.step_total);
+                MW_HIP(hipEventRecord(e1, st));
+                MW_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                MW_HIP(hipEventElapsedTime(&ms, e0, e1));
+                best_ms = std::min(best_ms, ms);
+            }
+            return best_ms;
+        };
+        // coordinate search: tile form, waves per workgroup, refill interval,
+        // walks per work item
+        mw_tune cur{0, 16, 8, 0};
+        float cur_ms = time_of(cur);
+        auto try_set = [&](int field, const std::vector<int>& vals) {
+            for (int v : vals) {
+                mw_tune t = cur;
+                int* f = field == 0 ? &t.tile_form : field == 1 ? &t.waves_per_wg : field == 2 ? &t.refill_every : &t.item_walks;
+                if (*f == v) continue;
+                *f = v;
+                const float ms = time_of(t);
+                if (ms < cur_ms) {
+                    cur_ms = ms;
+                    cur = t;
+                }
+            }
+        };
+        try_set(0, {2});
+        try_set(1, {4, 8});
+        try_set(2, {4, 16});
+        const int thr = 64 * cur.waves_per_wg;
+        try_set(3, {thr * 4, thr * 64});
+        *best = cur;
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tuned[batch_signature(n_cubes, n_cells, n_walks, lattice)] = cur;
+    });
+}
+
+// A batch captured once as a graph of (reset, prep, walk) kernels and
+// replayed with a new seed per run.
+struct mw_batch_plan {
+    BatchState B;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long* seed_host = nullptr;
+    ~mw_batch_plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (seed_host) (void)hipHostFree(seed_host);
+    }
+};
+
+extern "C" mw_status mw_batch_plan_create(int32_t n_cubes, const float* eps_cat, const int64_t* eps_off,
+                                          const int32_t* n_cells, int32_t lattice, const uint64_t* n_walks,
+                                          const int64_t* out_off, int32_t* hits_cat, int32_t* steps_cat,
+                                          const mw_tune* tune, mw_batch_plan** out) {
+    return guarded([&] {
+        MW_REQUIRE(out, MW_EINVAL, "null output handle");
+        check_batch_args(n_cubes, eps_cat, eps_off, n_cells, n_walks, out_off, hits_cat);
+        MW_REQUIRE(n_cubes > 0, MW_EINVAL, "empty batch");
+        auto P = std::make_unique<mw_batch_plan>();
+        P->B.build(n_cubes, eps_cat, eps_off, n_cells, lattice, n_walks, out_off, hits_cat, steps_cat, tune);
+        // validate the permittivities once, eagerly
+        hipStream_t st = nullptr;
+        MW_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        struct SG {
+            hipStream_t s;
+            ~SG() { (void)hipStreamDestroy(s); }
+        } sg{st};
+        P->B.enqueue(st, false);
+        int h_bad = 0;
+        MW_HIP(hipMemcpyAsync(&h_bad, P->B.bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
+        MW_HIP(hipStreamSynchronize(st));
+        MW_REQUIRE(!h_bad, MW_EINVAL, "permittivity outside [1e-3, 1e3]");
+        MW_HIP(hipHostMalloc((void**)&P->seed_host, sizeof(unsigned long long), hipHostMallocDefault));
+        MW_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        P->B.enqueue(st, true);
+        MW_HIP(hipStreamEndCapture(st, &P->graph));
+        MW_HIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+        *out = P.release();
+    });
+}
+
+extern "C" mw_status mw_batch_plan_run(mw_batch_plan* P, uint64_t seed, void* stream) {
+    return guarded([&] {
+        MW_REQUIRE(P, MW_EINVAL, "null plan");
+        hipStream_t st = (hipStream_t)stream;
+        // the previous run's copy of the seed must have completed before the
+        // pinned word is rewritten
+        MW_HIP(hipStreamSynchronize(st));
+        *P->seed_host = seed;
+        MW_HIP(hipMemcpyAsync(P->B.seed_dev, P->seed_host, sizeof(unsigned long long), hipMemcpyHostToDevice, st));
+        MW_HIP(hipGraphLaunch(P->exec, st));
+    });
+}
+
+extern "C" mw_status mw_batch_plan_destroy(mw_batch_plan* P) {
+    return guarded([&] {
+        if (!P) return;
+        (void)hipDeviceSynchronize();
+        delete P;
     });
 }

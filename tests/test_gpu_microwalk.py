@@ -153,3 +153,34 @@ def test_c3_full_size_sampled(mw, oracle_lib):
         assert (h[off[c]:off[c] + k].cpu().numpy() == ho).all(), c
         assert (s[off[c]:off[c] + k].cpu().numpy() == so).all(), c
     assert int(h.min()) >= 0
+
+
+def test_autotune_keeps_results(mw, oracle_lib):
+    """The autotuned setting changes only scheduling: hits stay bit-exact."""
+    cubes, walks = _batch_cubes(20, 909)
+    best = mw.mw_autotune_batch(cubes, walks)
+    print("autotuned", best)
+    assert best["waves_per_wg"] in (4, 8, 16)
+    h, s, off = mw.mw_transition_batch(cubes, walks, seed=4)  # uses the tuned setting
+    h, s = h.cpu().numpy(), s.cpu().numpy()
+    for c, (e, w) in enumerate(zip(cubes, walks)):
+        ho, so = oracle_lib.microwalk(e, 0, w, seed=4, cube_index=c)
+        assert (h[off[c]:off[c] + w] == ho).all() and (s[off[c]:off[c] + w] == so).all()
+
+
+def test_graph_plan_replays(mw):
+    """Graph replays with new seeds, interleaved with eager work, each equal
+    to the eager batch call with the same seed."""
+    import torch
+    cubes, walks = _batch_cubes(16, 77)
+    plan = mw.BatchPlan(cubes, walks)
+    x = torch.randn(1 << 20, device="cuda")
+    for rep, seed in enumerate([11, 12, 11, 13]):
+        hp, sp = plan.run(seed)
+        hp, sp = hp.clone(), sp.clone()
+        torch.cuda.synchronize()
+        he, se, _ = mw.mw_transition_batch(cubes, walks, seed=seed)
+        x = x * 1.0001 + rep  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(hp, he) and torch.equal(sp, se), (rep, seed)
+    plan.close()
