@@ -16,6 +16,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -67,6 +69,94 @@ def cpu_baseline(st, walks, seed):
                                                                 r["stats"]["micro_steps"] / dt)}
 
 
+def batched_vs_plain(mw, W, reps=5):
+    """4096-cube batched MicroWalk workload: autotuned graph replay of one
+    persistent launch vs one launch per cube, same walks and seed."""
+    import torch
+    cubes = W.c3_cubes()
+    eps = [c for c, _ in cubes]
+    walks = [w for _, w in cubes]
+    packed = mw.pack_cubes(eps)
+    best = mw.mw_autotune_batch(None, walks, packed=packed)
+    plan = mw.BatchPlan(None, walks, packed=packed, tune=best)
+    plan.run(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(reps):
+        h, st = plan.run(100 + k)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    steps = int(st.sum(dtype=torch.int64))
+    total = int(sum(walks))
+    eps_cat, ns, eoff = packed
+    off = np.concatenate([[0], np.cumsum(walks)[:-1]]).astype(np.int64)
+    hp = torch.empty(total, dtype=torch.int32, device="cuda")
+    sp = torch.empty(total, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(len(walks)):
+        n = int(ns[c])
+        e = eps_cat[int(eoff[c]):int(eoff[c]) + n ** 3].view(n, n, n)
+        mw.mw_transition(e, walks[c], seed=100 + reps - 1, cube_index=c,
+                         hits=hp[off[c]:off[c] + walks[c]], steps=sp[off[c]:off[c] + walks[c]])
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    same = bool(torch.equal(hp, h) and torch.equal(sp, st))
+    plan.close()
+    return {"workload": "4096 cubes, n 8-32, 1-6 inclusions, %d walks, %d micro-steps" % (total, steps),
+            "tune": best, "batched_ms": t_batch * 1e3, "plain_ms": t_plain * 1e3,
+            "batched_micro_steps_per_s": steps / t_batch, "plain_micro_steps_per_s": steps / t_plain,
+            "batched_walks_per_s": total / t_batch, "speedup": t_plain / t_batch,
+            "bit_identical": same,
+            "batched_alu_frac": steps * MW_STEP_SLOTS / t_batch / PEAK_LANE_OPS}
+
+
+def serving(mw, W, n_req=300, load=0.8):
+    """Request stream built like the serving workload (windows of 4-200
+    conductors, budgets 1e5-1e7 walks, Poisson arrivals at load x the serial
+    plain service rate): served with continuous batching vs serial plain
+    extraction (FIFO) on the same GPU."""
+    reqs = W.c5_requests(n_req)
+    service = []
+    for st, m, b, seed in reqs:
+        t0 = time.perf_counter()
+        h = mw.StructureHandle(st)
+        mw.frw_extract(h, m, b, seed=seed)
+        h.close()
+        service.append(time.perf_counter() - t0)
+    service = np.array(service)
+    mu = n_req / service.sum()
+    lam = load * mu
+    rng = np.random.default_rng(55)
+    arr = np.cumsum(rng.exponential(1.0 / lam, n_req))
+    arr -= arr[0]
+    t_free, lat_plain = 0.0, []
+    for a, sv in zip(arr, service):
+        start = max(a, t_free)
+        t_free = start + sv
+        lat_plain.append(t_free - a)
+    walks = float(sum(r[2] for r in reqs))
+    srv = mw.Server(8 << 30)
+    t0 = time.perf_counter()
+    tickets = []
+    for (st, m, b, seed), a in zip(reqs, arr):
+        while time.perf_counter() - t0 < a:
+            time.sleep(0.0002)
+        tickets.append(srv.submit(st, m, b, seed))
+    res = [srv.wait(t) for t in tickets]
+    makespan = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    lat = np.array([r["latency"] for r in res])
+    return {"workload": "%d requests, 4-200 conductors, budgets 1e5-1e7 (%.3g walks), Poisson "
+                        "arrivals at %.1f x serial service rate" % (n_req, walks, load),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "plain_p50_ms": float(np.percentile(lat_plain, 50) * 1e3),
+            "plain_p99_ms": float(np.percentile(lat_plain, 99) * 1e3),
+            "walks_per_s": walks / makespan, "plain_walks_per_s": walks / t_free,
+            "max_concurrent": stats["max_concurrent"], "rounds": stats["rounds"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,8 +164,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--walks", type=int, default=1000000)
     ap.add_argument("--n-cells", type=int, default=16)
-    ap.add_argument("--cpu-walks", type=int, default=60000)
+    ap.add_argument("--cpu-walks", type=int, default=900000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and serving comparisons")
+    ap.add_argument("--serving-requests", type=int, default=300)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU kernels "
@@ -83,7 +175,7 @@ def main():
               "sums; not built).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+
     import torch
 
     import paper_2507_09730_amd as mw
@@ -130,6 +222,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
                      "frac": achieved / peak, "traffic": traffic},
     }
+    if not args.no_extras:
+        out["batched"] = batched_vs_plain(mw, W)
+        out["serving"] = serving(mw, W, args.serving_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(st, args.cpu_walks, seed=7)
     print(json.dumps(out))

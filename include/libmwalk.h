@@ -251,8 +251,9 @@ typedef struct {
  * score_net/score_w (device, walk_budget entries each, or NULL): per-walk net
  * index (n_nets for env) and fp32 weight, indexed by walk - first_walk.
  * stats may be NULL.  Synchronous: returns after the result is on the host.
- * MW_ELIMIT if a cube touched more dielectric regions than the per-cube limit
- * (MW_MAX_REGIONS) supports.                                                */
+ * Transition cubes are the largest conductor-free cubes, halved while they
+ * touch more than MW_MAX_REGIONS dielectric boxes; MW_ELIMIT if more than
+ * MW_MAX_REGIONS dielectric boxes overlap at one point.                     */
 #define MW_MAX_REGIONS 16
 mw_status frw_extract(mw_structure* s, int32_t master, uint64_t walk_budget,
                       uint64_t seed, const frw_options* options,
@@ -263,12 +264,17 @@ mw_status frw_extract(mw_structure* s, int32_t master, uint64_t walk_budget,
  * Serving: a request loop over one device with continuous batching.
  *
  * mw_server_submit copies the structure description and returns a ticket.
- * A worker thread admits queued requests while their device footprint
- * (structure, grid index, per-round walk buffers, accumulators) fits within
- * hbm_budget_bytes, and runs rounds: each round gives every admitted request
- * a share of walks (its next walk ids, from 0) and runs all shares in one
- * set of kernel launches, so requests that arrive while others run join at
- * the next round and their work overlaps on the device.  A request completes
+ * A worker thread admits queued requests in arrival order while their device
+ * footprint (structure, grid index, reduction partials, accumulators) fits
+ * within hbm_budget_bytes, and runs rounds of a fixed walk capacity: the
+ * longest-running admitted request gets up to a quarter of it, the rest goes
+ * to the requests with the fewest remaining walks first; each share is that
+ * request's next walk ids (from 0).  All shares of a round run in one set of
+ * kernel launches, one reduction launch and one result copy, so requests
+ * that arrive while others run join at the next round and their work
+ * overlaps on the device.  The server's own round buffers (per-walk scores
+ * of one round, parked-walk queues; about 0.3 GB) are allocated at the
+ * first round and are not counted in the budget.  A request completes
  * when walk_budget walks have run or options->target_rel_3sigma is met
  * (checked after each of its rounds).  Per-walk results are those of
  * frw_extract(structure, master, walk_budget, seed, options) run alone; rows

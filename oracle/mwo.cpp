@@ -353,6 +353,7 @@ struct Structure {
 
 const double EPS0 = 8.8541878128e-3;  // vacuum permittivity, fF/um
 const int HOP_CAP = 100000;
+const int MAX_BOXES = 16;  // dielectric boxes a transition cube may touch
 
 double box_point_dist(const Box& b, const double p[3]) {
     double d = 0;
@@ -394,6 +395,34 @@ double structure_dist(const Structure& S, const double p[3], int* nearest) {
     }
     if (nearest) *nearest = who;
     return best;
+}
+
+// Number of dielectric boxes touching the cube [c-R, c+R] (faces clipped to
+// the window at symmetry walls).
+int boxes_touching(const Structure& S, const double c[3], double R) {
+    int cnt = 0;
+    for (const Box& b : S.diel) {
+        bool touch = true;
+        for (int a = 0; a < 3; ++a) {
+            double lo = c[a] - R, hi = c[a] + R;
+            if (S.bc[2 * a] == 1) lo = std::max(lo, S.wlo[a]);
+            if (S.bc[2 * a + 1] == 1) hi = std::min(hi, S.whi[a]);
+            if (!(b.lo[a] <= hi && b.hi[a] >= lo)) touch = false;
+        }
+        cnt += touch;
+    }
+    return cnt;
+}
+
+// Cube-size rule (reading of "build the transition cube centred at r"):
+// the largest conductor-free cube, halved while it touches more than
+// MAX_BOXES dielectric boxes.  Returns R <= 0 when no halving helps.
+double cube_half_size(const Structure& S, const double c[3], double R) {
+    for (int it = 0; it < 40; ++it) {
+        if (boxes_touching(S, c, R) <= MAX_BOXES) return R;
+        R *= 0.5;
+    }
+    return -1.0;
 }
 
 // Mirror folding of a coordinate at Neumann window faces.
@@ -750,7 +779,8 @@ bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P
 
     // FirstTransition(r): cube centred on G touching the master.
     int a = F.axis;
-    double R = std::min(structure_dist(S, r, nullptr), G.g);
+    double R = cube_half_size(S, r, std::min(structure_dist(S, r, nullptr), G.g));
+    if (R <= 0) return false;
     Cube C;
     build_cube(S, r, R, n, C);
     int branch, s;
@@ -814,7 +844,9 @@ bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P
             return true;
         }
         st.hops++;
-        build_cube(S, x, d, n, C);
+        const double Rh = cube_half_size(S, x, d);
+        if (Rh <= 0) return false;
+        build_cube(S, x, Rh, n, C);
         st.hop_class[C.cls]++;
         int hb;
         if (P.hybrid && C.cls <= 1) {

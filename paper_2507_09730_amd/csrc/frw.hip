@@ -553,11 +553,20 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
                                      a_norm == 2 ? pl : ub);
         const int cell = grid_cell(S, c);
         int who;
-        const float R = fminf(query_dist(S, c, cell, &who), G.g);
+        float R = fminf(query_dist(S, c, cell, &who), G.g);
         // FirstTransition: cube touching the master (Sec. III-C, Fig. 4
         // branches; homogenised along the normal when not stratified)
-        const CubeInfo I = build_cube(S, cell, c, R, n, L);
-        if (I.overflow) err |= ERR_REGIONS;
+        CubeInfo I = build_cube(S, cell, c, R, n, L);
+        for (int it = 0; it < 40 && I.overflow; ++it) {
+            R *= 0.5f;  // cube-size rule: halve while more than 16 boxes touch
+            I = build_cube(S, cell, c, R, n, L);
+        }
+        if (I.overflow) {
+            err |= ERR_REGIONS;
+            SG.first_done[k] = 1u;
+            SG.first_state[k] = make_float4(c.x, c.y, c.z, 0.f);
+            continue;
+        }
         const float h = 2.f * R / (float)n;
         int br, sax;
         if (I.cls == 0) {
@@ -719,8 +728,17 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                 }
             }
             if (!done) {
-                const CubeInfo I = build_cube(S, cell, c, R, n, L);
-                if (I.overflow) err |= ERR_REGIONS;
+                CubeInfo I = build_cube(S, cell, c, R, n, L);
+                for (int it = 0; it < 40 && I.overflow; ++it) {
+                    R *= 0.5f;  // cube-size rule: halve while more than 16 boxes touch
+                    I = build_cube(S, cell, c, R, n, L);
+                }
+                if (I.overflow) {
+                    // more than 16 boxes overlap at this point: the call fails
+                    err |= ERR_REGIONS;
+                    I.cls = 0;
+                    I.axis = 2;
+                }
                 const float h = 2.f * R / (float)n;
                 {
                     ++c_hops;
@@ -1154,22 +1172,16 @@ __device__ __forceinline__ void neumaier(float& s, float& c, float x) {
     s = t;
 }
 
-__global__ void __launch_bounds__(RED_THREADS) reduce_scores_kernel(const int32_t* __restrict__ net,
-                                                                   const float* __restrict__ w, uint64_t count,
-                                                                   int K, float4* __restrict__ partial) {
-    __shared__ int32_t snet[RED_CHUNK];
-    __shared__ float sw[RED_CHUNK];
-    __shared__ float4 part[RED_THREADS];
-    const uint64_t base = (uint64_t)blockIdx.x * RED_CHUNK;
-    const int len = (int)min((uint64_t)RED_CHUNK, count - base);
+// Block-level compensated sums of one RED_CHUNK slice of walks: per net,
+// the slice is split into `parts` contiguous pieces summed by different
+// threads, then combined in piece order (deterministic).
+__device__ void reduce_chunk(const int32_t* __restrict__ net, const float* __restrict__ w, uint64_t base, int len,
+                             int K, float4* __restrict__ out, int32_t* snet, float* sw, float4* part) {
     for (int q = threadIdx.x; q < len; q += blockDim.x) {
         snet[q] = net[base + q];
         sw[q] = w[base + q];
     }
     __syncthreads();
-    // nets in groups of up to RED_THREADS; each net's entries are split into
-    // `parts` contiguous slices summed by different threads, then combined in
-    // slice order (deterministic)
     for (int j0 = 0; j0 < K; j0 += RED_THREADS) {
         const int kn = min(K - j0, RED_THREADS);
         const int parts = RED_THREADS / kn;
@@ -1197,9 +1209,75 @@ __global__ void __launch_bounds__(RED_THREADS) reduce_scores_kernel(const int32_
                 neumaier(s2, c2, v.z);
                 neumaier(s2, c2, v.w);
             }
-            partial[(size_t)blockIdx.x * K + j0 + t] = make_float4(s1, c1, s2, c2);
+            out[j0 + t] = make_float4(s1, c1, s2, c2);
         }
         __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(RED_THREADS) reduce_scores_kernel(const int32_t* __restrict__ net,
+                                                                   const float* __restrict__ w, uint64_t count,
+                                                                   int K, float4* __restrict__ partial) {
+    __shared__ int32_t snet[RED_CHUNK];
+    __shared__ float sw[RED_CHUNK];
+    __shared__ float4 part[RED_THREADS];
+    const uint64_t base = (uint64_t)blockIdx.x * RED_CHUNK;
+    const int len = (int)min((uint64_t)RED_CHUNK, count - base);
+    reduce_chunk(net, w, base, len, K, partial + (size_t)blockIdx.x * K, snet, sw, part);
+}
+
+// Reduction of a round that served several requests: segment s owns blocks
+// [first_block, first_block + ceil(count / RED_CHUNK)) of the launch.
+struct RedSeg {
+    const int32_t* net;
+    const float* w;
+    unsigned long long count;
+    int32_t K, first_block;
+    float4* partial;
+    double* acc;
+    double n_total;
+    double* out;  // 2K results (row, se) for the host copy
+};
+
+__global__ void __launch_bounds__(RED_THREADS) reduce_multi_kernel(const RedSeg* __restrict__ segs, int n_segs) {
+    __shared__ int32_t snet[RED_CHUNK];
+    __shared__ float sw[RED_CHUNK];
+    __shared__ float4 part[RED_THREADS];
+    int lo = 0, hi = n_segs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].first_block <= (int)blockIdx.x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const RedSeg R = segs[lo];
+    const int local = (int)blockIdx.x - R.first_block;
+    const uint64_t base = (uint64_t)local * RED_CHUNK;
+    if (base >= R.count) return;
+    const int len = (int)min((uint64_t)RED_CHUNK, R.count - base);
+    reduce_chunk(R.net, R.w, base, len, R.K, R.partial + (size_t)local * R.K, snet, sw, part);
+}
+
+__global__ void finish_multi_kernel(const RedSeg* __restrict__ segs) {
+    const RedSeg R = segs[blockIdx.x];
+    const int blocks = (int)((R.count + RED_CHUNK - 1) / RED_CHUNK);
+    const int K = R.K;
+    for (int j = threadIdx.x; j < K; j += blockDim.x) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int b = 0; b < blocks; ++b) {
+            const float4 p = R.partial[(size_t)b * K + j];
+            s1 += (double)p.x + (double)p.y;
+            s2 += (double)p.z + (double)p.w;
+        }
+        s1 += R.acc[j];
+        s2 += R.acc[K + j];
+        R.acc[j] = s1;
+        R.acc[K + j] = s2;
+        const double m = s1 / R.n_total;
+        const double var = (s2 / R.n_total - m * m) / (R.n_total - 1.0);
+        R.out[j] = m;
+        R.out[K + j] = sqrt(var > 0.0 ? var : 0.0);
     }
 }
 
@@ -1787,7 +1865,7 @@ struct Runner {
     }
 
     static void check_errors(const Counters& h) {
-        MW_REQUIRE(!(h.err & ERR_REGIONS), MW_ELIMIT, "a transition cube touched more than %d dielectric regions",
+        MW_REQUIRE(!(h.err & ERR_REGIONS), MW_ELIMIT, "more than %d dielectric boxes overlap at one point",
                    MAX_REGIONS);
         MW_REQUIRE(!(h.err & ERR_TABLE_CAP), MW_ELIMIT, "SGF table cache full (MWALK_TABLE_CAP)");
         MW_REQUIRE(!(h.err & ERR_PARK_CAP), MW_ELIMIT, "parked-walk queue overflow");
@@ -1887,13 +1965,14 @@ struct Extraction {
     uint64_t done = 0;
     std::vector<double> res;
 
-    static size_t bytes(int K, uint64_t chunk_cap) {
+    static size_t bytes(int K, uint64_t chunk_cap, bool chunk_buffers = true) {
         const uint64_t red_blocks = (chunk_cap + RED_CHUNK - 1) / RED_CHUNK;
         return 256 * 12 + sizeof(StructDev) + sizeof(GaussDev) + 16 + sizeof(float4) * red_blocks * K +
-               sizeof(double) * 4 * K + chunk_cap * (4 + 4 + 16 + 4);
+               sizeof(double) * 4 * K + (chunk_buffers ? chunk_cap * (4 + 4 + 16 + 4) : 0);
     }
 
-    Extraction(const mw_structure& st, int master_, double abs_tol_rel, uint64_t chunk_cap_, bool own_scores)
+    Extraction(const mw_structure& st, int master_, double abs_tol_rel, uint64_t chunk_cap_, bool own_scores,
+               bool own_first = true)
         : K(st.n_nets + 1), master(master_), chunk_cap(chunk_cap_) {
         size_t o = 0;
         auto sz = [&](size_t b) {
@@ -1905,7 +1984,8 @@ struct Extraction {
         const size_t o_sd = sz(sizeof(StructDev)), o_G = sz(sizeof(GaussDev)), o_st = sz(16);
         const size_t o_part = sz(sizeof(float4) * red_blocks * K);
         const size_t o_acc = sz(sizeof(double) * 2 * K), o_res = sz(sizeof(double) * 2 * K);
-        const size_t o_fs = sz(sizeof(float4) * chunk_cap), o_fd = sz(sizeof(uint32_t) * chunk_cap);
+        const size_t o_fs = own_first ? sz(sizeof(float4) * chunk_cap) : 0;
+        const size_t o_fd = own_first ? sz(sizeof(uint32_t) * chunk_cap) : 0;
         const size_t o_sn = own_scores ? sz(4 * chunk_cap) : 0, o_sw = own_scores ? sz(4 * chunk_cap) : 0;
         mem = (char*)dev_alloc(o);
         dS = (StructDev*)(mem + o_sd);
@@ -1914,8 +1994,8 @@ struct Extraction {
         partial = (float4*)(mem + o_part);
         acc = (double*)(mem + o_acc);
         result = (double*)(mem + o_res);
-        first_state = (float4*)(mem + o_fs);
-        first_done = (uint32_t*)(mem + o_fd);
+        first_state = own_first ? (float4*)(mem + o_fs) : nullptr;
+        first_done = own_first ? (uint32_t*)(mem + o_fd) : nullptr;
         score_net = own_scores ? (int32_t*)(mem + o_sn) : nullptr;
         score_w = own_scores ? (float*)(mem + o_sw) : nullptr;
         StructDev S = st.h;
@@ -2111,6 +2191,61 @@ struct mw_server {
         st.failed++;
     }
 
+    // buffers of one round, shared by the requests of the round
+    char* rmem = nullptr;
+    int32_t* r_net = nullptr;
+    float* r_w = nullptr;
+    float4* r_fs = nullptr;
+    uint32_t* r_fd = nullptr;
+    RedSeg* r_segs = nullptr;
+    uint64_t r_cap = 0;
+    double* r_out = nullptr;
+    size_t r_out_cap = 0;
+
+    ~mw_server() {
+        dev_free(r_out);
+        dev_free(rmem);
+    }
+
+    void alloc_round_buffers() {
+        r_cap = round_walks + (uint64_t)max_slots * RED_CHUNK;
+        size_t o = 0;
+        auto sz = [&](size_t b) {
+            size_t r = o;
+            o += (b + 255) / 256 * 256;
+            return r;
+        };
+        const size_t o_n = sz(4 * r_cap), o_w = sz(4 * r_cap), o_fs = sz(16 * r_cap), o_fd = sz(4 * r_cap);
+        const size_t o_sg = sz(sizeof(RedSeg) * max_slots);
+        rmem = (char*)dev_alloc(o);
+        r_net = (int32_t*)(rmem + o_n);
+        r_w = (float*)(rmem + o_w);
+        r_fs = (float4*)(rmem + o_fs);
+        r_fd = (uint32_t*)(rmem + o_fd);
+        r_segs = (RedSeg*)(rmem + o_sg);
+    }
+
+    // Walk shares of one round (capacity round_walks): the longest-admitted
+    // request gets up to a quarter, the rest goes to the requests with the
+    // fewest remaining walks first.
+    std::vector<uint64_t> shares(const std::vector<std::shared_ptr<ServerRequest>>& running) const {
+        const size_t m = running.size();
+        std::vector<uint64_t> sh(m, 0), rem(m);
+        for (size_t i = 0; i < m; ++i) rem[i] = running[i]->budget - running[i]->X->done;
+        uint64_t used = std::min<uint64_t>(rem[0], round_walks / 4);
+        sh[0] = used;
+        std::vector<size_t> order(m);
+        for (size_t i = 0; i < m; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return rem[a] < rem[b]; });
+        for (size_t i : order) {
+            if (used >= round_walks) break;
+            const uint64_t take = std::min<uint64_t>(rem[i] - sh[i], round_walks - used);
+            sh[i] += take;
+            used += take;
+        }
+        return sh;
+    }
+
     void loop() {
         (void)hipSetDevice(device);
         std::unique_ptr<Runner> R;
@@ -2147,7 +2282,8 @@ struct mw_server {
                 std::string msg = rc ? mw_last_error() : "";
                 if (rc == MW_OK) {
                     rc = guarded([&] {
-                        r->X = std::make_unique<Extraction>(*r->st, r->master, opt.abs_tol_rel, round_walks, true);
+                        r->X = std::make_unique<Extraction>(*r->st, r->master, opt.abs_tol_rel, round_walks, false,
+                                                            false);
                     });
                     if (rc) msg = mw_last_error();
                 }
@@ -2159,7 +2295,7 @@ struct mw_server {
                     cv.notify_all();
                 } else {
                     // reconcile the reservation with the memory actually held
-                    const size_t actual = r->st->bytes + Extraction::bytes(r->X->K, round_walks);
+                    const size_t actual = r->st->bytes + Extraction::bytes(r->X->K, round_walks, false);
                     std::lock_guard<std::mutex> lk(mu);
                     if (actual > r->footprint) {
                         st.resident_bytes += actual - r->footprint;
@@ -2170,43 +2306,96 @@ struct mw_server {
                 }
             }
             if (running.empty()) continue;
-            // one round: every running request gets an equal share of walks
-            const uint64_t share = std::max<uint64_t>(round_walks / running.size(), MIN_SHARE);
+            // one round over the shares of the running requests
+            const std::vector<uint64_t> sh = shares(running);
+            std::vector<size_t> part;
             std::vector<Segment> segs;
-            uint64_t offset = 0;
-            for (auto& r : running) {
-                r->chunk = std::min<uint64_t>(std::min(share, round_walks), r->budget - r->X->done);
-                Segment sg{};
-                const mw_status rc = guarded([&] {
-                    sg = r->X->segment(opt.first_walk + r->X->done, r->chunk, r->seed, nullptr, nullptr);
-                });
-                (void)rc;
-                sg.offset = offset;
-                offset += r->chunk;
-                segs.push_back(sg);
-            }
+            std::vector<RedSeg> red;
+            uint64_t offset = 0, walks = 0;
+            int blocks = 0;
+            size_t outn = 0;
+            for (size_t i = 0; i < running.size(); ++i)
+                if (sh[i]) outn += 2 * (size_t)running[i]->X->K;
             mw_status rc = guarded([&] {
-                if (!R)
-                    R = std::make_unique<Runner>(opt.n_cells, opt.hybrid,
-                                                 std::max<uint64_t>(round_walks, MIN_SHARE * (uint64_t)max_slots),
-                                                 max_slots);
-                const Counters h = R->run(segs);
-                (void)h;
+                if (!rmem) alloc_round_buffers();
+                if (outn > r_out_cap) {
+                    dev_free(r_out);
+                    r_out = nullptr;
+                    r_out = (double*)dev_alloc(sizeof(double) * outn);
+                    r_out_cap = outn;
+                }
+                size_t out_off = 0;
                 for (size_t i = 0; i < running.size(); ++i) {
-                    running[i]->X->reduce(segs[i]);
-                    running[i]->stats.walks = running[i]->X->done;
+                    if (!sh[i]) continue;
+                    Extraction& X = *running[i]->X;
+                    Segment sg{};
+                    sg.S = X.dS;
+                    sg.G = X.G;
+                    sg.walk_begin = opt.first_walk + X.done;
+                    sg.offset = offset;
+                    sg.count = sh[i];
+                    sg.score_net = r_net + offset;
+                    sg.score_w = r_w + offset;
+                    sg.first_state = r_fs + offset;
+                    sg.first_done = r_fd + offset;
+                    sg.k0 = (uint32_t)running[i]->seed;
+                    sg.k1 = (uint32_t)(running[i]->seed >> 32);
+                    RedSeg rs{};
+                    rs.net = sg.score_net;
+                    rs.w = sg.score_w;
+                    rs.count = sh[i];
+                    rs.K = X.K;
+                    rs.first_block = blocks;
+                    rs.partial = X.partial;
+                    rs.acc = X.acc;
+                    rs.n_total = (double)(X.done + sh[i]);
+                    rs.out = r_out + out_off;
+                    out_off += 2 * (size_t)X.K;
+                    const int nblk = (int)((sh[i] + RED_CHUNK - 1) / RED_CHUNK);
+                    blocks += nblk;
+                    offset += (uint64_t)nblk * RED_CHUNK;  // segments start on reduction blocks
+                    walks += sh[i];
+                    segs.push_back(sg);
+                    red.push_back(rs);
+                    part.push_back(i);
+                }
+                // list indices are dense; the segments' buffers start on
+                // reduction blocks of the round buffers
+                uint64_t dense = 0;
+                for (Segment& sg : segs) {
+                    sg.offset = dense;
+                    dense += sg.count;
+                }
+                MW_HIP(hipMemsetAsync(r_fd, 0, sizeof(uint32_t) * offset, 0));
+                if (!R)
+                    R = std::make_unique<Runner>(opt.n_cells, opt.hybrid, round_walks, max_slots);
+                (void)R->run(segs);
+                MW_HIP(hipMemcpy(r_segs, red.data(), sizeof(RedSeg) * red.size(), hipMemcpyHostToDevice));
+                reduce_multi_kernel<<<blocks, RED_THREADS>>>(r_segs, (int)red.size());
+                finish_multi_kernel<<<(int)red.size(), 256>>>(r_segs);
+                MW_HIP(hipGetLastError());
+                std::vector<double> host(outn);
+                MW_HIP(hipMemcpy(host.data(), r_out, sizeof(double) * outn, hipMemcpyDeviceToHost));
+                size_t o2 = 0;
+                for (size_t q = 0; q < part.size(); ++q) {
+                    Extraction& X = *running[part[q]]->X;
+                    X.done += sh[part[q]];
+                    std::copy(host.begin() + o2, host.begin() + o2 + 2 * X.K, X.res.begin());
+                    o2 += 2 * (size_t)X.K;
+                    running[part[q]]->stats.walks = X.done;
                 }
             });
             std::string msg = rc ? mw_last_error() : "";
             std::lock_guard<std::mutex> lk(mu);
             st.rounds++;
-            st.walks += offset;
-            st.max_concurrent = std::max<uint64_t>(st.max_concurrent, running.size());
+            st.walks += walks;
+            st.max_concurrent = std::max<uint64_t>(st.max_concurrent, part.size());
             std::vector<std::shared_ptr<ServerRequest>> still;
-            for (auto& r : running) {
+            for (size_t i = 0; i < running.size(); ++i) {
+                auto& r = running[i];
                 if (rc != MW_OK) {
                     fail(r, rc, msg);
-                } else if (r->X->done >= r->budget || r->X->converged(opt.target_rel_3sigma)) {
+                } else if (r->X->done >= r->budget || (sh[i] && r->X->converged(opt.target_rel_3sigma))) {
                     const int K = r->X->K;
                     r->row.assign(r->X->res.begin(), r->X->res.begin() + K);
                     r->se.assign(r->X->res.begin() + K, r->X->res.end());
@@ -2235,7 +2424,7 @@ extern "C" mw_status mw_server_create(size_t hbm_budget_bytes, const frw_options
         s->budget = hbm_budget_bytes;
         s->opt = normalised_options(options);
         const LaunchGeom g = launch_geom(s->opt.n_cells);
-        s->round_walks = std::max<uint64_t>(2 * g.pool, 1 << 19);
+        s->round_walks = std::max<uint64_t>(8 * g.pool, 1 << 21);
         mw_server* raw = s.get();
         s->worker = std::thread([raw] { raw->loop(); });
         *out = s.release();
@@ -2267,7 +2456,7 @@ extern "C" mw_status mw_server_submit(mw_server* srv, const mw_structure_desc* D
         const size_t boxes = (size_t)D->n_cond + D->n_diel;
         const size_t cells = (size_t)std::min(262144.0, std::max(64.0, 16.0 * boxes)) * 4;  // grid rounding slack
         r->footprint = boxes * 64 + cells * 16 + cells * 4 * std::min<size_t>(boxes, 64) +
-                       Extraction::bytes(D->n_nets + 1, srv->round_walks) + 64 * 1024;
+                       Extraction::bytes(D->n_nets + 1, srv->round_walks, false) + 64 * 1024;
         r->t_submit = std::chrono::steady_clock::now();
         std::lock_guard<std::mutex> lk(srv->mu);
         MW_REQUIRE(!srv->stop, MW_EINVAL, "server is shutting down");

@@ -60,22 +60,29 @@ def test_mix_equals_alone(mw):
 
 def test_admission_respects_budget(mw):
     reqs = _requests()[:6]
-    # room for about two requests at a time
-    srv = mw.Server(220 << 20)
+    # footprint of one of these requests (all on the same structure)
+    srv = mw.Server(1 << 30)
+    srv.wait(srv.submit(*reqs[0]))
+    one = srv.stats()["max_resident_bytes"]
+    srv.close()
+    # room for two requests at a time
+    budget = int(2.5 * one)
+    srv = mw.Server(budget)
     tickets = [srv.submit(st, m, b, seed) for st, m, b, seed in reqs]
     results = [srv.wait(t) for t in tickets]
     stats = srv.stats()
     srv.close()
-    print("small-budget stats", stats)
+    print("small-budget stats", stats, "one", one)
     assert stats["completed"] == len(reqs)
-    assert stats["max_resident_bytes"] <= 220 << 20
+    assert stats["max_resident_bytes"] <= budget
+    assert stats["max_concurrent"] == 2
     for (st, m, b, seed), r in zip(reqs, results):
         alone = mw.frw_extract(st, m, b, seed=seed)
         assert _same(r, alone)
 
 
 def test_oversized_request_is_rejected(mw):
-    srv = mw.Server(1 << 20)
+    srv = mw.Server(16 << 10)
     t = srv.submit(W.c2_structure(), 0, 100000, 1)
     with pytest.raises(mw.MWError) as e:
         srv.wait(t, timeout=60)
