@@ -111,11 +111,11 @@ def batched_vs_plain(mw, W, reps=5):
             "batched_alu_frac": steps * MW_STEP_SLOTS / t_batch / PEAK_LANE_OPS}
 
 
-def serving(mw, W, n_req=300, load=0.8):
+def serving(mw, W, n_req=300, loads=(0.5, 0.8, 1.2)):
     """Request stream built like the serving workload (windows of 4-200
     conductors, budgets 1e5-1e7 walks, Poisson arrivals at load x the serial
     plain service rate): served with continuous batching vs serial plain
-    extraction (FIFO) on the same GPU."""
+    extraction (FIFO) on the same GPU, at each load."""
     reqs = W.c5_requests(n_req)
     service = []
     for st, m, b, seed in reqs:
@@ -126,35 +126,38 @@ def serving(mw, W, n_req=300, load=0.8):
         service.append(time.perf_counter() - t0)
     service = np.array(service)
     mu = n_req / service.sum()
-    lam = load * mu
-    rng = np.random.default_rng(55)
-    arr = np.cumsum(rng.exponential(1.0 / lam, n_req))
-    arr -= arr[0]
-    t_free, lat_plain = 0.0, []
-    for a, sv in zip(arr, service):
-        start = max(a, t_free)
-        t_free = start + sv
-        lat_plain.append(t_free - a)
     walks = float(sum(r[2] for r in reqs))
-    srv = mw.Server(8 << 30)
-    t0 = time.perf_counter()
-    tickets = []
-    for (st, m, b, seed), a in zip(reqs, arr):
-        while time.perf_counter() - t0 < a:
-            time.sleep(0.0002)
-        tickets.append(srv.submit(st, m, b, seed))
-    res = [srv.wait(t) for t in tickets]
-    makespan = time.perf_counter() - t0
-    stats = srv.stats()
-    srv.close()
-    lat = np.array([r["latency"] for r in res])
-    return {"workload": "%d requests, 4-200 conductors, budgets 1e5-1e7 (%.3g walks), Poisson "
-                        "arrivals at %.1f x serial service rate" % (n_req, walks, load),
+    out = {"workload": "%d requests, 4-200 conductors, budgets 1e5-1e7 (%.3g walks), Poisson "
+                       "arrivals at load x serial plain service rate (%.2f req/s)" % (n_req, walks, mu)}
+    for load in loads:
+        lam = load * mu
+        rng = np.random.default_rng(55)
+        arr = np.cumsum(rng.exponential(1.0 / lam, n_req))
+        arr -= arr[0]
+        t_free, lat_plain = 0.0, []
+        for a, sv in zip(arr, service):
+            start = max(a, t_free)
+            t_free = start + sv
+            lat_plain.append(t_free - a)
+        srv = mw.Server(8 << 30)
+        t0 = time.perf_counter()
+        tickets = []
+        for (st, m, b, seed), a in zip(reqs, arr):
+            while time.perf_counter() - t0 < a:
+                time.sleep(0.0002)
+            tickets.append(srv.submit(st, m, b, seed))
+        res = [srv.wait(t) for t in tickets]
+        makespan = time.perf_counter() - t0
+        stats = srv.stats()
+        srv.close()
+        lat = np.array([r["latency"] for r in res])
+        out["load_%.1f" % load] = {
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "plain_p50_ms": float(np.percentile(lat_plain, 50) * 1e3),
             "plain_p99_ms": float(np.percentile(lat_plain, 99) * 1e3),
             "walks_per_s": walks / makespan, "plain_walks_per_s": walks / t_free,
             "max_concurrent": stats["max_concurrent"], "rounds": stats["rounds"]}
+    return out
 
 
 def main():
@@ -168,6 +171,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and serving comparisons")
     ap.add_argument("--serving-requests", type=int, default=300)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only copy a device buffer of this size 3 times (calibrates the rocprofv3 "
+                         "FETCH_SIZE / WRITE_SIZE counters against a known byte count) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU kernels "
@@ -177,6 +183,17 @@ def main():
 
 
     import torch
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib << 18  # float32 elements
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_per_copy": n * 4, "copies": 3}))
+        return
 
     import paper_2507_09730_amd as mw
     import workloads as W

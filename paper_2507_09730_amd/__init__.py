@@ -327,7 +327,8 @@ def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
     row = (ctypes.c_double * K)()
     se = (ctypes.c_double * K)()
     stats = frw_stats()
-    opt = frw_options(n_cells, hybrid, 0, 0, target_rel_3sigma, abs_tol_rel, first_walk, batch_walks)
+    opt = frw_options(n_cells, hybrid, 0, 0, target_rel_3sigma, abs_tol_rel, first_walk,
+                      batch_walks)
     net = w = None
     if scores:
         net = torch.empty(walk_budget, dtype=torch.int32, device=device)

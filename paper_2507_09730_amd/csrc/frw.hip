@@ -39,7 +39,7 @@ constexpr float EPS0 = 8.8541878128e-3f;  // vacuum permittivity, fF/um
 constexpr uint32_t HOP_CAP = 100000;
 constexpr int MAX_REGIONS = MW_MAX_REGIONS;
 constexpr int FRW_THREADS = 256;   // first-transition kernel
-constexpr int WALK_THREADS = 128;  // walker kernel: small blocks pack the LDS of a CU
+constexpr int WALK_THREADS = 64;   // walker kernel: one-wave blocks pack the LDS of a CU
 constexpr uint32_t KEY_HDR = 4;
 constexpr uint32_t NO_INDEX = 0xffffffffu;
 
@@ -93,8 +93,8 @@ struct Parked {
     float px, py, pz, omega;
     uint32_t t;
     int32_t seg;
-    uint32_t pad[2];
 };
+static_assert(sizeof(Parked) == 32, "Parked moves as two 16-byte vectors");
 
 struct Counters {
     unsigned long long hops, micro_steps, hop_class[3], first_branch[4], env, hop_cap;
@@ -158,6 +158,56 @@ struct FirstArgs {
 };
 
 // -------------------------------------------------------------------------
+// Global-memory views.  Pointers loaded from device structs are generic;
+// reading through them emits flat instructions, which also count against the
+// LDS wait counter, so a wait for an LDS read would stall on every global load
+// in flight.  The walker reads global data through these address-space-1
+// views instead.
+// -------------------------------------------------------------------------
+#define GAS __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const GAS T* gp(const T* p) {
+    return (const GAS T*)p;
+}
+template <class T>
+__device__ __forceinline__ GAS T* gpw(T* p) {
+    return (GAS T*)p;
+}
+using SRef = const GAS StructDev&;
+// float4 is a class type (its copy constructor takes a generic reference), so
+// float4 values move through the builtin vector type.
+typedef float gvec4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ldf4(const float4* p) {
+    const gvec4 v = *(const GAS gvec4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+typedef unsigned int guvec4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ Parked ldpark(const Parked* p) {
+    const GAS guvec4* q = (const GAS guvec4*)p;
+    const guvec4 a = q[0], b = q[1];
+    Parked r;
+    __builtin_memcpy(&r, &a, 16);
+    __builtin_memcpy(reinterpret_cast<char*>(&r) + 16, &b, 16);
+    return r;
+}
+__device__ __forceinline__ void stpark(Parked* p, const Parked& v) {
+    guvec4 a, b;
+    __builtin_memcpy(&a, &v, 16);
+    __builtin_memcpy(&b, reinterpret_cast<const char*>(&v) + 16, 16);
+    GAS guvec4* q = (GAS guvec4*)p;
+    q[0] = a;
+    q[1] = b;
+}
+__device__ __forceinline__ void stf4(float4* p, float4 v) {
+    gvec4 w;
+    w.x = v.x;
+    w.y = v.y;
+    w.z = v.z;
+    w.w = v.w;
+    *(GAS gvec4*)p = w;
+}
+
+// -------------------------------------------------------------------------
 // Geometry helpers.
 // -------------------------------------------------------------------------
 __device__ __forceinline__ float box_dist(float4 lo, float4 hi, float3 p) {
@@ -169,7 +219,7 @@ __device__ __forceinline__ float box_dist(float4 lo, float4 hi, float3 p) {
 
 __device__ __forceinline__ float axis_of(float3 p, int a) { return a == 0 ? p.x : (a == 1 ? p.y : p.z); }
 
-__device__ __forceinline__ int grid_cell(const StructDev& S, float3 p) {
+__device__ __forceinline__ int grid_cell(SRef S, float3 p) {
     int c[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -181,13 +231,13 @@ __device__ __forceinline__ int grid_cell(const StructDev& S, float3 p) {
 
 // Largest conductor-free cube: L-infinity distance to the nearest conductor
 // or grounded window face; nearest = net, or n_nets for a grounded face.
-__device__ float query_dist(const StructDev& S, float3 p, int cell, int* nearest) {
+__device__ float query_dist(SRef S, float3 p, int cell, int* nearest) {
     float best = INFINITY;
     int who = S.n_nets;
-    const uint32_t b = S.gc_off[cell], e = S.gc_off[cell + 1];
+    const uint32_t b = gp(S.gc_off)[cell], e = gp(S.gc_off)[cell + 1];
     for (uint32_t q = b; q < e; ++q) {
-        const uint32_t c = S.gc_list[q];
-        const float4 lo = S.cond_lo[c], hi = S.cond_hi[c];
+        const uint32_t c = gp(S.gc_list)[q];
+        const float4 lo = ldf4(S.cond_lo + c), hi = ldf4(S.cond_hi + c);
         const float d = box_dist(lo, hi, p);
         if (d < best) {
             best = d;
@@ -210,13 +260,13 @@ __device__ float query_dist(const StructDev& S, float3 p, int cell, int* nearest
     return best;
 }
 
-__device__ __forceinline__ float fold(const StructDev& S, int a, float x) {
+__device__ __forceinline__ float fold(SRef S, int a, float x) {
     if (S.bc[2 * a] == MW_BC_NEUMANN && x < S.wlo[a]) x = 2.f * S.wlo[a] - x;
     if (S.bc[2 * a + 1] == MW_BC_NEUMANN && x > S.whi[a]) x = 2.f * S.whi[a] - x;
     return x;
 }
 
-__device__ __forceinline__ float3 fold3(const StructDev& S, float3 p) {
+__device__ __forceinline__ float3 fold3(SRef S, float3 p) {
     return make_float3(fold(S, 0, p.x), fold(S, 1, p.y), fold(S, 2, p.z));
 }
 
@@ -257,7 +307,7 @@ struct CubeInfo {
 // Regions are the dielectric boxes (bits, priority = list order) and the
 // background layers (per-z-cell codes); a region is present when it holds at
 // least one cell centre.
-__device__ CubeInfo build_cube(const StructDev& S, int cell, float3 c, float R, int n, LaneCube L) {
+__device__ CubeInfo build_cube(SRef S, int cell, float3 c, float R, int n, LaneCube L) {
     CubeInfo info{};
     const float h = 2.f * R / (float)n;
     const float lo0[3] = {c.x - R, c.y - R, c.z - R};
@@ -268,18 +318,18 @@ __device__ CubeInfo build_cube(const StructDev& S, int cell, float3 c, float R, 
         const float z = fold(S, 2, lo0[2] + ((float)k + 0.5f) * h);
         int l = 0;
         for (int q = 1; q < S.n_layers; ++q)
-            if (z >= S.layer_z0[q]) l = q;
+            if (z >= gp(S.layer_z0)[q]) l = q;
         lmin = min(lmin, l);
         lmax = max(lmax, l);
-        L.bz[k] = S.layer_code[l];
+        L.bz[k] = gp(S.layer_code)[l];
     }
     info.n_layers = lmax - lmin + 1;
     // dielectric boxes touching the cube, in priority order
     int nbits = 0;
-    const uint32_t b = S.gd_off[cell], e = S.gd_off[cell + 1];
+    const uint32_t b = gp(S.gd_off)[cell], e = gp(S.gd_off)[cell + 1];
     for (uint32_t q = b; q < e; ++q) {
-        const uint32_t id = S.gd_list[q];
-        const float4 blo = S.diel_lo[id], bhi = S.diel_hi[id];
+        const uint32_t id = gp(S.gd_list)[q];
+        const float4 blo = ldf4(S.diel_lo + id), bhi = ldf4(S.diel_hi + id);
         const float bl[3] = {blo.x, blo.y, blo.z}, bh[3] = {bhi.x, bhi.y, bhi.z};
         bool touch = true;
 #pragma unroll
@@ -433,7 +483,7 @@ __device__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t* out_index
     const unsigned long long hh = (unsigned long long)h << 32;
     uint32_t slot = (h * 0x9E3779B1u) & C.slot_mask;
     for (uint32_t probe = 0; probe <= C.slot_mask; ++probe) {
-        unsigned long long cur = __hip_atomic_load(&C.slot[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long cur = __hip_atomic_load(gpw(C.slot) + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cur == 0ull) {
             const unsigned long long old = atomicCAS(&C.slot[slot], 0ull, hh | NO_INDEX);
             if (old == 0ull) {
@@ -452,8 +502,8 @@ __device__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t* out_index
         if ((cur & SLOT_HASH_MASK) == hh) {
             const uint32_t idx = (uint32_t)cur;
             if (idx == NO_INDEX) return LOOKUP_PARK;
-            const uint32_t rdy = __hip_atomic_load(&C.ready[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t* k = C.keys + (size_t)idx * words;
+            const uint32_t rdy = __hip_atomic_load(gpw(C.ready) + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const GAS uint32_t* k = gp(C.keys) + (size_t)idx * words;
             bool same = true;
             for (uint32_t q = 0; q < words; ++q) same &= k[q] == key(q);
             if (same) {
@@ -472,8 +522,8 @@ __device__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t* out_index
 // answer for a word u lies in [guide[u>>24], guide[(u>>24)+1]].
 constexpr uint32_t TAB_GUIDE = 2, TAB_CDF = 2 + 257;
 
-__device__ __forceinline__ int table_sample(const uint32_t* tab, uint32_t nb, uint32_t u) {
-    const uint32_t* cdf = tab + TAB_CDF;
+__device__ __forceinline__ int table_sample(const GAS uint32_t* tab, uint32_t nb, uint32_t u) {
+    const GAS uint32_t* cdf = tab + TAB_CDF;
     const uint32_t g = u >> 24;
     uint32_t lo = tab[TAB_GUIDE + g], hi = tab[TAB_GUIDE + g + 1];
     if (hi < nb) ++hi;  // first b with cdf[b] > u lies in [lo, hi)
@@ -529,11 +579,11 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
     uint32_t err = 0, missing = 0;
     for (unsigned long long g = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; g < A.total;
          g += (unsigned long long)gridDim.x * blockDim.x) {
-        const Segment& SG = A.segs[find_segment(A.segs, A.n_segs, g)];
+        const GAS Segment& SG = gp(A.segs)[find_segment(A.segs, A.n_segs, g)];
         const unsigned long long k = g - SG.offset;
-        if (SG.first_done[k]) continue;
-        const StructDev& S = *SG.S;
-        const GaussDev& G = *SG.G;
+        if (gp(SG.first_done)[k]) continue;
+        SRef S = *gp(SG.S);
+        const GAS GaussDev& G = *gp(SG.G);
         const unsigned long long walk = SG.walk_begin + k;
         // GaussianSurfaceSampling(G): face by area, uniform point on it
         const Rand4 r = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_GAUSS), SG.k0, SG.k1);
@@ -563,8 +613,8 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         }
         if (I.overflow) {
             err |= ERR_REGIONS;
-            SG.first_done[k] = 1u;
-            SG.first_state[k] = make_float4(c.x, c.y, c.z, 0.f);
+            gpw(SG.first_done)[k] = 1u;
+            stf4(SG.first_state + k, make_float4(c.x, c.y, c.z, 0.f));
             continue;
         }
         const float h = 2.f * R / (float)n;
@@ -598,7 +648,7 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
             continue;
         }
         ++c_br[br];
-        const uint32_t* tab = A.cache.data + (size_t)idx * A.cache.tab_words;
+        const GAS uint32_t* tab = gp(A.cache.data) + (size_t)idx * A.cache.tab_words;
         const Rand4 r2 = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_FIRST), SG.k0, SG.k1);
         const int b = table_sample(tab, A.cache.nb, r2.x);
         const uint32_t sb = (tab[TAB_CDF + A.cache.nb + (b >> 5)] >> (b & 31)) & 1u;
@@ -610,8 +660,8 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         node_of_hit(n, b, nd);
         const float3 x = make_float3(c.x - R + (float)nd[0] * h, c.y - R + (float)nd[1] * h, c.z - R + (float)nd[2] * h);
         const float3 xf = fold3(S, x);
-        SG.first_state[k] = make_float4(xf.x, xf.y, xf.z, omega);
-        SG.first_done[k] = 1u;
+        stf4(SG.first_state + k, make_float4(xf.x, xf.y, xf.z, omega));
+        gpw(SG.first_done)[k] = 1u;
     }
     Counters& K = *A.ctr;
     for (int q = 0; q < 4; ++q)
@@ -621,9 +671,135 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
 }
 
 // -------------------------------------------------------------------------
-// Walker kernel: transitions after the first, until absorption.
+// MicroWalk on a lazily described cube (Alg. 3 with the link codes of the
+// eight cells around the current node taken from the per-axis masks).
+// -------------------------------------------------------------------------
+struct MwState {
+    int ni, nj, nk;
+    uint32_t s;  // steps taken
+    uint32_t mx0, mx1, my0, my1, mz0, mz1, bz0, bz1;
+};
+
+__device__ __forceinline__ void mw_begin(MwState& M, LaneCube L, int n) {
+    M.ni = M.nj = M.nk = n / 2;
+    M.s = 0;
+    M.mx0 = L.mask[M.ni - 1];
+    M.mx1 = L.mask[M.ni];
+    M.my0 = L.mask[n + M.nj - 1];
+    M.my1 = L.mask[n + M.nj];
+    M.mz0 = L.mask[2 * n + M.nk - 1];
+    M.mz1 = L.mask[2 * n + M.nk];
+    M.bz0 = L.bz[M.nk - 1];
+    M.bz1 = L.bz[M.nk];
+}
+
+// Up to four steps with the four words of one Philox block; false once the
+// walk has reached a boundary node.
+__device__ __forceinline__ bool mw_block(MwState& M, LaneCube L, int n, const Rand4& r) {
+    const uint32_t us[4] = {r.x, r.y, r.z, r.w};
+    bool alive = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (alive) {
+            uint32_t d;
+            if (M.mx0 == M.mx1 && M.my0 == M.my1 && M.mz0 == M.mz1 && M.bz0 == M.bz1) {
+                d = __umulhi(us[q], 6u);
+            } else {
+                const uint32_t m000 = M.mx0 & M.my0 & M.mz0, m001 = M.mx1 & M.my0 & M.mz0;
+                const uint32_t m010 = M.mx0 & M.my1 & M.mz0, m011 = M.mx1 & M.my1 & M.mz0;
+                const uint32_t m100 = M.mx0 & M.my0 & M.mz1, m101 = M.mx1 & M.my0 & M.mz1;
+                const uint32_t m110 = M.mx0 & M.my1 & M.mz1, m111 = M.mx1 & M.my1 & M.mz1;
+                const uint32_t c000 = cell_code(L, m000, M.bz0), c001 = cell_code(L, m001, M.bz0);
+                const uint32_t c010 = cell_code(L, m010, M.bz0), c011 = cell_code(L, m011, M.bz0);
+                const uint32_t c100 = cell_code(L, m100, M.bz1), c101 = cell_code(L, m101, M.bz1);
+                const uint32_t c110 = cell_code(L, m110, M.bz1), c111 = cell_code(L, m111, M.bz1);
+                const uint32_t a0 = c000 + c100, a1 = c010 + c110;
+                const uint32_t b0 = c001 + c101, b1 = c011 + c111;
+                const uint32_t gmx = a0 + a1, total = gmx + b0 + b1;
+                const uint32_t gmy = a0 + b0, gmz = c000 + c001 + c010 + c011;
+                const uint32_t S2 = total + gmy, S3 = total + total, S4 = S3 + gmz, S5 = S3 + total;
+                const uint32_t xq = __umulhi(us[q], S5);
+                d = (uint32_t)(xq >= gmx) + (uint32_t)(xq >= total) + (uint32_t)(xq >= S2) +
+                    (uint32_t)(xq >= S3) + (uint32_t)(xq >= S4);
+            }
+            const int ax = (int)(d >> 1);
+            const int dir = (d & 1u) ? 1 : -1;
+            ++M.s;
+            int cnew;
+            if (ax == 0) {
+                M.ni += dir;
+                cnew = M.ni;
+            } else if (ax == 1) {
+                M.nj += dir;
+                cnew = M.nj;
+            } else {
+                M.nk += dir;
+                cnew = M.nk;
+            }
+            if (cnew == 0 || cnew == n) {
+                alive = false;
+            } else {
+                const uint32_t lo = L.mask[ax * n + cnew - 1], hi = L.mask[ax * n + cnew];
+                if (ax == 0) {
+                    M.mx0 = lo;
+                    M.mx1 = hi;
+                } else if (ax == 1) {
+                    M.my0 = lo;
+                    M.my1 = hi;
+                } else {
+                    M.mz0 = lo;
+                    M.mz1 = hi;
+                    M.bz0 = L.bz[cnew - 1];
+                    M.bz1 = L.bz[cnew];
+                }
+            }
+        }
+    }
+    return alive;
+}
+
+// -------------------------------------------------------------------------
+// Walker kernel: transitions after the first, until absorption.  A lane
+// holds one walk; lanes whose next cube is not stratified run MicroWalk in
+// the loop below, the others take table transitions, and the wave switches
+// between the two while at least half of its working lanes walk.
 // -------------------------------------------------------------------------
 enum Phase : int { PH_IDLE = 0, PH_NEED = 1, PH_MW = 2, PH_EXHAUSTED = 3 };
+
+// Consecutive indices handed to the lanes of a wave from a global counter,
+// claimed CLAIM_CHUNK at a time: one device-scope atomic per chunk instead of
+// one per refill (same-address atomics from every wave serialise).  Indices
+// of a chunk are handed out in order, so a wave that stops taking work has
+// used every index below the first invalid one it saw.  Call at points where
+// the whole wave is active; state is wave-uniform.
+constexpr uint32_t CLAIM_CHUNK = 64;
+
+struct WaveClaim {
+    unsigned long long base = 0;
+    uint32_t left = 0;
+
+    // One index for every lane of `want` (returned to those lanes).
+    __device__ __forceinline__ unsigned long long take(unsigned long long* counter, uint64_t want, int lane) {
+        const uint32_t cnt = __popcll(want);
+        const uint32_t rank = __popcll(want & ((1ull << lane) - 1ull));
+        unsigned long long idx = ~0ull;
+        uint32_t served = 0;
+        while (served < cnt) {
+            if (left == 0) {
+                unsigned long long b = 0;
+                if (lane == 0) b = atomicAdd(counter, (unsigned long long)CLAIM_CHUNK);
+                base = __shfl(b, 0);
+                left = CLAIM_CHUNK;
+            }
+            const uint32_t n = min(cnt - served, left);
+            if (rank >= served && rank < served + n) idx = base + (rank - served);
+            base += n;
+            left -= n;
+            served += n;
+        }
+        return idx;
+    }
+};
 
 template <bool MULTI>
 __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
@@ -638,6 +814,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     uint32_t err = 0;
 
     int phase = PH_IDLE;
+    WaveClaim claim_rc, claim_fr;  // wave-level claims of resumed and fresh walks
+    bool resume_done = false;
     int sg = 0;  // segment of the lane's walk (always 0 for one segment)
     unsigned long long walk = 0;
     float3 pos = make_float3(0.f, 0.f, 0.f);
@@ -646,51 +824,39 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     // MicroWalk state
     float3 mc = pos;
     float mR = 0.f;
-    int ni = 0, nj = 0, nk = 0;
-    uint32_t s = 0;
-    uint32_t mx0 = 0, mx1 = 0, my0 = 0, my1 = 0, mz0 = 0, mz1 = 0, bz0 = 0, bz1 = 0;
+    MwState M{};
 
     for (;;) {
         // ---- take work: resumed walks first, then fresh walk ids ----
         {
-            const bool want = phase == PH_IDLE;
-            const uint64_t bal = __ballot(want);
+            const uint64_t bal = __ballot(phase == PH_IDLE);
             if (bal) {
-                const int leader = __ffsll((unsigned long long)bal) - 1;
-                const uint32_t cnt = __popcll(bal);
-                const uint32_t rank = __popcll(bal & ((1ull << lane) - 1ull));
-                unsigned long long base = 0;
-                if (A.n_resume) {
-                    if (lane == leader) base = atomicAdd(&K.resume_next, (unsigned long long)cnt);
-                    base = __shfl(base, leader);
-                }
                 bool got = false;
-                if (want && A.n_resume && base + rank < A.n_resume) {
-                    const Parked P = A.resume[base + rank];
-                    if (MULTI) sg = P.seg;
-                    walk = P.walk;
-                    pos = make_float3(P.px, P.py, P.pz);
-                    omega = P.omega;
-                    t = P.t;
-                    phase = PH_NEED;
-                    got = true;
+                if (A.n_resume && !resume_done) {
+                    const unsigned long long ri = claim_rc.take(&K.resume_next, bal, lane);
+                    if (phase == PH_IDLE) {
+                        if (ri < A.n_resume) {
+                            const Parked P = ldpark(A.resume + ri);
+                            if (MULTI) sg = P.seg;
+                            walk = P.walk;
+                            pos = make_float3(P.px, P.py, P.pz);
+                            omega = P.omega;
+                            t = P.t;
+                            phase = PH_NEED;
+                            got = true;
+                        }
+                    }
+                    resume_done = claim_rc.base >= A.n_resume;
                 }
-                const bool want2 = want && !got;
-                const uint64_t bal2 = __ballot(want2);
+                const uint64_t bal2 = __ballot(phase == PH_IDLE && !got);
                 if (bal2) {
-                    const int leader2 = __ffsll((unsigned long long)bal2) - 1;
-                    const uint32_t cnt2 = __popcll(bal2);
-                    const uint32_t rank2 = __popcll(bal2 & ((1ull << lane) - 1ull));
-                    unsigned long long base2 = 0;
-                    if (lane == leader2) base2 = atomicAdd(&K.walk_next, (unsigned long long)cnt2);
-                    base2 = __shfl(base2, leader2);
-                    if (want2) {
-                        const unsigned long long gi = base2 + rank2;
+                    const unsigned long long gi = claim_fr.take(&K.walk_next, bal2, lane);
+                    if (phase == PH_IDLE && !got) {
                         if (gi < A.total) {
                             if (MULTI) sg = find_segment(A.segs, A.n_segs, gi);
-                            const Segment& SG = A.segs[sg];
+                            const GAS Segment& SG = gp(A.segs)[sg];
                             const unsigned long long k = gi - SG.offset;
-                            const float4 f = SG.first_state[k];
+                            const float4 f = ldf4(SG.first_state + k);
                             walk = SG.walk_begin + k;
                             pos = make_float3(f.x, f.y, f.z);
                             omega = f.w;
@@ -707,8 +873,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
 
         // ---- one transition for lanes that need one ----
         if (phase == PH_NEED) {
-            const Segment& SG = A.segs[sg];
-            const StructDev& S = *SG.S;
+            const GAS Segment& SG = gp(A.segs)[sg];
+            SRef S = *gp(SG.S);
             bool park = false, done = false;
             int net = S.n_nets;
             float3 c;
@@ -764,7 +930,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             --c_hops;
                             --c_cls[I.cls];
                         } else {
-                            const uint32_t* tab = A.cache.data + (size_t)idx * A.cache.tab_words;
+                            const GAS uint32_t* tab = gp(A.cache.data) + (size_t)idx * A.cache.tab_words;
                             const Rand4 r = philox10(0u, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_TABLE), SG.k0, SG.k1);
                             const int b = table_sample(tab, A.cache.nb, r.x);
                             int nd[3];
@@ -776,27 +942,18 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                         }
                     } else {
                         // MicroWalk from the centre node
-                        phase = PH_MW;
                         mc = c;
                         mR = R;
-                        ni = nj = nk = n / 2;
-                        s = 0;
-                        mx0 = L.mask[ni - 1];
-                        mx1 = L.mask[ni];
-                        my0 = L.mask[n + nj - 1];
-                        my1 = L.mask[n + nj];
-                        mz0 = L.mask[2 * n + nk - 1];
-                        mz1 = L.mask[2 * n + nk];
-                        bz0 = L.bz[nk - 1];
-                        bz1 = L.bz[nk];
+                        phase = PH_MW;
+                        mw_begin(M, L, n);
                     }
                 }
             }
             if (done) {
                 const unsigned long long k = walk - SG.walk_begin;
                 if (net == S.n_nets) ++c_env;
-                SG.score_net[k] = net;
-                SG.score_w[k] = omega;
+                gpw(SG.score_net)[k] = net;
+                gpw(SG.score_w)[k] = omega;
                 phase = PH_IDLE;
             } else if (park) {
                 const uint32_t slot = atomicAdd(&K.park_count, 1u);
@@ -809,8 +966,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                     P.omega = omega;
                     P.t = t;
                     P.seg = sg;
-                    P.pad[0] = P.pad[1] = 0;
-                    A.park_out[slot] = P;
+                    stpark(A.park_out + slot, P);
                 } else {
                     err |= ERR_PARK_CAP;
                 }
@@ -825,68 +981,10 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
             const int nmw = __popcll(balmw), nact = __popcll(balact);
             if (nmw == 0 || 2 * nmw < nact) break;
             if (phase == PH_MW) {
-                const Segment& SG = A.segs[sg];
-                const Rand4 r = philox10(s >> 2, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), SG.k0, SG.k1);
-                const uint32_t us[4] = {r.x, r.y, r.z, r.w};
-                bool alive = true;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (alive) {
-                        uint32_t d;
-                        if (mx0 == mx1 && my0 == my1 && mz0 == mz1 && bz0 == bz1) {
-                            d = __umulhi(us[q], 6u);
-                        } else {
-                            const uint32_t m000 = mx0 & my0 & mz0, m001 = mx1 & my0 & mz0;
-                            const uint32_t m010 = mx0 & my1 & mz0, m011 = mx1 & my1 & mz0;
-                            const uint32_t m100 = mx0 & my0 & mz1, m101 = mx1 & my0 & mz1;
-                            const uint32_t m110 = mx0 & my1 & mz1, m111 = mx1 & my1 & mz1;
-                            const uint32_t c000 = cell_code(L, m000, bz0), c001 = cell_code(L, m001, bz0);
-                            const uint32_t c010 = cell_code(L, m010, bz0), c011 = cell_code(L, m011, bz0);
-                            const uint32_t c100 = cell_code(L, m100, bz1), c101 = cell_code(L, m101, bz1);
-                            const uint32_t c110 = cell_code(L, m110, bz1), c111 = cell_code(L, m111, bz1);
-                            const uint32_t a0 = c000 + c100, a1 = c010 + c110;
-                            const uint32_t b0 = c001 + c101, b1 = c011 + c111;
-                            const uint32_t gmx = a0 + a1, total = gmx + b0 + b1;
-                            const uint32_t gmy = a0 + b0, gmz = c000 + c001 + c010 + c011;
-                            const uint32_t S2 = total + gmy, S3 = total + total, S4 = S3 + gmz, S5 = S3 + total;
-                            const uint32_t xq = __umulhi(us[q], S5);
-                            d = (uint32_t)(xq >= gmx) + (uint32_t)(xq >= total) + (uint32_t)(xq >= S2) +
-                                (uint32_t)(xq >= S3) + (uint32_t)(xq >= S4);
-                        }
-                        const int ax = (int)(d >> 1);
-                        const int dir = (d & 1u) ? 1 : -1;
-                        ++s;
-                        int cnew;
-                        if (ax == 0) {
-                            ni += dir;
-                            cnew = ni;
-                        } else if (ax == 1) {
-                            nj += dir;
-                            cnew = nj;
-                        } else {
-                            nk += dir;
-                            cnew = nk;
-                        }
-                        if (cnew == 0 || cnew == n) {
-                            alive = false;
-                        } else {
-                            const uint32_t lo = L.mask[ax * n + cnew - 1], hi = L.mask[ax * n + cnew];
-                            if (ax == 0) {
-                                mx0 = lo;
-                                mx1 = hi;
-                            } else if (ax == 1) {
-                                my0 = lo;
-                                my1 = hi;
-                            } else {
-                                mz0 = lo;
-                                mz1 = hi;
-                                bz0 = L.bz[cnew - 1];
-                                bz1 = L.bz[cnew];
-                            }
-                        }
-                    }
-                }
-                if (alive && s >= MW_STEP_CAP) {
+                const GAS Segment& SG = gp(A.segs)[sg];
+                const Rand4 r = philox10(M.s >> 2, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), SG.k0, SG.k1);
+                bool alive = mw_block(M, L, n, r);
+                if (alive && M.s >= MW_STEP_CAP) {
                     // never reached for valid permittivities; keeps a logic
                     // error from spinning: the walk ends where it stands and
                     // the call reports MW_ELIMIT
@@ -894,11 +992,11 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                     alive = false;
                 }
                 if (!alive) {
-                    c_steps += s;
+                    c_steps += M.s;
                     const float h = 2.f * mR / (float)n;
-                    const float3 xx = make_float3(mc.x - mR + (float)ni * h, mc.y - mR + (float)nj * h,
-                                                  mc.z - mR + (float)nk * h);
-                    pos = fold3(*SG.S, xx);
+                    const float3 xx = make_float3(mc.x - mR + (float)M.ni * h, mc.y - mR + (float)M.nj * h,
+                                                  mc.z - mR + (float)M.nk * h);
+                    pos = fold3(*gp(SG.S), xx);
                     ++t;
                     phase = PH_NEED;
                 }
@@ -1749,7 +1847,8 @@ LaunchGeom launch_geom(int n) {
     g.first_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * n + 4 * (KEY_HDR + n) + 3) / 4) | 1u;
     g.lds = (size_t)g.lane_stride * 4 * WALK_THREADS;
     g.first_lds = (size_t)g.first_stride * 4 * FRW_THREADS;
-    g.blocks = cus * std::max(1, std::min(16, (int)(163840 / (g.lds + 512))));
+    // LDS is allocated in 512-byte granules; 16 waves per CU is the VGPR limit
+    g.blocks = cus * std::max(1, std::min(16, (int)(163840 / ((g.lds + 511) / 512 * 512))));
     g.first_blocks = cus * std::max(1, std::min(8, (int)(163840 / (g.first_lds + 512))));
     g.pool = (uint64_t)g.blocks * WALK_THREADS;
     return g;
@@ -1775,6 +1874,11 @@ struct Runner {
     uint64_t misses = 0, launches = 0;
     double walker_ms = 0.0;
 
+    template <class F>
+    void set_lds(F* f, size_t bytes) {
+        MW_HIP(hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    }
+
     Runner(int n_, int hybrid_, uint64_t max_walks, int seg_cap_) : n(n_), hybrid(hybrid_), seg_cap(seg_cap_) {
         cache = &get_cache(n);
         g = launch_geom(n);
@@ -1796,12 +1900,9 @@ struct Runner {
         dsegs = (Segment*)(mem + o_sg);
         MW_HIP(hipEventCreate(&ev0));
         MW_HIP(hipEventCreate(&ev1));
-        MW_HIP(hipFuncSetAttribute((const void*)frw_walk_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)g.lds));
-        MW_HIP(hipFuncSetAttribute((const void*)frw_walk_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)g.lds));
-        MW_HIP(hipFuncSetAttribute((const void*)first_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)g.first_lds));
+        set_lds(frw_walk_kernel<false>, g.lds);
+        set_lds(frw_walk_kernel<true>, g.lds);
+        set_lds(first_kernel, g.first_lds);
     }
     ~Runner() {
         if (ev0) (void)hipEventDestroy(ev0);
@@ -1904,6 +2005,7 @@ struct Runner {
         }
         uint32_t n_resume = 0;
         int cur = 0;
+        const bool multi = segs.size() > 1;
         for (uint64_t local = 0;; ++local) {
             WalkArgs W{};
             W.segs = dsegs;
@@ -1923,10 +2025,10 @@ struct Runner {
             MW_HIP(hipMemset(&ctr->park_count, 0, 4));
             MW_HIP(hipMemset(&ctr->resume_next, 0, 8));
             MW_HIP(hipEventRecord(ev0, 0));
-            if (segs.size() == 1)
-                frw_walk_kernel<false><<<g.blocks, WALK_THREADS, g.lds>>>(W);
-            else
+            if (multi)
                 frw_walk_kernel<true><<<g.blocks, WALK_THREADS, g.lds>>>(W);
+            else
+                frw_walk_kernel<false><<<g.blocks, WALK_THREADS, g.lds>>>(W);
             MW_HIP(hipGetLastError());
             MW_HIP(hipEventRecord(ev1, 0));
             ++launches;

@@ -154,3 +154,35 @@ def test_errors(mw):
     with pytest.raises(mw.MWError) as e:
         mw.frw_extract(st, 0, 1000, n_cells=15)
     assert e.value.status == mw.MW_EINVAL
+
+
+def test_c4_matches_oracle(mw, oracle_lib):
+    """Large interconnect window (192 nets, 7 background layers, coatings and
+    high-k fills): the GPU row at 2e6 walks against an oracle sample of 30000
+    walks (independent seeds), entry by entry in combined standard errors
+    for the self term and every coupling the oracle resolves."""
+    st = W.c4_structure()
+    m = st.meta["master"]
+    r_gpu = mw.frw_extract(st, m, 2000000, seed=41)
+    r_or = oracle_lib.frw_extract(st, m, 30000, seed=42, threads=_threads())
+    print("gpu stats", r_gpu["stats"])
+    print("oracle stats", r_or["stats"])
+    K = len(r_gpu["row"])
+    assert K == st.n_nets + 1
+    assert r_gpu["stats"]["walks"] == 2000000
+    zs = np.array([_z(r_gpu["row"][j], r_or["row"][j], r_gpu["se"][j], r_or["se"][j])
+                   if (r_gpu["se"][j] > 0 or r_or["se"][j] > 0) else 0.0 for j in range(K)])
+    resolved = [j for j in range(K) if abs(r_or["row"][j]) > 4 * r_or["se"][j]]
+    print("C_mm gpu %.6g +- %.3g, oracle %.6g +- %.3g; resolved couplings %d; max z %.2f"
+          % (r_gpu["row"][m], r_gpu["se"][m], r_or["row"][m], r_or["se"][m], len(resolved),
+             zs[resolved].max()))
+    assert m in resolved and len(resolved) >= 5
+    assert zs[m] < 4.0
+    assert zs[resolved].max() < 4.5
+    # the resolved entries as a whole: mean z^2 near 1
+    assert np.mean(zs[resolved] ** 2) < 2.5
+    # nets the GPU never reached are ones the oracle sample barely reached
+    for j in range(K):
+        if r_gpu["row"][j] == 0.0:
+            assert abs(r_or["row"][j]) < 4.5 * r_or["se"][j] + 1e-30
+
