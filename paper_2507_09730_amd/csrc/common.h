@@ -92,6 +92,25 @@ __device__ __forceinline__ Rand4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     return Rand4{c0, c1, c2, c3};
 }
 
+// Global-memory views.  Pointers loaded from device structs are generic;
+// reading through them emits flat instructions, which also count against the
+// LDS wait counter, so a wait for an LDS read would stall on every global
+// access in flight.  Kernels that mix LDS and global accesses read and write
+// global data through these address-space-1 views.  HIP's vector structs are
+// class types whose copy constructors take generic references, so 16-byte
+// values move through the builtin vector types below.
+#define GAS __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const GAS T* gp(const T* p) {
+    return (const GAS T*)p;
+}
+template <class T>
+__device__ __forceinline__ GAS T* gpw(T* p) {
+    return (GAS T*)p;
+}
+typedef float gvec4 __attribute__((ext_vector_type(4)));
+typedef unsigned int guvec4 __attribute__((ext_vector_type(4)));
+
 enum : uint32_t { PURPOSE_MICROWALK = 0, PURPOSE_GAUSS = 1, PURPOSE_FIRST = 2, PURPOSE_TABLE = 3 };
 
 __device__ __forceinline__ uint32_t ctr_hi(uint64_t walk, uint32_t purpose) {

@@ -157,31 +157,12 @@ struct FirstArgs {
     uint32_t lane_stride;
 };
 
-// -------------------------------------------------------------------------
-// Global-memory views.  Pointers loaded from device structs are generic;
-// reading through them emits flat instructions, which also count against the
-// LDS wait counter, so a wait for an LDS read would stall on every global load
-// in flight.  The walker reads global data through these address-space-1
-// views instead.
-// -------------------------------------------------------------------------
-#define GAS __attribute__((address_space(1)))
-template <class T>
-__device__ __forceinline__ const GAS T* gp(const T* p) {
-    return (const GAS T*)p;
-}
-template <class T>
-__device__ __forceinline__ GAS T* gpw(T* p) {
-    return (GAS T*)p;
-}
+// The walker reads device-struct data through global views (gp/gpw).
 using SRef = const GAS StructDev&;
-// float4 is a class type (its copy constructor takes a generic reference), so
-// float4 values move through the builtin vector type.
-typedef float gvec4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ float4 ldf4(const float4* p) {
     const gvec4 v = *(const GAS gvec4*)p;
     return make_float4(v.x, v.y, v.z, v.w);
 }
-typedef unsigned int guvec4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ Parked ldpark(const Parked* p) {
     const GAS guvec4* q = (const GAS guvec4*)p;
     const guvec4 a = q[0], b = q[1];
@@ -235,9 +216,20 @@ __device__ float query_dist(SRef S, float3 p, int cell, int* nearest) {
     float best = INFINITY;
     int who = S.n_nets;
     const uint32_t b = gp(S.gc_off)[cell], e = gp(S.gc_off)[cell + 1];
+    const GAS uint32_t* clist = gp(S.gc_list);
+    float4 nlo = make_float4(0.f, 0.f, 0.f, 0.f), nhi = nlo;
+    if (b < e) {
+        const uint32_t c = clist[b];
+        nlo = ldf4(S.cond_lo + c);
+        nhi = ldf4(S.cond_hi + c);
+    }
     for (uint32_t q = b; q < e; ++q) {
-        const uint32_t c = gp(S.gc_list)[q];
-        const float4 lo = ldf4(S.cond_lo + c), hi = ldf4(S.cond_hi + c);
+        const float4 lo = nlo, hi = nhi;
+        if (q + 1 < e) {
+            const uint32_t c = clist[q + 1];
+            nlo = ldf4(S.cond_lo + c);
+            nhi = ldf4(S.cond_hi + c);
+        }
         const float d = box_dist(lo, hi, p);
         if (d < best) {
             best = d;
@@ -311,25 +303,60 @@ __device__ CubeInfo build_cube(SRef S, int cell, float3 c, float R, int n, LaneC
     CubeInfo info{};
     const float h = 2.f * R / (float)n;
     const float lo0[3] = {c.x - R, c.y - R, c.z - R};
-    for (int q = 0; q < 3 * n; ++q) L.mask[q] = 0;
-    // background layer of every z cell
-    int lmin = 1 << 30, lmax = -1;
-    for (int k = 0; k < n; ++k) {
-        const float z = fold(S, 2, lo0[2] + ((float)k + 0.5f) * h);
-        int l = 0;
-        for (int q = 1; q < S.n_layers; ++q)
-            if (z >= gp(S.layer_z0)[q]) l = q;
-        lmin = min(lmin, l);
-        lmax = max(lmax, l);
-        L.bz[k] = gp(S.layer_code)[l];
+    uint32_t* mask32 = reinterpret_cast<uint32_t*>(L.mask);  // 3n is even
+    for (int q = 0; q < 3 * n / 2; ++q) mask32[q] = 0u;
+    // background layer of every z cell: layer(k) = #{q >= 1 : z_k >= z0[q]}
+    // for the cell centre z_k (layer_z0 ascends)
+    int lmin, lmax;
+    const GAS float* z0 = gp(S.layer_z0);
+    const GAS uint32_t* lcode = gp(S.layer_code);
+    const bool zfold = (S.bc[4] == MW_BC_NEUMANN && lo0[2] < S.wlo[2]) ||
+                       (S.bc[5] == MW_BC_NEUMANN && lo0[2] + 2.f * R > S.whi[2]);
+    if (!zfold) {
+        // centres rise with k: walk the layer boundaries once
+        int l = 0, k = 0;
+        while (l + 1 < S.n_layers && lo0[2] + 0.5f * h >= z0[l + 1]) ++l;
+        lmin = l;
+        for (;;) {
+            const float zb = l + 1 < S.n_layers ? z0[l + 1] : INFINITY;
+            const uint32_t code = lcode[l];
+            while (k < n && lo0[2] + ((float)k + 0.5f) * h < zb) L.bz[k++] = code;
+            if (k >= n) break;
+            while (l + 1 < S.n_layers && lo0[2] + ((float)k + 0.5f) * h >= z0[l + 1]) ++l;
+        }
+        lmax = l;
+    } else {
+        lmin = 1 << 30;
+        lmax = -1;
+        for (int k = 0; k < n; ++k) {
+            const float z = fold(S, 2, lo0[2] + ((float)k + 0.5f) * h);
+            int l = 0;
+            for (int q = 1; q < S.n_layers; ++q)
+                if (z >= z0[q]) l = q;
+            lmin = min(lmin, l);
+            lmax = max(lmax, l);
+            L.bz[k] = lcode[l];
+        }
     }
     info.n_layers = lmax - lmin + 1;
-    // dielectric boxes touching the cube, in priority order
+    // dielectric boxes touching the cube, in priority order (the next box's
+    // record is fetched while the current one is processed)
     int nbits = 0;
     const uint32_t b = gp(S.gd_off)[cell], e = gp(S.gd_off)[cell + 1];
+    const GAS uint32_t* glist = gp(S.gd_list);
+    float4 nlo = make_float4(0.f, 0.f, 0.f, 0.f), nhi = nlo;
+    if (b < e) {
+        const uint32_t id = glist[b];
+        nlo = ldf4(S.diel_lo + id);
+        nhi = ldf4(S.diel_hi + id);
+    }
     for (uint32_t q = b; q < e; ++q) {
-        const uint32_t id = gp(S.gd_list)[q];
-        const float4 blo = ldf4(S.diel_lo + id), bhi = ldf4(S.diel_hi + id);
+        const float4 blo = nlo, bhi = nhi;
+        if (q + 1 < e) {
+            const uint32_t id = glist[q + 1];
+            nlo = ldf4(S.diel_lo + id);
+            nhi = ldf4(S.diel_hi + id);
+        }
         const float bl[3] = {blo.x, blo.y, blo.z}, bh[3] = {bhi.x, bhi.y, bhi.z};
         bool touch = true;
 #pragma unroll

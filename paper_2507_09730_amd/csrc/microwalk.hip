@@ -178,10 +178,17 @@ struct NodeT {
     uint32_t t0, t1, t2, t3, t4;
 };
 
+template <int FORM>
 __device__ __forceinline__ NodeT load_t(const uint32_t* base, uint32_t t4_words, int node) {
     NodeT r;
-    r.t4 = base[node];
-    const uint4 q = reinterpret_cast<const uint4*>(base + t4_words)[node];
+    guvec4 q;
+    if (FORM == FORM_TGLOBAL) {
+        r.t4 = gp(base)[node];
+        q = ((const GAS guvec4*)(base + t4_words))[node];
+    } else {
+        r.t4 = base[node];
+        q = reinterpret_cast<const guvec4*>(base + t4_words)[node];
+    }
     r.t0 = q.x;
     r.t1 = q.y;
     r.t2 = q.z;
@@ -256,7 +263,7 @@ __device__ void run_item(const CubeDev& C, const uint32_t* tab, uint64_t wb, uin
                 if (FORM == FORM_CODES)
                     load_s(tab, P, node, S);
                 else
-                    T = load_t(tab, C.t4_words, node);
+                    T = load_t<FORM>(tab, C.t4_words, node);
             }
         }
         if (!__any(active)) break;
@@ -281,14 +288,14 @@ __device__ void run_item(const CubeDev& C, const uint32_t* tab, uint64_t wb, uin
                         if (FORM == FORM_CODES) {
                             alive = load_s(tab, P, node, S);
                         } else {
-                            T = load_t(tab, C.t4_words, node);
+                            T = load_t<FORM>(tab, C.t4_words, node);
                             alive = T.t4 != 0;
                         }
                     }
                 }
                 if (!alive || s >= STEP_CAP) {
-                    C.hits[rel] = alive ? -1 : hit_index(C, node);
-                    if (C.steps) C.steps[rel] = (int32_t)s;
+                    gpw(C.hits)[rel] = alive ? -1 : hit_index(C, node);
+                    if (C.steps) gpw(C.steps)[rel] = (int32_t)s;
                     my_steps += s;
                     active = false;
                 }
@@ -327,8 +334,8 @@ __global__ void __launch_bounds__(1024) walk_kernel(const CubeDev* __restrict__ 
         }
         const CubeDev C = cubes[I.cube];
         if (C.form != FORM_TGLOBAL && I.cube != cur_cube) {
-            const uint4* src = reinterpret_cast<const uint4*>(C.table);
-            uint4* dst = reinterpret_cast<uint4*>(lds);
+            const GAS guvec4* src = (const GAS guvec4*)C.table;
+            guvec4* dst = reinterpret_cast<guvec4*>(lds);
             for (uint32_t q = threadIdx.x; q < C.table_words / 4; q += blockDim.x) dst[q] = src[q];
             cur_cube = I.cube;
             __syncthreads();
