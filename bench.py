@@ -170,7 +170,8 @@ def main():
     ap.add_argument("--cpu-walks", type=int, default=900000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and serving comparisons")
-    ap.add_argument("--serving-requests", type=int, default=300)
+    ap.add_argument("--serving-requests", type=int, default=300,
+                    help="requests of the serving comparison (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only copy a device buffer of this size 3 times (calibrates the rocprofv3 "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count) and exit")
@@ -241,7 +242,8 @@ def main():
     }
     if not args.no_extras:
         out["batched"] = batched_vs_plain(mw, W)
-        out["serving"] = serving(mw, W, args.serving_requests)
+        if args.serving_requests > 0:
+            out["serving"] = serving(mw, W, args.serving_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(st, args.cpu_walks, seed=7)
     print(json.dumps(out))
