@@ -379,27 +379,37 @@ __device__ CubeInfo build_cube(SRef S, int cell, float3 c, float R, int n, LaneC
         for (int a = 0; a < 3; ++a) {
             const bool crosses = (S.bc[2 * a] == MW_BC_NEUMANN && lo0[a] < S.wlo[a]) ||
                                  (S.bc[2 * a + 1] == MW_BC_NEUMANN && lo0[a] + 2.f * R > S.whi[a]);
+            // masks hold toggles here (bit b flips where box b's run of
+            // cells starts or ends); the pass below turns them into masks
             if (!crosses) {
                 // cells whose centre lo0 + (i + 1/2) h lies in [bl, bh)
                 const float f0 = fminf(fmaxf((bl[a] - lo0[a]) * inv_h - 0.5f, -1.f), (float)n + 1.f);
                 const float f1 = fminf(fmaxf((bh[a] - lo0[a]) * inv_h - 0.5f, -1.f), (float)n + 1.f);
                 const int i0 = max((int)ceilf(f0), 0), i1 = min((int)ceilf(f1), n);
-                for (int i = i0; i < i1; ++i) L.mask[a * n + i] |= bit;
+                if (i0 < i1) {
+                    L.mask[a * n + i0] ^= bit;
+                    if (i1 < n) L.mask[a * n + i1] ^= bit;
+                }
             } else {
+                bool prev = false;
                 for (int i = 0; i < n; ++i) {
                     const float x = fold(S, a, lo0[a] + ((float)i + 0.5f) * h);
-                    if (x >= bl[a] && x < bh[a]) L.mask[a * n + i] |= bit;
+                    const bool in = x >= bl[a] && x < bh[a];
+                    if (in != prev) L.mask[a * n + i] ^= bit;
+                    prev = in;
                 }
             }
         }
     }
-    // aggregate masks: present boxes and boxes spanning all cells per axis
+    // toggles -> masks (prefix xor along each axis); aggregate masks:
+    // present boxes and boxes spanning all cells per axis
     uint32_t O[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        uint32_t A = 0xffffu, Oa = 0;
+        uint32_t A = 0xffffu, Oa = 0, m = 0;
         for (int i = 0; i < n; ++i) {
-            const uint32_t m = L.mask[a * n + i];
+            m ^= L.mask[a * n + i];
+            L.mask[a * n + i] = (uint16_t)m;
             A &= m;
             Oa |= m;
         }
