@@ -111,6 +111,35 @@ def batched_vs_plain(mw, W, reps=5):
             "batched_alu_frac": steps * MW_STEP_SLOTS / t_batch / PEAK_LANE_OPS}
 
 
+def fig3a(mw, W, ns=(4, 8, 12, 16, 20, 24, 28, 32), count=500, walks=4096):
+    """Fig. 3(a) study: E(tau) of MicroWalk over `count` cubes per lattice
+    size with randomly placed blocks of exponentially distributed
+    permittivity, each cube's E(tau) estimated by the mean step count of
+    `walks` walks from one batched launch per size; min/mean/max per n and the
+    log-log slope of the mean (O(N^2) expected)."""
+    import torch
+    rows = {}
+    total_steps, total_s = 0, 0.0
+    for n in ns:
+        cubes = W.fig3a_cubes(n, count)
+        packed = mw.pack_cubes(cubes)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, steps, off = mw.mw_transition_batch(None, [walks] * count, packed=packed, seed=3)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        per = steps[:count * walks].view(count, walks).double().mean(dim=1).cpu().numpy()
+        rows[str(n)] = {"min": float(per.min()), "mean": float(per.mean()), "max": float(per.max()),
+                        "mean_over_n2": float(per.mean() / n ** 2), "ms": dt * 1e3}
+        total_steps += int(steps[:count * walks].sum(dtype=torch.int64))
+        total_s += dt
+    means = [rows[str(n)]["mean"] for n in ns]
+    slope = float(np.polyfit(np.log(ns), np.log(means), 1)[0])
+    return {"workload": "%d cubes per n, 1-6 blocks, eps ~ Exp(rate 0.1) clipped at 0.01, %d walks per cube"
+                        % (count, walks),
+            "per_n": rows, "loglog_slope": slope, "micro_steps_per_s": total_steps / total_s}
+
+
 def serving(mw, W, n_req=300, loads=(0.5, 0.8, 1.2)):
     """Request stream built like the serving workload (windows of 4-200
     conductors, budgets 1e5-1e7 walks, Poisson arrivals at load x the serial
@@ -242,6 +271,7 @@ def main():
     }
     if not args.no_extras:
         out["batched"] = batched_vs_plain(mw, W)
+        out["fig3a"] = fig3a(mw, W)
         if args.serving_requests > 0:
             out["serving"] = serving(mw, W, args.serving_requests)
     if not args.no_cpu_baseline:

@@ -267,7 +267,7 @@ mw_status frw_extract(mw_structure* s, int32_t master, uint64_t walk_budget,
  * A worker thread admits queued requests in arrival order while their device
  * footprint (structure, grid index, reduction partials, accumulators) fits
  * within hbm_budget_bytes, and runs rounds of a fixed walk capacity: the
- * longest-running admitted request gets up to a quarter of it, the rest goes
+ * longest-running admitted request gets up to half of it, the rest goes
  * to the requests with the fewest remaining walks first; each share is that
  * request's next walk ids (from 0).  All shares of a round run in one set of
  * kernel launches, one reduction launch and one result copy, so requests

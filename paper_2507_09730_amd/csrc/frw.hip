@@ -2365,13 +2365,13 @@ struct mw_server {
     }
 
     // Walk shares of one round (capacity round_walks): the longest-admitted
-    // request gets up to a quarter, the rest goes to the requests with the
-    // fewest remaining walks first.
+    // request gets up to half, the rest goes to the requests with the fewest
+    // remaining walks first.
     std::vector<uint64_t> shares(const std::vector<std::shared_ptr<ServerRequest>>& running) const {
         const size_t m = running.size();
         std::vector<uint64_t> sh(m, 0), rem(m);
         for (size_t i = 0; i < m; ++i) rem[i] = running[i]->budget - running[i]->X->done;
-        uint64_t used = std::min<uint64_t>(rem[0], round_walks / 4);
+        uint64_t used = std::min<uint64_t>(rem[0], round_walks / 2);
         sh[0] = used;
         std::vector<size_t> order(m);
         for (size_t i = 0; i < m; ++i) order[i] = i;

@@ -184,3 +184,26 @@ def test_graph_plan_replays(mw):
         torch.cuda.synchronize()
         assert torch.equal(hp, he) and torch.equal(sp, se), (rep, seed)
     plan.close()
+
+
+@pytest.mark.parametrize("n,count", [(6, 60), (10, 40)])
+def test_fig3a_expected_steps_match_eq11(mw, oracle_lib, n, count):
+    """Batched MicroWalk on the Fig. 3(a) cubes (exponentially distributed
+    permittivities, contrast up to ~1e4): per cube, the mean step count of
+    20000 walks agrees with E(tau) of Eq. (11) (absorbing-chain solve on the
+    oracle's link codes) in standard errors."""
+    from oracle import pins
+    cubes = workloads.fig3a_cubes(n, count)
+    walks = [20000] * count
+    _, steps, off = mw.mw_transition_batch(cubes, walks, seed=17)
+    steps = steps.cpu().numpy()
+    zs = []
+    for c, e in enumerate(cubes):
+        links, _ = oracle_lib.vertex_thresholds(e)
+        et = pins.vertex_exit_distribution(links, n)[1]
+        s = steps[off[c]:off[c] + walks[c]].astype(np.float64)
+        zs.append((s.mean() - et) / (s.std() / np.sqrt(s.size)))
+    zs = np.array(zs)
+    print("n", n, "max |z|", np.abs(zs).max(), "mean z^2", np.mean(zs ** 2))
+    assert np.abs(zs).max() < 4.5
+    assert np.mean(zs ** 2) < 2.0

@@ -215,3 +215,22 @@ def test_walk_mean_value_property(oracle_lib):
     z = pins.vertex_boundary_nodes(n)[hits, 2]
     v = phi_nodes[z]
     assert abs(v.mean() - phi_nodes[n // 2]) < 4 * v.std() / np.sqrt(v.size)
+
+
+def test_fig3a_expected_length_scales_as_n_squared(oracle_lib):
+    """Fig. 3(a): for cubes with randomly placed blocks of exponentially
+    distributed permittivity, E(tau) of Eq. (11) grows as O(N^2).  Mean
+    E(tau) over 30 cubes per lattice size, from the absorbing-chain solve on
+    the oracle's link codes; log-log slope over n = 4..10."""
+    ns = (4, 6, 8, 10)
+    means = []
+    for n in ns:
+        ets = []
+        for e in workloads.fig3a_cubes(n, 30):
+            links, _ = oracle_lib.vertex_thresholds(e)
+            ets.append(pins.vertex_exit_distribution(links, n)[1])
+        means.append(np.mean(ets))
+        # same order as the single-dielectric constant 0.3373 N^2 (Sec. III-B)
+        assert 0.25 < np.mean(ets) / n ** 2 < 0.6
+    slope = np.polyfit(np.log(ns), np.log(means), 1)[0]
+    assert 1.8 < slope < 2.5, slope

@@ -85,6 +85,25 @@ def random_cube(n, rng, k_max=6, eps_choices=C3_EPS, background=3.9):
     return e
 
 
+def fig3a_cubes(n, count=500, seed=6, k_max=6, eps_min=1e-2):
+    """Fig. 3(a) study: n^3 cubes whose background and 1..k_max randomly
+    placed blocks take permittivities drawn from an exponential distribution
+    of rate 0.1 (mean 10), clipped below at eps_min so that every cell code
+    rint(eps * 2^16) is positive."""
+    rng = np.random.Generator(np.random.PCG64([seed, n]))
+    cubes = []
+    half = (n + 1) // 2
+    for _ in range(count):
+        e = np.full((n, n, n), max(rng.exponential(10.0), eps_min), dtype=np.float32)
+        for _ in range(int(rng.integers(1, k_max + 1))):
+            ext = rng.integers(1, half + 1, size=3)
+            org = np.array([rng.integers(0, n - ext[a] + 1) for a in range(3)])
+            e[org[2]:org[2] + ext[2], org[1]:org[1] + ext[1], org[0]:org[0] + ext[0]] = \
+                max(rng.exponential(10.0), eps_min)
+        cubes.append(e)
+    return cubes
+
+
 def c3_sizes(count=4096, seed=3):
     """(n, walks) of the batched-transition workload: n even, log-uniform in
     [8, 32]; walks log-uniform in [1e3, 1e5]."""
