@@ -261,6 +261,28 @@ mw_status frw_extract(mw_structure* s, int32_t master, uint64_t walk_budget,
                       int32_t* score_net, float* score_w);
 
 /* ------------------------------------------------------------------------
+ * frw_extract_matrix — Alg. 1 for n_masters masters (distinct net indices in
+ * masters[]): rows of the capacitance matrix.  Master i runs
+ * walks_per_master walks with Philox key seed + i, walk ids first_walk on;
+ * each row equals frw_extract(s, masters[i], walks_per_master, seed + i,
+ * options) up to fp32 summation order.  The masters' walks share rounds
+ * (one set of walker launches and one reduction per round).  With
+ * options->target_rel_3sigma > 0 a master stops once its own C_mm meets the
+ * target (checked every options->batch_walks walks, or only at the end when
+ * that is 0).
+ * cap, stderr (host, n_masters x (n_nets+1), row-major): rows as in
+ * frw_extract.  cap_sym (host, n_masters x n_masters, or NULL): the
+ * symmetrised block over the listed masters, (C[a][m_b] + C[b][m_a]) / 2 off
+ * the diagonal and C[a][m_a] on it (the matrix is symmetric in exact
+ * arithmetic; Maxwell reciprocity).  stats may be NULL; its walks field sums
+ * all masters.  Errors as frw_extract; MW_EINVAL for a repeated master.   */
+mw_status frw_extract_matrix(mw_structure* s, int32_t n_masters,
+                             const int32_t* masters, uint64_t walks_per_master,
+                             uint64_t seed, const frw_options* options,
+                             double* cap, double* stderr_, double* cap_sym,
+                             frw_stats* stats);
+
+/* ------------------------------------------------------------------------
  * Serving: a request loop over one device with continuous batching.
  *
  * mw_server_submit copies the structure description and returns a ticket.

@@ -344,6 +344,28 @@ def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
 
 
 
+def frw_extract_matrix(structure, walks_per_master, seed=0, masters=None, n_cells=16, hybrid=1,
+                       target_rel_3sigma=0.0, abs_tol_rel=1e-6, first_walk=0, batch_walks=0):
+    """Capacitance-matrix rows for several masters (default: every net) in
+    shared rounds.  Returns {"cap": (M, K) rows, "se": (M, K), "sym": (M, M)
+    symmetrised block, "masters": list, "stats": dict}; master i uses seed + i."""
+    if not isinstance(structure, StructureHandle):
+        structure = StructureHandle(structure)
+    K = structure.n_nets + 1
+    if masters is None:
+        masters = list(range(structure.n_nets))
+    m = np.ascontiguousarray(masters, dtype=np.int32)
+    M = int(m.size)
+    cap = np.zeros((M, K))
+    se = np.zeros((M, K))
+    sym = np.zeros((M, M))
+    stats = frw_stats()
+    opt = frw_options(n_cells, hybrid, 0, 0, target_rel_3sigma, abs_tol_rel, first_walk, batch_walks)
+    _check(_lib.frw_extract_matrix(structure.handle, I32(M), _vp(m), U64(walks_per_master), U64(seed),
+                                   ctypes.byref(opt), _vp(cap), _vp(se), _vp(sym), ctypes.byref(stats)))
+    return {"cap": cap, "se": se, "sym": sym, "masters": [int(x) for x in m], "stats": stats.as_dict()}
+
+
 # ---------------------------------------------------------------------------
 # Serving (continuous batching)
 # ---------------------------------------------------------------------------

@@ -2213,6 +2213,138 @@ void add_counters(frw_stats& st, const Counters& h) {
     st.hop_cap += h.hop_cap;
 }
 
+// One round over several extractions (server requests, or the masters of a
+// matrix extraction): their shares of walks run in one set of walker
+// launches, then one reduction launch and one copy of all results.  The
+// per-walk buffers of a round are shared; each share's buffers start on a
+// reduction block.
+struct SharedRound {
+    uint64_t cap = 0;
+    int max_segs = 0;
+    char* mem = nullptr;
+    int32_t* net = nullptr;
+    float* w = nullptr;
+    float4* fs = nullptr;
+    uint32_t* fd = nullptr;
+    RedSeg* dred = nullptr;
+    double* out = nullptr;
+    size_t out_cap = 0;
+
+    static size_t layout(uint64_t c, int segs, size_t* o_n, size_t* o_w, size_t* o_fs, size_t* o_fd,
+                         size_t* o_sg) {
+        size_t o = 0;
+        auto sz = [&](size_t b) {
+            size_t r = o;
+            o += (b + 255) / 256 * 256;
+            return r;
+        };
+        *o_n = sz(4 * c);
+        *o_w = sz(4 * c);
+        *o_fs = sz(16 * c);
+        *o_fd = sz(4 * c);
+        *o_sg = sz(sizeof(RedSeg) * (size_t)segs);
+        return o;
+    }
+    static size_t bytes(uint64_t round_walks, int segs) {
+        size_t a, b, c, d, e;
+        return layout(round_walks + (uint64_t)segs * RED_CHUNK, segs, &a, &b, &c, &d, &e);
+    }
+
+    SharedRound(uint64_t round_walks, int segs) : cap(round_walks + (uint64_t)segs * RED_CHUNK), max_segs(segs) {
+        size_t o_n, o_w, o_fs, o_fd, o_sg;
+        const size_t total = layout(cap, segs, &o_n, &o_w, &o_fs, &o_fd, &o_sg);
+        mem = (char*)dev_alloc(total);
+        net = (int32_t*)(mem + o_n);
+        w = (float*)(mem + o_w);
+        fs = (float4*)(mem + o_fs);
+        fd = (uint32_t*)(mem + o_fd);
+        dred = (RedSeg*)(mem + o_sg);
+    }
+    ~SharedRound() {
+        dev_free(out);
+        dev_free(mem);
+    }
+
+    // Runs share[i] walks of X[i] (walk ids first_walk + X[i]->done on,
+    // Philox key seeds[i]); shares of zero are skipped.  Updates done and res
+    // of every extraction that ran.  Returns the run's counters.
+    Counters run(Runner& R, const std::vector<Extraction*>& X, const std::vector<uint64_t>& share,
+                 const std::vector<uint64_t>& seeds, uint64_t first_walk) {
+        std::vector<Segment> segs;
+        std::vector<RedSeg> red;
+        std::vector<size_t> part;
+        uint64_t offset = 0;
+        int blocks = 0;
+        size_t outn = 0;
+        for (size_t i = 0; i < X.size(); ++i)
+            if (share[i]) outn += 2 * (size_t)X[i]->K;
+        if (outn > out_cap) {
+            dev_free(out);
+            out = nullptr;
+            out = (double*)dev_alloc(sizeof(double) * outn);
+            out_cap = outn;
+        }
+        size_t out_off = 0;
+        for (size_t i = 0; i < X.size(); ++i) {
+            if (!share[i]) continue;
+            Extraction& E = *X[i];
+            const int nblk = (int)((share[i] + RED_CHUNK - 1) / RED_CHUNK);
+            MW_REQUIRE(offset + (uint64_t)nblk * RED_CHUNK <= cap && (int)segs.size() < max_segs, MW_ELIMIT,
+                       "round larger than its buffers");
+            Segment sg{};
+            sg.S = E.dS;
+            sg.G = E.G;
+            sg.walk_begin = first_walk + E.done;
+            sg.count = share[i];
+            sg.score_net = net + offset;
+            sg.score_w = w + offset;
+            sg.first_state = fs + offset;
+            sg.first_done = fd + offset;
+            sg.k0 = (uint32_t)seeds[i];
+            sg.k1 = (uint32_t)(seeds[i] >> 32);
+            RedSeg rs{};
+            rs.net = sg.score_net;
+            rs.w = sg.score_w;
+            rs.count = share[i];
+            rs.K = E.K;
+            rs.first_block = blocks;
+            rs.partial = E.partial;
+            rs.acc = E.acc;
+            rs.n_total = (double)(E.done + share[i]);
+            rs.out = out + out_off;
+            out_off += 2 * (size_t)E.K;
+            blocks += nblk;
+            offset += (uint64_t)nblk * RED_CHUNK;
+            segs.push_back(sg);
+            red.push_back(rs);
+            part.push_back(i);
+        }
+        if (segs.empty()) return Counters{};
+        // list indices are dense; buffers start on reduction blocks
+        uint64_t dense = 0;
+        for (Segment& sg : segs) {
+            sg.offset = dense;
+            dense += sg.count;
+        }
+        MW_HIP(hipMemsetAsync(fd, 0, sizeof(uint32_t) * offset, 0));
+        const Counters h = R.run(segs);
+        MW_HIP(hipMemcpy(dred, red.data(), sizeof(RedSeg) * red.size(), hipMemcpyHostToDevice));
+        reduce_multi_kernel<<<blocks, RED_THREADS>>>(dred, (int)red.size());
+        finish_multi_kernel<<<(int)red.size(), 256>>>(dred);
+        MW_HIP(hipGetLastError());
+        std::vector<double> host(outn);
+        MW_HIP(hipMemcpy(host.data(), out, sizeof(double) * outn, hipMemcpyDeviceToHost));
+        size_t o2 = 0;
+        for (size_t q = 0; q < part.size(); ++q) {
+            Extraction& E = *X[part[q]];
+            E.done += share[part[q]];
+            std::copy(host.begin() + o2, host.begin() + o2 + 2 * E.K, E.res.begin());
+            o2 += 2 * (size_t)E.K;
+        }
+        return h;
+    }
+};
+
 }  // namespace
 
 extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk_budget, uint64_t seed,
@@ -2254,6 +2386,87 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         if (stats) {
             *stats = acc;
             stats->walks = X.done;
+            stats->cache_miss = R.misses;
+            stats->launches = R.launches;
+            stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+            stats->walker_seconds = R.walker_ms * 1e-3;
+        }
+    });
+}
+
+// Capacitance matrix: Alg. 1 for several masters in shared rounds.
+extern "C" mw_status frw_extract_matrix(mw_structure* st, int32_t n_masters, const int32_t* masters,
+                                        uint64_t walks_per_master, uint64_t seed, const frw_options* options,
+                                        double* cap, double* stderr_out, double* cap_sym, frw_stats* stats) {
+    return guarded([&] {
+        const auto t_start = std::chrono::steady_clock::now();
+        MW_REQUIRE(st, MW_EINVAL, "null structure");
+        MW_REQUIRE(n_masters >= 1 && masters, MW_EINVAL, "at least one master is required");
+        MW_REQUIRE(cap && stderr_out, MW_EINVAL, "cap and stderr are required");
+        MW_REQUIRE(walks_per_master >= 2, MW_EINVAL, "walks_per_master must be at least 2");
+        for (int i = 0; i < n_masters; ++i) {
+            MW_REQUIRE(masters[i] >= 0 && masters[i] < st->n_nets, MW_EINVAL, "master %d out of range", masters[i]);
+            for (int j = 0; j < i; ++j) MW_REQUIRE(masters[j] != masters[i], MW_EINVAL, "master %d listed twice", masters[i]);
+        }
+        const frw_options opt = normalised_options(options);
+        int dev = 0;
+        MW_HIP(hipGetDevice(&dev));
+        MW_REQUIRE(dev == st->device, MW_EINVAL, "structure belongs to device %d, current device is %d",
+                   st->device, dev);
+        const int n = opt.n_cells;
+        const LaunchGeom g = launch_geom(n);
+        // one round holds up to round_walks walks over all active masters
+        const uint64_t round_walks = std::max<uint64_t>(8 * g.pool, 1 << 22);
+        const uint64_t per_round = opt.target_rel_3sigma > 0 && opt.batch_walks ? opt.batch_walks : walks_per_master;
+        std::vector<std::unique_ptr<Extraction>> own;
+        std::vector<Extraction*> X;
+        std::vector<uint64_t> seeds;
+        for (int i = 0; i < n_masters; ++i) {
+            own.push_back(std::make_unique<Extraction>(*st, masters[i], opt.abs_tol_rel, round_walks, false, false));
+            X.push_back(own.back().get());
+            seeds.push_back(seed + (uint64_t)i);  // master i: Philox key seed + i
+        }
+        Runner R(n, opt.hybrid, round_walks, n_masters);
+        SharedRound round(round_walks, n_masters);
+        frw_stats acc{};
+        std::vector<bool> active(n_masters, true);
+        for (;;) {
+            // shares: each active master's next batch, as many masters as fit
+            std::vector<uint64_t> sh(n_masters, 0);
+            uint64_t used = 0;
+            bool any = false;
+            for (int i = 0; i < n_masters; ++i) {
+                if (!active[i]) continue;
+                any = true;
+                const uint64_t want = std::min<uint64_t>(per_round, walks_per_master - X[i]->done);
+                const uint64_t padded = (want + RED_CHUNK - 1) / RED_CHUNK * RED_CHUNK;
+                if (used > 0 && used + padded > round_walks) continue;  // next round
+                sh[i] = std::min<uint64_t>(want, round_walks);
+                used += (sh[i] + RED_CHUNK - 1) / RED_CHUNK * RED_CHUNK;
+            }
+            if (!any) break;
+            add_counters(acc, round.run(R, X, sh, seeds, opt.first_walk));
+            for (int i = 0; i < n_masters; ++i)
+                if (active[i] && (X[i]->done >= walks_per_master || (sh[i] && X[i]->converged(opt.target_rel_3sigma))))
+                    active[i] = false;
+        }
+        const int K = X[0]->K;
+        for (int i = 0; i < n_masters; ++i)
+            for (int j = 0; j < K; ++j) {
+                cap[(size_t)i * K + j] = X[i]->res[j];
+                stderr_out[(size_t)i * K + j] = X[i]->res[K + j];
+            }
+        if (cap_sym) {
+            // symmetrised block over the listed masters: mean of C_ab and C_ba
+            for (int a = 0; a < n_masters; ++a)
+                for (int b = 0; b < n_masters; ++b)
+                    cap_sym[(size_t)a * n_masters + b] =
+                        a == b ? X[a]->res[masters[a]] : 0.5 * (X[a]->res[masters[b]] + X[b]->res[masters[a]]);
+        }
+        if (stats) {
+            *stats = acc;
+            stats->walks = 0;
+            for (auto* e : X) stats->walks += e->done;
             stats->cache_miss = R.misses;
             stats->launches = R.launches;
             stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
@@ -2330,39 +2543,7 @@ struct mw_server {
         st.failed++;
     }
 
-    // buffers of one round, shared by the requests of the round
-    char* rmem = nullptr;
-    int32_t* r_net = nullptr;
-    float* r_w = nullptr;
-    float4* r_fs = nullptr;
-    uint32_t* r_fd = nullptr;
-    RedSeg* r_segs = nullptr;
-    uint64_t r_cap = 0;
-    double* r_out = nullptr;
-    size_t r_out_cap = 0;
-
-    ~mw_server() {
-        dev_free(r_out);
-        dev_free(rmem);
-    }
-
-    void alloc_round_buffers() {
-        r_cap = round_walks + (uint64_t)max_slots * RED_CHUNK;
-        size_t o = 0;
-        auto sz = [&](size_t b) {
-            size_t r = o;
-            o += (b + 255) / 256 * 256;
-            return r;
-        };
-        const size_t o_n = sz(4 * r_cap), o_w = sz(4 * r_cap), o_fs = sz(16 * r_cap), o_fd = sz(4 * r_cap);
-        const size_t o_sg = sz(sizeof(RedSeg) * max_slots);
-        rmem = (char*)dev_alloc(o);
-        r_net = (int32_t*)(rmem + o_n);
-        r_w = (float*)(rmem + o_w);
-        r_fs = (float4*)(rmem + o_fs);
-        r_fd = (uint32_t*)(rmem + o_fd);
-        r_segs = (RedSeg*)(rmem + o_sg);
-    }
+    std::unique_ptr<SharedRound> round;  // buffers of one round (first round on)
 
     // Walk shares of one round (capacity round_walks): the longest-admitted
     // request gets up to half, the rest goes to the requests with the fewest
@@ -2447,88 +2628,27 @@ struct mw_server {
             if (running.empty()) continue;
             // one round over the shares of the running requests
             const std::vector<uint64_t> sh = shares(running);
-            std::vector<size_t> part;
-            std::vector<Segment> segs;
-            std::vector<RedSeg> red;
-            uint64_t offset = 0, walks = 0;
-            int blocks = 0;
-            size_t outn = 0;
-            for (size_t i = 0; i < running.size(); ++i)
-                if (sh[i]) outn += 2 * (size_t)running[i]->X->K;
+            uint64_t walks = 0;
+            size_t n_run = 0;
+            std::vector<Extraction*> X;
+            std::vector<uint64_t> seeds;
+            for (size_t i = 0; i < running.size(); ++i) {
+                X.push_back(running[i]->X.get());
+                seeds.push_back(running[i]->seed);
+                walks += sh[i];
+                n_run += sh[i] ? 1 : 0;
+            }
             mw_status rc = guarded([&] {
-                if (!rmem) alloc_round_buffers();
-                if (outn > r_out_cap) {
-                    dev_free(r_out);
-                    r_out = nullptr;
-                    r_out = (double*)dev_alloc(sizeof(double) * outn);
-                    r_out_cap = outn;
-                }
-                size_t out_off = 0;
-                for (size_t i = 0; i < running.size(); ++i) {
-                    if (!sh[i]) continue;
-                    Extraction& X = *running[i]->X;
-                    Segment sg{};
-                    sg.S = X.dS;
-                    sg.G = X.G;
-                    sg.walk_begin = opt.first_walk + X.done;
-                    sg.offset = offset;
-                    sg.count = sh[i];
-                    sg.score_net = r_net + offset;
-                    sg.score_w = r_w + offset;
-                    sg.first_state = r_fs + offset;
-                    sg.first_done = r_fd + offset;
-                    sg.k0 = (uint32_t)running[i]->seed;
-                    sg.k1 = (uint32_t)(running[i]->seed >> 32);
-                    RedSeg rs{};
-                    rs.net = sg.score_net;
-                    rs.w = sg.score_w;
-                    rs.count = sh[i];
-                    rs.K = X.K;
-                    rs.first_block = blocks;
-                    rs.partial = X.partial;
-                    rs.acc = X.acc;
-                    rs.n_total = (double)(X.done + sh[i]);
-                    rs.out = r_out + out_off;
-                    out_off += 2 * (size_t)X.K;
-                    const int nblk = (int)((sh[i] + RED_CHUNK - 1) / RED_CHUNK);
-                    blocks += nblk;
-                    offset += (uint64_t)nblk * RED_CHUNK;  // segments start on reduction blocks
-                    walks += sh[i];
-                    segs.push_back(sg);
-                    red.push_back(rs);
-                    part.push_back(i);
-                }
-                // list indices are dense; the segments' buffers start on
-                // reduction blocks of the round buffers
-                uint64_t dense = 0;
-                for (Segment& sg : segs) {
-                    sg.offset = dense;
-                    dense += sg.count;
-                }
-                MW_HIP(hipMemsetAsync(r_fd, 0, sizeof(uint32_t) * offset, 0));
-                if (!R)
-                    R = std::make_unique<Runner>(opt.n_cells, opt.hybrid, round_walks, max_slots);
-                (void)R->run(segs);
-                MW_HIP(hipMemcpy(r_segs, red.data(), sizeof(RedSeg) * red.size(), hipMemcpyHostToDevice));
-                reduce_multi_kernel<<<blocks, RED_THREADS>>>(r_segs, (int)red.size());
-                finish_multi_kernel<<<(int)red.size(), 256>>>(r_segs);
-                MW_HIP(hipGetLastError());
-                std::vector<double> host(outn);
-                MW_HIP(hipMemcpy(host.data(), r_out, sizeof(double) * outn, hipMemcpyDeviceToHost));
-                size_t o2 = 0;
-                for (size_t q = 0; q < part.size(); ++q) {
-                    Extraction& X = *running[part[q]]->X;
-                    X.done += sh[part[q]];
-                    std::copy(host.begin() + o2, host.begin() + o2 + 2 * X.K, X.res.begin());
-                    o2 += 2 * (size_t)X.K;
-                    running[part[q]]->stats.walks = X.done;
-                }
+                if (!round) round = std::make_unique<SharedRound>(round_walks, max_slots);
+                if (!R) R = std::make_unique<Runner>(opt.n_cells, opt.hybrid, round_walks, max_slots);
+                (void)round->run(*R, X, sh, seeds, opt.first_walk);
+                for (auto& r : running) r->stats.walks = r->X->done;
             });
             std::string msg = rc ? mw_last_error() : "";
             std::lock_guard<std::mutex> lk(mu);
             st.rounds++;
             st.walks += walks;
-            st.max_concurrent = std::max<uint64_t>(st.max_concurrent, part.size());
+            st.max_concurrent = std::max<uint64_t>(st.max_concurrent, n_run);
             std::vector<std::shared_ptr<ServerRequest>> still;
             for (size_t i = 0; i < running.size(); ++i) {
                 auto& r = running[i];

@@ -186,3 +186,37 @@ def test_c4_matches_oracle(mw, oracle_lib):
         if r_gpu["row"][j] == 0.0:
             assert abs(r_or["row"][j]) < 4.5 * r_or["se"][j] + 1e-30
 
+
+
+def test_matrix_rows_equal_single_extractions(mw):
+    """frw_extract_matrix: every row equals frw_extract of that master with
+    key seed + i (same walks, fp32 summation order aside); the matrix obeys
+    reciprocity within standard errors and the symmetrised block is the
+    mean of the two estimates."""
+    st = W.c2_structure()
+    h = mw.StructureHandle(st)
+    walks = 300000
+    M = mw.frw_extract_matrix(h, walks, seed=40)
+    assert M["stats"]["walks"] == 4 * walks
+    cap, se, sym = M["cap"], M["se"], M["sym"]
+    for i, m in enumerate(M["masters"]):
+        alone = mw.frw_extract(h, m, walks, seed=40 + i)
+        scale = np.abs(alone["row"]).max()
+        assert np.all(np.abs(cap[i] - alone["row"]) <= 1e-6 * np.abs(alone["row"]) + 1e-9 * scale)
+        assert np.allclose(se[i], alone["se"], rtol=1e-4, atol=1e-12)
+    for a in range(4):
+        assert sym[a, a] == cap[a, a]
+        for b in range(4):
+            if a != b:
+                assert _z(cap[a, b], cap[b, a], se[a, b], se[b, a]) < 3.5
+                assert sym[a, b] == pytest.approx(0.5 * (cap[a, b] + cap[b, a]))
+    # a subset of masters, converging on its own target
+    M2 = mw.frw_extract_matrix(h, 20000000, seed=5, masters=[2, 0], target_rel_3sigma=0.03,
+                               batch_walks=100000)
+    assert M2["masters"] == [2, 0] and M2["sym"].shape == (2, 2)
+    for i, m in enumerate(M2["masters"]):
+        assert 3 * M2["se"][i, m] / M2["cap"][i, m] <= 0.03
+    assert M2["stats"]["walks"] < 2 * 20000000
+    with pytest.raises(mw.MWError) as e:
+        mw.frw_extract_matrix(h, 1000, masters=[1, 1])
+    assert e.value.status == mw.MW_EINVAL
