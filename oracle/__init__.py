@@ -189,8 +189,9 @@ STAT_KEYS = ("walks", "hops", "micro_steps", "cls_uniform", "cls_stratified", "c
 
 
 def frw_extract(st, master, n_walks, seed=0, first_walk=0, n_cells=16, hybrid=1,
-                abs_tol_rel=1e-6, threads=1, scores=False):
-    """Alg. 1: capacitance row (fF, last entry env) and standard errors."""
+                abs_tol_rel=1e-6, threads=1, scores=False, expand=1.0):
+    """Alg. 1: capacitance row (fF, last entry env) and standard errors.
+    expand > 1: MicroWalk-E transitions with that expansion factor."""
     args, keep = _structure_args(st)
     K = st.n_nets + 1
     row = np.zeros(K)
@@ -199,7 +200,7 @@ def frw_extract(st, master, n_walks, seed=0, first_walk=0, n_cells=16, hybrid=1,
     w = np.zeros(n_walks) if scores else None
     stats = np.zeros(13, dtype=np.uint64)
     rc = lib().mwo_frw_extract(*args, I32(master), U64(n_walks), U64(first_walk), U64(seed),
-                               I32(n_cells), I32(hybrid), DBL(abs_tol_rel), I32(threads),
+                               I32(n_cells), I32(hybrid), DBL(abs_tol_rel), DBL(expand), I32(threads),
                                _p(row), _p(se), _p(nets), _p(w), _p(stats))
     if rc:
         raise RuntimeError("oracle frw_extract failed (%d)" % rc)

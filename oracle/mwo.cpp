@@ -181,6 +181,60 @@ int microwalk_vertex(const std::vector<uint64_t>& e, int n, const int start[3], 
     }
 }
 
+// MicroWalk-E (Sec. III-B, Fig. 3(b)): Alg. 3 on the vertex lattice of an
+// expanded cube whose interior nodes may be absorbing (inside a conductor or
+// beyond a grounded window face).  absorb[(k*(n+1)+j)*(n+1)+i] = -1 for a free
+// node, else the net that absorbs the walk (n_nets = grounded enclosure).
+// Reading of "adjusts the lattice accordingly": a link from a free node into
+// an absorbing node is cut where it enters the conductor (or meets the
+// grounded face), at a fraction theta of its length (at least 1/16, which
+// keeps the codes bounded), and its code becomes rint(code / theta) — the
+// Shortley-Weller treatment of a Dirichlet boundary between nodes, exact for
+// linear potentials; the walk that takes it is absorbed.  Returns the hit index of a boundary node, or -2 with *net_out
+// set when an absorbing interior node is reached.  Same random stream as
+// Alg. 3.
+typedef double (*ThetaFn)(const void* ctx, const int p[3], int d);
+int microwalk_vertex_e(const std::vector<uint64_t>& e, const std::vector<int32_t>& absorb, int n, uint64_t seed,
+                       uint32_t c1, uint64_t walk, int32_t* steps_out, int* net_out, ThetaFn theta = nullptr,
+                       const void* ctx = nullptr) {
+    int p[3] = {n / 2, n / 2, n / 2};
+    uint64_t s = 0;
+    for (;;) {
+        if (s >= (1ull << 30)) {
+            if (steps_out) *steps_out = (int32_t)s;
+            return -1;
+        }
+        uint64_t g[6];
+        for (int d = 0; d < 6; ++d) {
+            g[d] = vertex_link(e, n, p[0], p[1], p[2], d);
+            if (theta) {
+                int q[3] = {p[0] + DIR[d][0], p[1] + DIR[d][1], p[2] + DIR[d][2]};
+                bool interior = q[0] > 0 && q[0] < n && q[1] > 0 && q[1] < n && q[2] > 0 && q[2] < n;
+                if (interior && absorb[((size_t)q[2] * (n + 1) + q[1]) * (n + 1) + q[0]] >= 0) {
+                    const double th = theta(ctx, p, d);
+                    g[d] = (uint64_t)std::nearbyint((double)g[d] / th);
+                }
+            }
+        }
+        uint32_t T[5];
+        thresholds_from_codes(g, T);
+        uint32_t u = rng_word(seed, c1, walk, PURPOSE_MW, s);
+        int d = choose_direction(u, T);
+        for (int a = 0; a < 3; ++a) p[a] += DIR[d][a];
+        ++s;
+        if (p[0] == 0 || p[0] == n || p[1] == 0 || p[1] == n || p[2] == 0 || p[2] == n) {
+            if (steps_out) *steps_out = (int32_t)s;
+            return vertex_hit_index(n, p[0], p[1], p[2]);
+        }
+        const int32_t a = absorb[((size_t)p[2] * (n + 1) + p[1]) * (n + 1) + p[0]];
+        if (a >= 0) {
+            if (steps_out) *steps_out = (int32_t)s;
+            *net_out = a;
+            return -2;
+        }
+    }
+}
+
 // Alg. 3 on the cell-centred lattice of Sec. III-A (nodes at voxel centres,
 // boundary nodes at panel centres, coefficients of Eq. 6).
 int microwalk_cell(const float* eps, int N, uint64_t seed, uint32_t c1, uint64_t walk, int32_t* steps_out) {
@@ -425,6 +479,49 @@ double cube_half_size(const Structure& S, const double c[3], double R) {
     return -1.0;
 }
 
+// Conductors holding part of the open cube (c-R, c+R), the cube clipped to
+// the window at symmetry walls.
+int conductors_touching(const Structure& S, const double c[3], double R) {
+    int cnt = 0;
+    for (const Box& b : S.cond) {
+        bool touch = true;
+        for (int a = 0; a < 3; ++a) {
+            double lo = c[a] - R, hi = c[a] + R;
+            if (S.bc[2 * a] == 1) lo = std::max(lo, S.wlo[a]);
+            if (S.bc[2 * a + 1] == 1) hi = std::min(hi, S.whi[a]);
+            if (!(b.lo[a] < hi && b.hi[a] > lo)) touch = false;
+        }
+        cnt += touch;
+    }
+    return cnt;
+}
+
+// Expanded-cube size rule of MicroWalk-E (reading; the paper fixes the
+// expansion factor, 5x, and says the lattice is adjusted to the conductors):
+// the half-size is n d / (2 m) with m = max(1, round(n / (2 E))), so that the
+// nearest conductor face or grounded face, at L-infinity distance d, lies on
+// a node plane (m nodes from the centre); it stops at symmetry walls (no
+// larger than the distance from c to any symmetry wall, so no node needs
+// folding), and is halved while more than MAX_BOXES dielectric boxes or
+// MAX_EXP_COND conductors touch the cube; never below d.  At d the ordinary
+// rule applies.  Returns the half-size (<= 0: no valid cube).
+const int MAX_EXP_COND = 7;  // conductors inside one expanded cube
+
+double expanded_half_size(const Structure& S, const double c[3], double d, double E, int n) {
+    const int m = std::max(1, (int)std::lround(n / (2.0 * E)));
+    double R = n * d / (2.0 * m);
+    for (int a = 0; a < 3; ++a) {
+        if (S.bc[2 * a] == 1) R = std::min(R, c[a] - S.wlo[a]);
+        if (S.bc[2 * a + 1] == 1) R = std::min(R, S.whi[a] - c[a]);
+    }
+    R = std::max(R, d);
+    for (int it = 0; it < 64 && R > d; ++it) {
+        if (boxes_touching(S, c, R) <= MAX_BOXES && conductors_touching(S, c, R) <= MAX_EXP_COND) return R;
+        R = std::max(0.5 * R, d);
+    }
+    return cube_half_size(S, c, d);
+}
+
 // Mirror folding of a coordinate at Neumann window faces.
 double fold(const Structure& S, int a, double x) {
     for (int it = 0; it < 64; ++it) {
@@ -531,6 +628,70 @@ void build_cube(const Structure& S, const double c[3], double R, int n, Cube& C)
         C.cls = 2;
         C.axis = -1;
     }
+}
+
+// Absorbing interior nodes of an expanded cube (MicroWalk-E): a node at or
+// beyond a grounded window face belongs to the enclosure (net n_nets); else,
+// after folding at symmetry walls, a node inside or on a conductor box takes
+// that conductor's net (the first such box).  Boundary nodes stay free: the
+// next hop's distance test absorbs a walk that stops inside a conductor.
+std::vector<int32_t> absorbing_nodes(const Structure& S, const Cube& C) {
+    const int n = C.n;
+    std::vector<int32_t> ab((size_t)(n + 1) * (n + 1) * (n + 1), -1);
+    for (int k = 1; k < n; ++k)
+        for (int j = 1; j < n; ++j)
+            for (int i = 1; i < n; ++i) {
+                const int q[3] = {i, j, k};
+                double p[3];
+                int net = -1;
+                for (int a = 0; a < 3; ++a) {
+                    const double x = C.c[a] - C.R + q[a] * C.h;
+                    if ((S.bc[2 * a] == 0 && x <= S.wlo[a]) || (S.bc[2 * a + 1] == 0 && x >= S.whi[a])) net = S.n_nets;
+                    p[a] = fold(S, a, x);
+                }
+                if (net < 0)
+                    for (const Box& b : S.cond)
+                        if (p[0] >= b.lo[0] && p[0] <= b.hi[0] && p[1] >= b.lo[1] && p[1] <= b.hi[1] &&
+                            p[2] >= b.lo[2] && p[2] <= b.hi[2]) {
+                            net = b.net;
+                            break;
+                        }
+                ab[((size_t)k * (n + 1) + j) * (n + 1) + i] = net;
+            }
+    return ab;
+}
+
+// Fraction theta in (0, 1] of the link from node p in direction d at which
+// the segment enters a conductor or reaches a grounded face (bisection).
+struct ThetaCtx {
+    const Structure* S;
+    const Cube* C;
+};
+bool absorbing_point(const Structure& S, const double x[3]) {
+    double p[3];
+    for (int a = 0; a < 3; ++a) {
+        if ((S.bc[2 * a] == 0 && x[a] <= S.wlo[a]) || (S.bc[2 * a + 1] == 0 && x[a] >= S.whi[a])) return true;
+        p[a] = fold(S, a, x[a]);
+    }
+    for (const Box& b : S.cond)
+        if (p[0] >= b.lo[0] && p[0] <= b.hi[0] && p[1] >= b.lo[1] && p[1] <= b.hi[1] && p[2] >= b.lo[2] &&
+            p[2] <= b.hi[2])
+            return true;
+    return false;
+}
+double link_theta(const void* vctx, const int q[3], int d) {
+    const ThetaCtx& T = *(const ThetaCtx*)vctx;
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 40; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        double x[3];
+        for (int a = 0; a < 3; ++a) x[a] = T.C->c[a] - T.C->R + (q[a] + mid * DIR[d][a]) * T.C->h;
+        if (absorbing_point(*T.S, x))
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return std::max(hi, 1.0 / 16.0);
 }
 
 bool stratified_along(const Cube& C, int s) {
@@ -751,6 +912,7 @@ struct FrwParams {
     int hybrid;
     double delta_abs;
     uint64_t seed;
+    double expand = 1.0;  // MicroWalk-E expansion factor (1: plain MicroWalk)
 };
 
 bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P, TableCache& TC, uint64_t walk,
@@ -853,6 +1015,25 @@ bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P
             auto HT = hop_table(TC, n, C.axis, plane_codes(C, C.axis));
             if (!HT) return false;
             hb = sample_index(HT->P, 1.0, rng_word(P.seed, t, walk, PURPOSE_TABLE, 0));
+        } else if (P.expand > 1.0) {
+            // MicroWalk-E: the transition cube grows to E times the
+            // conductor-free size and may hold conductors (Sec. III-B)
+            const double Re = expanded_half_size(S, x, d, P.expand, n);
+            if (Re <= 0) return false;
+            build_cube(S, x, Re, n, C);
+            const std::vector<int32_t> ab = absorbing_nodes(S, C);
+            int32_t steps = 0;
+            int net = -1;
+            ThetaCtx TCx{&S, &C};
+            hb = microwalk_vertex_e(C.e, ab, n, P.seed, t, walk, &steps, &net, link_theta, &TCx);
+            st.micro_steps += (uint64_t)steps;
+            if (hb == -2) {
+                *net_out = net;
+                *omega_out = omega;
+                if (net == S.n_nets) st.env++;
+                return true;
+            }
+            if (hb < 0) return false;
         } else {
             int start[3] = {n / 2, n / 2, n / 2};
             int32_t steps = 0;
@@ -1063,15 +1244,15 @@ int mwo_gauss(const double* cond, int n_cond, int n_nets, const double* win, con
 int mwo_frw_extract(const double* cond, int n_cond, int n_nets, const double* diel, int n_diel,
                     const double* layer_z0, const double* layer_eps, int n_layers, const double* win,
                     const int32_t* bc, int master, uint64_t n_walks, uint64_t first_walk, uint64_t seed, int n,
-                    int hybrid, double abs_tol_rel, int threads, double* row, double* se, int32_t* score_net,
-                    double* score_w, uint64_t* stats) {
+                    int hybrid, double abs_tol_rel, double expand, int threads, double* row, double* se,
+                    int32_t* score_net, double* score_w, uint64_t* stats) {
     if (n < 4 || n % 2 || n_walks < 2) return -1;
     Structure S = make_structure(cond, n_cond, n_nets, diel, n_diel, layer_z0, layer_eps, n_layers, win, bc);
     Gauss G;
     if (!build_gauss(S, master, G)) return -2;
     double diag = 0;
     for (int a = 0; a < 3; ++a) diag += (S.whi[a] - S.wlo[a]) * (S.whi[a] - S.wlo[a]);
-    FrwParams P{n, hybrid, abs_tol_rel * std::sqrt(diag), seed};
+    FrwParams P{n, hybrid, abs_tol_rel * std::sqrt(diag), seed, expand < 1.0 ? 1.0 : expand};
     TableCache TC;
     std::vector<int32_t> nets(n_walks);
     std::vector<double> om(n_walks);

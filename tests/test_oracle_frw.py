@@ -116,3 +116,46 @@ def test_cube_classification(oracle_lib):
     assert cls == (1, 0)  # wire end: coating face normal to x
     _, cls = oracle_lib.build_cube(st, [1.83, 0.97, 0.35], 0.029, 16)
     assert cls[0] == 2  # coating edge at the wire end
+
+
+# ---------------------------------------------------------------------------
+# MicroWalk-E (Sec. III-B, Fig. 3(b)): expanded transition cubes that may
+# hold conductors.  The paper gives the expansion factor (5x) and notes the
+# coarser lattice may cost some accuracy; the lattice treatment near
+# conductors (Shortley-Weller links) is a reading.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("variant", ["uniform", "columns", "series"])
+def test_microwalk_e_plates_closed_forms(oracle_lib, variant):
+    """Every non-first hop through MicroWalk-E (hybrid off): parallel plates
+    within 1 % + 3 SE of the closed form (links cut at the plate faces keep
+    the linear potential exact; the first transition is the usual one)."""
+    st = W.parallel_plates(variant)
+    exact = W.parallel_plates_exact(variant)
+    r = oracle_lib.frw_extract(st, 0, 100000, seed=31, threads=8, hybrid=0, expand=5.0)
+    print(variant, r["row"][0] / exact - 1, r["se"][0] / exact, r["stats"])
+    assert abs(r["row"][0] - exact) < 0.01 * exact + 3 * r["se"][0]
+    assert r["stats"]["micro_steps"] > 0
+
+
+def test_microwalk_e_factor_one_is_plain_microwalk(oracle_lib):
+    st = W.c2_structure()
+    a = oracle_lib.frw_extract(st, 0, 3000, seed=2, threads=4, scores=True)
+    b = oracle_lib.frw_extract(st, 0, 3000, seed=2, threads=4, scores=True, expand=1.0)
+    assert np.array_equal(a["net"], b["net"]) and np.array_equal(a["w"], b["w"])
+
+
+def test_microwalk_e_c2_fewer_hops_close_row(oracle_lib):
+    """C2: MicroWalk-E needs a fraction of the hops and micro-steps of
+    MicroWalk; its row stays within the coarser lattice's few-percent bias
+    (C_mm within 4 % + 3 combined SE)."""
+    st = W.c2_structure()
+    e = oracle_lib.frw_extract(st, 0, 60000, seed=8, threads=8, expand=5.0)
+    p = oracle_lib.frw_extract(st, 0, 60000, seed=9, threads=8)
+    print("E", e["row"], e["stats"])
+    print("plain", p["row"], p["stats"])
+    assert e["stats"]["hops"] * 2 < p["stats"]["hops"]
+    assert e["stats"]["micro_steps"] * 4 < p["stats"]["micro_steps"]
+    comb = np.hypot(e["se"][0], p["se"][0])
+    assert abs(e["row"][0] - p["row"][0]) < 0.04 * p["row"][0] + 3 * comb
+    # Maxwell signs hold for the E rows too
+    assert e["row"][0] > 0 and np.all(e["row"][1:] <= 3 * e["se"][1:])
