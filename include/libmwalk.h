@@ -211,7 +211,20 @@ typedef struct {
                                  the exact SGF table, the rest MicroWalk
                                  (Sec. III-C); 0: every non-first cube uses
                                  MicroWalk                                  */
-    int32_t reserved0, reserved1;
+    int32_t expand;           /* MicroWalk-E (Sec. III-B, Fig. 3(b)): 0 or 1
+                                 off; E > 1: MicroWalk hops use cubes of
+                                 half-size n d / (2 m), m = max(1,
+                                 round(n / (2 E))), d the conductor-free
+                                 half-size (E = 5, n = 16: 4 d), which may
+                                 hold conductors: walks reaching a node inside
+                                 a conductor or beyond a grounded face end
+                                 there, links into such nodes are cut at the
+                                 face (Shortley-Weller).  The cube stops at
+                                 symmetry walls and is halved, not below d,
+                                 while it touches more than 16 dielectric
+                                 boxes or 7 conductors.  n / (2 m) may not
+                                 exceed 4.                                  */
+    int32_t reserved1;
     double target_rel_3sigma; /* stop when 3*SE(C_mm)/|C_mm| <= target; 0 =
                                  run exactly walk_budget walks              */
     double abs_tol_rel;       /* absorption distance / window diagonal;

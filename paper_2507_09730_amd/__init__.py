@@ -241,7 +241,7 @@ class mw_structure_desc(ctypes.Structure):
 
 class frw_options(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int32), ("hybrid", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("expand", ctypes.c_int32), ("reserved1", ctypes.c_int32),
                 ("target_rel_3sigma", ctypes.c_double), ("abs_tol_rel", ctypes.c_double),
                 ("first_walk", ctypes.c_uint64), ("batch_walks", ctypes.c_uint64)]
 
@@ -316,7 +316,7 @@ def mw_structure_destroy(handle):
 
 def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
                 target_rel_3sigma=0.0, abs_tol_rel=1e-6, first_walk=0, batch_walks=0,
-                scores=False, device="cuda"):
+                scores=False, device="cuda", expand=0):
     """Alg. 1: one capacitance row (fF, last entry = grounded enclosure) and
     its standard errors.  With scores=True also returns the per-walk net and
     fp32 weight (CUDA tensors)."""
@@ -327,7 +327,7 @@ def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
     row = (ctypes.c_double * K)()
     se = (ctypes.c_double * K)()
     stats = frw_stats()
-    opt = frw_options(n_cells, hybrid, 0, 0, target_rel_3sigma, abs_tol_rel, first_walk,
+    opt = frw_options(n_cells, hybrid, expand, 0, target_rel_3sigma, abs_tol_rel, first_walk,
                       batch_walks)
     net = w = None
     if scores:
@@ -345,7 +345,7 @@ def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
 
 
 def frw_extract_matrix(structure, walks_per_master, seed=0, masters=None, n_cells=16, hybrid=1,
-                       target_rel_3sigma=0.0, abs_tol_rel=1e-6, first_walk=0, batch_walks=0):
+                       target_rel_3sigma=0.0, abs_tol_rel=1e-6, first_walk=0, batch_walks=0, expand=0):
     """Capacitance-matrix rows for several masters (default: every net) in
     shared rounds.  Returns {"cap": (M, K) rows, "se": (M, K), "sym": (M, M)
     symmetrised block, "masters": list, "stats": dict}; master i uses seed + i."""
@@ -360,7 +360,7 @@ def frw_extract_matrix(structure, walks_per_master, seed=0, masters=None, n_cell
     se = np.zeros((M, K))
     sym = np.zeros((M, M))
     stats = frw_stats()
-    opt = frw_options(n_cells, hybrid, 0, 0, target_rel_3sigma, abs_tol_rel, first_walk, batch_walks)
+    opt = frw_options(n_cells, hybrid, expand, 0, target_rel_3sigma, abs_tol_rel, first_walk, batch_walks)
     _check(_lib.frw_extract_matrix(structure.handle, I32(M), _vp(m), U64(walks_per_master), U64(seed),
                                    ctypes.byref(opt), _vp(cap), _vp(se), _vp(sym), ctypes.byref(stats)))
     return {"cap": cap, "se": se, "sym": sym, "masters": [int(x) for x in m], "stats": stats.as_dict()}
@@ -391,8 +391,8 @@ class Server:
     """Request loop over the device (mw_server_*): submit structures, poll rows."""
 
     def __init__(self, hbm_budget_bytes, n_cells=16, hybrid=1, target_rel_3sigma=0.0,
-                 abs_tol_rel=1e-6):
-        opt = frw_options(n_cells, hybrid, 0, 0, target_rel_3sigma, abs_tol_rel, 0, 0)
+                 abs_tol_rel=1e-6, expand=0):
+        opt = frw_options(n_cells, hybrid, expand, 0, target_rel_3sigma, abs_tol_rel, 0, 0)
         h = ctypes.c_void_p()
         _check(_lib.mw_server_create(ctypes.c_size_t(int(hbm_budget_bytes)), ctypes.byref(opt),
                                      ctypes.byref(h)))

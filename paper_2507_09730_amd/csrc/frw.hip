@@ -45,6 +45,10 @@ constexpr uint32_t NO_INDEX = 0xffffffffu;
 
 enum ErrBits : uint32_t { ERR_REGIONS = 1, ERR_TABLE_CAP = 2, ERR_PARK_CAP = 4, ERR_STEP_CAP = 8 };
 constexpr uint32_t MW_STEP_CAP = 1u << 26;
+// MicroWalk-E: expanded cubes reach at most EXP_LIST_FACTOR times the
+// conductor-free half-size and hold at most EXP_MAX_COND conductors.
+constexpr float EXP_LIST_FACTOR = 4.f;
+constexpr int EXP_MAX_COND = 7;
 
 // -------------------------------------------------------------------------
 // Device structure descriptor.
@@ -66,6 +70,12 @@ struct StructDev {
     const uint32_t* gc_list;
     const uint32_t* gd_off;
     const uint32_t* gd_list;
+    // candidates of expanded (MicroWalk-E) cubes: conductors and dielectric
+    // boxes within EXP_LIST_FACTOR times the cell's conductor-free distance
+    const uint32_t* ge_off;
+    const uint32_t* ge_list;
+    const uint32_t* gx_off;
+    const uint32_t* gx_list;
     float delta_abs;
 };
 
@@ -144,6 +154,7 @@ struct WalkArgs {
     Counters* ctr;
     uint32_t lane_stride;   // dwords of LDS per lane (odd)
     uint32_t uniform_index; // table of the uniform cube
+    int32_t expand_m;       // MicroWalk-E: expanded half-size n d / (2 m) (EXP kernels)
 };
 
 // First transitions of a batch of walks (one lane per walk).
@@ -287,6 +298,37 @@ __device__ __forceinline__ uint32_t cell_code(LaneCube L, uint32_t m, uint32_t b
     return m ? L.codes[hb16(m)] : b;
 }
 
+// MicroWalk-E additions to a lane's LDS, after the LaneCube arrays:
+// nmask[a * (n + 1) + i]: bit b < EXP_MAX_COND: conductor bit b (closed box)
+// holds coordinate i of axis a; bit 7: coordinate i of axis a lies at or
+// beyond a grounded window face.  cnet[b]: net of conductor bit b.
+// theta[(b * 3 + a) * 2 + side] / 65535: fraction of the link from the free
+// node next to object b (b = 7: the grounded faces) along axis a at which it
+// enters the object — side 0 through the object's low face (a +a move),
+// side 1 through its high face (a -a move).
+struct LaneExp {
+    uint8_t* nmask;
+    uint16_t* cnet;
+    uint16_t* theta;
+};
+
+__device__ __forceinline__ int lane_base_words(int n) { return (3 * n + 1) / 2 + MAX_REGIONS + n; }
+__host__ __device__ __forceinline__ int lane_exp_words(int n) { return (3 * (n + 1) + 3) / 4 + 4 + 24; }
+
+__device__ __forceinline__ LaneExp lane_exp(uint32_t* my, int n) {
+    LaneExp E;
+    uint32_t* q = my + lane_base_words(n);
+    E.nmask = reinterpret_cast<uint8_t*>(q);
+    q += (3 * (n + 1) + 3) / 4;
+    E.cnet = reinterpret_cast<uint16_t*>(q);
+    E.theta = reinterpret_cast<uint16_t*>(q + 4);
+    return E;
+}
+
+__device__ __forceinline__ uint16_t theta_q(float th) {
+    return (uint16_t)fminf(65535.f, fmaxf(4096.f, rintf(th * 65535.f)));  // theta >= 1/16
+}
+
 struct CubeInfo {
     uint32_t present, A[3];
     int n_layers;  // background layers holding at least one cell centre
@@ -299,7 +341,7 @@ struct CubeInfo {
 // Regions are the dielectric boxes (bits, priority = list order) and the
 // background layers (per-z-cell codes); a region is present when it holds at
 // least one cell centre.
-__device__ CubeInfo build_cube(SRef S, int cell, float3 c, float R, int n, LaneCube L) {
+__device__ CubeInfo build_cube(SRef S, int cell, float3 c, float R, int n, LaneCube L, bool expanded = false) {
     CubeInfo info{};
     const float h = 2.f * R / (float)n;
     const float lo0[3] = {c.x - R, c.y - R, c.z - R};
@@ -342,8 +384,9 @@ __device__ CubeInfo build_cube(SRef S, int cell, float3 c, float R, int n, LaneC
     // dielectric boxes touching the cube, in priority order (the next box's
     // record is fetched while the current one is processed)
     int nbits = 0;
-    const uint32_t b = gp(S.gd_off)[cell], e = gp(S.gd_off)[cell + 1];
-    const GAS uint32_t* glist = gp(S.gd_list);
+    const uint32_t* doff = expanded ? S.gx_off : S.gd_off;
+    const uint32_t b = gp(doff)[cell], e = gp(doff)[cell + 1];
+    const GAS uint32_t* glist = gp(expanded ? S.gx_list : S.gd_list);
     float4 nlo = make_float4(0.f, 0.f, 0.f, 0.f), nhi = nlo;
     if (b < e) {
         const uint32_t id = glist[b];
@@ -440,6 +483,85 @@ __device__ CubeInfo build_cube(SRef S, int cell, float3 c, float R, int n, LaneC
         info.axis = -1;
     }
     return info;
+}
+
+// Absorbing nodes of an expanded cube centred at c with half-size R (the
+// cube never crosses a symmetry wall): grounded faces first, then the
+// conductors holding part of the open cube, in candidate-list (index) order.
+// False when more than EXP_MAX_COND conductors do.
+__device__ bool build_conductors(SRef S, int cell, float3 c, float R, int n, LaneExp E) {
+    const float h = 2.f * R / (float)n;
+    const float o[3] = {c.x - R, c.y - R, c.z - R};
+    const int np = n + 1;
+    uint32_t* m32 = reinterpret_cast<uint32_t*>(E.nmask);
+    for (int q = 0; q < (3 * np + 3) / 4; ++q) m32[q] = 0u;
+    // toggles (bit flips where a run of nodes starts or ends), then prefix xor
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (S.bc[2 * a] == MW_BC_DIRICHLET && o[a] <= S.wlo[a]) {
+            const float u = (S.wlo[a] - o[a]) / h;  // nodes i <= u are at/beyond the face
+            const int iw = min((int)floorf(u), n);
+            E.nmask[a * np] ^= 0x80u;
+            if (iw + 1 <= n) E.nmask[a * np + iw + 1] ^= 0x80u;
+            E.theta[(7 * 3 + a) * 2 + 1] = theta_q((float)(iw + 1) - u);
+        }
+        if (S.bc[2 * a + 1] == MW_BC_DIRICHLET && o[a] + 2.f * R >= S.whi[a]) {
+            const float u = (S.whi[a] - o[a]) / h;  // nodes i >= u
+            const int iw = max((int)ceilf(u), 0);
+            if (iw <= n) E.nmask[a * np + iw] ^= 0x80u;
+            E.theta[(7 * 3 + a) * 2 + 0] = theta_q(u - (float)(iw - 1));
+        }
+    }
+    int nb = 0;
+    const uint32_t b = gp(S.ge_off)[cell], e = gp(S.ge_off)[cell + 1];
+    const GAS uint32_t* clist = gp(S.ge_list);
+    for (uint32_t q = b; q < e; ++q) {
+        const uint32_t id = clist[q];
+        const float4 lo4 = ldf4(S.cond_lo + id), hi4 = ldf4(S.cond_hi + id);
+        const float bl[3] = {lo4.x, lo4.y, lo4.z}, bh[3] = {hi4.x, hi4.y, hi4.z};
+        bool touch = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (!(bl[a] < o[a] + 2.f * R && bh[a] > o[a])) touch = false;
+        if (!touch) continue;
+        if (nb >= EXP_MAX_COND) return false;
+        const uint8_t bit = (uint8_t)(1u << nb);
+        E.cnet[nb] = (uint16_t)__float_as_int(lo4.w);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float u0 = (bl[a] - o[a]) / h, u1 = (bh[a] - o[a]) / h;
+            const int i0 = max((int)ceilf(u0), 0), i1 = min((int)floorf(u1), n);
+            if (i0 <= i1) {
+                E.nmask[a * np + i0] ^= bit;
+                if (i1 + 1 <= n) E.nmask[a * np + i1 + 1] ^= bit;
+            }
+            E.theta[(nb * 3 + a) * 2 + 0] = theta_q(u0 - (float)(i0 - 1));
+            E.theta[(nb * 3 + a) * 2 + 1] = theta_q((float)(i1 + 1) - u1);
+        }
+        ++nb;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        uint32_t m = 0;
+        for (int i = 0; i < np; ++i) {
+            m ^= E.nmask[a * np + i];
+            E.nmask[a * np + i] = (uint8_t)m;
+        }
+    }
+    return true;
+}
+
+// Half-size of the expanded cube (before the halving rule): n d / (2 m),
+// stopped at symmetry walls, never below d.
+__device__ __forceinline__ float expanded_size(SRef S, float3 c, float d, int n, int m) {
+    float R = (float)n * d / (float)(2 * m);
+    const float cc[3] = {c.x, c.y, c.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (S.bc[2 * a] == MW_BC_NEUMANN) R = fminf(R, cc[a] - S.wlo[a]);
+        if (S.bc[2 * a + 1] == MW_BC_NEUMANN) R = fminf(R, S.whi[a] - cc[a]);
+    }
+    return fmaxf(R, d);
 }
 
 __device__ __forceinline__ bool stratified_along(const CubeInfo& I, int s) {
@@ -795,6 +917,146 @@ __device__ __forceinline__ bool mw_block(MwState& M, LaneCube L, int n, const Ra
     return alive;
 }
 
+// MicroWalk-E steps: node masks of the current node and its two neighbours
+// per axis, kept in registers.
+struct MwStateE {
+    uint32_t xm, xc, xp, ym, yc, yp, zm, zc, zp;
+};
+
+__device__ __forceinline__ void mw_begin_e(const MwState& M, MwStateE& Q, LaneExp E, int n) {
+    const int np = n + 1;
+    Q.xm = E.nmask[M.ni - 1];
+    Q.xc = E.nmask[M.ni];
+    Q.xp = E.nmask[M.ni + 1];
+    Q.ym = E.nmask[np + M.nj - 1];
+    Q.yc = E.nmask[np + M.nj];
+    Q.yp = E.nmask[np + M.nj + 1];
+    Q.zm = E.nmask[2 * np + M.nk - 1];
+    Q.zc = E.nmask[2 * np + M.nk];
+    Q.zp = E.nmask[2 * np + M.nk + 1];
+}
+
+// Code of a link cut at fraction tq / 65535 of its length: rint(g / theta).
+__device__ __forceinline__ uint32_t cut_link(uint32_t g, uint32_t tq) {
+    return (uint32_t)(((uint64_t)g * 65535u + (tq >> 1)) / tq);
+}
+
+// Up to four MicroWalk-E steps (one Philox block).  Returns 0 while the walk
+// is inside, 1 when it reached a boundary node, 2 when it reached an
+// absorbing node (*net: the conductor's net, or env_net beyond a grounded
+// face).  Links into absorbing nodes are cut where they enter the object.
+__device__ __forceinline__ int mw_block_e(MwState& M, MwStateE& Q, LaneCube L, LaneExp E, int n, const Rand4& r,
+                                          int env_net, int* net) {
+    const uint32_t us[4] = {r.x, r.y, r.z, r.w};
+    const int np = n + 1;
+    int st = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (st == 0) {
+            const uint32_t m000 = M.mx0 & M.my0 & M.mz0, m001 = M.mx1 & M.my0 & M.mz0;
+            const uint32_t m010 = M.mx0 & M.my1 & M.mz0, m011 = M.mx1 & M.my1 & M.mz0;
+            const uint32_t m100 = M.mx0 & M.my0 & M.mz1, m101 = M.mx1 & M.my0 & M.mz1;
+            const uint32_t m110 = M.mx0 & M.my1 & M.mz1, m111 = M.mx1 & M.my1 & M.mz1;
+            const uint32_t c000 = cell_code(L, m000, M.bz0), c001 = cell_code(L, m001, M.bz0);
+            const uint32_t c010 = cell_code(L, m010, M.bz0), c011 = cell_code(L, m011, M.bz0);
+            const uint32_t c100 = cell_code(L, m100, M.bz1), c101 = cell_code(L, m101, M.bz1);
+            const uint32_t c110 = cell_code(L, m110, M.bz1), c111 = cell_code(L, m111, M.bz1);
+            const uint32_t a0 = c000 + c100, a1 = c010 + c110;
+            const uint32_t b0 = c001 + c101, b1 = c011 + c111;
+            // links -x, +x, -y, +y, -z, +z
+            uint32_t g[6] = {a0 + a1, b0 + b1, a0 + b0, a1 + b1, c000 + c001 + c010 + c011,
+                             c100 + c101 + c110 + c111};
+            const uint32_t nx[6] = {Q.xm, Q.xp, Q.xc, Q.xc, Q.xc, Q.xc};
+            const uint32_t ny[6] = {Q.yc, Q.yc, Q.ym, Q.yp, Q.yc, Q.yc};
+            const uint32_t nz[6] = {Q.zc, Q.zc, Q.zc, Q.zc, Q.zm, Q.zp};
+#pragma unroll
+            for (int dd = 0; dd < 6; ++dd) {
+                const uint32_t env = (nx[dd] | ny[dd] | nz[dd]) & 0x80u;
+                const uint32_t cm = nx[dd] & ny[dd] & nz[dd] & 0x7fu;
+                if (env | cm) {
+                    const int b = env ? 7 : __ffs(cm) - 1;
+                    g[dd] = cut_link(g[dd], E.theta[(b * 3 + (dd >> 1)) * 2 + ((dd & 1) ? 0 : 1)]);
+                }
+            }
+            const uint32_t S0 = g[0], S1 = S0 + g[1], S2 = S1 + g[2], S3 = S2 + g[3], S4 = S3 + g[4];
+            const uint32_t S5 = S4 + g[5];
+            const uint32_t xq = __umulhi(us[q], S5);
+            const uint32_t d = (uint32_t)(xq >= S0) + (uint32_t)(xq >= S1) + (uint32_t)(xq >= S2) +
+                               (uint32_t)(xq >= S3) + (uint32_t)(xq >= S4);
+            const int ax = (int)(d >> 1);
+            const bool up = (d & 1u) != 0;
+            ++M.s;
+            int cnew;
+            if (ax == 0) {
+                M.ni += up ? 1 : -1;
+                cnew = M.ni;
+                if (up) {
+                    Q.xm = Q.xc;
+                    Q.xc = Q.xp;
+                    Q.xp = E.nmask[min(cnew + 1, n)];
+                } else {
+                    Q.xp = Q.xc;
+                    Q.xc = Q.xm;
+                    Q.xm = E.nmask[max(cnew - 1, 0)];
+                }
+            } else if (ax == 1) {
+                M.nj += up ? 1 : -1;
+                cnew = M.nj;
+                if (up) {
+                    Q.ym = Q.yc;
+                    Q.yc = Q.yp;
+                    Q.yp = E.nmask[np + min(cnew + 1, n)];
+                } else {
+                    Q.yp = Q.yc;
+                    Q.yc = Q.ym;
+                    Q.ym = E.nmask[np + max(cnew - 1, 0)];
+                }
+            } else {
+                M.nk += up ? 1 : -1;
+                cnew = M.nk;
+                if (up) {
+                    Q.zm = Q.zc;
+                    Q.zc = Q.zp;
+                    Q.zp = E.nmask[2 * np + min(cnew + 1, n)];
+                } else {
+                    Q.zp = Q.zc;
+                    Q.zc = Q.zm;
+                    Q.zm = E.nmask[2 * np + max(cnew - 1, 0)];
+                }
+            }
+            if (cnew == 0 || cnew == n) {
+                st = 1;
+            } else {
+                const uint32_t env = (Q.xc | Q.yc | Q.zc) & 0x80u;
+                const uint32_t cm = Q.xc & Q.yc & Q.zc & 0x7fu;
+                if (env) {
+                    st = 2;
+                    *net = env_net;
+                } else if (cm) {
+                    st = 2;
+                    *net = E.cnet[__ffs(cm) - 1];
+                } else {
+                    // cell masks of the new node
+                    const uint32_t lo = L.mask[ax * n + cnew - 1], hi = L.mask[ax * n + cnew];
+                    if (ax == 0) {
+                        M.mx0 = lo;
+                        M.mx1 = hi;
+                    } else if (ax == 1) {
+                        M.my0 = lo;
+                        M.my1 = hi;
+                    } else {
+                        M.mz0 = lo;
+                        M.mz1 = hi;
+                        M.bz0 = L.bz[cnew - 1];
+                        M.bz1 = L.bz[cnew];
+                    }
+                }
+            }
+        }
+    }
+    return st;
+}
+
 // -------------------------------------------------------------------------
 // Walker kernel: transitions after the first, until absorption.  A lane
 // holds one walk; lanes whose next cube is not stratified run MicroWalk in
@@ -838,13 +1100,15 @@ struct WaveClaim {
     }
 };
 
-template <bool MULTI>
+// EXP: MicroWalk hops use expanded cubes (MicroWalk-E).
+template <bool MULTI, bool EXP>
 __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     extern __shared__ uint32_t lds[];
     const int n = A.n;
     const int lane = threadIdx.x & 63;
     uint32_t* my = lds + threadIdx.x * A.lane_stride;
     const LaneCube L = lane_cube(my, n);
+    const LaneExp E = lane_exp(my, n);  // used by EXP kernels only
 
     Counters& K = *A.ctr;
     unsigned long long c_hops = 0, c_steps = 0, c_cls[3] = {0, 0, 0}, c_env = 0, c_cap = 0;
@@ -862,6 +1126,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     float3 mc = pos;
     float mR = 0.f;
     MwState M{};
+    MwStateE Q{};
+    int env_net = 0;
 
     for (;;) {
         // ---- take work: resumed walks first, then fresh walk ids ----
@@ -918,9 +1184,11 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
             float R;
             float3 x;
             int cell;
+            float dq;  // conductor-free half-size before the cube-size rule
             {
                 cell = grid_cell(S, pos);
                 R = query_dist(S, pos, cell, &net);
+                dq = R;
                 c = pos;
                 if (R <= S.delta_abs) {
                     done = true;
@@ -982,7 +1250,27 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                         mc = c;
                         mR = R;
                         phase = PH_MW;
-                        mw_begin(M, L, n);
+                        if (EXP) {
+                            // MicroWalk-E: the cube grows to n dq / (2 m)
+                            // and may hold conductors; halved (not below
+                            // dq) while it holds too many boxes or
+                            // conductors, then by the ordinary rule
+                            float Re = expanded_size(S, c, dq, n, A.expand_m);
+                            bool ok = false;
+                            for (int it = 0;; ++it) {
+                                const CubeInfo IE = build_cube(S, cell, c, Re, n, L, true);
+                                ok = !IE.overflow && build_conductors(S, cell, c, Re, n, E);
+                                if (ok || it >= 110) break;
+                                Re = Re > dq ? fmaxf(0.5f * Re, dq) : 0.5f * Re;
+                            }
+                            if (!ok) err |= ERR_REGIONS;
+                            mR = Re;
+                            env_net = S.n_nets;
+                            mw_begin(M, L, n);
+                            mw_begin_e(M, Q, E, n);
+                        } else {
+                            mw_begin(M, L, n);
+                        }
                     }
                 }
             }
@@ -1020,7 +1308,9 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
             if (phase == PH_MW) {
                 const GAS Segment& SG = gp(A.segs)[sg];
                 const Rand4 r = philox10(M.s >> 2, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), SG.k0, SG.k1);
-                bool alive = mw_block(M, L, n, r);
+                int anet = 0;
+                const int stt = EXP ? mw_block_e(M, Q, L, E, n, r, env_net, &anet) : (mw_block(M, L, n, r) ? 0 : 1);
+                bool alive = stt == 0;
                 if (alive && M.s >= MW_STEP_CAP) {
                     // never reached for valid permittivities; keeps a logic
                     // error from spinning: the walk ends where it stands and
@@ -1028,7 +1318,15 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                     err |= ERR_STEP_CAP;
                     alive = false;
                 }
-                if (!alive) {
+                if (EXP && stt == 2) {
+                    // MicroWalk-E reached a conductor or the grounded enclosure
+                    c_steps += M.s;
+                    const unsigned long long k = walk - SG.walk_begin;
+                    if (anet == env_net) ++c_env;
+                    gpw(SG.score_net)[k] = anet;
+                    gpw(SG.score_w)[k] = omega;
+                    phase = PH_IDLE;
+                } else if (!alive) {
                     c_steps += M.s;
                     const float h = 2.f * mR / (float)n;
                     const float3 xx = make_float3(mc.x - mR + (float)M.ni * h, mc.y - mR + (float)M.nj * h,
@@ -1465,12 +1763,15 @@ __device__ float cell_dfar(const StructDev& S, const float lo[3], const float hi
     return dfar * 1.0001f + 1e-6f;
 }
 
-__global__ void grid_count_kernel(StructDev S, uint32_t* ccount, uint32_t* dcount, int ncells) {
+// Candidate counts and lists per grid cell: conductors within factor x the
+// cell's conductor-free distance (factor 1: the conductors that can be
+// nearest) and dielectric boxes within the same range.
+__global__ void grid_count_kernel(StructDev S, uint32_t* ccount, uint32_t* dcount, int ncells, float factor) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncells) return;
     float lo[3], hi[3];
     cell_box(S, c, lo, hi);
-    const float dfar = cell_dfar(S, lo, hi);
+    const float dfar = cell_dfar(S, lo, hi) * factor;
     uint32_t nc = 0, nd = 0;
     for (int q = 0; q < S.n_cond; ++q) {
         const float4 bl = S.cond_lo[q], bh = S.cond_hi[q];
@@ -1491,12 +1792,12 @@ __global__ void grid_count_kernel(StructDev S, uint32_t* ccount, uint32_t* dcoun
 }
 
 __global__ void grid_fill_kernel(StructDev S, const uint32_t* coff, const uint32_t* doff, uint32_t* clist,
-                                 uint32_t* dlist, int ncells) {
+                                 uint32_t* dlist, int ncells, float factor) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncells) return;
     float lo[3], hi[3];
     cell_box(S, c, lo, hi);
-    const float dfar = cell_dfar(S, lo, hi);
+    const float dfar = cell_dfar(S, lo, hi) * factor;
     uint32_t pc = coff[c], pd = doff[c];
     for (int q = 0; q < S.n_cond; ++q) {
         const float4 bl = S.cond_lo[q], bh = S.cond_hi[q];
@@ -1780,6 +2081,8 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
         const size_t o_z0 = sz(4 * nl), o_lc = sz(4 * nl);
         const size_t o_cc = sz(4 * ncells), o_dc = sz(4 * ncells), o_coff = sz(4 * (ncells + 1)),
                      o_doff = sz(4 * (ncells + 1));
+        const size_t o_ecc = sz(4 * ncells), o_edc = sz(4 * ncells), o_eoff = sz(4 * (ncells + 1)),
+                     o_xoff = sz(4 * (ncells + 1));
         const size_t o_desc = sz(sizeof(StructDev));
         char* m = (char*)dev_alloc(o);
         struct Guard {
@@ -1822,31 +2125,53 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
         uint32_t* dcount = (uint32_t*)(m + o_dc);
         uint32_t* coff = (uint32_t*)(m + o_coff);
         uint32_t* doff = (uint32_t*)(m + o_doff);
+        uint32_t* ecount = (uint32_t*)(m + o_ecc);
+        uint32_t* xcount = (uint32_t*)(m + o_edc);
+        uint32_t* eoff = (uint32_t*)(m + o_eoff);
+        uint32_t* xoff = (uint32_t*)(m + o_xoff);
         const int tb = 128, nbk = (ncells + tb - 1) / tb;
-        grid_count_kernel<<<nbk, tb>>>(S, ccount, dcount, ncells);
+        grid_count_kernel<<<nbk, tb>>>(S, ccount, dcount, ncells, 1.f);
+        grid_count_kernel<<<nbk, tb>>>(S, ecount, xcount, ncells, EXP_LIST_FACTOR);
         scan_kernel<<<1, 1024>>>(ccount, coff, ncells);
         scan_kernel<<<1, 1024>>>(dcount, doff, ncells);
+        scan_kernel<<<1, 1024>>>(ecount, eoff, ncells);
+        scan_kernel<<<1, 1024>>>(xcount, xoff, ncells);
         MW_HIP(hipGetLastError());
-        uint32_t tot[2];
+        uint32_t tot[4];
         MW_HIP(hipMemcpy(&tot[0], coff + ncells, 4, hipMemcpyDeviceToHost));
         MW_HIP(hipMemcpy(&tot[1], doff + ncells, 4, hipMemcpyDeviceToHost));
-        const size_t list_bytes = 4ull * (tot[0] + tot[1]) + 512;
+        MW_HIP(hipMemcpy(&tot[2], eoff + ncells, 4, hipMemcpyDeviceToHost));
+        MW_HIP(hipMemcpy(&tot[3], xoff + ncells, 4, hipMemcpyDeviceToHost));
+        size_t lo4[4], lb = 0;
+        for (int q = 0; q < 4; ++q) {
+            lo4[q] = lb;
+            lb += ((4ull * tot[q] + 255) / 256) * 256;
+        }
+        const size_t list_bytes = lb + 512;
         char* lists = (char*)dev_alloc(list_bytes);
         st->bytes = o + list_bytes;
-        uint32_t* clist = (uint32_t*)lists;
-        uint32_t* dlist = (uint32_t*)(lists + ((4ull * tot[0] + 255) / 256) * 256);
-        grid_fill_kernel<<<nbk, tb>>>(S, coff, doff, clist, dlist, ncells);
+        uint32_t* clist = (uint32_t*)(lists + lo4[0]);
+        uint32_t* dlist = (uint32_t*)(lists + lo4[1]);
+        uint32_t* elist = (uint32_t*)(lists + lo4[2]);
+        uint32_t* xlist = (uint32_t*)(lists + lo4[3]);
+        grid_fill_kernel<<<nbk, tb>>>(S, coff, doff, clist, dlist, ncells, 1.f);
+        grid_fill_kernel<<<nbk, tb>>>(S, eoff, xoff, elist, xlist, ncells, EXP_LIST_FACTOR);
         MW_HIP(hipGetLastError());
         S.gc_off = coff;
         S.gc_list = clist;
         S.gd_off = doff;
         S.gd_list = dlist;
+        S.ge_off = eoff;
+        S.ge_list = elist;
+        S.gx_off = xoff;
+        S.gx_list = xlist;
         st->d = (StructDev*)(m + o_desc);
         MW_HIP(hipMemcpy(st->d, &S, sizeof S, hipMemcpyHostToDevice));
         MW_HIP(hipDeviceSynchronize());
         st->mem = m;
         guard.keep = true;
-        // the list block is owned through a second pointer kept in h
+        // the list block (starting with the conductor list) is owned
+        // through the pointer kept in h.gc_list
         st->h.gc_list = clist;
         *out = st.release();
         (void)lists;
@@ -1867,9 +2192,9 @@ namespace {
 
 // Launch geometry of the FRW kernels for lattice size n.
 struct LaunchGeom {
-    uint32_t lane_stride, first_stride;
-    size_t lds, first_lds;
-    int blocks, first_blocks;
+    uint32_t lane_stride, first_stride, lane_stride_e;
+    size_t lds, first_lds, lds_e;
+    int blocks, first_blocks, blocks_e;
     uint64_t pool;
 };
 
@@ -1887,6 +2212,10 @@ LaunchGeom launch_geom(int n) {
     // LDS is allocated in 512-byte granules; 16 waves per CU is the VGPR limit
     g.blocks = cus * std::max(1, std::min(16, (int)(163840 / ((g.lds + 511) / 512 * 512))));
     g.first_blocks = cus * std::max(1, std::min(8, (int)(163840 / (g.first_lds + 512))));
+    // MicroWalk-E lanes also hold the expanded cube's node masks
+    g.lane_stride_e = (uint32_t)(g.lane_stride + lane_exp_words(n)) | 1u;
+    g.lds_e = (size_t)g.lane_stride_e * 4 * WALK_THREADS;
+    g.blocks_e = cus * std::max(1, std::min(16, (int)(163840 / ((g.lds_e + 511) / 512 * 512))));
     g.pool = (uint64_t)g.blocks * WALK_THREADS;
     return g;
 }
@@ -1897,6 +2226,7 @@ LaunchGeom launch_geom(int n) {
 // lattice size while it runs.
 struct Runner {
     int n, hybrid;
+    int expand_m = 0;  // MicroWalk-E when > 0 (expanded half-size n d / (2 m))
     Cache* cache;
     LaunchGeom g;
     uint32_t park_cap;
@@ -1937,8 +2267,10 @@ struct Runner {
         dsegs = (Segment*)(mem + o_sg);
         MW_HIP(hipEventCreate(&ev0));
         MW_HIP(hipEventCreate(&ev1));
-        set_lds(frw_walk_kernel<false>, g.lds);
-        set_lds(frw_walk_kernel<true>, g.lds);
+        set_lds(frw_walk_kernel<false, false>, g.lds);
+        set_lds(frw_walk_kernel<true, false>, g.lds);
+        set_lds(frw_walk_kernel<false, true>, g.lds_e);
+        set_lds(frw_walk_kernel<true, true>, g.lds_e);
         set_lds(first_kernel, g.first_lds);
     }
     ~Runner() {
@@ -2062,10 +2394,18 @@ struct Runner {
             MW_HIP(hipMemset(&ctr->park_count, 0, 4));
             MW_HIP(hipMemset(&ctr->resume_next, 0, 8));
             MW_HIP(hipEventRecord(ev0, 0));
-            if (multi)
-                frw_walk_kernel<true><<<g.blocks, WALK_THREADS, g.lds>>>(W);
-            else
-                frw_walk_kernel<false><<<g.blocks, WALK_THREADS, g.lds>>>(W);
+            if (expand_m > 0) {
+                W.lane_stride = g.lane_stride_e;
+                W.expand_m = expand_m;
+                if (multi)
+                    frw_walk_kernel<true, true><<<g.blocks_e, WALK_THREADS, g.lds_e>>>(W);
+                else
+                    frw_walk_kernel<false, true><<<g.blocks_e, WALK_THREADS, g.lds_e>>>(W);
+            } else if (multi) {
+                frw_walk_kernel<true, false><<<g.blocks, WALK_THREADS, g.lds>>>(W);
+            } else {
+                frw_walk_kernel<false, false><<<g.blocks, WALK_THREADS, g.lds>>>(W);
+            }
             MW_HIP(hipGetLastError());
             MW_HIP(hipEventRecord(ev1, 0));
             ++launches;
@@ -2201,7 +2541,20 @@ frw_options normalised_options(const frw_options* options) {
     MW_REQUIRE(opt.n_cells >= 4 && opt.n_cells <= 32 && opt.n_cells % 2 == 0, MW_EINVAL,
                "n_cells must be even in [4, 32]");
     if (opt.abs_tol_rel <= 0) opt.abs_tol_rel = 1e-6;
+    MW_REQUIRE(opt.expand >= 0 && opt.expand <= 64, MW_EINVAL, "expand must be in [0, 64]");
+    if (opt.expand > 1) {
+        const int m = std::max(1, (int)std::lround(opt.n_cells / (2.0 * opt.expand)));
+        MW_REQUIRE(opt.n_cells <= EXP_LIST_FACTOR * 2 * m, MW_EINVAL,
+                   "expand %d with n_cells %d gives cubes %.1fx the conductor-free size; the structure index "
+                   "covers %.0fx",
+                   opt.expand, opt.n_cells, opt.n_cells / (2.0 * m), (double)EXP_LIST_FACTOR);
+    }
     return opt;
+}
+
+// MicroWalk-E lattice factor m (expanded half-size n d / (2 m)); 0 = off.
+int expand_m_of(const frw_options& opt) {
+    return opt.expand > 1 ? std::max(1, (int)std::lround(opt.n_cells / (2.0 * opt.expand))) : 0;
 }
 
 void add_counters(frw_stats& st, const Counters& h) {
@@ -2369,6 +2722,7 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         const bool own_scores = !(score_net && score_w);
         Extraction X(*st, master, opt.abs_tol_rel, batch, own_scores);
         Runner R(n, opt.hybrid, batch, 1);
+        R.expand_m = expand_m_of(opt);
         frw_stats acc{};
         while (X.done < walk_budget) {
             const uint64_t nb = std::min<uint64_t>(batch, walk_budget - X.done);
@@ -2427,6 +2781,7 @@ extern "C" mw_status frw_extract_matrix(mw_structure* st, int32_t n_masters, con
             seeds.push_back(seed + (uint64_t)i);  // master i: Philox key seed + i
         }
         Runner R(n, opt.hybrid, round_walks, n_masters);
+        R.expand_m = expand_m_of(opt);
         SharedRound round(round_walks, n_masters);
         frw_stats acc{};
         std::vector<bool> active(n_masters, true);
@@ -2640,7 +2995,10 @@ struct mw_server {
             }
             mw_status rc = guarded([&] {
                 if (!round) round = std::make_unique<SharedRound>(round_walks, max_slots);
-                if (!R) R = std::make_unique<Runner>(opt.n_cells, opt.hybrid, round_walks, max_slots);
+                if (!R) {
+                    R = std::make_unique<Runner>(opt.n_cells, opt.hybrid, round_walks, max_slots);
+                    R->expand_m = expand_m_of(opt);
+                }
                 (void)round->run(*R, X, sh, seeds, opt.first_walk);
                 for (auto& r : running) r->stats.walks = r->X->done;
             });

@@ -220,3 +220,46 @@ def test_matrix_rows_equal_single_extractions(mw):
     with pytest.raises(mw.MWError) as e:
         mw.frw_extract_matrix(h, 1000, masters=[1, 1])
     assert e.value.status == mw.MW_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# MicroWalk-E (expanded transition cubes holding conductors)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("variant", ["uniform", "columns"])
+def test_microwalk_e_plates(mw, variant):
+    st = W.parallel_plates(variant)
+    exact = W.parallel_plates_exact(variant)
+    r = mw.frw_extract(st, 0, 1000000, seed=12, hybrid=0, expand=5)
+    print(variant, r["row"][0] / exact - 1, r["se"][0] / exact, r["stats"])
+    assert r["stats"]["micro_steps"] > 0
+    assert abs(r["row"][0] - exact) < 0.01 * exact + 3 * r["se"][0]
+
+
+def test_microwalk_e_c2_matches_oracle(mw, oracle_lib):
+    """GPU and oracle MicroWalk-E share the expanded-cube readings: the C2 rows
+    agree in combined standard errors (the GPU cuts links with 16-bit
+    fractions and fp32 geometry, so agreement is statistical)."""
+    st = W.c2_structure()
+    g = mw.frw_extract(st, 0, 2000000, seed=21, expand=5)
+    o = oracle_lib.frw_extract(st, 0, 150000, seed=22, threads=_threads(), expand=5.0)
+    p = mw.frw_extract(st, 0, 1000000, seed=23)
+    print("gpu E", g["row"], g["se"], g["stats"])
+    print("oracle E", o["row"], o["se"], o["stats"])
+    print("gpu plain", p["row"], p["stats"])
+    zs = [_z(g["row"][j], o["row"][j], g["se"][j], o["se"][j]) for j in range(5)]
+    print("z", zs)
+    assert max(zs) < 3.5
+    per = lambda r, k: r["stats"][k] / r["stats"]["walks"]
+    assert per(g, "hops") * 2 < per(p, "hops")
+    assert per(g, "micro_steps") * 4 < per(p, "micro_steps")
+
+
+def test_microwalk_e_options(mw):
+    st = W.c2_structure()
+    with pytest.raises(mw.MWError) as e:
+        mw.frw_extract(st, 0, 1000, expand=8)  # 8x the conductor-free size at n = 16
+    assert e.value.status == mw.MW_EINVAL
+    import torch
+    a = mw.frw_extract(st, 0, 20000, seed=3, scores=True)
+    b = mw.frw_extract(st, 0, 20000, seed=3, scores=True, expand=1)
+    assert torch.equal(a["net"], b["net"]) and torch.equal(a["w"], b["w"])
