@@ -111,6 +111,34 @@ def batched_vs_plain(mw, W, reps=5):
             "batched_alu_frac": steps * MW_STEP_SLOTS / t_batch / PEAK_LANE_OPS}
 
 
+def microwalk_e(mw, W, st, walks, n_cells, steps=5):
+    """The headline workload with MicroWalk-E transitions (expanded cubes of
+    4x the conductor-free size at n = 16, expansion option 5) beside the
+    plain MicroWalk figure: time per extraction, hops and micro-steps per
+    walk, and the row's shift against plain MicroWalk in combined SEs."""
+    h = mw.StructureHandle(st)
+    out = {}
+    rows = {}
+    for ex in (0, 5):
+        mw.frw_extract(h, 0, walks, seed=900, n_cells=n_cells, expand=ex)
+        t0 = time.perf_counter()
+        acc = []
+        for k in range(steps):
+            acc.append(mw.frw_extract(h, 0, walks, seed=500 + k, n_cells=n_cells, expand=ex))
+        dt = (time.perf_counter() - t0) / steps
+        s = acc[-1]["stats"]
+        rows[ex] = (np.mean([a["row"][0] for a in acc]), np.sqrt(np.mean([a["se"][0] ** 2 for a in acc]) / steps))
+        out["expand_%d" % ex] = {"ms_per_extraction": dt * 1e3, "walks_per_s": walks / dt,
+                                 "hops_per_walk": s["hops"] / s["walks"],
+                                 "micro_steps_per_walk": s["micro_steps"] / s["walks"],
+                                 "C_mm": rows[ex][0]}
+    h.close()
+    out["C_mm_shift_rel"] = float(rows[5][0] / rows[0][0] - 1)
+    out["C_mm_shift_z"] = float((rows[5][0] - rows[0][0]) / np.hypot(rows[5][1], rows[0][1]))
+    out["speedup"] = out["expand_0"]["ms_per_extraction"] / out["expand_5"]["ms_per_extraction"]
+    return out
+
+
 def fig3a(mw, W, ns=(4, 8, 12, 16, 20, 24, 28, 32), count=500, walks=4096):
     """Fig. 3(a) study: E(tau) of MicroWalk over `count` cubes per lattice
     size with randomly placed blocks of exponentially distributed
@@ -272,6 +300,7 @@ def main():
     if not args.no_extras:
         out["batched"] = batched_vs_plain(mw, W)
         out["fig3a"] = fig3a(mw, W)
+        out["microwalk_e"] = microwalk_e(mw, W, st, args.walks, args.n_cells)
         if args.serving_requests > 0:
             out["serving"] = serving(mw, W, args.serving_requests)
     if not args.no_cpu_baseline:
