@@ -293,9 +293,12 @@ __device__ __forceinline__ LaneCube lane_cube(uint32_t* my, int n) {
 
 __device__ __forceinline__ int hb16(uint32_t m) { return 31 - __clz(m | 1u); }
 
-// Code of a cell with box-membership m and background code b.
+// Code of a cell with box-membership m and background code b.  The read is
+// unconditional (bit 0's slot when m = 0) so that no branch splits the eight
+// reads of a step.
 __device__ __forceinline__ uint32_t cell_code(LaneCube L, uint32_t m, uint32_t b) {
-    return m ? L.codes[hb16(m)] : b;
+    const uint32_t v = L.codes[hb16(m)];
+    return m ? v : b;
 }
 
 // MicroWalk-E additions to a lane's LDS, after the LaneCube arrays:
@@ -853,65 +856,54 @@ __device__ __forceinline__ void mw_begin(MwState& M, LaneCube L, int n) {
 }
 
 // Up to four steps with the four words of one Philox block; false once the
-// walk has reached a boundary node.
+// walk has reached a boundary node.  Straight-line code: the eight cell codes
+// are always looked up (where all eight masks agree they are one code and the
+// choice reduces to floor(6 u / 2^32), but a branch for that case would run
+// beside the general one in most waves), and the move updates the masks with
+// selects.
 __device__ __forceinline__ bool mw_block(MwState& M, LaneCube L, int n, const Rand4& r) {
     const uint32_t us[4] = {r.x, r.y, r.z, r.w};
     bool alive = true;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (alive) {
-            uint32_t d;
-            if (M.mx0 == M.mx1 && M.my0 == M.my1 && M.mz0 == M.mz1 && M.bz0 == M.bz1) {
-                d = __umulhi(us[q], 6u);
-            } else {
-                const uint32_t m000 = M.mx0 & M.my0 & M.mz0, m001 = M.mx1 & M.my0 & M.mz0;
-                const uint32_t m010 = M.mx0 & M.my1 & M.mz0, m011 = M.mx1 & M.my1 & M.mz0;
-                const uint32_t m100 = M.mx0 & M.my0 & M.mz1, m101 = M.mx1 & M.my0 & M.mz1;
-                const uint32_t m110 = M.mx0 & M.my1 & M.mz1, m111 = M.mx1 & M.my1 & M.mz1;
-                const uint32_t c000 = cell_code(L, m000, M.bz0), c001 = cell_code(L, m001, M.bz0);
-                const uint32_t c010 = cell_code(L, m010, M.bz0), c011 = cell_code(L, m011, M.bz0);
-                const uint32_t c100 = cell_code(L, m100, M.bz1), c101 = cell_code(L, m101, M.bz1);
-                const uint32_t c110 = cell_code(L, m110, M.bz1), c111 = cell_code(L, m111, M.bz1);
-                const uint32_t a0 = c000 + c100, a1 = c010 + c110;
-                const uint32_t b0 = c001 + c101, b1 = c011 + c111;
-                const uint32_t gmx = a0 + a1, total = gmx + b0 + b1;
-                const uint32_t gmy = a0 + b0, gmz = c000 + c001 + c010 + c011;
-                const uint32_t S2 = total + gmy, S3 = total + total, S4 = S3 + gmz, S5 = S3 + total;
-                const uint32_t xq = __umulhi(us[q], S5);
-                d = (uint32_t)(xq >= gmx) + (uint32_t)(xq >= total) + (uint32_t)(xq >= S2) +
-                    (uint32_t)(xq >= S3) + (uint32_t)(xq >= S4);
-            }
+            const uint32_t m000 = M.mx0 & M.my0 & M.mz0, m001 = M.mx1 & M.my0 & M.mz0;
+            const uint32_t m010 = M.mx0 & M.my1 & M.mz0, m011 = M.mx1 & M.my1 & M.mz0;
+            const uint32_t m100 = M.mx0 & M.my0 & M.mz1, m101 = M.mx1 & M.my0 & M.mz1;
+            const uint32_t m110 = M.mx0 & M.my1 & M.mz1, m111 = M.mx1 & M.my1 & M.mz1;
+            const uint32_t c000 = cell_code(L, m000, M.bz0), c001 = cell_code(L, m001, M.bz0);
+            const uint32_t c010 = cell_code(L, m010, M.bz0), c011 = cell_code(L, m011, M.bz0);
+            const uint32_t c100 = cell_code(L, m100, M.bz1), c101 = cell_code(L, m101, M.bz1);
+            const uint32_t c110 = cell_code(L, m110, M.bz1), c111 = cell_code(L, m111, M.bz1);
+            const uint32_t a0 = c000 + c100, a1 = c010 + c110;
+            const uint32_t b0 = c001 + c101, b1 = c011 + c111;
+            const uint32_t gmx = a0 + a1, total = gmx + b0 + b1;
+            const uint32_t gmy = a0 + b0, gmz = c000 + c001 + c010 + c011;
+            const uint32_t S2 = total + gmy, S3 = total + total, S4 = S3 + gmz, S5 = S3 + total;
+            const uint32_t xq = __umulhi(us[q], S5);
+            const uint32_t d = (uint32_t)(xq >= gmx) + (uint32_t)(xq >= total) + (uint32_t)(xq >= S2) +
+                               (uint32_t)(xq >= S3) + (uint32_t)(xq >= S4);
             const int ax = (int)(d >> 1);
             const int dir = (d & 1u) ? 1 : -1;
             ++M.s;
-            int cnew;
-            if (ax == 0) {
-                M.ni += dir;
-                cnew = M.ni;
-            } else if (ax == 1) {
-                M.nj += dir;
-                cnew = M.nj;
-            } else {
-                M.nk += dir;
-                cnew = M.nk;
-            }
-            if (cnew == 0 || cnew == n) {
-                alive = false;
-            } else {
-                const uint32_t lo = L.mask[ax * n + cnew - 1], hi = L.mask[ax * n + cnew];
-                if (ax == 0) {
-                    M.mx0 = lo;
-                    M.mx1 = hi;
-                } else if (ax == 1) {
-                    M.my0 = lo;
-                    M.my1 = hi;
-                } else {
-                    M.mz0 = lo;
-                    M.mz1 = hi;
-                    M.bz0 = L.bz[cnew - 1];
-                    M.bz1 = L.bz[cnew];
-                }
-            }
+            M.ni += ax == 0 ? dir : 0;
+            M.nj += ax == 1 ? dir : 0;
+            M.nk += ax == 2 ? dir : 0;
+            const int cnew = ax == 0 ? M.ni : (ax == 1 ? M.nj : M.nk);
+            alive = cnew != 0 && cnew != n;
+            // masks of the two cell rows around the new node along ax (the
+            // index is clamped; a walk that left is not stepped again)
+            const int cc = min(max(cnew, 1), n - 1);
+            const uint32_t lo = L.mask[ax * n + cc - 1], hi = L.mask[ax * n + cc];
+            const uint32_t zlo = L.bz[cc - 1], zhi = L.bz[cc];
+            M.mx0 = ax == 0 ? lo : M.mx0;
+            M.mx1 = ax == 0 ? hi : M.mx1;
+            M.my0 = ax == 1 ? lo : M.my0;
+            M.my1 = ax == 1 ? hi : M.my1;
+            M.mz0 = ax == 2 ? lo : M.mz0;
+            M.mz1 = ax == 2 ? hi : M.mz1;
+            M.bz0 = ax == 2 ? zlo : M.bz0;
+            M.bz1 = ax == 2 ? zhi : M.bz1;
         }
     }
     return alive;
@@ -1118,6 +1110,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     WaveClaim claim_rc, claim_fr;  // wave-level claims of resumed and fresh walks
     bool resume_done = false;
     int sg = 0;  // segment of the lane's walk (always 0 for one segment)
+    uint32_t wk0 = 0, wk1 = 0;  // the walk's Philox key (its segment's seed)
     unsigned long long walk = 0;
     float3 pos = make_float3(0.f, 0.f, 0.f);
     float omega = 0.f;
@@ -1141,6 +1134,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                         if (ri < A.n_resume) {
                             const Parked P = ldpark(A.resume + ri);
                             if (MULTI) sg = P.seg;
+                            wk0 = gp(A.segs)[sg].k0;
+                            wk1 = gp(A.segs)[sg].k1;
                             walk = P.walk;
                             pos = make_float3(P.px, P.py, P.pz);
                             omega = P.omega;
@@ -1158,6 +1153,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                         if (gi < A.total) {
                             if (MULTI) sg = find_segment(A.segs, A.n_segs, gi);
                             const GAS Segment& SG = gp(A.segs)[sg];
+                            wk0 = SG.k0;
+                            wk1 = SG.k1;
                             const unsigned long long k = gi - SG.offset;
                             const float4 f = ldf4(SG.first_state + k);
                             walk = SG.walk_begin + k;
@@ -1236,7 +1233,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             --c_cls[I.cls];
                         } else {
                             const GAS uint32_t* tab = gp(A.cache.data) + (size_t)idx * A.cache.tab_words;
-                            const Rand4 r = philox10(0u, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_TABLE), SG.k0, SG.k1);
+                            const Rand4 r = philox10(0u, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_TABLE), wk0, wk1);
                             const int b = table_sample(tab, A.cache.nb, r.x);
                             int nd[3];
                             node_of_hit(n, b, nd);
@@ -1307,7 +1304,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
             if (nmw == 0 || 2 * nmw < nact) break;
             if (phase == PH_MW) {
                 const GAS Segment& SG = gp(A.segs)[sg];
-                const Rand4 r = philox10(M.s >> 2, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), SG.k0, SG.k1);
+                const Rand4 r = philox10(M.s >> 2, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), wk0, wk1);
                 int anet = 0;
                 const int stt = EXP ? mw_block_e(M, Q, L, E, n, r, env_net, &anet) : (mw_block(M, L, n, r) ? 0 : 1);
                 bool alive = stt == 0;
