@@ -1,19 +1,22 @@
 // frw.hip — Alg. 1 (FRW capacitance extraction) on the GPU: geometry store,
 // lazily voxelised transition cubes, the hybrid transition strategy of
 // Sec. III-C (exact SGF tables for stratified cubes, MicroWalk (Alg. 3) for
-// the rest), the first transition and the score reductions.
+// the rest), the first transition, MicroWalk-E (expanded cubes that may hold
+// conductors, Sec. III-B), the score reductions, capacitance-matrix rows and
+// the serving loop.
 //
-// Walker kernel.  Every lane owns one walk at a time.  A lane's transition
-// cube is never materialised: for the cube around its position the lane
-// lists the dielectric regions (background layers, then dielectric boxes in
-// priority order) that touch the cube and, per axis, a bitmask per cell
-// index of the regions whose interval holds that cell's centre (after mirror
-// folding at symmetry walls).  The region of a cell is the highest set bit
-// of the AND of its three axis masks; a MicroWalk step reads the two masks of
-// the moved axis from LDS and derives the six link codes of the new node
-// from the eight cells around it.  Nodes whose eight cells share one
-// membership pattern take the uniform-step shortcut d = mulhi(u, 6), which is
-// the same integer rule evaluated with equal codes.
+// First transitions run in their own kernel, one lane per walk.  The walker
+// kernel then takes walks in wave-sized chunks; every lane owns one walk at
+// a time.  A lane's transition cube is never materialised: the lane keeps in
+// LDS, per axis, a bitmask per cell index of the dielectric boxes (priority
+// order, at most 16) whose interval holds that cell's centre, the boxes'
+// codes, and the background layer code of each z cell.  A cell's code is the
+// code of the highest set bit of the AND of its three masks, else its z
+// cell's background code; a MicroWalk step derives the six link codes of its
+// node from the eight cells around it and reads the two masks of the moved
+// axis when it moves.  Lanes of a wave that need MicroWalk step together
+// while at least half of the working lanes do; the others take their next
+// hop meanwhile.
 //
 // Stratified cubes (every region present in the cube spans whole planes
 // normal to one axis) are sampled from cached exact SGF tables of the same
