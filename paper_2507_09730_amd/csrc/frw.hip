@@ -1307,9 +1307,22 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
             if (nmw == 0 || 2 * nmw < nact) break;
             if (phase == PH_MW) {
                 const GAS Segment& SG = gp(A.segs)[sg];
-                const Rand4 r = philox10(M.s >> 2, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), wk0, wk1);
                 int anet = 0;
-                const int stt = EXP ? mw_block_e(M, Q, L, E, n, r, env_net, &anet) : (mw_block(M, L, n, r) ? 0 : 1);
+                int stt;
+                if (EXP) {
+                    const Rand4 r = philox10(M.s >> 2, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), wk0, wk1);
+                    stt = mw_block_e(M, Q, L, E, n, r, env_net, &anet);
+                } else {
+                    // two Philox blocks per pass (eight steps); the second
+                    // block's counter is the one it would have after four
+                    // steps, so the words are those of one block at a time
+                    const uint32_t b0 = M.s >> 2;
+                    const Rand4 r0 = philox10(b0, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), wk0, wk1);
+                    const Rand4 r1 = philox10(b0 + 1, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), wk0, wk1);
+                    bool in = mw_block(M, L, n, r0);
+                    if (in) in = mw_block(M, L, n, r1);
+                    stt = in ? 0 : 1;
+                }
                 bool alive = stt == 0;
                 if (alive && M.s >= MW_STEP_CAP) {
                     // never reached for valid permittivities; keeps a logic
