@@ -2055,7 +2055,7 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
             ext[a] = D->win_hi[a] - D->win_lo[a];
             vol *= ext[a];
         }
-        const double target = std::min(262144.0, std::max(64.0, 16.0 * (nc + nd)));
+        const double target = std::min(1048576.0, std::max(512.0, 256.0 * (nc + nd)));
         const double cs = std::cbrt(vol / target);
         int gd[3];
         int ncells = 1;
