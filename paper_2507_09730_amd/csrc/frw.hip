@@ -2982,10 +2982,24 @@ struct mw_server {
                     fail(r, rc, msg);
                     cv.notify_all();
                 } else {
-                    // reconcile the reservation with the memory actually held
+                    // reconcile the reservation with the memory actually held;
+                    // a request that no longer fits waits at the queue's head
                     const size_t actual = r->st->bytes + Extraction::bytes(r->X->K, round_walks, false);
                     std::lock_guard<std::mutex> lk(mu);
                     if (actual > r->footprint) {
+                        if (st.resident_bytes - r->footprint + actual > budget) {
+                            r->release();
+                            st.resident_bytes -= r->footprint;
+                            r->footprint = actual;
+                            if (actual > budget) {
+                                fail(r, MW_ELIMIT, "request footprint exceeds the server's memory budget");
+                            } else {
+                                r->state = ServerRequest::QUEUED;
+                                queue.push_front(r);
+                            }
+                            cv.notify_all();
+                            continue;
+                        }
                         st.resident_bytes += actual - r->footprint;
                         r->footprint = actual;
                         st.max_resident_bytes = std::max(st.max_resident_bytes, st.resident_bytes);
@@ -3081,11 +3095,13 @@ extern "C" mw_status mw_server_submit(mw_server* srv, const mw_structure_desc* D
         r->master = master;
         r->budget = walk_budget;
         r->seed = seed;
-        // footprint: structure and grid index (bounded by the grid-size rule
-        // of mw_structure_create) plus the per-round extraction buffers
+        // footprint estimate: structure and grid index (the grid-size rule of
+        // mw_structure_create; candidate lists guessed at a few boxes per
+        // cell) plus the per-round extraction buffers.  Admission corrects it
+        // to the memory actually held once the structure exists.
         const size_t boxes = (size_t)D->n_cond + D->n_diel;
-        const size_t cells = (size_t)std::min(262144.0, std::max(64.0, 16.0 * boxes)) * 4;  // grid rounding slack
-        r->footprint = boxes * 64 + cells * 16 + cells * 4 * std::min<size_t>(boxes, 64) +
+        const size_t cells = (size_t)std::min(1048576.0, std::max(512.0, 256.0 * boxes)) * 2;  // rounding slack
+        r->footprint = boxes * 64 + cells * 32 + cells * 4 * std::min<size_t>(boxes, 32) +
                        Extraction::bytes(D->n_nets + 1, srv->round_walks, false) + 64 * 1024;
         r->t_submit = std::chrono::steady_clock::now();
         std::lock_guard<std::mutex> lk(srv->mu);
