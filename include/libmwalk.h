@@ -166,7 +166,8 @@ mw_status mw_batch_plan_destroy(mw_batch_plan* plan);
  * Geometry (Alg. 1 input: a 3-D structure of conductors and dielectrics).
  *
  * Conductor boxes are half-open [lo, hi) per axis and belong to nets
- * 0..n_nets-1; every net owns exactly one box.  Dielectric boxes override the
+ * 0..n_nets-1; a net owns one or more boxes, which may touch or overlap
+ * (boxes of different nets may not overlap).  Dielectric boxes override the
  * background; a later box wins where boxes overlap.  The background is a
  * stack of layers in z: layer l covers z in [layer_z0[l], layer_z0[l+1]) with
  * relative permittivity layer_eps[l]; the first layer extends to -inf and the
@@ -248,6 +249,12 @@ typedef struct {
     double seconds;           /* wall time of the call                      */
     double walker_seconds;    /* summed duration of the walker-kernel launches
                                  (HIP events on the launch stream)          */
+    double gauss_g;           /* frw_extract: growth g of the master's
+                                 Gaussian surface (um); 0 for the matrix    */
+    double gauss_area;        /* frw_extract: its area (um^2); 0 for the
+                                 matrix                                     */
+    uint64_t gauss_faces;     /* frw_extract: its rectangles; 0 for the
+                                 matrix                                     */
 } frw_stats;
 
 /* ------------------------------------------------------------------------

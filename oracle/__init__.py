@@ -170,14 +170,18 @@ def dist(st, p):
     return d.value, who.value
 
 
-def gauss(st, master):
+def gauss(st, master, cap=4096):
+    """Gaussian surface of net `master`: g, total area and its rectangles as
+    rows [axis, side, plane, lo3, hi3, area]."""
     args, keep = _structure_args(st)
     g = ctypes.c_double(0)
     area = ctypes.c_double(0)
-    faces = np.zeros((6, 10))
+    faces = np.zeros((cap, 10))
     nf = ctypes.c_int32(0)
     rc = lib().mwo_gauss(args[0], args[1], args[2], args[8], args[9], I32(master), ctypes.byref(g),
-                         ctypes.byref(area), _p(faces), ctypes.byref(nf))
+                         ctypes.byref(area), _p(faces), I32(cap), ctypes.byref(nf))
+    if rc == -2:
+        raise ValueError("Gaussian surface has more than %d rectangles" % cap)
     if rc:
         raise ValueError("no Gaussian surface (touching conductors?)")
     return g.value, area.value, faces[:nf.value]

@@ -834,11 +834,18 @@ int sample_index(const std::vector<double>& wts, double total, uint32_t u) {
 }
 
 // ---------------------------------------------------------------------------
-// Gaussian surface (Alg. 1 input G).  Reading: G is the boundary of the
-// master box expanded by g = half the L-infinity gap to the nearest other
-// conductor or grounded window face, restricted to the window (faces lying
-// outside it or on a symmetry wall carry no flux and are dropped; kept faces
-// are clipped to the window).
+// Gaussian surface (Alg. 1 input G).  Reading: every box of the master net is
+// grown by g on all sides, g = half the smallest L-infinity gap between a box
+// of the net and a box of any other net or a grounded window face; G is the
+// boundary of the union of the grown boxes, restricted to the window (pieces
+// lying outside it or on a symmetry wall carry no flux and are dropped; kept
+// pieces are clipped to the window).  With one box this is the six faces of
+// the grown box.  The boundary is found by cutting each grown face along every
+// coordinate at which some grown box (or the window) starts or ends and
+// testing the centre of every resulting rectangle: it is on the boundary when
+// a point just outside it lies in no grown box.  Two coplanar faces with the
+// same outward normal can both cover a rectangle; it is counted once, for the
+// box that comes first in the input.
 // ---------------------------------------------------------------------------
 struct GFace {
     int axis, side;
@@ -853,48 +860,93 @@ struct Gauss {
     double area;
 };
 
+static bool in_grown_open(const Box& b, double g, const double x[3]) {
+    for (int a = 0; a < 3; ++a)
+        if (!(x[a] > b.lo[a] - g && x[a] < b.hi[a] + g)) return false;
+    return true;
+}
+
 bool build_gauss(const Structure& S, int master, Gauss& G) {
-    const Box* M = nullptr;
+    std::vector<const Box*> M;
     for (const Box& b : S.cond)
-        if (b.net == master) M = &b;
-    if (!M) return false;
+        if (b.net == master) M.push_back(&b);
+    if (M.empty()) return false;
     double g0 = INFINITY;
-    for (const Box& b : S.cond) {
-        if (&b == M) continue;
-        double gap = 0;
-        for (int a = 0; a < 3; ++a) gap = std::max(gap, std::max(b.lo[a] - M->hi[a], M->lo[a] - b.hi[a]));
-        g0 = std::min(g0, gap);
-    }
-    for (int a = 0; a < 3; ++a) {
-        if (S.bc[2 * a] == 0) g0 = std::min(g0, M->lo[a] - S.wlo[a]);
-        if (S.bc[2 * a + 1] == 0) g0 = std::min(g0, S.whi[a] - M->hi[a]);
+    for (const Box* m : M) {
+        for (const Box& b : S.cond) {
+            if (b.net == master) continue;
+            double gap = 0;
+            for (int a = 0; a < 3; ++a) gap = std::max(gap, std::max(b.lo[a] - m->hi[a], m->lo[a] - b.hi[a]));
+            g0 = std::min(g0, gap);
+        }
+        for (int a = 0; a < 3; ++a) {
+            if (S.bc[2 * a] == 0) g0 = std::min(g0, m->lo[a] - S.wlo[a]);
+            if (S.bc[2 * a + 1] == 0) g0 = std::min(g0, S.whi[a] - m->hi[a]);
+        }
     }
     if (!(g0 > 0) || !std::isfinite(g0)) return false;
-    G.g = g0 / 2;
+    const double g = g0 / 2;
+    G.g = g;
     G.faces.clear();
     G.area = 0;
-    for (int a = 0; a < 3; ++a)
-        for (int side = 0; side < 2; ++side) {
-            GFace F;
-            F.axis = a;
-            F.side = side;
-            F.plane = side ? M->hi[a] + G.g : M->lo[a] - G.g;
-            if (!(F.plane > S.wlo[a] && F.plane < S.whi[a])) continue;
-            double area = 1;
-            for (int b = 0; b < 3; ++b) {
-                if (b == a) {
-                    F.lo[b] = F.hi[b] = F.plane;
-                    continue;
-                }
-                F.lo[b] = std::max(M->lo[b] - G.g, S.wlo[b]);
-                F.hi[b] = std::min(M->hi[b] + G.g, S.whi[b]);
-                area *= std::max(F.hi[b] - F.lo[b], 0.0);
-            }
-            F.area = area;
-            if (area <= 0) continue;
-            G.faces.push_back(F);
-            G.area += area;
+    // every coordinate at which a grown box or the window starts or ends
+    std::vector<double> cuts[3];
+    for (int a = 0; a < 3; ++a) {
+        cuts[a].push_back(S.wlo[a]);
+        cuts[a].push_back(S.whi[a]);
+        for (const Box* m : M) {
+            cuts[a].push_back(m->lo[a] - g);
+            cuts[a].push_back(m->hi[a] + g);
         }
+        std::sort(cuts[a].begin(), cuts[a].end());
+        cuts[a].erase(std::unique(cuts[a].begin(), cuts[a].end()), cuts[a].end());
+    }
+    for (size_t i = 0; i < M.size(); ++i)
+        for (int a = 0; a < 3; ++a)
+            for (int side = 0; side < 2; ++side) {
+                const double plane = side ? M[i]->hi[a] + g : M[i]->lo[a] - g;
+                if (!(plane > S.wlo[a] && plane < S.whi[a])) continue;
+                const int t0 = (a + 1) % 3, t1 = (a + 2) % 3;
+                const int ta = std::min(t0, t1), tb = std::max(t0, t1);
+                const double elo[2] = {std::max(M[i]->lo[ta] - g, S.wlo[ta]), std::max(M[i]->lo[tb] - g, S.wlo[tb])};
+                const double ehi[2] = {std::min(M[i]->hi[ta] + g, S.whi[ta]), std::min(M[i]->hi[tb] + g, S.whi[tb])};
+                const double eta = 1e-9 * (S.whi[a] - S.wlo[a]);
+                for (size_t u = 0; u + 1 < cuts[ta].size(); ++u) {
+                    const double u0 = cuts[ta][u], u1 = cuts[ta][u + 1];
+                    if (u0 < elo[0] || u1 > ehi[0]) continue;
+                    for (size_t v = 0; v + 1 < cuts[tb].size(); ++v) {
+                        const double v0 = cuts[tb][v], v1 = cuts[tb][v + 1];
+                        if (v0 < elo[1] || v1 > ehi[1]) continue;
+                        double out[3];
+                        out[a] = plane + (side ? eta : -eta);
+                        out[ta] = 0.5 * (u0 + u1);
+                        out[tb] = 0.5 * (v0 + v1);
+                        bool covered = false;
+                        for (const Box* m : M) covered = covered || in_grown_open(*m, g, out);
+                        if (covered) continue;
+                        bool counted = false;
+                        for (size_t j = 0; j < i; ++j) {
+                            const double pj = side ? M[j]->hi[a] + g : M[j]->lo[a] - g;
+                            if (pj == plane && out[ta] > M[j]->lo[ta] - g && out[ta] < M[j]->hi[ta] + g &&
+                                out[tb] > M[j]->lo[tb] - g && out[tb] < M[j]->hi[tb] + g)
+                                counted = true;
+                        }
+                        if (counted) continue;
+                        GFace F;
+                        F.axis = a;
+                        F.side = side;
+                        F.plane = plane;
+                        F.lo[a] = F.hi[a] = plane;
+                        F.lo[ta] = u0;
+                        F.hi[ta] = u1;
+                        F.lo[tb] = v0;
+                        F.hi[tb] = v1;
+                        F.area = (u1 - u0) * (v1 - v0);
+                        G.faces.push_back(F);
+                        G.area += F.area;
+                    }
+                }
+            }
     return !G.faces.empty();
 }
 
@@ -1215,13 +1267,14 @@ int mwo_dist(const double* cond, int n_cond, int n_nets, const double* win, cons
 
 // Gaussian surface: returns g and |G|; faces as [axis, side, plane, lo3, hi3, area].
 int mwo_gauss(const double* cond, int n_cond, int n_nets, const double* win, const int32_t* bc, int master,
-              double* g, double* area, double* faces, int32_t* n_faces) {
+              double* g, double* area, double* faces, int32_t cap, int32_t* n_faces) {
     Structure S = make_structure(cond, n_cond, n_nets, nullptr, 0, nullptr, nullptr, 0, win, bc);
     Gauss G;
     if (!build_gauss(S, master, G)) return -1;
     *g = G.g;
     *area = G.area;
     *n_faces = (int32_t)G.faces.size();
+    if ((int32_t)G.faces.size() > cap) return -2;
     for (size_t f = 0; f < G.faces.size(); ++f) {
         double* o = faces + f * 10;
         o[0] = G.faces[f].axis;

@@ -252,14 +252,16 @@ class frw_stats(ctypes.Structure):
                 ("first_branch", ctypes.c_uint64 * 4), ("cache_miss", ctypes.c_uint64),
                 ("env_absorbed", ctypes.c_uint64), ("hop_cap", ctypes.c_uint64),
                 ("launches", ctypes.c_uint64), ("seconds", ctypes.c_double),
-                ("walker_seconds", ctypes.c_double)]
+                ("walker_seconds", ctypes.c_double), ("gauss_g", ctypes.c_double),
+                ("gauss_area", ctypes.c_double), ("gauss_faces", ctypes.c_uint64)]
 
     def as_dict(self):
         return {"walks": self.walks, "hops": self.hops, "micro_steps": self.micro_steps,
                 "hop_class": list(self.hop_class), "first_branch": list(self.first_branch),
                 "cache_miss": self.cache_miss, "env_absorbed": self.env_absorbed,
                 "hop_cap": self.hop_cap, "launches": self.launches, "seconds": self.seconds,
-                "walker_seconds": self.walker_seconds}
+                "walker_seconds": self.walker_seconds, "gauss_g": self.gauss_g,
+                "gauss_area": self.gauss_area, "gauss_faces": self.gauss_faces}
 
 
 def make_desc(st):

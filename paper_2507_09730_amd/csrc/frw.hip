@@ -82,11 +82,17 @@ struct StructDev {
     float delta_abs;
 };
 
+// One rectangle of a Gaussian surface: p = {plane, cumulative area, axis |
+// side << 2 (bits), 0}, t = {lo, hi} along the lower tangent axis, then
+// {lo, hi} along the higher one.
+struct GaussFace {
+    float4 p, t;
+};
+
 struct GaussDev {
     float g, area;
-    int32_t n_faces;
-    int32_t axis[6], side[6];
-    float plane[6], lo[6][3], hi[6][3], cum[6];
+    int32_t n_faces, pad;
+    const GaussFace* faces;
 };
 
 // Table cache for one lattice size.
@@ -750,20 +756,25 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         SRef S = *gp(SG.S);
         const GAS GaussDev& G = *gp(SG.G);
         const unsigned long long walk = SG.walk_begin + k;
-        // GaussianSurfaceSampling(G): face by area, uniform point on it
+        // GaussianSurfaceSampling(G): rectangle by area (the first whose
+        // cumulative area exceeds the draw), uniform point on it
         const Rand4 r = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_GAUSS), SG.k0, SG.k1);
         const float xa = ((float)r.x + 0.5f) * 2.3283064365386963e-10f * G.area;
-        int f = G.n_faces - 1;
-        for (int q = 0; q < G.n_faces - 1; ++q)
-            if (xa < G.cum[q]) {
-                f = q;
-                break;
-            }
-        const int a_norm = G.axis[f], side = G.side[f];
-        const int ta = a_norm == 0 ? 1 : 0, tb = a_norm == 2 ? 1 : 2;
-        const float ua = G.lo[f][ta] + ((float)r.y + 0.5f) * 2.3283064365386963e-10f * (G.hi[f][ta] - G.lo[f][ta]);
-        const float ub = G.lo[f][tb] + ((float)r.z + 0.5f) * 2.3283064365386963e-10f * (G.hi[f][tb] - G.lo[f][tb]);
-        const float pl = G.plane[f];
+        const GAS GaussFace* gf = gp(G.faces);
+        int f_lo = 0, f_hi = G.n_faces - 1;
+        while (f_lo < f_hi) {
+            const int mid = (f_lo + f_hi) >> 1;
+            if (xa < gf[mid].p.y)
+                f_hi = mid;
+            else
+                f_lo = mid + 1;
+        }
+        const float4 fp = ldf4(&G.faces[f_lo].p), ft = ldf4(&G.faces[f_lo].t);
+        const uint32_t fbits = __float_as_uint(fp.z);
+        const int a_norm = (int)(fbits & 3u), side = (int)(fbits >> 2);
+        const float ua = ft.x + ((float)r.y + 0.5f) * 2.3283064365386963e-10f * (ft.y - ft.x);
+        const float ub = ft.z + ((float)r.z + 0.5f) * 2.3283064365386963e-10f * (ft.w - ft.z);
+        const float pl = fp.x;
         const float3 c = make_float3(a_norm == 0 ? pl : ua, a_norm == 1 ? pl : (a_norm == 0 ? ua : ub),
                                      a_norm == 2 ? pl : ub);
         const int cell = grid_cell(S, c);
@@ -1854,73 +1865,6 @@ __global__ void scan_kernel(const uint32_t* count, uint32_t* off, int n) {
     }
 }
 
-// Gaussian surface of the master (one thread): G = boundary of the master box
-// expanded by half its L-infinity gap to the nearest other conductor or
-// grounded face, kept inside the window.
-__global__ void gauss_kernel(StructDev S, int master, GaussDev* G, int* status) {
-    if (threadIdx.x || blockIdx.x) return;
-    int mi = -1;
-    for (int c = 0; c < S.n_cond; ++c)
-        if (__float_as_int(S.cond_lo[c].w) == master) mi = c;
-    if (mi < 0) {
-        *status = 1;
-        return;
-    }
-    const float4 ml4 = S.cond_lo[mi], mh4 = S.cond_hi[mi];
-    const float ml[3] = {ml4.x, ml4.y, ml4.z}, mh[3] = {mh4.x, mh4.y, mh4.z};
-    float g0 = INFINITY;
-    for (int c = 0; c < S.n_cond; ++c) {
-        if (c == mi) continue;
-        const float4 bl = S.cond_lo[c], bh = S.cond_hi[c];
-        const float l[3] = {bl.x, bl.y, bl.z}, h[3] = {bh.x, bh.y, bh.z};
-        float gap = 0.f;
-        for (int a = 0; a < 3; ++a) gap = fmaxf(gap, fmaxf(l[a] - mh[a], ml[a] - h[a]));
-        g0 = fminf(g0, gap);
-    }
-    for (int a = 0; a < 3; ++a) {
-        if (S.bc[2 * a] == MW_BC_DIRICHLET) g0 = fminf(g0, ml[a] - S.wlo[a]);
-        if (S.bc[2 * a + 1] == MW_BC_DIRICHLET) g0 = fminf(g0, S.whi[a] - mh[a]);
-    }
-    if (!(g0 > 0.f) || !isfinite(g0)) {
-        *status = 2;
-        return;
-    }
-    const float g = 0.5f * g0;
-    G->g = g;
-    int nf = 0;
-    float area = 0.f;
-    for (int a = 0; a < 3; ++a)
-        for (int side = 0; side < 2; ++side) {
-            const float plane = side ? mh[a] + g : ml[a] - g;
-            if (!(plane > S.wlo[a] && plane < S.whi[a])) continue;
-            float ar = 1.f;
-            float lo[3], hi[3];
-            for (int b = 0; b < 3; ++b) {
-                if (b == a) {
-                    lo[b] = hi[b] = plane;
-                    continue;
-                }
-                lo[b] = fmaxf(ml[b] - g, S.wlo[b]);
-                hi[b] = fminf(mh[b] + g, S.whi[b]);
-                ar *= fmaxf(hi[b] - lo[b], 0.f);
-            }
-            if (ar <= 0.f) continue;
-            G->axis[nf] = a;
-            G->side[nf] = side;
-            G->plane[nf] = plane;
-            for (int b = 0; b < 3; ++b) {
-                G->lo[nf][b] = lo[b];
-                G->hi[nf][b] = hi[b];
-            }
-            area += ar;
-            G->cum[nf] = area;
-            ++nf;
-        }
-    G->n_faces = nf;
-    G->area = area;
-    *status = nf > 0 ? 0 : 3;
-}
-
 // -------------------------------------------------------------------------
 // Host side.
 // -------------------------------------------------------------------------
@@ -1928,6 +1872,7 @@ struct Cache {
     CacheDev d{};
     void* mem = nullptr;
     std::mutex mu;
+    uint32_t uniform_index = NO_INDEX;  // tables are never evicted
 };
 
 std::mutex g_cache_mu;
@@ -2019,10 +1964,11 @@ static void validate_desc(const mw_structure_desc* D) {
                        "conductor %d leaves the window", i);
         }
     }
-    for (int j = 0; j < D->n_nets; ++j)
-        MW_REQUIRE(per_net[j] == 1, MW_EGEOM, "net %d has %d boxes (exactly one is supported)", j, per_net[j]);
+    for (int j = 0; j < D->n_nets; ++j) MW_REQUIRE(per_net[j] >= 1, MW_EGEOM, "net %d has no box", j);
+    // boxes of one net may touch or overlap; boxes of different nets may not
     for (int i = 0; i < D->n_cond; ++i)
         for (int k = i + 1; k < D->n_cond; ++k) {
+            if (D->cond[i].net == D->cond[k].net) continue;
             bool overlap = true;
             for (int a = 0; a < 3; ++a)
                 overlap &= D->cond[i].lo[a] < D->cond[k].hi[a] && D->cond[k].lo[a] < D->cond[i].hi[a];
@@ -2332,6 +2278,7 @@ struct Runner {
     }
 
     void ensure_uniform_table() {
+        if (uniform_index == NO_INDEX) uniform_index = cache->uniform_index;
         for (int it = 0; it < 3 && uniform_index == NO_INDEX; ++it) {
             uniform_table_kernel<<<1, 1>>>(cache->d, n, status);
             MW_HIP(hipGetLastError());
@@ -2345,6 +2292,7 @@ struct Runner {
                 build_pending();
         }
         MW_REQUIRE(uniform_index != NO_INDEX, MW_EDEVICE, "uniform SGF table could not be built");
+        cache->uniform_index = uniform_index;
     }
 
     static void check_errors(const Counters& h) {
@@ -2437,6 +2385,123 @@ struct Runner {
     }
 };
 
+// Gaussian surface of a net (Alg. 1 input G) as a list of axis-aligned
+// rectangles.  G is the boundary of the union of the net's boxes, each grown by
+// g on every side, where g is half the smallest L-infinity gap between a box of
+// the net and a box of another net or a grounded window face; a net of one box
+// gets the six faces of its grown box.  Pieces on planes outside the open
+// window are dropped (a symmetry wall closes the surface there and carries no
+// flux) and the rest are clipped to the window.  Each grown face is cut along
+// the extents of the grown boxes that reach its plane; a piece is kept when
+// the space just outside it belongs to no other grown box and no earlier box
+// of the net has a coplanar face with the same outward normal over it.
+// Returns 0, or 1 (no box), 2 (no positive gap), 3 (empty surface),
+// 4 (too many pieces).
+constexpr size_t GAUSS_MAX_FACES = 1 << 16;
+
+struct GaussHost {
+    double g = 0, area = 0;
+    std::vector<GaussFace> faces;
+};
+
+int gauss_surface(const mw_structure& st, int master, GaussHost& out) {
+    struct Grown {
+        double lo[3], hi[3];
+    };
+    std::vector<Grown> B;
+    for (const mw_cond_box& b : st.cond)
+        if (b.net == master) B.push_back({{b.lo[0], b.lo[1], b.lo[2]}, {b.hi[0], b.hi[1], b.hi[2]}});
+    if (B.empty()) return 1;
+    const StructDev& S = st.h;
+    double g0 = INFINITY;
+    for (const mw_cond_box& o : st.cond) {
+        if (o.net == master) continue;
+        for (const Grown& m : B) {
+            double gap = 0;
+            for (int a = 0; a < 3; ++a) gap = std::max(gap, std::max((double)o.lo[a] - m.hi[a], m.lo[a] - (double)o.hi[a]));
+            g0 = std::min(g0, gap);
+        }
+    }
+    for (const Grown& m : B)
+        for (int a = 0; a < 3; ++a) {
+            if (S.bc[2 * a] == MW_BC_DIRICHLET) g0 = std::min(g0, m.lo[a] - (double)S.wlo[a]);
+            if (S.bc[2 * a + 1] == MW_BC_DIRICHLET) g0 = std::min(g0, (double)S.whi[a] - m.hi[a]);
+        }
+    if (!(g0 > 0) || !std::isfinite(g0)) return 2;
+    const double g = 0.5 * g0;
+    for (Grown& m : B)
+        for (int a = 0; a < 3; ++a) {
+            m.lo[a] -= g;
+            m.hi[a] += g;
+        }
+    out.g = g;
+    out.area = 0;
+    out.faces.clear();
+    const int nb = (int)B.size();
+    std::vector<int> near;
+    std::vector<double> cu, cv;
+    for (int i = 0; i < nb; ++i)
+        for (int a = 0; a < 3; ++a)
+            for (int side = 0; side < 2; ++side) {
+                const double p = side ? B[i].hi[a] : B[i].lo[a];
+                if (!(p > S.wlo[a] && p < S.whi[a])) continue;
+                const int ta = a == 0 ? 1 : 0, tb = a == 2 ? 1 : 2;
+                const double u0 = std::max(B[i].lo[ta], (double)S.wlo[ta]), u1 = std::min(B[i].hi[ta], (double)S.whi[ta]);
+                const double v0 = std::max(B[i].lo[tb], (double)S.wlo[tb]), v1 = std::min(B[i].hi[tb], (double)S.whi[tb]);
+                if (!(u0 < u1 && v0 < v1)) continue;
+                // grown boxes that reach the plane over the face
+                near.clear();
+                for (int j = 0; j < nb; ++j)
+                    if (j != i && B[j].lo[a] <= p && p <= B[j].hi[a] && B[j].lo[ta] < u1 && B[j].hi[ta] > u0 &&
+                        B[j].lo[tb] < v1 && B[j].hi[tb] > v0)
+                        near.push_back(j);
+                cu.assign({u0, u1});
+                cv.assign({v0, v1});
+                for (int j : near) {
+                    for (double x : {B[j].lo[ta], B[j].hi[ta]})
+                        if (x > u0 && x < u1) cu.push_back(x);
+                    for (double x : {B[j].lo[tb], B[j].hi[tb]})
+                        if (x > v0 && x < v1) cv.push_back(x);
+                }
+                std::sort(cu.begin(), cu.end());
+                cu.erase(std::unique(cu.begin(), cu.end()), cu.end());
+                std::sort(cv.begin(), cv.end());
+                cv.erase(std::unique(cv.begin(), cv.end()), cv.end());
+                for (size_t iu = 0; iu + 1 < cu.size(); ++iu)
+                    for (size_t iv = 0; iv + 1 < cv.size(); ++iv) {
+                        const double qu = 0.5 * (cu[iu] + cu[iu + 1]), qv = 0.5 * (cv[iv] + cv[iv + 1]);
+                        bool keep = true;
+                        for (int j : near) {
+                            if (!(B[j].lo[ta] < qu && qu < B[j].hi[ta] && B[j].lo[tb] < qv && qv < B[j].hi[tb]))
+                                continue;
+                            // another grown box just outside the piece
+                            const bool outside = side ? (B[j].lo[a] <= p && p < B[j].hi[a])
+                                                      : (B[j].lo[a] < p && p <= B[j].hi[a]);
+                            // an earlier coplanar face with the same normal
+                            const bool earlier = j < i && (side ? B[j].hi[a] == p : B[j].lo[a] == p);
+                            if (outside || earlier) {
+                                keep = false;
+                                break;
+                            }
+                        }
+                        if (!keep) continue;
+                        const double ar = (cu[iu + 1] - cu[iu]) * (cv[iv + 1] - cv[iv]);
+                        if (!(ar > 0)) continue;
+                        if (out.faces.size() >= GAUSS_MAX_FACES) return 4;
+                        out.area += ar;
+                        GaussFace F;
+                        const uint32_t bits = (uint32_t)a | (uint32_t)side << 2;
+                        float fbits;
+                        memcpy(&fbits, &bits, 4);
+                        F.p = make_float4((float)p, (float)out.area, fbits, 0.f);
+                        F.t = make_float4((float)cu[iu], (float)cu[iu + 1], (float)cv[iv], (float)cv[iv + 1]);
+                        out.faces.push_back(F);
+                    }
+            }
+    if (out.faces.empty()) return 3;
+    return 0;
+}
+
 // Device state of one extraction: structure copy with the call's absorption
 // tolerance, Gaussian surface, per-walk buffers of one chunk and the fp64
 // accumulators.
@@ -2446,7 +2511,6 @@ struct Extraction {
     char* mem = nullptr;
     StructDev* dS;
     GaussDev* G;
-    int* status;
     float4* partial;
     double* acc;
     double* result;
@@ -2457,15 +2521,26 @@ struct Extraction {
     uint64_t done = 0;
     std::vector<double> res;
 
-    static size_t bytes(int K, uint64_t chunk_cap, bool chunk_buffers = true) {
+    static size_t bytes(int K, uint64_t chunk_cap, bool chunk_buffers = true, size_t n_faces = 6) {
         const uint64_t red_blocks = (chunk_cap + RED_CHUNK - 1) / RED_CHUNK;
-        return 256 * 12 + sizeof(StructDev) + sizeof(GaussDev) + 16 + sizeof(float4) * red_blocks * K +
-               sizeof(double) * 4 * K + (chunk_buffers ? chunk_cap * (4 + 4 + 16 + 4) : 0);
+        return 256 * 12 + sizeof(StructDev) + sizeof(GaussDev) + sizeof(GaussFace) * n_faces +
+               sizeof(float4) * red_blocks * K + sizeof(double) * 4 * K +
+               (chunk_buffers ? chunk_cap * (4 + 4 + 16 + 4) : 0);
     }
+    size_t n_faces = 0;
+    double gauss_g = 0, gauss_area = 0;
 
     Extraction(const mw_structure& st, int master_, double abs_tol_rel, uint64_t chunk_cap_, bool own_scores,
                bool own_first = true)
         : K(st.n_nets + 1), master(master_), chunk_cap(chunk_cap_) {
+        GaussHost GH;
+        const int gst = gauss_surface(st, master, GH);
+        MW_REQUIRE(gst != 4, MW_ELIMIT, "Gaussian surface of net %d needs more than %zu rectangles", master,
+                   GAUSS_MAX_FACES);
+        MW_REQUIRE(gst == 0, MW_EGEOM, "no valid Gaussian surface for net %d (status %d)", master, gst);
+        n_faces = GH.faces.size();
+        gauss_g = GH.g;
+        gauss_area = GH.area;
         size_t o = 0;
         auto sz = [&](size_t b) {
             size_t r = o;
@@ -2473,7 +2548,7 @@ struct Extraction {
             return r;
         };
         const uint64_t red_blocks = (chunk_cap + RED_CHUNK - 1) / RED_CHUNK;
-        const size_t o_sd = sz(sizeof(StructDev)), o_G = sz(sizeof(GaussDev)), o_st = sz(16);
+        const size_t o_sd = sz(sizeof(StructDev)), o_G = sz(sizeof(GaussDev)), o_gf = sz(sizeof(GaussFace) * n_faces);
         const size_t o_part = sz(sizeof(float4) * red_blocks * K);
         const size_t o_acc = sz(sizeof(double) * 2 * K), o_res = sz(sizeof(double) * 2 * K);
         const size_t o_fs = own_first ? sz(sizeof(float4) * chunk_cap) : 0;
@@ -2482,7 +2557,6 @@ struct Extraction {
         mem = (char*)dev_alloc(o);
         dS = (StructDev*)(mem + o_sd);
         G = (GaussDev*)(mem + o_G);
-        status = (int*)(mem + o_st);
         partial = (float4*)(mem + o_part);
         acc = (double*)(mem + o_acc);
         result = (double*)(mem + o_res);
@@ -2494,18 +2568,19 @@ struct Extraction {
         double diag = 0;
         for (int a = 0; a < 3; ++a) diag += (double)(S.whi[a] - S.wlo[a]) * (S.whi[a] - S.wlo[a]);
         S.delta_abs = (float)(abs_tol_rel * std::sqrt(diag));
-        MW_HIP(hipMemcpy(dS, &S, sizeof S, hipMemcpyHostToDevice));
+        GaussDev Gh{};
+        Gh.g = (float)GH.g;
+        Gh.area = (float)GH.area;
+        Gh.n_faces = (int32_t)n_faces;
+        Gh.faces = (const GaussFace*)(mem + o_gf);
+        // one host-to-device copy of the structure header, the surface header
+        // and its rectangles (laid out as on the device)
+        std::vector<char> staging(o_gf + sizeof(GaussFace) * n_faces - o_sd);
+        memcpy(staging.data(), &S, sizeof S);
+        memcpy(staging.data() + (o_G - o_sd), &Gh, sizeof Gh);
+        memcpy(staging.data() + (o_gf - o_sd), GH.faces.data(), sizeof(GaussFace) * n_faces);
+        MW_HIP(hipMemcpy(mem + o_sd, staging.data(), staging.size(), hipMemcpyHostToDevice));
         MW_HIP(hipMemset(acc, 0, sizeof(double) * 2 * K));
-        MW_HIP(hipMemset(status, 0, 16));
-        gauss_kernel<<<1, 1>>>(S, master, G, status);
-        MW_HIP(hipGetLastError());
-        int gst = 0;
-        MW_HIP(hipMemcpy(&gst, status, 4, hipMemcpyDeviceToHost));
-        if (gst != 0) {
-            dev_free(mem);
-            mem = nullptr;
-            MW_REQUIRE(false, MW_EGEOM, "no valid Gaussian surface for net %d (status %d)", master, gst);
-        }
         res.assign(2 * K, 0.0);
     }
     ~Extraction() { dev_free(mem); }
@@ -2757,6 +2832,9 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
             stats->launches = R.launches;
             stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
             stats->walker_seconds = R.walker_ms * 1e-3;
+            stats->gauss_g = X.gauss_g;
+            stats->gauss_area = X.gauss_area;
+            stats->gauss_faces = X.n_faces;
         }
     });
 }
@@ -2984,7 +3062,7 @@ struct mw_server {
                 } else {
                     // reconcile the reservation with the memory actually held;
                     // a request that no longer fits waits at the queue's head
-                    const size_t actual = r->st->bytes + Extraction::bytes(r->X->K, round_walks, false);
+                    const size_t actual = r->st->bytes + Extraction::bytes(r->X->K, round_walks, false, r->X->n_faces);
                     std::lock_guard<std::mutex> lk(mu);
                     if (actual > r->footprint) {
                         if (st.resident_bytes - r->footprint + actual > budget) {
@@ -3027,7 +3105,12 @@ struct mw_server {
                     R->expand_m = expand_m_of(opt);
                 }
                 (void)round->run(*R, X, sh, seeds, opt.first_walk);
-                for (auto& r : running) r->stats.walks = r->X->done;
+                for (auto& r : running) {
+                    r->stats.walks = r->X->done;
+                    r->stats.gauss_g = r->X->gauss_g;
+                    r->stats.gauss_area = r->X->gauss_area;
+                    r->stats.gauss_faces = r->X->n_faces;
+                }
             });
             std::string msg = rc ? mw_last_error() : "";
             std::lock_guard<std::mutex> lk(mu);

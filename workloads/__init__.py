@@ -163,6 +163,34 @@ def parallel_plates_exact(variant="uniform"):
     raise ValueError(variant)
 
 
+def sandwich_plates(split=False):
+    """Multi-box nets: 1x1x1 um window with symmetry walls and eps 3.9; net 0
+    is two plates, z in [0, 0.1] and [0.9, 1.0], around net 1, a plate at
+    z in [0.45, 0.55] (gaps 0.35 um).  split: every plate is also cut into
+    boxes (net 0 into quadrants, net 1 into two halves), which leaves the
+    conductors, and so the capacitances, unchanged."""
+    if not split:
+        cond = [[0, 0, 0, 1, 1, 0.1], [0, 0, 0.9, 1, 1, 1.0], [0, 0, 0.45, 1, 1, 0.55]]
+        nets = [0, 0, 1]
+    else:
+        cond, nets = [], []
+        for z0, z1 in ((0.0, 0.1), (0.9, 1.0)):
+            for x0, x1 in ((0.0, 0.5), (0.5, 1.0)):
+                for y0, y1 in ((0.0, 0.375), (0.375, 1.0)):
+                    cond.append([x0, y0, z0, x1, y1, z1])
+                    nets.append(0)
+        cond += [[0, 0, 0.45, 0.625, 1, 0.55], [0.625, 0, 0.45, 1, 1, 0.55]]
+        nets += [1, 1]
+    return make_structure(cond, nets, [], [], [0.0], [3.9], [0, 0, 0], [1, 1, 1], (NEUMANN,) * 6,
+                          name="sandwich-plates" + ("-split" if split else ""))
+
+
+def sandwich_plates_exact():
+    """Closed-form C_00 (= -C_01) of sandwich_plates(), fF: two parallel-plate
+    gaps of 0.35 um over 1 um^2 in parallel."""
+    return 2 * EPS0 * 3.9 * 1.0 / 0.35
+
+
 def c2_structure():
     """Crossing wires in a 2x2x1 um grounded window: two x-directed wires at
     z in [0.30, 0.40] (nets 0, 1) under two y-directed wires at z in
@@ -175,6 +203,55 @@ def c2_structure():
     coat = [_grow(w, 0.02) for w in wires]
     return make_structure(wires, [0, 1, 2, 3], coat, [7.0] * 4, [0.0, 0.5], [3.9, 2.7],
                           [0, 0, 0], [2, 2, 1], (DIRICHLET,) * 6, name="c2-crossing-wires")
+
+
+def c2_multibox_structure(split_net1=False):
+    """C2 with a multi-box master: net 0 is its x-wire cut at x = 1.0 into two
+    abutting boxes, a via (x in [1.6, 1.7], z in [0.40, 0.60]) up from the
+    wire's end and a y-directed wire (y in [0.85, 1.4]) on the upper level,
+    all coated like the other wires.  split_net1: net 1's wire is also cut
+    into two abutting boxes (same conductors)."""
+    net0 = [[0.2, 0.85, 0.30, 1.0, 0.95, 0.40],
+            [1.0, 0.85, 0.30, 1.8, 0.95, 0.40],
+            [1.6, 0.85, 0.40, 1.7, 0.95, 0.60],
+            [1.6, 0.85, 0.60, 1.7, 1.40, 0.70]]
+    net1 = ([[0.2, 1.05, 0.30, 1.3, 1.15, 0.40], [1.3, 1.05, 0.30, 1.8, 1.15, 0.40]] if split_net1
+            else [[0.2, 1.05, 0.30, 1.8, 1.15, 0.40]])
+    others = [[0.85, 0.2, 0.60, 0.95, 1.8, 0.70],
+              [1.05, 0.2, 0.60, 1.15, 1.8, 0.70]]
+    cond = net0 + net1 + others
+    nets = [0] * len(net0) + [1] * len(net1) + [2, 3]
+    # coatings follow the conductors, not how they are cut into boxes
+    coat = [_grow(w, 0.02) for w in net0 + [[0.2, 1.05, 0.30, 1.8, 1.15, 0.40]] + others]
+    return make_structure(cond, nets, coat, [7.0] * len(coat), [0.0, 0.5], [3.9, 2.7],
+                          [0, 0, 0], [2, 2, 1], (DIRICHLET,) * 6,
+                          name="c2-multibox" + ("-split1" if split_net1 else ""),
+                          meta={"master": 0})
+
+
+def random_multibox_net(seed, n_boxes=5):
+    """Unit window with symmetry walls and eps 3.9 holding net 1, a small box
+    at the origin corner, and net 0, a union of n_boxes random boxes on a 1/32
+    grid (overlapping, and one abutting another).  The box at (8, 8, 8)/32 is
+    4/32 from net 1 in every axis and every other box is at least that far, so
+    the Gaussian surface of net 0 grows its boxes by 2/32."""
+    rng = np.random.default_rng(seed)
+    q = 1.0 / 32
+    boxes = [[8, 8, 8, 8 + int(rng.integers(2, 8)), 8 + int(rng.integers(2, 8)), 8 + int(rng.integers(2, 8))]]
+    while len(boxes) < n_boxes - 1:
+        lo = [int(rng.integers(8, 24)), int(rng.integers(2, 24)), int(rng.integers(2, 24))]
+        hi = [min(30, lo[a] + int(rng.integers(1, 9))) for a in range(3)]
+        boxes.append(lo + hi)
+    # one box abutting the previous one along x
+    b = boxes[-1]
+    lo = [b[3], b[1] + int(rng.integers(0, 2)), b[2]]
+    hi = [min(31, lo[0] + int(rng.integers(1, 6))), b[4] + int(rng.integers(0, 3)), b[5]]
+    hi[1] = min(31, max(hi[1], lo[1] + 1))
+    boxes.append(lo + hi)
+    cond = [[c * q for c in bx] for bx in boxes] + [[0, 0, 0, 4 * q, 4 * q, 4 * q]]
+    nets = [0] * len(boxes) + [1]
+    return make_structure(cond, nets, [], [], [0.0], [3.9], [0, 0, 0], [1, 1, 1], (NEUMANN,) * 6,
+                          name="random-multibox-%d" % seed)
 
 
 C4_STACK_Z0 = (0.0, 0.4, 0.6, 0.9, 1.1, 1.4, 1.6)
