@@ -164,6 +164,10 @@ struct WalkArgs {
     uint32_t lane_stride;   // dwords of LDS per lane (odd)
     uint32_t uniform_index; // table of the uniform cube
     int32_t expand_m;       // MicroWalk-E: expanded half-size n d / (2 m) (EXP kernels)
+    // single-segment launches: a copy of the structure header, read through
+    // the kernel-argument segment (uniform scalar loads) instead of memory
+    // that the kernel also writes
+    StructDev S0;
 };
 
 // First transitions of a batch of walks (one lane per walk).
@@ -220,7 +224,8 @@ __device__ __forceinline__ float box_dist(float4 lo, float4 hi, float3 p) {
 
 __device__ __forceinline__ float axis_of(float3 p, int a) { return a == 0 ? p.x : (a == 1 ? p.y : p.z); }
 
-__device__ __forceinline__ int grid_cell(SRef S, float3 p) {
+template <class SR>
+__device__ __forceinline__ int grid_cell(SR& S, float3 p) {
     int c[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -232,7 +237,8 @@ __device__ __forceinline__ int grid_cell(SRef S, float3 p) {
 
 // Largest conductor-free cube: L-infinity distance to the nearest conductor
 // or grounded window face; nearest = net, or n_nets for a grounded face.
-__device__ float query_dist(SRef S, float3 p, int cell, int* nearest) {
+template <class SR>
+__device__ float query_dist(SR& S, float3 p, int cell, int* nearest) {
     float best = INFINITY;
     int who = S.n_nets;
     const uint32_t b = gp(S.gc_off)[cell], e = gp(S.gc_off)[cell + 1];
@@ -272,13 +278,15 @@ __device__ float query_dist(SRef S, float3 p, int cell, int* nearest) {
     return best;
 }
 
-__device__ __forceinline__ float fold(SRef S, int a, float x) {
+template <class SR>
+__device__ __forceinline__ float fold(SR& S, int a, float x) {
     if (S.bc[2 * a] == MW_BC_NEUMANN && x < S.wlo[a]) x = 2.f * S.wlo[a] - x;
     if (S.bc[2 * a + 1] == MW_BC_NEUMANN && x > S.whi[a]) x = 2.f * S.whi[a] - x;
     return x;
 }
 
-__device__ __forceinline__ float3 fold3(SRef S, float3 p) {
+template <class SR>
+__device__ __forceinline__ float3 fold3(SR& S, float3 p) {
     return make_float3(fold(S, 0, p.x), fold(S, 1, p.y), fold(S, 2, p.z));
 }
 
@@ -349,11 +357,54 @@ struct CubeInfo {
     bool overflow;
 };
 
+constexpr int LAYER_LDS = 8;  // stacks of up to this many layers: a copy in LDS
+
+// Background layer of every z cell of a cube: layer(k) = #{q >= 1 : z_k >=
+// z0[q]} for the cell centre z_k (z0 ascending), walking the boundaries once
+// since the centres rise with k.  Z and C index z0 and the layer codes (global
+// memory, or a copy in LDS).
+template <class Z, class C>
+__device__ __forceinline__ void layer_walk(Z z0, C lcode, int nl, float zlo, float h, int n, LaneCube L, int* lmin,
+                                           int* lmax) {
+    // layers of the lowest and the highest centre
+    int l = 0;
+    while (l + 1 < nl && zlo + 0.5f * h >= z0[l + 1]) ++l;
+    int lt = l;
+    while (lt + 1 < nl && zlo + ((float)(n - 1) + 0.5f) * h >= z0[lt + 1]) ++lt;
+    *lmin = l;
+    *lmax = lt;
+    uint32_t code = lcode[l];
+    uint32_t* bz2 = L.bz;
+    if (l == lt) {
+        // one layer holds every centre (n is even)
+        for (int k = 0; k < n; k += 2) {
+            bz2[k] = code;
+            bz2[k + 1] = code;
+        }
+        return;
+    }
+    // the same count for every lane; a boundary is crossed a few times
+    float zb = z0[l + 1];
+    for (int k = 0; k < n; ++k) {
+        const float z = zlo + ((float)k + 0.5f) * h;
+        while (z >= zb) {
+            ++l;
+            zb = l + 1 < nl ? z0[l + 1] : INFINITY;
+            code = lcode[l];
+        }
+        L.bz[k] = code;
+    }
+}
+
 // Builds the region description of the cube centred at c with half-size R.
 // Regions are the dielectric boxes (bits, priority = list order) and the
 // background layers (per-z-cell codes); a region is present when it holds at
 // least one cell centre.
-__device__ CubeInfo build_cube(SRef S, int cell, float3 c, float R, int n, LaneCube L, bool expanded = false) {
+// lt: when not null, an LDS copy of the structure's layer boundaries (words
+// 0..7, as float bits) and codes (words 8..15), for at most LAYER_LDS layers.
+template <class SR>
+__device__ CubeInfo build_cube(SR& S, int cell, float3 c, float R, int n, LaneCube L, bool expanded = false,
+                               const uint32_t* lt = nullptr) {
     CubeInfo info{};
     const float h = 2.f * R / (float)n;
     const float lo0[3] = {c.x - R, c.y - R, c.z - R};
@@ -366,19 +417,10 @@ __device__ CubeInfo build_cube(SRef S, int cell, float3 c, float R, int n, LaneC
     const GAS uint32_t* lcode = gp(S.layer_code);
     const bool zfold = (S.bc[4] == MW_BC_NEUMANN && lo0[2] < S.wlo[2]) ||
                        (S.bc[5] == MW_BC_NEUMANN && lo0[2] + 2.f * R > S.whi[2]);
-    if (!zfold) {
-        // centres rise with k: walk the layer boundaries once
-        int l = 0, k = 0;
-        while (l + 1 < S.n_layers && lo0[2] + 0.5f * h >= z0[l + 1]) ++l;
-        lmin = l;
-        for (;;) {
-            const float zb = l + 1 < S.n_layers ? z0[l + 1] : INFINITY;
-            const uint32_t code = lcode[l];
-            while (k < n && lo0[2] + ((float)k + 0.5f) * h < zb) L.bz[k++] = code;
-            if (k >= n) break;
-            while (l + 1 < S.n_layers && lo0[2] + ((float)k + 0.5f) * h >= z0[l + 1]) ++l;
-        }
-        lmax = l;
+    if (!zfold && lt) {
+        layer_walk(reinterpret_cast<const float*>(lt), lt + LAYER_LDS, S.n_layers, lo0[2], h, n, L, &lmin, &lmax);
+    } else if (!zfold) {
+        layer_walk(z0, lcode, S.n_layers, lo0[2], h, n, L, &lmin, &lmax);
     } else {
         lmin = 1 << 30;
         lmax = -1;
@@ -461,12 +503,17 @@ __device__ CubeInfo build_cube(SRef S, int cell, float3 c, float R, int n, LaneC
     uint32_t O[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
+        // two cells per dword (n is even, so every axis starts on a dword)
         uint32_t A = 0xffffu, Oa = 0, m = 0;
-        for (int i = 0; i < n; ++i) {
-            m ^= L.mask[a * n + i];
-            L.mask[a * n + i] = (uint16_t)m;
-            A &= m;
-            Oa |= m;
+        uint32_t* w32 = mask32 + a * (n / 2);
+        for (int i = 0; i < n / 2; ++i) {
+            const uint32_t w = w32[i];
+            const uint32_t m0 = m ^ (w & 0xffffu);
+            const uint32_t m1 = m0 ^ (w >> 16);
+            w32[i] = m0 | (m1 << 16);
+            A &= m0 & m1;
+            Oa |= m0 | m1;
+            m = m1;
         }
         info.A[a] = A;
         O[a] = Oa;
@@ -501,7 +548,8 @@ __device__ CubeInfo build_cube(SRef S, int cell, float3 c, float R, int n, LaneC
 // cube never crosses a symmetry wall): grounded faces first, then the
 // conductors holding part of the open cube, in candidate-list (index) order.
 // False when more than EXP_MAX_COND conductors do.
-__device__ bool build_conductors(SRef S, int cell, float3 c, float R, int n, LaneExp E) {
+template <class SR>
+__device__ bool build_conductors(SR& S, int cell, float3 c, float R, int n, LaneExp E) {
     const float h = 2.f * R / (float)n;
     const float o[3] = {c.x - R, c.y - R, c.z - R};
     const int np = n + 1;
@@ -565,7 +613,8 @@ __device__ bool build_conductors(SRef S, int cell, float3 c, float R, int n, Lan
 
 // Half-size of the expanded cube (before the halving rule): n d / (2 m),
 // stopped at symmetry walls, never below d.
-__device__ __forceinline__ float expanded_size(SRef S, float3 c, float d, int n, int m) {
+template <class SR>
+__device__ __forceinline__ float expanded_size(SR& S, float3 c, float d, int n, int m) {
     float R = (float)n * d / (float)(2 * m);
     const float cc[3] = {c.x, c.y, c.z};
 #pragma unroll
@@ -641,15 +690,26 @@ constexpr unsigned long long SLOT_HASH_MASK = 0xffffffff00000000ull;
 // Finds the table of a key (words produced by key(q), q < key_words) or
 // queues it for building.  Slot words pack a 32-bit key hash with the table
 // index; the full key is compared before a hit is reported.
+__device__ __forceinline__ uint32_t key_hash_step(uint32_t h, uint32_t w) {
+    h ^= w;
+    h *= 0x01000193u;
+    return h ^ (h >> 15);
+}
+constexpr uint32_t KEY_HASH_SEED = 0x811c9dc5u;
+
 template <class KeyF>
-__device__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t* out_index) {
+__device__ uint32_t key_hash(uint32_t words, KeyF key) {
+    uint32_t h = KEY_HASH_SEED;
+#pragma unroll 4
+    for (uint32_t q = 0; q < words; ++q) h = key_hash_step(h, key(q));
+    return h;
+}
+
+// hash: key_hash of the key (computed by the caller)
+template <class KeyF>
+__device__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t hash, uint32_t* out_index) {
     const uint32_t words = C.key_words;
-    uint32_t h = 0x811c9dc5u;
-    for (uint32_t q = 0; q < words; ++q) {
-        h ^= key(q);
-        h *= 0x01000193u;
-        h ^= h >> 15;
-    }
+    uint32_t h = hash;
     if (h == 0u) h = 1u;
     const unsigned long long hh = (unsigned long long)h << 32;
     uint32_t slot = (h * 0x9E3779B1u) & C.slot_mask;
@@ -676,6 +736,7 @@ __device__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t* out_index
             const uint32_t rdy = __hip_atomic_load(gpw(C.ready) + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const GAS uint32_t* k = gp(C.keys) + (size_t)idx * words;
             bool same = true;
+#pragma unroll 4
             for (uint32_t q = 0; q < words; ++q) same &= k[q] == key(q);
             if (same) {
                 if (!rdy) return LOOKUP_PARK;
@@ -725,8 +786,8 @@ __device__ __forceinline__ void node_of_hit(int n, int b, int node[3]) {
 __global__ void uniform_table_kernel(CacheDev C, int n, uint32_t* out) {
     if (threadIdx.x || blockIdx.x) return;
     uint32_t idx = NO_INDEX;
-    const int res = lookup_or_insert(
-        C, [&](uint32_t q) { return q == 1 ? (uint32_t)n : (q == 2 ? 2u : (q < KEY_HDR ? 0u : 1u)); }, &idx);
+    auto key = [&](uint32_t q) { return q == 1 ? (uint32_t)n : (q == 2 ? 2u : (q < KEY_HDR ? 0u : 1u)); };
+    const int res = lookup_or_insert(C, key, key_hash(C.key_words, key), &idx);
     out[0] = (uint32_t)res;
     out[1] = idx;
 }
@@ -817,7 +878,8 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         else
             for (int p = 0; p < n; ++p) kbuf[KEY_HDR + p] = plane_code(L, I, n, sax, p);
         uint32_t idx;
-        const int res = lookup_or_insert(A.cache, [&](uint32_t q) { return kbuf[q]; }, &idx);
+        auto key = [&](uint32_t q) { return kbuf[q]; };
+        const int res = lookup_or_insert(A.cache, key, key_hash(A.cache.key_words, key), &idx);
         if (res != LOOKUP_HIT) {
             if (res == LOOKUP_FULL) err |= ERR_TABLE_CAP;
             ++missing;
@@ -1106,6 +1168,16 @@ struct WaveClaim {
     }
 };
 
+// The structure a walker lane reads: the launch's copy for one segment, the
+// lane's segment's otherwise.
+template <bool MULTI>
+__device__ __forceinline__ decltype(auto) walk_struct(const WalkArgs& A, const GAS Segment& SG) {
+    if constexpr (MULTI)
+        return *gp(SG.S);
+    else
+        return (A.S0);
+}
+
 // EXP: MicroWalk hops use expanded cubes (MicroWalk-E).
 template <bool MULTI, bool EXP>
 __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
@@ -1119,6 +1191,20 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     Counters& K = *A.ctr;
     unsigned long long c_hops = 0, c_steps = 0, c_cls[3] = {0, 0, 0}, c_env = 0, c_cap = 0;
     uint32_t err = 0;
+    // one structure per launch: its layer table goes to LDS once
+    uint32_t* lt_lds = lds + WALK_THREADS * A.lane_stride;
+    const uint32_t* lt = nullptr;
+    if (!MULTI) {
+        const StructDev& S0 = A.S0;
+        if (S0.n_layers <= LAYER_LDS) {
+            if (threadIdx.x < 2 * LAYER_LDS) {
+                const int q = min((int)(threadIdx.x % LAYER_LDS), S0.n_layers - 1);
+                lt_lds[threadIdx.x] = threadIdx.x < LAYER_LDS ? __float_as_uint(gp(S0.layer_z0)[q]) : gp(S0.layer_code)[q];
+            }
+            lt = lt_lds;
+        }
+        __syncthreads();
+    }
 
     int phase = PH_IDLE;
     WaveClaim claim_rc, claim_fr;  // wave-level claims of resumed and fresh walks
@@ -1188,7 +1274,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
         // ---- one transition for lanes that need one ----
         if (phase == PH_NEED) {
             const GAS Segment& SG = gp(A.segs)[sg];
-            SRef S = *gp(SG.S);
+            auto& S = walk_struct<MULTI>(A, SG);
             bool park = false, done = false;
             int net = S.n_nets;
             float3 c;
@@ -1210,10 +1296,10 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                 }
             }
             if (!done) {
-                CubeInfo I = build_cube(S, cell, c, R, n, L);
+                CubeInfo I = build_cube(S, cell, c, R, n, L, false, lt);
                 for (int it = 0; it < 40 && I.overflow; ++it) {
                     R *= 0.5f;  // cube-size rule: halve while more than 16 boxes touch
-                    I = build_cube(S, cell, c, R, n, L);
+                    I = build_cube(S, cell, c, R, n, L, false, lt);
                 }
                 if (I.overflow) {
                     // more than 16 boxes overlap at this point: the call fails
@@ -1231,15 +1317,32 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                         // uniform cube shares one table
                         uint32_t idx = A.uniform_index;
                         int res = LOOKUP_HIT;
-                        if (I.cls != 0)
+                        if (I.cls != 0) {
+                            // plane codes written once over the background
+                            // codes (the cube is not used after this hop),
+                            // hashed as they are formed
+                            uint32_t hsh = KEY_HASH_SEED;
+                            hsh = key_hash_step(hsh, 0u);
+                            hsh = key_hash_step(hsh, (uint32_t)n);
+                            hsh = key_hash_step(hsh, (uint32_t)sax);
+                            hsh = key_hash_step(hsh, 0u);
+                            const uint32_t b0 = L.bz[0];
+#pragma unroll 4
+                            for (int p = 0; p < n; ++p) {
+                                const uint32_t pc =
+                                    cell_code(L, L.mask[sax * n + p] & I.present, sax == 2 ? L.bz[p] : b0);
+                                L.bz[p] = pc;
+                                hsh = key_hash_step(hsh, pc);
+                            }
+                            static_assert(KEY_HDR == 4, "hop-table key header is four words");
                             res = lookup_or_insert(
                                 A.cache,
                                 [&](uint32_t q) {
                                     return q == 1 ? (uint32_t)n
-                                                  : (q == 2 ? (uint32_t)sax
-                                                            : (q < KEY_HDR ? 0u : plane_code(L, I, n, sax, (int)q - KEY_HDR)));
+                                                  : (q == 2 ? (uint32_t)sax : (q < KEY_HDR ? 0u : L.bz[q - KEY_HDR]));
                                 },
-                                &idx);
+                                hsh, &idx);
+                        }
                         if (res != LOOKUP_HIT) {
                             if (res == LOOKUP_FULL) err |= ERR_TABLE_CAP;
                             park = true;
@@ -1269,7 +1372,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             float Re = expanded_size(S, c, dq, n, A.expand_m);
                             bool ok = false;
                             for (int it = 0;; ++it) {
-                                const CubeInfo IE = build_cube(S, cell, c, Re, n, L, true);
+                                const CubeInfo IE = build_cube(S, cell, c, Re, n, L, true, lt);
                                 ok = !IE.overflow && build_conductors(S, cell, c, Re, n, E);
                                 if (ok || it >= 110) break;
                                 Re = Re > dq ? fmaxf(0.5f * Re, dq) : 0.5f * Re;
@@ -1355,7 +1458,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                     const float h = 2.f * mR / (float)n;
                     const float3 xx = make_float3(mc.x - mR + (float)M.ni * h, mc.y - mR + (float)M.nj * h,
                                                   mc.z - mR + (float)M.nk * h);
-                    pos = fold3(*gp(SG.S), xx);
+                    pos = fold3(walk_struct<MULTI>(A, SG), xx);
                     ++t;
                     phase = PH_NEED;
                 }
@@ -2166,14 +2269,15 @@ LaunchGeom launch_geom(int n) {
     // transitions); odd dword strides spread lanes over the banks
     g.lane_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * n + 3) / 4) | 1u;
     g.first_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * n + 4 * (KEY_HDR + n) + 3) / 4) | 1u;
-    g.lds = (size_t)g.lane_stride * 4 * WALK_THREADS;
+    // (+ the walker's LDS copy of the layer table)
+    g.lds = (size_t)g.lane_stride * 4 * WALK_THREADS + 4 * 2 * LAYER_LDS;
     g.first_lds = (size_t)g.first_stride * 4 * FRW_THREADS;
     // LDS is allocated in 512-byte granules; 16 waves per CU is the VGPR limit
     g.blocks = cus * std::max(1, std::min(16, (int)(163840 / ((g.lds + 511) / 512 * 512))));
     g.first_blocks = cus * std::max(1, std::min(8, (int)(163840 / (g.first_lds + 512))));
     // MicroWalk-E lanes also hold the expanded cube's node masks
     g.lane_stride_e = (uint32_t)(g.lane_stride + lane_exp_words(n)) | 1u;
-    g.lds_e = (size_t)g.lane_stride_e * 4 * WALK_THREADS;
+    g.lds_e = (size_t)g.lane_stride_e * 4 * WALK_THREADS + 4 * 2 * LAYER_LDS;
     g.blocks_e = cus * std::max(1, std::min(16, (int)(163840 / ((g.lds_e + 511) / 512 * 512))));
     g.pool = (uint64_t)g.blocks * WALK_THREADS;
     return g;
@@ -2303,9 +2407,11 @@ struct Runner {
         MW_REQUIRE(!(h.err & ERR_STEP_CAP), MW_ELIMIT, "a micro-walk exceeded %u steps", MW_STEP_CAP);
     }
 
-    // Runs every walk of segs (first_done must be zeroed by the caller).
-    Counters run(const std::vector<Segment>& segs) {
+    // Runs every walk of segs (first_done must be zeroed by the caller).  s0:
+    // host copy of the structure header of a single segment.
+    Counters run(const std::vector<Segment>& segs, const StructDev* s0) {
         MW_REQUIRE((int)segs.size() <= seg_cap && !segs.empty(), MW_EINVAL, "bad segment list");
+        MW_REQUIRE(segs.size() > 1 || s0, MW_EINVAL, "single-segment run without its structure");
         std::lock_guard<std::mutex> lock(cache->mu);
         ensure_uniform_table();
         unsigned long long total = 0;
@@ -2351,6 +2457,7 @@ struct Runner {
             W.ctr = ctr;
             W.lane_stride = g.lane_stride;
             W.uniform_index = uniform_index;
+            if (!multi) W.S0 = *s0;
             // reset the per-launch queue state, keep the walk counter
             MW_HIP(hipMemset(&ctr->park_count, 0, 4));
             MW_HIP(hipMemset(&ctr->resume_next, 0, 8));
@@ -2529,6 +2636,7 @@ struct Extraction {
     }
     size_t n_faces = 0;
     double gauss_g = 0, gauss_area = 0;
+    StructDev hS{};  // host copy of the device structure header
 
     Extraction(const mw_structure& st, int master_, double abs_tol_rel, uint64_t chunk_cap_, bool own_scores,
                bool own_first = true)
@@ -2568,6 +2676,7 @@ struct Extraction {
         double diag = 0;
         for (int a = 0; a < 3; ++a) diag += (double)(S.whi[a] - S.wlo[a]) * (S.whi[a] - S.wlo[a]);
         S.delta_abs = (float)(abs_tol_rel * std::sqrt(diag));
+        hS = S;
         GaussDev Gh{};
         Gh.g = (float)GH.g;
         Gh.area = (float)GH.area;
@@ -2768,7 +2877,7 @@ struct SharedRound {
             dense += sg.count;
         }
         MW_HIP(hipMemsetAsync(fd, 0, sizeof(uint32_t) * offset, 0));
-        const Counters h = R.run(segs);
+        const Counters h = R.run(segs, segs.size() == 1 ? &X[part[0]]->hS : nullptr);
         MW_HIP(hipMemcpy(dred, red.data(), sizeof(RedSeg) * red.size(), hipMemcpyHostToDevice));
         reduce_multi_kernel<<<blocks, RED_THREADS>>>(dred, (int)red.size());
         finish_multi_kernel<<<(int)red.size(), 256>>>(dred);
@@ -2816,7 +2925,7 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
             const uint64_t nb = std::min<uint64_t>(batch, walk_budget - X.done);
             const Segment sgm = X.segment(opt.first_walk + X.done, nb, seed, own_scores ? nullptr : score_net + X.done,
                                           own_scores ? nullptr : score_w + X.done);
-            add_counters(acc, R.run({sgm}));
+            add_counters(acc, R.run({sgm}, &X.hS));
             X.reduce(sgm);
             if (X.converged(opt.target_rel_3sigma)) break;
         }
