@@ -79,6 +79,10 @@ struct StructDev {
     const uint32_t* ge_list;
     const uint32_t* gx_off;
     const uint32_t* gx_list;
+    // the boxes of gc_list and gd_list in place (lo, hi per entry): one
+    // load per candidate instead of an index and then the box
+    const float4* gc_rec;
+    const float4* gd_rec;
     float delta_abs;
 };
 
@@ -105,6 +109,7 @@ struct CacheDev {
     uint32_t* pending;
     uint32_t* n_pending;
     uint32_t slot_mask, capacity, key_words, tab_words, n, nb;
+    uint32_t key_stride;  // key_words rounded up to whole 16-byte rows (zero padded)
 };
 
 struct Parked {
@@ -242,19 +247,17 @@ __device__ float query_dist(SR& S, float3 p, int cell, int* nearest) {
     float best = INFINITY;
     int who = S.n_nets;
     const uint32_t b = gp(S.gc_off)[cell], e = gp(S.gc_off)[cell + 1];
-    const GAS uint32_t* clist = gp(S.gc_list);
+    const float4* rec = S.gc_rec;
     float4 nlo = make_float4(0.f, 0.f, 0.f, 0.f), nhi = nlo;
     if (b < e) {
-        const uint32_t c = clist[b];
-        nlo = ldf4(S.cond_lo + c);
-        nhi = ldf4(S.cond_hi + c);
+        nlo = ldf4(rec + 2 * (size_t)b);
+        nhi = ldf4(rec + 2 * (size_t)b + 1);
     }
     for (uint32_t q = b; q < e; ++q) {
         const float4 lo = nlo, hi = nhi;
         if (q + 1 < e) {
-            const uint32_t c = clist[q + 1];
-            nlo = ldf4(S.cond_lo + c);
-            nhi = ldf4(S.cond_hi + c);
+            nlo = ldf4(rec + 2 * (size_t)(q + 1));
+            nhi = ldf4(rec + 2 * (size_t)(q + 1) + 1);
         }
         const float d = box_dist(lo, hi, p);
         if (d < best) {
@@ -402,9 +405,11 @@ __device__ __forceinline__ void layer_walk(Z z0, C lcode, int nl, float zlo, flo
 // least one cell centre.
 // lt: when not null, an LDS copy of the structure's layer boundaries (words
 // 0..7, as float bits) and codes (words 8..15), for at most LAYER_LDS layers.
+// dr: when not null, the cell's dielectric candidate range (gd_off[cell],
+// gd_off[cell + 1]) read ahead by the caller (ordinary cubes only).
 template <class SR>
 __device__ CubeInfo build_cube(SR& S, int cell, float3 c, float R, int n, LaneCube L, bool expanded = false,
-                               const uint32_t* lt = nullptr) {
+                               const uint32_t* lt = nullptr, const uint2* dr = nullptr) {
     CubeInfo info{};
     const float h = 2.f * R / (float)n;
     const float lo0[3] = {c.x - R, c.y - R, c.z - R};
@@ -439,21 +444,26 @@ __device__ CubeInfo build_cube(SR& S, int cell, float3 c, float R, int n, LaneCu
     // record is fetched while the current one is processed)
     int nbits = 0;
     const uint32_t* doff = expanded ? S.gx_off : S.gd_off;
-    const uint32_t b = gp(doff)[cell], e = gp(doff)[cell + 1];
+    const uint32_t b = dr ? dr->x : gp(doff)[cell], e = dr ? dr->y : gp(doff)[cell + 1];
     const GAS uint32_t* glist = gp(expanded ? S.gx_list : S.gd_list);
+    const float4* drec = S.gd_rec;
+    // record q of the candidate list: in place for ordinary cubes, through
+    // the box index for expanded ones
+    auto cand = [&](uint32_t q, float4& lo, float4& hi) {
+        if (!expanded) {
+            lo = ldf4(drec + 2 * (size_t)q);
+            hi = ldf4(drec + 2 * (size_t)q + 1);
+        } else {
+            const uint32_t id = glist[q];
+            lo = ldf4(S.diel_lo + id);
+            hi = ldf4(S.diel_hi + id);
+        }
+    };
     float4 nlo = make_float4(0.f, 0.f, 0.f, 0.f), nhi = nlo;
-    if (b < e) {
-        const uint32_t id = glist[b];
-        nlo = ldf4(S.diel_lo + id);
-        nhi = ldf4(S.diel_hi + id);
-    }
+    if (b < e) cand(b, nlo, nhi);
     for (uint32_t q = b; q < e; ++q) {
         const float4 blo = nlo, bhi = nhi;
-        if (q + 1 < e) {
-            const uint32_t id = glist[q + 1];
-            nlo = ldf4(S.diel_lo + id);
-            nhi = ldf4(S.diel_hi + id);
-        }
+        if (q + 1 < e) cand(q + 1, nlo, nhi);
         const float bl[3] = {blo.x, blo.y, blo.z}, bh[3] = {bhi.x, bhi.y, bhi.z};
         bool touch = true;
 #pragma unroll
@@ -690,6 +700,11 @@ constexpr unsigned long long SLOT_HASH_MASK = 0xffffffff00000000ull;
 // Finds the table of a key (words produced by key(q), q < key_words) or
 // queues it for building.  Slot words pack a 32-bit key hash with the table
 // index; the full key is compared before a hit is reported.
+// Table layout: [last positive index, Kh bits, guide[257], CDF[nb],
+// sign bits[ceil(nb/32)]].  guide[g] = first b with CDF[b] > g * 2^24, so the
+// answer for a word u lies in [guide[u>>24], guide[(u>>24)+1]].
+constexpr uint32_t TAB_GUIDE = 2, TAB_CDF = 2 + 257;
+
 __device__ __forceinline__ uint32_t key_hash_step(uint32_t h, uint32_t w) {
     h ^= w;
     h *= 0x01000193u;
@@ -705,9 +720,12 @@ __device__ uint32_t key_hash(uint32_t words, KeyF key) {
     return h;
 }
 
-// hash: key_hash of the key (computed by the caller)
+// hash: key_hash of the key (computed by the caller).  On a hit, *glo and
+// *ghi receive the guide pair of word u's bucket in the table (loaded with the
+// key comparison).
 template <class KeyF>
-__device__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t hash, uint32_t* out_index) {
+__device__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t hash, uint32_t* out_index, uint32_t u = 0,
+                                uint32_t* glo = nullptr, uint32_t* ghi = nullptr) {
     const uint32_t words = C.key_words;
     uint32_t h = hash;
     if (h == 0u) h = 1u;
@@ -720,8 +738,9 @@ __device__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t hash, uint
             if (old == 0ull) {
                 const uint32_t idx = atomicAdd(C.n_tables, 1u);
                 if (idx >= C.capacity) return LOOKUP_FULL;
-                uint32_t* dst = C.keys + (size_t)idx * words;
+                uint32_t* dst = C.keys + (size_t)idx * C.key_stride;
                 for (uint32_t q = 0; q < words; ++q) dst[q] = key(q);
+                for (uint32_t q = words; q < C.key_stride; ++q) dst[q] = 0u;
                 __threadfence();
                 __hip_atomic_store(&C.slot[slot], hh | idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t pos = atomicAdd(C.n_pending, 1u);
@@ -734,13 +753,33 @@ __device__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t hash, uint
             const uint32_t idx = (uint32_t)cur;
             if (idx == NO_INDEX) return LOOKUP_PARK;
             const uint32_t rdy = __hip_atomic_load(gpw(C.ready) + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const GAS uint32_t* k = gp(C.keys) + (size_t)idx * words;
+            uint32_t g0 = 0, g1 = 0;
+            if (glo) {
+                // the table's guide pair, read with the key (unused unless
+                // the table is ready)
+                const GAS uint32_t* tab = gp(C.data) + (size_t)idx * C.tab_words + TAB_GUIDE + (u >> 24);
+                g0 = tab[0];
+                g1 = tab[1];
+            }
+            // the stored key in 16-byte rows (padding words are zero)
+            const GAS guvec4* k4 = reinterpret_cast<const GAS guvec4*>(gp(C.keys) + (size_t)idx * C.key_stride);
             bool same = true;
-#pragma unroll 4
-            for (uint32_t q = 0; q < words; ++q) same &= k[q] == key(q);
+#pragma unroll 2
+            for (uint32_t c = 0; c < C.key_stride / 4; ++c) {
+                const guvec4 v = k4[c];
+                const uint32_t q = 4 * c;
+                same &= v.x == (q < words ? key(q) : 0u);
+                same &= v.y == (q + 1 < words ? key(q + 1) : 0u);
+                same &= v.z == (q + 2 < words ? key(q + 2) : 0u);
+                same &= v.w == (q + 3 < words ? key(q + 3) : 0u);
+            }
             if (same) {
                 if (!rdy) return LOOKUP_PARK;
                 *out_index = idx;
+                if (glo) {
+                    *glo = g0;
+                    *ghi = g1;
+                }
                 return LOOKUP_HIT;
             }
         }
@@ -749,16 +788,16 @@ __device__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t hash, uint
     return LOOKUP_FULL;
 }
 
-// Table layout: [last positive index, Kh bits, guide[257], CDF[nb],
-// sign bits[ceil(nb/32)]].  guide[g] = first b with CDF[b] > g * 2^24, so the
-// answer for a word u lies in [guide[u>>24], guide[(u>>24)+1]].
-constexpr uint32_t TAB_GUIDE = 2, TAB_CDF = 2 + 257;
 
-__device__ __forceinline__ int table_sample(const GAS uint32_t* tab, uint32_t nb, uint32_t u) {
+// Sample for word u given the guide pair of its bucket (g = u >> 24):
+// glo = guide[g], ghi = guide[g + 1].  The first b with cdf[b] > u lies in
+// [glo, ghi + 1) and is found by bisection (few loads per lane: the lanes'
+// addresses are scattered, so each load costs a cache access per lane).
+__device__ __forceinline__ int table_sample_guided(const GAS uint32_t* tab, uint32_t nb, uint32_t u, uint32_t glo,
+                                                   uint32_t ghi) {
     const GAS uint32_t* cdf = tab + TAB_CDF;
-    const uint32_t g = u >> 24;
-    uint32_t lo = tab[TAB_GUIDE + g], hi = tab[TAB_GUIDE + g + 1];
-    if (hi < nb) ++hi;  // first b with cdf[b] > u lies in [lo, hi)
+    uint32_t lo = glo, hi = ghi;
+    if (hi < nb) ++hi;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
         if (cdf[mid] > u)
@@ -767,6 +806,11 @@ __device__ __forceinline__ int table_sample(const GAS uint32_t* tab, uint32_t nb
             lo = mid + 1;
     }
     return lo < nb ? (int)lo : (int)tab[0];
+}
+
+__device__ __forceinline__ int table_sample(const GAS uint32_t* tab, uint32_t nb, uint32_t u) {
+    const uint32_t g = u >> 24;
+    return table_sample_guided(tab, nb, u, tab[TAB_GUIDE + g], tab[TAB_GUIDE + g + 1]);
 }
 
 // Vertex-lattice boundary node of hit index b.
@@ -877,18 +921,19 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
             plane_mean_codes(L, n, a_norm, kbuf + KEY_HDR);
         else
             for (int p = 0; p < n; ++p) kbuf[KEY_HDR + p] = plane_code(L, I, n, sax, p);
-        uint32_t idx;
+        uint32_t idx, glo = 0, ghi = 0;
+        const Rand4 r2 = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_FIRST), SG.k0, SG.k1);
         auto key = [&](uint32_t q) { return kbuf[q]; };
-        const int res = lookup_or_insert(A.cache, key, key_hash(A.cache.key_words, key), &idx);
+        const int res = lookup_or_insert(A.cache, key, key_hash(A.cache.key_words, key), &idx, r2.x, &glo, &ghi);
         if (res != LOOKUP_HIT) {
             if (res == LOOKUP_FULL) err |= ERR_TABLE_CAP;
             ++missing;
             continue;
         }
-        ++c_br[br];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c_br[q] += br == q ? 1ull : 0ull;  // constant indices: registers
         const GAS uint32_t* tab = gp(A.cache.data) + (size_t)idx * A.cache.tab_words;
-        const Rand4 r2 = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_FIRST), SG.k0, SG.k1);
-        const int b = table_sample(tab, A.cache.nb, r2.x);
+        const int b = table_sample_guided(tab, A.cache.nb, r2.x, glo, ghi);
         const uint32_t sb = (tab[TAB_CDF + A.cache.nb + (b >> 5)] >> (b & 31)) & 1u;
         const float Kh = __uint_as_float(tab[1]);
         float sgn = sb ? 1.f : -1.f;
@@ -1282,8 +1327,12 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
             float3 x;
             int cell;
             float dq;  // conductor-free half-size before the cube-size rule
+            uint2 drange;
             {
                 cell = grid_cell(S, pos);
+                // the cell's dielectric candidate range, read with the
+                // conductor candidates
+                drange = make_uint2(gp(S.gd_off)[cell], gp(S.gd_off)[cell + 1]);
                 R = query_dist(S, pos, cell, &net);
                 dq = R;
                 c = pos;
@@ -1296,10 +1345,10 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                 }
             }
             if (!done) {
-                CubeInfo I = build_cube(S, cell, c, R, n, L, false, lt);
+                CubeInfo I = build_cube(S, cell, c, R, n, L, false, lt, &drange);
                 for (int it = 0; it < 40 && I.overflow; ++it) {
                     R *= 0.5f;  // cube-size rule: halve while more than 16 boxes touch
-                    I = build_cube(S, cell, c, R, n, L, false, lt);
+                    I = build_cube(S, cell, c, R, n, L, false, lt, &drange);
                 }
                 if (I.overflow) {
                     // more than 16 boxes overlap at this point: the call fails
@@ -1317,6 +1366,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                         // uniform cube shares one table
                         uint32_t idx = A.uniform_index;
                         int res = LOOKUP_HIT;
+                        const Rand4 r = philox10(0u, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_TABLE), wk0, wk1);
+                        uint32_t glo = 0, ghi = 0;
                         if (I.cls != 0) {
                             // plane codes written once over the background
                             // codes (the cube is not used after this hop),
@@ -1341,7 +1392,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                                     return q == 1 ? (uint32_t)n
                                                   : (q == 2 ? (uint32_t)sax : (q < KEY_HDR ? 0u : L.bz[q - KEY_HDR]));
                                 },
-                                hsh, &idx);
+                                hsh, &idx, r.x, &glo, &ghi);
                         }
                         if (res != LOOKUP_HIT) {
                             if (res == LOOKUP_FULL) err |= ERR_TABLE_CAP;
@@ -1350,8 +1401,12 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             --c_cls[I.cls];
                         } else {
                             const GAS uint32_t* tab = gp(A.cache.data) + (size_t)idx * A.cache.tab_words;
-                            const Rand4 r = philox10(0u, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_TABLE), wk0, wk1);
-                            const int b = table_sample(tab, A.cache.nb, r.x);
+                            if (I.cls == 0) {
+                                // the uniform table's guide pair (read with the key otherwise)
+                                glo = tab[TAB_GUIDE + (r.x >> 24)];
+                                ghi = tab[TAB_GUIDE + (r.x >> 24) + 1];
+                            }
+                            const int b = table_sample_guided(tab, A.cache.nb, r.x, glo, ghi);
                             int nd[3];
                             node_of_hit(n, b, nd);
                             x = make_float3(c.x - R + (float)nd[0] * h, c.y - R + (float)nd[1] * h,
@@ -1509,7 +1564,7 @@ struct BuildArgs {
 __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
     const uint32_t idx = B.list[blockIdx.x];
     const CacheDev& C = B.cache;
-    const uint32_t* key = C.keys + (size_t)idx * C.key_words;
+    const uint32_t* key = C.keys + (size_t)idx * C.key_stride;
     const int kind = (int)key[0], n = (int)key[1], s = (int)key[2], anorm = (int)key[3];
     const int M = n - 1, M2 = M * M, nb = 6 * M2;
     __shared__ double Sm[31 * 31];
@@ -1942,6 +1997,16 @@ __global__ void grid_fill_kernel(StructDev S, const uint32_t* coff, const uint32
     }
 }
 
+// In-place candidate records: rec[2 i] = lo[list[i]], rec[2 i + 1] = hi[list[i]].
+__global__ void grid_records_kernel(const uint32_t* list, uint32_t total, const float4* lo, const float4* hi,
+                                    float4* rec) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const uint32_t id = list[i];
+    rec[2 * (size_t)i] = lo[id];
+    rec[2 * (size_t)i + 1] = hi[id];
+}
+
 // Exclusive scan of counts (single block) into off[0..n].
 __global__ void scan_kernel(const uint32_t* count, uint32_t* off, int n) {
     __shared__ uint32_t part[1024];
@@ -2003,9 +2068,10 @@ Cache& get_cache(int n) {
         c->d.capacity = cap;
         c->d.slot_mask = nslots - 1;
         c->d.key_words = KEY_HDR + n;
+        c->d.key_stride = (c->d.key_words + 3) & ~3u;
         c->d.tab_words = TAB_CDF + nb + (nb + 31) / 32;
         const size_t b_hash = (size_t)nslots * 8, b_ready = (size_t)cap * 4;
-        const size_t b_keys = (size_t)cap * c->d.key_words * 4, b_data = (size_t)cap * c->d.tab_words * 4;
+        const size_t b_keys = (size_t)cap * c->d.key_stride * 4, b_data = (size_t)cap * c->d.tab_words * 4;
         const size_t b_misc = 256, b_pend = (size_t)cap * 4;
         const size_t total = b_hash + b_ready + b_keys + b_data + b_misc + b_pend + 2048;
         char* m = (char*)dev_alloc(total);
@@ -2209,6 +2275,10 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
             lo4[q] = lb;
             lb += ((4ull * tot[q] + 255) / 256) * 256;
         }
+        const size_t o_crec = lb;
+        lb += ((32ull * tot[0] + 255) / 256) * 256;
+        const size_t o_drec = lb;
+        lb += ((32ull * tot[1] + 255) / 256) * 256;
         const size_t list_bytes = lb + 512;
         char* lists = (char*)dev_alloc(list_bytes);
         st->bytes = o + list_bytes;
@@ -2218,6 +2288,10 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
         uint32_t* xlist = (uint32_t*)(lists + lo4[3]);
         grid_fill_kernel<<<nbk, tb>>>(S, coff, doff, clist, dlist, ncells, 1.f);
         grid_fill_kernel<<<nbk, tb>>>(S, eoff, xoff, elist, xlist, ncells, EXP_LIST_FACTOR);
+        float4* crec = (float4*)(lists + o_crec);
+        float4* drec = (float4*)(lists + o_drec);
+        if (tot[0]) grid_records_kernel<<<(tot[0] + 255) / 256, 256>>>(clist, tot[0], S.cond_lo, S.cond_hi, crec);
+        if (tot[1]) grid_records_kernel<<<(tot[1] + 255) / 256, 256>>>(dlist, tot[1], S.diel_lo, S.diel_hi, drec);
         MW_HIP(hipGetLastError());
         S.gc_off = coff;
         S.gc_list = clist;
@@ -2227,6 +2301,8 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
         S.ge_list = elist;
         S.gx_off = xoff;
         S.gx_list = xlist;
+        S.gc_rec = crec;
+        S.gd_rec = drec;
         st->d = (StructDev*)(m + o_desc);
         MW_HIP(hipMemcpy(st->d, &S, sizeof S, hipMemcpyHostToDevice));
         MW_HIP(hipDeviceSynchronize());
@@ -3293,7 +3369,7 @@ extern "C" mw_status mw_server_submit(mw_server* srv, const mw_structure_desc* D
         // to the memory actually held once the structure exists.
         const size_t boxes = (size_t)D->n_cond + D->n_diel;
         const size_t cells = (size_t)std::min(1048576.0, std::max(512.0, 256.0 * boxes)) * 2;  // rounding slack
-        r->footprint = boxes * 64 + cells * 32 + cells * 4 * std::min<size_t>(boxes, 32) +
+        r->footprint = boxes * 64 + cells * 32 + cells * 36 * std::min<size_t>(boxes, 32) +
                        Extraction::bytes(D->n_nets + 1, srv->round_walks, false) + 64 * 1024;
         r->t_submit = std::chrono::steady_clock::now();
         std::lock_guard<std::mutex> lk(srv->mu);
