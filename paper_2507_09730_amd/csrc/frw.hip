@@ -295,12 +295,13 @@ __device__ __forceinline__ float3 fold3(SR& S, float3 p) {
 
 // -------------------------------------------------------------------------
 // Per-lane cube description in LDS: masks[3][n] (u16, dielectric boxes),
-// box codes[16] (u32), background codes bz[n] (u32, per z cell).
+// box codes[16] (u32, box bit b at codes[15 - b]), background codes bz[n]
+// (u32, per z cell) directly after them.
 // -------------------------------------------------------------------------
 struct LaneCube {
     uint16_t* mask;   // mask[a * n + i]: bit b = box b's interval holds cell i's centre
-    uint32_t* codes;  // code of box bit b
-    uint32_t* bz;     // background (layer) code of z cell k
+    uint32_t* codes;  // codes[15 - b]: code of box bit b
+    uint32_t* bz;     // background (layer) code of z cell k (= codes + 16)
 };
 
 __device__ __forceinline__ LaneCube lane_cube(uint32_t* my, int n) {
@@ -317,7 +318,7 @@ __device__ __forceinline__ int hb16(uint32_t m) { return 31 - __clz(m | 1u); }
 // unconditional (bit 0's slot when m = 0) so that no branch splits the eight
 // reads of a step.
 __device__ __forceinline__ uint32_t cell_code(LaneCube L, uint32_t m, uint32_t b) {
-    const uint32_t v = L.codes[hb16(m)];
+    const uint32_t v = L.codes[MAX_REGIONS - 1 - hb16(m)];
     return m ? v : b;
 }
 
@@ -479,7 +480,7 @@ __device__ CubeInfo build_cube(SR& S, int cell, float3 c, float R, int n, LaneCu
             break;
         }
         const uint16_t bit = (uint16_t)(1u << nbits);
-        L.codes[nbits] = __float_as_uint(bhi.w);
+        L.codes[MAX_REGIONS - 1 - nbits] = __float_as_uint(bhi.w);
         ++nbits;
         const float inv_h = (float)n / (2.f * R);
 #pragma unroll
@@ -961,7 +962,75 @@ struct MwState {
     int ni, nj, nk;
     uint32_t s;  // steps taken
     uint32_t mx0, mx1, my0, my1, mz0, mz1, bz0, bz1;
+    // n <= 16: the masks of the cell rows around the node with the box bits
+    // moved to bits 16..31; x and y rows set bits 0..15, a z row k sets bit
+    // 15 - k (its background)
+    uint32_t px0, px1, py0, py1, pz0, pz1;
 };
+
+// n <= 16: the code of a cell whose prepared masks meet in m sits at
+// codes[clz(m)]: a box bit 16 + b gives codes[15 - b], the background bit
+// 15 - k of z row k gives codes[16 + k] = bz[k].  One read, no select.
+__device__ __forceinline__ uint32_t cell_code16(LaneCube L, uint32_t m) { return L.codes[__builtin_clz(m)]; }
+
+__device__ __forceinline__ uint32_t prep_xy(uint32_t v) { return (v << 16) | 0xffffu; }
+__device__ __forceinline__ uint32_t prep_z(uint32_t v, int k) { return (v << 16) | (1u << (15 - k)); }
+
+__device__ __forceinline__ void mw_begin16(MwState& M, LaneCube L, int n) {
+    M.ni = M.nj = M.nk = n / 2;
+    M.s = 0;
+    M.px0 = prep_xy(L.mask[M.ni - 1]);
+    M.px1 = prep_xy(L.mask[M.ni]);
+    M.py0 = prep_xy(L.mask[n + M.nj - 1]);
+    M.py1 = prep_xy(L.mask[n + M.nj]);
+    M.pz0 = prep_z(L.mask[2 * n + M.nk - 1], M.nk - 1);
+    M.pz1 = prep_z(L.mask[2 * n + M.nk], M.nk);
+}
+
+// mw_block for n <= 16 (the same steps and moves; the cell codes come from
+// cell_code16).
+__device__ __forceinline__ bool mw_block16(MwState& M, LaneCube L, int n, const Rand4& r) {
+    const uint32_t us[4] = {r.x, r.y, r.z, r.w};
+    bool alive = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (alive) {
+            const uint32_t c000 = cell_code16(L, M.px0 & M.py0 & M.pz0), c001 = cell_code16(L, M.px1 & M.py0 & M.pz0);
+            const uint32_t c010 = cell_code16(L, M.px0 & M.py1 & M.pz0), c011 = cell_code16(L, M.px1 & M.py1 & M.pz0);
+            const uint32_t c100 = cell_code16(L, M.px0 & M.py0 & M.pz1), c101 = cell_code16(L, M.px1 & M.py0 & M.pz1);
+            const uint32_t c110 = cell_code16(L, M.px0 & M.py1 & M.pz1), c111 = cell_code16(L, M.px1 & M.py1 & M.pz1);
+            const uint32_t a0 = c000 + c100, a1 = c010 + c110;
+            const uint32_t b0 = c001 + c101, b1 = c011 + c111;
+            const uint32_t gmx = a0 + a1, total = gmx + b0 + b1;
+            const uint32_t gmy = a0 + b0, gmz = c000 + c001 + c010 + c011;
+            const uint32_t S2 = total + gmy, S3 = total + total, S4 = S3 + gmz, S5 = S3 + total;
+            const uint32_t xq = __umulhi(us[q], S5);
+            const uint32_t d = (uint32_t)(xq >= gmx) + (uint32_t)(xq >= total) + (uint32_t)(xq >= S2) +
+                               (uint32_t)(xq >= S3) + (uint32_t)(xq >= S4);
+            const int ax = (int)(d >> 1);
+            const int dir = (d & 1u) ? 1 : -1;
+            ++M.s;
+            M.ni += ax == 0 ? dir : 0;
+            M.nj += ax == 1 ? dir : 0;
+            M.nk += ax == 2 ? dir : 0;
+            const int cnew = ax == 0 ? M.ni : (ax == 1 ? M.nj : M.nk);
+            alive = cnew != 0 && cnew != n;
+            // prepared masks of the two cell rows around the new node along
+            // ax (the index is clamped; a walk that left is not stepped again)
+            const int cc = min(max(cnew, 1), n - 1);
+            const uint32_t lo = L.mask[ax * n + cc - 1], hi = L.mask[ax * n + cc];
+            const uint32_t plo = ax == 2 ? prep_z(lo, cc - 1) : prep_xy(lo);
+            const uint32_t phi = ax == 2 ? prep_z(hi, cc) : prep_xy(hi);
+            M.px0 = ax == 0 ? plo : M.px0;
+            M.px1 = ax == 0 ? phi : M.px1;
+            M.py0 = ax == 1 ? plo : M.py0;
+            M.py1 = ax == 1 ? phi : M.py1;
+            M.pz0 = ax == 2 ? plo : M.pz0;
+            M.pz1 = ax == 2 ? phi : M.pz1;
+        }
+    }
+    return alive;
+}
 
 __device__ __forceinline__ void mw_begin(MwState& M, LaneCube L, int n) {
     M.ni = M.nj = M.nk = n / 2;
@@ -1224,7 +1293,8 @@ __device__ __forceinline__ decltype(auto) walk_struct(const WalkArgs& A, const G
 }
 
 // EXP: MicroWalk hops use expanded cubes (MicroWalk-E).
-template <bool MULTI, bool EXP>
+// N16: ordinary MicroWalk reads cell codes as cell_code16 (n <= 16).
+template <bool MULTI, bool EXP, bool N16 = false>
 __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     extern __shared__ uint32_t lds[];
     const int n = A.n;
@@ -1437,6 +1507,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             env_net = S.n_nets;
                             mw_begin(M, L, n);
                             mw_begin_e(M, Q, E, n);
+                        } else if (N16) {
+                            mw_begin16(M, L, n);
                         } else {
                             mw_begin(M, L, n);
                         }
@@ -1488,8 +1560,14 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                     const uint32_t b0 = M.s >> 2;
                     const Rand4 r0 = philox10(b0, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), wk0, wk1);
                     const Rand4 r1 = philox10(b0 + 1, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), wk0, wk1);
-                    bool in = mw_block(M, L, n, r0);
-                    if (in) in = mw_block(M, L, n, r1);
+                    bool in;
+                    if (N16) {
+                        in = mw_block16(M, L, n, r0);
+                        if (in) in = mw_block16(M, L, n, r1);
+                    } else {
+                        in = mw_block(M, L, n, r0);
+                        if (in) in = mw_block(M, L, n, r1);
+                    }
                     stt = in ? 0 : 1;
                 }
                 bool alive = stt == 0;
@@ -2408,6 +2486,8 @@ struct Runner {
         MW_HIP(hipEventCreate(&ev1));
         set_lds(frw_walk_kernel<false, false>, g.lds);
         set_lds(frw_walk_kernel<true, false>, g.lds);
+        set_lds(frw_walk_kernel<false, false, true>, g.lds);
+        set_lds(frw_walk_kernel<true, false, true>, g.lds);
         set_lds(frw_walk_kernel<false, true>, g.lds_e);
         set_lds(frw_walk_kernel<true, true>, g.lds_e);
         set_lds(first_kernel, g.first_lds);
@@ -2546,9 +2626,15 @@ struct Runner {
                 else
                     frw_walk_kernel<false, true><<<g.blocks_e, WALK_THREADS, g.lds_e>>>(W);
             } else if (multi) {
-                frw_walk_kernel<true, false><<<g.blocks, WALK_THREADS, g.lds>>>(W);
+                if (n <= 16)
+                    frw_walk_kernel<true, false, true><<<g.blocks, WALK_THREADS, g.lds>>>(W);
+                else
+                    frw_walk_kernel<true, false><<<g.blocks, WALK_THREADS, g.lds>>>(W);
             } else {
-                frw_walk_kernel<false, false><<<g.blocks, WALK_THREADS, g.lds>>>(W);
+                if (n <= 16)
+                    frw_walk_kernel<false, false, true><<<g.blocks, WALK_THREADS, g.lds>>>(W);
+                else
+                    frw_walk_kernel<false, false><<<g.blocks, WALK_THREADS, g.lds>>>(W);
             }
             MW_HIP(hipGetLastError());
             MW_HIP(hipEventRecord(ev1, 0));
