@@ -184,6 +184,7 @@ struct FirstArgs {
     int32_t n;
     Counters* ctr;
     uint32_t lane_stride;
+    StructDev S0;  // single-segment launches: the structure header (kernel arguments)
 };
 
 // The walker reads device-struct data through global views (gp/gpw).
@@ -846,6 +847,7 @@ __global__ void uniform_table_kernel(CacheDev C, int n, uint32_t* out) {
 // -------------------------------------------------------------------------
 __device__ __forceinline__ float sel3(float3 v, int a) { return a == 0 ? v.x : (a == 1 ? v.y : v.z); }
 
+template <bool MULTI>
 __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
     extern __shared__ uint32_t lds[];
     const int n = A.n;
@@ -854,12 +856,31 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
     uint32_t* kbuf = L.bz + n;
     unsigned long long c_br[4] = {0, 0, 0, 0};
     uint32_t err = 0, missing = 0;
+    // one structure per launch: its layer table goes to LDS once
+    uint32_t* lt_lds = lds + FRW_THREADS * A.lane_stride;
+    const uint32_t* lt = nullptr;
+    if (!MULTI) {
+        if (A.S0.n_layers <= LAYER_LDS) {
+            if (threadIdx.x < 2 * LAYER_LDS) {
+                const int q = min((int)(threadIdx.x % LAYER_LDS), A.S0.n_layers - 1);
+                lt_lds[threadIdx.x] =
+                    threadIdx.x < LAYER_LDS ? __float_as_uint(gp(A.S0.layer_z0)[q]) : gp(A.S0.layer_code)[q];
+            }
+            lt = lt_lds;
+        }
+        __syncthreads();
+    }
     for (unsigned long long g = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; g < A.total;
          g += (unsigned long long)gridDim.x * blockDim.x) {
-        const GAS Segment& SG = gp(A.segs)[find_segment(A.segs, A.n_segs, g)];
+        const GAS Segment& SG = gp(A.segs)[MULTI ? find_segment(A.segs, A.n_segs, g) : 0];
         const unsigned long long k = g - SG.offset;
         if (gp(SG.first_done)[k]) continue;
-        SRef S = *gp(SG.S);
+        auto& S = [&]() -> decltype(auto) {
+            if constexpr (MULTI)
+                return *gp(SG.S);
+            else
+                return (A.S0);
+        }();
         const GAS GaussDev& G = *gp(SG.G);
         const unsigned long long walk = SG.walk_begin + k;
         // GaussianSurfaceSampling(G): rectangle by area (the first whose
@@ -867,13 +888,25 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         const Rand4 r = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_GAUSS), SG.k0, SG.k1);
         const float xa = ((float)r.x + 0.5f) * 2.3283064365386963e-10f * G.area;
         const GAS GaussFace* gf = gp(G.faces);
-        int f_lo = 0, f_hi = G.n_faces - 1;
-        while (f_lo < f_hi) {
-            const int mid = (f_lo + f_hi) >> 1;
-            if (xa < gf[mid].p.y)
-                f_hi = mid;
-            else
-                f_lo = mid + 1;
+        const int nf = G.n_faces;
+        int f_lo = 0;
+        if (nf <= 8) {
+            // few rectangles: count those whose cumulative area is <= the
+            // draw (independent loads)
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+                const float cq = gf[min(q, nf - 1)].p.y;
+                f_lo += (q < nf - 1 && !(xa < cq)) ? 1 : 0;
+            }
+        } else {
+            int f_hi = nf - 1;
+            while (f_lo < f_hi) {
+                const int mid = (f_lo + f_hi) >> 1;
+                if (xa < gf[mid].p.y)
+                    f_hi = mid;
+                else
+                    f_lo = mid + 1;
+            }
         }
         const float4 fp = ldf4(&G.faces[f_lo].p), ft = ldf4(&G.faces[f_lo].t);
         const uint32_t fbits = __float_as_uint(fp.z);
@@ -884,14 +917,15 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         const float3 c = make_float3(a_norm == 0 ? pl : ua, a_norm == 1 ? pl : (a_norm == 0 ? ua : ub),
                                      a_norm == 2 ? pl : ub);
         const int cell = grid_cell(S, c);
+        const uint2 drange = make_uint2(gp(S.gd_off)[cell], gp(S.gd_off)[cell + 1]);
         int who;
         float R = fminf(query_dist(S, c, cell, &who), G.g);
         // FirstTransition: cube touching the master (Sec. III-C, Fig. 4
         // branches; homogenised along the normal when not stratified)
-        CubeInfo I = build_cube(S, cell, c, R, n, L);
+        CubeInfo I = build_cube(S, cell, c, R, n, L, false, lt, &drange);
         for (int it = 0; it < 40 && I.overflow; ++it) {
             R *= 0.5f;  // cube-size rule: halve while more than 16 boxes touch
-            I = build_cube(S, cell, c, R, n, L);
+            I = build_cube(S, cell, c, R, n, L, false, lt, &drange);
         }
         if (I.overflow) {
             err |= ERR_REGIONS;
@@ -1975,21 +2009,36 @@ __global__ void finish_multi_kernel(const RedSeg* __restrict__ segs) {
 }
 
 // acc[2*K]: running binary64 sums (S1, S2) per net; result[2*K]: row, se.
-__global__ void finish_kernel(const float4* __restrict__ partial, int blocks, int K, double* acc, double n_total,
-                              double* result) {
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < K; j += gridDim.x * blockDim.x) {
-        double s1 = 0.0, s2 = 0.0;
-        for (int b = 0; b < blocks; ++b) {
-            const float4 p = partial[(size_t)b * K + j];
-            s1 += (double)p.x + (double)p.y;
-            s2 += (double)p.z + (double)p.w;
+// One block per net j: strided fp64 sums of the block partials, then a
+// fixed-order tree over the threads (deterministic).
+constexpr int FIN_THREADS = 256;
+
+__global__ void __launch_bounds__(FIN_THREADS) finish_kernel(const float4* __restrict__ partial, int blocks, int K,
+                                                             double* acc, double n_total, double* result) {
+    __shared__ double t1[FIN_THREADS], t2[FIN_THREADS];
+    const int j = blockIdx.x;
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = threadIdx.x; b < blocks; b += FIN_THREADS) {
+        const float4 p = partial[(size_t)b * K + j];
+        s1 += (double)p.x + (double)p.y;
+        s2 += (double)p.z + (double)p.w;
+    }
+    t1[threadIdx.x] = s1;
+    t2[threadIdx.x] = s2;
+    __syncthreads();
+    for (int h = FIN_THREADS / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            t1[threadIdx.x] += t1[threadIdx.x + h];
+            t2[threadIdx.x] += t2[threadIdx.x + h];
         }
-        s1 += acc[j];
-        s2 += acc[K + j];
-        acc[j] = s1;
-        acc[K + j] = s2;
-        const double m = s1 / n_total;
-        const double var = (s2 / n_total - m * m) / (n_total - 1.0);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double a1 = t1[0] + acc[j], a2 = t2[0] + acc[K + j];
+        acc[j] = a1;
+        acc[K + j] = a2;
+        const double m = a1 / n_total;
+        const double var = (a2 / n_total - m * m) / (n_total - 1.0);
         result[j] = m;
         result[K + j] = sqrt(var > 0.0 ? var : 0.0);
     }
@@ -2425,7 +2474,7 @@ LaunchGeom launch_geom(int n) {
     g.first_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * n + 4 * (KEY_HDR + n) + 3) / 4) | 1u;
     // (+ the walker's LDS copy of the layer table)
     g.lds = (size_t)g.lane_stride * 4 * WALK_THREADS + 4 * 2 * LAYER_LDS;
-    g.first_lds = (size_t)g.first_stride * 4 * FRW_THREADS;
+    g.first_lds = (size_t)g.first_stride * 4 * FRW_THREADS + 4 * 2 * LAYER_LDS;
     // LDS is allocated in 512-byte granules; 16 waves per CU is the VGPR limit
     g.blocks = cus * std::max(1, std::min(16, (int)(163840 / ((g.lds + 511) / 512 * 512))));
     g.first_blocks = cus * std::max(1, std::min(8, (int)(163840 / (g.first_lds + 512))));
@@ -2490,7 +2539,8 @@ struct Runner {
         set_lds(frw_walk_kernel<true, false, true>, g.lds);
         set_lds(frw_walk_kernel<false, true>, g.lds_e);
         set_lds(frw_walk_kernel<true, true>, g.lds_e);
-        set_lds(first_kernel, g.first_lds);
+        set_lds(first_kernel<false>, g.first_lds);
+        set_lds(first_kernel<true>, g.first_lds);
     }
     ~Runner() {
         if (ev0) (void)hipEventDestroy(ev0);
@@ -2584,9 +2634,13 @@ struct Runner {
             F.n = n;
             F.ctr = ctr;
             F.lane_stride = g.first_stride;
+            if (segs.size() == 1) F.S0 = *s0;
             MW_HIP(hipMemset(&ctr->first_missing, 0, 4));
             const int fblocks = (int)std::min<uint64_t>((total + FRW_THREADS - 1) / FRW_THREADS, (uint64_t)g.first_blocks);
-            first_kernel<<<fblocks, FRW_THREADS, g.first_lds>>>(F);
+            if (segs.size() == 1)
+                first_kernel<false><<<fblocks, FRW_THREADS, g.first_lds>>>(F);
+            else
+                first_kernel<true><<<fblocks, FRW_THREADS, g.first_lds>>>(F);
             MW_HIP(hipGetLastError());
             Counters h{};
             MW_HIP(hipMemcpy(&h, ctr, sizeof h, hipMemcpyDeviceToHost));
@@ -2880,7 +2934,7 @@ struct Extraction {
         const int rb = (int)((s.count + RED_CHUNK - 1) / RED_CHUNK);
         done += s.count;
         reduce_scores_kernel<<<rb, RED_THREADS>>>(s.score_net, s.score_w, s.count, K, partial);
-        finish_kernel<<<(K + 255) / 256, 256>>>(partial, rb, K, acc, (double)done, result);
+        finish_kernel<<<K, FIN_THREADS>>>(partial, rb, K, acc, (double)done, result);
         MW_HIP(hipGetLastError());
         MW_HIP(hipMemcpy(res.data(), result, sizeof(double) * 2 * K, hipMemcpyDeviceToHost));
     }
