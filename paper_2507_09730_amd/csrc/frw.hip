@@ -1839,45 +1839,74 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
                 if (Pout[3 * nb + q * 32 + k] > 0.0) bits |= 1u << k;
             tab[TAB_CDF + nb + q] = bits;
         }
-        if (threadIdx.x == 0) {
-            double K = 0.0;
-            for (int b = 0; b < nb; ++b) K += fabs(Pout[3 * nb + b]);
-            double cum = 0.0;
-            int last = 0;
-            for (int b = 0; b < nb; ++b) {
-                const double a = fabs(Pout[3 * nb + b]);
-                cum += a;
-                if (a > 0.0) last = b;
-                const double cv = ceil(cum / K * 4294967296.0);
-                tab[TAB_CDF + b] = cv >= 4294967295.0 ? 0xffffffffu : (uint32_t)cv;
-            }
-            tab[0] = (uint32_t)last;
-            tab[1] = __float_as_uint((float)K);
+    }
+    // weights -> CDF in hit-index order: each thread sums a contiguous
+    // chunk, one thread scans the chunk sums, every thread then writes its
+    // chunk's thresholds ceil(cum / total * 2^32) (the last equals 2^32
+    // exactly: the chunk sums are formed in the same order)
+    const double* wv = kind == 1 ? Pout + 3 * nb : Pout;
+    const bool absw = kind == 1;
+    __shared__ double csum[TB_THREADS];
+    __shared__ int clast[TB_THREADS];
+    const int chunk = (nb + TB_THREADS - 1) / TB_THREADS;
+    const int b0 = threadIdx.x * chunk, b1 = min(nb, b0 + chunk);
+    {
+        double sloc = 0.0;
+        int last = -1;
+        for (int b = b0; b < b1; ++b) {
+            const double v = absw ? fabs(wv[b]) : wv[b];
+            sloc += v;
+            if (v > 0.0) last = b;
         }
-    } else {
-        if (threadIdx.x == 0) {
-            double tot = 0.0;
-            for (int b = 0; b < nb; ++b) tot += Pout[b];
-            double cum = 0.0;
-            int last = 0;
-            for (int b = 0; b < nb; ++b) {
-                cum += Pout[b];
-                if (Pout[b] > 0.0) last = b;
-                const double cv = ceil(cum / tot * 4294967296.0);
-                tab[TAB_CDF + b] = cv >= 4294967295.0 ? 0xffffffffu : (uint32_t)cv;
-            }
-            tab[0] = (uint32_t)last;
-            tab[1] = 0u;
+        csum[threadIdx.x] = sloc;
+        clast[threadIdx.x] = last;
+    }
+    __syncthreads();
+    __shared__ double total_sh;
+    __shared__ int last_sh;
+    if (threadIdx.x == 0) {
+        double run = 0.0;
+        int last = 0;
+        for (int t = 0; t < TB_THREADS; ++t) {
+            const double c = csum[t];
+            csum[t] = run;  // exclusive prefix
+            run += c;
+            if (clast[t] >= 0) last = clast[t];
         }
+        total_sh = run;
+        last_sh = last;
+    }
+    __syncthreads();
+    {
+        const double tot = total_sh;
+        const double off = csum[threadIdx.x];
+        double loc = 0.0;
+        for (int b = b0; b < b1; ++b) {
+            loc += absw ? fabs(wv[b]) : wv[b];
+            const double cv = ceil((off + loc) / tot * 4294967296.0);
+            tab[TAB_CDF + b] = cv >= 4294967295.0 ? 0xffffffffu : (uint32_t)cv;
+        }
+    }
+    if (threadIdx.x == 0) {
+        tab[0] = (uint32_t)last_sh;
+        tab[1] = kind == 1 ? __float_as_uint((float)total_sh) : 0u;
+    }
+    __syncthreads();
+    // guide[g] = first b with CDF[b] > g * 2^24 (CDF nondecreasing)
+    for (int g = threadIdx.x; g <= 256; g += TB_THREADS) {
+        const unsigned long long thr = (unsigned long long)g << 24;
+        uint32_t lo = 0, hi = (uint32_t)nb;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((unsigned long long)tab[TAB_CDF + mid] <= thr)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        tab[TAB_GUIDE + g] = lo;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t b = 0;
-        for (uint32_t g = 0; g <= 256; ++g) {
-            const unsigned long long thr = (unsigned long long)g << 24;
-            while (b < (uint32_t)nb && (unsigned long long)tab[TAB_CDF + b] <= thr) ++b;
-            tab[TAB_GUIDE + g] = b;
-        }
         __threadfence();
         C.ready[idx] = 1u;
     }
