@@ -184,6 +184,7 @@ struct FirstArgs {
     int32_t n;
     Counters* ctr;
     uint32_t lane_stride;
+    int32_t round;  // 0: every walk is processed and its done flag written
     StructDev S0;  // single-segment launches: the structure header (kernel arguments)
 };
 
@@ -874,7 +875,7 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
          g += (unsigned long long)gridDim.x * blockDim.x) {
         const GAS Segment& SG = gp(A.segs)[MULTI ? find_segment(A.segs, A.n_segs, g) : 0];
         const unsigned long long k = g - SG.offset;
-        if (gp(SG.first_done)[k]) continue;
+        if (A.round > 0 && gp(SG.first_done)[k]) continue;
         auto& S = [&]() -> decltype(auto) {
             if constexpr (MULTI)
                 return *gp(SG.S);
@@ -962,6 +963,7 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         const int res = lookup_or_insert(A.cache, key, key_hash(A.cache.key_words, key), &idx, r2.x, &glo, &ghi);
         if (res != LOOKUP_HIT) {
             if (res == LOOKUP_FULL) err |= ERR_TABLE_CAP;
+            if (A.round == 0) gpw(SG.first_done)[k] = 0u;
             ++missing;
             continue;
         }
@@ -2551,9 +2553,9 @@ struct Runner {
             o += (b + 255) / 256 * 256;
             return r;
         };
-        const size_t o_ctr = sz(sizeof(Counters)), o_st = sz(16);
+        // counters and segment list adjacent: one copy sets both per run
+        const size_t o_ctr = sz(sizeof(Counters)), o_sg = sz(sizeof(Segment) * (size_t)seg_cap), o_st = sz(16);
         const size_t o_p0 = sz(sizeof(Parked) * (size_t)park_cap), o_p1 = sz(sizeof(Parked) * (size_t)park_cap);
-        const size_t o_sg = sz(sizeof(Segment) * (size_t)seg_cap);
         mem = (char*)dev_alloc(o);
         ctr = (Counters*)(mem + o_ctr);
         status = (uint32_t*)(mem + o_st);
@@ -2642,7 +2644,8 @@ struct Runner {
         MW_REQUIRE(!(h.err & ERR_STEP_CAP), MW_ELIMIT, "a micro-walk exceeded %u steps", MW_STEP_CAP);
     }
 
-    // Runs every walk of segs (first_done must be zeroed by the caller).  s0:
+    // Runs every walk of segs (the first round of first transitions writes
+    // every walk's done flag).  s0:
     // host copy of the structure header of a single segment.
     Counters run(const std::vector<Segment>& segs, const StructDev* s0) {
         MW_REQUIRE((int)segs.size() <= seg_cap && !segs.empty(), MW_EINVAL, "bad segment list");
@@ -2652,8 +2655,13 @@ struct Runner {
         unsigned long long total = 0;
         for (const Segment& sgm : segs) total += sgm.count;
         MW_REQUIRE(total <= park_cap || total <= (1ull << 40), MW_ELIMIT, "round too large");
-        MW_HIP(hipMemcpy(dsegs, segs.data(), sizeof(Segment) * segs.size(), hipMemcpyHostToDevice));
-        MW_HIP(hipMemset(ctr, 0, sizeof(Counters)));
+        {
+            // zeroed counters and the segment list in one copy
+            const size_t off = (char*)dsegs - (char*)ctr;
+            std::vector<char> staging(off + sizeof(Segment) * segs.size(), 0);
+            memcpy(staging.data() + off, segs.data(), sizeof(Segment) * segs.size());
+            MW_HIP(hipMemcpy(ctr, staging.data(), staging.size(), hipMemcpyHostToDevice));
+        }
         for (int round = 0;; ++round) {
             FirstArgs F{};
             F.segs = dsegs;
@@ -2664,7 +2672,8 @@ struct Runner {
             F.ctr = ctr;
             F.lane_stride = g.first_stride;
             if (segs.size() == 1) F.S0 = *s0;
-            MW_HIP(hipMemset(&ctr->first_missing, 0, 4));
+            F.round = round;
+            if (round > 0) MW_HIP(hipMemset(&ctr->first_missing, 0, 4));
             const int fblocks = (int)std::min<uint64_t>((total + FRW_THREADS - 1) / FRW_THREADS, (uint64_t)g.first_blocks);
             if (segs.size() == 1)
                 first_kernel<false><<<fblocks, FRW_THREADS, g.first_lds>>>(F);
@@ -2675,8 +2684,8 @@ struct Runner {
             MW_HIP(hipMemcpy(&h, ctr, sizeof h, hipMemcpyDeviceToHost));
             check_errors(h);
             MW_REQUIRE(round < 1000, MW_ELIMIT, "first-transition retry limit reached");
+            if (h.first_missing == 0) break;  // no walk missed a table, so none was queued
             build_pending();
-            if (h.first_missing == 0) break;
         }
         uint32_t n_resume = 0;
         int cur = 0;
@@ -2697,9 +2706,12 @@ struct Runner {
             W.lane_stride = g.lane_stride;
             W.uniform_index = uniform_index;
             if (!multi) W.S0 = *s0;
-            // reset the per-launch queue state, keep the walk counter
-            MW_HIP(hipMemset(&ctr->park_count, 0, 4));
-            MW_HIP(hipMemset(&ctr->resume_next, 0, 8));
+            // reset the per-launch queue state, keep the walk counter (zero
+            // from the start of the run for the first launch)
+            if (local > 0) {
+                MW_HIP(hipMemset(&ctr->park_count, 0, 4));
+                MW_HIP(hipMemset(&ctr->resume_next, 0, 8));
+            }
             MW_HIP(hipEventRecord(ev0, 0));
             if (expand_m > 0) {
                 W.lane_stride = g.lane_stride_e;
@@ -2729,7 +2741,8 @@ struct Runner {
             walker_ms += ms;
             check_errors(h);
             MW_REQUIRE(local < 100000, MW_ELIMIT, "walker relaunch limit reached");
-            build_pending();
+            // a lane that queued a table parked its walk
+            if (h.park_count > 0) build_pending();
             n_resume = std::min(h.park_count, park_cap);
             cur ^= 1;
             if (n_resume == 0 && h.walk_next >= total) return h;
@@ -2902,8 +2915,9 @@ struct Extraction {
         };
         const uint64_t red_blocks = (chunk_cap + RED_CHUNK - 1) / RED_CHUNK;
         const size_t o_sd = sz(sizeof(StructDev)), o_G = sz(sizeof(GaussDev)), o_gf = sz(sizeof(GaussFace) * n_faces);
+        const size_t o_acc = sz(sizeof(double) * 2 * K);  // zeroed by the same copy
         const size_t o_part = sz(sizeof(float4) * red_blocks * K);
-        const size_t o_acc = sz(sizeof(double) * 2 * K), o_res = sz(sizeof(double) * 2 * K);
+        const size_t o_res = sz(sizeof(double) * 2 * K);
         const size_t o_fs = own_first ? sz(sizeof(float4) * chunk_cap) : 0;
         const size_t o_fd = own_first ? sz(sizeof(uint32_t) * chunk_cap) : 0;
         const size_t o_sn = own_scores ? sz(4 * chunk_cap) : 0, o_sw = own_scores ? sz(4 * chunk_cap) : 0;
@@ -2927,14 +2941,13 @@ struct Extraction {
         Gh.area = (float)GH.area;
         Gh.n_faces = (int32_t)n_faces;
         Gh.faces = (const GaussFace*)(mem + o_gf);
-        // one host-to-device copy of the structure header, the surface header
-        // and its rectangles (laid out as on the device)
-        std::vector<char> staging(o_gf + sizeof(GaussFace) * n_faces - o_sd);
+        // one host-to-device copy of the structure header, the surface header,
+        // its rectangles and the zeroed fp64 sums (laid out as on the device)
+        std::vector<char> staging(o_acc + sizeof(double) * 2 * K - o_sd, 0);
         memcpy(staging.data(), &S, sizeof S);
         memcpy(staging.data() + (o_G - o_sd), &Gh, sizeof Gh);
         memcpy(staging.data() + (o_gf - o_sd), GH.faces.data(), sizeof(GaussFace) * n_faces);
         MW_HIP(hipMemcpy(mem + o_sd, staging.data(), staging.size(), hipMemcpyHostToDevice));
-        MW_HIP(hipMemset(acc, 0, sizeof(double) * 2 * K));
         res.assign(2 * K, 0.0);
     }
     ~Extraction() { dev_free(mem); }
@@ -2943,7 +2956,6 @@ struct Extraction {
     // the extraction's own buffers).
     Segment segment(uint64_t first, uint64_t count, uint64_t seed, int32_t* net, float* w) {
         MW_REQUIRE(count <= chunk_cap, MW_EINVAL, "chunk larger than its buffers");
-        MW_HIP(hipMemset(first_done, 0, sizeof(uint32_t) * count));
         Segment s{};
         s.S = dS;
         s.G = G;
