@@ -659,6 +659,21 @@ __device__ __forceinline__ uint32_t plane_code(LaneCube L, const CubeInfo& I, in
 __device__ void plane_mean_codes(LaneCube L, int n, int a, uint32_t* out) {
     const int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
     const unsigned long long area = (unsigned long long)n * n;
+    // runs of equal masks along u, and of equal masks and background codes
+    // along v (bit i: a run starts at i), found once for all planes
+    uint32_t ubnd = 1u, vbnd = 1u;
+    {
+        uint32_t pu = L.mask[u * n], pv = L.mask[v * n], pb = a == 2 ? 0u : L.bz[0];
+        for (int i = 1; i < n; ++i) {
+            const uint32_t cu = L.mask[u * n + i], cv = L.mask[v * n + i], cb = a == 2 ? 0u : L.bz[i];
+            ubnd |= (cu != pu ? 1u : 0u) << i;
+            vbnd |= (cv != pv || cb != pb ? 1u : 0u) << i;
+            pu = cu;
+            pv = cv;
+            pb = cb;
+        }
+    }
+    const uint32_t full = n == 32 ? 0xffffffffu : ((1u << n) - 1u);
     uint32_t prev_ma = 0xffffffffu, prev_b = 0, prev = 0;
     for (int p = 0; p < n; ++p) {
         const uint32_t ma = L.mask[a * n + p];
@@ -668,22 +683,20 @@ __device__ void plane_mean_codes(LaneCube L, int n, int a, uint32_t* out) {
             continue;
         }
         unsigned long long sum = 0;
-        int i = 0;
-        while (i < n) {
-            const uint32_t mu = L.mask[u * n + i];
-            int li = 1;
-            while (i + li < n && L.mask[u * n + i + li] == mu) ++li;
-            const uint32_t mau = ma & mu;
-            int j = 0;
-            while (j < n) {
-                const uint32_t mv = L.mask[v * n + j];
+        for (uint32_t ur = ubnd; ur;) {
+            const int i = __builtin_ctz(ur);
+            ur &= ur - 1u;
+            const int li = (ur ? __builtin_ctz(ur) : n) - i;
+            const uint32_t mau = ma & L.mask[u * n + i];
+            unsigned long long row = 0;
+            for (uint32_t vr = vbnd & full; vr;) {
+                const int j = __builtin_ctz(vr);
+                vr &= vr - 1u;
+                const int lj = (vr ? __builtin_ctz(vr) : n) - j;
                 const uint32_t bv = a == 2 ? bp : L.bz[j];
-                int lj = 1;
-                while (j + lj < n && L.mask[v * n + j + lj] == mv && (a == 2 || L.bz[j + lj] == bv)) ++lj;
-                sum += (unsigned long long)(li * lj) * cell_code(L, mau & mv, bv);
-                j += lj;
+                row += (unsigned long long)lj * cell_code(L, mau & L.mask[v * n + j], bv);
             }
-            i += li;
+            sum += (unsigned long long)li * row;
         }
         unsigned long long qt = sum / area, rem = sum % area;
         if (2 * rem > area || (2 * rem == area && (qt & 1))) ++qt;
