@@ -1041,6 +1041,9 @@ __device__ __forceinline__ void mw_begin16(MwState& M, LaneCube L, int n) {
 __device__ __forceinline__ bool mw_block16(MwState& M, LaneCube L, int n, const Rand4& r) {
     const uint32_t us[4] = {r.x, r.y, r.z, r.w};
     bool alive = true;
+    // node coordinates packed in bytes 0, 1, 2 (a coordinate never drops
+    // below 0, so a move is one shifted add)
+    uint32_t co = (uint32_t)M.ni | ((uint32_t)M.nj << 8) | ((uint32_t)M.nk << 16);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (alive) {
@@ -1054,30 +1057,39 @@ __device__ __forceinline__ bool mw_block16(MwState& M, LaneCube L, int n, const 
             const uint32_t gmy = a0 + b0, gmz = c000 + c001 + c010 + c011;
             const uint32_t S2 = total + gmy, S3 = total + total, S4 = S3 + gmz, S5 = S3 + total;
             const uint32_t xq = __umulhi(us[q], S5);
-            const uint32_t d = (uint32_t)(xq >= gmx) + (uint32_t)(xq >= total) + (uint32_t)(xq >= S2) +
-                               (uint32_t)(xq >= S3) + (uint32_t)(xq >= S4);
-            const int ax = (int)(d >> 1);
-            const int dir = (d & 1u) ? 1 : -1;
+            // the move #{k : xq >= S_k} of the five thresholds, decoded from
+            // the comparisons: x while xq < total (up when xq >= gmx), y while
+            // xq < S3 (up when xq >= S2), z otherwise (up when xq >= S4)
+            const bool t2 = xq >= total, t4 = xq >= S3;
+            const bool ux = xq >= gmx, uy = xq >= S2, uz = xq >= S4;
+            const bool up = (t4 & uz) | (t2 & !t4 & uy) | (!t2 & ux);  // lane masks: scalar logic
+            const uint32_t sh = t4 ? 16u : (t2 ? 8u : 0u);
             ++M.s;
-            M.ni += ax == 0 ? dir : 0;
-            M.nj += ax == 1 ? dir : 0;
-            M.nk += ax == 2 ? dir : 0;
-            const int cnew = ax == 0 ? M.ni : (ax == 1 ? M.nj : M.nk);
+            co += (up ? 1u : 0xffffffffu) << sh;
+            const int cnew = (int)((co >> sh) & 0xffu);
             alive = cnew != 0 && cnew != n;
             // prepared masks of the two cell rows around the new node along
             // ax (the index is clamped; a walk that left is not stepped again)
             const int cc = min(max(cnew, 1), n - 1);
-            const uint32_t lo = L.mask[ax * n + cc - 1], hi = L.mask[ax * n + cc];
-            const uint32_t plo = ax == 2 ? prep_z(lo, cc - 1) : prep_xy(lo);
-            const uint32_t phi = ax == 2 ? prep_z(hi, cc) : prep_xy(hi);
-            M.px0 = ax == 0 ? plo : M.px0;
-            M.px1 = ax == 0 ? phi : M.px1;
-            M.py0 = ax == 1 ? plo : M.py0;
-            M.py1 = ax == 1 ? phi : M.py1;
-            M.pz0 = ax == 2 ? plo : M.pz0;
-            M.pz1 = ax == 2 ? phi : M.pz1;
+            // rows cc - 1 and cc of the move's axis (row0 points at row -1 of
+            // x; n is even, so the three axes start n u16 apart)
+            const uint16_t* rr = (t4 ? L.mask + 2 * n : (t2 ? L.mask + n : L.mask)) - 1 + cc;
+            const uint32_t lo = rr[0], hi = rr[1];
+            const uint32_t bgz = 1u << (15 - cc);  // background bit of z row cc
+            const uint32_t plo = t4 ? (lo << 16) | (bgz << 1) : prep_xy(lo);
+            const uint32_t phi = t4 ? (hi << 16) | bgz : prep_xy(hi);
+            const bool xm = !t2, ym = t2 && !t4;
+            M.px0 = xm ? plo : M.px0;
+            M.px1 = xm ? phi : M.px1;
+            M.py0 = ym ? plo : M.py0;
+            M.py1 = ym ? phi : M.py1;
+            M.pz0 = t4 ? plo : M.pz0;
+            M.pz1 = t4 ? phi : M.pz1;
         }
     }
+    M.ni = (int)(co & 0xffu);
+    M.nj = (int)((co >> 8) & 0xffu);
+    M.nk = (int)((co >> 16) & 0xffu);
     return alive;
 }
 
