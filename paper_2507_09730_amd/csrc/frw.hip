@@ -79,10 +79,12 @@ struct StructDev {
     const uint32_t* ge_list;
     const uint32_t* gx_off;
     const uint32_t* gx_list;
-    // the boxes of gc_list and gd_list in place (lo, hi per entry): one
-    // load per candidate instead of an index and then the box
+    // the boxes of gc_list, gd_list, ge_list and gx_list in place (lo, hi
+    // per entry): one load per candidate instead of an index and then the box
     const float4* gc_rec;
     const float4* gd_rec;
+    const float4* ge_rec;
+    const float4* gx_rec;
     float delta_abs;
 };
 
@@ -194,6 +196,28 @@ __device__ __forceinline__ float4 ldf4(const float4* p) {
     const gvec4 v = *(const GAS gvec4*)p;
     return make_float4(v.x, v.y, v.z, v.w);
 }
+// Candidate records rec[2 q] (lo), rec[2 q + 1] (hi) for q in [b, e), handed
+// to f in list order; the loads of CAND_BATCH records are issued together (a
+// batch running past e repeats the last record, which f does not see).  f
+// returns false to stop.
+constexpr int CAND_BATCH = 4;
+template <class F>
+__device__ __forceinline__ void for_each_record(const float4* rec, uint32_t b, uint32_t e, F&& f) {
+    for (uint32_t q0 = b; q0 < e; q0 += CAND_BATCH) {
+        float4 lo[CAND_BATCH], hi[CAND_BATCH];
+#pragma unroll
+        for (int j = 0; j < CAND_BATCH; ++j) {
+            const uint32_t q = min(q0 + (uint32_t)j, e - 1);
+            lo[j] = ldf4(rec + 2 * (size_t)q);
+            hi[j] = ldf4(rec + 2 * (size_t)q + 1);
+        }
+        bool go = true;
+#pragma unroll
+        for (int j = 0; j < CAND_BATCH; ++j)
+            if (go && q0 + (uint32_t)j < e) go = f(lo[j], hi[j]);
+        if (!go) return;
+    }
+}
 __device__ __forceinline__ Parked ldpark(const Parked* p) {
     const GAS guvec4* q = (const GAS guvec4*)p;
     const guvec4 a = q[0], b = q[1];
@@ -249,24 +273,14 @@ __device__ float query_dist(SR& S, float3 p, int cell, int* nearest) {
     float best = INFINITY;
     int who = S.n_nets;
     const uint32_t b = gp(S.gc_off)[cell], e = gp(S.gc_off)[cell + 1];
-    const float4* rec = S.gc_rec;
-    float4 nlo = make_float4(0.f, 0.f, 0.f, 0.f), nhi = nlo;
-    if (b < e) {
-        nlo = ldf4(rec + 2 * (size_t)b);
-        nhi = ldf4(rec + 2 * (size_t)b + 1);
-    }
-    for (uint32_t q = b; q < e; ++q) {
-        const float4 lo = nlo, hi = nhi;
-        if (q + 1 < e) {
-            nlo = ldf4(rec + 2 * (size_t)(q + 1));
-            nhi = ldf4(rec + 2 * (size_t)(q + 1) + 1);
-        }
+    for_each_record(S.gc_rec, b, e, [&](const float4& lo, const float4& hi) {
         const float d = box_dist(lo, hi, p);
         if (d < best) {
             best = d;
             who = __float_as_int(lo.w);
         }
-    }
+        return true;
+    });
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float x = axis_of(p, a);
@@ -443,55 +457,43 @@ __device__ CubeInfo build_cube(SR& S, int cell, float3 c, float R, int n, LaneCu
         }
     }
     info.n_layers = lmax - lmin + 1;
-    // dielectric boxes touching the cube, in priority order (the next box's
-    // record is fetched while the current one is processed)
+    // dielectric boxes touching the cube, in priority order
     int nbits = 0;
     const uint32_t* doff = expanded ? S.gx_off : S.gd_off;
     const uint32_t b = dr ? dr->x : gp(doff)[cell], e = dr ? dr->y : gp(doff)[cell + 1];
-    const GAS uint32_t* glist = gp(expanded ? S.gx_list : S.gd_list);
-    const float4* drec = S.gd_rec;
-    // record q of the candidate list: in place for ordinary cubes, through
-    // the box index for expanded ones
-    auto cand = [&](uint32_t q, float4& lo, float4& hi) {
-        if (!expanded) {
-            lo = ldf4(drec + 2 * (size_t)q);
-            hi = ldf4(drec + 2 * (size_t)q + 1);
-        } else {
-            const uint32_t id = glist[q];
-            lo = ldf4(S.diel_lo + id);
-            hi = ldf4(S.diel_hi + id);
-        }
-    };
-    float4 nlo = make_float4(0.f, 0.f, 0.f, 0.f), nhi = nlo;
-    if (b < e) cand(b, nlo, nhi);
-    for (uint32_t q = b; q < e; ++q) {
-        const float4 blo = nlo, bhi = nhi;
-        if (q + 1 < e) cand(q + 1, nlo, nhi);
+    // the cube's extent inside the window along each axis, and whether it
+    // crosses a symmetry wall (then cells fold back into the window)
+    float clo[3], chi[3];
+    bool crosses[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        clo[a] = lo0[a];
+        chi[a] = lo0[a] + 2.f * R;
+        if (S.bc[2 * a] == MW_BC_NEUMANN) clo[a] = fmaxf(clo[a], S.wlo[a]);
+        if (S.bc[2 * a + 1] == MW_BC_NEUMANN) chi[a] = fminf(chi[a], S.whi[a]);
+        crosses[a] = (S.bc[2 * a] == MW_BC_NEUMANN && lo0[a] < S.wlo[a]) ||
+                     (S.bc[2 * a + 1] == MW_BC_NEUMANN && lo0[a] + 2.f * R > S.whi[a]);
+    }
+    const float inv_h = (float)n / (2.f * R);
+    for_each_record(expanded ? S.gx_rec : S.gd_rec, b, e, [&](const float4& blo, const float4& bhi) {
         const float bl[3] = {blo.x, blo.y, blo.z}, bh[3] = {bhi.x, bhi.y, bhi.z};
         bool touch = true;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            float clo = lo0[a], chi = lo0[a] + 2.f * R;
-            if (S.bc[2 * a] == MW_BC_NEUMANN) clo = fmaxf(clo, S.wlo[a]);
-            if (S.bc[2 * a + 1] == MW_BC_NEUMANN) chi = fminf(chi, S.whi[a]);
-            if (!(bl[a] <= chi && bh[a] >= clo)) touch = false;
-        }
-        if (!touch) continue;
+        for (int a = 0; a < 3; ++a)
+            if (!(bl[a] <= chi[a] && bh[a] >= clo[a])) touch = false;
+        if (!touch) return true;
         if (nbits >= MAX_REGIONS) {
             info.overflow = true;
-            break;
+            return false;
         }
         const uint16_t bit = (uint16_t)(1u << nbits);
         L.codes[MAX_REGIONS - 1 - nbits] = __float_as_uint(bhi.w);
         ++nbits;
-        const float inv_h = (float)n / (2.f * R);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const bool crosses = (S.bc[2 * a] == MW_BC_NEUMANN && lo0[a] < S.wlo[a]) ||
-                                 (S.bc[2 * a + 1] == MW_BC_NEUMANN && lo0[a] + 2.f * R > S.whi[a]);
             // masks hold toggles here (bit b flips where box b's run of
             // cells starts or ends); the pass below turns them into masks
-            if (!crosses) {
+            if (!crosses[a]) {
                 // cells whose centre lo0 + (i + 1/2) h lies in [bl, bh)
                 const float f0 = fminf(fmaxf((bl[a] - lo0[a]) * inv_h - 0.5f, -1.f), (float)n + 1.f);
                 const float f1 = fminf(fmaxf((bh[a] - lo0[a]) * inv_h - 0.5f, -1.f), (float)n + 1.f);
@@ -510,7 +512,8 @@ __device__ CubeInfo build_cube(SR& S, int cell, float3 c, float R, int n, LaneCu
                 }
             }
         }
-    }
+        return true;
+    });
     // toggles -> masks (prefix xor along each axis); aggregate masks:
     // present boxes and boxes spanning all cells per axis
     uint32_t O[3];
@@ -587,17 +590,18 @@ __device__ bool build_conductors(SR& S, int cell, float3 c, float R, int n, Lane
     }
     int nb = 0;
     const uint32_t b = gp(S.ge_off)[cell], e = gp(S.ge_off)[cell + 1];
-    const GAS uint32_t* clist = gp(S.ge_list);
-    for (uint32_t q = b; q < e; ++q) {
-        const uint32_t id = clist[q];
-        const float4 lo4 = ldf4(S.cond_lo + id), hi4 = ldf4(S.cond_hi + id);
+    bool fits = true;
+    for_each_record(S.ge_rec, b, e, [&](const float4& lo4, const float4& hi4) {
         const float bl[3] = {lo4.x, lo4.y, lo4.z}, bh[3] = {hi4.x, hi4.y, hi4.z};
         bool touch = true;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
             if (!(bl[a] < o[a] + 2.f * R && bh[a] > o[a])) touch = false;
-        if (!touch) continue;
-        if (nb >= EXP_MAX_COND) return false;
+        if (!touch) return true;
+        if (nb >= EXP_MAX_COND) {
+            fits = false;
+            return false;
+        }
         const uint8_t bit = (uint8_t)(1u << nb);
         E.cnet[nb] = (uint16_t)__float_as_int(lo4.w);
 #pragma unroll
@@ -612,14 +616,23 @@ __device__ bool build_conductors(SR& S, int cell, float3 c, float R, int n, Lane
             E.theta[(nb * 3 + a) * 2 + 1] = theta_q((float)(i1 + 1) - u1);
         }
         ++nb;
-    }
+        return true;
+    });
+    if (!fits) return false;
+    // prefix xor along each axis, four nodes per dword (the axes follow each
+    // other without padding: the running value restarts at nodes np and 2 np)
+    int idx = 0;
+    uint32_t m = 0;
+    for (int w = 0; w < (3 * np + 3) / 4; ++w) {
+        const uint32_t v = m32[w];
+        uint32_t out = 0;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        uint32_t m = 0;
-        for (int i = 0; i < np; ++i) {
-            m ^= E.nmask[a * np + i];
-            E.nmask[a * np + i] = (uint8_t)m;
+        for (int j = 0; j < 4; ++j, ++idx) {
+            if (idx == np || idx == 2 * np) m = 0;
+            m ^= (v >> (8 * j)) & 0xffu;
+            out |= m << (8 * j);
         }
+        m32[w] = out;
     }
     return true;
 }
@@ -636,6 +649,65 @@ __device__ __forceinline__ float expanded_size(SR& S, float3 c, float d, int n, 
         if (S.bc[2 * a + 1] == MW_BC_NEUMANN) R = fminf(R, S.whi[a] - cc[a]);
     }
     return fmaxf(R, d);
+}
+
+// Expanded cubes are halved while they touch more than MAX_REGIONS dielectric
+// boxes or more than EXP_MAX_COND conductors: R -> max(R / 2, d) while R > d,
+// then R / 2.  exp_fit counts, in one pass over both candidate lists and with
+// the comparisons build_cube and build_conductors make, the boxes touched at
+// the first EXP_LEVELS sizes of that sequence and returns the first size that
+// fits (else the last one, from which halving goes on), so that the cube is
+// built once instead of once per size tried.  *level: its index.
+constexpr int EXP_LEVELS = 3;
+template <class SR>
+__device__ __forceinline__ float exp_fit(SR& S, int cell, float3 c, float R0, float d, int* level) {
+    const float cc[3] = {c.x, c.y, c.z};
+    float Rk[EXP_LEVELS];
+    // per size and axis: the cube's extent [lo, lo + 2R] and its part
+    // inside the window at symmetry walls
+    float lo[EXP_LEVELS][3], hi[EXP_LEVELS][3], clo[EXP_LEVELS][3], chi[EXP_LEVELS][3];
+    Rk[0] = R0;
+#pragma unroll
+    for (int k = 1; k < EXP_LEVELS; ++k)
+        Rk[k] = Rk[k - 1] > d ? fmaxf(0.5f * Rk[k - 1], d) : 0.5f * Rk[k - 1];
+#pragma unroll
+    for (int k = 0; k < EXP_LEVELS; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[k][a] = cc[a] - Rk[k];
+            hi[k][a] = lo[k][a] + 2.f * Rk[k];
+            clo[k][a] = S.bc[2 * a] == MW_BC_NEUMANN ? fmaxf(lo[k][a], S.wlo[a]) : lo[k][a];
+            chi[k][a] = S.bc[2 * a + 1] == MW_BC_NEUMANN ? fminf(hi[k][a], S.whi[a]) : hi[k][a];
+        }
+    int nd[EXP_LEVELS] = {}, nc[EXP_LEVELS] = {};
+    for_each_record(S.gx_rec, gp(S.gx_off)[cell], gp(S.gx_off)[cell + 1], [&](const float4& bl, const float4& bh) {
+#pragma unroll
+        for (int k = 0; k < EXP_LEVELS; ++k) {
+            const bool t = bl.x <= chi[k][0] && bh.x >= clo[k][0] && bl.y <= chi[k][1] && bh.y >= clo[k][1] &&
+                           bl.z <= chi[k][2] && bh.z >= clo[k][2];
+            nd[k] += t ? 1 : 0;
+        }
+        return true;
+    });
+    for_each_record(S.ge_rec, gp(S.ge_off)[cell], gp(S.ge_off)[cell + 1], [&](const float4& bl, const float4& bh) {
+#pragma unroll
+        for (int k = 0; k < EXP_LEVELS; ++k) {
+            const bool t = bl.x < hi[k][0] && bh.x > lo[k][0] && bl.y < hi[k][1] && bh.y > lo[k][1] &&
+                           bl.z < hi[k][2] && bh.z > lo[k][2];
+            nc[k] += t ? 1 : 0;
+        }
+        return true;
+    });
+    int lv = EXP_LEVELS - 1;
+    float R = Rk[EXP_LEVELS - 1];
+#pragma unroll
+    for (int k = EXP_LEVELS - 2; k >= 0; --k)
+        if (nd[k] <= MAX_REGIONS && nc[k] <= EXP_MAX_COND) {
+            lv = k;
+            R = Rk[k];
+        }
+    *level = lv;
+    return R;
 }
 
 __device__ __forceinline__ bool stratified_along(const CubeInfo& I, int s) {
@@ -1555,9 +1627,10 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             // and may hold conductors; halved (not below
                             // dq) while it holds too many boxes or
                             // conductors, then by the ordinary rule
-                            float Re = expanded_size(S, c, dq, n, A.expand_m);
+                            int it0;
+                            float Re = exp_fit(S, cell, c, expanded_size(S, c, dq, n, A.expand_m), dq, &it0);
                             bool ok = false;
-                            for (int it = 0;; ++it) {
+                            for (int it = it0;; ++it) {
                                 const CubeInfo IE = build_cube(S, cell, c, Re, n, L, true, lt);
                                 ok = !IE.overflow && build_conductors(S, cell, c, Re, n, E);
                                 if (ok || it >= 110) break;
@@ -2462,6 +2535,10 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
         lb += ((32ull * tot[0] + 255) / 256) * 256;
         const size_t o_drec = lb;
         lb += ((32ull * tot[1] + 255) / 256) * 256;
+        const size_t o_erec = lb;
+        lb += ((32ull * tot[2] + 255) / 256) * 256;
+        const size_t o_xrec = lb;
+        lb += ((32ull * tot[3] + 255) / 256) * 256;
         const size_t list_bytes = lb + 512;
         char* lists = (char*)dev_alloc(list_bytes);
         st->bytes = o + list_bytes;
@@ -2475,6 +2552,10 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
         float4* drec = (float4*)(lists + o_drec);
         if (tot[0]) grid_records_kernel<<<(tot[0] + 255) / 256, 256>>>(clist, tot[0], S.cond_lo, S.cond_hi, crec);
         if (tot[1]) grid_records_kernel<<<(tot[1] + 255) / 256, 256>>>(dlist, tot[1], S.diel_lo, S.diel_hi, drec);
+        float4* erec = (float4*)(lists + o_erec);
+        float4* xrec = (float4*)(lists + o_xrec);
+        if (tot[2]) grid_records_kernel<<<(tot[2] + 255) / 256, 256>>>(elist, tot[2], S.cond_lo, S.cond_hi, erec);
+        if (tot[3]) grid_records_kernel<<<(tot[3] + 255) / 256, 256>>>(xlist, tot[3], S.diel_lo, S.diel_hi, xrec);
         MW_HIP(hipGetLastError());
         S.gc_off = coff;
         S.gc_list = clist;
@@ -2486,6 +2567,8 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
         S.gx_list = xlist;
         S.gc_rec = crec;
         S.gd_rec = drec;
+        S.ge_rec = erec;
+        S.gx_rec = xrec;
         st->d = (StructDev*)(m + o_desc);
         MW_HIP(hipMemcpy(st->d, &S, sizeof S, hipMemcpyHostToDevice));
         MW_HIP(hipDeviceSynchronize());
