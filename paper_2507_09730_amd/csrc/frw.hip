@@ -269,7 +269,7 @@ __device__ __forceinline__ int grid_cell(SR& S, float3 p) {
 // Largest conductor-free cube: L-infinity distance to the nearest conductor
 // or grounded window face; nearest = net, or n_nets for a grounded face.
 template <class SR>
-__device__ float query_dist(SR& S, float3 p, int cell, int* nearest) {
+__device__ __forceinline__ float query_dist(SR& S, float3 p, int cell, int* nearest) {
     float best = INFINITY;
     int who = S.n_nets;
     const uint32_t b = gp(S.gc_off)[cell], e = gp(S.gc_off)[cell + 1];
@@ -312,18 +312,22 @@ __device__ __forceinline__ float3 fold3(SR& S, float3 p) {
 // -------------------------------------------------------------------------
 // Per-lane cube description in LDS: masks[3][n] (u16, dielectric boxes),
 // box codes[16] (u32, box bit b at codes[15 - b]), background codes bz[n]
-// (u32, per z cell) directly after them.
+// (u32, per z cell) directly after them.  The pointers carry the LDS address
+// space, so that functions the compiler does not inline still use LDS
+// instructions on them.
 // -------------------------------------------------------------------------
+#define LAS __attribute__((address_space(3)))
 struct LaneCube {
-    uint16_t* mask;   // mask[a * n + i]: bit b = box b's interval holds cell i's centre
-    uint32_t* codes;  // codes[15 - b]: code of box bit b
-    uint32_t* bz;     // background (layer) code of z cell k (= codes + 16)
+    LAS uint16_t* mask;   // mask[a * n + i]: bit b = box b's interval holds cell i's centre
+    LAS uint32_t* codes;  // codes[15 - b]: code of box bit b
+    LAS uint32_t* bz;     // background (layer) code of z cell k (= codes + 16)
 };
 
 __device__ __forceinline__ LaneCube lane_cube(uint32_t* my, int n) {
+    LAS uint32_t* m = (LAS uint32_t*)my;
     LaneCube L;
-    L.mask = reinterpret_cast<uint16_t*>(my);
-    L.codes = my + ((3 * n + 1) / 2);
+    L.mask = reinterpret_cast<LAS uint16_t*>(m);
+    L.codes = m + ((3 * n + 1) / 2);
     L.bz = L.codes + MAX_REGIONS;
     return L;
 }
@@ -347,9 +351,9 @@ __device__ __forceinline__ uint32_t cell_code(LaneCube L, uint32_t m, uint32_t b
 // enters the object — side 0 through the object's low face (a +a move),
 // side 1 through its high face (a -a move).
 struct LaneExp {
-    uint8_t* nmask;
-    uint16_t* cnet;
-    uint16_t* theta;
+    LAS uint8_t* nmask;
+    LAS uint16_t* cnet;
+    LAS uint16_t* theta;
 };
 
 __device__ __forceinline__ int lane_base_words(int n) { return (3 * n + 1) / 2 + MAX_REGIONS + n; }
@@ -357,16 +361,29 @@ __host__ __device__ __forceinline__ int lane_exp_words(int n) { return (3 * (n +
 
 __device__ __forceinline__ LaneExp lane_exp(uint32_t* my, int n) {
     LaneExp E;
-    uint32_t* q = my + lane_base_words(n);
-    E.nmask = reinterpret_cast<uint8_t*>(q);
+    LAS uint32_t* q = (LAS uint32_t*)my + lane_base_words(n);
+    E.nmask = reinterpret_cast<LAS uint8_t*>(q);
     q += (3 * (n + 1) + 3) / 4;
-    E.cnet = reinterpret_cast<uint16_t*>(q);
-    E.theta = reinterpret_cast<uint16_t*>(q + 4);
+    E.cnet = reinterpret_cast<LAS uint16_t*>(q);
+    E.theta = reinterpret_cast<LAS uint16_t*>(q + 4);
     return E;
 }
 
 __device__ __forceinline__ uint16_t theta_q(float th) {
     return (uint16_t)fminf(65535.f, fmaxf(4096.f, rintf(th * 65535.f)));  // theta >= 1/16
+}
+
+// Bit toggles of 16-bit and 8-bit LDS entries (dword-aligned arrays) as LDS
+// atomics on the containing dword: they return nothing, so a run of toggles
+// issues without waiting for read-modify-write round trips.
+__device__ __forceinline__ void lds_xor(LAS uint32_t* p, uint32_t v) {
+    __hip_atomic_fetch_xor(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void toggle16(LAS uint16_t* base, int k, uint32_t bits) {
+    lds_xor(reinterpret_cast<LAS uint32_t*>(base) + (k >> 1), bits << (16 * (k & 1)));
+}
+__device__ __forceinline__ void toggle8(LAS uint8_t* base, int k, uint32_t bits) {
+    lds_xor(reinterpret_cast<LAS uint32_t*>(base) + (k >> 2), bits << (8 * (k & 3)));
 }
 
 struct CubeInfo {
@@ -394,7 +411,7 @@ __device__ __forceinline__ void layer_walk(Z z0, C lcode, int nl, float zlo, flo
     *lmin = l;
     *lmax = lt;
     uint32_t code = lcode[l];
-    uint32_t* bz2 = L.bz;
+    LAS uint32_t* bz2 = L.bz;
     if (l == lt) {
         // one layer holds every centre (n is even)
         for (int k = 0; k < n; k += 2) {
@@ -425,12 +442,13 @@ __device__ __forceinline__ void layer_walk(Z z0, C lcode, int nl, float zlo, flo
 // dr: when not null, the cell's dielectric candidate range (gd_off[cell],
 // gd_off[cell + 1]) read ahead by the caller (ordinary cubes only).
 template <class SR>
-__device__ CubeInfo build_cube(SR& S, int cell, float3 c, float R, int n, LaneCube L, bool expanded = false,
-                               const uint32_t* lt = nullptr, const uint2* dr = nullptr) {
+__device__ __forceinline__ CubeInfo build_cube(SR& S, int cell, float3 c, float R, int n, LaneCube L,
+                                              bool expanded = false, const uint32_t* lt = nullptr,
+                                              const uint2* dr = nullptr) {
     CubeInfo info{};
     const float h = 2.f * R / (float)n;
     const float lo0[3] = {c.x - R, c.y - R, c.z - R};
-    uint32_t* mask32 = reinterpret_cast<uint32_t*>(L.mask);  // 3n is even
+    LAS uint32_t* mask32 = reinterpret_cast<LAS uint32_t*>(L.mask);  // 3n is even
     for (int q = 0; q < 3 * n / 2; ++q) mask32[q] = 0u;
     // background layer of every z cell: layer(k) = #{q >= 1 : z_k >= z0[q]}
     // for the cell centre z_k (layer_z0 ascends)
@@ -499,15 +517,15 @@ __device__ CubeInfo build_cube(SR& S, int cell, float3 c, float R, int n, LaneCu
                 const float f1 = fminf(fmaxf((bh[a] - lo0[a]) * inv_h - 0.5f, -1.f), (float)n + 1.f);
                 const int i0 = max((int)ceilf(f0), 0), i1 = min((int)ceilf(f1), n);
                 if (i0 < i1) {
-                    L.mask[a * n + i0] ^= bit;
-                    if (i1 < n) L.mask[a * n + i1] ^= bit;
+                    toggle16(L.mask, a * n + i0, bit);
+                    if (i1 < n) toggle16(L.mask, a * n + i1, bit);
                 }
             } else {
                 bool prev = false;
                 for (int i = 0; i < n; ++i) {
                     const float x = fold(S, a, lo0[a] + ((float)i + 0.5f) * h);
                     const bool in = x >= bl[a] && x < bh[a];
-                    if (in != prev) L.mask[a * n + i] ^= bit;
+                    if (in != prev) toggle16(L.mask, a * n + i, bit);
                     prev = in;
                 }
             }
@@ -521,7 +539,7 @@ __device__ CubeInfo build_cube(SR& S, int cell, float3 c, float R, int n, LaneCu
     for (int a = 0; a < 3; ++a) {
         // two cells per dword (n is even, so every axis starts on a dword)
         uint32_t A = 0xffffu, Oa = 0, m = 0;
-        uint32_t* w32 = mask32 + a * (n / 2);
+        LAS uint32_t* w32 = mask32 + a * (n / 2);
         for (int i = 0; i < n / 2; ++i) {
             const uint32_t w = w32[i];
             const uint32_t m0 = m ^ (w & 0xffffu);
@@ -565,11 +583,11 @@ __device__ CubeInfo build_cube(SR& S, int cell, float3 c, float R, int n, LaneCu
 // conductors holding part of the open cube, in candidate-list (index) order.
 // False when more than EXP_MAX_COND conductors do.
 template <class SR>
-__device__ bool build_conductors(SR& S, int cell, float3 c, float R, int n, LaneExp E) {
+__device__ __forceinline__ bool build_conductors(SR& S, int cell, float3 c, float R, int n, LaneExp E) {
     const float h = 2.f * R / (float)n;
     const float o[3] = {c.x - R, c.y - R, c.z - R};
     const int np = n + 1;
-    uint32_t* m32 = reinterpret_cast<uint32_t*>(E.nmask);
+    LAS uint32_t* m32 = reinterpret_cast<LAS uint32_t*>(E.nmask);
     for (int q = 0; q < (3 * np + 3) / 4; ++q) m32[q] = 0u;
     // toggles (bit flips where a run of nodes starts or ends), then prefix xor
 #pragma unroll
@@ -577,14 +595,14 @@ __device__ bool build_conductors(SR& S, int cell, float3 c, float R, int n, Lane
         if (S.bc[2 * a] == MW_BC_DIRICHLET && o[a] <= S.wlo[a]) {
             const float u = (S.wlo[a] - o[a]) / h;  // nodes i <= u are at/beyond the face
             const int iw = min((int)floorf(u), n);
-            E.nmask[a * np] ^= 0x80u;
-            if (iw + 1 <= n) E.nmask[a * np + iw + 1] ^= 0x80u;
+            toggle8(E.nmask, a * np, 0x80u);
+            if (iw + 1 <= n) toggle8(E.nmask, a * np + iw + 1, 0x80u);
             E.theta[(7 * 3 + a) * 2 + 1] = theta_q((float)(iw + 1) - u);
         }
         if (S.bc[2 * a + 1] == MW_BC_DIRICHLET && o[a] + 2.f * R >= S.whi[a]) {
             const float u = (S.whi[a] - o[a]) / h;  // nodes i >= u
             const int iw = max((int)ceilf(u), 0);
-            if (iw <= n) E.nmask[a * np + iw] ^= 0x80u;
+            if (iw <= n) toggle8(E.nmask, a * np + iw, 0x80u);
             E.theta[(7 * 3 + a) * 2 + 0] = theta_q(u - (float)(iw - 1));
         }
     }
@@ -609,8 +627,8 @@ __device__ bool build_conductors(SR& S, int cell, float3 c, float R, int n, Lane
             const float u0 = (bl[a] - o[a]) / h, u1 = (bh[a] - o[a]) / h;
             const int i0 = max((int)ceilf(u0), 0), i1 = min((int)floorf(u1), n);
             if (i0 <= i1) {
-                E.nmask[a * np + i0] ^= bit;
-                if (i1 + 1 <= n) E.nmask[a * np + i1 + 1] ^= bit;
+                toggle8(E.nmask, a * np + i0, bit);
+                if (i1 + 1 <= n) toggle8(E.nmask, a * np + i1 + 1, bit);
             }
             E.theta[(nb * 3 + a) * 2 + 0] = theta_q(u0 - (float)(i0 - 1));
             E.theta[(nb * 3 + a) * 2 + 1] = theta_q((float)(i1 + 1) - u1);
@@ -728,7 +746,7 @@ __device__ __forceinline__ uint32_t plane_code(LaneCube L, const CubeInfo& I, in
 // background codes) along the two in-plane axes; planes whose own mask and
 // background equal the previous plane's repeat it.  When a is not z, the
 // second in-plane axis v is z.
-__device__ void plane_mean_codes(LaneCube L, int n, int a, uint32_t* out) {
+__device__ void plane_mean_codes(LaneCube L, int n, int a, LAS uint32_t* out) {
     const int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
     const unsigned long long area = (unsigned long long)n * n;
     // runs of equal masks along u, and of equal masks and background codes
@@ -812,8 +830,8 @@ __device__ uint32_t key_hash(uint32_t words, KeyF key) {
 // *ghi receive the guide pair of word u's bucket in the table (loaded with the
 // key comparison).
 template <class KeyF>
-__device__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t hash, uint32_t* out_index, uint32_t u = 0,
-                                uint32_t* glo = nullptr, uint32_t* ghi = nullptr) {
+__device__ __forceinline__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t hash, uint32_t* out_index,
+                                               uint32_t u = 0, uint32_t* glo = nullptr, uint32_t* ghi = nullptr) {
     const uint32_t words = C.key_words;
     uint32_t h = hash;
     if (h == 0u) h = 1u;
@@ -939,7 +957,7 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
     const int n = A.n;
     uint32_t* my = lds + threadIdx.x * A.lane_stride;
     const LaneCube L = lane_cube(my, n);
-    uint32_t* kbuf = L.bz + n;
+    LAS uint32_t* kbuf = L.bz + n;
     unsigned long long c_br[4] = {0, 0, 0, 0};
     uint32_t err = 0, missing = 0;
     // one structure per launch: its layer table goes to LDS once
@@ -1145,7 +1163,7 @@ __device__ __forceinline__ bool mw_block16(MwState& M, LaneCube L, int n, const 
             const int cc = min(max(cnew, 1), n - 1);
             // rows cc - 1 and cc of the move's axis (row0 points at row -1 of
             // x; n is even, so the three axes start n u16 apart)
-            const uint16_t* rr = (t4 ? L.mask + 2 * n : (t2 ? L.mask + n : L.mask)) - 1 + cc;
+            const LAS uint16_t* rr = (t4 ? L.mask + 2 * n : (t2 ? L.mask + n : L.mask)) - 1 + cc;
             const uint32_t lo = rr[0], hi = rr[1];
             const uint32_t bgz = 1u << (15 - cc);  // background bit of z row cc
             const uint32_t plo = t4 ? (lo << 16) | (bgz << 1) : prep_xy(lo);
