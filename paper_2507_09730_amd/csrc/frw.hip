@@ -535,22 +535,37 @@ __device__ __forceinline__ CubeInfo build_cube(SR& S, int cell, float3 c, float 
     // toggles -> masks (prefix xor along each axis); aggregate masks:
     // present boxes and boxes spanning all cells per axis
     uint32_t O[3];
+    // two cells per dword (n is even, so every axis starts on a dword)
+    auto prefix = [&](int a, int i, uint32_t w, uint32_t& m, uint32_t& A, uint32_t& Oa) {
+        const uint32_t m0 = m ^ (w & 0xffffu);
+        const uint32_t m1 = m0 ^ (w >> 16);
+        mask32[a * (n / 2) + i] = m0 | (m1 << 16);
+        A &= m0 & m1;
+        Oa |= m0 | m1;
+        m = m1;
+    };
+    if (n == 16) {
+        // all 24 dwords are read before any is written back: one LDS round
+        // trip instead of one per dword
+        uint32_t w[24];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        // two cells per dword (n is even, so every axis starts on a dword)
-        uint32_t A = 0xffffu, Oa = 0, m = 0;
-        LAS uint32_t* w32 = mask32 + a * (n / 2);
-        for (int i = 0; i < n / 2; ++i) {
-            const uint32_t w = w32[i];
-            const uint32_t m0 = m ^ (w & 0xffffu);
-            const uint32_t m1 = m0 ^ (w >> 16);
-            w32[i] = m0 | (m1 << 16);
-            A &= m0 & m1;
-            Oa |= m0 | m1;
-            m = m1;
+        for (int q = 0; q < 24; ++q) w[q] = mask32[q];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            uint32_t A = 0xffffu, Oa = 0, m = 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) prefix(a, i, w[a * 8 + i], m, A, Oa);
+            info.A[a] = A;
+            O[a] = Oa;
         }
-        info.A[a] = A;
-        O[a] = Oa;
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            uint32_t A = 0xffffu, Oa = 0, m = 0;
+            for (int i = 0; i < n / 2; ++i) prefix(a, i, mask32[a * (n / 2) + i], m, A, Oa);
+            info.A[a] = A;
+            O[a] = Oa;
+        }
     }
     info.present = O[0] & O[1] & O[2];
     // layers span every x and y cell; they span every z cell only when a
@@ -641,8 +656,7 @@ __device__ __forceinline__ bool build_conductors(SR& S, int cell, float3 c, floa
     // other without padding: the running value restarts at nodes np and 2 np)
     int idx = 0;
     uint32_t m = 0;
-    for (int w = 0; w < (3 * np + 3) / 4; ++w) {
-        const uint32_t v = m32[w];
+    auto prefix = [&](int w, uint32_t v) {
         uint32_t out = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j, ++idx) {
@@ -651,6 +665,16 @@ __device__ __forceinline__ bool build_conductors(SR& S, int cell, float3 c, floa
             out |= m << (8 * j);
         }
         m32[w] = out;
+    };
+    if (n == 16) {
+        // all 13 dwords are read before any is written back
+        uint32_t v[13];
+#pragma unroll
+        for (int w = 0; w < 13; ++w) v[w] = m32[w];
+#pragma unroll
+        for (int w = 0; w < 13; ++w) prefix(w, v[w]);
+    } else {
+        for (int w = 0; w < (3 * np + 3) / 4; ++w) prefix(w, m32[w]);
     }
     return true;
 }
@@ -788,7 +812,15 @@ __device__ void plane_mean_codes(LaneCube L, int n, int a, LAS uint32_t* out) {
             }
             sum += (unsigned long long)li * row;
         }
-        unsigned long long qt = sum / area, rem = sum % area;
+        unsigned long long qt, rem;
+        if ((n & (n - 1)) == 0) {
+            // the area n^2 is a power of two
+            qt = sum >> (2 * __builtin_ctz((unsigned)n));
+            rem = sum & (area - 1ull);
+        } else {
+            qt = sum / area;
+            rem = sum % area;
+        }
         if (2 * rem > area || (2 * rem == area && (qt & 1))) ++qt;
         prev_ma = ma;
         prev_b = bp;
@@ -1269,9 +1301,14 @@ __device__ __forceinline__ void mw_begin_e(const MwState& M, MwStateE& Q, LaneEx
     Q.zp = E.nmask[2 * np + M.nk + 1];
 }
 
-// Code of a link cut at fraction tq / 65535 of its length: rint(g / theta).
+// Code of a link cut at fraction tq / 65535 of its length: rint(g / theta),
+// that is floor((65535 g + tq / 2) / tq).  The numerator is below 2^48 and
+// tq >= 4096, so a quotient that is not an integer lies at least 1 / tq from
+// one, more than half an ulp of its double value: the floor of the double
+// division is the integer quotient (without a 64-bit integer division).
 __device__ __forceinline__ uint32_t cut_link(uint32_t g, uint32_t tq) {
-    return (uint32_t)(((uint64_t)g * 65535u + (tq >> 1)) / tq);
+    const double x = (double)((uint64_t)g * 65535u + (tq >> 1));
+    return (uint32_t)floor(x / (double)tq);
 }
 
 // Up to four MicroWalk-E steps (one Philox block).  Returns 0 while the walk
