@@ -1,9 +1,14 @@
 """GPU FRW extraction (Alg. 1 with the hybrid strategy of Sec. III-C) through
 the C ABI, against closed forms, Maxwell-matrix properties and the CPU oracle.
 
-Capacitances are Monte Carlo estimates: agreement is stated in combined
-standard errors (3 sigma), never bit for bit.  Per-walk scores are integer-
-and seed-determined, so repeated or resumed runs must reproduce them exactly.
+Capacitances are Monte Carlo estimates: rows are compared in combined
+standard errors (3 sigma).  Walks are compared one by one as well: GPU and
+oracle draw every random word from the same Philox streams (walk, hop, step,
+purpose), so a walk follows the same path on both until an fp32 decision of
+the GPU differs from the oracle's fp64 one (a point within rounding of a box
+face or a lattice boundary); nearly every walk must end on the same net with
+the same weight to fp32 rounding.  Per-walk scores are integer- and
+seed-determined, so repeated or resumed runs must reproduce them exactly.
 """
 import os
 
@@ -75,6 +80,51 @@ def test_c2_matches_oracle(c2_gpu, oracle_lib):
     zs = [_z(r_gpu["row"][j], r_or["row"][j], r_gpu["se"][j], r_or["se"][j]) for j in range(5)]
     print("z", zs)
     assert max(zs) < 3.0
+
+
+# walks whose weights agree to this relative error count as equal (the GPU
+# weight is fp32: one walk's weight is a product and quotient of a few fp32
+# terms, a few ulp of 6e-8 apart from the fp64 value)
+W_REL = 1e-5
+
+
+def _walk_agreement(g, o_net, o_w):
+    g_net = g["net"].cpu().numpy() if hasattr(g["net"], "cpu") else np.asarray(g["net"])
+    g_w = (g["w"].cpu().numpy() if hasattr(g["w"], "cpu") else np.asarray(g["w"])).astype(np.float64)
+    same = g_net == o_net
+    rel = np.abs(g_w - o_w) / np.maximum(np.abs(o_w), 1e-30)
+    return float(same.mean()), float((same & (rel <= W_REL)).mean())
+
+
+@pytest.mark.parametrize("name,expand,floor", [("plates", 0, 0.999), ("c2", 0, 0.999), ("c4", 0, 0.995),
+                                               ("c2", 5, 0.99)])
+def test_walks_match_oracle_one_by_one(mw, oracle_lib, name, expand, floor):
+    st = {"plates": W.parallel_plates, "c2": W.c2_structure, "c4": W.c4_structure}[name]()
+    m = st.meta["master"] if name == "c4" else 0
+    N = 20000
+    g = mw.frw_extract(st, m, N, seed=77, scores=True, expand=expand)
+    o = oracle_lib.frw_extract(st, m, N, seed=77, threads=_threads(), scores=True,
+                               expand=float(expand) if expand else 1.0)
+    same_net, same_walk = _walk_agreement(g, o["net"], o["w"])
+    print(name, expand, "same net", same_net, "same net and weight", same_walk)
+    assert same_walk >= floor
+
+
+def test_c2_full_size_sampled_walks_match_oracle(c2_gpu, oracle_lib):
+    """The bench configuration (1e6 walks, 16^3-cell cubes, hybrid): eight
+    runs of 250 walks spread over the extraction, recomputed by the oracle
+    from their walk indices, equal the GPU's walks one by one."""
+    st = W.c2_structure()
+    g = c2_gpu[0]
+    n_walks = len(g["net"])
+    assert n_walks == 1000000
+    agree = []
+    for f in np.linspace(0, n_walks - 250, 8).astype(np.int64):
+        o = oracle_lib.frw_extract(st, 0, 250, seed=20, first_walk=int(f), threads=_threads(), scores=True)
+        part = {"net": g["net"][f:f + 250], "w": g["w"][f:f + 250]}
+        agree.append(_walk_agreement(part, o["net"], o["w"])[1])
+    print("per-run agreement", agree)
+    assert min(agree) >= 0.99 and np.mean(agree) >= 0.999
 
 
 def test_c2_reciprocity_and_signs(c2_gpu):
