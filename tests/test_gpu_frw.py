@@ -96,17 +96,21 @@ def _walk_agreement(g, o_net, o_w):
     return float(same.mean()), float((same & (rel <= W_REL)).mean())
 
 
-@pytest.mark.parametrize("name,expand,floor", [("plates", 0, 0.999), ("c2", 0, 0.999), ("c4", 0, 0.995),
-                                               ("c2", 5, 0.99)])
-def test_walks_match_oracle_one_by_one(mw, oracle_lib, name, expand, floor):
-    st = {"plates": W.parallel_plates, "c2": W.c2_structure, "c4": W.c4_structure}[name]()
+@pytest.mark.parametrize("name,expand,n_cells,floor", [
+    ("plates", 0, 16, 0.999), ("stack", 0, 16, 0.999), ("c2", 0, 16, 0.999), ("c4", 0, 16, 0.995),
+    ("c2", 5, 16, 0.99), ("c2", 0, 8, 0.999), ("c2", 0, 12, 0.999), ("c2", 0, 24, 0.999), ("c2", 0, 32, 0.999)])
+def test_walks_match_oracle_one_by_one(mw, oracle_lib, name, expand, n_cells, floor):
+    """Cube sizes above 16 cells run the walker's general MicroWalk step, the
+    twelve-layer stack its background-layer walk over global memory."""
+    st = {"plates": W.parallel_plates, "stack": lambda: W.parallel_plates("stack"), "c2": W.c2_structure,
+          "c4": W.c4_structure}[name]()
     m = st.meta["master"] if name == "c4" else 0
-    N = 20000
-    g = mw.frw_extract(st, m, N, seed=77, scores=True, expand=expand)
-    o = oracle_lib.frw_extract(st, m, N, seed=77, threads=_threads(), scores=True,
+    N = 20000 if n_cells <= 16 else 5000
+    g = mw.frw_extract(st, m, N, seed=77, scores=True, expand=expand, n_cells=n_cells)
+    o = oracle_lib.frw_extract(st, m, N, seed=77, threads=_threads(), scores=True, n_cells=n_cells,
                                expand=float(expand) if expand else 1.0)
     same_net, same_walk = _walk_agreement(g, o["net"], o["w"])
-    print(name, expand, "same net", same_net, "same net and weight", same_walk)
+    print(name, expand, n_cells, "same net", same_net, "same net and weight", same_walk)
     assert same_walk >= floor
 
 

@@ -142,6 +142,10 @@ def parallel_plates(variant="uniform"):
         diel, deps = [[0.5, 0, 0, 1, 0.5, 1], [0, 0.5, 0, 0.5, 1, 1]], [7.0, 7.0]
     elif variant == "series":
         z0, le = [0.0, 0.5], [3.9, 2.7]
+    elif variant == "stack":
+        # twelve layers: the gap cut into twelve slabs of 0.8/12 um
+        z0 = [0.0] + [0.1 + q * 0.8 / 12 for q in range(1, 12)]
+        le = [STACK_EPS[q % 4] for q in range(12)]
     elif variant != "uniform":
         raise ValueError(variant)
     return make_structure(cond, [0, 1], diel, deps, z0, le, [0, 0, 0], [1, 1, 1], (NEUMANN,) * 6,
@@ -149,6 +153,7 @@ def parallel_plates(variant="uniform"):
 
 
 EPS0 = 8.8541878128e-3  # fF/um
+STACK_EPS = (3.9, 2.7, 7.0, 2.2)
 
 
 def parallel_plates_exact(variant="uniform"):
@@ -160,6 +165,8 @@ def parallel_plates_exact(variant="uniform"):
         return EPS0 * (0.5 * 3.9 + 0.5 * 7.0) * A / d
     if variant == "series":
         return EPS0 * A / (0.4 / 3.9 + 0.4 / 2.7)
+    if variant == "stack":
+        return EPS0 * A / sum((d / 12) / STACK_EPS[q % 4] for q in range(12))
     raise ValueError(variant)
 
 
