@@ -1636,12 +1636,36 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             hsh = key_hash_step(hsh, (uint32_t)sax);
                             hsh = key_hash_step(hsh, 0u);
                             const uint32_t b0 = L.bz[0];
+                            if (n == 16) {
+                                // eight planes at a time: their mask words,
+                                // background codes and box codes each in one
+                                // LDS round trip
+                                const LAS uint32_t* row = reinterpret_cast<const LAS uint32_t*>(L.mask) + sax * 8;
+#pragma unroll
+                                for (int p0 = 0; p0 < 16; p0 += 8) {
+                                    uint32_t mw[4], bq[8], pc[8];
+#pragma unroll
+                                    for (int j = 0; j < 4; ++j) mw[j] = row[p0 / 2 + j];
+#pragma unroll
+                                    for (int j = 0; j < 8; ++j) bq[j] = sax == 2 ? L.bz[p0 + j] : b0;
+#pragma unroll
+                                    for (int j = 0; j < 8; ++j)
+                                        pc[j] = cell_code(
+                                            L, ((j & 1) ? mw[j / 2] >> 16 : mw[j / 2] & 0xffffu) & I.present, bq[j]);
+#pragma unroll
+                                    for (int j = 0; j < 8; ++j) {
+                                        L.bz[p0 + j] = pc[j];
+                                        hsh = key_hash_step(hsh, pc[j]);
+                                    }
+                                }
+                            } else {
 #pragma unroll 4
-                            for (int p = 0; p < n; ++p) {
-                                const uint32_t pc =
-                                    cell_code(L, L.mask[sax * n + p] & I.present, sax == 2 ? L.bz[p] : b0);
-                                L.bz[p] = pc;
-                                hsh = key_hash_step(hsh, pc);
+                                for (int p = 0; p < n; ++p) {
+                                    const uint32_t pc =
+                                        cell_code(L, L.mask[sax * n + p] & I.present, sax == 2 ? L.bz[p] : b0);
+                                    L.bz[p] = pc;
+                                    hsh = key_hash_step(hsh, pc);
+                                }
                             }
                             static_assert(KEY_HDR == 4, "hop-table key header is four words");
                             res = lookup_or_insert(
