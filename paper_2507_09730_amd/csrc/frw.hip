@@ -1427,6 +1427,116 @@ __device__ __forceinline__ int mw_block_e(MwState& M, MwStateE& Q, LaneCube L, L
     return st;
 }
 
+// mw_block_e for n <= 16: the same steps, moves and absorptions, with the
+// cell codes of cell_code16 and the move decoded from the comparisons as in
+// mw_block16 (no branch on the axis).
+__device__ __forceinline__ int mw_block_e16(MwState& M, MwStateE& Q, LaneCube L, LaneExp E, int n, const Rand4& r,
+                                            int env_net, int* net) {
+    const uint32_t us[4] = {r.x, r.y, r.z, r.w};
+    const int np = n + 1;
+    int st = 0;
+    uint32_t co = (uint32_t)M.ni | ((uint32_t)M.nj << 8) | ((uint32_t)M.nk << 16);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (st == 0) {
+            const uint32_t c000 = cell_code16(L, M.px0 & M.py0 & M.pz0), c001 = cell_code16(L, M.px1 & M.py0 & M.pz0);
+            const uint32_t c010 = cell_code16(L, M.px0 & M.py1 & M.pz0), c011 = cell_code16(L, M.px1 & M.py1 & M.pz0);
+            const uint32_t c100 = cell_code16(L, M.px0 & M.py0 & M.pz1), c101 = cell_code16(L, M.px1 & M.py0 & M.pz1);
+            const uint32_t c110 = cell_code16(L, M.px0 & M.py1 & M.pz1), c111 = cell_code16(L, M.px1 & M.py1 & M.pz1);
+            const uint32_t a0 = c000 + c100, a1 = c010 + c110;
+            const uint32_t b0 = c001 + c101, b1 = c011 + c111;
+            // links -x, +x, -y, +y, -z, +z
+            uint32_t g[6] = {a0 + a1, b0 + b1, a0 + b0, a1 + b1, c000 + c001 + c010 + c011,
+                             c100 + c101 + c110 + c111};
+            // a link is cut only if its far node is absorbing: some
+            // neighbour lies beyond a grounded face (the node itself does
+            // not), or one conductor holds a coordinate of every axis
+            const uint32_t near = (((Q.xm | Q.xc | Q.xp) & (Q.ym | Q.yc | Q.yp) & (Q.zm | Q.zc | Q.zp)) & 0x7fu) |
+                                  ((Q.xm | Q.xp | Q.ym | Q.yp | Q.zm | Q.zp) & 0x80u);
+            if (near) {
+                const uint32_t nx[6] = {Q.xm, Q.xp, Q.xc, Q.xc, Q.xc, Q.xc};
+                const uint32_t ny[6] = {Q.yc, Q.yc, Q.ym, Q.yp, Q.yc, Q.yc};
+                const uint32_t nz[6] = {Q.zc, Q.zc, Q.zc, Q.zc, Q.zm, Q.zp};
+#pragma unroll
+                for (int dd = 0; dd < 6; ++dd) {
+                    const uint32_t env = (nx[dd] | ny[dd] | nz[dd]) & 0x80u;
+                    const uint32_t cm = nx[dd] & ny[dd] & nz[dd] & 0x7fu;
+                    if (env | cm) {
+                        const int b = env ? 7 : __ffs(cm) - 1;
+                        g[dd] = cut_link(g[dd], E.theta[(b * 3 + (dd >> 1)) * 2 + ((dd & 1) ? 0 : 1)]);
+                    }
+                }
+            }
+            const uint32_t S0 = g[0], S1 = S0 + g[1], S2 = S1 + g[2], S3 = S2 + g[3], S4 = S3 + g[4];
+            const uint32_t S5 = S4 + g[5];
+            const uint32_t xq = __umulhi(us[q], S5);
+            // the move #{k : xq >= S_k}: x while xq < S1 (up when xq >= S0),
+            // y while xq < S3 (up when xq >= S2), z otherwise (up when xq >= S4)
+            const bool t2 = xq >= S1, t4 = xq >= S3;
+            const bool ux = xq >= S0, uy = xq >= S2, uz = xq >= S4;
+            const bool up = (t4 & uz) | (t2 & !t4 & uy) | (!t2 & ux);
+            const uint32_t sh = t4 ? 16u : (t2 ? 8u : 0u);
+            ++M.s;
+            co += (up ? 1u : 0xffffffffu) << sh;
+            const int cnew = (int)((co >> sh) & 0xffu);
+            const bool xm = !t2, ym = t2 && !t4;
+            // node masks along the move's axis shift by one; the new far one
+            // is read (index clamped as in mw_block_e)
+            const LAS uint8_t* nrow = E.nmask + (t4 ? 2 * np : (t2 ? np : 0));
+            const uint32_t ne = nrow[up ? min(cnew + 1, n) : max(cnew - 1, 0)];
+            {
+                const uint32_t m0 = Q.xm, c0 = Q.xc, p0 = Q.xp;
+                Q.xm = xm ? (up ? c0 : ne) : m0;
+                Q.xc = xm ? (up ? p0 : m0) : c0;
+                Q.xp = xm ? (up ? ne : c0) : p0;
+            }
+            {
+                const uint32_t m0 = Q.ym, c0 = Q.yc, p0 = Q.yp;
+                Q.ym = ym ? (up ? c0 : ne) : m0;
+                Q.yc = ym ? (up ? p0 : m0) : c0;
+                Q.yp = ym ? (up ? ne : c0) : p0;
+            }
+            {
+                const uint32_t m0 = Q.zm, c0 = Q.zc, p0 = Q.zp;
+                Q.zm = t4 ? (up ? c0 : ne) : m0;
+                Q.zc = t4 ? (up ? p0 : m0) : c0;
+                Q.zp = t4 ? (up ? ne : c0) : p0;
+            }
+            if (cnew == 0 || cnew == n) {
+                st = 1;
+            } else {
+                const uint32_t env = (Q.xc | Q.yc | Q.zc) & 0x80u;
+                const uint32_t cm = Q.xc & Q.yc & Q.zc & 0x7fu;
+                if (env) {
+                    st = 2;
+                    *net = env_net;
+                } else if (cm) {
+                    st = 2;
+                    *net = E.cnet[__ffs(cm) - 1];
+                }
+            }
+            // prepared masks of the two cell rows around the new node along
+            // the move's axis (a walk that stopped is not stepped again)
+            const int cc = min(max(cnew, 1), n - 1);
+            const LAS uint16_t* rr = (t4 ? L.mask + 2 * n : (t2 ? L.mask + n : L.mask)) - 1 + cc;
+            const uint32_t lo = rr[0], hi = rr[1];
+            const uint32_t bgz = 1u << (15 - cc);
+            const uint32_t plo = t4 ? (lo << 16) | (bgz << 1) : prep_xy(lo);
+            const uint32_t phi = t4 ? (hi << 16) | bgz : prep_xy(hi);
+            M.px0 = xm ? plo : M.px0;
+            M.px1 = xm ? phi : M.px1;
+            M.py0 = ym ? plo : M.py0;
+            M.py1 = ym ? phi : M.py1;
+            M.pz0 = t4 ? plo : M.pz0;
+            M.pz1 = t4 ? phi : M.pz1;
+        }
+    }
+    M.ni = (int)(co & 0xffu);
+    M.nj = (int)((co >> 8) & 0xffu);
+    M.nk = (int)((co >> 16) & 0xffu);
+    return st;
+}
+
 // -------------------------------------------------------------------------
 // Walker kernel: transitions after the first, until absorption.  A lane
 // holds one walk; lanes whose next cube is not stratified run MicroWalk in
@@ -1718,7 +1828,10 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             if (!ok) err |= ERR_REGIONS;
                             mR = Re;
                             env_net = S.n_nets;
-                            mw_begin(M, L, n);
+                            if (N16)
+                                mw_begin16(M, L, n);
+                            else
+                                mw_begin(M, L, n);
                             mw_begin_e(M, Q, E, n);
                         } else if (N16) {
                             mw_begin16(M, L, n);
@@ -1765,7 +1878,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                 int stt;
                 if (EXP) {
                     const Rand4 r = philox10(M.s >> 2, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), wk0, wk1);
-                    stt = mw_block_e(M, Q, L, E, n, r, env_net, &anet);
+                    stt = N16 ? mw_block_e16(M, Q, L, E, n, r, env_net, &anet)
+                              : mw_block_e(M, Q, L, E, n, r, env_net, &anet);
                 } else {
                     // two Philox blocks per pass (eight steps); the second
                     // block's counter is the one it would have after four
@@ -2757,6 +2871,8 @@ struct Runner {
         set_lds(frw_walk_kernel<true, false, true>, g.lds);
         set_lds(frw_walk_kernel<false, true>, g.lds_e);
         set_lds(frw_walk_kernel<true, true>, g.lds_e);
+        set_lds(frw_walk_kernel<false, true, true>, g.lds_e);
+        set_lds(frw_walk_kernel<true, true, true>, g.lds_e);
         set_lds(first_kernel<false>, g.first_lds);
         set_lds(first_kernel<true>, g.first_lds);
     }
@@ -2903,8 +3019,12 @@ struct Runner {
             if (expand_m > 0) {
                 W.lane_stride = g.lane_stride_e;
                 W.expand_m = expand_m;
-                if (multi)
+                if (multi && n <= 16)
+                    frw_walk_kernel<true, true, true><<<g.blocks_e, WALK_THREADS, g.lds_e>>>(W);
+                else if (multi)
                     frw_walk_kernel<true, true><<<g.blocks_e, WALK_THREADS, g.lds_e>>>(W);
+                else if (n <= 16)
+                    frw_walk_kernel<false, true, true><<<g.blocks_e, WALK_THREADS, g.lds_e>>>(W);
                 else
                     frw_walk_kernel<false, true><<<g.blocks_e, WALK_THREADS, g.lds_e>>>(W);
             } else if (multi) {
