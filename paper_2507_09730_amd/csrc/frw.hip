@@ -1448,11 +1448,11 @@ __device__ __forceinline__ int mw_block_e16(MwState& M, MwStateE& Q, LaneCube L,
             // links -x, +x, -y, +y, -z, +z
             uint32_t g[6] = {a0 + a1, b0 + b1, a0 + b0, a1 + b1, c000 + c001 + c010 + c011,
                              c100 + c101 + c110 + c111};
-            // a link is cut only if its far node is absorbing: some
-            // neighbour lies beyond a grounded face (the node itself does
-            // not), or one conductor holds a coordinate of every axis
+            // a link is cut only if its far node is absorbing: one of the
+            // coordinates around the node lies beyond a grounded face, or
+            // one conductor holds a coordinate of every axis
             const uint32_t near = (((Q.xm | Q.xc | Q.xp) & (Q.ym | Q.yc | Q.yp) & (Q.zm | Q.zc | Q.zp)) & 0x7fu) |
-                                  ((Q.xm | Q.xp | Q.ym | Q.yp | Q.zm | Q.zp) & 0x80u);
+                                  ((Q.xm | Q.xc | Q.xp | Q.ym | Q.yc | Q.yp | Q.zm | Q.zc | Q.zp) & 0x80u);
             if (near) {
                 const uint32_t nx[6] = {Q.xm, Q.xp, Q.xc, Q.xc, Q.xc, Q.xc};
                 const uint32_t ny[6] = {Q.yc, Q.yc, Q.ym, Q.yp, Q.yc, Q.yc};
