@@ -111,23 +111,24 @@ def batched_vs_plain(mw, W, reps=5):
             "batched_alu_frac": steps * MW_STEP_SLOTS / t_batch / PEAK_LANE_OPS}
 
 
-def microwalk_e(mw, W, st, walks, n_cells, steps=5):
-    """The headline workload with MicroWalk-E transitions (expanded cubes of
-    4x the conductor-free size at n = 16, expansion option 5) beside the
-    plain MicroWalk figure: time per extraction, hops and micro-steps per
-    walk, and the row's shift against plain MicroWalk in combined SEs."""
+def microwalk_e(mw, W, st, walks, n_cells, steps=5, master=0):
+    """A workload with MicroWalk-E transitions (expanded cubes of 4x the
+    conductor-free size at n = 16, expansion option 5) beside the plain
+    MicroWalk figure: time per extraction, hops and micro-steps per walk, and
+    the master's self term shift against plain MicroWalk in combined SEs."""
     h = mw.StructureHandle(st)
     out = {}
     rows = {}
     for ex in (0, 5):
-        mw.frw_extract(h, 0, walks, seed=900, n_cells=n_cells, expand=ex)
+        mw.frw_extract(h, master, walks, seed=900, n_cells=n_cells, expand=ex)
         t0 = time.perf_counter()
         acc = []
         for k in range(steps):
-            acc.append(mw.frw_extract(h, 0, walks, seed=500 + k, n_cells=n_cells, expand=ex))
+            acc.append(mw.frw_extract(h, master, walks, seed=500 + k, n_cells=n_cells, expand=ex))
         dt = (time.perf_counter() - t0) / steps
         s = acc[-1]["stats"]
-        rows[ex] = (np.mean([a["row"][0] for a in acc]), np.sqrt(np.mean([a["se"][0] ** 2 for a in acc]) / steps))
+        rows[ex] = (np.mean([a["row"][master] for a in acc]),
+                    np.sqrt(np.mean([a["se"][master] ** 2 for a in acc]) / steps))
         out["expand_%d" % ex] = {"ms_per_extraction": dt * 1e3, "walks_per_s": walks / dt,
                                  "hops_per_walk": s["hops"] / s["walks"],
                                  "micro_steps_per_walk": s["micro_steps"] / s["walks"],
@@ -301,6 +302,8 @@ def main():
         out["batched"] = batched_vs_plain(mw, W)
         out["fig3a"] = fig3a(mw, W)
         out["microwalk_e"] = microwalk_e(mw, W, st, args.walks, args.n_cells)
+        c4 = W.c4_structure()
+        out["microwalk_e_c4"] = microwalk_e(mw, W, c4, args.walks, args.n_cells, master=c4.meta["master"])
         if args.serving_requests > 0:
             out["serving"] = serving(mw, W, args.serving_requests)
     if not args.no_cpu_baseline:
