@@ -838,10 +838,13 @@ constexpr unsigned long long SLOT_HASH_MASK = 0xffffffff00000000ull;
 // Finds the table of a key (words produced by key(q), q < key_words) or
 // queues it for building.  Slot words pack a 32-bit key hash with the table
 // index; the full key is compared before a hit is reported.
-// Table layout: [last positive index, Kh bits, guide[257], CDF[nb],
-// sign bits[ceil(nb/32)]].  guide[g] = first b with CDF[b] > g * 2^24, so the
-// answer for a word u lies in [guide[u>>24], guide[(u>>24)+1]].
-constexpr uint32_t TAB_GUIDE = 2, TAB_CDF = 2 + 257;
+// Table layout: [last positive index, Kh bits, guide[2^GUIDE_BITS + 1],
+// CDF[nb], sign bits[ceil(nb/32)]].  guide[g] = first b with CDF[b] >
+// g * 2^GUIDE_SHIFT, so the answer for a word u lies in [guide[u >>
+// GUIDE_SHIFT], guide[(u >> GUIDE_SHIFT) + 1]].  With 2048 buckets for the
+// 6 (n-1)^2 entries of a 16-cell cube most buckets hold at most one entry.
+constexpr uint32_t GUIDE_BITS = 11, GUIDE_SHIFT = 32 - GUIDE_BITS;
+constexpr uint32_t TAB_GUIDE = 2, TAB_CDF = 2 + (1u << GUIDE_BITS) + 1;
 
 __device__ __forceinline__ uint32_t key_hash_step(uint32_t h, uint32_t w) {
     h ^= w;
@@ -895,7 +898,7 @@ __device__ __forceinline__ int lookup_or_insert(const CacheDev& C, KeyF key, uin
             if (glo) {
                 // the table's guide pair, read with the key (unused unless
                 // the table is ready)
-                const GAS uint32_t* tab = gp(C.data) + (size_t)idx * C.tab_words + TAB_GUIDE + (u >> 24);
+                const GAS uint32_t* tab = gp(C.data) + (size_t)idx * C.tab_words + TAB_GUIDE + (u >> GUIDE_SHIFT);
                 g0 = tab[0];
                 g1 = tab[1];
             }
@@ -927,15 +930,15 @@ __device__ __forceinline__ int lookup_or_insert(const CacheDev& C, KeyF key, uin
 }
 
 
-// Sample for word u given the guide pair of its bucket (g = u >> 24):
+// Sample for word u given the guide pair of its bucket (g = u >> GUIDE_SHIFT):
 // glo = guide[g], ghi = guide[g + 1].  The first b with cdf[b] > u lies in
-// [glo, ghi + 1) and is found by bisection (few loads per lane: the lanes'
-// addresses are scattered, so each load costs a cache access per lane).
+// [glo, ghi] (ghi itself when no b below it qualifies), so bisection over
+// [glo, ghi) finds it, with no load at all when the bucket holds no entry
+// boundary (glo = ghi).  nb: the answer when no entry qualifies.
 __device__ __forceinline__ int table_sample_guided(const GAS uint32_t* tab, uint32_t nb, uint32_t u, uint32_t glo,
                                                    uint32_t ghi) {
     const GAS uint32_t* cdf = tab + TAB_CDF;
     uint32_t lo = glo, hi = ghi;
-    if (hi < nb) ++hi;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
         if (cdf[mid] > u)
@@ -947,7 +950,7 @@ __device__ __forceinline__ int table_sample_guided(const GAS uint32_t* tab, uint
 }
 
 __device__ __forceinline__ int table_sample(const GAS uint32_t* tab, uint32_t nb, uint32_t u) {
-    const uint32_t g = u >> 24;
+    const uint32_t g = u >> GUIDE_SHIFT;
     return table_sample_guided(tab, nb, u, tab[TAB_GUIDE + g], tab[TAB_GUIDE + g + 1]);
 }
 
@@ -1795,8 +1798,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             const GAS uint32_t* tab = gp(A.cache.data) + (size_t)idx * A.cache.tab_words;
                             if (I.cls == 0) {
                                 // the uniform table's guide pair (read with the key otherwise)
-                                glo = tab[TAB_GUIDE + (r.x >> 24)];
-                                ghi = tab[TAB_GUIDE + (r.x >> 24) + 1];
+                                glo = tab[TAB_GUIDE + (r.x >> GUIDE_SHIFT)];
+                                ghi = tab[TAB_GUIDE + (r.x >> GUIDE_SHIFT) + 1];
                             }
                             const int b = table_sample_guided(tab, A.cache.nb, r.x, glo, ghi);
                             int nd[3];
@@ -2185,9 +2188,9 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
         tab[1] = kind == 1 ? __float_as_uint((float)total_sh) : 0u;
     }
     __syncthreads();
-    // guide[g] = first b with CDF[b] > g * 2^24 (CDF nondecreasing)
-    for (int g = threadIdx.x; g <= 256; g += TB_THREADS) {
-        const unsigned long long thr = (unsigned long long)g << 24;
+    // guide[g] = first b with CDF[b] > g * 2^GUIDE_SHIFT (CDF nondecreasing)
+    for (int g = threadIdx.x; g <= (1 << GUIDE_BITS); g += TB_THREADS) {
+        const unsigned long long thr = (unsigned long long)g << GUIDE_SHIFT;
         uint32_t lo = 0, hi = (uint32_t)nb;
         while (lo < hi) {
             const uint32_t mid = (lo + hi) >> 1;
