@@ -140,6 +140,29 @@ def microwalk_e(mw, W, st, walks, n_cells, steps=5, master=0):
     return out
 
 
+def c4_to_target(mw, W, target=0.01, budget=100000000, reps=3):
+    """The large interconnect (C4: 20x20x2 um, 192 wires) walked until the
+    master's self capacitance reaches 3 SE / |C_mm| <= target (Alg. 1 with
+    the stopping rule on the running estimate): walks, time and throughput
+    of each run, with the error reached."""
+    st = W.c4_structure()
+    m = st.meta["master"]
+    h = mw.StructureHandle(st)
+    mw.frw_extract(h, m, 1000000, seed=800)  # table cache warm, as in a long-running process
+    runs = []
+    for k in range(reps):
+        t0 = time.perf_counter()
+        r = mw.frw_extract(h, m, budget, seed=810 + k, target_rel_3sigma=target)
+        dt = time.perf_counter() - t0
+        s = r["stats"]
+        runs.append({"walks": s["walks"], "ms": dt * 1e3, "walks_per_s": s["walks"] / dt,
+                     "micro_steps_per_s": s["micro_steps"] / dt,
+                     "rel_3sigma_reached": float(3 * r["se"][m] / abs(r["row"][m])), "C_mm": float(r["row"][m])})
+    h.close()
+    return {"workload": "C4 interconnect, master %d, n = 16, stop at 3 SE / |C_mm| <= %g" % (m, target),
+            "runs": runs, "median_walks_per_s": float(np.median([q["walks_per_s"] for q in runs]))}
+
+
 def fig3a(mw, W, ns=(4, 8, 12, 16, 20, 24, 28, 32), count=500, walks=4096):
     """Fig. 3(a) study: E(tau) of MicroWalk over `count` cubes per lattice
     size with randomly placed blocks of exponentially distributed
@@ -304,6 +327,7 @@ def main():
         out["microwalk_e"] = microwalk_e(mw, W, st, args.walks, args.n_cells)
         c4 = W.c4_structure()
         out["microwalk_e_c4"] = microwalk_e(mw, W, c4, args.walks, args.n_cells, master=c4.meta["master"])
+        out["c4_to_1pct"] = c4_to_target(mw, W)
         if args.serving_requests > 0:
             out["serving"] = serving(mw, W, args.serving_requests)
     if not args.no_cpu_baseline:
