@@ -66,7 +66,7 @@ def cpu_baseline(st, walks, seed):
     return {"value": walks / dt, "unit": "walks/s", "cores": cores, "kind": "oracle",
             "sample": "%d walks of the same workload (binary64 C++ oracle, %d threads over walk "
                       "ranges), %.1f s; micro-steps/s %.4g" % (walks, cores, dt,
-                                                                r["stats"]["micro_steps"] / dt)}
+                                                                r["stats"]["micro_steps"] / dt)}, r
 
 
 def batched_vs_plain(mw, W, reps=5):
@@ -290,8 +290,11 @@ def main():
     walks = steps = launches = 0
     walker_s = 0.0
     rel = []
+    rows, ses = [], []
     for k in range(args.steps):
         r = mw.frw_extract(h, 0, args.walks, seed=k, n_cells=args.n_cells)
+        rows.append(r["row"])
+        ses.append(r["se"])
         s = r["stats"]
         walks += s["walks"]
         steps += s["micro_steps"]
@@ -331,7 +334,16 @@ def main():
         if args.serving_requests > 0:
             out["serving"] = serving(mw, W, args.serving_requests)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(st, args.cpu_walks, seed=7)
+        out["cpu_baseline"], r_or = cpu_baseline(st, args.cpu_walks, seed=7)
+        # accuracy beside throughput: the timed extractions' mean row against
+        # the oracle's row, entry by entry, in combined standard errors
+        g_row = np.mean(rows, axis=0)
+        g_se = np.sqrt(np.mean(np.square(ses), axis=0) / len(rows))
+        den = np.hypot(g_se, r_or["se"])
+        z = np.where(den > 0, np.abs(g_row - r_or["row"]) / np.where(den > 0, den, 1.0), 0.0)
+        out["oracle_agreement"] = {"gpu_row": g_row.tolist(), "gpu_se": g_se.tolist(),
+                                   "oracle_row": list(map(float, r_or["row"])),
+                                   "oracle_se": list(map(float, r_or["se"])), "max_z": float(z.max())}
     print(json.dumps(out))
 
 
