@@ -258,9 +258,9 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU kernels "
+        print("bench.py runs on one GPU only: the library has single-GPU kernels only "
               "(walk ranges would shard across GPUs with one fp64 all-reduce of the per-net "
-              "sums; not built).", file=sys.stderr)
+              "sums; not implemented).", file=sys.stderr)
         sys.exit(2)
 
 
