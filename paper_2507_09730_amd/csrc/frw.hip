@@ -218,6 +218,33 @@ __device__ __forceinline__ void for_each_record(const float4* rec, uint32_t b, u
         if (!go) return;
     }
 }
+// The same over the entries b + i of a list for the set bits i of mask (list
+// order).
+template <class F>
+__device__ __forceinline__ void for_each_marked(const float4* rec, uint32_t b, unsigned long long mask, F&& f) {
+    while (mask) {
+        uint32_t q[CAND_BATCH];
+        bool v[CAND_BATCH];
+#pragma unroll
+        for (int j = 0; j < CAND_BATCH; ++j) {
+            v[j] = mask != 0ull;
+            q[j] = v[j] ? b + (uint32_t)__builtin_ctzll(mask) : b;
+            mask &= mask - 1ull;
+        }
+        float4 lo[CAND_BATCH], hi[CAND_BATCH];
+#pragma unroll
+        for (int j = 0; j < CAND_BATCH; ++j) {
+            const uint32_t qq = v[j] ? q[j] : q[0];
+            lo[j] = ldf4(rec + 2 * (size_t)qq);
+            hi[j] = ldf4(rec + 2 * (size_t)qq + 1);
+        }
+        bool go = true;
+#pragma unroll
+        for (int j = 0; j < CAND_BATCH; ++j)
+            if (go && v[j]) go = f(lo[j], hi[j]);
+        if (!go) return;
+    }
+}
 __device__ __forceinline__ Parked ldpark(const Parked* p) {
     const GAS guvec4* q = (const GAS guvec4*)p;
     const guvec4 a = q[0], b = q[1];
@@ -441,10 +468,13 @@ __device__ __forceinline__ void layer_walk(Z z0, C lcode, int nl, float zlo, flo
 // 0..7, as float bits) and codes (words 8..15), for at most LAYER_LDS layers.
 // dr: when not null, the cell's dielectric candidate range (gd_off[cell],
 // gd_off[cell + 1]) read ahead by the caller (ordinary cubes only).
+// marked: only the list entries b + i for the set bits i of marks are
+// visited (the boxes exp_fit found touching this cube).
 template <class SR>
 __device__ __forceinline__ CubeInfo build_cube(SR& S, int cell, float3 c, float R, int n, LaneCube L,
                                               bool expanded = false, const uint32_t* lt = nullptr,
-                                              const uint2* dr = nullptr) {
+                                              const uint2* dr = nullptr, bool marked = false,
+                                              unsigned long long marks = 0ull) {
     CubeInfo info{};
     const float h = 2.f * R / (float)n;
     const float lo0[3] = {c.x - R, c.y - R, c.z - R};
@@ -493,7 +523,7 @@ __device__ __forceinline__ CubeInfo build_cube(SR& S, int cell, float3 c, float 
                      (S.bc[2 * a + 1] == MW_BC_NEUMANN && lo0[a] + 2.f * R > S.whi[a]);
     }
     const float inv_h = (float)n / (2.f * R);
-    for_each_record(expanded ? S.gx_rec : S.gd_rec, b, e, [&](const float4& blo, const float4& bhi) {
+    auto box = [&](const float4& blo, const float4& bhi) {
         const float bl[3] = {blo.x, blo.y, blo.z}, bh[3] = {bhi.x, bhi.y, bhi.z};
         bool touch = true;
 #pragma unroll
@@ -531,7 +561,11 @@ __device__ __forceinline__ CubeInfo build_cube(SR& S, int cell, float3 c, float 
             }
         }
         return true;
-    });
+    };
+    if (marked)
+        for_each_marked(expanded ? S.gx_rec : S.gd_rec, b, marks, box);
+    else
+        for_each_record(expanded ? S.gx_rec : S.gd_rec, b, e, box);
     // toggles -> masks (prefix xor along each axis); aggregate masks:
     // present boxes and boxes spanning all cells per axis
     uint32_t O[3];
@@ -596,9 +630,11 @@ __device__ __forceinline__ CubeInfo build_cube(SR& S, int cell, float3 c, float 
 // Absorbing nodes of an expanded cube centred at c with half-size R (the
 // cube never crosses a symmetry wall): grounded faces first, then the
 // conductors holding part of the open cube, in candidate-list (index) order.
-// False when more than EXP_MAX_COND conductors do.
+// False when more than EXP_MAX_COND conductors do.  marked, marks: as for
+// build_cube.
 template <class SR>
-__device__ __forceinline__ bool build_conductors(SR& S, int cell, float3 c, float R, int n, LaneExp E) {
+__device__ __forceinline__ bool build_conductors(SR& S, int cell, float3 c, float R, int n, LaneExp E,
+                                                 bool marked = false, unsigned long long marks = 0ull) {
     const float h = 2.f * R / (float)n;
     const float o[3] = {c.x - R, c.y - R, c.z - R};
     const int np = n + 1;
@@ -624,7 +660,7 @@ __device__ __forceinline__ bool build_conductors(SR& S, int cell, float3 c, floa
     int nb = 0;
     const uint32_t b = gp(S.ge_off)[cell], e = gp(S.ge_off)[cell + 1];
     bool fits = true;
-    for_each_record(S.ge_rec, b, e, [&](const float4& lo4, const float4& hi4) {
+    auto box = [&](const float4& lo4, const float4& hi4) {
         const float bl[3] = {lo4.x, lo4.y, lo4.z}, bh[3] = {hi4.x, hi4.y, hi4.z};
         bool touch = true;
 #pragma unroll
@@ -650,7 +686,11 @@ __device__ __forceinline__ bool build_conductors(SR& S, int cell, float3 c, floa
         }
         ++nb;
         return true;
-    });
+    };
+    if (marked)
+        for_each_marked(S.ge_rec, b, marks, box);
+    else
+        for_each_record(S.ge_rec, b, e, box);
     if (!fits) return false;
     // prefix xor along each axis, four nodes per dword (the axes follow each
     // other without padding: the running value restarts at nodes np and 2 np)
@@ -699,10 +739,14 @@ __device__ __forceinline__ float expanded_size(SR& S, float3 c, float d, int n, 
 // the comparisons build_cube and build_conductors make, the boxes touched at
 // the first EXP_LEVELS sizes of that sequence and returns the first size that
 // fits (else the last one, from which halving goes on), so that the cube is
-// built once instead of once per size tried.  *level: its index.
+// built once instead of once per size tried.  *level: its index.  When that
+// size fits, both lists have at most 64 entries and one more than 8, *marked
+// is set and *mdiel, *mcond mark (bit i: list entry b + i) the boxes the
+// cube touches, so that the builds visit only those.
 constexpr int EXP_LEVELS = 3;
 template <class SR>
-__device__ __forceinline__ float exp_fit(SR& S, int cell, float3 c, float R0, float d, int* level) {
+__device__ __forceinline__ float exp_fit(SR& S, int cell, float3 c, float R0, float d, int* level, bool* marked,
+                                         unsigned long long* mdiel, unsigned long long* mcond) {
     const float cc[3] = {c.x, c.y, c.z};
     float Rk[EXP_LEVELS];
     // per size and axis: the cube's extent [lo, lo + 2R] and its part
@@ -722,33 +766,53 @@ __device__ __forceinline__ float exp_fit(SR& S, int cell, float3 c, float R0, fl
             chi[k][a] = S.bc[2 * a + 1] == MW_BC_NEUMANN ? fminf(hi[k][a], S.whi[a]) : hi[k][a];
         }
     int nd[EXP_LEVELS] = {}, nc[EXP_LEVELS] = {};
-    for_each_record(S.gx_rec, gp(S.gx_off)[cell], gp(S.gx_off)[cell + 1], [&](const float4& bl, const float4& bh) {
+    unsigned long long md[EXP_LEVELS] = {}, mc[EXP_LEVELS] = {};
+    const uint32_t db = gp(S.gx_off)[cell], de = gp(S.gx_off)[cell + 1];
+    const uint32_t cb = gp(S.ge_off)[cell], ce = gp(S.ge_off)[cell + 1];
+    uint32_t i = 0;
+    for_each_record(S.gx_rec, db, de, [&](const float4& bl, const float4& bh) {
+        const unsigned long long bit = i < 64 ? 1ull << i : 0ull;
 #pragma unroll
         for (int k = 0; k < EXP_LEVELS; ++k) {
             const bool t = bl.x <= chi[k][0] && bh.x >= clo[k][0] && bl.y <= chi[k][1] && bh.y >= clo[k][1] &&
                            bl.z <= chi[k][2] && bh.z >= clo[k][2];
             nd[k] += t ? 1 : 0;
+            md[k] |= t ? bit : 0ull;
         }
+        ++i;
         return true;
     });
-    for_each_record(S.ge_rec, gp(S.ge_off)[cell], gp(S.ge_off)[cell + 1], [&](const float4& bl, const float4& bh) {
+    i = 0;
+    for_each_record(S.ge_rec, cb, ce, [&](const float4& bl, const float4& bh) {
+        const unsigned long long bit = i < 64 ? 1ull << i : 0ull;
 #pragma unroll
         for (int k = 0; k < EXP_LEVELS; ++k) {
             const bool t = bl.x < hi[k][0] && bh.x > lo[k][0] && bl.y < hi[k][1] && bh.y > lo[k][1] &&
                            bl.z < hi[k][2] && bh.z > lo[k][2];
             nc[k] += t ? 1 : 0;
+            mc[k] |= t ? bit : 0ull;
         }
+        ++i;
         return true;
     });
     int lv = EXP_LEVELS - 1;
     float R = Rk[EXP_LEVELS - 1];
+    bool fits = nd[EXP_LEVELS - 1] <= MAX_REGIONS && nc[EXP_LEVELS - 1] <= EXP_MAX_COND;
+    unsigned long long mdv = md[EXP_LEVELS - 1], mcv = mc[EXP_LEVELS - 1];
 #pragma unroll
     for (int k = EXP_LEVELS - 2; k >= 0; --k)
         if (nd[k] <= MAX_REGIONS && nc[k] <= EXP_MAX_COND) {
             lv = k;
             R = Rk[k];
+            fits = true;
+            mdv = md[k];
+            mcv = mc[k];
         }
     *level = lv;
+    // (short lists are scanned in full: marking them saves nothing)
+    *marked = fits && (de - db > 8 || ce - cb > 8) && de - db <= 64 && ce - cb <= 64;
+    *mdiel = mdv;
+    *mcond = mcv;
     return R;
 }
 
@@ -1820,11 +1884,16 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             // dq) while it holds too many boxes or
                             // conductors, then by the ordinary rule
                             int it0;
-                            float Re = exp_fit(S, cell, c, expanded_size(S, c, dq, n, A.expand_m), dq, &it0);
+                            bool marked;
+                            unsigned long long mdiel, mcond;
+                            float Re = exp_fit(S, cell, c, expanded_size(S, c, dq, n, A.expand_m), dq, &it0, &marked,
+                                               &mdiel, &mcond);
                             bool ok = false;
                             for (int it = it0;; ++it) {
-                                const CubeInfo IE = build_cube(S, cell, c, Re, n, L, true, lt);
-                                ok = !IE.overflow && build_conductors(S, cell, c, Re, n, E);
+                                // the marks describe the first size only
+                                const bool mk = marked && it == it0;
+                                const CubeInfo IE = build_cube(S, cell, c, Re, n, L, true, lt, nullptr, mk, mdiel);
+                                ok = !IE.overflow && build_conductors(S, cell, c, Re, n, E, mk, mcond);
                                 if (ok || it >= 110) break;
                                 Re = Re > dq ? fmaxf(0.5f * Re, dq) : 0.5f * Re;
                             }
