@@ -193,9 +193,14 @@ STAT_KEYS = ("walks", "hops", "micro_steps", "cls_uniform", "cls_stratified", "c
 
 
 def frw_extract(st, master, n_walks, seed=0, first_walk=0, n_cells=16, hybrid=1,
-                abs_tol_rel=1e-6, threads=1, scores=False, expand=1.0):
+                abs_tol_rel=1e-6, threads=1, scores=False, expand=1.0, kernel_limits=False):
     """Alg. 1: capacitance row (fF, last entry env) and standard errors.
-    expand > 1: MicroWalk-E transitions with that expansion factor."""
+    expand > 1: MicroWalk-E transitions with that expansion factor.
+    Transition cubes are the largest conductor-free cubes (expanded by the
+    MicroWalk-E rule when expand > 1).  kernel_limits=True reproduces the GPU
+    kernel's capacity rule instead (a cube is halved while more than 16
+    dielectric boxes, or for MicroWalk-E 7 conductors, touch it); it exists
+    only so that single walks can be compared with the kernel's one by one."""
     args, keep = _structure_args(st)
     K = st.n_nets + 1
     row = np.zeros(K)
@@ -204,7 +209,8 @@ def frw_extract(st, master, n_walks, seed=0, first_walk=0, n_cells=16, hybrid=1,
     w = np.zeros(n_walks) if scores else None
     stats = np.zeros(13, dtype=np.uint64)
     rc = lib().mwo_frw_extract(*args, I32(master), U64(n_walks), U64(first_walk), U64(seed),
-                               I32(n_cells), I32(hybrid), DBL(abs_tol_rel), DBL(expand), I32(threads),
+                               I32(n_cells), I32(hybrid), DBL(abs_tol_rel), DBL(expand),
+                               I32(1 if kernel_limits else 0), I32(threads),
                                _p(row), _p(se), _p(nets), _p(w), _p(stats))
     if rc:
         raise RuntimeError("oracle frw_extract failed (%d)" % rc)
@@ -213,3 +219,21 @@ def frw_extract(st, master, n_walks, seed=0, first_walk=0, n_cells=16, hybrid=1,
         out["net"] = nets
         out["w"] = w
     return out
+
+
+def microwalk_e_cube(st, centre, R, n, n_walks, seed=0, first_walk=0, c1=0):
+    """MicroWalk-E (Sec. III-B) on one expanded cube of structure st (centre,
+    half-size R, n cells): per walk the boundary hit index, or -2 with the
+    absorbing net (n_nets for the grounded enclosure), and the step count."""
+    args, keep = _structure_args(st)
+    c = np.asarray(centre, dtype=np.float64)
+    hits = np.zeros(n_walks, dtype=np.int32)
+    nets = np.zeros(n_walks, dtype=np.int32)
+    steps = np.zeros(n_walks, dtype=np.int32)
+    rc = lib().mwo_microwalk_e_cube(*args, _p(c), DBL(R), I32(n), U64(n_walks), U64(first_walk), U64(seed),
+                                    ctypes.c_uint32(c1), _p(hits), _p(nets), _p(steps))
+    if rc == -2:
+        raise ValueError("the cube's centre node is absorbing")
+    if rc:
+        raise ValueError("vertex lattice needs even n")
+    return hits, nets, steps

@@ -100,7 +100,9 @@ void thresholds_from_codes(const uint64_t g[6], uint32_t T[5]) {
         acc += g[d];
         S[d] = acc;
     }
-    for (int k = 0; k < 5; ++k) T[k] = (uint32_t)(((S[k] << 32) + S[5] - 1) / S[5]);
+    // 128-bit numerator: cut links of MicroWalk-E can push S_k past 2^32
+    for (int k = 0; k < 5; ++k)
+        T[k] = (uint32_t)((((unsigned __int128)S[k] << 32) + S[5] - 1) / S[5]);
 }
 
 int choose_direction(uint32_t u, const uint32_t T[5]) {
@@ -407,7 +409,7 @@ struct Structure {
 
 const double EPS0 = 8.8541878128e-3;  // vacuum permittivity, fF/um
 const int HOP_CAP = 100000;
-const int MAX_BOXES = 16;  // dielectric boxes a transition cube may touch
+const int MAX_BOXES = 16;  // dielectric boxes of one GPU cube mask (kernel_limits only)
 
 double box_point_dist(const Box& b, const double p[3]) {
     double d = 0;
@@ -468,10 +470,20 @@ int boxes_touching(const Structure& S, const double c[3], double R) {
     return cnt;
 }
 
-// Cube-size rule (reading of "build the transition cube centred at r"):
-// the largest conductor-free cube, halved while it touches more than
-// MAX_BOXES dielectric boxes.  Returns R <= 0 when no halving helps.
-double cube_half_size(const Structure& S, const double c[3], double R) {
+// Cube-size rule (reading of "build the transition cube centred at r",
+// Alg. 3, and of the conductor-free cubes of Sec. III-B): the largest
+// conductor-free cube, R = the distance d from c to the nearest conductor or
+// grounded face.
+//
+// kernel_limits (test option, never the default): the GPU kernel keeps the
+// dielectric boxes of a cube in a 16-bit mask and halves a cube while more
+// than MAX_BOXES boxes touch it.  Any conductor-free cube gives a valid
+// transition, so the halving changes which cube is used, not what the
+// estimator converges to; the option reproduces it so that single walks can
+// be compared with the kernel's one by one.  Returns R <= 0 when no halving
+// helps.
+double cube_half_size(const Structure& S, const double c[3], double R, bool kernel_limits) {
+    if (!kernel_limits) return R;
     for (int it = 0; it < 40; ++it) {
         if (boxes_touching(S, c, R) <= MAX_BOXES) return R;
         R *= 0.5;
@@ -496,18 +508,21 @@ int conductors_touching(const Structure& S, const double c[3], double R) {
     return cnt;
 }
 
-// Expanded-cube size rule of MicroWalk-E (reading; the paper fixes the
+// Expanded-cube size rule of MicroWalk-E (reading; Sec. III-B fixes the
 // expansion factor, 5x, and says the lattice is adjusted to the conductors):
 // the half-size is n d / (2 m) with m = max(1, round(n / (2 E))), so that the
 // nearest conductor face or grounded face, at L-infinity distance d, lies on
 // a node plane (m nodes from the centre); it stops at symmetry walls (no
 // larger than the distance from c to any symmetry wall, so no node needs
-// folding), and is halved while more than MAX_BOXES dielectric boxes or
-// MAX_EXP_COND conductors touch the cube; never below d.  At d the ordinary
-// rule applies.  Returns the half-size (<= 0: no valid cube).
-const int MAX_EXP_COND = 7;  // conductors inside one expanded cube
+// folding), and is never below d.
+//
+// kernel_limits (test option): the GPU kernel also halves the cube, not below
+// d, while more than MAX_BOXES dielectric boxes or MAX_EXP_COND conductors
+// touch it (the widths of its per-cube bit masks), and applies the ordinary
+// rule once it is back at d.  Returns the half-size (<= 0: no valid cube).
+const int MAX_EXP_COND = 7;  // conductors inside one expanded cube (kernel_limits)
 
-double expanded_half_size(const Structure& S, const double c[3], double d, double E, int n) {
+double expanded_half_size(const Structure& S, const double c[3], double d, double E, int n, bool kernel_limits) {
     const int m = std::max(1, (int)std::lround(n / (2.0 * E)));
     double R = n * d / (2.0 * m);
     for (int a = 0; a < 3; ++a) {
@@ -515,11 +530,12 @@ double expanded_half_size(const Structure& S, const double c[3], double d, doubl
         if (S.bc[2 * a + 1] == 1) R = std::min(R, S.whi[a] - c[a]);
     }
     R = std::max(R, d);
+    if (!kernel_limits) return R;
     for (int it = 0; it < 64 && R > d; ++it) {
         if (boxes_touching(S, c, R) <= MAX_BOXES && conductors_touching(S, c, R) <= MAX_EXP_COND) return R;
         R = std::max(0.5 * R, d);
     }
-    return cube_half_size(S, c, d);
+    return cube_half_size(S, c, d, true);
 }
 
 // Mirror folding of a coordinate at Neumann window faces.
@@ -965,6 +981,7 @@ struct FrwParams {
     double delta_abs;
     uint64_t seed;
     double expand = 1.0;  // MicroWalk-E expansion factor (1: plain MicroWalk)
+    bool kernel_limits = false;  // reproduce the GPU kernel's cube halving (tests only)
 };
 
 bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P, TableCache& TC, uint64_t walk,
@@ -993,7 +1010,7 @@ bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P
 
     // FirstTransition(r): cube centred on G touching the master.
     int a = F.axis;
-    double R = cube_half_size(S, r, std::min(structure_dist(S, r, nullptr), G.g));
+    double R = cube_half_size(S, r, std::min(structure_dist(S, r, nullptr), G.g), P.kernel_limits);
     if (R <= 0) return false;
     Cube C;
     build_cube(S, r, R, n, C);
@@ -1058,7 +1075,7 @@ bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P
             return true;
         }
         st.hops++;
-        const double Rh = cube_half_size(S, x, d);
+        const double Rh = cube_half_size(S, x, d, P.kernel_limits);
         if (Rh <= 0) return false;
         build_cube(S, x, Rh, n, C);
         st.hop_class[C.cls]++;
@@ -1070,7 +1087,7 @@ bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P
         } else if (P.expand > 1.0) {
             // MicroWalk-E: the transition cube grows to E times the
             // conductor-free size and may hold conductors (Sec. III-B)
-            const double Re = expanded_half_size(S, x, d, P.expand, n);
+            const double Re = expanded_half_size(S, x, d, P.expand, n, P.kernel_limits);
             if (Re <= 0) return false;
             build_cube(S, x, Re, n, C);
             const std::vector<int32_t> ab = absorbing_nodes(S, C);
@@ -1255,6 +1272,33 @@ int mwo_build_cube(const double* cond, int n_cond, int n_nets, const double* die
     return 0;
 }
 
+// MicroWalk-E (Sec. III-B) on one expanded cube of a structure: the cube
+// centred at `centre` with half-size R and n cells, its absorbing nodes and
+// cut links as in the FRW walk; walks first_walk.. with Philox c1 = c1.
+// hits[w] = boundary hit index, or -2 when the walk was absorbed inside the
+// cube (nets[w] = that net, n_nets for the grounded enclosure; else -1).
+int mwo_microwalk_e_cube(const double* cond, int n_cond, int n_nets, const double* diel, int n_diel,
+                         const double* layer_z0, const double* layer_eps, int n_layers, const double* win,
+                         const int32_t* bc, const double* centre, double R, int n, uint64_t n_walks,
+                         uint64_t first_walk, uint64_t seed, uint32_t c1, int32_t* hits, int32_t* nets,
+                         int32_t* steps) {
+    if (n < 2 || n % 2) return -1;
+    Structure S = make_structure(cond, n_cond, n_nets, diel, n_diel, layer_z0, layer_eps, n_layers, win, bc);
+    Cube C;
+    build_cube(S, centre, R, n, C);
+    const std::vector<int32_t> ab = absorbing_nodes(S, C);
+    if (ab[((size_t)(n / 2) * (n + 1) + n / 2) * (n + 1) + n / 2] >= 0) return -2;  // centre absorbing
+    ThetaCtx TCx{&S, &C};
+    for (uint64_t w = 0; w < n_walks; ++w) {
+        int32_t st = 0;
+        int net = -1;
+        hits[w] = microwalk_vertex_e(C.e, ab, n, seed, c1, first_walk + w, &st, &net, link_theta, &TCx);
+        nets[w] = hits[w] == -2 ? net : -1;
+        if (steps) steps[w] = st;
+    }
+    return 0;
+}
+
 // Largest conductor-free cube query (half-size and nearest net).
 int mwo_dist(const double* cond, int n_cond, int n_nets, const double* win, const int32_t* bc, const double* p,
              double* d, int32_t* nearest) {
@@ -1297,15 +1341,15 @@ int mwo_gauss(const double* cond, int n_cond, int n_nets, const double* win, con
 int mwo_frw_extract(const double* cond, int n_cond, int n_nets, const double* diel, int n_diel,
                     const double* layer_z0, const double* layer_eps, int n_layers, const double* win,
                     const int32_t* bc, int master, uint64_t n_walks, uint64_t first_walk, uint64_t seed, int n,
-                    int hybrid, double abs_tol_rel, double expand, int threads, double* row, double* se,
-                    int32_t* score_net, double* score_w, uint64_t* stats) {
+                    int hybrid, double abs_tol_rel, double expand, int kernel_limits, int threads, double* row,
+                    double* se, int32_t* score_net, double* score_w, uint64_t* stats) {
     if (n < 4 || n % 2 || n_walks < 2) return -1;
     Structure S = make_structure(cond, n_cond, n_nets, diel, n_diel, layer_z0, layer_eps, n_layers, win, bc);
     Gauss G;
     if (!build_gauss(S, master, G)) return -2;
     double diag = 0;
     for (int a = 0; a < 3; ++a) diag += (S.whi[a] - S.wlo[a]) * (S.whi[a] - S.wlo[a]);
-    FrwParams P{n, hybrid, abs_tol_rel * std::sqrt(diag), seed, expand < 1.0 ? 1.0 : expand};
+    FrwParams P{n, hybrid, abs_tol_rel * std::sqrt(diag), seed, expand < 1.0 ? 1.0 : expand, kernel_limits != 0};
     TableCache TC;
     std::vector<int32_t> nets(n_walks);
     std::vector<double> om(n_walks);

@@ -140,3 +140,95 @@ def series_potential(eps_layers):
     for e in eps_layers:
         phi.append(phi[-1] + 1.0 / float(e))
     return np.array(phi)
+
+
+def vertex_links_from_codes(codes):
+    """Link codes of every interior node of the vertex lattice from the cell
+    codes (numpy, written independently of the C++ oracle): the link of
+    direction d is the sum of the four cells that share its edge.  codes:
+    (n, n, n) indexed [k, j, i].  Returns an (n-1)^3 x 6 array in node order
+    ((k-1)M+(j-1))M+(i-1), directions -x,+x,-y,+y,-z,+z."""
+    E = np.asarray(codes, dtype=np.int64)
+    n = E.shape[0]
+    M = n - 1
+    out = np.zeros((M ** 3, 6), dtype=np.int64)
+    for k in range(1, n):
+        for j in range(1, n):
+            for i in range(1, n):
+                v = ((k - 1) * M + (j - 1)) * M + (i - 1)
+                out[v, 0] = E[k - 1:k + 1, j - 1:j + 1, i - 1].sum()
+                out[v, 1] = E[k - 1:k + 1, j - 1:j + 1, i].sum()
+                out[v, 2] = E[k - 1:k + 1, j - 1, i - 1:i + 1].sum()
+                out[v, 3] = E[k - 1:k + 1, j, i - 1:i + 1].sum()
+                out[v, 4] = E[k - 1, j - 1:j + 1, i - 1:i + 1].sum()
+                out[v, 5] = E[k, j - 1:j + 1, i - 1:i + 1].sum()
+    return out
+
+
+def expanded_cube_chain(codes, node_net, cut_theta):
+    """Absorbing-chain solve of a MicroWalk-E cube (Sec. III-B with Theorem 1):
+    the vertex lattice of Alg. 3 in which some interior nodes are absorbing
+    (inside a conductor, or beyond a grounded face) and the links into them
+    are shortened to the fraction theta of their length at which they meet
+    the object, their code becoming rint(code / theta) (the Shortley-Weller
+    form of a Dirichlet boundary between nodes).
+
+    codes: (n, n, n) cell codes [k, j, i]; node_net(i, j, k): the absorbing net
+    of an interior node or -1; cut_theta(i, j, k, d): theta of the link from
+    free node (i, j, k) in direction d into an absorbing node.  Returns
+    (P over the 6 M^2 boundary hit indices, {net: probability}, E(tau)) for
+    walks from the centre node, by a sparse LU solve of (I - Q)^T x = e_c."""
+    n = np.asarray(codes).shape[0]
+    M = n - 1
+    links = vertex_links_from_codes(codes)
+    idx = lambda i, j, k: ((k - 1) * M + (j - 1)) * M + (i - 1)
+    bnodes = vertex_boundary_nodes(n)
+    bindex = {tuple(c): h for h, c in enumerate(bnodes)}
+    free = {}
+    nets = {}
+    for k in range(1, n):
+        for j in range(1, n):
+            for i in range(1, n):
+                a = node_net(i, j, k)
+                if a < 0:
+                    free[(i, j, k)] = len(free)
+                else:
+                    nets[(i, j, k)] = a
+    labels = sorted(set(nets.values()))
+    lab_index = {a: q for q, a in enumerate(labels)}
+    NF = len(free)
+    rows, cols, vals = [], [], []
+    brow, bcol, bval = [], [], []
+    arow, acol, aval = [], [], []
+    for (i, j, k), v in free.items():
+        g = links[idx(i, j, k)].astype(np.float64)
+        for d in range(6):
+            q = (i + DIRS[d, 0], j + DIRS[d, 1], k + DIRS[d, 2])
+            if q in nets:
+                th = max(cut_theta(i, j, k, d), 1.0 / 16.0)
+                g[d] = np.rint(g[d] / th)
+        p = g / g.sum()
+        for d in range(6):
+            q = (i + DIRS[d, 0], j + DIRS[d, 1], k + DIRS[d, 2])
+            if min(q) == 0 or max(q) == n:
+                brow.append(v)
+                bcol.append(bindex[q])
+                bval.append(p[d])
+            elif q in nets:
+                arow.append(v)
+                acol.append(lab_index[nets[q]])
+                aval.append(p[d])
+            else:
+                rows.append(v)
+                cols.append(free[q])
+                vals.append(p[d])
+    Q = sp.csr_matrix((vals, (rows, cols)), shape=(NF, NF))
+    QB = sp.csr_matrix((bval, (brow, bcol)), shape=(NF, 6 * M * M))
+    QA = sp.csr_matrix((aval, (arow, acol)), shape=(NF, max(len(labels), 1)))
+    A = sp.identity(NF, format="csc") - Q.tocsc()
+    e = np.zeros(NF)
+    e[free[(n // 2,) * 3]] = 1.0
+    x = spla.spsolve(A.T.tocsc(), e)
+    P = np.asarray(QB.T @ x).ravel()
+    pa = np.asarray(QA.T @ x).ravel()
+    return P, {a: float(pa[lab_index[a]]) for a in labels}, float(x.sum())
