@@ -98,7 +98,10 @@ mw_status mw_init(int32_t device);
  *            other node coordinates in ascending axis order.  -1 if the walk
  *            exceeded 2^30 steps (cannot happen for valid permittivities).
  * steps      device, n_walks int32 step counts tau, or NULL.
- * Stream-ordered.                                                          */
+ * Ordering: the permittivity range check needs one device round trip, so the
+ * call enqueues the table preparation on `stream`, waits for it (and for the
+ * work queued before it on that stream), then enqueues the walks and returns
+ * without waiting for them.                                                 */
 mw_status mw_transition(const float* eps, int32_t n_cells, int32_t lattice,
                         uint64_t n_walks, uint64_t first_walk, uint64_t seed,
                         uint32_t cube_index, int32_t* hit_idx, int32_t* steps,
@@ -124,7 +127,9 @@ typedef struct {
  * for every tuning.  eps_off, n_cells, n_walks, out_off are host arrays.
  * tune may be NULL (the setting mw_autotune_batch found for a batch of the
  * same shape, else defaults).
- * Stream-ordered; the host arrays may be reused once the call returns.      */
+ * Synchronous: waits on `stream` for the permittivity range check of the
+ * prepared tables, then for the walks; the host arrays may be reused once the
+ * call returns.  (mw_batch_plan_run is the stream-ordered form.)           */
 mw_status mw_transition_batch(int32_t n_cubes, const float* eps_cat,
                               const int64_t* eps_off, const int32_t* n_cells,
                               int32_t lattice, const uint64_t* n_walks,
@@ -201,8 +206,9 @@ typedef struct mw_structure mw_structure;
 /* Copies the description to the device and builds the uniform-grid
  * acceleration structure (per grid cell: the conductors that can be nearest
  * to a point of the cell and the dielectric boxes that a conductor-free cube
- * centred in the cell can touch).  MW_EGEOM on overlapping conductors, a net
- * with zero or several boxes, boxes outside the window or empty boxes. */
+ * centred in the cell can touch).  MW_EGEOM on overlapping boxes of different
+ * nets, a net with no box, a net index outside [0, n_nets), boxes outside the
+ * window or empty boxes; a net may own several boxes (multi-box nets).      */
 mw_status mw_structure_create(const mw_structure_desc* desc, mw_structure** out);
 mw_status mw_structure_destroy(mw_structure* s);
 
@@ -225,7 +231,13 @@ typedef struct {
                                  while it touches more than 16 dielectric
                                  boxes or 7 conductors.  n / (2 m) may not
                                  exceed 4.                                  */
-    int32_t reserved1;
+    int32_t plain;            /* 0 (default): persistent walker launches (a
+                                 lane takes a new walk as soon as its walk
+                                 ends); 1: the plain form, one walker launch
+                                 per transition round (each launch moves every
+                                 live walk by one transition, survivors are
+                                 queued for the next launch).  Per-walk
+                                 results are the same in both forms.        */
     double target_rel_3sigma; /* stop when 3*SE(C_mm)/|C_mm| <= target; 0 =
                                  run exactly walk_budget walks              */
     double abs_tol_rel;       /* absorption distance / window diagonal;
@@ -255,6 +267,11 @@ typedef struct {
                                  matrix                                     */
     uint64_t gauss_faces;     /* frw_extract: its rectangles; 0 for the
                                  matrix                                     */
+    uint64_t cube_halved;     /* transitions (first and non-first) whose cube
+                                 the capacity rule (MW_MAX_REGIONS dielectric
+                                 boxes, or the MicroWalk-E limits) made
+                                 smaller than the conductor-free, or
+                                 expanded, size                             */
 } frw_stats;
 
 /* ------------------------------------------------------------------------
@@ -279,6 +296,35 @@ mw_status frw_extract(mw_structure* s, int32_t master, uint64_t walk_budget,
                       uint64_t seed, const frw_options* options,
                       double* cap_row, double* stderr_row, frw_stats* stats,
                       int32_t* score_net, float* score_w);
+
+/* ------------------------------------------------------------------------
+ * mw_sgf_table — one entry of the transition-table cache (the "analytical
+ * path" of the hybrid strategy, Sec. III-C), built on the device if missing,
+ * copied to the host.  Used to check the tables against an independent exact
+ * solve; extraction calls never need it.
+ *
+ * The cube has n_cells = n cells per axis on the vertex lattice and is
+ * stratified along `axis`: plane p normal to it (p = 0..n-1, ascending
+ * coordinate) has cell code plane_codes[p] = rint(eps_p * 2^16).
+ * kind 0 (hop table): the exit distribution P_b of the walk from the centre
+ *   node (Eq. 8 via Theorem 1), b the vertex-lattice hit index
+ *   (f*M^2 + (b1-1)*M + (a-1), M = n-1, as mw_transition).
+ * kind 1 (first-transition table, normal axis `normal_axis`): the flux
+ *   weights w_b = [G+ (P^c_b - P^+_b) + G- (P^-_b - P^c_b)] / 2 of the
+ *   centre node c and its two neighbours c +- e_normal, G+-  the link
+ *   conductances of c along +-normal in units of eps (the four cell codes of
+ *   the link / 2^18); sampled in proportion to |w_b|.
+ * cdf        host, 6 M^2 uint32: cdf[b] = ceil(2^32 * (sum of the weights of
+ *            entries <= b) / (sum of all weights)), clamped to 2^32 - 1 (a
+ *            word u samples the first b with cdf[b] > u).
+ * sign_bits  host, ceil(6 M^2 / 32) uint32 or NULL: kind 1, bit b set when
+ *            w_b > 0 (kind 0: unspecified).
+ * kh         host, 1 float or NULL: kind 1, sum_b |w_b| (the first-transition
+ *            weight is eps0 |G| kh / h times the sign); kind 0: 0.
+ * n_cells even in 4..32; codes in [66, 65536000] (eps in [1e-3, 1e3]).
+ * MW_ELIMIT when the cache is full.  Synchronous.                          */
+mw_status mw_sgf_table(int32_t n_cells, int32_t kind, int32_t axis, int32_t normal_axis,
+                       const uint32_t* plane_codes, uint32_t* cdf, uint32_t* sign_bits, float* kh);
 
 /* ------------------------------------------------------------------------
  * frw_extract_matrix — Alg. 1 for n_masters masters (distinct net indices in

@@ -132,6 +132,34 @@ def sgf_vertex(codes, src=None):
     return P, et.value
 
 
+def hop_table(plane_codes, axis):
+    """Exit distribution (6 M^2, hit-index order) from the centre of a cube
+    stratified along `axis` with the given plane codes (Sec. III-C, Eq. 8)."""
+    seq = np.ascontiguousarray(plane_codes, dtype=np.uint64)
+    n = int(seq.size)
+    P = np.zeros(6 * (n - 1) ** 2)
+    rc = lib().mwo_hop_table(I32(n), I32(axis), _p(seq), _p(P))
+    if rc:
+        raise ValueError("hop table failed (%d)" % rc)
+    return P
+
+
+def first_table(plane_codes, axis, normal_axis):
+    """First-transition ingredients of a stratified cube: exit distributions
+    from the centre c and from c +- e_normal, and the link conductances G+, G-
+    of c along the normal (eps units)."""
+    seq = np.ascontiguousarray(plane_codes, dtype=np.uint64)
+    n = int(seq.size)
+    nb = 6 * (n - 1) ** 2
+    Pc, Pp, Pm = np.zeros(nb), np.zeros(nb), np.zeros(nb)
+    gp, gm = ctypes.c_double(0), ctypes.c_double(0)
+    rc = lib().mwo_first_table(I32(n), I32(axis), I32(normal_axis), _p(seq), _p(Pc), _p(Pp), _p(Pm),
+                               ctypes.byref(gp), ctypes.byref(gm))
+    if rc:
+        raise ValueError("first table failed (%d)" % rc)
+    return Pc, Pp, Pm, gp.value, gm.value
+
+
 def _structure_args(st):
     cond = np.zeros((st.n_cond, 7))
     cond[:, :6] = st.cond.astype(np.float64)

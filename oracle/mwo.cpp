@@ -1299,6 +1299,34 @@ int mwo_microwalk_e_cube(const double* cond, int n_cond, int n_nets, const doubl
     return 0;
 }
 
+// Transition tables of a stratified cube (plane codes seq[n] along axis s),
+// as the walks use them (Sec. III-C; the exact discrete SGF, Eq. 8).
+// Hop table: exit distribution P (6 M^2) from the centre node.
+int mwo_hop_table(int n, int s, const uint64_t* seq, double* P) {
+    if (n < 2 || n % 2 || s < 0 || s > 2) return -1;
+    TableCache TC;
+    auto T = hop_table(TC, n, s, std::vector<uint64_t>(seq, seq + n));
+    if (!T) return -2;
+    std::copy(T->P.begin(), T->P.end(), P);
+    return 0;
+}
+
+// First-transition table for normal axis a: exit distributions from the
+// centre c and from c +- e_a, and the link conductances G+, G- of c along a.
+int mwo_first_table(int n, int s, int a, const uint64_t* seq, double* Pc, double* Pp, double* Pm, double* Gp,
+                    double* Gm) {
+    if (n < 4 || n % 2 || s < 0 || s > 2 || a < 0 || a > 2) return -1;
+    TableCache TC;
+    auto T = first_table(TC, n, s, a, std::vector<uint64_t>(seq, seq + n));
+    if (!T) return -2;
+    std::copy(T->Pc.begin(), T->Pc.end(), Pc);
+    std::copy(T->Pp.begin(), T->Pp.end(), Pp);
+    std::copy(T->Pm.begin(), T->Pm.end(), Pm);
+    *Gp = T->Gp;
+    *Gm = T->Gm;
+    return 0;
+}
+
 // Largest conductor-free cube query (half-size and nearest net).
 int mwo_dist(const double* cond, int n_cond, int n_nets, const double* win, const int32_t* bc, const double* p,
              double* d, int32_t* nearest) {

@@ -241,7 +241,7 @@ class mw_structure_desc(ctypes.Structure):
 
 class frw_options(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int32), ("hybrid", ctypes.c_int32),
-                ("expand", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("expand", ctypes.c_int32), ("plain", ctypes.c_int32),
                 ("target_rel_3sigma", ctypes.c_double), ("abs_tol_rel", ctypes.c_double),
                 ("first_walk", ctypes.c_uint64), ("batch_walks", ctypes.c_uint64)]
 
@@ -253,7 +253,8 @@ class frw_stats(ctypes.Structure):
                 ("env_absorbed", ctypes.c_uint64), ("hop_cap", ctypes.c_uint64),
                 ("launches", ctypes.c_uint64), ("seconds", ctypes.c_double),
                 ("walker_seconds", ctypes.c_double), ("gauss_g", ctypes.c_double),
-                ("gauss_area", ctypes.c_double), ("gauss_faces", ctypes.c_uint64)]
+                ("gauss_area", ctypes.c_double), ("gauss_faces", ctypes.c_uint64),
+                ("cube_halved", ctypes.c_uint64)]
 
     def as_dict(self):
         return {"walks": self.walks, "hops": self.hops, "micro_steps": self.micro_steps,
@@ -261,7 +262,8 @@ class frw_stats(ctypes.Structure):
                 "cache_miss": self.cache_miss, "env_absorbed": self.env_absorbed,
                 "hop_cap": self.hop_cap, "launches": self.launches, "seconds": self.seconds,
                 "walker_seconds": self.walker_seconds, "gauss_g": self.gauss_g,
-                "gauss_area": self.gauss_area, "gauss_faces": self.gauss_faces}
+                "gauss_area": self.gauss_area, "gauss_faces": self.gauss_faces,
+                "cube_halved": self.cube_halved}
 
 
 def make_desc(st):
@@ -318,7 +320,7 @@ def mw_structure_destroy(handle):
 
 def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
                 target_rel_3sigma=0.0, abs_tol_rel=1e-6, first_walk=0, batch_walks=0,
-                scores=False, device="cuda", expand=0):
+                scores=False, device="cuda", expand=0, plain=0):
     """Alg. 1: one capacitance row (fF, last entry = grounded enclosure) and
     its standard errors.  With scores=True also returns the per-walk net and
     fp32 weight (CUDA tensors)."""
@@ -329,7 +331,7 @@ def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
     row = (ctypes.c_double * K)()
     se = (ctypes.c_double * K)()
     stats = frw_stats()
-    opt = frw_options(n_cells, hybrid, expand, 0, target_rel_3sigma, abs_tol_rel, first_walk,
+    opt = frw_options(n_cells, hybrid, expand, plain, target_rel_3sigma, abs_tol_rel, first_walk,
                       batch_walks)
     net = w = None
     if scores:
@@ -346,8 +348,26 @@ def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
 
 
 
+def mw_sgf_table(plane_codes, axis, kind=0, normal_axis=0):
+    """One transition table of the device cache (built if missing): the
+    stratified cube's plane codes along `axis`; kind 0 hop table, kind 1
+    first-transition table for `normal_axis`.  Returns {"cdf": uint32[6 M^2],
+    "sign": bool[6 M^2] (kind 1), "kh": float (kind 1)}."""
+    codes = np.ascontiguousarray(plane_codes, dtype=np.uint32)
+    n = int(codes.size)
+    nb = 6 * (n - 1) ** 2
+    cdf = np.zeros(nb, dtype=np.uint32)
+    bits = np.zeros((nb + 31) // 32, dtype=np.uint32)
+    kh = ctypes.c_float(0)
+    _check(_lib.mw_sgf_table(I32(n), I32(kind), I32(axis), I32(normal_axis), _vp(codes), _vp(cdf),
+                             _vp(bits), ctypes.byref(kh)))
+    sign = ((bits[np.arange(nb) >> 5] >> (np.arange(nb) & 31).astype(np.uint32)) & 1).astype(bool)
+    return {"cdf": cdf, "sign": sign, "kh": float(kh.value)}
+
+
 def frw_extract_matrix(structure, walks_per_master, seed=0, masters=None, n_cells=16, hybrid=1,
-                       target_rel_3sigma=0.0, abs_tol_rel=1e-6, first_walk=0, batch_walks=0, expand=0):
+                       target_rel_3sigma=0.0, abs_tol_rel=1e-6, first_walk=0, batch_walks=0, expand=0,
+                       plain=0):
     """Capacitance-matrix rows for several masters (default: every net) in
     shared rounds.  Returns {"cap": (M, K) rows, "se": (M, K), "sym": (M, M)
     symmetrised block, "masters": list, "stats": dict}; master i uses seed + i."""
@@ -362,7 +382,7 @@ def frw_extract_matrix(structure, walks_per_master, seed=0, masters=None, n_cell
     se = np.zeros((M, K))
     sym = np.zeros((M, M))
     stats = frw_stats()
-    opt = frw_options(n_cells, hybrid, expand, 0, target_rel_3sigma, abs_tol_rel, first_walk, batch_walks)
+    opt = frw_options(n_cells, hybrid, expand, plain, target_rel_3sigma, abs_tol_rel, first_walk, batch_walks)
     _check(_lib.frw_extract_matrix(structure.handle, I32(M), _vp(m), U64(walks_per_master), U64(seed),
                                    ctypes.byref(opt), _vp(cap), _vp(se), _vp(sym), ctypes.byref(stats)))
     return {"cap": cap, "se": se, "sym": sym, "masters": [int(x) for x in m], "stats": stats.as_dict()}
@@ -393,8 +413,8 @@ class Server:
     """Request loop over the device (mw_server_*): submit structures, poll rows."""
 
     def __init__(self, hbm_budget_bytes, n_cells=16, hybrid=1, target_rel_3sigma=0.0,
-                 abs_tol_rel=1e-6, expand=0):
-        opt = frw_options(n_cells, hybrid, expand, 0, target_rel_3sigma, abs_tol_rel, 0, 0)
+                 abs_tol_rel=1e-6, expand=0, plain=0):
+        opt = frw_options(n_cells, hybrid, expand, plain, target_rel_3sigma, abs_tol_rel, 0, 0)
         h = ctypes.c_void_p()
         _check(_lib.mw_server_create(ctypes.c_size_t(int(hbm_budget_bytes)), ctypes.byref(opt),
                                      ctypes.byref(h)))

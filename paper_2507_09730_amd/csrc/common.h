@@ -117,15 +117,10 @@ __device__ __forceinline__ uint32_t ctr_hi(uint64_t walk, uint32_t purpose) {
     return (uint32_t)((walk >> 32) & 0xffffffu) | (purpose << 24);
 }
 
-// Exact T = ceil(S * 2^32 / S5) for 0 < S <= S5 < 2^32 (no 64-bit division):
-// binary64 estimate, then an integer correction.
+// T = ceil(S * 2^32 / S5) for 0 < S < S5 < 2^32, in 64-bit integers (table
+// preparation only; the walk steps compare mulhi(u, S5) with S instead).
 __device__ __forceinline__ uint32_t ceil_threshold(uint64_t S, uint64_t S5) {
-    double q = (double)(S << 32) / (double)S5;
-    uint64_t t = (uint64_t)ceil(q);
-    const uint64_t num = S << 32;
-    if (t * S5 < num) ++t;
-    if (t > 0 && (t - 1) * S5 >= num) --t;
-    return (uint32_t)t;
+    return (uint32_t)(((S << 32) + S5 - 1) / S5);
 }
 
 }  // namespace mw

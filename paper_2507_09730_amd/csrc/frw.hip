@@ -126,6 +126,9 @@ struct Counters {
     unsigned long long hops, micro_steps, hop_class[3], first_branch[4], env, hop_cap;
     uint32_t err, park_count, first_missing, pad;
     unsigned long long resume_next, walk_next;
+    // transitions whose cube the capacity rule made smaller than the
+    // conductor-free (or expanded) size
+    unsigned long long halved;
 };
 
 // A contiguous range of walks of one extraction request.  One launch of the
@@ -171,6 +174,7 @@ struct WalkArgs {
     uint32_t lane_stride;   // dwords of LDS per lane (odd)
     uint32_t uniform_index; // table of the uniform cube
     int32_t expand_m;       // MicroWalk-E: expanded half-size n d / (2 m) (EXP kernels)
+    int32_t plain;          // 1: every walk makes one transition per launch, then parks
     // single-segment launches: a copy of the structure header, read through
     // the kernel-argument segment (uniform scalar loads) instead of memory
     // that the kernel also writes
@@ -1030,6 +1034,17 @@ __device__ __forceinline__ void node_of_hit(int n, int b, int node[3]) {
     node[o1] = bb;
 }
 
+// Looks up (or queues) the table of the key in key[0 .. C.key_words);
+// out[0] = status, out[1] = table index.
+__global__ void key_table_kernel(CacheDev C, const uint32_t* key, uint32_t* out) {
+    if (threadIdx.x || blockIdx.x) return;
+    uint32_t idx = NO_INDEX;
+    auto kf = [&](uint32_t q) { return key[q]; };
+    const int res = lookup_or_insert(C, kf, key_hash(C.key_words, kf), &idx);
+    out[0] = (uint32_t)res;
+    out[1] = idx;
+}
+
 // Looks up (or queues) the hop table of the uniform cube; out[0] = status,
 // out[1] = table index.
 __global__ void uniform_table_kernel(CacheDev C, int n, uint32_t* out) {
@@ -1057,7 +1072,7 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
     uint32_t* my = lds + threadIdx.x * A.lane_stride;
     const LaneCube L = lane_cube(my, n);
     LAS uint32_t* kbuf = L.bz + n;
-    unsigned long long c_br[4] = {0, 0, 0, 0};
+    unsigned long long c_br[4] = {0, 0, 0, 0}, c_halved = 0;
     uint32_t err = 0, missing = 0;
     // one structure per launch: its layer table goes to LDS once
     uint32_t* lt_lds = lds + FRW_THREADS * A.lane_stride;
@@ -1126,8 +1141,9 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         // FirstTransition: cube touching the master (Sec. III-C, Fig. 4
         // branches; homogenised along the normal when not stratified)
         CubeInfo I = build_cube(S, cell, c, R, n, L, false, lt, &drange);
+        const bool halved = I.overflow;
         for (int it = 0; it < 40 && I.overflow; ++it) {
-            R *= 0.5f;  // cube-size rule: halve while more than 16 boxes touch
+            R *= 0.5f;  // capacity rule: halve while more than 16 boxes touch
             I = build_cube(S, cell, c, R, n, L, false, lt, &drange);
         }
         if (I.overflow) {
@@ -1171,6 +1187,7 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) c_br[q] += br == q ? 1ull : 0ull;  // constant indices: registers
+        c_halved += halved ? 1ull : 0ull;
         const GAS uint32_t* tab = gp(A.cache.data) + (size_t)idx * A.cache.tab_words;
         const int b = table_sample_guided(tab, A.cache.nb, r2.x, glo, ghi);
         const uint32_t sb = (tab[TAB_CDF + A.cache.nb + (b >> 5)] >> (b & 31)) & 1u;
@@ -1188,6 +1205,7 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
     Counters& K = *A.ctr;
     for (int q = 0; q < 4; ++q)
         if (c_br[q]) atomicAdd(&K.first_branch[q], c_br[q]);
+    if (c_halved) atomicAdd(&K.halved, c_halved);
     if (err) atomicOr(&K.err, err);
     if (missing) atomicAdd(&K.first_missing, missing);
 }
@@ -1369,13 +1387,36 @@ __device__ __forceinline__ void mw_begin_e(const MwState& M, MwStateE& Q, LaneEx
 }
 
 // Code of a link cut at fraction tq / 65535 of its length: rint(g / theta),
-// that is floor((65535 g + tq / 2) / tq).  The numerator is below 2^48 and
-// tq >= 4096, so a quotient that is not an integer lies at least 1 / tq from
-// one, more than half an ulp of its double value: the floor of the double
-// division is the integer quotient (without a 64-bit integer division).
+// that is floor((65535 g + tq / 2) / tq), in integers.  g is at most four
+// cell codes (< 2^28) and tq >= 4096, so the numerator x is below 2^44 and
+// the quotient below 2^32; long division in two steps of 32-bit divisions:
+// x = xh 2^16 + xl, q = (xh / tq) 2^16 + ((xh % tq) 2^16 + xl) / tq.
 __device__ __forceinline__ uint32_t cut_link(uint32_t g, uint32_t tq) {
-    const double x = (double)((uint64_t)g * 65535u + (tq >> 1));
-    return (uint32_t)floor(x / (double)tq);
+    const uint64_t x = (uint64_t)g * 65535u + (tq >> 1);
+    const uint32_t xh = (uint32_t)(x >> 16), xl = (uint32_t)x & 0xffffu;
+    const uint32_t q1 = xh / tq, r1 = xh - q1 * tq;
+    const uint32_t q2 = ((r1 << 16) | xl) / tq;
+    return (q1 << 16) + q2;
+}
+
+// The direction rule of Alg. 3 as comparisons: bit k (k = 0..4) is set when
+// floor(u S5 / 2^32) >= S_k, S_k the prefix sums of the six link codes; the
+// direction is the number of set bits.  Six uncut links sum to less than
+// 2^31 (24 cell codes of at most rint(1e3 2^16)); cut links (wide) can carry
+// the sums past 2^32, so they are formed in 64 bits and the product's high
+// part is u (S5 >> 32) + mulhi(u, S5 mod 2^32).
+__device__ __forceinline__ uint32_t step_bits(const uint32_t g[6], uint32_t u, bool wide) {
+    if (!wide) {
+        const uint32_t S0 = g[0], S1 = S0 + g[1], S2 = S1 + g[2], S3 = S2 + g[3], S4 = S3 + g[4];
+        const uint32_t xq = __umulhi(u, S4 + g[5]);
+        return (uint32_t)(xq >= S0) | ((uint32_t)(xq >= S1) << 1) | ((uint32_t)(xq >= S2) << 2) |
+               ((uint32_t)(xq >= S3) << 3) | ((uint32_t)(xq >= S4) << 4);
+    }
+    const uint64_t S0 = g[0], S1 = S0 + g[1], S2 = S1 + g[2], S3 = S2 + g[3], S4 = S3 + g[4];
+    const uint64_t S5 = S4 + g[5];
+    const uint64_t xq = (uint64_t)u * (uint32_t)(S5 >> 32) + __umulhi(u, (uint32_t)S5);
+    return (uint32_t)(xq >= S0) | ((uint32_t)(xq >= S1) << 1) | ((uint32_t)(xq >= S2) << 2) |
+           ((uint32_t)(xq >= S3) << 3) | ((uint32_t)(xq >= S4) << 4);
 }
 
 // Up to four MicroWalk-E steps (one Philox block).  Returns 0 while the walk
@@ -1406,6 +1447,7 @@ __device__ __forceinline__ int mw_block_e(MwState& M, MwStateE& Q, LaneCube L, L
             const uint32_t nx[6] = {Q.xm, Q.xp, Q.xc, Q.xc, Q.xc, Q.xc};
             const uint32_t ny[6] = {Q.yc, Q.yc, Q.ym, Q.yp, Q.yc, Q.yc};
             const uint32_t nz[6] = {Q.zc, Q.zc, Q.zc, Q.zc, Q.zm, Q.zp};
+            bool cut = false;
 #pragma unroll
             for (int dd = 0; dd < 6; ++dd) {
                 const uint32_t env = (nx[dd] | ny[dd] | nz[dd]) & 0x80u;
@@ -1413,13 +1455,10 @@ __device__ __forceinline__ int mw_block_e(MwState& M, MwStateE& Q, LaneCube L, L
                 if (env | cm) {
                     const int b = env ? 7 : __ffs(cm) - 1;
                     g[dd] = cut_link(g[dd], E.theta[(b * 3 + (dd >> 1)) * 2 + ((dd & 1) ? 0 : 1)]);
+                    cut = true;
                 }
             }
-            const uint32_t S0 = g[0], S1 = S0 + g[1], S2 = S1 + g[2], S3 = S2 + g[3], S4 = S3 + g[4];
-            const uint32_t S5 = S4 + g[5];
-            const uint32_t xq = __umulhi(us[q], S5);
-            const uint32_t d = (uint32_t)(xq >= S0) + (uint32_t)(xq >= S1) + (uint32_t)(xq >= S2) +
-                               (uint32_t)(xq >= S3) + (uint32_t)(xq >= S4);
+            const uint32_t d = (uint32_t)__popc(step_bits(g, us[q], cut));
             const int ax = (int)(d >> 1);
             const bool up = (d & 1u) != 0;
             ++M.s;
@@ -1520,6 +1559,7 @@ __device__ __forceinline__ int mw_block_e16(MwState& M, MwStateE& Q, LaneCube L,
             // one conductor holds a coordinate of every axis
             const uint32_t near = (((Q.xm | Q.xc | Q.xp) & (Q.ym | Q.yc | Q.yp) & (Q.zm | Q.zc | Q.zp)) & 0x7fu) |
                                   ((Q.xm | Q.xc | Q.xp | Q.ym | Q.yc | Q.yp | Q.zm | Q.zc | Q.zp) & 0x80u);
+            bool cut = false;
             if (near) {
                 const uint32_t nx[6] = {Q.xm, Q.xp, Q.xc, Q.xc, Q.xc, Q.xc};
                 const uint32_t ny[6] = {Q.yc, Q.yc, Q.ym, Q.yp, Q.yc, Q.yc};
@@ -1531,16 +1571,16 @@ __device__ __forceinline__ int mw_block_e16(MwState& M, MwStateE& Q, LaneCube L,
                     if (env | cm) {
                         const int b = env ? 7 : __ffs(cm) - 1;
                         g[dd] = cut_link(g[dd], E.theta[(b * 3 + (dd >> 1)) * 2 + ((dd & 1) ? 0 : 1)]);
+                        cut = true;
                     }
                 }
             }
-            const uint32_t S0 = g[0], S1 = S0 + g[1], S2 = S1 + g[2], S3 = S2 + g[3], S4 = S3 + g[4];
-            const uint32_t S5 = S4 + g[5];
-            const uint32_t xq = __umulhi(us[q], S5);
-            // the move #{k : xq >= S_k}: x while xq < S1 (up when xq >= S0),
-            // y while xq < S3 (up when xq >= S2), z otherwise (up when xq >= S4)
-            const bool t2 = xq >= S1, t4 = xq >= S3;
-            const bool ux = xq >= S0, uy = xq >= S2, uz = xq >= S4;
+            // the move #{k : floor(u S5 / 2^32) >= S_k}: x while bit 1 is
+            // clear (up when bit 0 is set), y while bit 3 is clear (up when
+            // bit 2 is set), z otherwise (up when bit 4 is set)
+            const uint32_t bits = step_bits(g, us[q], cut);
+            const bool t2 = (bits & 2u) != 0, t4 = (bits & 8u) != 0;
+            const bool ux = (bits & 1u) != 0, uy = (bits & 4u) != 0, uz = (bits & 16u) != 0;
             const bool up = (t4 & uz) | (t2 & !t4 & uy) | (!t2 & ux);
             const uint32_t sh = t4 ? 16u : (t2 ? 8u : 0u);
             ++M.s;
@@ -1610,7 +1650,7 @@ __device__ __forceinline__ int mw_block_e16(MwState& M, MwStateE& Q, LaneCube L,
 // the loop below, the others take table transitions, and the wave switches
 // between the two while at least half of its working lanes walk.
 // -------------------------------------------------------------------------
-enum Phase : int { PH_IDLE = 0, PH_NEED = 1, PH_MW = 2, PH_EXHAUSTED = 3 };
+enum Phase : int { PH_IDLE = 0, PH_NEED = 1, PH_MW = 2, PH_EXHAUSTED = 3, PH_PARK = 4 };
 
 // Consecutive indices handed to the lanes of a wave from a global counter,
 // claimed CLAIM_CHUNK at a time: one device-scope atomic per chunk instead of
@@ -1669,7 +1709,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     const LaneExp E = lane_exp(my, n);  // used by EXP kernels only
 
     Counters& K = *A.ctr;
-    unsigned long long c_hops = 0, c_steps = 0, c_cls[3] = {0, 0, 0}, c_env = 0, c_cap = 0;
+    unsigned long long c_hops = 0, c_steps = 0, c_cls[3] = {0, 0, 0}, c_env = 0, c_cap = 0, c_halved = 0;
     uint32_t err = 0;
     // one structure per launch: its layer table goes to LDS once
     uint32_t* lt_lds = lds + WALK_THREADS * A.lane_stride;
@@ -1703,6 +1743,33 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     int env_net = 0;
 
     for (;;) {
+        // ---- plain form: walks that made their transition of this launch
+        // park for the next one (one queue slot range claimed per wave) ----
+        if (A.plain) {
+            const uint64_t bp = __ballot(phase == PH_PARK);
+            if (bp) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&K.park_count, (uint32_t)__popcll(bp));
+                base = __shfl(base, 0);
+                if (phase == PH_PARK) {
+                    const uint32_t slot = base + (uint32_t)__popcll(bp & ((1ull << lane) - 1ull));
+                    if (slot < A.park_cap) {
+                        Parked P;
+                        P.walk = walk;
+                        P.px = pos.x;
+                        P.py = pos.y;
+                        P.pz = pos.z;
+                        P.omega = omega;
+                        P.t = t;
+                        P.seg = sg;
+                        stpark(A.park_out + slot, P);
+                    } else {
+                        err |= ERR_PARK_CAP;
+                    }
+                    phase = PH_IDLE;
+                }
+            }
+        }
         // ---- take work: resumed walks first, then fresh walk ids ----
         {
             const uint64_t bal = __ballot(phase == PH_IDLE);
@@ -1781,8 +1848,9 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
             }
             if (!done) {
                 CubeInfo I = build_cube(S, cell, c, R, n, L, false, lt, &drange);
+                const bool halved = I.overflow;
                 for (int it = 0; it < 40 && I.overflow; ++it) {
-                    R *= 0.5f;  // cube-size rule: halve while more than 16 boxes touch
+                    R *= 0.5f;  // capacity rule: halve while more than 16 boxes touch
                     I = build_cube(S, cell, c, R, n, L, false, lt, &drange);
                 }
                 if (I.overflow) {
@@ -1859,6 +1927,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             --c_hops;
                             --c_cls[I.cls];
                         } else {
+                            c_halved += halved ? 1ull : 0ull;
                             const GAS uint32_t* tab = gp(A.cache.data) + (size_t)idx * A.cache.tab_words;
                             if (I.cls == 0) {
                                 // the uniform table's guide pair (read with the key otherwise)
@@ -1872,6 +1941,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                                             c.z - R + (float)nd[2] * h);
                             pos = fold3(S, x);
                             ++t;
+                            if (A.plain) phase = PH_PARK;
                         }
                     } else {
                         // MicroWalk from the centre node
@@ -1886,8 +1956,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             int it0;
                             bool marked;
                             unsigned long long mdiel, mcond;
-                            float Re = exp_fit(S, cell, c, expanded_size(S, c, dq, n, A.expand_m), dq, &it0, &marked,
-                                               &mdiel, &mcond);
+                            const float Rx = expanded_size(S, c, dq, n, A.expand_m);
+                            float Re = exp_fit(S, cell, c, Rx, dq, &it0, &marked, &mdiel, &mcond);
                             bool ok = false;
                             for (int it = it0;; ++it) {
                                 // the marks describe the first size only
@@ -1898,6 +1968,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                                 Re = Re > dq ? fmaxf(0.5f * Re, dq) : 0.5f * Re;
                             }
                             if (!ok) err |= ERR_REGIONS;
+                            c_halved += Re < Rx ? 1ull : 0ull;
                             mR = Re;
                             env_net = S.n_nets;
                             if (N16)
@@ -1906,8 +1977,10 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                                 mw_begin(M, L, n);
                             mw_begin_e(M, Q, E, n);
                         } else if (N16) {
+                            c_halved += halved ? 1ull : 0ull;
                             mw_begin16(M, L, n);
                         } else {
+                            c_halved += halved ? 1ull : 0ull;
                             mw_begin(M, L, n);
                         }
                     }
@@ -1992,7 +2065,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                                                   mc.z - mR + (float)M.nk * h);
                     pos = fold3(walk_struct<MULTI>(A, SG), xx);
                     ++t;
-                    phase = PH_NEED;
+                    phase = A.plain ? PH_PARK : PH_NEED;
                 }
             }
         }
@@ -2008,6 +2081,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     for (int q = 0; q < 3; ++q) c_cls[q] = wsum(c_cls[q]);
     c_env = wsum(c_env);
     c_cap = wsum(c_cap);
+    c_halved = wsum(c_halved);
     for (int off = 32; off > 0; off >>= 1) err |= __shfl_down(err, off);
     if (lane == 0) {
         if (c_hops) atomicAdd(&K.hops, c_hops);
@@ -2016,6 +2090,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
             if (c_cls[q]) atomicAdd(&K.hop_class[q], c_cls[q]);
         if (c_env) atomicAdd(&K.env, c_env);
         if (c_cap) atomicAdd(&K.hop_cap, c_cap);
+        if (c_halved) atomicAdd(&K.halved, c_halved);
         if (err) atomicOr(&K.err, err);
     }
 }
@@ -2897,6 +2972,7 @@ LaunchGeom launch_geom(int n) {
 struct Runner {
     int n, hybrid;
     int expand_m = 0;  // MicroWalk-E when > 0 (expanded half-size n d / (2 m))
+    int plain = 0;     // one walker launch per transition round
     Cache* cache;
     LaunchGeom g;
     uint32_t park_cap;
@@ -3011,6 +3087,29 @@ struct Runner {
         cache->uniform_index = uniform_index;
     }
 
+    // The cached table of a key (built if missing), copied to the host.
+    void fetch_table(const std::vector<uint32_t>& key, std::vector<uint32_t>& tab) {
+        std::lock_guard<std::mutex> lock(cache->mu);
+        MW_REQUIRE(key.size() == cache->d.key_words, MW_EINVAL, "bad table key length");
+        // the key goes to the status buffer's neighbour: the first parked
+        // queue, unused outside walker runs
+        uint32_t* dkey = reinterpret_cast<uint32_t*>(park[0]);
+        MW_HIP(hipMemcpy(dkey, key.data(), 4 * key.size(), hipMemcpyHostToDevice));
+        uint32_t res[2] = {LOOKUP_PARK, NO_INDEX};
+        for (int it = 0; it < 3; ++it) {
+            key_table_kernel<<<1, 1>>>(cache->d, dkey, status);
+            MW_HIP(hipGetLastError());
+            MW_HIP(hipMemcpy(res, status, 8, hipMemcpyDeviceToHost));
+            if (res[0] != LOOKUP_PARK) break;
+            build_pending();
+        }
+        MW_REQUIRE(res[0] != LOOKUP_FULL, MW_ELIMIT, "SGF table cache full (MWALK_TABLE_CAP)");
+        MW_REQUIRE(res[0] == LOOKUP_HIT, MW_EDEVICE, "SGF table could not be built");
+        tab.resize(cache->d.tab_words);
+        MW_HIP(hipMemcpy(tab.data(), cache->d.data + (size_t)res[1] * cache->d.tab_words, 4ull * tab.size(),
+                         hipMemcpyDeviceToHost));
+    }
+
     static void check_errors(const Counters& h) {
         MW_REQUIRE(!(h.err & ERR_REGIONS), MW_ELIMIT, "more than %d dielectric boxes overlap at one point",
                    MAX_REGIONS);
@@ -3080,6 +3179,7 @@ struct Runner {
             W.ctr = ctr;
             W.lane_stride = g.lane_stride;
             W.uniform_index = uniform_index;
+            W.plain = plain;
             if (!multi) W.S0 = *s0;
             // reset the per-launch queue state, keep the walk counter (zero
             // from the start of the run for the first launch)
@@ -3128,6 +3228,39 @@ struct Runner {
         }
     }
 };
+
+}  // namespace
+
+extern "C" mw_status mw_sgf_table(int32_t n_cells, int32_t kind, int32_t axis, int32_t normal_axis,
+                                  const uint32_t* plane_codes, uint32_t* cdf, uint32_t* sign_bits, float* kh) {
+    return guarded([&] {
+        MW_REQUIRE(n_cells >= 4 && n_cells <= 32 && n_cells % 2 == 0, MW_EINVAL,
+                   "table lattice size must be even, 4..32");
+        MW_REQUIRE(kind == 0 || kind == 1, MW_EINVAL, "kind must be 0 (hop) or 1 (first transition)");
+        MW_REQUIRE(axis >= 0 && axis < 3, MW_EINVAL, "axis must be 0, 1 or 2");
+        MW_REQUIRE(kind == 0 || (normal_axis >= 0 && normal_axis < 3), MW_EINVAL, "normal axis must be 0, 1 or 2");
+        MW_REQUIRE(plane_codes && cdf, MW_EINVAL, "null plane codes or CDF buffer");
+        const int n = n_cells;
+        for (int p = 0; p < n; ++p)
+            MW_REQUIRE(plane_codes[p] >= 66u && plane_codes[p] <= 65536000u, MW_EINVAL,
+                       "plane code outside rint(eps * 2^16) for eps in [1e-3, 1e3]");
+        std::vector<uint32_t> key(KEY_HDR + n);
+        key[0] = (uint32_t)kind;
+        key[1] = (uint32_t)n;
+        key[2] = (uint32_t)axis;
+        key[3] = kind == 1 ? (uint32_t)normal_axis : 0u;
+        for (int p = 0; p < n; ++p) key[KEY_HDR + p] = plane_codes[p];
+        Runner R(n, 1, 0, 1);
+        std::vector<uint32_t> tab;
+        R.fetch_table(key, tab);
+        const uint32_t nb = 6u * (n - 1) * (n - 1);
+        memcpy(cdf, tab.data() + TAB_CDF, 4ull * nb);
+        if (sign_bits) memcpy(sign_bits, tab.data() + TAB_CDF + nb, 4ull * ((nb + 31) / 32));
+        if (kh) memcpy(kh, tab.data() + 1, 4);
+    });
+}
+
+namespace {
 
 // Gaussian surface of a net (Alg. 1 input G) as a list of axis-aligned
 // rectangles.  G is the boundary of the union of the net's boxes, each grown by
@@ -3374,6 +3507,7 @@ frw_options normalised_options(const frw_options* options) {
     MW_REQUIRE(opt.n_cells >= 4 && opt.n_cells <= 32 && opt.n_cells % 2 == 0, MW_EINVAL,
                "n_cells must be even in [4, 32]");
     if (opt.abs_tol_rel <= 0) opt.abs_tol_rel = 1e-6;
+    MW_REQUIRE(opt.plain == 0 || opt.plain == 1, MW_EINVAL, "plain must be 0 or 1");
     MW_REQUIRE(opt.expand >= 0 && opt.expand <= 64, MW_EINVAL, "expand must be in [0, 64]");
     if (opt.expand > 1) {
         const int m = std::max(1, (int)std::lround(opt.n_cells / (2.0 * opt.expand)));
@@ -3397,6 +3531,7 @@ void add_counters(frw_stats& st, const Counters& h) {
     for (int q = 0; q < 4; ++q) st.first_branch[q] += h.first_branch[q];
     st.env_absorbed += h.env;
     st.hop_cap += h.hop_cap;
+    st.cube_halved += h.halved;
 }
 
 // One round over several extractions (server requests, or the masters of a
@@ -3556,6 +3691,7 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         Extraction X(*st, master, opt.abs_tol_rel, batch, own_scores);
         Runner R(n, opt.hybrid, batch, 1);
         R.expand_m = expand_m_of(opt);
+        R.plain = opt.plain;
         frw_stats acc{};
         while (X.done < walk_budget) {
             const uint64_t nb = std::min<uint64_t>(batch, walk_budget - X.done);
@@ -3618,6 +3754,7 @@ extern "C" mw_status frw_extract_matrix(mw_structure* st, int32_t n_masters, con
         }
         Runner R(n, opt.hybrid, round_walks, n_masters);
         R.expand_m = expand_m_of(opt);
+        R.plain = opt.plain;
         SharedRound round(round_walks, n_masters);
         frw_stats acc{};
         std::vector<bool> active(n_masters, true);
@@ -3848,6 +3985,7 @@ struct mw_server {
                 if (!R) {
                     R = std::make_unique<Runner>(opt.n_cells, opt.hybrid, round_walks, max_slots);
                     R->expand_m = expand_m_of(opt);
+                    R->plain = opt.plain;
                 }
                 (void)round->run(*R, X, sh, seeds, opt.first_walk);
                 for (auto& r : running) {

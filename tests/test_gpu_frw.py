@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from _stats import z_crit
 
 pytestmark = pytest.mark.gpu
 
@@ -108,9 +109,14 @@ def test_walks_match_oracle_one_by_one(mw, oracle_lib, name, expand, n_cells, fl
     N = 20000 if n_cells <= 16 else 5000
     g = mw.frw_extract(st, m, N, seed=77, scores=True, expand=expand, n_cells=n_cells)
     o = oracle_lib.frw_extract(st, m, N, seed=77, threads=_threads(), scores=True, n_cells=n_cells,
-                               expand=float(expand) if expand else 1.0)
+                               expand=float(expand) if expand else 1.0, kernel_limits=True)
     same_net, same_walk = _walk_agreement(g, o["net"], o["w"])
-    print(name, expand, n_cells, "same net", same_net, "same net and weight", same_walk)
+    # the oracle reproduces the kernel's capacity rule here (kernel_limits);
+    # cube_halved counts the transitions where that rule applied
+    print(name, expand, n_cells, "same net", same_net, "same net and weight", same_walk,
+          "halved cubes", g["stats"]["cube_halved"], "of", g["stats"]["hops"] + N)
+    if name in ("plates", "stack") or (name == "c2" and not expand):
+        assert g["stats"]["cube_halved"] == 0
     assert same_walk >= floor
 
 
@@ -124,7 +130,8 @@ def test_c2_full_size_sampled_walks_match_oracle(c2_gpu, oracle_lib):
     assert n_walks == 1000000
     agree = []
     for f in np.linspace(0, n_walks - 250, 8).astype(np.int64):
-        o = oracle_lib.frw_extract(st, 0, 250, seed=20, first_walk=int(f), threads=_threads(), scores=True)
+        o = oracle_lib.frw_extract(st, 0, 250, seed=20, first_walk=int(f), threads=_threads(), scores=True,
+                                   kernel_limits=True)
         part = {"net": g["net"][f:f + 250], "w": g["w"][f:f + 250]}
         agree.append(_walk_agreement(part, o["net"], o["w"])[1])
     print("per-run agreement", agree)
@@ -168,8 +175,9 @@ def test_c2_hybrid_equals_all_microwalk(mw, c2_gpu):
     r_hy = c2_gpu[0]
     print("all-microwalk", r_mw["row"], r_mw["se"], r_mw["stats"])
     assert r_mw["stats"]["hop_class"][1] + r_mw["stats"]["hop_class"][0] > 0
-    for j in range(5):
-        assert _z(r_hy["row"][j], r_mw["row"][j], r_hy["se"][j], r_mw["se"][j]) < 3.5
+    zs = [_z(r_hy["row"][j], r_mw["row"][j], r_hy["se"][j], r_mw["se"][j]) for j in range(5)]
+    print("z", zs)
+    assert max(zs) < z_crit(5)
 
 
 def test_scores_independent_of_cache_state_and_resume(mw):
@@ -186,6 +194,24 @@ def test_scores_independent_of_cache_state_and_resume(mw):
     c2 = mw.frw_extract(h, 0, 13000, seed=5, n_cells=12, first_walk=7000, scores=True)
     assert torch.equal(torch.cat([c1["net"], c2["net"]]), a["net"])
     assert torch.equal(torch.cat([c1["w"], c2["w"]]), a["w"])
+
+
+@pytest.mark.parametrize("expand", [0, 5])
+def test_plain_form_equals_persistent(mw, expand):
+    """The plain form (one walker launch per transition round, survivors
+    queued for the next launch) gives every walk the same result as the
+    persistent launch; it needs as many launches as the longest walk has
+    transitions."""
+    import torch
+    st = W.c2_structure()
+    h = mw.StructureHandle(st)
+    a = mw.frw_extract(h, 0, 30000, seed=15, scores=True, expand=expand)
+    b = mw.frw_extract(h, 0, 30000, seed=15, scores=True, expand=expand, plain=1)
+    print("launches persistent", a["stats"]["launches"], "plain", b["stats"]["launches"])
+    assert torch.equal(a["net"], b["net"]) and torch.equal(a["w"], b["w"])
+    assert b["stats"]["launches"] > 4 * a["stats"]["launches"]
+    assert a["stats"]["hops"] == b["stats"]["hops"]
+    assert a["stats"]["micro_steps"] == b["stats"]["micro_steps"]
 
 
 def test_convergence_target(mw):
@@ -231,14 +257,17 @@ def test_c4_matches_oracle(mw, oracle_lib):
           % (r_gpu["row"][m], r_gpu["se"][m], r_or["row"][m], r_or["se"][m], len(resolved),
              zs[resolved].max()))
     assert m in resolved and len(resolved) >= 5
-    assert zs[m] < 4.0
-    assert zs[resolved].max() < 4.5
+    print("halved cubes", r_gpu["stats"]["cube_halved"], "of", r_gpu["stats"]["hops"] + 2000000)
+    # the self term alone at 3 combined SE; the resolved entries together at
+    # the Bonferroni threshold over their number
+    assert zs[m] < 3.0
+    assert zs[resolved].max() < z_crit(len(resolved))
     # the resolved entries as a whole: mean z^2 near 1
     assert np.mean(zs[resolved] ** 2) < 2.5
     # nets the GPU never reached are ones the oracle sample barely reached
     for j in range(K):
         if r_gpu["row"][j] == 0.0:
-            assert abs(r_or["row"][j]) < 4.5 * r_or["se"][j] + 1e-30
+            assert abs(r_or["row"][j]) < z_crit(K) * r_or["se"][j] + 1e-30
 
 
 
@@ -262,7 +291,7 @@ def test_matrix_rows_equal_single_extractions(mw):
         assert sym[a, a] == cap[a, a]
         for b in range(4):
             if a != b:
-                assert _z(cap[a, b], cap[b, a], se[a, b], se[b, a]) < 3.5
+                assert _z(cap[a, b], cap[b, a], se[a, b], se[b, a]) < z_crit(6)
                 assert sym[a, b] == pytest.approx(0.5 * (cap[a, b] + cap[b, a]))
     # a subset of masters, converging on its own target
     M2 = mw.frw_extract_matrix(h, 20000000, seed=5, masters=[2, 0], target_rel_3sigma=0.03,
@@ -274,6 +303,27 @@ def test_matrix_rows_equal_single_extractions(mw):
     with pytest.raises(mw.MWError) as e:
         mw.frw_extract_matrix(h, 1000, masters=[1, 1])
     assert e.value.status == mw.MW_EINVAL
+
+
+def test_matrix_rows_match_oracle(mw, oracle_lib):
+    """frw_extract_matrix on the crossing wires against the oracle: each GPU
+    row against the oracle's row of the same master, and reciprocity across
+    the two implementations (GPU C_ab against the oracle's C_ba), all
+    entries together at the Bonferroni threshold."""
+    st = W.c2_structure()
+    M = mw.frw_extract_matrix(st, 1000000, seed=70)
+    rows = {m: oracle_lib.frw_extract(st, m, 60000, seed=170 + m, threads=_threads()) for m in range(4)}
+    zs, zr = [], []
+    for i, m in enumerate(M["masters"]):
+        o = rows[m]
+        zs += [_z(M["cap"][i, j], o["row"][j], M["se"][i, j], o["se"][j]) for j in range(5)]
+        for j in range(4):
+            if j != m:
+                zr.append(_z(M["cap"][i, j], rows[j]["row"][m], M["se"][i, j], rows[j]["se"][m]))
+    zs, zr = np.array(zs), np.array(zr)
+    print("rows: max z %.2f; reciprocity across implementations: max z %.2f" % (zs.max(), zr.max()))
+    assert zs.max() < z_crit(zs.size)
+    assert zr.max() < z_crit(zr.size)
 
 
 # ---------------------------------------------------------------------------
@@ -302,10 +352,28 @@ def test_microwalk_e_c2_matches_oracle(mw, oracle_lib):
     print("gpu plain", p["row"], p["stats"])
     zs = [_z(g["row"][j], o["row"][j], g["se"][j], o["se"][j]) for j in range(5)]
     print("z", zs)
-    assert max(zs) < 3.5
+    assert max(zs) < z_crit(5)
     per = lambda r, k: r["stats"][k] / r["stats"]["walks"]
     assert per(g, "hops") * 2 < per(p, "hops")
     assert per(g, "micro_steps") * 4 < per(p, "micro_steps")
+
+
+def test_microwalk_e_high_permittivity_beside_conductors(mw, oracle_lib):
+    """MicroWalk-E with eps = 1e3 (the largest accepted) filling half of a
+    parallel-plate gap: links cut near the plates carry up to 16 times a
+    link code of 2.6e8, so the direction sums pass 2^32.  Walks equal the
+    oracle's one by one, and the row meets the closed form."""
+    st = W.parallel_plates("columns_highk")
+    g = mw.frw_extract(st, 0, 20000, seed=77, scores=True, hybrid=0, expand=5)
+    o = oracle_lib.frw_extract(st, 0, 20000, seed=77, threads=_threads(), scores=True, hybrid=0, expand=5.0,
+                               kernel_limits=True)
+    same_net, same_walk = _walk_agreement(g, o["net"], o["w"])
+    print("highk MicroWalk-E same net", same_net, "same net and weight", same_walk)
+    assert same_walk >= 0.99
+    exact = W.parallel_plates_exact("columns_highk")
+    r = mw.frw_extract(st, 0, 1000000, seed=13, hybrid=0, expand=5)
+    print("highk", r["row"][0] / exact - 1, r["se"][0] / exact, r["stats"]["micro_steps"])
+    assert abs(r["row"][0] - exact) < 0.01 * exact + 3 * r["se"][0]
 
 
 def test_microwalk_e_options(mw):

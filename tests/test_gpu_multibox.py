@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from _stats import z_crit
 
 pytestmark = pytest.mark.gpu
 
@@ -76,7 +77,7 @@ def test_c2_multibox_matches_oracle(mw, oracle_lib):
     print("gpu", r_gpu["row"], r_gpu["se"])
     print("oracle", r_or["row"], r_or["se"])
     print("z", zs)
-    assert zs.max() < 4.0
+    assert zs.max() < z_crit(K)
     # Maxwell signs: positive self term, negative couplings
     assert r_gpu["row"][0] > 0 and (r_gpu["row"][1:] <= 0).all()
 

@@ -4,10 +4,13 @@ Every request's result in a mixed, overlapping request stream must equal the
 same extraction run alone (frw_extract) up to fp32 summation order, and the
 admitted device footprint must stay within the memory budget.
 """
+import os
+
 import numpy as np
 import pytest
 
 import workloads as W
+from _stats import z, z_crit
 
 pytestmark = pytest.mark.gpu
 
@@ -39,13 +42,19 @@ def _same(a, b):
     return np.all(np.abs(a["row"] - b["row"]) <= 1e-6 * np.abs(b["row"]) + 1e-9 * scale)
 
 
-def test_mix_equals_alone(mw):
+@pytest.fixture(scope="module")
+def served(mw):
     reqs = _requests()
     srv = mw.Server(4 << 30)
     tickets = [srv.submit(st, m, b, seed) for st, m, b, seed in reqs]
     results = [srv.wait(t) for t in tickets]
     stats = srv.stats()
     srv.close()
+    return reqs, results, stats
+
+
+def test_mix_equals_alone(mw, served):
+    reqs, results, stats = served
     print("server stats", stats)
     assert stats["completed"] == len(reqs) and stats["failed"] == 0
     assert stats["max_concurrent"] > 1  # requests overlapped on the device
@@ -97,3 +106,26 @@ def test_target_stops_early(mw):
     srv.close()
     assert r["walks"] < 50000000
     assert 3 * r["se"][0] / r["row"][0] <= 0.05
+
+
+def test_served_rows_match_oracle(served, oracle_lib):
+    """Each served row against the oracle's row of the same request (Alg. 1,
+    independent seed): every entry that both sides resolve (|C| > 4 SE; an
+    entry that a small oracle sample never reached has no usable standard
+    error), all requests together, within the Bonferroni threshold of 3
+    combined standard errors over the number of entries compared."""
+    reqs, results, _ = served
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    zs = []
+    for (st, m, b, seed), r in zip(reqs, results):
+        o = oracle_lib.frw_extract(st, m, 20000 if st.n_nets <= 4 else 12000, seed=seed + 5000, threads=threads)
+        keep = (np.abs(o["row"]) > 4 * o["se"]) & (np.abs(r["row"]) > 4 * r["se"])
+        assert keep[m]
+        zz = z(r["row"][keep], o["row"][keep], r["se"][keep], o["se"][keep])
+        print(st.name, "master", m, "entries", int(keep.sum()), "max z %.2f" % zz.max(),
+              "C_mm served %.5g oracle %.5g" % (r["row"][m], o["row"][m]))
+        zs.append(zz)
+    allz = np.concatenate(zs)
+    print("entries compared", allz.size, "threshold", z_crit(allz.size), "mean z^2", np.mean(allz ** 2))
+    assert allz.max() < z_crit(allz.size)
+    assert np.mean(allz ** 2) < 2.0

@@ -138,6 +138,9 @@ def parallel_plates(variant="uniform"):
     z0, le = [0.0], [3.9]
     if variant == "columns":
         diel, deps = [[0.5, 0, 0, 1, 1, 1]], [7.0]
+    elif variant == "columns_highk":
+        # the largest permittivity the library accepts, against both plates
+        diel, deps = [[0.5, 0, 0, 1, 1, 1]], [1000.0]
     elif variant == "checkerboard":
         diel, deps = [[0.5, 0, 0, 1, 0.5, 1], [0, 0.5, 0, 0.5, 1, 1]], [7.0, 7.0]
     elif variant == "series":
@@ -163,6 +166,8 @@ def parallel_plates_exact(variant="uniform"):
         return EPS0 * 3.9 * A / d
     if variant in ("columns", "checkerboard"):
         return EPS0 * (0.5 * 3.9 + 0.5 * 7.0) * A / d
+    if variant == "columns_highk":
+        return EPS0 * (0.5 * 3.9 + 0.5 * 1000.0) * A / d
     if variant == "series":
         return EPS0 * A / (0.4 / 3.9 + 0.4 / 2.7)
     if variant == "stack":
