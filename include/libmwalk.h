@@ -107,6 +107,28 @@ mw_status mw_transition(const float* eps, int32_t n_cells, int32_t lattice,
                         uint32_t cube_index, int32_t* hit_idx, int32_t* steps,
                         void* stream);
 
+/* ------------------------------------------------------------------------
+ * mw_transition_noalloc — mw_transition for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results bit-identical to
+ * mw_transition.  Instead of a per-call allocation it uses a static device
+ * array of MW_NOALLOC_SCRATCH_BYTES per device (the cube descriptor, counters
+ * and the prepared threshold or cell-code table: 256 bytes plus about 20
+ * bytes per lattice node; vertex-lattice cubes up to n = 48 fit).  It calls no
+ * hipMalloc, hipFree or allocating library routine.  MW_ELIMIT when the cube's
+ * table does not fit (the error names both sizes).  Every call on a device
+ * shares that device's array, which keeps the last call's contents; the
+ * counters are cleared by a kernel at the start of each call.  Calls that
+ * overlap on one device (other host threads, or other streams) race on the
+ * array and give wrong results: the caller serialises them.  Like
+ * mw_transition it waits on `stream` for the permittivity range check before
+ * enqueueing the walks.                                                     */
+#define MW_NOALLOC_SCRATCH_BYTES (4u << 20)
+mw_status mw_transition_noalloc(const float* eps, int32_t n_cells, int32_t lattice,
+                                uint64_t n_walks, uint64_t first_walk, uint64_t seed,
+                                uint32_t cube_index, int32_t* hit_idx, int32_t* steps,
+                                void* stream);
+
 /* Tuning knobs of the batched MicroWalk launch.  Zero fields mean "use the
  * autotuned or default value". */
 typedef struct {

@@ -89,6 +89,24 @@ def mw_transition(eps, n_walks, lattice=MW_LATTICE_VERTEX, first_walk=0, seed=0,
     return hits, steps
 
 
+def mw_transition_noalloc(eps, n_walks, lattice=MW_LATTICE_VERTEX, first_walk=0, seed=0, cube_index=0,
+                          hits=None, steps=None, want_steps=True, stream=None):
+    """mw_transition through the entry point that allocates no device memory
+    (static per-device scratch).  The caller passes the outputs to keep the
+    call allocation-free; when they are None they are created here."""
+    import torch
+    assert eps.is_cuda and eps.dtype == torch.float32 and eps.is_contiguous()
+    n = int(eps.shape[0])
+    assert eps.shape == (n, n, n)
+    if hits is None:
+        hits = torch.empty(n_walks, dtype=torch.int32, device=eps.device)
+    if steps is None and want_steps:
+        steps = torch.empty(n_walks, dtype=torch.int32, device=eps.device)
+    _check(_lib.mw_transition_noalloc(_ptr(eps), I32(n), I32(lattice), U64(n_walks), U64(first_walk),
+                                      U64(seed), U32(cube_index), _ptr(hits), _ptr(steps), _stream(stream)))
+    return hits, steps
+
+
 def pack_cubes(eps_list, device="cuda"):
     """Concatenates cube grids into one device buffer: (eps_cat, n_cells, eps_off)."""
     import torch

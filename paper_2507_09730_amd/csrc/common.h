@@ -61,6 +61,10 @@ mw_status guarded(F&& body) {
 // MWALK_FAULT=alloc:<k> makes the k-th device allocation (1-based) fail.
 bool inject_alloc_failure();
 
+// Device address of the static scratch of mw_transition_noalloc on the
+// current device (looked up on the first call per device).
+char* noalloc_scratch();
+
 // Device allocation helpers (throw Fail on error).
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);

@@ -461,6 +461,105 @@ Launch default_launch(const mw_tune* t, uint64_t total_walks) {
 
 using namespace mw;
 
+namespace mw {
+namespace {
+
+// Scratch of one single-cube call: [bad flag | step counter | item counter |
+// seed | cube descriptor | prepared table].
+constexpr size_t CALL_HDR = 256;
+
+size_t transition_scratch_bytes(const Plan& p) { return CALL_HDR + (size_t)p.table_words * 4; }
+
+// Enqueues one cube's preparation and walks on st with the given device
+// scratch (at least transition_scratch_bytes(p)).  Returns false, with
+// nothing but the preparation enqueued, when a permittivity is outside
+// [1e-3, 1e3]; the range check waits for the preparation kernel.
+bool transition_enqueue(const Plan& p, const float* eps, int32_t n_cells, int32_t lattice, uint64_t n_walks,
+                        uint64_t first_walk, uint64_t seed, uint32_t cube_index, int32_t* hit_idx,
+                        int32_t* steps, hipStream_t st, char* scratch) {
+    int* bad = (int*)scratch;
+    unsigned long long* step_total = (unsigned long long*)(scratch + 8);
+    int32_t* item_counter = (int32_t*)(scratch + 16);
+    unsigned long long* seed_dev = (unsigned long long*)(scratch + 24);
+    CubeDev* dcube = (CubeDev*)(scratch + 64);
+    CubeDev C{};
+    C.eps = eps;
+    C.table = (uint32_t*)(scratch + CALL_HDR);
+    C.hits = hit_idx;
+    C.steps = steps;
+    C.walk0 = first_walk;
+    C.n_walks = n_walks;
+    C.n = n_cells;
+    C.lattice = lattice;
+    C.form = p.form;
+    C.P = p.P;
+    C.table_words = p.table_words;
+    C.t4_words = p.t4_words;
+    C.c1 = cube_index;
+    const int cen = lattice == MW_LATTICE_VERTEX ? n_cells / 2 : (n_cells - 1) / 2 + 1;
+    C.start = cen * (p.P * p.P + p.P + 1);
+    // counters cleared by a kernel (no memset node if a caller captures it)
+    reset_kernel<<<1, 1, 0, st>>>(bad, step_total, item_counter);
+    MW_HIP(hipMemcpyAsync(dcube, &C, sizeof C, hipMemcpyHostToDevice, st));
+    const uint32_t nodes = (uint32_t)p.P * p.P * p.P;
+    prep_kernel<<<dim3(std::min<uint32_t>((nodes + 255) / 256, 1024), 1), 256, 0, st>>>(dcube, bad);
+    MW_HIP(hipGetLastError());
+    // eps is device memory: its range check needs one device round trip
+    int h_bad = 0;
+    MW_HIP(hipMemcpyAsync(&h_bad, bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
+    MW_HIP(hipStreamSynchronize(st));
+    if (h_bad) return false;
+    const Launch L = default_launch(nullptr, n_walks);
+    const int threads = 64 * L.waves;
+    uint64_t iw = L.item_walks ? L.item_walks : std::max<uint64_t>(threads * 4, 4096);
+    const int cus = num_cus();
+    // enough items to keep every CU busy
+    while (iw > (uint64_t)threads && (n_walks + iw - 1) / iw < (uint64_t)cus * 2) iw /= 2;
+    const int64_t n_items = (int64_t)((n_walks + iw - 1) / iw);
+    MW_REQUIRE(n_items < (1ll << 31), MW_ELIMIT, "too many walks for one launch");
+    const size_t lds = p.form == FORM_TGLOBAL ? 16 : (size_t)p.table_words * 4;
+    const int blocks = (int)std::min<int64_t>(n_items, (int64_t)cus * blocks_per_cu(lds));
+    allow_large_lds();
+    seed_kernel<<<1, 1, 0, st>>>(seed_dev, seed);
+    walk_kernel<<<blocks, threads, lds, st>>>(dcube, nullptr, (int32_t)n_items, iw, item_counter, seed_dev,
+                                               L.groups, step_total);
+    MW_HIP(hipGetLastError());
+    return true;
+}
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = MW_NOALLOC_SCRATCH_BYTES;
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[MAX_DEVICES] = {};
+
+}  // namespace
+
+// Static scratch of mw_transition_noalloc: each device holds its own copy
+// until the process ends.  Host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device; the array's name is a
+// host-side stand-in, not a device address.
+__device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+// Device address of the current device's static scratch (looked up once per
+// device, with that device current).
+char* noalloc_scratch() {
+    int dev = 0;
+    MW_HIP(hipGetDevice(&dev));
+    MW_REQUIRE(dev >= 0 && dev < MAX_DEVICES, MW_ELIMIT, "device %d beyond the %d supported", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        MW_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        MW_REQUIRE(ptr, MW_EDEVICE, "no device address for the static scratch");
+        g_scratch_ptr[dev] = (char*)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace mw
+
+using namespace mw;
+
 extern "C" mw_status mw_transition(const float* eps, int32_t n_cells, int32_t lattice, uint64_t n_walks,
                                    uint64_t first_walk, uint64_t seed, uint32_t cube_index, int32_t* hit_idx,
                                    int32_t* steps, void* stream) {
@@ -470,62 +569,38 @@ extern "C" mw_status mw_transition(const float* eps, int32_t n_cells, int32_t la
         MW_REQUIRE(eps && hit_idx, MW_EINVAL, "eps and hit_idx are required");
         hipStream_t st = (hipStream_t)stream;
         const Plan p = plan_cube(n_cells, lattice, 0);
-        // scratch: [bad flag | step counter | item counter | cube desc | table]
-        const size_t hdr = 256;
-        const size_t bytes = hdr + (size_t)p.table_words * 4;
-        char* scratch = nullptr;
+        char* scr = nullptr;
         MW_REQUIRE(!inject_alloc_failure(), MW_ENOMEM, "injected device allocation failure");
-        MW_HIP(hipMallocAsync((void**)&scratch, bytes, st));
-        int* bad = (int*)scratch;
-        unsigned long long* step_total = (unsigned long long*)(scratch + 8);
-        int32_t* item_counter = (int32_t*)(scratch + 16);
-        unsigned long long* seed_dev = (unsigned long long*)(scratch + 24);
-        CubeDev* dcube = (CubeDev*)(scratch + 64);
-        CubeDev C{};
-        C.eps = eps;
-        C.table = (uint32_t*)(scratch + hdr);
-        C.hits = hit_idx;
-        C.steps = steps;
-        C.walk0 = first_walk;
-        C.n_walks = n_walks;
-        C.n = n_cells;
-        C.lattice = lattice;
-        C.form = p.form;
-        C.P = p.P;
-        C.table_words = p.table_words;
-        C.t4_words = p.t4_words;
-        C.c1 = cube_index;
-        const int cen = lattice == MW_LATTICE_VERTEX ? n_cells / 2 : (n_cells - 1) / 2 + 1;
-        C.start = cen * (p.P * p.P + p.P + 1);
-        MW_HIP(hipMemsetAsync(scratch, 0, 64, st));
-        MW_HIP(hipMemcpyAsync(dcube, &C, sizeof C, hipMemcpyHostToDevice, st));
-        const uint32_t nodes = (uint32_t)p.P * p.P * p.P;
-        prep_kernel<<<dim3(std::min<uint32_t>((nodes + 255) / 256, 1024), 1), 256, 0, st>>>(dcube, bad);
-        MW_HIP(hipGetLastError());
-        // eps is device memory: its range check needs one device round trip
-        int h_bad = 0;
-        MW_HIP(hipMemcpyAsync(&h_bad, bad, sizeof h_bad, hipMemcpyDeviceToHost, st));
-        MW_HIP(hipStreamSynchronize(st));
-        if (h_bad) {
-            (void)hipFreeAsync(scratch, st);
-            MW_REQUIRE(false, MW_EINVAL, "permittivity outside [1e-3, 1e3]");
+        MW_HIP(hipMallocAsync((void**)&scr, transition_scratch_bytes(p), st));
+        bool ok = false;
+        try {
+            ok = transition_enqueue(p, eps, n_cells, lattice, n_walks, first_walk, seed, cube_index, hit_idx, steps,
+                                    st, scr);
+        } catch (...) {
+            (void)hipFreeAsync(scr, st);
+            throw;
         }
-        const Launch L = default_launch(nullptr, n_walks);
-        const int threads = 64 * L.waves;
-        uint64_t iw = L.item_walks ? L.item_walks : std::max<uint64_t>(threads * 4, 4096);
-        const int cus = num_cus();
-        // enough items to keep every CU busy
-        while (iw > (uint64_t)threads && (n_walks + iw - 1) / iw < (uint64_t)cus * 2) iw /= 2;
-        const int64_t n_items = (int64_t)((n_walks + iw - 1) / iw);
-        MW_REQUIRE(n_items < (1ll << 31), MW_ELIMIT, "too many walks for one launch");
-        const size_t lds = p.form == FORM_TGLOBAL ? 16 : (size_t)p.table_words * 4;
-        const int blocks = (int)std::min<int64_t>(n_items, (int64_t)cus * blocks_per_cu(lds));
-        allow_large_lds();
-        seed_kernel<<<1, 1, 0, st>>>(seed_dev, seed);
-        walk_kernel<<<blocks, threads, lds, st>>>(dcube, nullptr, (int32_t)n_items, iw, item_counter, seed_dev,
-                                                   L.groups, step_total);
-        MW_HIP(hipGetLastError());
-        MW_HIP(hipFreeAsync(scratch, st));
+        MW_HIP(hipFreeAsync(scr, st));
+        MW_REQUIRE(ok, MW_EINVAL, "permittivity outside [1e-3, 1e3]");
+    });
+}
+
+extern "C" mw_status mw_transition_noalloc(const float* eps, int32_t n_cells, int32_t lattice, uint64_t n_walks,
+                                           uint64_t first_walk, uint64_t seed, uint32_t cube_index,
+                                           int32_t* hit_idx, int32_t* steps, void* stream) {
+    return guarded([&] {
+        validate_cube(n_cells, lattice);
+        if (n_walks == 0) return;
+        MW_REQUIRE(eps && hit_idx, MW_EINVAL, "eps and hit_idx are required");
+        const Plan p = plan_cube(n_cells, lattice, 0);
+        const size_t need = transition_scratch_bytes(p);
+        MW_REQUIRE(need <= NOALLOC_SCRATCH_BYTES, MW_ELIMIT,
+                   "cube of %d cells needs %zu bytes of scratch; the static scratch holds %zu", n_cells, need,
+                   NOALLOC_SCRATCH_BYTES);
+        char* scr = noalloc_scratch();
+        const bool ok = transition_enqueue(p, eps, n_cells, lattice, n_walks, first_walk, seed, cube_index, hit_idx,
+                                           steps, (hipStream_t)stream, scr);
+        MW_REQUIRE(ok, MW_EINVAL, "permittivity outside [1e-3, 1e3]");
     });
 }
 

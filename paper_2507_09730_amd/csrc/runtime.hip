@@ -123,5 +123,7 @@ extern "C" mw_status mw_init(int32_t device) {
         MW_HIP(hipGetDeviceCount(&count));
         MW_REQUIRE(device >= 0 && device < count, MW_EINVAL, "device %d out of range (%d devices)", device, count);
         MW_HIP(hipSetDevice(device));
+        // the device address of mw_transition_noalloc's static scratch
+        (void)mw::noalloc_scratch();
     });
 }
