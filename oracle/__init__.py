@@ -221,9 +221,12 @@ STAT_KEYS = ("walks", "hops", "micro_steps", "cls_uniform", "cls_stratified", "c
 
 
 def frw_extract(st, master, n_walks, seed=0, first_walk=0, n_cells=16, hybrid=1,
-                abs_tol_rel=1e-6, threads=1, scores=False, expand=1.0, kernel_limits=False):
+                abs_tol_rel=1e-6, threads=1, scores=False, expand=1.0, kernel_limits=False, gauss_is=0.0):
     """Alg. 1: capacitance row (fF, last entry env) and standard errors.
     expand > 1: MicroWalk-E transitions with that expansion factor.
+    gauss_is > 0: importance sampling of the Gaussian-surface point over
+    patches of edge at most gauss_is x g, each weighted by its area times the
+    first-transition kernel sum K at its centre (0: uniform by area).
     Transition cubes are the largest conductor-free cubes (expanded by the
     MicroWalk-E rule when expand > 1).  kernel_limits=True reproduces the GPU
     kernel's capacity rule instead (a cube is halved while more than 16
@@ -238,7 +241,7 @@ def frw_extract(st, master, n_walks, seed=0, first_walk=0, n_cells=16, hybrid=1,
     stats = np.zeros(13, dtype=np.uint64)
     rc = lib().mwo_frw_extract(*args, I32(master), U64(n_walks), U64(first_walk), U64(seed),
                                I32(n_cells), I32(hybrid), DBL(abs_tol_rel), DBL(expand),
-                               I32(1 if kernel_limits else 0), I32(threads),
+                               I32(1 if kernel_limits else 0), DBL(gauss_is), I32(threads),
                                _p(row), _p(se), _p(nets), _p(w), _p(stats))
     if rc:
         raise RuntimeError("oracle frw_extract failed (%d)" % rc)

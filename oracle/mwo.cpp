@@ -870,10 +870,23 @@ struct GFace {
     double area;
 };
 
+// Importance-sampling patch of G (reading of the importance sampling of
+// Alg. 1's first transition, applied to the Gaussian-surface point): a
+// rectangle of a face, its area, its weight q = area x K(centre) (K the
+// first-transition kernel sum at the patch centre) and the weight factor
+// Q area / q (Q = sum of q) that keeps the estimator unbiased.
+struct GPatch {
+    int face;
+    double lo[3], hi[3];
+    double area, q, factor;
+};
+
 struct Gauss {
     double g;
     std::vector<GFace> faces;
     double area;
+    std::vector<GPatch> patches;  // empty: uniform-area sampling
+    double Q = 0;
 };
 
 static bool in_grown_open(const Box& b, double g, const double x[3]) {
@@ -984,35 +997,17 @@ struct FrwParams {
     bool kernel_limits = false;  // reproduce the GPU kernel's cube halving (tests only)
 };
 
-bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P, TableCache& TC, uint64_t walk,
-              int* net_out, double* omega_out, WalkStats& st) {
-    int n = P.n;
-    // GaussianSurfaceSampling(G)
-    uint32_t w0 = rng_word(P.seed, 0, walk, PURPOSE_GAUSS, 0);
-    uint32_t w1 = rng_word(P.seed, 0, walk, PURPOSE_GAUSS, 1);
-    uint32_t w2 = rng_word(P.seed, 0, walk, PURPOSE_GAUSS, 2);
-    double xa = u01(w0) * G.area, cum = 0;
-    size_t fi = G.faces.size() - 1;
-    for (size_t f = 0; f < G.faces.size(); ++f) {
-        cum += G.faces[f].area;
-        if (xa < cum) {
-            fi = f;
-            break;
-        }
-    }
-    const GFace& F = G.faces[fi];
-    double r[3];
-    int t0 = (F.axis + 1) % 3, t1 = (F.axis + 2) % 3;
-    int ta = std::min(t0, t1), tb = std::max(t0, t1);
-    r[F.axis] = F.plane;
-    r[ta] = F.lo[ta] + u01(w1) * (F.hi[ta] - F.lo[ta]);
-    r[tb] = F.lo[tb] + u01(w2) * (F.hi[tb] - F.lo[tb]);
-
-    // FirstTransition(r): cube centred on G touching the master.
+// FirstTransition(r) kernel: the first cube centred at r on face F of G (it
+// touches the master), its branch (Fig. 4 reading), and the flux weights
+// w_b of its boundary nodes along the outward normal (Sec. II-A: the
+// normal derivative of the discrete SGF by a centred difference).  Returns
+// K = sum |w_b|, or a negative value when no valid cube exists.
+double first_weights(const Structure& S, const Gauss& G, const GFace& F, const double r[3], const FrwParams& P,
+                     TableCache& TC, Cube& C, std::vector<double>& w, int* branch_out) {
+    const int n = P.n;
     int a = F.axis;
     double R = cube_half_size(S, r, std::min(structure_dist(S, r, nullptr), G.g), P.kernel_limits);
-    if (R <= 0) return false;
-    Cube C;
+    if (R <= 0) return -1.0;
     build_cube(S, r, R, n, C);
     int branch, s;
     std::vector<uint64_t> seq;
@@ -1033,24 +1028,106 @@ bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P
         s = a;
         seq = homogenised_codes(C, a);
     }
-    st.first_branch[branch]++;
+    *branch_out = branch;
     auto FT = first_table(TC, n, s, a, seq);
-    if (!FT) return false;
+    if (!FT) return -1.0;
     // flux stencil along the outward normal
     const std::vector<double>& Pout = F.side ? FT->Pp : FT->Pm;
     const std::vector<double>& Pin = F.side ? FT->Pm : FT->Pp;
     double Gout = F.side ? FT->Gp : FT->Gm;
     double Gin = F.side ? FT->Gm : FT->Gp;
     size_t NB = FT->Pc.size();
-    std::vector<double> w(NB), aw(NB);
+    w.assign(NB, 0.0);
     double K = 0;
     for (size_t b = 0; b < NB; ++b) {
         w[b] = (Gout * (FT->Pc[b] - Pout[b]) + Gin * (Pin[b] - FT->Pc[b])) / (2 * C.h);
-        aw[b] = std::fabs(w[b]);
-        K += aw[b];
+        K += std::fabs(w[b]);
     }
+    return K;
+}
+
+// Importance-sampling patches of G: every rectangle cut into nu x nv equal
+// patches with edges at most edge (nu = ceil(length / edge)), each weighted
+// by q = area x K(patch centre).
+bool build_patches(const Structure& S, Gauss& G, double edge, const FrwParams& P, TableCache& TC) {
+    G.patches.clear();
+    G.Q = 0;
+    Cube C;
+    std::vector<double> w;
+    for (size_t f = 0; f < G.faces.size(); ++f) {
+        const GFace& F = G.faces[f];
+        const int t0 = (F.axis + 1) % 3, t1 = (F.axis + 2) % 3;
+        const int ta = std::min(t0, t1), tb = std::max(t0, t1);
+        const double la = F.hi[ta] - F.lo[ta], lb = F.hi[tb] - F.lo[tb];
+        const int nu = std::max(1, (int)std::ceil(la / edge)), nv = std::max(1, (int)std::ceil(lb / edge));
+        for (int j = 0; j < nv; ++j)
+            for (int i = 0; i < nu; ++i) {
+                GPatch Pt;
+                Pt.face = (int)f;
+                Pt.lo[F.axis] = Pt.hi[F.axis] = F.plane;
+                Pt.lo[ta] = F.lo[ta] + la * i / nu;
+                Pt.hi[ta] = F.lo[ta] + la * (i + 1) / nu;
+                Pt.lo[tb] = F.lo[tb] + lb * j / nv;
+                Pt.hi[tb] = F.lo[tb] + lb * (j + 1) / nv;
+                Pt.area = (Pt.hi[ta] - Pt.lo[ta]) * (Pt.hi[tb] - Pt.lo[tb]);
+                double c[3];
+                for (int q = 0; q < 3; ++q) c[q] = 0.5 * (Pt.lo[q] + Pt.hi[q]);
+                c[F.axis] = F.plane;
+                int br;
+                const double K = first_weights(S, G, F, c, P, TC, C, w, &br);
+                if (!(K > 0)) return false;
+                Pt.q = Pt.area * K;
+                G.Q += Pt.q;
+                G.patches.push_back(Pt);
+            }
+    }
+    for (GPatch& Pt : G.patches) Pt.factor = G.Q * Pt.area / Pt.q;
+    return true;
+}
+
+bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P, TableCache& TC, uint64_t walk,
+              int* net_out, double* omega_out, WalkStats& st) {
+    int n = P.n;
+    // GaussianSurfaceSampling(G): a rectangle by area (uniform on G) or, with
+    // importance sampling, a patch by its weight q; then a uniform point on it
+    uint32_t w0 = rng_word(P.seed, 0, walk, PURPOSE_GAUSS, 0);
+    uint32_t w1 = rng_word(P.seed, 0, walk, PURPOSE_GAUSS, 1);
+    uint32_t w2 = rng_word(P.seed, 0, walk, PURPOSE_GAUSS, 2);
+    const bool is = !G.patches.empty();
+    const size_t cnt = is ? G.patches.size() : G.faces.size();
+    double xa = u01(w0) * (is ? G.Q : G.area), cum = 0;
+    size_t fi = cnt - 1;
+    for (size_t f = 0; f < cnt; ++f) {
+        cum += is ? G.patches[f].q : G.faces[f].area;
+        if (xa < cum) {
+            fi = f;
+            break;
+        }
+    }
+    const GFace& F = G.faces[is ? G.patches[fi].face : fi];
+    const double* lo = is ? G.patches[fi].lo : F.lo;
+    const double* hi = is ? G.patches[fi].hi : F.hi;
+    const double factor = is ? G.patches[fi].factor : G.area;
+    double r[3];
+    int t0 = (F.axis + 1) % 3, t1 = (F.axis + 2) % 3;
+    int ta = std::min(t0, t1), tb = std::max(t0, t1);
+    r[F.axis] = F.plane;
+    r[ta] = lo[ta] + u01(w1) * (hi[ta] - lo[ta]);
+    r[tb] = lo[tb] + u01(w2) * (hi[tb] - lo[tb]);
+
+    // FirstTransition(r): cube centred on G touching the master; the next
+    // point b ~ |w_b| / K, weight eps0 K sign(w_b) times |G| (uniform) or
+    // the patch factor Q area / q (importance sampling).
+    Cube C;
+    std::vector<double> w;
+    int branch;
+    const double K = first_weights(S, G, F, r, P, TC, C, w, &branch);
+    if (!(K > 0)) return false;
+    st.first_branch[branch]++;
+    std::vector<double> aw(w.size());
+    for (size_t b = 0; b < w.size(); ++b) aw[b] = std::fabs(w[b]);
     int b = sample_index(aw, K, rng_word(P.seed, 0, walk, PURPOSE_FIRST, 0));
-    double omega = EPS0 * G.area * K * (w[b] > 0 ? 1.0 : -1.0);
+    double omega = EPS0 * factor * K * (w[b] > 0 ? 1.0 : -1.0);
     int node[3];
     vertex_node_of_hit(n, b, node);
     // The walker's position is folded back into the window at symmetry
@@ -1369,8 +1446,8 @@ int mwo_gauss(const double* cond, int n_cond, int n_nets, const double* win, con
 int mwo_frw_extract(const double* cond, int n_cond, int n_nets, const double* diel, int n_diel,
                     const double* layer_z0, const double* layer_eps, int n_layers, const double* win,
                     const int32_t* bc, int master, uint64_t n_walks, uint64_t first_walk, uint64_t seed, int n,
-                    int hybrid, double abs_tol_rel, double expand, int kernel_limits, int threads, double* row,
-                    double* se, int32_t* score_net, double* score_w, uint64_t* stats) {
+                    int hybrid, double abs_tol_rel, double expand, int kernel_limits, double gauss_is, int threads,
+                    double* row, double* se, int32_t* score_net, double* score_w, uint64_t* stats) {
     if (n < 4 || n % 2 || n_walks < 2) return -1;
     Structure S = make_structure(cond, n_cond, n_nets, diel, n_diel, layer_z0, layer_eps, n_layers, win, bc);
     Gauss G;
@@ -1379,6 +1456,8 @@ int mwo_frw_extract(const double* cond, int n_cond, int n_nets, const double* di
     for (int a = 0; a < 3; ++a) diag += (S.whi[a] - S.wlo[a]) * (S.whi[a] - S.wlo[a]);
     FrwParams P{n, hybrid, abs_tol_rel * std::sqrt(diag), seed, expand < 1.0 ? 1.0 : expand, kernel_limits != 0};
     TableCache TC;
+    // importance sampling over G: patches of edge at most gauss_is x g
+    if (gauss_is > 0 && !build_patches(S, G, gauss_is * G.g, P, TC)) return -4;
     std::vector<int32_t> nets(n_walks);
     std::vector<double> om(n_walks);
     if (threads < 1) threads = 1;
