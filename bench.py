@@ -2,10 +2,15 @@
 """Benchmark of FRW capacitance extraction with MicroWalk transitions on one
 MI355X.
 
-Workload (one step): frw_extract on the crossing-wire structure (2x2x1 um
-grounded window, four 100x100 nm wires on two layers, 20 nm eps 7.0 coatings,
-background eps 3.9 / 2.7), master net 0, 16^3-cell transition cubes, 1e6 walks,
-a fresh seed per step.  Prints one JSON line (see the keys below).
+Workload (one step): frw_extract on the large interconnect window (20x20x2 um,
+three metal layers of 64 wires, layered eps 3.9 / 2.7 dielectric, 20 nm eps 7.0
+coatings, eps 25 gap fills; 192 nets), the middle-layer wire nearest the window
+centre as master, 16^3-cell transition cubes, walked until 3 SE / |C_mm| <= 1 %
+(Alg. 1 with the stopping rule checked every convergence batch), a fresh seed
+per step.  The structure and its transition-table cache are resident on the
+device when the timed region starts.  Prints one JSON line (keys below); the
+extras compare the crossing-wire workload, the single-cube and batched
+MicroWalk workloads, the plain forms, MicroWalk-E and serving.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -26,11 +31,11 @@ METRIC = "micro-steps/s + walks/s at 1% 3σ cap error; p50/p99 latency vs plain"
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # Algorithmic lane-op slots of one MicroWalk step (Alg. 3 loop body): a quarter
 # of a Philox4x32-10 block (10 rounds x (2 quarter-rate 32x32->64 products =
-# 8 slots + 2 three-input xors) / 4 = 25), five threshold compares, one index
-# update and one boundary test.
-MW_STEP_SLOTS = 32
+# 8 slots + 2 three-input xors) / 4 = 25) and about 15 for the direction
+# (five threshold compares), the move and the boundary test: 40 slots.
+MW_STEP_SLOTS = 40
 WALKER_SRC = os.path.join(ROOT, "paper_2507_09730_amd", "csrc", "frw.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "frw_walk_kernel_c2_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "frw_walk_kernel_c4_traffic.txt")
 
 
 def _sha(path):
@@ -55,18 +60,111 @@ def _traffic():
         return None
 
 
-def cpu_baseline(st, walks, seed):
-    import oracle
+def _progress(msg):
+    """One line on stderr per finished section (the JSON result goes to stdout)."""
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
+
+
+def _cores():
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(cores, 64))
+    return max(1, min(cores, 64))
+
+
+def cpu_baseline(st, master, walks_all, walks_one, seed):
+    """The oracle on the same workload, a bounded sample of walks: all host
+    cores (threads over walk ranges) and one thread."""
+    import oracle
+    cores = _cores()
     oracle.build()
     t0 = time.perf_counter()
-    r = oracle.frw_extract(st, 0, walks, seed=seed, threads=cores)
+    r = oracle.frw_extract(st, master, walks_all, seed=seed, threads=cores)
     dt = time.perf_counter() - t0
-    return {"value": walks / dt, "unit": "walks/s", "cores": cores, "kind": "oracle",
-            "sample": "%d walks of the same workload (binary64 C++ oracle, %d threads over walk "
-                      "ranges), %.1f s; micro-steps/s %.4g" % (walks, cores, dt,
-                                                                r["stats"]["micro_steps"] / dt)}, r
+    t1 = time.perf_counter()
+    r1 = oracle.frw_extract(st, master, walks_one, seed=seed + 1, threads=1)
+    dt1 = time.perf_counter() - t1
+    return {"value": walks_all / dt, "unit": "walks/s", "cores": cores, "kind": "oracle",
+            "sample": "%d walks of the same workload and master, binary64 C++ oracle, %d threads over "
+                      "walk ranges, %.1f s (%.4g micro-steps/s); one thread: %d walks in %.1f s"
+                      % (walks_all, cores, dt, r["stats"]["micro_steps"] / dt, walks_one, dt1),
+            "micro_steps_per_s": r["stats"]["micro_steps"] / dt,
+            "one_thread_walks_per_s": walks_one / dt1,
+            "one_thread_micro_steps_per_s": r1["stats"]["micro_steps"] / dt1}, r
+
+
+def agreement(rows, ses, r_or):
+    """Mean of the timed GPU rows against an oracle row, on the entries both
+    resolve (|C| > 4 SE), in combined standard errors."""
+    g_row = np.mean(rows, axis=0)
+    g_se = np.sqrt(np.mean(np.square(ses), axis=0) / len(rows))
+    o_row, o_se = np.asarray(r_or["row"]), np.asarray(r_or["se"])
+    both = (np.abs(g_row) > 4 * g_se) & (np.abs(o_row) > 4 * o_se)
+    z = np.abs(g_row - o_row)[both] / np.hypot(g_se, o_se)[both]
+    return {"entries_compared": int(both.sum()), "max_z": float(z.max()) if z.size else None,
+            "mean_z2": float(np.mean(z ** 2)) if z.size else None}
+
+
+def c1_single_cube(mw, W, reps=20):
+    """Single-cube MicroWalk (8^3 cells, eps 3.9 with an eps 7.0 block, 1e5
+    walks from the centre): one mw_transition call per repetition."""
+    import torch
+    eps_h = W.c1_eps()
+    eps = torch.as_tensor(eps_h).cuda()
+    hits = torch.empty(100000, dtype=torch.int32, device="cuda")
+    steps = torch.empty(100000, dtype=torch.int32, device="cuda")
+    mw.mw_transition(eps, 100000, seed=0, hits=hits, steps=steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(reps):
+        mw.mw_transition(eps, 100000, seed=k, hits=hits, steps=steps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    n_steps = int(steps.sum(dtype=torch.int64))
+    return {"workload": "8^3-cell cube, eps 3.9 with an eps 7.0 block at cells [1,4)x[1,5)x[3,8), "
+                        "1e5 walks from the centre (one mw_transition call)",
+            "ms_per_call": dt * 1e3, "walks_per_s": 1e5 / dt, "micro_steps_per_s": n_steps / dt,
+            "mean_steps": n_steps / 1e5}
+
+
+def cpu_baseline_c1(W):
+    """The oracle's MicroWalk on the single-cube workload (one thread)."""
+    import oracle
+    t0 = time.perf_counter()
+    _, so = oracle.microwalk(W.c1_eps(), 0, 100000, seed=1)
+    dt = time.perf_counter() - t0
+    return {"walks_per_s": 1e5 / dt, "micro_steps_per_s": float(so.sum()) / dt, "threads": 1}
+
+
+def c2_figures(mw, W, steps=20, walks=1000000, n_cells=16):
+    """Crossing wires (4 nets), 1e6 walks per extraction: the persistent
+    walker and the plain form (one walker launch per transition round)."""
+    st = W.c2_structure()
+    h = mw.StructureHandle(st)
+    out, rows, ses = {}, [], []
+    for plain, reps in ((0, steps), (1, 5)):
+        mw.frw_extract(h, 0, walks, seed=9000, n_cells=n_cells, plain=plain)
+        t0 = time.perf_counter()
+        wsum = ssum = wk = launches = 0
+        for k in range(reps):
+            r = mw.frw_extract(h, 0, walks, seed=k, n_cells=n_cells, plain=plain)
+            s = r["stats"]
+            wsum += s["walks"]
+            ssum += s["micro_steps"]
+            wk += s["walker_seconds"]
+            launches += s["launches"]
+            if not plain:
+                rows.append(r["row"])
+                ses.append(r["se"])
+        dt = time.perf_counter() - t0
+        out["plain" if plain else "persistent"] = {
+            "ms_per_extraction": dt / reps * 1e3, "walks_per_s": wsum / dt, "micro_steps_per_s": ssum / dt,
+            "walker_ms_per_extraction": wk / reps * 1e3, "walker_launches_per_extraction": launches / reps,
+            "roofline_frac": ssum * MW_STEP_SLOTS / wk / PEAK_LANE_OPS}
+    h.close()
+    out["workload"] = "crossing wires 2x2x1 um, 4 nets, master 0, %d^3-cell cubes, %d walks per extraction" % (
+        n_cells, walks)
+    out["rel_3sigma_Cmm"] = float(np.mean([3 * e[0] / r[0] for r, e in zip(rows, ses)]))
+    out["persistent_speedup_over_plain"] = out["plain"]["ms_per_extraction"] / out["persistent"]["ms_per_extraction"]
+    return out, rows, ses
 
 
 def batched_vs_plain(mw, W, reps=5):
@@ -140,27 +238,26 @@ def microwalk_e(mw, W, st, walks, n_cells, steps=5, master=0):
     return out
 
 
-def c4_to_target(mw, W, target=0.01, budget=100000000, reps=3):
-    """The large interconnect (C4: 20x20x2 um, 192 wires) walked until the
-    master's self capacitance reaches 3 SE / |C_mm| <= target (Alg. 1 with
-    the stopping rule on the running estimate): walks, time and throughput
-    of each run, with the error reached."""
-    st = W.c4_structure()
-    m = st.meta["master"]
-    h = mw.StructureHandle(st)
-    mw.frw_extract(h, m, 1000000, seed=800)  # table cache warm, as in a long-running process
-    runs = []
-    for k in range(reps):
+def c4_plain_vs_persistent(mw, h, master, walks, reps=3):
+    """The large interconnect at a fixed walk count (the headline's mean walks
+    to 1 %): persistent walker launches against the plain form."""
+    out = {}
+    for plain in (0, 1):
+        mw.frw_extract(h, master, walks, seed=700, plain=plain)
         t0 = time.perf_counter()
-        r = mw.frw_extract(h, m, budget, seed=810 + k, target_rel_3sigma=target)
-        dt = time.perf_counter() - t0
-        s = r["stats"]
-        runs.append({"walks": s["walks"], "ms": dt * 1e3, "walks_per_s": s["walks"] / dt,
-                     "micro_steps_per_s": s["micro_steps"] / dt,
-                     "rel_3sigma_reached": float(3 * r["se"][m] / abs(r["row"][m])), "C_mm": float(r["row"][m])})
-    h.close()
-    return {"workload": "C4 interconnect, master %d, n = 16, stop at 3 SE / |C_mm| <= %g" % (m, target),
-            "runs": runs, "median_walks_per_s": float(np.median([q["walks_per_s"] for q in runs]))}
+        wk = 0.0
+        launches = 0
+        for k in range(reps):
+            r = mw.frw_extract(h, master, walks, seed=710 + k, plain=plain)
+            wk += r["stats"]["walker_seconds"]
+            launches += r["stats"]["launches"]
+        dt = (time.perf_counter() - t0) / reps
+        out["plain" if plain else "persistent"] = {"ms_per_extraction": dt * 1e3, "walks_per_s": walks / dt,
+                                                   "walker_ms": wk / reps * 1e3,
+                                                   "walker_launches": launches / reps}
+    out["walks"] = walks
+    out["persistent_speedup_over_plain"] = out["plain"]["ms_per_extraction"] / out["persistent"]["ms_per_extraction"]
+    return out
 
 
 def fig3a(mw, W, ns=(4, 8, 12, 16, 20, 24, 28, 32), count=500, walks=4096):
@@ -192,12 +289,26 @@ def fig3a(mw, W, ns=(4, 8, 12, 16, 20, 24, 28, 32), count=500, walks=4096):
             "per_n": rows, "loglog_slope": slope, "micro_steps_per_s": total_steps / total_s}
 
 
-def serving(mw, W, n_req=300, loads=(0.5, 0.8, 1.2)):
+def serving(mw, W, n_req=2000, loads=(0.5, 0.8, 1.2)):
     """Request stream built like the serving workload (windows of 4-200
     conductors, budgets 1e5-1e7 walks, Poisson arrivals at load x the serial
-    plain service rate): served with continuous batching vs serial plain
-    extraction (FIFO) on the same GPU, at each load."""
+    plain service rate): served with continuous batching against serial plain
+    extraction on the same GPU.  The serial plain latencies are a FIFO queue
+    model over the measured per-request service times (structure upload and
+    frw_extract, one request at a time): serial service does not depend on
+    the arrival pattern, so the model gives the latency a serial server
+    would have on the same arrival trace.  Both forms run after a warm-up
+    pass, with the transition tables of the windows cached."""
     reqs = W.c5_requests(n_req)
+    # warm-up: every request once through the server at full rate, so that
+    # the serial and the served runs below both find the transition tables
+    # of these windows in the cache (a long-running process)
+    srv = mw.Server(8 << 30)
+    t0 = time.perf_counter()
+    for t in [srv.submit(st, m, b, seed) for st, m, b, seed in reqs]:
+        srv.wait(t)
+    srv.close()
+    _progress("serving: warm-up pass over %d requests in %.1f s" % (n_req, time.perf_counter() - t0))
     service = []
     for st, m, b, seed in reqs:
         t0 = time.perf_counter()
@@ -206,10 +317,12 @@ def serving(mw, W, n_req=300, loads=(0.5, 0.8, 1.2)):
         h.close()
         service.append(time.perf_counter() - t0)
     service = np.array(service)
+    _progress("serving: serial plain pass over %d requests in %.1f s" % (n_req, service.sum()))
     mu = n_req / service.sum()
     walks = float(sum(r[2] for r in reqs))
     out = {"workload": "%d requests, 4-200 conductors, budgets 1e5-1e7 (%.3g walks), Poisson "
-                       "arrivals at load x serial plain service rate (%.2f req/s)" % (n_req, walks, mu)}
+                       "arrivals at load x serial plain service rate (%.2f req/s)" % (n_req, walks, mu),
+           "plain_latency": "FIFO model over measured serial service times"}
     for load in loads:
         lam = load * mu
         rng = np.random.default_rng(55)
@@ -232,6 +345,7 @@ def serving(mw, W, n_req=300, loads=(0.5, 0.8, 1.2)):
         stats = srv.stats()
         srv.close()
         lat = np.array([r["latency"] for r in res])
+        _progress("serving load %.1f: %d requests in %.1f s" % (load, n_req, makespan))
         out["load_%.1f" % load] = {
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "plain_p50_ms": float(np.percentile(lat_plain, 50) * 1e3),
@@ -241,17 +355,49 @@ def serving(mw, W, n_req=300, loads=(0.5, 0.8, 1.2)):
     return out
 
 
+def headline(mw, W, steps, warmup, target):
+    """The large interconnect walked to 3 SE / |C_mm| <= target, `steps`
+    timed extractions after `warmup` untimed ones (the first builds the
+    transition tables the structure needs)."""
+    import torch
+    st = W.c4_structure()
+    m = st.meta["master"]
+    h = mw.StructureHandle(st)
+    budget = 100000000
+    for i in range(warmup):
+        mw.frw_extract(h, m, budget, seed=10000 + i, target_rel_3sigma=target)
+    torch.cuda.synchronize()
+    acc = {"walks": 0, "micro_steps": 0, "launches": 0, "walker_s": 0.0, "hops": 0, "rel": [], "rows": [],
+           "ses": [], "halved": 0}
+    t0 = time.perf_counter()
+    for k in range(steps):
+        r = mw.frw_extract(h, m, budget, seed=k, target_rel_3sigma=target)
+        s = r["stats"]
+        acc["walks"] += s["walks"]
+        acc["micro_steps"] += s["micro_steps"]
+        acc["launches"] += s["launches"]
+        acc["walker_s"] += s["walker_seconds"]
+        acc["hops"] += s["hops"]
+        acc["halved"] += s["cube_halved"]
+        acc["rel"].append(3 * r["se"][m] / abs(r["row"][m]))
+        acc["rows"].append(r["row"])
+        acc["ses"].append(r["se"])
+    torch.cuda.synchronize()
+    acc["dt"] = time.perf_counter() - t0
+    return st, m, h, acc
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--walks", type=int, default=1000000)
-    ap.add_argument("--n-cells", type=int, default=16)
-    ap.add_argument("--cpu-walks", type=int, default=900000)
+    ap.add_argument("--target", type=float, default=0.01, help="3 SE / |C_mm| at which an extraction stops")
+    ap.add_argument("--cpu-walks", type=int, default=4000, help="oracle sample, all host cores")
+    ap.add_argument("--cpu-walks-one", type=int, default=300, help="oracle sample, one thread")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and serving comparisons")
-    ap.add_argument("--serving-requests", type=int, default=300,
+    ap.add_argument("--no-extras", action="store_true", help="skip the comparison workloads")
+    ap.add_argument("--serving-requests", type=int, default=2000,
                     help="requests of the serving comparison (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only copy a device buffer of this size 3 times (calibrates the rocprofv3 "
@@ -262,7 +408,6 @@ def main():
               "(walk ranges would shard across GPUs with one fp64 all-reduce of the per-net "
               "sums; not implemented).", file=sys.stderr)
         sys.exit(2)
-
 
     import torch
 
@@ -281,69 +426,62 @@ def main():
     import workloads as W
 
     mw.mw_init(0)
-    st = W.c2_structure()
-    h = mw.StructureHandle(st)
-    for i in range(args.warmup):
-        mw.frw_extract(h, 0, args.walks, seed=10000 + i, n_cells=args.n_cells)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    walks = steps = launches = 0
-    walker_s = 0.0
-    rel = []
-    rows, ses = [], []
-    for k in range(args.steps):
-        r = mw.frw_extract(h, 0, args.walks, seed=k, n_cells=args.n_cells)
-        rows.append(r["row"])
-        ses.append(r["se"])
-        s = r["stats"]
-        walks += s["walks"]
-        steps += s["micro_steps"]
-        launches += s["launches"]
-        walker_s += s["walker_seconds"]
-        rel.append(3 * r["se"][0] / r["row"][0])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    value = walks / dt
+    st, m, h, acc = headline(mw, W, args.steps, args.warmup, args.target)
+    dt = acc["dt"]
     # roofline of the walker kernel (dominant kernel): algorithmic MicroWalk
-    # slots per launch / measured launch duration
-    achieved = steps * MW_STEP_SLOTS / walker_s / 1e12  # T lane-op slots/s
+    # slots of the timed launches / their summed duration (HIP events on the
+    # launch stream)
+    achieved = acc["micro_steps"] * MW_STEP_SLOTS / acc["walker_s"] / 1e12  # T lane-op slots/s
     peak = PEAK_LANE_OPS / 1e12
-    traffic = _traffic()
     out = {
-        "metric": METRIC, "value": value, "unit": "walks/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC, "value": acc["walks"] / dt, "unit": "walks/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "crossing wires 2x2x1 um, 4 nets, 20 nm eps-7 coatings, "
-                               "eps 3.9/2.7 layers, master 0, %d^3-cell cubes, %d walks/step"
-                               % (args.n_cells, args.walks),
-                   "walks_per_step": args.walks, "n_cells": args.n_cells, "hybrid": 1},
-        "micro_steps_per_s": steps / dt,
-        "rel_3sigma_Cmm": float(np.mean(rel)),
-        "walker_kernel_ms_per_step": walker_s / args.steps * 1e3,
-        "walker_launches_per_step": launches / args.steps,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved / peak, "traffic": traffic},
+        "config": {"workload": "large interconnect 20x20x2 um: 3 metal layers x 64 wires (192 nets), "
+                               "eps 3.9/2.7 dielectric stack, 20 nm eps-7 coatings, eps-25 gap fills; "
+                               "master net %d; 16^3-cell cubes; each step walks until 3 SE/|C_mm| <= %g"
+                               % (m, args.target),
+                   "target_rel_3sigma": args.target, "n_cells": 16, "hybrid": 1, "master": m},
+        "micro_steps_per_s": acc["micro_steps"] / dt,
+        "walks_per_step": acc["walks"] / args.steps,
+        "ms_to_target": dt / args.steps * 1e3,
+        "rel_3sigma_reached": float(np.mean(acc["rel"])),
+        "hops_per_walk": acc["hops"] / acc["walks"],
+        "cube_halved": acc["halved"],
+        "walker_kernel_ms_per_step": acc["walker_s"] / args.steps * 1e3,
+        "walker_launches_per_step": acc["launches"] / args.steps,
+        "roofline": {"bound": "alu", "kernel": "frw_walk_kernel", "achieved": achieved, "peak": peak,
+                     "unit": "TOP/s", "frac": achieved / peak, "traffic": _traffic()},
     }
+    extras_rows = {}
+    _progress("headline: %d extractions to target in %.2f s" % (args.steps, dt))
     if not args.no_extras:
+        out["c4_plain_vs_persistent"] = c4_plain_vs_persistent(mw, h, m, int(round(out["walks_per_step"] / 1e5)) * 100000)
+        _progress("c4 plain vs persistent")
+        out["c2"], extras_rows["c2_rows"], extras_rows["c2_ses"] = c2_figures(mw, W)
+        _progress("c2")
+        out["c1"] = c1_single_cube(mw, W)
         out["batched"] = batched_vs_plain(mw, W)
+        _progress("c1, batched")
         out["fig3a"] = fig3a(mw, W)
-        out["microwalk_e"] = microwalk_e(mw, W, st, args.walks, args.n_cells)
-        c4 = W.c4_structure()
-        out["microwalk_e_c4"] = microwalk_e(mw, W, c4, args.walks, args.n_cells, master=c4.meta["master"])
-        out["c4_to_1pct"] = c4_to_target(mw, W)
+        _progress("fig3a")
+        out["microwalk_e"] = microwalk_e(mw, W, W.c2_structure(), 1000000, 16)
+        out["microwalk_e_c4"] = microwalk_e(mw, W, st, 1000000, 16, master=m)
+        _progress("microwalk-e")
         if args.serving_requests > 0:
             out["serving"] = serving(mw, W, args.serving_requests)
+    h.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], r_or = cpu_baseline(st, args.cpu_walks, seed=7)
+        out["cpu_baseline"], r_or = cpu_baseline(st, m, args.cpu_walks, args.cpu_walks_one, seed=7)
         # accuracy beside throughput: the timed extractions' mean row against
-        # the oracle's row, entry by entry, in combined standard errors
-        g_row = np.mean(rows, axis=0)
-        g_se = np.sqrt(np.mean(np.square(ses), axis=0) / len(rows))
-        den = np.hypot(g_se, r_or["se"])
-        z = np.where(den > 0, np.abs(g_row - r_or["row"]) / np.where(den > 0, den, 1.0), 0.0)
-        out["oracle_agreement"] = {"gpu_row": g_row.tolist(), "gpu_se": g_se.tolist(),
-                                   "oracle_row": list(map(float, r_or["row"])),
-                                   "oracle_se": list(map(float, r_or["se"])), "max_z": float(z.max())}
+        # the oracle's row
+        out["oracle_agreement"] = agreement(acc["rows"], acc["ses"], r_or)
+        _progress("cpu baseline")
+        if not args.no_extras:
+            import oracle
+            out["c1"]["oracle"] = cpu_baseline_c1(W)
+            r2 = oracle.frw_extract(W.c2_structure(), 0, 200000, seed=7, threads=_cores())
+            out["c2"]["oracle_agreement"] = agreement(extras_rows["c2_rows"], extras_rows["c2_ses"], r2)
     print(json.dumps(out))
 
 

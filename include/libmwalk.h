@@ -132,10 +132,11 @@ mw_status mw_transition_noalloc(const float* eps, int32_t n_cells, int32_t latti
 /* Tuning knobs of the batched MicroWalk launch.  Zero fields mean "use the
  * autotuned or default value". */
 typedef struct {
-    int32_t tile_form;    /* 1 threshold rows in LDS, 2 cell-code tile in LDS */
-    int32_t waves_per_wg; /* 1..16                                          */
-    int32_t refill_every; /* steps between lane refills: 4, 8 or 16         */
-    int32_t item_walks;   /* walks per (cube, walk-range) work item         */
+    int32_t tile_form;      /* 1 threshold rows in LDS, 2 cell-code tile in LDS */
+    int32_t waves_per_wg;   /* 1..16                                          */
+    int32_t refill_every;   /* steps between lane refills: 4, 8 or 16         */
+    int32_t item_walks;     /* walks per (cube, walk-range) work item         */
+    int32_t walks_per_lane; /* interleaved walks per lane: 1, 2 or 4          */
 } mw_tune;
 
 /* ------------------------------------------------------------------------
@@ -161,15 +162,24 @@ mw_status mw_transition_batch(int32_t n_cubes, const float* eps_cat,
 
 /* Autotuner of the batched launch: times the batch's walk kernel under
  * candidate tunings (tile form, waves per workgroup, refill interval, walks
- * per work item; coordinate search) and writes the fastest to *best.  Later
- * mw_transition_batch calls with tune == NULL on a batch of the same shape
- * (cube-size histogram and walk-count scale) use it.  Writes hits/steps as a
- * side effect (with an internal seed).  Synchronous.                        */
+ * per work item, interleaved walks per lane; coordinate search) and writes
+ * the fastest to *best.  Later mw_transition_batch and mw_batch_plan_create
+ * calls with tune == NULL on a batch of the same shape (histogram of cube
+ * sizes in buckets of 4 cells and walk-count scale) use it.  When the
+ * environment variable MWALK_TUNE_CACHE names a file, tuned settings are
+ * kept there as JSON (per device architecture) and read by later processes.
+ * Writes hits/steps as a side effect (with an internal seed).  Synchronous. */
 mw_status mw_autotune_batch(int32_t n_cubes, const float* eps_cat,
                             const int64_t* eps_off, const int32_t* n_cells,
                             int32_t lattice, const uint64_t* n_walks,
                             const int64_t* out_off, int32_t* hits_cat,
                             int32_t* steps_cat, mw_tune* best, void* stream);
+
+/* The setting a batch call with tune == NULL would use for a batch of this
+ * shape (found = 1), from this process's autotuning or the MWALK_TUNE_CACHE
+ * file; found = 0 when there is none (defaults apply).  Host arrays.        */
+mw_status mw_tune_lookup(int32_t n_cubes, const int32_t* n_cells, const uint64_t* n_walks,
+                         int32_t lattice, mw_tune* out, int32_t* found);
 
 /* A batch prepared once (cube descriptors, work items, table buffers) and
  * captured as a HIP graph (counter reset, table preparation, walk kernels).
@@ -266,6 +276,20 @@ typedef struct {
                                  default 1e-6                               */
     uint64_t first_walk;      /* id of the first walk (resume point)         */
     uint64_t batch_walks;     /* walks per convergence check; 0 = auto      */
+    double gauss_is;          /* sampling of the Gaussian-surface point.  0
+                                 (default): uniform by area, weight factor
+                                 |G|.  > 0: importance sampling over G (the
+                                 first transition of Alg. 1 is importance
+                                 sampling with its weight): every surface
+                                 rectangle is cut into equal patches of edge
+                                 at most gauss_is * g, patch p is drawn with
+                                 probability q_p / Q, q_p = area_p K(c_p) / h
+                                 (the first-transition kernel sum at its
+                                 centre, computed once per extraction), the
+                                 point is uniform on it and the weight factor
+                                 is Q area_p / q_p.  The estimator keeps its
+                                 expectation; its variance drops where K
+                                 varies over G.  0 or in [0.05, 64].       */
 } frw_options;
 
 typedef struct {
@@ -318,6 +342,18 @@ mw_status frw_extract(mw_structure* s, int32_t master, uint64_t walk_budget,
                       uint64_t seed, const frw_options* options,
                       double* cap_row, double* stderr_row, frw_stats* stats,
                       int32_t* score_net, float* score_w);
+
+/* ------------------------------------------------------------------------
+ * frw_autotune — launch geometry of the FRW walker kernel: times the walker
+ * on `walks` walks of this extraction (walk ids options->first_walk on,
+ * Philox key seed) with 4, 6, 8, ... up to the most resident waves per CU
+ * that its LDS allows, and keeps the fastest for the lattice size and
+ * MicroWalk-E setting of the options; later extractions, matrix calls and
+ * servers use it (also across processes through MWALK_TUNE_CACHE).  The
+ * geometry changes no per-walk result.  *waves_per_cu receives the choice.
+ * Synchronous.                                                              */
+mw_status frw_autotune(mw_structure* s, int32_t master, uint64_t walks, uint64_t seed,
+                       const frw_options* options, int32_t* waves_per_cu);
 
 /* ------------------------------------------------------------------------
  * mw_sgf_table — one entry of the transition-table cache (the "analytical
@@ -374,17 +410,20 @@ mw_status frw_extract_matrix(mw_structure* s, int32_t n_masters,
  * Serving: a request loop over one device with continuous batching.
  *
  * mw_server_submit copies the structure description and returns a ticket.
- * A worker thread admits queued requests in arrival order while their device
- * footprint (structure, grid index, reduction partials, accumulators) fits
- * within hbm_budget_bytes, and runs rounds of a fixed walk capacity: the
- * longest-running admitted request gets up to half of it, the rest goes
- * to the requests with the fewest remaining walks first; each share is that
- * request's next walk ids (from 0).  All shares of a round run in one set of
- * kernel launches, one reduction launch and one result copy, so requests
- * that arrive while others run join at the next round and their work
- * overlaps on the device.  The server's own round buffers (per-walk scores
- * of one round, parked-walk queues; about 0.3 GB) are allocated at the
- * first round and are not counted in the budget.  A request completes
+ * A preparation thread takes queued requests in arrival order while their
+ * device footprint (structure, grid index, reduction partials, accumulators)
+ * fits within hbm_budget_bytes, and uploads each structure and builds its
+ * grid index on a stream of its own, while rounds run.  A round worker runs
+ * rounds of a fixed walk capacity over every prepared request: the
+ * longest-running one gets up to three quarters of it, the rest goes to the
+ * requests with the fewest remaining walks first, and capacity they leave
+ * goes back to the longest-running one; each share is that request's next
+ * walk ids (from 0).  All shares of a round run in one set of kernel
+ * launches, one reduction launch and one result copy, so requests that
+ * arrive while others run join at the next round and their work overlaps on
+ * the device.  The server's own round buffers (per-walk scores of one round,
+ * parked-walk queues; about 0.8 GB) are allocated at the first round and
+ * are not counted in the budget.  A request completes
  * when walk_budget walks have run or options->target_rel_3sigma is met
  * (checked after each of its rounds).  Per-walk results are those of
  * frw_extract(structure, master, walk_budget, seed, options) run alone; rows

@@ -69,7 +69,8 @@ def mw_init(device=0):
 
 class mw_tune(ctypes.Structure):
     _fields_ = [("tile_form", ctypes.c_int32), ("waves_per_wg", ctypes.c_int32),
-                ("refill_every", ctypes.c_int32), ("item_walks", ctypes.c_int32)]
+                ("refill_every", ctypes.c_int32), ("item_walks", ctypes.c_int32),
+                ("walks_per_lane", ctypes.c_int32)]
 
 
 def mw_transition(eps, n_walks, lattice=MW_LATTICE_VERTEX, first_walk=0, seed=0, cube_index=0,
@@ -144,8 +145,7 @@ def mw_transition_batch(eps_list, walks, lattice=MW_LATTICE_VERTEX, seed=0, tune
                  if want_steps else None)
     t = None
     if tune is not None:
-        t = mw_tune(*[int(tune.get(k, 0)) for k in ("tile_form", "waves_per_wg", "refill_every",
-                                                    "item_walks")])
+        t = mw_tune(*[int(tune.get(k, 0)) for k, _ in mw_tune._fields_])
     _check(_lib.mw_transition_batch(
         I32(n_cubes), _ptr(eps_cat), eps_off.ctypes.data_as(ctypes.c_void_p),
         ns.ctypes.data_as(ctypes.c_void_p), I32(lattice), walks.ctypes.data_as(ctypes.c_void_p),
@@ -183,6 +183,16 @@ def mw_autotune_batch(eps_list, walks, lattice=MW_LATTICE_VERTEX, device="cuda",
     return {k: int(getattr(best, k)) for k, _ in mw_tune._fields_}
 
 
+def mw_tune_lookup(n_cells, walks, lattice=MW_LATTICE_VERTEX):
+    """The tuned setting a batch of this shape would use, or None."""
+    ns = np.ascontiguousarray(n_cells, dtype=np.int32)
+    w = np.ascontiguousarray(walks, dtype=np.uint64)
+    t = mw_tune()
+    found = ctypes.c_int32(0)
+    _check(_lib.mw_tune_lookup(I32(len(ns)), _vp(ns), _vp(w), I32(lattice), ctypes.byref(t), ctypes.byref(found)))
+    return {k: int(getattr(t, k)) for k, _ in mw_tune._fields_} if found.value else None
+
+
 class BatchPlan:
     """mw_batch_plan_*: a batch captured as a HIP graph, replayed per seed."""
 
@@ -197,8 +207,7 @@ class BatchPlan:
         self.total = total
         t = None
         if tune is not None:
-            t = mw_tune(*[int(tune.get(k, 0)) for k in ("tile_form", "waves_per_wg", "refill_every",
-                                                        "item_walks")])
+            t = mw_tune(*[int(tune.get(k, 0)) for k, _ in mw_tune._fields_])
         h = ctypes.c_void_p()
         _check(_lib.mw_batch_plan_create(I32(len(ns)), _ptr(self.eps_cat), _vp(eps_off), _vp(ns),
                                          I32(lattice), _vp(walks), _vp(self.out_off), _ptr(self.hits),
@@ -261,7 +270,8 @@ class frw_options(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int32), ("hybrid", ctypes.c_int32),
                 ("expand", ctypes.c_int32), ("plain", ctypes.c_int32),
                 ("target_rel_3sigma", ctypes.c_double), ("abs_tol_rel", ctypes.c_double),
-                ("first_walk", ctypes.c_uint64), ("batch_walks", ctypes.c_uint64)]
+                ("first_walk", ctypes.c_uint64), ("batch_walks", ctypes.c_uint64),
+                ("gauss_is", ctypes.c_double)]
 
 
 class frw_stats(ctypes.Structure):
@@ -338,7 +348,7 @@ def mw_structure_destroy(handle):
 
 def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
                 target_rel_3sigma=0.0, abs_tol_rel=1e-6, first_walk=0, batch_walks=0,
-                scores=False, device="cuda", expand=0, plain=0):
+                scores=False, device="cuda", expand=0, plain=0, gauss_is=0.0):
     """Alg. 1: one capacitance row (fF, last entry = grounded enclosure) and
     its standard errors.  With scores=True also returns the per-walk net and
     fp32 weight (CUDA tensors)."""
@@ -350,7 +360,7 @@ def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
     se = (ctypes.c_double * K)()
     stats = frw_stats()
     opt = frw_options(n_cells, hybrid, expand, plain, target_rel_3sigma, abs_tol_rel, first_walk,
-                      batch_walks)
+                      batch_walks, gauss_is)
     net = w = None
     if scores:
         net = torch.empty(walk_budget, dtype=torch.int32, device=device)
@@ -364,6 +374,18 @@ def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
         out["net"], out["w"] = net[:n], w[:n]
     return out
 
+
+
+def frw_autotune(structure, master, walks, seed=0, n_cells=16, hybrid=1, expand=0):
+    """Tunes the FRW walker's resident waves per CU on this extraction and
+    keeps the choice (returned) for later calls with the same lattice."""
+    if not isinstance(structure, StructureHandle):
+        structure = StructureHandle(structure)
+    opt = frw_options(n_cells, hybrid, expand, 0, 0.0, 1e-6, 0, 0, 0.0)
+    w = ctypes.c_int32(0)
+    _check(_lib.frw_autotune(structure.handle, I32(master), U64(walks), U64(seed), ctypes.byref(opt),
+                             ctypes.byref(w)))
+    return int(w.value)
 
 
 def mw_sgf_table(plane_codes, axis, kind=0, normal_axis=0):
@@ -385,7 +407,7 @@ def mw_sgf_table(plane_codes, axis, kind=0, normal_axis=0):
 
 def frw_extract_matrix(structure, walks_per_master, seed=0, masters=None, n_cells=16, hybrid=1,
                        target_rel_3sigma=0.0, abs_tol_rel=1e-6, first_walk=0, batch_walks=0, expand=0,
-                       plain=0):
+                       plain=0, gauss_is=0.0):
     """Capacitance-matrix rows for several masters (default: every net) in
     shared rounds.  Returns {"cap": (M, K) rows, "se": (M, K), "sym": (M, M)
     symmetrised block, "masters": list, "stats": dict}; master i uses seed + i."""
@@ -400,7 +422,8 @@ def frw_extract_matrix(structure, walks_per_master, seed=0, masters=None, n_cell
     se = np.zeros((M, K))
     sym = np.zeros((M, M))
     stats = frw_stats()
-    opt = frw_options(n_cells, hybrid, expand, plain, target_rel_3sigma, abs_tol_rel, first_walk, batch_walks)
+    opt = frw_options(n_cells, hybrid, expand, plain, target_rel_3sigma, abs_tol_rel, first_walk, batch_walks,
+                      gauss_is)
     _check(_lib.frw_extract_matrix(structure.handle, I32(M), _vp(m), U64(walks_per_master), U64(seed),
                                    ctypes.byref(opt), _vp(cap), _vp(se), _vp(sym), ctypes.byref(stats)))
     return {"cap": cap, "se": se, "sym": sym, "masters": [int(x) for x in m], "stats": stats.as_dict()}
@@ -431,8 +454,8 @@ class Server:
     """Request loop over the device (mw_server_*): submit structures, poll rows."""
 
     def __init__(self, hbm_budget_bytes, n_cells=16, hybrid=1, target_rel_3sigma=0.0,
-                 abs_tol_rel=1e-6, expand=0, plain=0):
-        opt = frw_options(n_cells, hybrid, expand, plain, target_rel_3sigma, abs_tol_rel, 0, 0)
+                 abs_tol_rel=1e-6, expand=0, plain=0, gauss_is=0.0):
+        opt = frw_options(n_cells, hybrid, expand, plain, target_rel_3sigma, abs_tol_rel, 0, 0, gauss_is)
         h = ctypes.c_void_p()
         _check(_lib.mw_server_create(ctypes.c_size_t(int(hbm_budget_bytes)), ctypes.byref(opt),
                                      ctypes.byref(h)))

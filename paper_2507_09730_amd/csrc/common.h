@@ -65,6 +65,11 @@ bool inject_alloc_failure();
 // current device (looked up on the first call per device).
 char* noalloc_scratch();
 
+// Tuned FRW walker geometry (resident waves per CU) for lattice size n and
+// MicroWalk-E factor m (0 = off), from this process or MWALK_TUNE_CACHE.
+bool frw_tuned_waves(int n, int expand_m, int* waves);
+void frw_store_waves(int n, int expand_m, int waves);
+
 // Device allocation helpers (throw Fail on error).
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);

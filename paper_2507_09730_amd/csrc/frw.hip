@@ -45,6 +45,7 @@ constexpr int FRW_THREADS = 256;   // first-transition kernel
 constexpr int WALK_THREADS = 64;   // walker kernel: one-wave blocks pack the LDS of a CU
 constexpr uint32_t KEY_HDR = 4;
 constexpr uint32_t NO_INDEX = 0xffffffffu;
+constexpr uint32_t FULL_INDEX = 0xfffffffeu;  // slot of a key that found the table cache full
 
 enum ErrBits : uint32_t { ERR_REGIONS = 1, ERR_TABLE_CAP = 2, ERR_PARK_CAP = 4, ERR_STEP_CAP = 8 };
 constexpr uint32_t MW_STEP_CAP = 1u << 26;
@@ -88,15 +89,18 @@ struct StructDev {
     float delta_abs;
 };
 
-// One rectangle of a Gaussian surface: p = {plane, cumulative area, axis |
-// side << 2 (bits), 0}, t = {lo, hi} along the lower tangent axis, then
-// {lo, hi} along the higher one.
+// One rectangle of a Gaussian surface, or one importance-sampling patch of
+// it: p = {plane, cumulative sampling weight, axis | side << 2 (bits), weight
+// factor}, t = {lo, hi} along the lower tangent axis, then {lo, hi} along the
+// higher one.  Uniform sampling: the weight is the area and the factor |G|;
+// importance sampling: the weight is q = area K(centre) and the factor
+// Q area / q.
 struct GaussFace {
     float4 p, t;
 };
 
 struct GaussDev {
-    float g, area;
+    float g, area;  // area: the total sampling weight (|G| or Q)
     int32_t n_faces, pad;
     const GaussFace* faces;
 };
@@ -184,6 +188,7 @@ struct WalkArgs {
 // First transitions of a batch of walks (one lane per walk).
 struct FirstArgs {
     const Segment* segs;
+    const float4* eval;  // non-null: evaluate K / h at these points (xyz, w = axis | side << 2 bits)
     int32_t n_segs, pad0;
     unsigned long long total;
     CacheDev cache;
@@ -946,7 +951,12 @@ __device__ __forceinline__ int lookup_or_insert(const CacheDev& C, KeyF key, uin
             const unsigned long long old = atomicCAS(&C.slot[slot], 0ull, hh | NO_INDEX);
             if (old == 0ull) {
                 const uint32_t idx = atomicAdd(C.n_tables, 1u);
-                if (idx >= C.capacity) return LOOKUP_FULL;
+                if (idx >= C.capacity) {
+                    // no room: the slot says so to every later lookup of
+                    // this key until the cache is emptied
+                    __hip_atomic_store(&C.slot[slot], hh | FULL_INDEX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    return LOOKUP_FULL;
+                }
                 uint32_t* dst = C.keys + (size_t)idx * C.key_stride;
                 for (uint32_t q = 0; q < words; ++q) dst[q] = key(q);
                 for (uint32_t q = words; q < C.key_stride; ++q) dst[q] = 0u;
@@ -961,6 +971,7 @@ __device__ __forceinline__ int lookup_or_insert(const CacheDev& C, KeyF key, uin
         if ((cur & SLOT_HASH_MASK) == hh) {
             const uint32_t idx = (uint32_t)cur;
             if (idx == NO_INDEX) return LOOKUP_PARK;
+            if (idx == FULL_INDEX) return LOOKUP_FULL;
             const uint32_t rdy = __hip_atomic_load(gpw(C.ready) + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             uint32_t g0 = 0, g1 = 0;
             if (glo) {
@@ -1101,39 +1112,53 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         }();
         const GAS GaussDev& G = *gp(SG.G);
         const unsigned long long walk = SG.walk_begin + k;
-        // GaussianSurfaceSampling(G): rectangle by area (the first whose
-        // cumulative area exceeds the draw), uniform point on it
-        const Rand4 r = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_GAUSS), SG.k0, SG.k1);
-        const float xa = ((float)r.x + 0.5f) * 2.3283064365386963e-10f * G.area;
-        const GAS GaussFace* gf = gp(G.faces);
-        const int nf = G.n_faces;
-        int f_lo = 0;
-        if (nf <= 8) {
-            // few rectangles: count those whose cumulative area is <= the
-            // draw (independent loads)
-#pragma unroll
-            for (int q = 0; q < 7; ++q) {
-                const float cq = gf[min(q, nf - 1)].p.y;
-                f_lo += (q < nf - 1 && !(xa < cq)) ? 1 : 0;
-            }
+        float3 c;
+        int a_norm, side;
+        float factor = 0.f;
+        if (A.eval) {
+            // evaluation of the kernel sum at a given point of G
+            const float4 e = ldf4(A.eval + k);
+            c = make_float3(e.x, e.y, e.z);
+            const uint32_t fbits = __float_as_uint(e.w);
+            a_norm = (int)(fbits & 3u);
+            side = (int)(fbits >> 2);
         } else {
-            int f_hi = nf - 1;
-            while (f_lo < f_hi) {
-                const int mid = (f_lo + f_hi) >> 1;
-                if (xa < gf[mid].p.y)
-                    f_hi = mid;
-                else
-                    f_lo = mid + 1;
+            // GaussianSurfaceSampling(G): rectangle (or patch) by its sampling
+            // weight (the first whose cumulative weight exceeds the draw),
+            // uniform point on it
+            const Rand4 r = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_GAUSS), SG.k0, SG.k1);
+            const float xa = ((float)r.x + 0.5f) * 2.3283064365386963e-10f * G.area;
+            const GAS GaussFace* gf = gp(G.faces);
+            const int nf = G.n_faces;
+            int f_lo = 0;
+            if (nf <= 8) {
+                // few rectangles: count those whose cumulative weight is <=
+                // the draw (independent loads)
+#pragma unroll
+                for (int q = 0; q < 7; ++q) {
+                    const float cq = gf[min(q, nf - 1)].p.y;
+                    f_lo += (q < nf - 1 && !(xa < cq)) ? 1 : 0;
+                }
+            } else {
+                int f_hi = nf - 1;
+                while (f_lo < f_hi) {
+                    const int mid = (f_lo + f_hi) >> 1;
+                    if (xa < gf[mid].p.y)
+                        f_hi = mid;
+                    else
+                        f_lo = mid + 1;
+                }
             }
+            const float4 fp = ldf4(&G.faces[f_lo].p), ft = ldf4(&G.faces[f_lo].t);
+            const uint32_t fbits = __float_as_uint(fp.z);
+            a_norm = (int)(fbits & 3u);
+            side = (int)(fbits >> 2);
+            factor = fp.w;
+            const float ua = ft.x + ((float)r.y + 0.5f) * 2.3283064365386963e-10f * (ft.y - ft.x);
+            const float ub = ft.z + ((float)r.z + 0.5f) * 2.3283064365386963e-10f * (ft.w - ft.z);
+            const float pl = fp.x;
+            c = make_float3(a_norm == 0 ? pl : ua, a_norm == 1 ? pl : (a_norm == 0 ? ua : ub), a_norm == 2 ? pl : ub);
         }
-        const float4 fp = ldf4(&G.faces[f_lo].p), ft = ldf4(&G.faces[f_lo].t);
-        const uint32_t fbits = __float_as_uint(fp.z);
-        const int a_norm = (int)(fbits & 3u), side = (int)(fbits >> 2);
-        const float ua = ft.x + ((float)r.y + 0.5f) * 2.3283064365386963e-10f * (ft.y - ft.x);
-        const float ub = ft.z + ((float)r.z + 0.5f) * 2.3283064365386963e-10f * (ft.w - ft.z);
-        const float pl = fp.x;
-        const float3 c = make_float3(a_norm == 0 ? pl : ua, a_norm == 1 ? pl : (a_norm == 0 ? ua : ub),
-                                     a_norm == 2 ? pl : ub);
         const int cell = grid_cell(S, c);
         const uint2 drange = make_uint2(gp(S.gd_off)[cell], gp(S.gd_off)[cell + 1]);
         int who;
@@ -1185,16 +1210,21 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
             ++missing;
             continue;
         }
+        const GAS uint32_t* tab = gp(A.cache.data) + (size_t)idx * A.cache.tab_words;
+        const float Kh = __uint_as_float(tab[1]);
+        if (A.eval) {
+            stf4(SG.first_state + k, make_float4(Kh / h, 0.f, 0.f, 0.f));
+            gpw(SG.first_done)[k] = 1u;
+            continue;
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) c_br[q] += br == q ? 1ull : 0ull;  // constant indices: registers
         c_halved += halved ? 1ull : 0ull;
-        const GAS uint32_t* tab = gp(A.cache.data) + (size_t)idx * A.cache.tab_words;
         const int b = table_sample_guided(tab, A.cache.nb, r2.x, glo, ghi);
         const uint32_t sb = (tab[TAB_CDF + A.cache.nb + (b >> 5)] >> (b & 31)) & 1u;
-        const float Kh = __uint_as_float(tab[1]);
         float sgn = sb ? 1.f : -1.f;
         if (!side) sgn = -sgn;
-        const float omega = EPS0 * G.area * (Kh / h) * sgn;
+        const float omega = EPS0 * factor * (Kh / h) * sgn;
         int nd[3];
         node_of_hit(n, b, nd);
         const float3 x = make_float3(c.x - R + (float)nd[0] * h, c.y - R + (float)nd[1] * h, c.z - R + (float)nd[2] * h);
@@ -1743,9 +1773,10 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     int env_net = 0;
 
     for (;;) {
-        // ---- plain form: walks that made their transition of this launch
-        // park for the next one (one queue slot range claimed per wave) ----
-        if (A.plain) {
+        // ---- walks that park for the next launch: in the plain form after
+        // each transition, and fresh walks whose first transition is still
+        // missing (t = 0); one queue slot range claimed per wave ----
+        {
             const uint64_t bp = __ballot(phase == PH_PARK);
             if (bp) {
                 uint32_t base = 0;
@@ -1781,12 +1812,22 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                         if (ri < A.n_resume) {
                             const Parked P = ldpark(A.resume + ri);
                             if (MULTI) sg = P.seg;
-                            wk0 = gp(A.segs)[sg].k0;
-                            wk1 = gp(A.segs)[sg].k1;
+                            const GAS Segment& SG = gp(A.segs)[sg];
+                            wk0 = SG.k0;
+                            wk1 = SG.k1;
                             walk = P.walk;
-                            pos = make_float3(P.px, P.py, P.pz);
-                            omega = P.omega;
-                            t = P.t;
+                            if (P.t == 0u) {
+                                // parked before its first transition existed:
+                                // start from it now
+                                const float4 f = ldf4(SG.first_state + (walk - SG.walk_begin));
+                                pos = make_float3(f.x, f.y, f.z);
+                                omega = f.w;
+                                t = 1;
+                            } else {
+                                pos = make_float3(P.px, P.py, P.pz);
+                                omega = P.omega;
+                                t = P.t;
+                            }
                             phase = PH_NEED;
                             got = true;
                         }
@@ -1804,11 +1845,14 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                             wk1 = SG.k1;
                             const unsigned long long k = gi - SG.offset;
                             const float4 f = ldf4(SG.first_state + k);
+                            const uint32_t fdone = gp(SG.first_done)[k];
                             walk = SG.walk_begin + k;
                             pos = make_float3(f.x, f.y, f.z);
                             omega = f.w;
-                            t = 1;
-                            phase = PH_NEED;
+                            t = fdone ? 1u : 0u;
+                            // a walk whose first transition missed its table
+                            // waits in the park queue (t = 0)
+                            phase = fdone ? PH_NEED : PH_PARK;
                         } else {
                             phase = PH_EXHAUSTED;
                         }
@@ -1816,7 +1860,8 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                 }
             }
         }
-        if (!__any(phase == PH_NEED || phase == PH_MW)) break;
+        // (a lane about to park keeps the loop going: the next pass parks it)
+        if (!__any(phase == PH_NEED || phase == PH_MW || phase == PH_PARK)) break;
 
         // ---- one transition for lanes that need one ----
         if (phase == PH_NEED) {
@@ -2370,20 +2415,80 @@ __device__ __forceinline__ void neumaier(float& s, float& c, float x) {
 
 // Block-level compensated sums of one RED_CHUNK slice of walks: per net,
 // the slice is split into `parts` contiguous pieces summed by different
-// threads, then combined in piece order (deterministic).
+// threads, then combined in piece order (deterministic).  Only the nets that
+// occur in the slice are scanned (found with a flag per net when K <=
+// RED_FLAGS), so the work is about (nets present) x len / RED_THREADS per
+// thread instead of K x len.
+constexpr int RED_FLAGS = 4096;
+
 __device__ void reduce_chunk(const int32_t* __restrict__ net, const float* __restrict__ w, uint64_t base, int len,
-                             int K, float4* __restrict__ out, int32_t* snet, float* sw, float4* part) {
+                             int K, float4* __restrict__ out, int32_t* snet, float* sw, float4* part,
+                             int32_t* flag) {
+    const bool sparse = K <= RED_FLAGS;
+    if (sparse)
+        for (int j = threadIdx.x; j < K; j += blockDim.x) flag[j] = 0;
+    __syncthreads();
     for (int q = threadIdx.x; q < len; q += blockDim.x) {
-        snet[q] = net[base + q];
+        const int32_t nq = net[base + q];
+        snet[q] = nq;
         sw[q] = w[base + q];
+        if (sparse) flag[nq] = 1;
     }
     __syncthreads();
-    for (int j0 = 0; j0 < K; j0 += RED_THREADS) {
-        const int kn = min(K - j0, RED_THREADS);
+    // the nets to scan, in increasing order: flag[j] becomes the index of
+    // net j in that list (or -1); n_list of them
+    __shared__ int32_t n_list;
+    __shared__ int32_t wsum[RED_THREADS / 64];
+    if (sparse) {
+        // block-wide exclusive scan of the flags, RED_FLAGS / RED_THREADS per thread
+        constexpr int PER = RED_FLAGS / RED_THREADS;
+        const int t0 = threadIdx.x * PER;
+        int loc[PER];
+        int run = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            loc[i] = t0 + i < K ? flag[t0 + i] : 0;
+            run += loc[i];
+        }
+        int incl = run;
+        const int lane = threadIdx.x & 63;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off);
+            if (lane >= off) incl += v;
+        }
+        if (lane == 63) wsum[threadIdx.x >> 6] = incl;
+        __syncthreads();
+        int before = incl - run;
+        for (int wv = 0; wv < (int)(threadIdx.x >> 6); ++wv) before += wsum[wv];
+        if (threadIdx.x == RED_THREADS - 1) n_list = before + run;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            if (t0 + i < K) flag[t0 + i] = loc[i] ? before : -1;
+            before += loc[i];
+        }
+        __syncthreads();
+    } else if (threadIdx.x == 0) {
+        n_list = K;
+    }
+    __syncthreads();
+    const int L = n_list;
+    __shared__ int32_t lnet[RED_THREADS];  // list position -> net, one group of nets at a time
+    for (int j0 = 0; j0 < L; j0 += RED_THREADS) {
+        const int kn = min(L - j0, RED_THREADS);
         const int parts = RED_THREADS / kn;
         const int t = threadIdx.x;
+        if (sparse) {
+            for (int j = threadIdx.x; j < K; j += blockDim.x) {
+                const int li = flag[j];
+                if (li >= j0 && li < j0 + kn) lnet[li - j0] = j;
+            }
+        } else if (t < kn) {
+            lnet[t] = j0 + t;
+        }
+        __syncthreads();
         if (t < kn * parts) {
-            const int j = j0 + t / parts, pi = t % parts;
+            const int j = lnet[t / parts], pi = t % parts;
             const int q0 = (int)((long long)len * pi / parts), q1 = (int)((long long)len * (pi + 1) / parts);
             float s1 = 0.f, c1 = 0.f, s2 = 0.f, c2 = 0.f;
             for (int q = q0; q < q1; ++q) {
@@ -2405,10 +2510,14 @@ __device__ void reduce_chunk(const int32_t* __restrict__ net, const float* __res
                 neumaier(s2, c2, v.z);
                 neumaier(s2, c2, v.w);
             }
-            out[j0 + t] = make_float4(s1, c1, s2, c2);
+            out[lnet[t]] = make_float4(s1, c1, s2, c2);
         }
         __syncthreads();
     }
+    // nets absent from the slice contribute zero
+    if (sparse)
+        for (int j = threadIdx.x; j < K; j += blockDim.x)
+            if (flag[j] < 0) out[j] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 __global__ void __launch_bounds__(RED_THREADS) reduce_scores_kernel(const int32_t* __restrict__ net,
@@ -2417,9 +2526,10 @@ __global__ void __launch_bounds__(RED_THREADS) reduce_scores_kernel(const int32_
     __shared__ int32_t snet[RED_CHUNK];
     __shared__ float sw[RED_CHUNK];
     __shared__ float4 part[RED_THREADS];
+    __shared__ int32_t flag[RED_FLAGS];
     const uint64_t base = (uint64_t)blockIdx.x * RED_CHUNK;
     const int len = (int)min((uint64_t)RED_CHUNK, count - base);
-    reduce_chunk(net, w, base, len, K, partial + (size_t)blockIdx.x * K, snet, sw, part);
+    reduce_chunk(net, w, base, len, K, partial + (size_t)blockIdx.x * K, snet, sw, part, flag);
 }
 
 // Reduction of a round that served several requests: segment s owns blocks
@@ -2439,6 +2549,7 @@ __global__ void __launch_bounds__(RED_THREADS) reduce_multi_kernel(const RedSeg*
     __shared__ int32_t snet[RED_CHUNK];
     __shared__ float sw[RED_CHUNK];
     __shared__ float4 part[RED_THREADS];
+    __shared__ int32_t flag[RED_FLAGS];
     int lo = 0, hi = n_segs - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -2452,7 +2563,7 @@ __global__ void __launch_bounds__(RED_THREADS) reduce_multi_kernel(const RedSeg*
     const uint64_t base = (uint64_t)local * RED_CHUNK;
     if (base >= R.count) return;
     const int len = (int)min((uint64_t)RED_CHUNK, R.count - base);
-    reduce_chunk(R.net, R.w, base, len, R.K, R.partial + (size_t)local * R.K, snet, sw, part);
+    reduce_chunk(R.net, R.w, base, len, R.K, R.partial + (size_t)local * R.K, snet, sw, part, flag);
 }
 
 __global__ void finish_multi_kernel(const RedSeg* __restrict__ segs) {
@@ -2482,10 +2593,16 @@ __global__ void finish_multi_kernel(const RedSeg* __restrict__ segs) {
 // fixed-order tree over the threads (deterministic).
 constexpr int FIN_THREADS = 256;
 
+// gate (or null): the counters of the walker run that wrote the scores; the
+// sums are added only when that run ended every walk of its gate_total (no
+// walk parked, no first transition missing), else nothing is written and
+// the host completes the run and reduces again.
 __global__ void __launch_bounds__(FIN_THREADS) finish_kernel(const float4* __restrict__ partial, int blocks, int K,
-                                                             double* acc, double n_total, double* result) {
+                                                             double* acc, double n_total, double* result,
+                                                             const Counters* gate, unsigned long long gate_total) {
     __shared__ double t1[FIN_THREADS], t2[FIN_THREADS];
     const int j = blockIdx.x;
+    if (gate && (gate->park_count != 0u || gate->first_missing != 0u || gate->walk_next < gate_total)) return;
     double s1 = 0.0, s2 = 0.0;
     for (int b = threadIdx.x; b < blocks; b += FIN_THREADS) {
         const float4 p = partial[(size_t)b * K + j];
@@ -2636,7 +2753,8 @@ struct Cache {
     CacheDev d{};
     void* mem = nullptr;
     std::mutex mu;
-    uint32_t uniform_index = NO_INDEX;  // tables are never evicted
+    uint32_t uniform_index = NO_INDEX;  // valid until the cache is emptied
+    uint64_t flushes = 0;               // times the full cache was emptied
 };
 
 std::mutex g_cache_mu;
@@ -2751,10 +2869,27 @@ static void validate_desc(const mw_structure_desc* D) {
     }
 }
 
+// A non-blocking stream of the calling thread for structure creation and
+// extraction set-up: their copies and kernels neither wait for nor hold up
+// work on the legacy default stream (a server prepares the next requests
+// while a round runs there).
+hipStream_t setup_stream() {
+    thread_local hipStream_t s = nullptr;
+    thread_local int dev = -1;
+    int cur = 0;
+    MW_HIP(hipGetDevice(&cur));
+    if (!s || dev != cur) {
+        MW_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        dev = cur;
+    }
+    return s;
+}
+
 extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structure** out) {
     return guarded([&] {
         MW_REQUIRE(out, MW_EINVAL, "null output handle");
         validate_desc(D);
+        hipStream_t ss = setup_stream();
         auto st = std::make_unique<mw_structure>();
         MW_HIP(hipGetDevice(&st->device));
         st->n_nets = D->n_nets;
@@ -2816,12 +2951,12 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
                 if (!keep) dev_free(p);
             }
         } guard{m};
-        MW_HIP(hipMemcpy(m + o_clo, clo.data(), 16 * nc, hipMemcpyHostToDevice));
-        MW_HIP(hipMemcpy(m + o_chi, chi.data(), 16 * nc, hipMemcpyHostToDevice));
-        MW_HIP(hipMemcpy(m + o_dlo, dlo.data(), 16 * dlo.size(), hipMemcpyHostToDevice));
-        MW_HIP(hipMemcpy(m + o_dhi, dhi.data(), 16 * dhi.size(), hipMemcpyHostToDevice));
-        MW_HIP(hipMemcpy(m + o_z0, z0.data(), 4 * nl, hipMemcpyHostToDevice));
-        MW_HIP(hipMemcpy(m + o_lc, lcode.data(), 4 * nl, hipMemcpyHostToDevice));
+        MW_HIP(hipMemcpyAsync(m + o_clo, clo.data(), 16 * nc, hipMemcpyHostToDevice, ss));
+        MW_HIP(hipMemcpyAsync(m + o_chi, chi.data(), 16 * nc, hipMemcpyHostToDevice, ss));
+        MW_HIP(hipMemcpyAsync(m + o_dlo, dlo.data(), 16 * dlo.size(), hipMemcpyHostToDevice, ss));
+        MW_HIP(hipMemcpyAsync(m + o_dhi, dhi.data(), 16 * dhi.size(), hipMemcpyHostToDevice, ss));
+        MW_HIP(hipMemcpyAsync(m + o_z0, z0.data(), 4 * nl, hipMemcpyHostToDevice, ss));
+        MW_HIP(hipMemcpyAsync(m + o_lc, lcode.data(), 4 * nl, hipMemcpyHostToDevice, ss));
         StructDev& S = st->h;
         S.n_cond = nc;
         S.n_nets = D->n_nets;
@@ -2854,18 +2989,19 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
         uint32_t* eoff = (uint32_t*)(m + o_eoff);
         uint32_t* xoff = (uint32_t*)(m + o_xoff);
         const int tb = 128, nbk = (ncells + tb - 1) / tb;
-        grid_count_kernel<<<nbk, tb>>>(S, ccount, dcount, ncells, 1.f);
-        grid_count_kernel<<<nbk, tb>>>(S, ecount, xcount, ncells, EXP_LIST_FACTOR);
-        scan_kernel<<<1, 1024>>>(ccount, coff, ncells);
-        scan_kernel<<<1, 1024>>>(dcount, doff, ncells);
-        scan_kernel<<<1, 1024>>>(ecount, eoff, ncells);
-        scan_kernel<<<1, 1024>>>(xcount, xoff, ncells);
+        grid_count_kernel<<<nbk, tb, 0, ss>>>(S, ccount, dcount, ncells, 1.f);
+        grid_count_kernel<<<nbk, tb, 0, ss>>>(S, ecount, xcount, ncells, EXP_LIST_FACTOR);
+        scan_kernel<<<1, 1024, 0, ss>>>(ccount, coff, ncells);
+        scan_kernel<<<1, 1024, 0, ss>>>(dcount, doff, ncells);
+        scan_kernel<<<1, 1024, 0, ss>>>(ecount, eoff, ncells);
+        scan_kernel<<<1, 1024, 0, ss>>>(xcount, xoff, ncells);
         MW_HIP(hipGetLastError());
         uint32_t tot[4];
-        MW_HIP(hipMemcpy(&tot[0], coff + ncells, 4, hipMemcpyDeviceToHost));
-        MW_HIP(hipMemcpy(&tot[1], doff + ncells, 4, hipMemcpyDeviceToHost));
-        MW_HIP(hipMemcpy(&tot[2], eoff + ncells, 4, hipMemcpyDeviceToHost));
-        MW_HIP(hipMemcpy(&tot[3], xoff + ncells, 4, hipMemcpyDeviceToHost));
+        MW_HIP(hipMemcpyAsync(&tot[0], coff + ncells, 4, hipMemcpyDeviceToHost, ss));
+        MW_HIP(hipMemcpyAsync(&tot[1], doff + ncells, 4, hipMemcpyDeviceToHost, ss));
+        MW_HIP(hipMemcpyAsync(&tot[2], eoff + ncells, 4, hipMemcpyDeviceToHost, ss));
+        MW_HIP(hipMemcpyAsync(&tot[3], xoff + ncells, 4, hipMemcpyDeviceToHost, ss));
+        MW_HIP(hipStreamSynchronize(ss));
         size_t lo4[4], lb = 0;
         for (int q = 0; q < 4; ++q) {
             lo4[q] = lb;
@@ -2886,16 +3022,16 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
         uint32_t* dlist = (uint32_t*)(lists + lo4[1]);
         uint32_t* elist = (uint32_t*)(lists + lo4[2]);
         uint32_t* xlist = (uint32_t*)(lists + lo4[3]);
-        grid_fill_kernel<<<nbk, tb>>>(S, coff, doff, clist, dlist, ncells, 1.f);
-        grid_fill_kernel<<<nbk, tb>>>(S, eoff, xoff, elist, xlist, ncells, EXP_LIST_FACTOR);
+        grid_fill_kernel<<<nbk, tb, 0, ss>>>(S, coff, doff, clist, dlist, ncells, 1.f);
+        grid_fill_kernel<<<nbk, tb, 0, ss>>>(S, eoff, xoff, elist, xlist, ncells, EXP_LIST_FACTOR);
         float4* crec = (float4*)(lists + o_crec);
         float4* drec = (float4*)(lists + o_drec);
-        if (tot[0]) grid_records_kernel<<<(tot[0] + 255) / 256, 256>>>(clist, tot[0], S.cond_lo, S.cond_hi, crec);
-        if (tot[1]) grid_records_kernel<<<(tot[1] + 255) / 256, 256>>>(dlist, tot[1], S.diel_lo, S.diel_hi, drec);
+        if (tot[0]) grid_records_kernel<<<(tot[0] + 255) / 256, 256, 0, ss>>>(clist, tot[0], S.cond_lo, S.cond_hi, crec);
+        if (tot[1]) grid_records_kernel<<<(tot[1] + 255) / 256, 256, 0, ss>>>(dlist, tot[1], S.diel_lo, S.diel_hi, drec);
         float4* erec = (float4*)(lists + o_erec);
         float4* xrec = (float4*)(lists + o_xrec);
-        if (tot[2]) grid_records_kernel<<<(tot[2] + 255) / 256, 256>>>(elist, tot[2], S.cond_lo, S.cond_hi, erec);
-        if (tot[3]) grid_records_kernel<<<(tot[3] + 255) / 256, 256>>>(xlist, tot[3], S.diel_lo, S.diel_hi, xrec);
+        if (tot[2]) grid_records_kernel<<<(tot[2] + 255) / 256, 256, 0, ss>>>(elist, tot[2], S.cond_lo, S.cond_hi, erec);
+        if (tot[3]) grid_records_kernel<<<(tot[3] + 255) / 256, 256, 0, ss>>>(xlist, tot[3], S.diel_lo, S.diel_hi, xrec);
         MW_HIP(hipGetLastError());
         S.gc_off = coff;
         S.gc_list = clist;
@@ -2910,8 +3046,8 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
         S.ge_rec = erec;
         S.gx_rec = xrec;
         st->d = (StructDev*)(m + o_desc);
-        MW_HIP(hipMemcpy(st->d, &S, sizeof S, hipMemcpyHostToDevice));
-        MW_HIP(hipDeviceSynchronize());
+        MW_HIP(hipMemcpyAsync(st->d, &S, sizeof S, hipMemcpyHostToDevice, ss));
+        MW_HIP(hipStreamSynchronize(ss));
         st->mem = m;
         guard.keep = true;
         // the list block (starting with the conductor list) is owned
@@ -2939,6 +3075,7 @@ struct LaunchGeom {
     uint32_t lane_stride, first_stride, lane_stride_e;
     size_t lds, first_lds, lds_e;
     int blocks, first_blocks, blocks_e;
+    int cus;
     uint64_t pool;
 };
 
@@ -2947,6 +3084,7 @@ LaunchGeom launch_geom(int n) {
     MW_HIP(hipGetDevice(&dev));
     MW_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     LaunchGeom g;
+    g.cus = cus;
     // LDS per lane: axis masks + region codes (+ a key buffer for first
     // transitions); odd dword strides spread lanes over the banks
     g.lane_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * n + 3) / 4) | 1u;
@@ -2986,6 +3124,19 @@ struct Runner {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     uint64_t misses = 0, launches = 0;
     double walker_ms = 0.0;
+    // stream of this runner's launches and copies (nullptr: the legacy
+    // default stream); table builds and cache flushes always run on the
+    // default stream with the device otherwise idle
+    hipStream_t stream = nullptr;
+    int waves_per_cu = 0;  // resident walker waves per CU (0: as many as LDS allows)
+    // the run in progress (start .. finish)
+    std::vector<Segment> cur_segs;
+    StructDev cur_s0{};
+    bool cur_single = false;
+    unsigned long long cur_total = 0;
+    uint32_t n_resume = 0;
+    int cur = 0;
+    bool walker_pending = false;  // a launched walker whose duration is not yet counted
 
     template <class F>
     void set_lds(F* f, size_t bytes) {
@@ -3030,11 +3181,12 @@ struct Runner {
         dev_free(mem);
     }
 
-    // builds every table queued since the last call (binary64 solves)
-    void build_pending() {
+    // builds every table queued since the last call (binary64 solves);
+    // returns how many
+    size_t build_pending() {
         uint32_t npend = 0;
         MW_HIP(hipMemcpy(&npend, cache->d.n_pending, 4, hipMemcpyDeviceToHost));
-        if (!npend) return;
+        if (!npend) return 0;
         std::vector<uint32_t> list(npend);
         MW_HIP(hipMemcpy(list.data(), cache->d.pending, 4ull * npend, hipMemcpyDeviceToHost));
         std::vector<uint32_t> valid;
@@ -3067,10 +3219,13 @@ struct Runner {
         MW_HIP(hipDeviceSynchronize());
         MW_HIP(hipMemset(cache->d.n_pending, 0, 4));
         misses += valid.size();
+        return valid.size();
     }
 
+    // The cache-wide index of the uniform cube's table (another runner may
+    // have emptied the cache since this one last ran).
     void ensure_uniform_table() {
-        if (uniform_index == NO_INDEX) uniform_index = cache->uniform_index;
+        uniform_index = cache->uniform_index;
         for (int it = 0; it < 3 && uniform_index == NO_INDEX; ++it) {
             uniform_table_kernel<<<1, 1>>>(cache->d, n, status);
             MW_HIP(hipGetLastError());
@@ -3079,7 +3234,7 @@ struct Runner {
             if (res[0] == LOOKUP_HIT)
                 uniform_index = res[1];
             else if (res[0] == LOOKUP_FULL)
-                MW_REQUIRE(false, MW_ELIMIT, "SGF table cache full (MWALK_TABLE_CAP)");
+                flush_cache();
             else
                 build_pending();
         }
@@ -3087,23 +3242,58 @@ struct Runner {
         cache->uniform_index = uniform_index;
     }
 
+    // Empties the table cache when it is full.  Tables are pure functions of
+    // their keys and a walk that finds the cache full parks as on a miss, so
+    // the walks resume after the flush, rebuild what they need and keep
+    // their results.  Called between launches, with the cache lock held.
+    uint32_t flushes = 0;
+    void flush_cache() {
+        MW_REQUIRE(++flushes <= 4096, MW_ELIMIT,
+                   "SGF table cache emptied 4096 times in one call (raise MWALK_TABLE_CAP)");
+        const CacheDev& d = cache->d;
+        MW_HIP(hipMemset(d.slot, 0, 8ull * ((size_t)d.slot_mask + 1)));
+        MW_HIP(hipMemset(d.ready, 0, 4ull * d.capacity));
+        MW_HIP(hipMemset(d.n_tables, 0, 4));
+        MW_HIP(hipMemset(d.n_pending, 0, 4));
+        MW_HIP(hipDeviceSynchronize());
+        cache->uniform_index = uniform_index = NO_INDEX;
+        ++cache->flushes;
+        ensure_uniform_table();
+    }
+
+    // Handles a full cache reported by the last launch (the walks that met
+    // it are parked or marked missing): the tables queued before it filled
+    // are built first, so that the walks waiting for them move on; a cache
+    // that is full with nothing queued is emptied.
+    void after_launch(Counters& h) {
+        if (h.err & ERR_TABLE_CAP) {
+            if (build_pending() == 0) flush_cache();
+            MW_HIP(hipMemset(&ctr->err, 0, 4));
+            h.err &= ~(uint32_t)ERR_TABLE_CAP;
+        }
+        check_errors(h);
+    }
+
     // The cached table of a key (built if missing), copied to the host.
     void fetch_table(const std::vector<uint32_t>& key, std::vector<uint32_t>& tab) {
         std::lock_guard<std::mutex> lock(cache->mu);
+        flushes = 0;
         MW_REQUIRE(key.size() == cache->d.key_words, MW_EINVAL, "bad table key length");
         // the key goes to the status buffer's neighbour: the first parked
         // queue, unused outside walker runs
         uint32_t* dkey = reinterpret_cast<uint32_t*>(park[0]);
         MW_HIP(hipMemcpy(dkey, key.data(), 4 * key.size(), hipMemcpyHostToDevice));
         uint32_t res[2] = {LOOKUP_PARK, NO_INDEX};
-        for (int it = 0; it < 3; ++it) {
+        for (int it = 0; it < 4; ++it) {
             key_table_kernel<<<1, 1>>>(cache->d, dkey, status);
             MW_HIP(hipGetLastError());
             MW_HIP(hipMemcpy(res, status, 8, hipMemcpyDeviceToHost));
-            if (res[0] != LOOKUP_PARK) break;
-            build_pending();
+            if (res[0] == LOOKUP_HIT) break;
+            if (res[0] == LOOKUP_FULL)
+                flush_cache();
+            else
+                build_pending();
         }
-        MW_REQUIRE(res[0] != LOOKUP_FULL, MW_ELIMIT, "SGF table cache full (MWALK_TABLE_CAP)");
         MW_REQUIRE(res[0] == LOOKUP_HIT, MW_EDEVICE, "SGF table could not be built");
         tab.resize(cache->d.tab_words);
         MW_HIP(hipMemcpy(tab.data(), cache->d.data + (size_t)res[1] * cache->d.tab_words, 4ull * tab.size(),
@@ -3113,119 +3303,199 @@ struct Runner {
     static void check_errors(const Counters& h) {
         MW_REQUIRE(!(h.err & ERR_REGIONS), MW_ELIMIT, "more than %d dielectric boxes overlap at one point",
                    MAX_REGIONS);
-        MW_REQUIRE(!(h.err & ERR_TABLE_CAP), MW_ELIMIT, "SGF table cache full (MWALK_TABLE_CAP)");
         MW_REQUIRE(!(h.err & ERR_PARK_CAP), MW_ELIMIT, "parked-walk queue overflow");
         MW_REQUIRE(!(h.err & ERR_STEP_CAP), MW_ELIMIT, "a micro-walk exceeded %u steps", MW_STEP_CAP);
     }
 
-    // Runs every walk of segs (the first round of first transitions writes
-    // every walk's done flag).  s0:
-    // host copy of the structure header of a single segment.
-    Counters run(const std::vector<Segment>& segs, const StructDev* s0) {
+    // Zeroed counters and the segment list in one copy; returns the number
+    // of walks (or points) of the list.
+    unsigned long long upload(const std::vector<Segment>& segs, const StructDev* s0) {
         MW_REQUIRE((int)segs.size() <= seg_cap && !segs.empty(), MW_EINVAL, "bad segment list");
         MW_REQUIRE(segs.size() > 1 || s0, MW_EINVAL, "single-segment run without its structure");
-        std::lock_guard<std::mutex> lock(cache->mu);
-        ensure_uniform_table();
         unsigned long long total = 0;
         for (const Segment& sgm : segs) total += sgm.count;
         MW_REQUIRE(total <= park_cap || total <= (1ull << 40), MW_ELIMIT, "round too large");
-        {
-            // zeroed counters and the segment list in one copy
-            const size_t off = (char*)dsegs - (char*)ctr;
-            std::vector<char> staging(off + sizeof(Segment) * segs.size(), 0);
-            memcpy(staging.data() + off, segs.data(), sizeof(Segment) * segs.size());
-            MW_HIP(hipMemcpy(ctr, staging.data(), staging.size(), hipMemcpyHostToDevice));
-        }
-        for (int round = 0;; ++round) {
-            FirstArgs F{};
-            F.segs = dsegs;
-            F.n_segs = (int)segs.size();
-            F.total = total;
-            F.cache = cache->d;
-            F.n = n;
-            F.ctr = ctr;
-            F.lane_stride = g.first_stride;
-            if (segs.size() == 1) F.S0 = *s0;
-            F.round = round;
-            if (round > 0) MW_HIP(hipMemset(&ctr->first_missing, 0, 4));
-            const int fblocks = (int)std::min<uint64_t>((total + FRW_THREADS - 1) / FRW_THREADS, (uint64_t)g.first_blocks);
-            if (segs.size() == 1)
-                first_kernel<false><<<fblocks, FRW_THREADS, g.first_lds>>>(F);
-            else
-                first_kernel<true><<<fblocks, FRW_THREADS, g.first_lds>>>(F);
-            MW_HIP(hipGetLastError());
-            Counters h{};
-            MW_HIP(hipMemcpy(&h, ctr, sizeof h, hipMemcpyDeviceToHost));
-            check_errors(h);
-            MW_REQUIRE(round < 1000, MW_ELIMIT, "first-transition retry limit reached");
-            if (h.first_missing == 0) break;  // no walk missed a table, so none was queued
-            build_pending();
-        }
-        uint32_t n_resume = 0;
-        int cur = 0;
-        const bool multi = segs.size() > 1;
-        for (uint64_t local = 0;; ++local) {
-            WalkArgs W{};
-            W.segs = dsegs;
-            W.n_segs = (int)segs.size();
-            W.total = total;
-            W.cache = cache->d;
-            W.n = n;
-            W.hybrid = hybrid;
-            W.resume = park[cur];
-            W.n_resume = n_resume;
-            W.park_out = park[cur ^ 1];
-            W.park_cap = park_cap;
-            W.ctr = ctr;
-            W.lane_stride = g.lane_stride;
-            W.uniform_index = uniform_index;
-            W.plain = plain;
-            if (!multi) W.S0 = *s0;
-            // reset the per-launch queue state, keep the walk counter (zero
-            // from the start of the run for the first launch)
-            if (local > 0) {
-                MW_HIP(hipMemset(&ctr->park_count, 0, 4));
-                MW_HIP(hipMemset(&ctr->resume_next, 0, 8));
-            }
-            MW_HIP(hipEventRecord(ev0, 0));
-            if (expand_m > 0) {
-                W.lane_stride = g.lane_stride_e;
-                W.expand_m = expand_m;
-                if (multi && n <= 16)
-                    frw_walk_kernel<true, true, true><<<g.blocks_e, WALK_THREADS, g.lds_e>>>(W);
-                else if (multi)
-                    frw_walk_kernel<true, true><<<g.blocks_e, WALK_THREADS, g.lds_e>>>(W);
-                else if (n <= 16)
-                    frw_walk_kernel<false, true, true><<<g.blocks_e, WALK_THREADS, g.lds_e>>>(W);
-                else
-                    frw_walk_kernel<false, true><<<g.blocks_e, WALK_THREADS, g.lds_e>>>(W);
-            } else if (multi) {
-                if (n <= 16)
-                    frw_walk_kernel<true, false, true><<<g.blocks, WALK_THREADS, g.lds>>>(W);
-                else
-                    frw_walk_kernel<true, false><<<g.blocks, WALK_THREADS, g.lds>>>(W);
-            } else {
-                if (n <= 16)
-                    frw_walk_kernel<false, false, true><<<g.blocks, WALK_THREADS, g.lds>>>(W);
-                else
-                    frw_walk_kernel<false, false><<<g.blocks, WALK_THREADS, g.lds>>>(W);
-            }
-            MW_HIP(hipGetLastError());
-            MW_HIP(hipEventRecord(ev1, 0));
-            ++launches;
-            Counters h{};
-            MW_HIP(hipMemcpy(&h, ctr, sizeof h, hipMemcpyDeviceToHost));
+        const size_t off = (char*)dsegs - (char*)ctr;
+        std::vector<char> staging(off + sizeof(Segment) * segs.size(), 0);
+        memcpy(staging.data() + off, segs.data(), sizeof(Segment) * segs.size());
+        MW_HIP(hipMemcpyAsync(ctr, staging.data(), staging.size(), hipMemcpyHostToDevice, stream));
+        MW_HIP(hipStreamSynchronize(stream));  // the staging buffer goes out of scope
+        return total;
+    }
+
+    Counters read_counters() {
+        Counters h{};
+        MW_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, stream));
+        MW_HIP(hipStreamSynchronize(stream));
+        if (walker_pending) {
             float ms = 0.f;
             MW_HIP(hipEventElapsedTime(&ms, ev0, ev1));
             walker_ms += ms;
-            check_errors(h);
-            MW_REQUIRE(local < 100000, MW_ELIMIT, "walker relaunch limit reached");
+            walker_pending = false;
+        }
+        return h;
+    }
+
+    // One first-transition launch (round 0: every walk, writing its done
+    // flag; later rounds: the walks still missing), without waiting.
+    void launch_first(const std::vector<Segment>& segs, const StructDev* s0, unsigned long long total, int round,
+                      const float4* eval) {
+        FirstArgs F{};
+        F.eval = eval;
+        F.segs = dsegs;
+        F.n_segs = (int)segs.size();
+        F.total = total;
+        F.cache = cache->d;
+        F.n = n;
+        F.ctr = ctr;
+        F.lane_stride = g.first_stride;
+        if (segs.size() == 1) F.S0 = *s0;
+        F.round = round;
+        if (round > 0) MW_HIP(hipMemsetAsync(&ctr->first_missing, 0, 4, stream));
+        const int fblocks = (int)std::min<uint64_t>((total + FRW_THREADS - 1) / FRW_THREADS, (uint64_t)g.first_blocks);
+        if (segs.size() == 1)
+            first_kernel<false><<<fblocks, FRW_THREADS, g.first_lds, stream>>>(F);
+        else
+            first_kernel<true><<<fblocks, FRW_THREADS, g.first_lds, stream>>>(F);
+        MW_HIP(hipGetLastError());
+    }
+
+    // One walker launch over the current run (fresh walks not yet taken and
+    // the n_resume parked walks in park[cur]), without waiting.
+    void launch_walker() {
+        const bool multi = !cur_single;
+        WalkArgs W{};
+        W.segs = dsegs;
+        W.n_segs = (int)cur_segs.size();
+        W.total = cur_total;
+        W.cache = cache->d;
+        W.n = n;
+        W.hybrid = hybrid;
+        W.resume = park[cur];
+        W.n_resume = n_resume;
+        W.park_out = park[cur ^ 1];
+        W.park_cap = park_cap;
+        W.ctr = ctr;
+        W.lane_stride = g.lane_stride;
+        W.uniform_index = uniform_index;
+        W.plain = plain;
+        if (!multi) W.S0 = cur_s0;
+        // one-wave blocks: the grid sets the resident waves per CU
+        const int blocks = waves_per_cu > 0 ? std::min(g.blocks, g.cus * waves_per_cu) : g.blocks;
+        const int blocks_e = waves_per_cu > 0 ? std::min(g.blocks_e, g.cus * waves_per_cu) : g.blocks_e;
+        MW_HIP(hipEventRecord(ev0, stream));
+        if (expand_m > 0) {
+            W.lane_stride = g.lane_stride_e;
+            W.expand_m = expand_m;
+            if (multi && n <= 16)
+                frw_walk_kernel<true, true, true><<<blocks_e, WALK_THREADS, g.lds_e, stream>>>(W);
+            else if (multi)
+                frw_walk_kernel<true, true><<<blocks_e, WALK_THREADS, g.lds_e, stream>>>(W);
+            else if (n <= 16)
+                frw_walk_kernel<false, true, true><<<blocks_e, WALK_THREADS, g.lds_e, stream>>>(W);
+            else
+                frw_walk_kernel<false, true><<<blocks_e, WALK_THREADS, g.lds_e, stream>>>(W);
+        } else if (multi) {
+            if (n <= 16)
+                frw_walk_kernel<true, false, true><<<blocks, WALK_THREADS, g.lds, stream>>>(W);
+            else
+                frw_walk_kernel<true, false><<<blocks, WALK_THREADS, g.lds, stream>>>(W);
+        } else {
+            if (n <= 16)
+                frw_walk_kernel<false, false, true><<<blocks, WALK_THREADS, g.lds, stream>>>(W);
+            else
+                frw_walk_kernel<false, false><<<blocks, WALK_THREADS, g.lds, stream>>>(W);
+        }
+        MW_HIP(hipGetLastError());
+        MW_HIP(hipEventRecord(ev1, stream));
+        walker_pending = true;
+        ++launches;
+    }
+
+    // Enqueues a run without waiting: counters and segments, the first
+    // transitions of every walk and one walker launch (walks whose first
+    // transition missed its table park until finish()).  The caller holds the
+    // cache lock and has called ensure_uniform_table().
+    void start(const std::vector<Segment>& segs, const StructDev* s0) {
+        cur_segs = segs;
+        cur_single = segs.size() == 1;
+        if (cur_single) cur_s0 = *s0;
+        cur_total = upload(segs, s0);
+        n_resume = 0;
+        cur = 0;
+        launch_first(cur_segs, &cur_s0, cur_total, 0, nullptr);
+        launch_walker();
+    }
+
+    // Waits for the started run and completes it: missing tables are built,
+    // first transitions that missed them are redone and parked walks resume,
+    // until every walk has ended.  Builds run with no other FRW work in
+    // flight on the device (the caller's guarantee).
+    Counters finish() { return finish_from(read_counters()); }
+
+    // finish() after the caller has read the counters of the first launch
+    Counters finish_from(Counters h) {
+        for (uint64_t local = 1;; ++local) {
+            after_launch(h);
+            if (h.first_missing > 0) {
+                build_pending();
+                first_rounds(cur_segs, &cur_s0, cur_total, nullptr, 1);
+                h = read_counters();
+            }
             // a lane that queued a table parked its walk
             if (h.park_count > 0) build_pending();
             n_resume = std::min(h.park_count, park_cap);
             cur ^= 1;
-            if (n_resume == 0 && h.walk_next >= total) return h;
+            if (n_resume == 0 && h.walk_next >= cur_total) return h;
+            MW_REQUIRE(local < 100000, MW_ELIMIT, "walker relaunch limit reached");
+            // reset the per-launch queue state, keep the walk counter
+            MW_HIP(hipMemsetAsync(&ctr->park_count, 0, 4, stream));
+            MW_HIP(hipMemsetAsync(&ctr->resume_next, 0, 8, stream));
+            launch_walker();
+            h = read_counters();
         }
+    }
+
+    // First-kernel rounds until no walk misses a table (eval: the kernel
+    // sums K / h at given points instead of sampling first transitions).
+    void first_rounds(const std::vector<Segment>& segs, const StructDev* s0, unsigned long long total,
+                      const float4* eval, int first_round = 0) {
+        for (int round = first_round;; ++round) {
+            launch_first(segs, s0, total, round, eval);
+            Counters h = read_counters();
+            after_launch(h);
+            MW_REQUIRE(round < 1000, MW_ELIMIT, "first-transition retry limit reached");
+            if (h.first_missing == 0) break;  // no walk missed a table, so none was queued
+            build_pending();
+        }
+    }
+
+    // K / h of the first-transition kernel at each point of eval (device,
+    // count entries, w = axis | side << 2 bits) on Gaussian surface G of
+    // structure s0; written to out[k].x (device).
+    void evaluate(const StructDev& s0, StructDev* dS, GaussDev* G, const float4* eval, uint64_t count, float4* out,
+                  uint32_t* done) {
+        std::lock_guard<std::mutex> lock(cache->mu);
+        flushes = 0;
+        ensure_uniform_table();
+        Segment sgm{};
+        sgm.S = dS;
+        sgm.G = G;
+        sgm.count = count;
+        sgm.first_state = out;
+        sgm.first_done = done;
+        const std::vector<Segment> segs{sgm};
+        first_rounds(segs, &s0, upload(segs, &s0), eval);
+    }
+
+    // Runs every walk of segs to its end (synchronous).  s0: host copy of
+    // the structure header of a single segment.
+    Counters run(const std::vector<Segment>& segs, const StructDev* s0) {
+        std::lock_guard<std::mutex> lock(cache->mu);
+        flushes = 0;
+        ensure_uniform_table();
+        start(segs, s0);
+        return finish();
     }
 };
 
@@ -3275,10 +3545,12 @@ namespace {
 // Returns 0, or 1 (no box), 2 (no positive gap), 3 (empty surface),
 // 4 (too many pieces).
 constexpr size_t GAUSS_MAX_FACES = 1 << 16;
+constexpr size_t GAUSS_MAX_PATCHES = 1 << 22;
 
 struct GaussHost {
     double g = 0, area = 0;
     std::vector<GaussFace> faces;
+    std::vector<double> rect;  // per rectangle: plane, lo, hi (lower tangent axis), lo, hi (higher), binary64
 };
 
 int gauss_surface(const mw_structure& st, int master, GaussHost& out) {
@@ -3373,6 +3645,7 @@ int gauss_surface(const mw_structure& st, int master, GaussHost& out) {
                         F.p = make_float4((float)p, (float)out.area, fbits, 0.f);
                         F.t = make_float4((float)cu[iu], (float)cu[iu + 1], (float)cv[iv], (float)cv[iv + 1]);
                         out.faces.push_back(F);
+                        out.rect.insert(out.rect.end(), {p, cu[iu], cu[iu + 1], cv[iv], cv[iv + 1]});
                     }
             }
     if (out.faces.empty()) return 3;
@@ -3407,6 +3680,10 @@ struct Extraction {
     size_t n_faces = 0;
     double gauss_g = 0, gauss_area = 0;
     StructDev hS{};  // host copy of the device structure header
+    std::vector<GaussFace> faces_h;  // the surface's rectangles (uniform sampling)
+    std::vector<double> rect_h;      // their binary64 bounds
+    char* patch_mem = nullptr;       // importance-sampling patches (device)
+    size_t n_patches = 0;
 
     Extraction(const mw_structure& st, int master_, double abs_tol_rel, uint64_t chunk_cap_, bool own_scores,
                bool own_first = true)
@@ -3419,6 +3696,10 @@ struct Extraction {
         n_faces = GH.faces.size();
         gauss_g = GH.g;
         gauss_area = GH.area;
+        // uniform sampling: every rectangle's weight factor is |G|
+        for (GaussFace& F : GH.faces) F.p.w = (float)GH.area;
+        faces_h = GH.faces;
+        rect_h = GH.rect;
         size_t o = 0;
         auto sz = [&](size_t b) {
             size_t r = o;
@@ -3459,37 +3740,151 @@ struct Extraction {
         memcpy(staging.data(), &S, sizeof S);
         memcpy(staging.data() + (o_G - o_sd), &Gh, sizeof Gh);
         memcpy(staging.data() + (o_gf - o_sd), GH.faces.data(), sizeof(GaussFace) * n_faces);
-        MW_HIP(hipMemcpy(mem + o_sd, staging.data(), staging.size(), hipMemcpyHostToDevice));
+        hipStream_t cs = setup_stream();
+        MW_HIP(hipMemcpyAsync(mem + o_sd, staging.data(), staging.size(), hipMemcpyHostToDevice, cs));
+        MW_HIP(hipStreamSynchronize(cs));
         res.assign(2 * K, 0.0);
     }
-    ~Extraction() { dev_free(mem); }
+    ~Extraction() {
+        dev_free(patch_mem);
+        dev_free(mem);
+    }
+
+    // Importance sampling of the Gaussian-surface point (the first
+    // transition of Alg. 1 is importance sampling with its weight): each
+    // rectangle is cut into nu x nv equal patches, nu = ceil(length / edge),
+    // and patch p is drawn with probability q_p / Q, q_p = area_p K(c_p) / h
+    // (the first-transition kernel sum at the patch centre, evaluated by the
+    // first-transition kernel itself), then a uniform point on it; the
+    // walk's weight uses Q area_p / q_p in place of |G|, so the estimator is
+    // unchanged in expectation.
+    void importance(Runner& R, double edge) {
+        std::vector<double> pb;  // plane, u0, u1, v0, v1 per patch
+        std::vector<uint32_t> bits;
+        for (size_t f = 0; f < faces_h.size(); ++f) {
+            const double* r = &rect_h[5 * f];
+            const double la = r[2] - r[1], lb = r[4] - r[3];
+            const int nu = std::max(1, (int)std::ceil(la / edge)), nv = std::max(1, (int)std::ceil(lb / edge));
+            MW_REQUIRE((double)nu * nv + (double)bits.size() <= (double)GAUSS_MAX_PATCHES, MW_ELIMIT,
+                       "importance sampling needs more than %zu patches", GAUSS_MAX_PATCHES);
+            uint32_t fb;
+            memcpy(&fb, &faces_h[f].p.z, 4);
+            for (int j = 0; j < nv; ++j)
+                for (int i = 0; i < nu; ++i) {
+                    pb.insert(pb.end(), {r[0], r[1] + la * i / nu, r[1] + la * (i + 1) / nu, r[3] + lb * j / nv,
+                                         r[3] + lb * (j + 1) / nv});
+                    bits.push_back(fb);
+                }
+        }
+        const size_t np = bits.size();
+        dev_free(patch_mem);
+        patch_mem = nullptr;
+        const size_t o_eval = 0, o_out = o_eval + 16 * np, o_done = o_out + 16 * np;
+        const size_t o_faces = (o_done + 4 * np + 255) / 256 * 256;
+        patch_mem = (char*)dev_alloc(o_faces + sizeof(GaussFace) * np);
+        std::vector<float4> ev(np);
+        for (size_t k = 0; k < np; ++k) {
+            const double* q = &pb[5 * k];
+            const int a = (int)(bits[k] & 3u);
+            const int ta = a == 0 ? 1 : 0, tb = a == 2 ? 1 : 2;
+            double c[3];
+            c[a] = q[0];
+            c[ta] = 0.5 * (q[1] + q[2]);
+            c[tb] = 0.5 * (q[3] + q[4]);
+            float fb;
+            memcpy(&fb, &bits[k], 4);
+            ev[k] = make_float4((float)c[0], (float)c[1], (float)c[2], fb);
+        }
+        MW_HIP(hipMemcpy(patch_mem + o_eval, ev.data(), 16 * np, hipMemcpyHostToDevice));
+        R.evaluate(hS, dS, G, (const float4*)(patch_mem + o_eval), np, (float4*)(patch_mem + o_out),
+                   (uint32_t*)(patch_mem + o_done));
+        std::vector<float4> kv(np);
+        MW_HIP(hipMemcpy(kv.data(), patch_mem + o_out, 16 * np, hipMemcpyDeviceToHost));
+        std::vector<double> q(np);
+        double Q = 0;
+        for (size_t k = 0; k < np; ++k) {
+            const double* b = &pb[5 * k];
+            const double area = (b[2] - b[1]) * (b[4] - b[3]);
+            q[k] = area * (double)kv[k].x;
+            MW_REQUIRE(q[k] > 0, MW_EDEVICE, "importance-sampling patch %zu has no weight", k);
+            Q += q[k];
+        }
+        std::vector<GaussFace> F(np);
+        double cum = 0;
+        for (size_t k = 0; k < np; ++k) {
+            const double* b = &pb[5 * k];
+            const double area = (b[2] - b[1]) * (b[4] - b[3]);
+            cum += q[k];
+            float fb;
+            memcpy(&fb, &bits[k], 4);
+            F[k].p = make_float4((float)b[0], (float)cum, fb, (float)(Q * area / q[k]));
+            F[k].t = make_float4((float)b[1], (float)b[2], (float)b[3], (float)b[4]);
+        }
+        MW_HIP(hipMemcpy(patch_mem + o_faces, F.data(), sizeof(GaussFace) * np, hipMemcpyHostToDevice));
+        GaussDev Gh{};
+        Gh.g = (float)gauss_g;
+        Gh.area = (float)Q;
+        Gh.n_faces = (int32_t)np;
+        Gh.faces = (const GaussFace*)(patch_mem + o_faces);
+        MW_HIP(hipMemcpy(G, &Gh, sizeof Gh, hipMemcpyHostToDevice));
+        n_patches = np;
+    }
 
     // Segment for walks [first, first + count) writing scores to net/w (or
-    // the extraction's own buffers).
-    Segment segment(uint64_t first, uint64_t count, uint64_t seed, int32_t* net, float* w) {
-        MW_REQUIRE(count <= chunk_cap, MW_EINVAL, "chunk larger than its buffers");
+    // the extraction's own buffers from entry `at` on).
+    Segment segment(uint64_t first, uint64_t count, uint64_t seed, int32_t* net, float* w, uint64_t at = 0) {
+        MW_REQUIRE(at + count <= chunk_cap, MW_EINVAL, "chunk larger than its buffers");
         Segment s{};
         s.S = dS;
         s.G = G;
         s.walk_begin = first;
         s.count = count;
-        s.score_net = net ? net : score_net;
-        s.score_w = w ? w : score_w;
-        s.first_state = first_state;
-        s.first_done = first_done;
+        s.score_net = net ? net : score_net + at;
+        s.score_w = w ? w : score_w + at;
+        s.first_state = first_state + at;
+        s.first_done = first_done + at;
         s.k0 = (uint32_t)seed;
         s.k1 = (uint32_t)(seed >> 32);
         return s;
     }
 
-    // Adds the scores of a finished segment to the fp64 sums; refreshes res.
-    void reduce(const Segment& s) {
+    // Adds the scores of a finished segment to the fp64 sums (segments in
+    // walk order); refreshes res.
+    void reduce(const Segment& s, hipStream_t stream = nullptr) {
         const int rb = (int)((s.count + RED_CHUNK - 1) / RED_CHUNK);
         done += s.count;
-        reduce_scores_kernel<<<rb, RED_THREADS>>>(s.score_net, s.score_w, s.count, K, partial);
-        finish_kernel<<<K, FIN_THREADS>>>(partial, rb, K, acc, (double)done, result);
+        reduce_scores_kernel<<<rb, RED_THREADS, 0, stream>>>(s.score_net, s.score_w, s.count, K, partial);
+        finish_kernel<<<K, FIN_THREADS, 0, stream>>>(partial, rb, K, acc, (double)done, result, nullptr, 0ull);
         MW_HIP(hipGetLastError());
-        MW_HIP(hipMemcpy(res.data(), result, sizeof(double) * 2 * K, hipMemcpyDeviceToHost));
+        MW_HIP(hipMemcpyAsync(res.data(), result, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, stream));
+        MW_HIP(hipStreamSynchronize(stream));
+    }
+
+    // One batch with a single wait in the usual case: the walks, then the
+    // reduction gated on the walker's counters and one copy of the row and
+    // the counters.  When a walk parked or a first transition missed its
+    // table the gate drops the sums; the batch is then completed and reduced
+    // as usual.
+    Counters run_batch(Runner& R, const Segment& sg) {
+        R.start({sg}, &hS);
+        const int rb = (int)((sg.count + RED_CHUNK - 1) / RED_CHUNK);
+        reduce_scores_kernel<<<rb, RED_THREADS, 0, R.stream>>>(sg.score_net, sg.score_w, sg.count, K, partial);
+        finish_kernel<<<K, FIN_THREADS, 0, R.stream>>>(partial, rb, K, acc, (double)(done + sg.count), result, R.ctr,
+                                                        sg.count);
+        MW_HIP(hipGetLastError());
+        Counters h{};
+        std::vector<double> row(2 * K);
+        MW_HIP(hipMemcpyAsync(row.data(), result, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, R.stream));
+        h = R.read_counters();  // waits for the stream
+        if (h.park_count == 0 && h.first_missing == 0 && h.walk_next >= sg.count && !(h.err & ERR_TABLE_CAP)) {
+            R.check_errors(h);
+            done += sg.count;
+            res = row;
+            return h;
+        }
+        h = R.finish_from(h);
+        reduce(sg, R.stream);
+        return h;
     }
 
     bool converged(double target) const {
@@ -3508,6 +3903,8 @@ frw_options normalised_options(const frw_options* options) {
                "n_cells must be even in [4, 32]");
     if (opt.abs_tol_rel <= 0) opt.abs_tol_rel = 1e-6;
     MW_REQUIRE(opt.plain == 0 || opt.plain == 1, MW_EINVAL, "plain must be 0 or 1");
+    MW_REQUIRE(opt.gauss_is == 0 || (opt.gauss_is >= 0.05 && opt.gauss_is <= 64), MW_EINVAL,
+               "gauss_is must be 0 or in [0.05, 64]");
     MW_REQUIRE(opt.expand >= 0 && opt.expand <= 64, MW_EINVAL, "expand must be in [0, 64]");
     if (opt.expand > 1) {
         const int m = std::max(1, (int)std::lround(opt.n_cells / (2.0 * opt.expand)));
@@ -3692,13 +4089,19 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         Runner R(n, opt.hybrid, batch, 1);
         R.expand_m = expand_m_of(opt);
         R.plain = opt.plain;
+        (void)frw_tuned_waves(n, R.expand_m, &R.waves_per_cu);
+        if (opt.gauss_is > 0) X.importance(R, opt.gauss_is * X.gauss_g);
         frw_stats acc{};
         while (X.done < walk_budget) {
             const uint64_t nb = std::min<uint64_t>(batch, walk_budget - X.done);
             const Segment sgm = X.segment(opt.first_walk + X.done, nb, seed, own_scores ? nullptr : score_net + X.done,
                                           own_scores ? nullptr : score_w + X.done);
-            add_counters(acc, R.run({sgm}, &X.hS));
-            X.reduce(sgm);
+            {
+                std::lock_guard<std::mutex> lock(R.cache->mu);
+                R.flushes = 0;
+                R.ensure_uniform_table();
+                add_counters(acc, X.run_batch(R, sgm));
+            }
             if (X.converged(opt.target_rel_3sigma)) break;
         }
         const int K = X.K;
@@ -3717,6 +4120,49 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
             stats->gauss_area = X.gauss_area;
             stats->gauss_faces = X.n_faces;
         }
+    });
+}
+
+// Walker launch geometry: times the walker on `walks` walks of this
+// extraction at several resident-wave counts per CU and keeps the fastest for
+// the lattice size and MicroWalk-E setting of the options.
+extern "C" mw_status frw_autotune(mw_structure* st, int32_t master, uint64_t walks, uint64_t seed,
+                                  const frw_options* options, int32_t* waves_per_cu) {
+    return guarded([&] {
+        MW_REQUIRE(st && waves_per_cu, MW_EINVAL, "null argument");
+        MW_REQUIRE(master >= 0 && master < st->n_nets, MW_EINVAL, "master %d out of range", master);
+        MW_REQUIRE(walks >= 1024, MW_EINVAL, "autotune needs at least 1024 walks");
+        frw_options opt = normalised_options(options);
+        const int n = opt.n_cells;
+        const int em = expand_m_of(opt);
+        const LaunchGeom g = launch_geom(n);
+        const int most = (em > 0 ? g.blocks_e : g.blocks) / g.cus;
+        std::vector<int> cand;
+        for (int w : {4, 6, 8, 10, 12, 16})
+            if (w < most) cand.push_back(w);
+        cand.push_back(most);
+        Extraction X(*st, master, opt.abs_tol_rel, walks, true);
+        double best_ms = 1e30;
+        int best = most;
+        for (int w : cand) {
+            Runner R(n, opt.hybrid, walks, 1);
+            R.expand_m = em;
+            R.waves_per_cu = w;
+            double t = 1e30;
+            for (int rep = 0; rep < 3; ++rep) {
+                // the first pass also builds the tables the walks need
+                const Segment sgm = X.segment(opt.first_walk, walks, seed, nullptr, nullptr);
+                const double before = R.walker_ms;
+                (void)R.run({sgm}, &X.hS);
+                if (rep > 0) t = std::min(t, R.walker_ms - before);
+            }
+            if (t < best_ms) {
+                best_ms = t;
+                best = w;
+            }
+        }
+        frw_store_waves(n, em, best);
+        *waves_per_cu = best;
     });
 }
 
@@ -3755,6 +4201,9 @@ extern "C" mw_status frw_extract_matrix(mw_structure* st, int32_t n_masters, con
         Runner R(n, opt.hybrid, round_walks, n_masters);
         R.expand_m = expand_m_of(opt);
         R.plain = opt.plain;
+        (void)frw_tuned_waves(n, R.expand_m, &R.waves_per_cu);
+        if (opt.gauss_is > 0)
+            for (Extraction* x : X) x->importance(R, opt.gauss_is * x->gauss_g);
         SharedRound round(round_walks, n_masters);
         frw_stats acc{};
         std::vector<bool> active(n_masters, true);
@@ -3853,15 +4302,18 @@ struct mw_server {
     frw_options opt{};
     size_t max_queue = 100000;
     int max_slots = 256;
+    int max_ready = 8;  // requests prepared ahead of the rounds
     uint64_t round_walks = 0;
     std::mutex mu;
     std::condition_variable cv;
     bool stop = false;
-    std::deque<std::shared_ptr<ServerRequest>> queue;
+    std::deque<std::shared_ptr<ServerRequest>> queue;  // submitted, not yet on the device
+    std::deque<std::shared_ptr<ServerRequest>> ready;  // structure and buffers on the device
     std::map<uint64_t, std::shared_ptr<ServerRequest>> tickets;
     uint64_t next_ticket = 1;
     mw_server_stats st{};
-    std::thread worker;
+    std::thread worker, preparer;
+    bool preparing = false;  // the preparation thread holds a request
 
     void fail(const std::shared_ptr<ServerRequest>& r, mw_status code, const std::string& msg) {
         r->state = ServerRequest::FAILED;
@@ -3874,24 +4326,102 @@ struct mw_server {
     std::unique_ptr<SharedRound> round;  // buffers of one round (first round on)
 
     // Walk shares of one round (capacity round_walks): the longest-admitted
-    // request gets up to half, the rest goes to the requests with the fewest
-    // remaining walks first.
+    // request gets up to three quarters, the rest goes to the requests with
+    // the fewest remaining walks first, and capacity they leave goes back to
+    // the longest-admitted one (which alone gets the whole round).
     std::vector<uint64_t> shares(const std::vector<std::shared_ptr<ServerRequest>>& running) const {
         const size_t m = running.size();
         std::vector<uint64_t> sh(m, 0), rem(m);
         for (size_t i = 0; i < m; ++i) rem[i] = running[i]->budget - running[i]->X->done;
-        uint64_t used = std::min<uint64_t>(rem[0], round_walks / 2);
+        uint64_t used = std::min<uint64_t>(rem[0], round_walks / 4 * 3);
         sh[0] = used;
         std::vector<size_t> order(m);
         for (size_t i = 0; i < m; ++i) order[i] = i;
         std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return rem[a] < rem[b]; });
         for (size_t i : order) {
             if (used >= round_walks) break;
+            if (i == 0) continue;
             const uint64_t take = std::min<uint64_t>(rem[i] - sh[i], round_walks - used);
             sh[i] += take;
             used += take;
         }
+        sh[0] += std::min<uint64_t>(rem[0] - sh[0], round_walks - used);
         return sh;
+    }
+
+    // Preparation thread: in arrival order, while the memory budget allows,
+    // copies each request's structure to the device and builds its grid
+    // index and extraction buffers (on a non-blocking stream, overlapping
+    // the rounds), then hands it to the round worker.
+    void prepare_loop() {
+        (void)hipSetDevice(device);
+        for (;;) {
+            std::shared_ptr<ServerRequest> r;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                for (;;) {
+                    if (stop) {
+                        for (auto& q : queue) fail(q, MW_EBUSY, "server destroyed before the request ran");
+                        queue.clear();
+                        cv.notify_all();
+                        return;
+                    }
+                    if (!queue.empty()) {
+                        auto& f = queue.front();
+                        if (f->footprint > budget) {
+                            fail(f, MW_ELIMIT, "request footprint exceeds the server's memory budget");
+                            queue.pop_front();
+                            cv.notify_all();
+                            continue;
+                        }
+                        if ((int)ready.size() < max_ready && st.resident_bytes + f->footprint <= budget) break;
+                    }
+                    cv.wait(lk);
+                }
+                r = queue.front();
+                queue.pop_front();
+                preparing = true;
+                st.resident_bytes += r->footprint;
+                st.max_resident_bytes = std::max(st.max_resident_bytes, st.resident_bytes);
+            }
+            mw_status rc = mw_structure_create(&r->desc, &r->st);
+            std::string msg = rc ? mw_last_error() : "";
+            if (rc == MW_OK) {
+                rc = guarded([&] {
+                    r->X = std::make_unique<Extraction>(*r->st, r->master, opt.abs_tol_rel, round_walks, false,
+                                                        false);
+                });
+                if (rc) msg = mw_last_error();
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            preparing = false;
+            if (rc != MW_OK) {
+                r->release();
+                st.resident_bytes -= r->footprint;
+                fail(r, rc, msg);
+                cv.notify_all();
+                continue;
+            }
+            // reconcile the reservation with the memory actually held; a
+            // request that no longer fits waits at the queue's head
+            const size_t actual = r->st->bytes + Extraction::bytes(r->X->K, round_walks, false, r->X->n_faces);
+            if (actual > r->footprint && st.resident_bytes - r->footprint + actual > budget) {
+                r->release();
+                st.resident_bytes -= r->footprint;
+                r->footprint = actual;
+                if (actual > budget)
+                    fail(r, MW_ELIMIT, "request footprint exceeds the server's memory budget");
+                else
+                    queue.push_front(r);
+                cv.notify_all();
+                continue;
+            }
+            st.resident_bytes += actual - r->footprint;
+            r->footprint = actual;
+            st.max_resident_bytes = std::max(st.max_resident_bytes, st.resident_bytes);
+            ready.push_back(r);
+            cv.notify_all();
+        }
     }
 
     void loop() {
@@ -3899,73 +4429,31 @@ struct mw_server {
         std::unique_ptr<Runner> R;
         std::vector<std::shared_ptr<ServerRequest>> running;
         for (;;) {
-            std::vector<std::shared_ptr<ServerRequest>> admitted;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                while (!stop && queue.empty() && running.empty()) cv.wait(lk);
+                // an idle device waits for the request being prepared, so
+                // that requests submitted together share their first round
+                while (!stop && running.empty() && (ready.empty() || (preparing && (int)ready.size() < max_ready)))
+                    cv.wait(lk);
                 if (stop && running.empty()) {
-                    for (auto& r : queue) fail(r, MW_EBUSY, "server destroyed before the request ran");
-                    queue.clear();
+                    // prepared requests that never ran give their memory back
+                    for (auto& r : ready) {
+                        r->release();
+                        st.resident_bytes -= r->footprint;
+                        fail(r, MW_EBUSY, "server destroyed before the request ran");
+                    }
+                    ready.clear();
                     cv.notify_all();
                     return;
                 }
-                // admission by device footprint
-                while (!stop && !queue.empty() && (int)(running.size() + admitted.size()) < max_slots) {
-                    auto r = queue.front();
-                    if (r->footprint > budget) {
-                        queue.pop_front();
-                        fail(r, MW_ELIMIT, "request footprint exceeds the server's memory budget");
-                        continue;
-                    }
-                    if (st.resident_bytes + r->footprint > budget) break;
-                    queue.pop_front();
-                    st.resident_bytes += r->footprint;
-                    st.max_resident_bytes = std::max(st.max_resident_bytes, st.resident_bytes);
+                // continuous admission: every prepared request joins the next round
+                while (!stop && !ready.empty() && (int)running.size() < max_slots) {
+                    auto r = ready.front();
+                    ready.pop_front();
                     r->state = ServerRequest::RUNNING;
-                    admitted.push_back(r);
-                }
-            }
-            for (auto& r : admitted) {
-                mw_status rc = mw_structure_create(&r->desc, &r->st);
-                std::string msg = rc ? mw_last_error() : "";
-                if (rc == MW_OK) {
-                    rc = guarded([&] {
-                        r->X = std::make_unique<Extraction>(*r->st, r->master, opt.abs_tol_rel, round_walks, false,
-                                                            false);
-                    });
-                    if (rc) msg = mw_last_error();
-                }
-                if (rc != MW_OK) {
-                    r->release();
-                    std::lock_guard<std::mutex> lk(mu);
-                    st.resident_bytes -= r->footprint;
-                    fail(r, rc, msg);
-                    cv.notify_all();
-                } else {
-                    // reconcile the reservation with the memory actually held;
-                    // a request that no longer fits waits at the queue's head
-                    const size_t actual = r->st->bytes + Extraction::bytes(r->X->K, round_walks, false, r->X->n_faces);
-                    std::lock_guard<std::mutex> lk(mu);
-                    if (actual > r->footprint) {
-                        if (st.resident_bytes - r->footprint + actual > budget) {
-                            r->release();
-                            st.resident_bytes -= r->footprint;
-                            r->footprint = actual;
-                            if (actual > budget) {
-                                fail(r, MW_ELIMIT, "request footprint exceeds the server's memory budget");
-                            } else {
-                                r->state = ServerRequest::QUEUED;
-                                queue.push_front(r);
-                            }
-                            cv.notify_all();
-                            continue;
-                        }
-                        st.resident_bytes += actual - r->footprint;
-                        r->footprint = actual;
-                        st.max_resident_bytes = std::max(st.max_resident_bytes, st.resident_bytes);
-                    }
                     running.push_back(r);
                 }
+                cv.notify_all();
             }
             if (running.empty()) continue;
             // one round over the shares of the running requests
@@ -3986,7 +4474,11 @@ struct mw_server {
                     R = std::make_unique<Runner>(opt.n_cells, opt.hybrid, round_walks, max_slots);
                     R->expand_m = expand_m_of(opt);
                     R->plain = opt.plain;
+                    (void)frw_tuned_waves(opt.n_cells, R->expand_m, &R->waves_per_cu);
                 }
+                if (opt.gauss_is > 0)
+                    for (auto& r : running)
+                        if (!r->X->n_patches) r->X->importance(*R, opt.gauss_is * r->X->gauss_g);
                 (void)round->run(*R, X, sh, seeds, opt.first_walk);
                 for (auto& r : running) {
                     r->stats.walks = r->X->done;
@@ -3996,31 +4488,39 @@ struct mw_server {
                 }
             });
             std::string msg = rc ? mw_last_error() : "";
-            std::lock_guard<std::mutex> lk(mu);
-            st.rounds++;
-            st.walks += walks;
-            st.max_concurrent = std::max<uint64_t>(st.max_concurrent, n_run);
-            std::vector<std::shared_ptr<ServerRequest>> still;
-            for (size_t i = 0; i < running.size(); ++i) {
-                auto& r = running[i];
-                if (rc != MW_OK) {
-                    fail(r, rc, msg);
-                } else if (r->X->done >= r->budget || (sh[i] && r->X->converged(opt.target_rel_3sigma))) {
-                    const int K = r->X->K;
-                    r->row.assign(r->X->res.begin(), r->X->res.begin() + K);
-                    r->se.assign(r->X->res.begin() + K, r->X->res.end());
-                    r->state = ServerRequest::DONE;
-                    r->t_done = std::chrono::steady_clock::now();
-                    st.completed++;
-                } else {
-                    still.push_back(r);
-                    continue;
+            std::vector<std::shared_ptr<ServerRequest>> still, finished;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                st.rounds++;
+                st.walks += walks;
+                st.max_concurrent = std::max<uint64_t>(st.max_concurrent, n_run);
+                for (size_t i = 0; i < running.size(); ++i) {
+                    auto& r = running[i];
+                    if (rc != MW_OK) {
+                        fail(r, rc, msg);
+                    } else if (r->X->done >= r->budget || (sh[i] && r->X->converged(opt.target_rel_3sigma))) {
+                        const int K = r->X->K;
+                        r->row.assign(r->X->res.begin(), r->X->res.begin() + K);
+                        r->se.assign(r->X->res.begin() + K, r->X->res.end());
+                        r->state = ServerRequest::DONE;
+                        r->t_done = std::chrono::steady_clock::now();
+                        st.completed++;
+                    } else {
+                        still.push_back(r);
+                        continue;
+                    }
+                    finished.push_back(r);
                 }
-                r->release();
-                st.resident_bytes -= r->footprint;
+                cv.notify_all();
+            }
+            // device memory of finished requests is freed outside the lock
+            for (auto& r : finished) r->release();
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                for (auto& r : finished) st.resident_bytes -= r->footprint;
+                cv.notify_all();
             }
             running.swap(still);
-            cv.notify_all();
         }
     }
 };
@@ -4034,9 +4534,10 @@ extern "C" mw_status mw_server_create(size_t hbm_budget_bytes, const frw_options
         s->budget = hbm_budget_bytes;
         s->opt = normalised_options(options);
         const LaunchGeom g = launch_geom(s->opt.n_cells);
-        s->round_walks = std::max<uint64_t>(8 * g.pool, 1 << 21);
+        s->round_walks = std::max<uint64_t>(32 * g.pool, 1 << 23);
         mw_server* raw = s.get();
         s->worker = std::thread([raw] { raw->loop(); });
+        s->preparer = std::thread([raw] { raw->prepare_loop(); });
         *out = s.release();
     });
 }
@@ -4127,6 +4628,7 @@ extern "C" mw_status mw_server_destroy(mw_server* srv) {
             srv->stop = true;
         }
         srv->cv.notify_all();
+        if (srv->preparer.joinable()) srv->preparer.join();
         if (srv->worker.joinable()) srv->worker.join();
         delete srv;
     });

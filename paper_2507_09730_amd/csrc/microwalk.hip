@@ -234,80 +234,115 @@ __device__ __forceinline__ int select_delta(uint32_t u, uint32_t t0, uint32_t t1
     return delta;
 }
 
-template <int FORM>
+// Walks of one work item [wb, we) of cube C, WPL interleaved walks per lane:
+// each lane holds WPL walk slots and steps every live one per Philox block,
+// so the slots' dependent chains (table load, compare, move) overlap.  Free
+// slots are refilled wave-wide every groups_per_refill blocks; a walk's
+// result depends only on its index, not on the lane or slot that runs it.
+template <int FORM, int WPL>
 __device__ void run_item(const CubeDev& C, const uint32_t* tab, uint64_t wb, uint64_t we, uint32_t* s_next,
                          uint32_t k0, uint32_t k1, int groups_per_refill, unsigned long long& my_steps) {
     const int lane = threadIdx.x & 63;
     const int P = C.P, P2 = C.P * C.P;
     const uint64_t cnt = we - wb;
-    bool active = false;
-    int node = 0;
-    uint32_t s = 0;
-    uint64_t rel = 0;
-    NodeT T{};
-    NodeS S{};
-    for (;;) {
-        const bool want = !active;
-        const uint64_t bal = __ballot(want);
-        if (bal) {
-            const int leader = __ffsll((unsigned long long)bal) - 1;
-            uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(s_next, (uint32_t)__popcll(bal));
-            base = __shfl(base, leader);
-            const uint32_t rank = __popcll(bal & ((1ull << lane) - 1ull));
-            if (want && (uint64_t)base + rank < cnt) {
-                active = true;
-                rel = wb + base + rank;
-                s = 0;
-                node = C.start;
-                if (FORM == FORM_CODES)
-                    load_s(tab, P, node, S);
-                else
-                    T = load_t<FORM>(tab, C.t4_words, node);
-            }
-        }
-        if (!__any(active)) break;
-        for (int g = 0; g < groups_per_refill; ++g) {
-            if (active) {
-                const uint64_t walk = C.walk0 + rel;
-                const Rand4 r = philox10(s >> 2, C.c1, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), k0, k1);
-                const uint32_t us[4] = {r.x, r.y, r.z, r.w};
-                bool alive = true;
+    bool active[WPL];
+    int node[WPL];
+    uint32_t s[WPL];
+    uint64_t rel[WPL];
+    NodeT T[WPL];
+    NodeS S[WPL];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (alive) {
-                        int delta;
-                        if (FORM == FORM_CODES) {
-                            const uint32_t x = __umulhi(us[q], S.s5);
-                            delta = select_delta(x, S.s0, S.s1, S.s2, S.s3, S.s4, P, P2);
-                        } else {
-                            delta = select_delta(us[q], T.t0, T.t1, T.t2, T.t3, T.t4, P, P2);
-                        }
-                        node += delta;
-                        ++s;
-                        if (FORM == FORM_CODES) {
-                            alive = load_s(tab, P, node, S);
-                        } else {
-                            T = load_t<FORM>(tab, C.t4_words, node);
-                            alive = T.t4 != 0;
+    for (int w = 0; w < WPL; ++w) {
+        active[w] = false;
+        node[w] = 0;
+        s[w] = 0;
+        rel[w] = 0;
+        T[w] = NodeT{};
+        S[w] = NodeS{};
+    }
+    for (;;) {
+        bool any = false;
+#pragma unroll
+        for (int w = 0; w < WPL; ++w) {
+            const bool want = !active[w];
+            const uint64_t bal = __ballot(want);
+            if (bal) {
+                const int leader = __ffsll((unsigned long long)bal) - 1;
+                uint32_t base = 0;
+                if (lane == leader) base = atomicAdd(s_next, (uint32_t)__popcll(bal));
+                base = __shfl(base, leader);
+                const uint32_t rank = __popcll(bal & ((1ull << lane) - 1ull));
+                if (want && (uint64_t)base + rank < cnt) {
+                    active[w] = true;
+                    rel[w] = wb + base + rank;
+                    s[w] = 0;
+                    node[w] = C.start;
+                    if (FORM == FORM_CODES)
+                        load_s(tab, P, node[w], S[w]);
+                    else
+                        T[w] = load_t<FORM>(tab, C.t4_words, node[w]);
+                }
+            }
+            any |= active[w];
+        }
+        if (!__any(any)) break;
+        for (int g = 0; g < groups_per_refill; ++g) {
+#pragma unroll
+            for (int w = 0; w < WPL; ++w) {
+                if (active[w]) {
+                    const uint64_t walk = C.walk0 + rel[w];
+                    const Rand4 r = philox10(s[w] >> 2, C.c1, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), k0, k1);
+                    const uint32_t us[4] = {r.x, r.y, r.z, r.w};
+                    bool alive = true;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (alive) {
+                            int delta;
+                            if (FORM == FORM_CODES) {
+                                const uint32_t x = __umulhi(us[q], S[w].s5);
+                                delta = select_delta(x, S[w].s0, S[w].s1, S[w].s2, S[w].s3, S[w].s4, P, P2);
+                            } else {
+                                delta = select_delta(us[q], T[w].t0, T[w].t1, T[w].t2, T[w].t3, T[w].t4, P, P2);
+                            }
+                            node[w] += delta;
+                            ++s[w];
+                            if (FORM == FORM_CODES) {
+                                alive = load_s(tab, P, node[w], S[w]);
+                            } else {
+                                T[w] = load_t<FORM>(tab, C.t4_words, node[w]);
+                                alive = T[w].t4 != 0;
+                            }
                         }
                     }
-                }
-                if (!alive || s >= STEP_CAP) {
-                    gpw(C.hits)[rel] = alive ? -1 : hit_index(C, node);
-                    if (C.steps) gpw(C.steps)[rel] = (int32_t)s;
-                    my_steps += s;
-                    active = false;
+                    if (!alive || s[w] >= STEP_CAP) {
+                        gpw(C.hits)[rel[w]] = alive ? -1 : hit_index(C, node[w]);
+                        if (C.steps) gpw(C.steps)[rel[w]] = (int32_t)s[w];
+                        my_steps += s[w];
+                        active[w] = false;
+                    }
                 }
             }
         }
     }
 }
 
+template <int FORM>
+__device__ __forceinline__ void run_item_wpl(int wpl, const CubeDev& C, const uint32_t* tab, uint64_t wb,
+                                             uint64_t we, uint32_t* s_next, uint32_t k0, uint32_t k1,
+                                             int groups_per_refill, unsigned long long& my_steps) {
+    if (wpl >= 4)
+        run_item<FORM, 4>(C, tab, wb, we, s_next, k0, k1, groups_per_refill, my_steps);
+    else if (wpl == 2)
+        run_item<FORM, 2>(C, tab, wb, we, s_next, k0, k1, groups_per_refill, my_steps);
+    else
+        run_item<FORM, 1>(C, tab, wb, we, s_next, k0, k1, groups_per_refill, my_steps);
+}
+
 __global__ void __launch_bounds__(1024) walk_kernel(const CubeDev* __restrict__ cubes, const Item* __restrict__ items,
                                                     int32_t n_items, uint64_t item_walks, int32_t* item_counter,
                                                     const unsigned long long* __restrict__ seed_dev,
-                                                    int32_t groups_per_refill, unsigned long long* step_total) {
+                                                    int32_t groups_per_refill, unsigned long long* step_total,
+                                                    int32_t wpl) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const unsigned long long seed = *seed_dev;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -342,11 +377,12 @@ __global__ void __launch_bounds__(1024) walk_kernel(const CubeDev* __restrict__ 
         }
         // separate call sites keep the LDS table in the LDS address space
         if (C.form == FORM_CODES)
-            run_item<FORM_CODES>(C, lds, I.w_begin, I.w_end, &s_next, k0, k1, groups_per_refill, my_steps);
+            run_item_wpl<FORM_CODES>(wpl, C, lds, I.w_begin, I.w_end, &s_next, k0, k1, groups_per_refill, my_steps);
         else if (C.form == FORM_TLDS)
-            run_item<FORM_TLDS>(C, lds, I.w_begin, I.w_end, &s_next, k0, k1, groups_per_refill, my_steps);
+            run_item_wpl<FORM_TLDS>(wpl, C, lds, I.w_begin, I.w_end, &s_next, k0, k1, groups_per_refill, my_steps);
         else
-            run_item<FORM_TGLOBAL>(C, C.table, I.w_begin, I.w_end, &s_next, k0, k1, groups_per_refill, my_steps);
+            run_item_wpl<FORM_TGLOBAL>(wpl, C, C.table, I.w_begin, I.w_end, &s_next, k0, k1, groups_per_refill,
+                                       my_steps);
         __syncthreads();
     }
     // device-counted micro-steps
@@ -443,14 +479,16 @@ struct Launch {
     int waves;
     int groups;
     uint64_t item_walks;
+    int wpl;  // interleaved walks per lane
 };
 
 Launch default_launch(const mw_tune* t, uint64_t total_walks) {
-    Launch L{16, 2, 0};
+    Launch L{16, 2, 0, 1};
     if (t) {
         if (t->waves_per_wg > 0) L.waves = std::min(16, std::max(1, (int)t->waves_per_wg));
         if (t->refill_every > 0) L.groups = std::max(1, (int)t->refill_every / 4);
         if (t->item_walks > 0) L.item_walks = (uint64_t)t->item_walks;
+        if (t->walks_per_lane > 0) L.wpl = t->walks_per_lane >= 4 ? 4 : (t->walks_per_lane >= 2 ? 2 : 1);
     }
     (void)total_walks;
     return L;
@@ -522,7 +560,7 @@ bool transition_enqueue(const Plan& p, const float* eps, int32_t n_cells, int32_
     allow_large_lds();
     seed_kernel<<<1, 1, 0, st>>>(seed_dev, seed);
     walk_kernel<<<blocks, threads, lds, st>>>(dcube, nullptr, (int32_t)n_items, iw, item_counter, seed_dev,
-                                               L.groups, step_total);
+                                               L.groups, step_total, L.wpl);
     MW_HIP(hipGetLastError());
     return true;
 }
@@ -708,7 +746,7 @@ struct BatchState {
         prep_kernel<<<dim3(64, n_cubes), 256, 0, st>>>(dcubes, bad);
         if (with_walk && n_items)
             walk_kernel<<<blocks, threads, lds, st>>>(dcubes, ditems, (int32_t)n_items, 0, item_counter, seed_dev,
-                                                       L.groups, step_total);
+                                                       L.groups, step_total, L.wpl);
     }
 };
 
@@ -725,6 +763,93 @@ void check_batch_args(int32_t n_cubes, const float* eps_cat, const int64_t* eps_
 // walk-count scale); filled by mw_autotune_batch.
 std::mutex g_tune_mu;
 std::map<std::vector<int64_t>, mw_tune> g_tuned;
+std::string g_tune_loaded;  // the cache file last read
+
+// Tuned settings persist across processes in the JSON file named by
+// MWALK_TUNE_CACHE (when set): {"<device name>": [{"key": [...18 ints],
+// "tune": [tile_form, waves_per_wg, refill_every, item_walks,
+// walks_per_lane]}, ...]}.  The file holds this device's entries only; it is
+// read at the first batch call after MWALK_TUNE_CACHE names it (its entries
+// replace those in memory for the same batch shapes) and rewritten after
+// every autotune.
+std::string tune_device_name() {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    return std::string(prop.gcnArchName);
+}
+
+void load_tune_cache() {  // with g_tune_mu held
+    const char* path = getenv("MWALK_TUNE_CACHE");
+    if (!path || !*path || g_tune_loaded == path) return;
+    g_tune_loaded = path;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    fclose(f);
+    const std::string dev = "\"" + tune_device_name() + "\"";
+    size_t at = text.find(dev);
+    if (at == std::string::npos) return;
+    // entries: every "key": [...] followed by "tune": [...] (the file holds
+    // one device's list)
+    auto ints = [&](size_t from, std::vector<int64_t>& out) -> size_t {
+        const size_t b = text.find('[', from), e = text.find(']', b);
+        if (b == std::string::npos || e == std::string::npos) return std::string::npos;
+        out.clear();
+        const char* p = text.c_str() + b + 1;
+        const char* q = text.c_str() + e;
+        while (p < q) {
+            char* next = nullptr;
+            const long long v = strtoll(p, &next, 10);
+            if (next == p) {
+                ++p;
+                continue;
+            }
+            out.push_back(v);
+            p = next;
+        }
+        return e + 1;
+    };
+    size_t pos = at;
+    for (;;) {
+        const size_t k = text.find("\"key\"", pos);
+        if (k == std::string::npos) break;
+        std::vector<int64_t> key, tv;
+        const size_t after_key = ints(k, key);
+        if (after_key == std::string::npos) break;
+        const size_t t = text.find("\"tune\"", after_key);
+        if (t == std::string::npos) break;
+        pos = ints(t, tv);
+        if (pos == std::string::npos) break;
+        if ((key.size() == 18 || (key.size() == 3 && key[0] == -1)) && tv.size() == 5)
+            g_tuned[key] = mw_tune{(int32_t)tv[0], (int32_t)tv[1], (int32_t)tv[2], (int32_t)tv[3], (int32_t)tv[4]};
+    }
+}
+
+void save_tune_cache() {  // with g_tune_mu held
+    const char* path = getenv("MWALK_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::string out = "{\"" + tune_device_name() + "\": [";
+    bool first = true;
+    for (const auto& kv : g_tuned) {
+        out += first ? "\n  {\"key\": [" : ",\n  {\"key\": [";
+        first = false;
+        for (size_t i = 0; i < kv.first.size(); ++i) out += (i ? ", " : "") + std::to_string(kv.first[i]);
+        const mw_tune& t = kv.second;
+        out += "], \"tune\": [" + std::to_string(t.tile_form) + ", " + std::to_string(t.waves_per_wg) + ", " +
+               std::to_string(t.refill_every) + ", " + std::to_string(t.item_walks) + ", " +
+               std::to_string(t.walks_per_lane) + "]}";
+    }
+    out += "\n]}\n";
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    const bool ok = fwrite(out.data(), 1, out.size(), f) == out.size();
+    if (fclose(f) == 0 && ok) rename(tmp.c_str(), path);
+}
 
 std::vector<int64_t> batch_signature(int32_t n_cubes, const int32_t* n_cells, const uint64_t* n_walks,
                                      int32_t lattice) {
@@ -741,6 +866,26 @@ std::vector<int64_t> batch_signature(int32_t n_cubes, const int32_t* n_cells, co
 }
 
 }  // namespace
+
+// FRW walker launch geometry (resident waves per CU) tuned by frw_autotune,
+// kept with the batch settings (key [-1, n, expand m], value in the waves
+// field) and in the same MWALK_TUNE_CACHE file.
+bool frw_tuned_waves(int n, int expand_m, int* waves) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    load_tune_cache();
+    auto it = g_tuned.find(std::vector<int64_t>{-1, n, expand_m});
+    if (it == g_tuned.end()) return false;
+    *waves = it->second.waves_per_wg;
+    return true;
+}
+
+void frw_store_waves(int n, int expand_m, int waves) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    load_tune_cache();
+    g_tuned[std::vector<int64_t>{-1, n, expand_m}] = mw_tune{0, waves, 0, 0, 0};
+    save_tune_cache();
+}
+
 }  // namespace mw
 
 using namespace mw;
@@ -756,6 +901,7 @@ extern "C" mw_status mw_transition_batch(int32_t n_cubes, const float* eps_cat, 
         mw_tune tuned{};
         if (!tune) {
             std::lock_guard<std::mutex> g(g_tune_mu);
+            load_tune_cache();
             auto it = g_tuned.find(batch_signature(n_cubes, n_cells, n_walks, lattice));
             if (it != g_tuned.end()) {
                 tuned = it->second;
@@ -772,7 +918,7 @@ extern "C" mw_status mw_transition_batch(int32_t n_cubes, const float* eps_cat, 
         MW_REQUIRE(!h_bad, MW_EINVAL, "permittivity outside [1e-3, 1e3]");
         if (B.n_items)
             walk_kernel<<<B.blocks, B.threads, B.lds, st>>>(B.dcubes, B.ditems, (int32_t)B.n_items, 0, B.item_counter,
-                                                             B.seed_dev, B.L.groups, B.step_total);
+                                                             B.seed_dev, B.L.groups, B.step_total, B.L.wpl);
         MW_HIP(hipGetLastError());
         MW_HIP(hipStreamSynchronize(st));
     });
@@ -785,7 +931,7 @@ extern "C" mw_status mw_autotune_batch(int32_t n_cubes, const float* eps_cat, co
     return guarded([&] {
         check_batch_args(n_cubes, eps_cat, eps_off, n_cells, n_walks, out_off, hits_cat);
         MW_REQUIRE(best, MW_EINVAL, "null output");
-        *best = mw_tune{0, 16, 8, 0};
+        *best = mw_tune{0, 16, 8, 0, 1};
         if (n_cubes == 0) return;
         hipStream_t st = (hipStream_t)stream;
         hipEvent_t e0, e1;
@@ -812,7 +958,8 @@ extern "C" mw_status mw_autotune_batch(int32_t n_cubes, const float* eps_cat, co
                 reset_kernel<<<1, 1, 0, st>>>(B.bad, B.step_total, B.item_counter);
                 MW_HIP(hipEventRecord(e0, st));
                 walk_kernel<<<B.blocks, B.threads, B.lds, st>>>(B.dcubes, B.ditems, (int32_t)B.n_items, 0,
-                                                                 B.item_counter, B.seed_dev, B.L.groups, B.step_total);
+                                                                 B.item_counter, B.seed_dev, B.L.groups, B.step_total,
+                                                                 B.L.wpl);
                 MW_HIP(hipEventRecord(e1, st));
                 MW_HIP(hipEventSynchronize(e1));
                 float ms = 0.f;
@@ -822,13 +969,17 @@ extern "C" mw_status mw_autotune_batch(int32_t n_cubes, const float* eps_cat, co
             return best_ms;
         };
         // coordinate search: tile form, waves per workgroup, refill interval,
-        // walks per work item
-        mw_tune cur{0, 16, 8, 0};
+        // walks per work item, interleaved walks per lane
+        mw_tune cur{0, 16, 8, 0, 1};
         float cur_ms = time_of(cur);
         auto try_set = [&](int field, const std::vector<int>& vals) {
             for (int v : vals) {
                 mw_tune t = cur;
-                int* f = field == 0 ? &t.tile_form : field == 1 ? &t.waves_per_wg : field == 2 ? &t.refill_every : &t.item_walks;
+                int* f = field == 0   ? &t.tile_form
+                         : field == 1 ? &t.waves_per_wg
+                         : field == 2 ? &t.refill_every
+                         : field == 3 ? &t.item_walks
+                                      : &t.walks_per_lane;
                 if (*f == v) continue;
                 *f = v;
                 const float ms = time_of(t);
@@ -843,9 +994,11 @@ extern "C" mw_status mw_autotune_batch(int32_t n_cubes, const float* eps_cat, co
         try_set(2, {4, 16});
         const int thr = 64 * cur.waves_per_wg;
         try_set(3, {thr * 4, thr * 64});
+        try_set(4, {2, 4});
         *best = cur;
         std::lock_guard<std::mutex> g(g_tune_mu);
         g_tuned[batch_signature(n_cubes, n_cells, n_walks, lattice)] = cur;
+        save_tune_cache();
     });
 }
 
@@ -863,6 +1016,18 @@ struct mw_batch_plan {
     }
 };
 
+extern "C" mw_status mw_tune_lookup(int32_t n_cubes, const int32_t* n_cells, const uint64_t* n_walks,
+                                    int32_t lattice, mw_tune* out, int32_t* found) {
+    return guarded([&] {
+        MW_REQUIRE(n_cubes > 0 && n_cells && n_walks && out && found, MW_EINVAL, "bad arguments");
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        load_tune_cache();
+        auto it = g_tuned.find(batch_signature(n_cubes, n_cells, n_walks, lattice));
+        *found = it != g_tuned.end() ? 1 : 0;
+        if (*found) *out = it->second;
+    });
+}
+
 extern "C" mw_status mw_batch_plan_create(int32_t n_cubes, const float* eps_cat, const int64_t* eps_off,
                                           const int32_t* n_cells, int32_t lattice, const uint64_t* n_walks,
                                           const int64_t* out_off, int32_t* hits_cat, int32_t* steps_cat,
@@ -871,6 +1036,16 @@ extern "C" mw_status mw_batch_plan_create(int32_t n_cubes, const float* eps_cat,
         MW_REQUIRE(out, MW_EINVAL, "null output handle");
         check_batch_args(n_cubes, eps_cat, eps_off, n_cells, n_walks, out_off, hits_cat);
         MW_REQUIRE(n_cubes > 0, MW_EINVAL, "empty batch");
+        mw_tune tuned{};
+        if (!tune) {
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            load_tune_cache();
+            auto it = g_tuned.find(batch_signature(n_cubes, n_cells, n_walks, lattice));
+            if (it != g_tuned.end()) {
+                tuned = it->second;
+                tune = &tuned;
+            }
+        }
         auto P = std::make_unique<mw_batch_plan>();
         P->B.build(n_cubes, eps_cat, eps_off, n_cells, lattice, n_walks, out_off, hits_cat, steps_cat, tune);
         // validate the permittivities once, eagerly

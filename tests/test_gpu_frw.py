@@ -169,6 +169,25 @@ def test_c2_reduction_matches_fp64_resum(c2_gpu):
         assert np.allclose(r["se"], se, rtol=1e-5, atol=1e-12)
 
 
+def test_c4_reduction_matches_fp64_resum(mw):
+    """The 193-column row of the large interconnect (most nets absent from a
+    given 4096-walk slice of the reduction) against an fp64 re-sum of the
+    same per-walk fp32 scores."""
+    st = W.c4_structure()
+    m = st.meta["master"]
+    r = mw.frw_extract(st, m, 300000, seed=44, scores=True)
+    net = r["net"].cpu().numpy()
+    w = r["w"].cpu().numpy().astype(np.float64)
+    K = len(r["row"])
+    resum = np.bincount(net, weights=w, minlength=K) / w.size
+    scale = np.abs(resum).max()
+    assert np.all(np.abs(r["row"] - resum) <= 1e-6 * np.abs(resum) + 1e-9 * scale)
+    sq = np.bincount(net, weights=w * w, minlength=K) / w.size
+    se = np.sqrt(np.maximum(sq - resum ** 2, 0) / (w.size - 1))
+    assert np.allclose(r["se"], se, rtol=1e-5, atol=1e-12)
+    assert (r["row"][np.bincount(net, minlength=K) == 0] == 0).all()
+
+
 def test_c2_hybrid_equals_all_microwalk(mw, c2_gpu):
     st = W.c2_structure()
     r_mw = mw.frw_extract(st, 0, 1000000, seed=321, hybrid=0)
@@ -212,6 +231,45 @@ def test_plain_form_equals_persistent(mw, expand):
     assert b["stats"]["launches"] > 4 * a["stats"]["launches"]
     assert a["stats"]["hops"] == b["stats"]["hops"]
     assert a["stats"]["micro_steps"] == b["stats"]["micro_steps"]
+
+
+def test_full_table_cache_keeps_results(mw, oracle_lib, monkeypatch):
+    """A table cache far too small for the workload (MWALK_TABLE_CAP=200 for
+    the 10-cell lattice, which no other test uses) fills again and again:
+    walks that meet the full cache park as on a miss, the host builds what
+    was queued or empties the cache, and the walks still equal the oracle's
+    one by one."""
+    monkeypatch.setenv("MWALK_TABLE_CAP", "200")
+    st = W.c2_structure()
+    g = mw.frw_extract(st, 0, 10000, seed=6, n_cells=10, scores=True)
+    monkeypatch.delenv("MWALK_TABLE_CAP")
+    o = oracle_lib.frw_extract(st, 0, 10000, seed=6, n_cells=10, threads=_threads(), scores=True,
+                               kernel_limits=True)
+    same_net, same_walk = _walk_agreement(g, o["net"], o["w"])
+    print("cache of 200 tables: misses", g["stats"]["cache_miss"], "launches", g["stats"]["launches"],
+          "same walk", same_walk)
+    assert g["stats"]["cache_miss"] > 200  # more builds than the cache holds: it was emptied
+    assert same_walk >= 0.999
+
+
+def test_frw_autotune_keeps_results(mw, monkeypatch, tmp_path):
+    """The walker's launch geometry (resident waves per CU) is tuned on a
+    14-cell lattice (no other test uses it), kept in the tune cache file and
+    used by later extractions, whose walks stay bit-identical."""
+    import json
+    import torch
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("MWALK_TUNE_CACHE", str(cache))
+    st = W.c2_structure()
+    h = mw.StructureHandle(st)
+    a = mw.frw_extract(h, 0, 30000, seed=4, n_cells=14, scores=True)
+    w = mw.frw_autotune(h, 0, 300000, n_cells=14)
+    b = mw.frw_extract(h, 0, 30000, seed=4, n_cells=14, scores=True)
+    print("tuned waves per CU", w)
+    assert 4 <= w <= 16
+    assert torch.equal(a["net"], b["net"]) and torch.equal(a["w"], b["w"])
+    entries = next(iter(json.load(open(cache)).values()))
+    assert any(e["key"] == [-1, 14, 0] and e["tune"][1] == w for e in entries)
 
 
 def test_convergence_target(mw):
@@ -374,6 +432,47 @@ def test_microwalk_e_high_permittivity_beside_conductors(mw, oracle_lib):
     r = mw.frw_extract(st, 0, 1000000, seed=13, hybrid=0, expand=5)
     print("highk", r["row"][0] / exact - 1, r["se"][0] / exact, r["stats"]["micro_steps"])
     assert abs(r["row"][0] - exact) < 0.01 * exact + 3 * r["se"][0]
+
+
+# ---------------------------------------------------------------------------
+# Importance sampling of the Gaussian-surface point
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["highk", "c2"])
+def test_gauss_importance_walks_match_oracle(mw, oracle_lib, name):
+    """Both sides cut G into the same patches and weight them by the first-
+    transition kernel at the patch centres (fp32 on the GPU, fp64 in the
+    oracle), so walks agree one by one except where a draw falls within
+    rounding of a patch boundary."""
+    st = W.parallel_plates("columns_highk") if name == "highk" else W.c2_structure()
+    g = mw.frw_extract(st, 0, 20000, seed=78, scores=True, gauss_is=1.0)
+    o = oracle_lib.frw_extract(st, 0, 20000, seed=78, threads=_threads(), scores=True, gauss_is=1.0,
+                               kernel_limits=True)
+    same_net, same_walk = _walk_agreement(g, o["net"], o["w"])
+    print(name, "importance sampling: same net", same_net, "same net and weight", same_walk)
+    assert same_walk >= 0.995
+
+
+def test_gauss_importance_closed_form_and_variance(mw):
+    st = W.parallel_plates("columns_highk")
+    exact = W.parallel_plates_exact("columns_highk")
+    u = mw.frw_extract(st, 0, 1000000, seed=30)
+    s = mw.frw_extract(st, 0, 1000000, seed=31, gauss_is=1.0)
+    print("uniform %.5f +- %.5f; importance %.5f +- %.5f; exact %.5f"
+          % (u["row"][0], u["se"][0], s["row"][0], s["se"][0], exact))
+    assert abs(s["row"][0] - exact) < 3 * s["se"][0]
+    assert abs(s["row"][1] + exact) < 3 * s["se"][1]
+    assert s["se"][0] < 0.85 * u["se"][0]
+
+
+def test_gauss_importance_keeps_c2_rows(mw, c2_gpu):
+    s = mw.frw_extract(W.c2_structure(), 0, 1000000, seed=33, gauss_is=1.0)
+    u = c2_gpu[0]
+    zs = np.abs(s["row"] - u["row"]) / np.hypot(s["se"], u["se"])
+    print("importance", s["row"], s["se"], "z", zs)
+    assert zs.max() < z_crit(5)
+    with pytest.raises(mw.MWError) as e:
+        mw.frw_extract(W.c2_structure(), 0, 1000, gauss_is=0.01)
+    assert e.value.status == mw.MW_EINVAL
 
 
 def test_microwalk_e_options(mw):

@@ -117,7 +117,9 @@ def _batch_cubes(count, seed, nmin=4, nmax=32):
 
 @pytest.mark.parametrize("tune", [None, {"tile_form": 1}, {"tile_form": 2}, {"tile_form": 3},
                                   {"waves_per_wg": 1, "refill_every": 16, "item_walks": 100},
-                                  {"waves_per_wg": 4, "refill_every": 4, "item_walks": 777}])
+                                  {"waves_per_wg": 4, "refill_every": 4, "item_walks": 777},
+                                  {"walks_per_lane": 2}, {"walks_per_lane": 4, "tile_form": 2},
+                                  {"walks_per_lane": 4, "tile_form": 3, "waves_per_wg": 2, "item_walks": 300}])
 def test_batch_bit_exact_vs_oracle(mw, oracle_lib, tune):
     cubes, walks = _batch_cubes(24, 77)
     h, s, off = mw.mw_transition_batch(cubes, walks, seed=31, tune=tune)
@@ -166,6 +168,40 @@ def test_autotune_keeps_results(mw, oracle_lib):
     for c, (e, w) in enumerate(zip(cubes, walks)):
         ho, so = oracle_lib.microwalk(e, 0, w, seed=4, cube_index=c)
         assert (h[off[c]:off[c] + w] == ho).all() and (s[off[c]:off[c] + w] == so).all()
+
+
+def test_tune_cache_file(mw, tmp_path, monkeypatch):
+    """MWALK_TUNE_CACHE: an autotune writes its setting to the JSON file; a
+    file named later is read and its setting is what a batch of that shape
+    uses (checked with one edited entry)."""
+    import json
+    rng = np.random.Generator(np.random.PCG64(5))
+    cubes = [workloads.random_cube(n, rng) for n in (8, 12, 16, 20, 24, 8, 10, 14)]
+    walks = [int(w) for w in rng.integers(500, 3000, size=len(cubes))]
+    ns = [c.shape[0] for c in cubes]
+    first = tmp_path / "tune.json"
+    monkeypatch.setenv("MWALK_TUNE_CACHE", str(first))
+    tuned = mw.mw_autotune_batch(cubes, walks)
+    data = json.load(open(first))
+    entries = next(iter(data.values()))
+    assert len(data) == 1 and len(entries) >= 1
+    assert mw.mw_tune_lookup(ns, walks) == tuned
+    # an edited copy under another name: its entry wins once it is named
+    keys = [k for k, _ in mw.mw_tune._fields_]
+    for e in entries:
+        if e["tune"] == [tuned[k] for k in keys]:
+            e["tune"] = [0, 2, 16, 333, 4]
+    second = tmp_path / "tune2.json"
+    json.dump(data, open(second, "w"))
+    monkeypatch.setenv("MWALK_TUNE_CACHE", str(second))
+    found = mw.mw_tune_lookup(ns, walks)
+    print("tuned", tuned, "from the edited file", found)
+    assert found == dict(zip(keys, [0, 2, 16, 333, 4]))
+    # the batch runs with it and stays bit-identical to the default setting
+    h1, s1, _ = mw.mw_transition_batch(cubes, walks, seed=8)
+    h0, s0, _ = mw.mw_transition_batch(cubes, walks, seed=8, tune={"waves_per_wg": 16})
+    import torch
+    assert torch.equal(h1, h0) and torch.equal(s1, s0)
 
 
 def test_graph_plan_replays(mw):

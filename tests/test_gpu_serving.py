@@ -84,7 +84,10 @@ def test_admission_respects_budget(mw):
     print("small-budget stats", stats, "one", one)
     assert stats["completed"] == len(reqs)
     assert stats["max_resident_bytes"] <= budget
-    assert stats["max_concurrent"] == 2
+    # the budget holds 2.5 footprint estimates; a prepared request keeps
+    # only the memory it holds (below the estimate), so two or three share
+    # the device, never all six
+    assert 2 <= stats["max_concurrent"] <= 3
     for (st, m, b, seed), r in zip(reqs, results):
         alone = mw.frw_extract(st, m, b, seed=seed)
         assert _same(r, alone)
