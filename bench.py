@@ -393,8 +393,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--target", type=float, default=0.01, help="3 SE / |C_mm| at which an extraction stops")
-    ap.add_argument("--cpu-walks", type=int, default=4000, help="oracle sample, all host cores")
-    ap.add_argument("--cpu-walks-one", type=int, default=300, help="oracle sample, one thread")
+    ap.add_argument("--cpu-walks", type=int, default=40000, help="oracle sample, all host cores")
+    ap.add_argument("--cpu-walks-one", type=int, default=1000, help="oracle sample, one thread")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the comparison workloads")
     ap.add_argument("--serving-requests", type=int, default=2000,
