@@ -367,13 +367,14 @@ def headline(mw, W, steps, warmup, target):
     for i in range(warmup):
         mw.frw_extract(h, m, budget, seed=10000 + i, target_rel_3sigma=target)
     torch.cuda.synchronize()
-    acc = {"walks": 0, "micro_steps": 0, "launches": 0, "walker_s": 0.0, "hops": 0, "rel": [], "rows": [],
-           "ses": [], "halved": 0}
+    acc = {"walks": 0, "walks_launched": 0, "micro_steps": 0, "launches": 0, "walker_s": 0.0, "hops": 0,
+           "rel": [], "rows": [], "ses": [], "halved": 0}
     t0 = time.perf_counter()
     for k in range(steps):
         r = mw.frw_extract(h, m, budget, seed=k, target_rel_3sigma=target)
         s = r["stats"]
         acc["walks"] += s["walks"]
+        acc["walks_launched"] += s["walks_launched"]
         acc["micro_steps"] += s["micro_steps"]
         acc["launches"] += s["launches"]
         acc["walker_s"] += s["walker_seconds"]
@@ -442,11 +443,14 @@ def main():
                                "master net %d; 16^3-cell cubes; each step walks until 3 SE/|C_mm| <= %g"
                                % (m, args.target),
                    "target_rel_3sigma": args.target, "n_cells": 16, "hybrid": 1, "master": m},
+        # every micro-step walked, including those of walks after the
+        # stopping checkpoint (dropped from the row)
         "micro_steps_per_s": acc["micro_steps"] / dt,
         "walks_per_step": acc["walks"] / args.steps,
+        "walks_launched_per_step": acc["walks_launched"] / args.steps,
         "ms_to_target": dt / args.steps * 1e3,
         "rel_3sigma_reached": float(np.mean(acc["rel"])),
-        "hops_per_walk": acc["hops"] / acc["walks"],
+        "hops_per_walk": acc["hops"] / acc["walks_launched"],
         "cube_halved": acc["halved"],
         "walker_kernel_ms_per_step": acc["walker_s"] / args.steps * 1e3,
         "walker_launches_per_step": acc["launches"] / args.steps,

@@ -275,7 +275,9 @@ typedef struct {
     double abs_tol_rel;       /* absorption distance / window diagonal;
                                  default 1e-6                               */
     uint64_t first_walk;      /* id of the first walk (resume point)         */
-    uint64_t batch_walks;     /* walks per convergence check; 0 = auto      */
+    uint64_t batch_walks;     /* walks between checks of the target (a
+                                 multiple of 4096 after rounding up);
+                                 0 = 262144 for frw_extract                 */
     double gauss_is;          /* sampling of the Gaussian-surface point.  0
                                  (default): uniform by area, weight factor
                                  |G|.  > 0: importance sampling over G (the
@@ -318,6 +320,10 @@ typedef struct {
                                  boxes, or the MicroWalk-E limits) made
                                  smaller than the conductor-free, or
                                  expanded, size                             */
+    uint64_t walks_launched;  /* frw_extract: walks walked, including those
+                                 after the checkpoint where the target was
+                                 met (not in the row); the counters above
+                                 count the work of all of them               */
 } frw_stats;
 
 /* ------------------------------------------------------------------------
@@ -328,11 +334,20 @@ typedef struct {
  * C_{master,k} += omega.  cap_row[j] = sum of omega over walks ending on net j
  * divided by the number of walks (fF); cap_row[n_nets] is the env column.
  * stderr_row[j] is the standard error of cap_row[j].  Runs walk_budget walks,
- * or fewer when options->target_rel_3sigma > 0 and the target is met first
- * (checked every batch).  Walk scores are summed per net in fp32 with
- * compensated (Kahan) sums per block and in fp64 across blocks.
+ * or, when options->target_rel_3sigma > 0, stops at the first checkpoint
+ * (every options->batch_walks walks, rounded up to a multiple of 4096;
+ * default 262144) where 3 SE(C_mm) / |C_mm| <= target, and the row holds
+ * exactly the walks up to that checkpoint.  The walks are run in launches of
+ * several checkpoints, sized from the walk count the last such call on this
+ * structure, master and rule needed; walks after the stopping checkpoint are
+ * dropped (stats->walks_launched counts them).  Walk scores are summed per
+ * net in fp32 with compensated (Kahan) sums per block of 4096 walks and in
+ * fp64 across blocks, in walk order, so a row is the same for any split
+ * into launches: a target-mode row equals the fixed-budget row of the same
+ * number of walks.
  * score_net/score_w (device, walk_budget entries each, or NULL): per-walk net
- * index (n_nets for env) and fp32 weight, indexed by walk - first_walk.
+ * index (n_nets for env) and fp32 weight, indexed by walk - first_walk;
+ * entries from stats->walks on are unspecified.
  * stats may be NULL.  Synchronous: returns after the result is on the host.
  * Transition cubes are the largest conductor-free cubes, halved while they
  * touch more than MW_MAX_REGIONS dielectric boxes; MW_ELIMIT if more than

@@ -31,6 +31,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "common.h"
@@ -133,6 +134,11 @@ struct Counters {
     // transitions whose cube the capacity rule made smaller than the
     // conductor-free (or expanded) size
     unsigned long long halved;
+    // the parked walks the next walker launch resumes, from park[resume_side]
+    uint32_t resume_count, resume_side;
+    // device-driven rounds: tables they built, 1 once they handed over to
+    // the host, 1 when their first-transition launch has walks to redo
+    uint32_t tables_built, dev_stop, need_first, pad2;
 };
 
 // A contiguous range of walks of one extraction request.  One launch of the
@@ -170,9 +176,7 @@ struct WalkArgs {
     unsigned long long total;
     CacheDev cache;
     int32_t n, hybrid;
-    const Parked* resume;
-    uint32_t n_resume;
-    Parked* park_out;
+    Parked* park[2];        // parked-walk queues: resume from park[resume_side], park to the other
     uint32_t park_cap;
     Counters* ctr;
     uint32_t lane_stride;   // dwords of LDS per lane (odd)
@@ -196,6 +200,7 @@ struct FirstArgs {
     Counters* ctr;
     uint32_t lane_stride;
     int32_t round;  // 0: every walk is processed and its done flag written
+    int32_t dev_round;  // 1: a device-driven round (runs only when the counters ask for it)
     StructDev S0;  // single-segment launches: the structure header (kernel arguments)
 };
 
@@ -1079,6 +1084,7 @@ __device__ __forceinline__ float sel3(float3 v, int a) { return a == 0 ? v.x : (
 template <bool MULTI>
 __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
     extern __shared__ uint32_t lds[];
+    if (A.dev_round && A.ctr->need_first == 0u) return;
     const int n = A.n;
     uint32_t* my = lds + threadIdx.x * A.lane_stride;
     const LaneCube L = lane_cube(my, n);
@@ -1756,6 +1762,11 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
         __syncthreads();
     }
 
+    // the parked walks this launch resumes (set by the kernel before it)
+    const uint32_t n_resume = K.resume_count;
+    const Parked* resume = A.park[K.resume_side & 1u];
+    Parked* park_out = A.park[(K.resume_side & 1u) ^ 1u];
+
     int phase = PH_IDLE;
     WaveClaim claim_rc, claim_fr;  // wave-level claims of resumed and fresh walks
     bool resume_done = false;
@@ -1793,7 +1804,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                         P.omega = omega;
                         P.t = t;
                         P.seg = sg;
-                        stpark(A.park_out + slot, P);
+                        stpark(park_out + slot, P);
                     } else {
                         err |= ERR_PARK_CAP;
                     }
@@ -1806,33 +1817,39 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
             const uint64_t bal = __ballot(phase == PH_IDLE);
             if (bal) {
                 bool got = false;
-                if (A.n_resume && !resume_done) {
+                if (n_resume && !resume_done) {
                     const unsigned long long ri = claim_rc.take(&K.resume_next, bal, lane);
                     if (phase == PH_IDLE) {
-                        if (ri < A.n_resume) {
-                            const Parked P = ldpark(A.resume + ri);
+                        if (ri < n_resume) {
+                            const Parked P = ldpark(resume + ri);
                             if (MULTI) sg = P.seg;
                             const GAS Segment& SG = gp(A.segs)[sg];
                             wk0 = SG.k0;
                             wk1 = SG.k1;
                             walk = P.walk;
+                            phase = PH_NEED;
                             if (P.t == 0u) {
                                 // parked before its first transition existed:
-                                // start from it now
-                                const float4 f = ldf4(SG.first_state + (walk - SG.walk_begin));
+                                // start from it now, or park again while it
+                                // is still missing
+                                const unsigned long long k = walk - SG.walk_begin;
+                                const float4 f = ldf4(SG.first_state + k);
                                 pos = make_float3(f.x, f.y, f.z);
                                 omega = f.w;
                                 t = 1;
+                                if (!gp(SG.first_done)[k]) {
+                                    t = 0;
+                                    phase = PH_PARK;
+                                }
                             } else {
                                 pos = make_float3(P.px, P.py, P.pz);
                                 omega = P.omega;
                                 t = P.t;
                             }
-                            phase = PH_NEED;
                             got = true;
                         }
                     }
-                    resume_done = claim_rc.base >= A.n_resume;
+                    resume_done = claim_rc.base >= n_resume;
                 }
                 const uint64_t bal2 = __ballot(phase == PH_IDLE && !got);
                 if (bal2) {
@@ -2048,7 +2065,7 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                     P.omega = omega;
                     P.t = t;
                     P.seg = sg;
-                    stpark(A.park_out + slot, P);
+                    stpark(park_out + slot, P);
                 } else {
                     err |= ERR_PARK_CAP;
                 }
@@ -2156,10 +2173,17 @@ struct BuildArgs {
     uint32_t count;
     double* work;          // per block: 3 M^3 + 3 nb doubles
     size_t work_stride;    // doubles per block
+    // device-driven rounds: the list is the cache's queue and its length
+    // is read here (blocks past it, and every block once the rounds handed
+    // over to the host, do nothing)
+    const uint32_t* dev_count;
+    const Counters* ctr;
 };
 
 __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
+    if (B.dev_count && (B.ctr->dev_stop || blockIdx.x >= *B.dev_count)) return;
     const uint32_t idx = B.list[blockIdx.x];
+    if (idx >= B.cache.capacity) return;  // a queue entry of a full cache
     const CacheDev& C = B.cache;
     const uint32_t* key = C.keys + (size_t)idx * C.key_stride;
     const int kind = (int)key[0], n = (int)key[1], s = (int)key[2], anorm = (int)key[3];
@@ -2398,6 +2422,41 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
 }
 
 // -------------------------------------------------------------------------
+// Between walker launches.  The next launch resumes the walks the last one
+// parked, from the queue it wrote, with the queue state reset.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ void prep_resume(Counters& K, uint32_t park_cap) {
+    K.resume_count = min(K.park_count, park_cap);
+    K.resume_side ^= 1u;
+    K.park_count = 0u;
+    K.resume_next = 0ull;
+}
+
+__global__ void resume_prep_kernel(Counters* K, uint32_t park_cap) { prep_resume(*K, park_cap); }
+
+// A device-driven round (no host decision between launches): the tables
+// queued by the earlier launches were built by the kernel before this one,
+// first transitions that missed one are redone next, then the parked walks
+// resume.  More queued tables than that build covers hand everything over
+// to the host: the rest of the round does nothing and the parked walks stay
+// where they are.
+__global__ void device_round_prep_kernel(Counters* K, CacheDev C, uint32_t build_max, uint32_t park_cap) {
+    if (K->dev_stop) return;
+    const uint32_t np = *C.n_pending;
+    if (np > build_max) {
+        K->dev_stop = 1u;
+        K->need_first = 0u;
+        K->resume_count = 0u;
+        return;
+    }
+    *C.n_pending = 0u;
+    K->tables_built += np;
+    K->need_first = K->first_missing;
+    K->first_missing = 0u;
+    prep_resume(*K, park_cap);
+}
+
+// -------------------------------------------------------------------------
 // Score reduction: per block fp32 compensated sums per net, then binary64
 // across blocks.
 // -------------------------------------------------------------------------
@@ -2413,123 +2472,217 @@ __device__ __forceinline__ void neumaier(float& s, float& c, float x) {
     s = t;
 }
 
-// Block-level compensated sums of one RED_CHUNK slice of walks: per net,
-// the slice is split into `parts` contiguous pieces summed by different
-// threads, then combined in piece order (deterministic).  Only the nets that
-// occur in the slice are scanned (found with a flag per net when K <=
-// RED_FLAGS), so the work is about (nets present) x len / RED_THREADS per
-// thread instead of K x len.
+// Block-level compensated sums of one RED_CHUNK slice of walks, per net.
+//
+// Up to RED_FLAGS nets: a stable counting sort of the slice by net (counts,
+// segment starts, then one wave places the scores in walk order, ranking
+// equal nets with ballots), after which every net's segment is cut into
+// RED_PARTS contiguous pieces summed by different threads and combined in
+// piece order.  The work is O(len) and the order of every sum is fixed by
+// the slice alone (deterministic).  More nets: each thread scans the slice
+// for one net.
 constexpr int RED_FLAGS = 4096;
+constexpr int RED_PARTS = 16;
 
-__device__ void reduce_chunk(const int32_t* __restrict__ net, const float* __restrict__ w, uint64_t base, int len,
-                             int K, float4* __restrict__ out, int32_t* snet, float* sw, float4* part,
-                             int32_t* flag) {
-    const bool sparse = K <= RED_FLAGS;
-    if (sparse)
-        for (int j = threadIdx.x; j < K; j += blockDim.x) flag[j] = 0;
+struct RedSorted {
+    uint16_t snet[RED_CHUNK];
+    float sw[RED_CHUNK];
+    float sorted[RED_CHUNK];
+    uint32_t pos[RED_FLAGS];  // counts, then segment starts, then segment ends
+    float4 part[RED_THREADS];
+};
+struct RedScan {
+    int32_t snet[RED_CHUNK];
+    float sw[RED_CHUNK];
+    float4 part[RED_THREADS];
+};
+union RedLds {
+    RedSorted s;
+    RedScan d;
+};
+
+__device__ __forceinline__ void reduce_chunk_sorted(const int32_t* __restrict__ net, const float* __restrict__ w, uint64_t base,
+                                    int len, int K, float4* __restrict__ out, RedSorted& L) {
+    const int t = threadIdx.x;
+    for (int j = t; j < K; j += RED_THREADS) L.pos[j] = 0u;
     __syncthreads();
-    for (int q = threadIdx.x; q < len; q += blockDim.x) {
-        const int32_t nq = net[base + q];
-        snet[q] = nq;
-        sw[q] = w[base + q];
-        if (sparse) flag[nq] = 1;
+    for (int q0 = 0; q0 < len; q0 += 4 * RED_THREADS) {
+        // four loads in flight per thread
+        int32_t nq[4];
+        float wq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u * RED_THREADS + t;
+            if (q < len) {
+                nq[u] = net[base + q];
+                wq[u] = w[base + q];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u * RED_THREADS + t;
+            if (q < len) {
+                L.snet[q] = (uint16_t)nq[u];
+                L.sw[q] = wq[u];
+                atomicAdd(&L.pos[nq[u]], 1u);
+            }
+        }
     }
     __syncthreads();
-    // the nets to scan, in increasing order: flag[j] becomes the index of
-    // net j in that list (or -1); n_list of them
-    __shared__ int32_t n_list;
-    __shared__ int32_t wsum[RED_THREADS / 64];
-    if (sparse) {
-        // block-wide exclusive scan of the flags, RED_FLAGS / RED_THREADS per thread
+    {
+        // exclusive scan of the counts: segment starts
+        __shared__ uint32_t wsum[RED_THREADS / 64];
         constexpr int PER = RED_FLAGS / RED_THREADS;
-        const int t0 = threadIdx.x * PER;
-        int loc[PER];
-        int run = 0;
+        const int j0 = t * PER;
+        uint32_t loc[PER];
+        uint32_t run = 0;
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-            loc[i] = t0 + i < K ? flag[t0 + i] : 0;
+            loc[i] = j0 + i < K ? L.pos[j0 + i] : 0u;
             run += loc[i];
         }
-        int incl = run;
-        const int lane = threadIdx.x & 63;
+        uint32_t incl = run;
+        const int lane = t & 63;
         for (int off = 1; off < 64; off <<= 1) {
-            const int v = __shfl_up(incl, off);
+            const uint32_t v = __shfl_up(incl, off);
             if (lane >= off) incl += v;
         }
-        if (lane == 63) wsum[threadIdx.x >> 6] = incl;
+        if (lane == 63) wsum[t >> 6] = incl;
         __syncthreads();
-        int before = incl - run;
-        for (int wv = 0; wv < (int)(threadIdx.x >> 6); ++wv) before += wsum[wv];
-        if (threadIdx.x == RED_THREADS - 1) n_list = before + run;
-        __syncthreads();
+        uint32_t before = incl - run;
+        for (int wv = 0; wv < (t >> 6); ++wv) before += wsum[wv];
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-            if (t0 + i < K) flag[t0 + i] = loc[i] ? before : -1;
+            if (j0 + i < K) L.pos[j0 + i] = before;
             before += loc[i];
         }
-        __syncthreads();
-    } else if (threadIdx.x == 0) {
-        n_list = K;
     }
     __syncthreads();
-    const int L = n_list;
-    __shared__ int32_t lnet[RED_THREADS];  // list position -> net, one group of nets at a time
-    for (int j0 = 0; j0 < L; j0 += RED_THREADS) {
-        const int kn = min(L - j0, RED_THREADS);
-        const int parts = RED_THREADS / kn;
-        const int t = threadIdx.x;
-        if (sparse) {
-            for (int j = threadIdx.x; j < K; j += blockDim.x) {
-                const int li = flag[j];
-                if (li >= j0 && li < j0 + kn) lnet[li - j0] = j;
+    if (t < 64) {
+        // stable placement, 64 scores at a time: the lanes holding the same
+        // net find each other with one ballot per bit of the net index; a
+        // lane's rank is the number of such lanes below it, and the group's
+        // last lane moves the segment pointer
+        const int nbits = K > 1 ? 32 - __clz(K - 1) : 0;
+        const unsigned long long below = (1ull << t) - 1ull;
+        // the next 64 keys and scores are read one pass ahead
+        uint32_t key_n = t < len ? (uint32_t)L.snet[t] : 0u;
+        float w_n = t < len ? L.sw[t] : 0.f;
+        for (int i = 0; i < len; i += 64) {
+            const int q = i + t;
+            const bool ok = q < len;
+            const uint32_t key = key_n;
+            const float wq = w_n;
+            if (q + 64 < len) {
+                key_n = L.snet[q + 64];
+                w_n = L.sw[q + 64];
             }
-        } else if (t < kn) {
-            lnet[t] = j0 + t;
+            unsigned long long match = __ballot(ok);
+            for (int bt = 0; bt < nbits; ++bt) {
+                const bool bit = (key >> bt) & 1u;
+                const unsigned long long m = __ballot(bit);
+                match &= bit ? m : ~m;
+            }
+            if (ok) {
+                const uint32_t p0 = L.pos[key];
+                L.sorted[p0 + (uint32_t)__popcll(match & below)] = wq;
+                if ((match >> t) == 1ull) L.pos[key] = p0 + (uint32_t)__popcll(match);
+            }
         }
-        __syncthreads();
-        if (t < kn * parts) {
-            const int j = lnet[t / parts], pi = t % parts;
-            const int q0 = (int)((long long)len * pi / parts), q1 = (int)((long long)len * (pi + 1) / parts);
-            float s1 = 0.f, c1 = 0.f, s2 = 0.f, c2 = 0.f;
-            for (int q = q0; q < q1; ++q) {
-                if (snet[q] == j) {
-                    const float x = sw[q];
-                    neumaier(s1, c1, x);
-                    neumaier(s2, c2, x * x);
+    }
+    __syncthreads();
+    // pos[j] is now the end of net j's segment (and the start of j + 1's)
+    for (int g0 = 0; g0 < K * RED_PARTS; g0 += RED_THREADS) {
+        const int task = g0 + t, j = task / RED_PARTS, pi = task % RED_PARTS;
+        float s1 = 0.f, c1 = 0.f, s2 = 0.f, c2 = 0.f;
+        if (j < K) {
+            const uint32_t e = L.pos[j], b = j ? L.pos[j - 1] : 0u, c = e - b;
+            const uint32_t q0 = b + c * pi / RED_PARTS, q1 = b + c * (pi + 1) / RED_PARTS;
+            uint32_t q = q0;
+            for (; q + 4 <= q1; q += 4) {
+                // four scores read ahead, added in order
+                float xv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) xv[u] = L.sorted[q + u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    neumaier(s1, c1, xv[u]);
+                    neumaier(s2, c2, xv[u] * xv[u]);
                 }
             }
-            part[t] = make_float4(s1, c1, s2, c2);
-        }
-        __syncthreads();
-        if (t < kn) {
-            float s1 = 0.f, c1 = 0.f, s2 = 0.f, c2 = 0.f;
-            for (int pi = 0; pi < parts; ++pi) {
-                const float4 v = part[t * parts + pi];
-                neumaier(s1, c1, v.x);
-                neumaier(s1, c1, v.y);
-                neumaier(s2, c2, v.z);
-                neumaier(s2, c2, v.w);
+            for (; q < q1; ++q) {
+                const float x = L.sorted[q];
+                neumaier(s1, c1, x);
+                neumaier(s2, c2, x * x);
             }
-            out[lnet[t]] = make_float4(s1, c1, s2, c2);
+        }
+        L.part[t] = make_float4(s1, c1, s2, c2);
+        __syncthreads();
+        if (t < RED_THREADS / RED_PARTS) {
+            const int jj = g0 / RED_PARTS + t;
+            if (jj < K) {
+                float a1 = 0.f, e1 = 0.f, a2 = 0.f, e2 = 0.f;
+                for (int k = 0; k < RED_PARTS; ++k) {
+                    const float4 v = L.part[t * RED_PARTS + k];
+                    neumaier(a1, e1, v.x);
+                    neumaier(a1, e1, v.y);
+                    neumaier(a2, e2, v.z);
+                    neumaier(a2, e2, v.w);
+                }
+                out[jj] = make_float4(a1, e1, a2, e2);
+            }
         }
         __syncthreads();
     }
-    // nets absent from the slice contribute zero
-    if (sparse)
-        for (int j = threadIdx.x; j < K; j += blockDim.x)
-            if (flag[j] < 0) out[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__device__ __forceinline__ void reduce_chunk_scan(const int32_t* __restrict__ net, const float* __restrict__ w, uint64_t base,
+                                  int len, int K, float4* __restrict__ out, RedScan& L) {
+    const int t = threadIdx.x;
+    for (int q = t; q < len; q += RED_THREADS) {
+        L.snet[q] = net[base + q];
+        L.sw[q] = w[base + q];
+    }
+    __syncthreads();
+    for (int j = t; j < K; j += RED_THREADS) {
+        float s1 = 0.f, c1 = 0.f, s2 = 0.f, c2 = 0.f;
+        for (int q = 0; q < len; ++q) {
+            if (L.snet[q] == j) {
+                const float x = L.sw[q];
+                neumaier(s1, c1, x);
+                neumaier(s2, c2, x * x);
+            }
+        }
+        out[j] = make_float4(s1, c1, s2, c2);
+    }
+}
+
+__device__ __forceinline__ void reduce_chunk(const int32_t* __restrict__ net, const float* __restrict__ w,
+                                             uint64_t base, int len, int K, float4* __restrict__ out, RedLds& L) {
+    if (K <= RED_FLAGS)
+        reduce_chunk_sorted(net, w, base, len, K, out, L.s);
+    else
+        reduce_chunk_scan(net, w, base, len, K, out, L.d);
+}
+
+// The gate of a reduction: the counters of the walker run that wrote the
+// scores.  Closed when that run did not end every walk of its gate_total (a
+// walk parked, a first transition missed its table): the scores are then
+// incomplete, nothing is reduced, and the host completes the run first.
+__device__ __forceinline__ bool gate_closed(const Counters* gate, unsigned long long gate_total) {
+    return gate && (gate->park_count != 0u || gate->first_missing != 0u || gate->walk_next < gate_total);
 }
 
 __global__ void __launch_bounds__(RED_THREADS) reduce_scores_kernel(const int32_t* __restrict__ net,
                                                                    const float* __restrict__ w, uint64_t count,
-                                                                   int K, float4* __restrict__ partial) {
-    __shared__ int32_t snet[RED_CHUNK];
-    __shared__ float sw[RED_CHUNK];
-    __shared__ float4 part[RED_THREADS];
-    __shared__ int32_t flag[RED_FLAGS];
+                                                                   int K, float4* __restrict__ partial,
+                                                                   const Counters* gate,
+                                                                   unsigned long long gate_total) {
+    __shared__ RedLds L;
+    if (gate_closed(gate, gate_total)) return;
     const uint64_t base = (uint64_t)blockIdx.x * RED_CHUNK;
     const int len = (int)min((uint64_t)RED_CHUNK, count - base);
-    reduce_chunk(net, w, base, len, K, partial + (size_t)blockIdx.x * K, snet, sw, part, flag);
+    reduce_chunk(net, w, base, len, K, partial + (size_t)blockIdx.x * K, L);
 }
 
 // Reduction of a round that served several requests: segment s owns blocks
@@ -2546,10 +2699,7 @@ struct RedSeg {
 };
 
 __global__ void __launch_bounds__(RED_THREADS) reduce_multi_kernel(const RedSeg* __restrict__ segs, int n_segs) {
-    __shared__ int32_t snet[RED_CHUNK];
-    __shared__ float sw[RED_CHUNK];
-    __shared__ float4 part[RED_THREADS];
-    __shared__ int32_t flag[RED_FLAGS];
+    __shared__ RedLds L;
     int lo = 0, hi = n_segs - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -2563,7 +2713,7 @@ __global__ void __launch_bounds__(RED_THREADS) reduce_multi_kernel(const RedSeg*
     const uint64_t base = (uint64_t)local * RED_CHUNK;
     if (base >= R.count) return;
     const int len = (int)min((uint64_t)RED_CHUNK, R.count - base);
-    reduce_chunk(R.net, R.w, base, len, R.K, R.partial + (size_t)local * R.K, snet, sw, part, flag);
+    reduce_chunk(R.net, R.w, base, len, R.K, R.partial + (size_t)local * R.K, L);
 }
 
 __global__ void finish_multi_kernel(const RedSeg* __restrict__ segs) {
@@ -2588,46 +2738,139 @@ __global__ void finish_multi_kernel(const RedSeg* __restrict__ segs) {
     }
 }
 
-// acc[2*K]: running binary64 sums (S1, S2) per net; result[2*K]: row, se.
-// One block per net j: strided fp64 sums of the block partials, then a
-// fixed-order tree over the threads (deterministic).
-constexpr int FIN_THREADS = 256;
+// Binary64 sums of a launch's block partials, in walk order, and the
+// stopping rule of Alg. 1 (walk until the estimate of C_mm is accurate
+// enough).  acc[2*K]: running sums (S1, S2) per net over the walks before
+// the launch; every block's partial is added to them one block at a time
+// in walk order, so the sums do not depend on how the walks were split into
+// launches.  Checkpoints fall every `per_ck` blocks of the launch (launches
+// start on a checkpoint); the first checkpoint where 3 SE(C_mm) / |C_mm| <=
+// target ends the extraction, and the blocks after it are not added.
+struct Choice {
+    int32_t blocks;  // blocks added (-1: the gate was closed, nothing added)
+    int32_t met;     // 1: the target was met at that checkpoint
+    unsigned long long walks;
+};
 
-// gate (or null): the counters of the walker run that wrote the scores; the
-// sums are added only when that run ended every walk of its gate_total (no
-// walk parked, no first transition missing), else nothing is written and
-// the host completes the run and reduces again.
-__global__ void __launch_bounds__(FIN_THREADS) finish_kernel(const float4* __restrict__ partial, int blocks, int K,
-                                                             double* acc, double n_total, double* result,
-                                                             const Counters* gate, unsigned long long gate_total) {
-    __shared__ double t1[FIN_THREADS], t2[FIN_THREADS];
-    const int j = blockIdx.x;
-    if (gate && (gate->park_count != 0u || gate->first_missing != 0u || gate->walk_next < gate_total)) return;
-    double s1 = 0.0, s2 = 0.0;
-    for (int b = threadIdx.x; b < blocks; b += FIN_THREADS) {
-        const float4 p = partial[(size_t)b * K + j];
-        s1 += (double)p.x + (double)p.y;
-        s2 += (double)p.z + (double)p.w;
-    }
-    t1[threadIdx.x] = s1;
-    t2[threadIdx.x] = s2;
-    __syncthreads();
-    for (int h = FIN_THREADS / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            t1[threadIdx.x] += t1[threadIdx.x + h];
-            t2[threadIdx.x] += t2[threadIdx.x + h];
+constexpr int DECIDE_MAX_BLOCKS = 4096;  // master partials staged in LDS
+
+__device__ __forceinline__ void mean_se(double s1, double s2, double n, double* m, double* se) {
+    const double mm = s1 / n;
+    const double var = (s2 / n - mm * mm) / (n - 1.0);
+    *m = mm;
+    *se = sqrt(var > 0.0 ? var : 0.0);
+}
+
+// A net's partials of blocks [0, blocks) staged in LDS by one wave (the
+// first DECIDE_MAX_BLOCKS of them; later ones are read in place).
+__device__ __forceinline__ void stage_column(const float4* __restrict__ partial, int blocks, int K, int j,
+                                             float4* col) {
+    const int nb = min(blocks, DECIDE_MAX_BLOCKS);
+    for (int b0 = 0; b0 < nb; b0 += 64 * 4) {
+        float4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = b0 + u * 64 + (int)threadIdx.x;
+            if (b < nb) v[u] = partial[(size_t)b * K + j];
         }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int b = b0 + u * 64 + (int)threadIdx.x;
+            if (b < nb) col[b] = v[u];
+        }
     }
-    if (threadIdx.x == 0) {
-        const double a1 = t1[0] + acc[j], a2 = t2[0] + acc[K + j];
-        acc[j] = a1;
-        acc[K + j] = a2;
-        const double m = a1 / n_total;
-        const double var = (a2 / n_total - m * m) / (n_total - 1.0);
-        result[j] = m;
-        result[K + j] = sqrt(var > 0.0 ? var : 0.0);
+    __syncthreads();
+}
+
+// One wave: the master's partials go to LDS, then lane 0 adds them in order
+// and tests each checkpoint.  target <= 0: every block is added.
+__global__ void __launch_bounds__(64) decide_kernel(const float4* __restrict__ partial, int blocks, int K, int master,
+                                                    int per_ck, const double* __restrict__ acc, double n_before,
+                                                    unsigned long long count, double target, const Counters* gate,
+                                                    unsigned long long gate_total, Choice* out) {
+    __shared__ float4 pm[DECIDE_MAX_BLOCKS];
+    if (gate_closed(gate, gate_total)) {
+        if (threadIdx.x == 0) {
+            out->blocks = -1;
+            out->met = 0;
+            out->walks = 0ull;
+        }
+        return;
     }
+    int chosen = blocks, met = 0;
+    if (target > 0.0) {
+        stage_column(partial, blocks, K, master, pm);
+        if (threadIdx.x != 0) return;
+        double s1 = acc[master], s2 = acc[K + master];
+        int to_ck = per_ck;
+        for (int b0 = 0; b0 < blocks && !met; b0 += 8) {
+            // eight partials loaded ahead, added one at a time
+            float4 pv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int b = b0 + u;
+                pv[u] = b >= blocks ? make_float4(0.f, 0.f, 0.f, 0.f)
+                                    : (b < DECIDE_MAX_BLOCKS ? pm[b] : partial[(size_t)b * K + master]);
+            }
+            for (int u = 0; u < 8 && b0 + u < blocks; ++u) {
+                const int b = b0 + u;
+                s1 += (double)pv[u].x + (double)pv[u].y;
+                s2 += (double)pv[u].z + (double)pv[u].w;
+                if (--to_ck == 0 || b + 1 == blocks) {
+                    to_ck = per_ck;
+                    const unsigned long long w = min((unsigned long long)(b + 1) * RED_CHUNK, count);
+                    double m, se;
+                    mean_se(s1, s2, n_before + (double)w, &m, &se);
+                    if (m != 0.0 && 3.0 * se / fabs(m) <= target) {
+                        chosen = b + 1;
+                        met = 1;
+                        break;
+                    }
+                }
+            }
+        }
+    } else if (threadIdx.x != 0) {
+        return;
+    }
+    out->blocks = chosen;
+    out->met = met;
+    out->walks = min((unsigned long long)chosen * RED_CHUNK, count);
+}
+
+// One wave per net: the chosen blocks' partials staged in LDS, added in
+// order by lane 0, then the row entry and its standard error.
+__global__ void __launch_bounds__(64) finish_seq_kernel(const float4* __restrict__ partial, int K, double* acc,
+                                                        double n_before, const Choice* choice, double* result) {
+    __shared__ float4 col[DECIDE_MAX_BLOCKS];
+    const int j = blockIdx.x;
+    const int nb = choice->blocks;
+    if (nb < 0) return;
+    stage_column(partial, nb, K, j, col);
+    if (threadIdx.x != 0) return;
+    double s1 = acc[j], s2 = acc[K + j];
+    for (int b0 = 0; b0 < nb; b0 += 8) {
+        // eight partials loaded ahead, added one at a time
+        float4 pv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int b = b0 + u;
+            pv[u] = b >= nb ? make_float4(0.f, 0.f, 0.f, 0.f)
+                            : (b < DECIDE_MAX_BLOCKS ? col[b] : partial[(size_t)b * K + j]);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (b0 + u < nb) {
+                s1 += (double)pv[u].x + (double)pv[u].y;
+                s2 += (double)pv[u].z + (double)pv[u].w;
+            }
+        }
+    }
+    acc[j] = s1;
+    acc[K + j] = s2;
+    double m, se;
+    mean_se(s1, s2, n_before + (double)choice->walks, &m, &se);
+    result[j] = m;
+    result[K + j] = se;
 }
 
 // -------------------------------------------------------------------------
@@ -2826,6 +3069,19 @@ struct mw_structure {
     char* mem = nullptr;
     int32_t n_nets = 0;
     std::vector<mw_cond_box> cond;
+    // walks the last target-mode extraction per (master, checkpoint, target)
+    // needed: sizes the next one's first launch (results do not depend on it)
+    std::mutex hint_mu;
+    std::map<std::tuple<int, uint64_t, double>, uint64_t> hints;
+    uint64_t walk_hint(int master, uint64_t ck, double target) {
+        std::lock_guard<std::mutex> g(hint_mu);
+        auto it = hints.find({master, ck, target});
+        return it == hints.end() ? 0 : it->second;
+    }
+    void set_walk_hint(int master, uint64_t ck, double target, uint64_t walks) {
+        std::lock_guard<std::mutex> g(hint_mu);
+        hints[{master, ck, target}] = walks;
+    }
 };
 
 static void validate_desc(const mw_structure_desc* D) {
@@ -3107,6 +3363,12 @@ LaunchGeom launch_geom(int n) {
 // (retried after missing tables are built), then walker launches (parked
 // walks resume after their tables are built).  Holds the table cache of one
 // lattice size while it runs.
+// Device-driven rounds enqueued after a run's first walker launch (table
+// builds and resumes without a host decision in between), and the most
+// queued tables one such round builds.
+constexpr int DEVICE_ROUNDS = 2;
+constexpr uint32_t DEV_BUILD_MAX = 128;
+
 struct Runner {
     int n, hybrid;
     int expand_m = 0;  // MicroWalk-E when > 0 (expanded half-size n d / (2 m))
@@ -3121,9 +3383,13 @@ struct Runner {
     uint32_t* status;
     Parked* park[2];
     Segment* dsegs;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // HIP event pairs around the walker launches not yet counted in walker_ms
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+    size_t ev_used = 0;
     uint64_t misses = 0, launches = 0;
+    uint32_t built_seen = 0;  // device-round table builds already counted in misses
     double walker_ms = 0.0;
+    double* dev_work = nullptr;  // workspace of the device-round table builds
     // stream of this runner's launches and copies (nullptr: the legacy
     // default stream); table builds and cache flushes always run on the
     // default stream with the device otherwise idle
@@ -3134,9 +3400,6 @@ struct Runner {
     StructDev cur_s0{};
     bool cur_single = false;
     unsigned long long cur_total = 0;
-    uint32_t n_resume = 0;
-    int cur = 0;
-    bool walker_pending = false;  // a launched walker whose duration is not yet counted
 
     template <class F>
     void set_lds(F* f, size_t bytes) {
@@ -3162,8 +3425,6 @@ struct Runner {
         park[0] = (Parked*)(mem + o_p0);
         park[1] = (Parked*)(mem + o_p1);
         dsegs = (Segment*)(mem + o_sg);
-        MW_HIP(hipEventCreate(&ev0));
-        MW_HIP(hipEventCreate(&ev1));
         set_lds(frw_walk_kernel<false, false>, g.lds);
         set_lds(frw_walk_kernel<true, false>, g.lds);
         set_lds(frw_walk_kernel<false, false, true>, g.lds);
@@ -3176,8 +3437,11 @@ struct Runner {
         set_lds(first_kernel<true>, g.first_lds);
     }
     ~Runner() {
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
+        for (auto& e : evs) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        dev_free(dev_work);
         dev_free(mem);
     }
 
@@ -3327,19 +3591,21 @@ struct Runner {
         Counters h{};
         MW_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, stream));
         MW_HIP(hipStreamSynchronize(stream));
-        if (walker_pending) {
+        for (size_t i = 0; i < ev_used; ++i) {
             float ms = 0.f;
-            MW_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+            MW_HIP(hipEventElapsedTime(&ms, evs[i].first, evs[i].second));
             walker_ms += ms;
-            walker_pending = false;
         }
+        ev_used = 0;
+        misses += h.tables_built - built_seen;
+        built_seen = h.tables_built;
         return h;
     }
 
     // One first-transition launch (round 0: every walk, writing its done
     // flag; later rounds: the walks still missing), without waiting.
     void launch_first(const std::vector<Segment>& segs, const StructDev* s0, unsigned long long total, int round,
-                      const float4* eval) {
+                      const float4* eval, bool dev_round = false) {
         FirstArgs F{};
         F.eval = eval;
         F.segs = dsegs;
@@ -3351,7 +3617,8 @@ struct Runner {
         F.lane_stride = g.first_stride;
         if (segs.size() == 1) F.S0 = *s0;
         F.round = round;
-        if (round > 0) MW_HIP(hipMemsetAsync(&ctr->first_missing, 0, 4, stream));
+        F.dev_round = dev_round ? 1 : 0;
+        if (round > 0 && !dev_round) MW_HIP(hipMemsetAsync(&ctr->first_missing, 0, 4, stream));
         const int fblocks = (int)std::min<uint64_t>((total + FRW_THREADS - 1) / FRW_THREADS, (uint64_t)g.first_blocks);
         if (segs.size() == 1)
             first_kernel<false><<<fblocks, FRW_THREADS, g.first_lds, stream>>>(F);
@@ -3361,7 +3628,7 @@ struct Runner {
     }
 
     // One walker launch over the current run (fresh walks not yet taken and
-    // the n_resume parked walks in park[cur]), without waiting.
+    // the parked walks the counters name), without waiting.
     void launch_walker() {
         const bool multi = !cur_single;
         WalkArgs W{};
@@ -3371,9 +3638,8 @@ struct Runner {
         W.cache = cache->d;
         W.n = n;
         W.hybrid = hybrid;
-        W.resume = park[cur];
-        W.n_resume = n_resume;
-        W.park_out = park[cur ^ 1];
+        W.park[0] = park[0];
+        W.park[1] = park[1];
         W.park_cap = park_cap;
         W.ctr = ctr;
         W.lane_stride = g.lane_stride;
@@ -3383,6 +3649,17 @@ struct Runner {
         // one-wave blocks: the grid sets the resident waves per CU
         const int blocks = waves_per_cu > 0 ? std::min(g.blocks, g.cus * waves_per_cu) : g.blocks;
         const int blocks_e = waves_per_cu > 0 ? std::min(g.blocks_e, g.cus * waves_per_cu) : g.blocks_e;
+        if (ev_used == evs.size()) {
+            hipEvent_t a = nullptr, b = nullptr;
+            MW_HIP(hipEventCreate(&a));
+            if (hipEventCreate(&b) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                MW_REQUIRE(false, MW_EDEVICE, "hipEventCreate failed");
+            }
+            evs.push_back({a, b});
+        }
+        hipEvent_t ev0 = evs[ev_used].first, ev1 = evs[ev_used].second;
+        ++ev_used;
         MW_HIP(hipEventRecord(ev0, stream));
         if (expand_m > 0) {
             W.lane_stride = g.lane_stride_e;
@@ -3408,8 +3685,22 @@ struct Runner {
         }
         MW_HIP(hipGetLastError());
         MW_HIP(hipEventRecord(ev1, stream));
-        walker_pending = true;
         ++launches;
+    }
+
+    // One device-driven round, enqueued without waiting: build the queued
+    // tables, redo first transitions that missed one, resume the parked
+    // walks.  A round with nothing to do costs a few empty launches.
+    void device_round() {
+        const uint32_t M = n - 1;
+        const size_t stride = (size_t)3 * M * M * M + (size_t)4 * 6 * M * M + 64;
+        if (!dev_work) dev_work = (double*)dev_alloc(sizeof(double) * stride * DEV_BUILD_MAX);
+        BuildArgs Ba{cache->d, cache->d.pending, 0u, dev_work, stride, cache->d.n_pending, ctr};
+        build_tables_kernel<<<DEV_BUILD_MAX, TB_THREADS, 0, stream>>>(Ba);
+        device_round_prep_kernel<<<1, 1, 0, stream>>>(ctr, cache->d, DEV_BUILD_MAX, park_cap);
+        MW_HIP(hipGetLastError());
+        launch_first(cur_segs, &cur_s0, cur_total, 1, nullptr, true);
+        launch_walker();
     }
 
     // Enqueues a run without waiting: counters and segments, the first
@@ -3421,10 +3712,10 @@ struct Runner {
         cur_single = segs.size() == 1;
         if (cur_single) cur_s0 = *s0;
         cur_total = upload(segs, s0);
-        n_resume = 0;
-        cur = 0;
+        built_seen = 0;
         launch_first(cur_segs, &cur_s0, cur_total, 0, nullptr);
         launch_walker();
+        for (int r = 0; r < DEVICE_ROUNDS; ++r) device_round();
     }
 
     // Waits for the started run and completes it: missing tables are built,
@@ -3444,13 +3735,10 @@ struct Runner {
             }
             // a lane that queued a table parked its walk
             if (h.park_count > 0) build_pending();
-            n_resume = std::min(h.park_count, park_cap);
-            cur ^= 1;
-            if (n_resume == 0 && h.walk_next >= cur_total) return h;
+            if (h.park_count == 0 && h.walk_next >= cur_total) return h;
             MW_REQUIRE(local < 100000, MW_ELIMIT, "walker relaunch limit reached");
-            // reset the per-launch queue state, keep the walk counter
-            MW_HIP(hipMemsetAsync(&ctr->park_count, 0, 4, stream));
-            MW_HIP(hipMemsetAsync(&ctr->resume_next, 0, 8, stream));
+            // the parked walks resume; the walk counter is kept
+            resume_prep_kernel<<<1, 1, 0, stream>>>(ctr, park_cap);
             launch_walker();
             h = read_counters();
         }
@@ -3546,6 +3834,12 @@ namespace {
 // 4 (too many pieces).
 constexpr size_t GAUSS_MAX_FACES = 1 << 16;
 constexpr size_t GAUSS_MAX_PATCHES = 1 << 22;
+
+// frw_extract: walks between two checks of the stopping rule (default), most
+// walks per launch, and the first launch of an extraction with no size hint
+constexpr uint64_t FRW_CHECKPOINT = 1u << 18;
+constexpr uint64_t FRW_LAUNCH_CAP = 1u << 22;
+constexpr uint64_t FRW_FIRST_LAUNCH = 1u << 20;
 
 struct GaussHost {
     double g = 0, area = 0;
@@ -3664,11 +3958,13 @@ struct Extraction {
     float4* partial;
     double* acc;
     double* result;
+    Choice* choice;
     int32_t* score_net;
     float* score_w;
     float4* first_state;
     uint32_t* first_done;
-    uint64_t done = 0;
+    uint64_t done = 0;      // walks in the sums
+    uint64_t launched = 0;  // walks walked, including those after the stopping checkpoint
     std::vector<double> res;
 
     static size_t bytes(int K, uint64_t chunk_cap, bool chunk_buffers = true, size_t n_faces = 6) {
@@ -3710,7 +4006,7 @@ struct Extraction {
         const size_t o_sd = sz(sizeof(StructDev)), o_G = sz(sizeof(GaussDev)), o_gf = sz(sizeof(GaussFace) * n_faces);
         const size_t o_acc = sz(sizeof(double) * 2 * K);  // zeroed by the same copy
         const size_t o_part = sz(sizeof(float4) * red_blocks * K);
-        const size_t o_res = sz(sizeof(double) * 2 * K);
+        const size_t o_res = sz(sizeof(double) * 2 * K + sizeof(Choice));  // the choice follows the row
         const size_t o_fs = own_first ? sz(sizeof(float4) * chunk_cap) : 0;
         const size_t o_fd = own_first ? sz(sizeof(uint32_t) * chunk_cap) : 0;
         const size_t o_sn = own_scores ? sz(4 * chunk_cap) : 0, o_sw = own_scores ? sz(4 * chunk_cap) : 0;
@@ -3720,6 +4016,7 @@ struct Extraction {
         partial = (float4*)(mem + o_part);
         acc = (double*)(mem + o_acc);
         result = (double*)(mem + o_res);
+        choice = (Choice*)(result + 2 * K);
         first_state = own_first ? (float4*)(mem + o_fs) : nullptr;
         first_done = own_first ? (uint32_t*)(mem + o_fd) : nullptr;
         score_net = own_scores ? (int32_t*)(mem + o_sn) : nullptr;
@@ -3848,42 +4145,44 @@ struct Extraction {
         return s;
     }
 
-    // Adds the scores of a finished segment to the fp64 sums (segments in
-    // walk order); refreshes res.
-    void reduce(const Segment& s, hipStream_t stream = nullptr) {
-        const int rb = (int)((s.count + RED_CHUNK - 1) / RED_CHUNK);
-        done += s.count;
-        reduce_scores_kernel<<<rb, RED_THREADS, 0, stream>>>(s.score_net, s.score_w, s.count, K, partial);
-        finish_kernel<<<K, FIN_THREADS, 0, stream>>>(partial, rb, K, acc, (double)done, result, nullptr, 0ull);
-        MW_HIP(hipGetLastError());
-        MW_HIP(hipMemcpyAsync(res.data(), result, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, stream));
-        MW_HIP(hipStreamSynchronize(stream));
-    }
-
-    // One batch with a single wait in the usual case: the walks, then the
-    // reduction gated on the walker's counters and one copy of the row and
-    // the counters.  When a walk parked or a first transition missed its
-    // table the gate drops the sums; the batch is then completed and reduced
-    // as usual.
-    Counters run_batch(Runner& R, const Segment& sg) {
-        R.start({sg}, &hS);
+    // One launch of walks [done, done + sg.count) (done is a checkpoint)
+    // with a single wait in the usual case: the walks, then the reduction,
+    // the stopping rule and the binary64 sums, all gated on the walker's
+    // counters, and one copy of the row and the choice.  When a walk parked
+    // or a first transition missed its table the gate drops all three; the
+    // launch's walks are then completed and the same kernels run ungated.
+    // Returns the walker counters; *met tells whether the target was met.
+    Counters run_launch(Runner& R, const Segment& sg, int per_ck, double target, bool* met) {
         const int rb = (int)((sg.count + RED_CHUNK - 1) / RED_CHUNK);
-        reduce_scores_kernel<<<rb, RED_THREADS, 0, R.stream>>>(sg.score_net, sg.score_w, sg.count, K, partial);
-        finish_kernel<<<K, FIN_THREADS, 0, R.stream>>>(partial, rb, K, acc, (double)(done + sg.count), result, R.ctr,
-                                                        sg.count);
-        MW_HIP(hipGetLastError());
-        Counters h{};
-        std::vector<double> row(2 * K);
-        MW_HIP(hipMemcpyAsync(row.data(), result, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, R.stream));
-        h = R.read_counters();  // waits for the stream
-        if (h.park_count == 0 && h.first_missing == 0 && h.walk_next >= sg.count && !(h.err & ERR_TABLE_CAP)) {
+        const size_t out_bytes = sizeof(double) * 2 * K + sizeof(Choice);
+        std::vector<char> out(out_bytes);
+        auto tail = [&](const Counters* gate) {
+            reduce_scores_kernel<<<rb, RED_THREADS, 0, R.stream>>>(sg.score_net, sg.score_w, sg.count, K, partial,
+                                                                    gate, sg.count);
+            decide_kernel<<<1, 64, 0, R.stream>>>(partial, rb, K, master, per_ck, acc, (double)done, sg.count, target,
+                                                  gate, sg.count, choice);
+            finish_seq_kernel<<<K, 64, 0, R.stream>>>(partial, K, acc, (double)done, choice, result);
+            MW_HIP(hipGetLastError());
+            MW_HIP(hipMemcpyAsync(out.data(), result, out_bytes, hipMemcpyDeviceToHost, R.stream));
+        };
+        R.start({sg}, &hS);
+        tail(R.ctr);
+        Counters h = R.read_counters();  // waits for the stream
+        Choice c;
+        memcpy(&c, out.data() + sizeof(double) * 2 * K, sizeof c);
+        if (c.blocks < 0) {
+            h = R.finish_from(h);
+            tail(nullptr);
+            MW_HIP(hipStreamSynchronize(R.stream));
+            memcpy(&c, out.data() + sizeof(double) * 2 * K, sizeof c);
+        } else {
             R.check_errors(h);
-            done += sg.count;
-            res = row;
-            return h;
         }
-        h = R.finish_from(h);
-        reduce(sg, R.stream);
+        MW_REQUIRE(c.blocks >= 0 && c.walks <= sg.count, MW_EDEVICE, "stopping rule returned no choice");
+        done += c.walks;
+        launched += sg.count;
+        memcpy(res.data(), out.data(), sizeof(double) * 2 * K);
+        *met = c.met != 0;
         return h;
     }
 
@@ -4080,30 +4379,56 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         MW_REQUIRE(dev == st->device, MW_EINVAL, "structure belongs to device %d, current device is %d",
                    st->device, dev);
         const int n = opt.n_cells;
-        const LaunchGeom g = launch_geom(n);
-        uint64_t batch = opt.batch_walks ? opt.batch_walks : std::max<uint64_t>(g.pool * 8, 1 << 20);
-        if (opt.target_rel_3sigma <= 0) batch = walk_budget;  // fixed budget: one pass
-        batch = std::min<uint64_t>(batch, walk_budget);
+        const bool target_mode = opt.target_rel_3sigma > 0;
+        // the stopping rule's checkpoints: every ck walks, a whole number of
+        // reduction blocks; a launch walks a whole number of checkpoints (or
+        // reduction blocks without a target) and the binary64 sums run in
+        // walk order, so the result does not depend on the launch sizes
+        uint64_t ck = RED_CHUNK;
+        if (target_mode) {
+            ck = opt.batch_walks ? opt.batch_walks : FRW_CHECKPOINT;
+            ck = (ck + RED_CHUNK - 1) / RED_CHUNK * RED_CHUNK;
+        }
+        const uint64_t launch_cap = std::min<uint64_t>(walk_budget, std::max<uint64_t>(ck, FRW_LAUNCH_CAP / ck * ck));
+        // first launch: the walks the last extraction of this structure,
+        // master and rule needed, plus one checkpoint (performance only)
+        uint64_t next = launch_cap;
+        if (target_mode) {
+            const uint64_t hint = st->walk_hint(master, ck, opt.target_rel_3sigma);
+            next = hint ? hint + ck : std::max<uint64_t>(ck, FRW_FIRST_LAUNCH / ck * ck);
+        }
         const bool own_scores = !(score_net && score_w);
-        Extraction X(*st, master, opt.abs_tol_rel, batch, own_scores);
-        Runner R(n, opt.hybrid, batch, 1);
+        Extraction X(*st, master, opt.abs_tol_rel, launch_cap, own_scores);
+        Runner R(n, opt.hybrid, launch_cap, 1);
         R.expand_m = expand_m_of(opt);
         R.plain = opt.plain;
         (void)frw_tuned_waves(n, R.expand_m, &R.waves_per_cu);
         if (opt.gauss_is > 0) X.importance(R, opt.gauss_is * X.gauss_g);
         frw_stats acc{};
-        while (X.done < walk_budget) {
-            const uint64_t nb = std::min<uint64_t>(batch, walk_budget - X.done);
+        bool met = false;
+        while (X.done < walk_budget && !met) {
+            const uint64_t nb = std::min(std::min(next, launch_cap), walk_budget - X.done);
             const Segment sgm = X.segment(opt.first_walk + X.done, nb, seed, own_scores ? nullptr : score_net + X.done,
                                           own_scores ? nullptr : score_w + X.done);
             {
                 std::lock_guard<std::mutex> lock(R.cache->mu);
                 R.flushes = 0;
                 R.ensure_uniform_table();
-                add_counters(acc, X.run_batch(R, sgm));
+                add_counters(acc, X.run_launch(R, sgm, (int)(ck / RED_CHUNK), opt.target_rel_3sigma, &met));
             }
-            if (X.converged(opt.target_rel_3sigma)) break;
+            if (!met && target_mode) {
+                // the walks still needed, predicted from the estimate so far
+                // (performance only: the checkpoints decide)
+                const double m = X.res[X.master], se = X.res[X.K + X.master];
+                double want = 0.0;
+                if (m != 0.0 && se > 0.0) {
+                    const double rel = 3.0 * se / std::fabs(m) / opt.target_rel_3sigma;
+                    want = 1.05 * (double)X.done * rel * rel - (double)X.done;
+                }
+                next = want > (double)ck ? (uint64_t)std::ceil(want / (double)ck) * ck : ck;
+            }
         }
+        if (met) st->set_walk_hint(master, ck, opt.target_rel_3sigma, X.done);
         const int K = X.K;
         for (int j = 0; j < K; ++j) {
             cap_row[j] = X.res[j];
@@ -4112,6 +4437,7 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         if (stats) {
             *stats = acc;
             stats->walks = X.done;
+            stats->walks_launched = X.launched;
             stats->cache_miss = R.misses;
             stats->launches = R.launches;
             stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
@@ -4244,6 +4570,7 @@ extern "C" mw_status frw_extract_matrix(mw_structure* st, int32_t n_masters, con
             *stats = acc;
             stats->walks = 0;
             for (auto* e : X) stats->walks += e->done;
+            stats->walks_launched = stats->walks;
             stats->cache_miss = R.misses;
             stats->launches = R.launches;
             stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
@@ -4482,6 +4809,7 @@ struct mw_server {
                 (void)round->run(*R, X, sh, seeds, opt.first_walk);
                 for (auto& r : running) {
                     r->stats.walks = r->X->done;
+                    r->stats.walks_launched = r->X->done;
                     r->stats.gauss_g = r->X->gauss_g;
                     r->stats.gauss_area = r->X->gauss_area;
                     r->stats.gauss_faces = r->X->n_faces;

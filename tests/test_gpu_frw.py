@@ -275,8 +275,57 @@ def test_frw_autotune_keeps_results(mw, monkeypatch, tmp_path):
 def test_convergence_target(mw):
     st = W.c2_structure()
     r = mw.frw_extract(st, 0, 50000000, seed=9, target_rel_3sigma=0.02, batch_walks=200000)
-    assert r["stats"]["walks"] < 50000000
+    ck = 200704  # 200000 rounded up to whole 4096-walk reduction blocks
+    assert r["stats"]["walks"] < 50000000 and r["stats"]["walks"] % ck == 0
+    assert r["stats"]["walks_launched"] >= r["stats"]["walks"]
     assert 3 * r["se"][0] / r["row"][0] <= 0.02
+
+
+def _rel_at(net, w, n, master):
+    """3 SE / |mean| of the master column over the first n walks (binary64)."""
+    x = np.where(net[:n] == master, w[:n], 0.0)
+    m = x.sum() / n
+    var = max((x * x).sum() / n - m * m, 0.0) / (n - 1)
+    return 3 * np.sqrt(var) / abs(m)
+
+
+def test_target_stops_at_first_checkpoint(mw):
+    """The stopping rule against the per-walk scores: the row holds the walks
+    up to the first checkpoint (every 65536 walks) where 3 SE(C_mm)/|C_mm|
+    meets the target, recomputed here in binary64 from the same scores (the
+    GPU sums in fp32 per block, so a checkpoint within 1e-5 of the target
+    may fall either way)."""
+    st = W.c2_structure()
+    ck, target = 65536, 0.02
+    r = mw.frw_extract(st, 0, 3000000, seed=12, target_rel_3sigma=target, batch_walks=ck, scores=True)
+    n = r["stats"]["walks"]
+    assert n % ck == 0 and n < 3000000
+    net = r["net"].cpu().numpy()
+    w = r["w"].cpu().numpy().astype(np.float64)
+    assert _rel_at(net, w, n, 0) <= target * (1 + 1e-5)
+    for c in range(ck, n, ck):
+        assert _rel_at(net, w, c, 0) > target * (1 - 1e-5), c
+
+
+def test_target_rows_independent_of_launch_split(mw):
+    """A target-mode row depends on the walks, not on how they were split
+    into launches: a fresh structure handle (first launch of 2^20 walks,
+    then a predicted one), the same handle again (one launch sized from the
+    first call) and a fixed-budget call over the same number of walks give
+    bit-identical rows."""
+    st = W.c2_structure()
+    h = mw.StructureHandle(st)
+    kw = dict(seed=31, target_rel_3sigma=0.006, batch_walks=131072)
+    a = mw.frw_extract(h, 0, 20000000, **kw)
+    b = mw.frw_extract(h, 0, 20000000, **kw)
+    n = a["stats"]["walks"]
+    print("walks", n, a["stats"]["walks_launched"], a["stats"]["launches"], b["stats"]["walks_launched"],
+          b["stats"]["launches"])
+    assert n > (1 << 20) and n == b["stats"]["walks"]
+    assert np.array_equal(a["row"], b["row"]) and np.array_equal(a["se"], b["se"])
+    c = mw.frw_extract(h, 0, n, seed=31)
+    assert np.array_equal(a["row"], c["row"]) and np.array_equal(a["se"], c["se"])
+    h.close()
 
 
 def test_errors(mw):
