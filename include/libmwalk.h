@@ -277,7 +277,7 @@ typedef struct {
     uint64_t first_walk;      /* id of the first walk (resume point)         */
     uint64_t batch_walks;     /* walks between checks of the target (a
                                  multiple of 4096 after rounding up);
-                                 0 = 262144 for frw_extract                 */
+                                 0 = 65536 for frw_extract                 */
     double gauss_is;          /* sampling of the Gaussian-surface point.  0
                                  (default): uniform by area, weight factor
                                  |G|.  > 0: importance sampling over G (the
@@ -324,6 +324,9 @@ typedef struct {
                                  after the checkpoint where the target was
                                  met (not in the row); the counters above
                                  count the work of all of them               */
+    uint64_t tables_built_in_launch; /* frw_extract: SGF tables built by the
+                                 walker launches' builder waves while walks
+                                 waited for them (part of cache_miss)       */
 } frw_stats;
 
 /* ------------------------------------------------------------------------
@@ -336,7 +339,7 @@ typedef struct {
  * stderr_row[j] is the standard error of cap_row[j].  Runs walk_budget walks,
  * or, when options->target_rel_3sigma > 0, stops at the first checkpoint
  * (every options->batch_walks walks, rounded up to a multiple of 4096;
- * default 262144) where 3 SE(C_mm) / |C_mm| <= target, and the row holds
+ * default 65536) where 3 SE(C_mm) / |C_mm| <= target, and the row holds
  * exactly the walks up to that checkpoint.  The walks are run in launches of
  * several checkpoints, sized from the walk count the last such call on this
  * structure, master and rule needed; walks after the stopping checkpoint are
@@ -369,6 +372,14 @@ mw_status frw_extract(mw_structure* s, int32_t master, uint64_t walk_budget,
  * Synchronous.                                                              */
 mw_status frw_autotune(mw_structure* s, int32_t master, uint64_t walks, uint64_t seed,
                        const frw_options* options, int32_t* waves_per_cu);
+
+/* ------------------------------------------------------------------------
+ * mw_table_cache_clear — empties the transition-table cache of lattice size
+ * n_cells (even, 4..32) on the current device; later calls rebuild the
+ * tables they need (the tables are pure functions of their keys, so no
+ * result changes).  Must not run while an extraction or server uses that
+ * cache.  MW_EINVAL for a bad size.  Synchronous.                          */
+mw_status mw_table_cache_clear(int32_t n_cells);
 
 /* ------------------------------------------------------------------------
  * mw_sgf_table — one entry of the transition-table cache (the "analytical

@@ -282,7 +282,8 @@ class frw_stats(ctypes.Structure):
                 ("launches", ctypes.c_uint64), ("seconds", ctypes.c_double),
                 ("walker_seconds", ctypes.c_double), ("gauss_g", ctypes.c_double),
                 ("gauss_area", ctypes.c_double), ("gauss_faces", ctypes.c_uint64),
-                ("cube_halved", ctypes.c_uint64), ("walks_launched", ctypes.c_uint64)]
+                ("cube_halved", ctypes.c_uint64), ("walks_launched", ctypes.c_uint64),
+                ("tables_built_in_launch", ctypes.c_uint64)]
 
     def as_dict(self):
         return {"walks": self.walks, "hops": self.hops, "micro_steps": self.micro_steps,
@@ -291,7 +292,8 @@ class frw_stats(ctypes.Structure):
                 "hop_cap": self.hop_cap, "launches": self.launches, "seconds": self.seconds,
                 "walker_seconds": self.walker_seconds, "gauss_g": self.gauss_g,
                 "gauss_area": self.gauss_area, "gauss_faces": self.gauss_faces,
-                "cube_halved": self.cube_halved, "walks_launched": self.walks_launched}
+                "cube_halved": self.cube_halved, "walks_launched": self.walks_launched,
+                "tables_built_in_launch": self.tables_built_in_launch}
 
 
 def make_desc(st):
@@ -386,6 +388,11 @@ def frw_autotune(structure, master, walks, seed=0, n_cells=16, hybrid=1, expand=
     _check(_lib.frw_autotune(structure.handle, I32(master), U64(walks), U64(seed), ctypes.byref(opt),
                              ctypes.byref(w)))
     return int(w.value)
+
+
+def mw_table_cache_clear(n_cells):
+    """Empties the device's transition-table cache of this lattice size."""
+    _check(_lib.mw_table_cache_clear(I32(n_cells)))
 
 
 def mw_sgf_table(plane_codes, axis, kind=0, normal_axis=0):

@@ -25,6 +25,7 @@
 // their saved position (their random numbers depend only on walk id and hop
 // index, so parking does not change any result).
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <cmath>
@@ -138,7 +139,13 @@ struct Counters {
     uint32_t resume_count, resume_side;
     // device-driven rounds: tables they built, 1 once they handed over to
     // the host, 1 when their first-transition launch has walks to redo
-    uint32_t tables_built, dev_stop, need_first, pad2;
+    uint32_t tables_built, dev_stop, need_first;
+    // builder waves of a walker launch: tables built, next queue entry,
+    // walker waves finished
+    uint32_t walker_builds, build_next, walkers_done;
+    // set between launches: the next walker launch has no walk to resume
+    // and no fresh walk left (every block of it ends at once)
+    uint32_t launch_idle;
 };
 
 // A contiguous range of walks of one extraction request.  One launch of the
@@ -183,6 +190,14 @@ struct WalkArgs {
     uint32_t uniform_index; // table of the uniform cube
     int32_t expand_m;       // MicroWalk-E: expanded half-size n d / (2 m) (EXP kernels)
     int32_t plain;          // 1: every walk makes one transition per launch, then parks
+    // blocks [0, builders) are builder waves: they build the tables that
+    // walker lanes queue, each in its own global build space (build_stride
+    // doubles), marked ready with epoch (>= 2, unique per launch); lanes
+    // that need such a table wait for it (bounded) instead of parking
+    uint32_t builders;
+    uint32_t epoch;
+    double* build_space;
+    unsigned long long build_stride;
     // single-segment launches: a copy of the structure header, read through
     // the kernel-argument segment (uniform scalar loads) instead of memory
     // that the kernel also writes
@@ -941,10 +956,16 @@ __device__ uint32_t key_hash(uint32_t words, KeyF key) {
 
 // hash: key_hash of the key (computed by the caller).  On a hit, *glo and
 // *ghi receive the guide pair of word u's bucket in the table (loaded with the
-// key comparison).
+// key comparison).  A new key is queued for building (pending list).  A
+// table is ready when its ready word is nonzero, except that a walker launch
+// (epoch > 0) does not take tables built during itself (ready word = its
+// epoch: compute units may hold stale cache lines of them) other than `own`,
+// one its lane waited for.  LOOKUP_PARK leaves the table index in
+// *out_index (NO_INDEX while another lane is still adding the key).
 template <class KeyF>
 __device__ __forceinline__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t hash, uint32_t* out_index,
-                                               uint32_t u = 0, uint32_t* glo = nullptr, uint32_t* ghi = nullptr) {
+                                               uint32_t u = 0, uint32_t* glo = nullptr, uint32_t* ghi = nullptr,
+                                               uint32_t epoch = 0, uint32_t own = NO_INDEX) {
     const uint32_t words = C.key_words;
     uint32_t h = hash;
     if (h == 0u) h = 1u;
@@ -968,14 +989,18 @@ __device__ __forceinline__ int lookup_or_insert(const CacheDev& C, KeyF key, uin
                 __threadfence();
                 __hip_atomic_store(&C.slot[slot], hh | idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t pos = atomicAdd(C.n_pending, 1u);
-                C.pending[pos] = idx;
+                __hip_atomic_store(C.pending + pos, idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                *out_index = idx;
                 return LOOKUP_PARK;
             }
             cur = old;
         }
         if ((cur & SLOT_HASH_MASK) == hh) {
             const uint32_t idx = (uint32_t)cur;
-            if (idx == NO_INDEX) return LOOKUP_PARK;
+            if (idx == NO_INDEX) {
+                *out_index = NO_INDEX;
+                return LOOKUP_PARK;
+            }
             if (idx == FULL_INDEX) return LOOKUP_FULL;
             const uint32_t rdy = __hip_atomic_load(gpw(C.ready) + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             uint32_t g0 = 0, g1 = 0;
@@ -999,7 +1024,10 @@ __device__ __forceinline__ int lookup_or_insert(const CacheDev& C, KeyF key, uin
                 same &= v.w == (q + 3 < words ? key(q + 3) : 0u);
             }
             if (same) {
-                if (!rdy) return LOOKUP_PARK;
+                if (!rdy || (rdy == epoch && idx != own)) {
+                    *out_index = idx;
+                    return LOOKUP_PARK;
+                }
                 *out_index = idx;
                 if (glo) {
                     *glo = g0;
@@ -1044,10 +1072,12 @@ __device__ __forceinline__ void node_of_hit(int n, int b, int node[3]) {
     const int f = b / (M * M), rem = b - f * M * M;
     const int bb = rem / M + 1, aa = rem - (bb - 1) * M + 1;
     const int ax = f >> 1, side = f & 1;
-    const int o0 = ax == 0 ? 1 : 0, o1 = ax == 2 ? 1 : 2;
-    node[ax] = side ? n : 0;
-    node[o0] = aa;
-    node[o1] = bb;
+    const int face = side ? n : 0;
+    // the two in-plane axes in ascending order take aa and bb (selects: no
+    // indexed private array)
+    node[0] = ax == 0 ? face : aa;
+    node[1] = ax == 1 ? face : (ax == 0 ? aa : bb);
+    node[2] = ax == 2 ? face : bb;
 }
 
 // Looks up (or queues) the table of the key in key[0 .. C.key_words);
@@ -1686,7 +1716,14 @@ __device__ __forceinline__ int mw_block_e16(MwState& M, MwStateE& Q, LaneCube L,
 // the loop below, the others take table transitions, and the wave switches
 // between the two while at least half of its working lanes walk.
 // -------------------------------------------------------------------------
-enum Phase : int { PH_IDLE = 0, PH_NEED = 1, PH_MW = 2, PH_EXHAUSTED = 3, PH_PARK = 4 };
+// builder waves of a walker launch (defined with the table builds)
+__device__ void builder_wave(const CacheDev& C, Counters* K, uint32_t walker_blocks, double* space, uint32_t epoch,
+                             int lane);
+
+// PH_WAIT: the lane's next transition needs a table that the launch's
+// builder waves are building; it waits (bounded) and then makes it
+enum Phase : int { PH_IDLE = 0, PH_NEED = 1, PH_MW = 2, PH_EXHAUSTED = 3, PH_PARK = 4, PH_WAIT = 5 };
+constexpr uint32_t WAIT_TICKS = 200000;  // 2 ms of the 100 MHz wall clock
 
 // Consecutive indices handed to the lanes of a wave from a global counter,
 // claimed CLAIM_CHUNK at a time: one device-scope atomic per chunk instead of
@@ -1736,10 +1773,26 @@ __device__ __forceinline__ decltype(auto) walk_struct(const WalkArgs& A, const G
 // EXP: MicroWalk hops use expanded cubes (MicroWalk-E).
 // N16: ordinary MicroWalk reads cell codes as cell_code16 (n <= 16).
 template <bool MULTI, bool EXP, bool N16 = false>
-__global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
+// three resident waves per SIMD (at most 168 VGPRs) for the plain MicroWalk
+// kernels, whose LDS allows 11 waves per compute unit; two for MicroWalk-E
+__global__ void __launch_bounds__(WALK_THREADS) __attribute__((amdgpu_waves_per_eu(EXP ? 2 : 3)))
+frw_walk_kernel(WalkArgs A) {
     extern __shared__ uint32_t lds[];
     const int n = A.n;
     const int lane = threadIdx.x & 63;
+    // a launch with no parked walk to resume and no fresh walk left (a
+    // device-driven round after a run that finished) ends at once; the flag
+    // is fixed for the whole launch, so builder and walker waves agree
+    if (A.ctr->launch_idle) return;
+    if constexpr (!EXP) {
+        // MicroWalk-E launches have no builder waves (their registers are
+        // spent on the expanded cubes): their lanes park on missing tables
+        if (blockIdx.x < A.builders) {
+            builder_wave(A.cache, A.ctr, gridDim.x - A.builders, A.build_space + (size_t)blockIdx.x * A.build_stride,
+                         A.epoch, lane);
+            return;
+        }
+    }
     uint32_t* my = lds + threadIdx.x * A.lane_stride;
     const LaneCube L = lane_cube(my, n);
     const LaneExp E = lane_exp(my, n);  // used by EXP kernels only
@@ -1764,8 +1817,9 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
 
     // the parked walks this launch resumes (set by the kernel before it)
     const uint32_t n_resume = K.resume_count;
-    const Parked* resume = A.park[K.resume_side & 1u];
-    Parked* park_out = A.park[(K.resume_side & 1u) ^ 1u];
+    const bool side1 = (K.resume_side & 1u) != 0u;
+    const Parked* resume = side1 ? A.park[1] : A.park[0];
+    Parked* park_out = side1 ? A.park[0] : A.park[1];
 
     int phase = PH_IDLE;
     WaveClaim claim_rc, claim_fr;  // wave-level claims of resumed and fresh walks
@@ -1782,8 +1836,34 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
     MwState M{};
     MwStateE Q{};
     int env_net = 0;
+    // table this lane waits for (PH_WAIT), and after the wait the one built
+    // in this launch that the lane may take
+    uint32_t wait_idx = NO_INDEX;
+    uint32_t wait_t0 = 0;  // low word of the wall clock when the wait began
 
     for (;;) {
+        // ---- lanes waiting for a table that a builder wave is building:
+        // ready now (the transition is made again, after this compute
+        // unit's L1 lines are dropped so that the new table is read from
+        // L2), or parked after 2 ms ----
+        {
+            const uint64_t bw = __ballot(phase == PH_WAIT);
+            if (bw) {
+                bool got = false;
+                if (phase == PH_WAIT) {
+                    const uint32_t rdy =
+                        __hip_atomic_load(gpw(A.cache.ready) + wait_idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (rdy) {
+                        phase = PH_NEED;
+                        got = true;
+                    } else if ((uint32_t)wall_clock64() - wait_t0 > WAIT_TICKS) {
+                        phase = PH_PARK;
+                    }
+                }
+                if (__any(got)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (__ballot(phase != PH_WAIT && phase != PH_EXHAUSTED) == 0ull) __builtin_amdgcn_s_sleep(4);
+            }
+        }
         // ---- walks that park for the next launch: in the plain form after
         // each transition, and fresh walks whose first transition is still
         // missing (t = 0); one queue slot range claimed per wave ----
@@ -1878,13 +1958,13 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
             }
         }
         // (a lane about to park keeps the loop going: the next pass parks it)
-        if (!__any(phase == PH_NEED || phase == PH_MW || phase == PH_PARK)) break;
+        if (!__any(phase == PH_NEED || phase == PH_MW || phase == PH_PARK || phase == PH_WAIT)) break;
 
         // ---- one transition for lanes that need one ----
         if (phase == PH_NEED) {
             const GAS Segment& SG = gp(A.segs)[sg];
             auto& S = walk_struct<MULTI>(A, SG);
-            bool park = false, done = false;
+            bool park = false, done = false, wait_me = false;
             int net = S.n_nets;
             float3 c;
             float R;
@@ -1981,9 +2061,17 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                                     return q == 1 ? (uint32_t)n
                                                   : (q == 2 ? (uint32_t)sax : (q < KEY_HDR ? 0u : L.bz[q - KEY_HDR]));
                                 },
-                                hsh, &idx, r.x, &glo, &ghi);
+                                hsh, &idx, r.x, &glo, &ghi, A.epoch, wait_idx);
                         }
-                        if (res != LOOKUP_HIT) {
+                        if (res == LOOKUP_PARK && A.builders > 0 && idx != NO_INDEX) {
+                            // the table is being built in this launch: the
+                            // lane waits for it, then makes this transition
+                            // again
+                            wait_idx = idx;
+                            wait_me = true;
+                            --c_hops;
+                            --c_cls[I.cls];
+                        } else if (res != LOOKUP_HIT) {
                             if (res == LOOKUP_FULL) err |= ERR_TABLE_CAP;
                             park = true;
                             --c_hops;
@@ -2054,6 +2142,9 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
                 gpw(SG.score_net)[k] = net;
                 gpw(SG.score_w)[k] = omega;
                 phase = PH_IDLE;
+            } else if (wait_me) {
+                phase = PH_WAIT;
+                wait_t0 = (uint32_t)wall_clock64();
             } else if (park) {
                 const uint32_t slot = atomicAdd(&K.park_count, 1u);
                 if (slot < A.park_cap) {
@@ -2155,6 +2246,9 @@ __global__ void __launch_bounds__(WALK_THREADS) frw_walk_kernel(WalkArgs A) {
         if (c_halved) atomicAdd(&K.halved, c_halved);
         if (err) atomicOr(&K.err, err);
     }
+    // every key this wave queued is visible before the builders see it done
+    __threadfence();
+    if (lane == 0) atomicAdd(&K.walkers_done, 1u);
 }
 
 // -------------------------------------------------------------------------
@@ -2180,34 +2274,58 @@ struct BuildArgs {
     const Counters* ctr;
 };
 
-__global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
-    if (B.dev_count && (B.ctr->dev_stop || blockIdx.x >= *B.dev_count)) return;
-    const uint32_t idx = B.list[blockIdx.x];
-    if (idx >= B.cache.capacity) return;  // a queue entry of a full cache
-    const CacheDev& C = B.cache;
+// Storage of one table build besides the per-source mode columns: the
+// sine basis, eigenvalues, plane coefficients, a matrix product buffer and
+// the CDF chunk sums (in LDS for the build kernel, in global scratch for a
+// build inside the walker).
+struct BuildSpace {
+    double* zh;    // [src][r][m][l] mode columns, then [src][nb] exit rows (3 M^3 + 4 nb doubles)
+    double* Sm;    // 31 x 31
+    double* lam;   // 32
+    double* cr;    // 33
+    double* ar;    // 33
+    double* br;    // 33
+    double* tmp;   // 31 x 31
+    double* csum;  // TB_THREADS
+    int* clast;    // TB_THREADS
+    double* total;
+    int* last;
+    double* thomas;  // groups of 64 threads: 2 x 32 doubles per thread (elimination coefficients)
+};
+
+// Exact SGF table idx of the cache, built by a group of NT threads (thread
+// tid) that call sync() between phases.  Every value is computed by one
+// thread in a fixed order and the CDF is cut into TB_THREADS chunks whatever
+// NT is, so the table is the same bit for bit for any group size.  The
+// table's ready word receives ready_value.
+template <int NT, class Sync>
+__device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const BuildSpace& W, Sync sync,
+                                 uint32_t ready_value) {
     const uint32_t* key = C.keys + (size_t)idx * C.key_stride;
     const int kind = (int)key[0], n = (int)key[1], s = (int)key[2], anorm = (int)key[3];
     const int M = n - 1, M2 = M * M, nb = 6 * M2;
-    __shared__ double Sm[31 * 31];
-    __shared__ double lam[32];
-    __shared__ double cr[33], ar[33], br[33];
-    __shared__ double tmp[31 * 31];
-    double* zh = B.work + (size_t)blockIdx.x * B.work_stride;  // [src][r][m][l]
-    double* Pout = zh + (size_t)3 * M * M2;                      // [src][nb]
+    double* Sm = W.Sm;
+    double* lam = W.lam;
+    double* cr = W.cr;
+    double* ar = W.ar;
+    double* br = W.br;
+    double* tmp = W.tmp;
+    double* zh = W.zh;
+    double* Pout = zh + (size_t)3 * M * M2;  // [src][nb]
     const double norm = sqrt(2.0 / (double)(M + 1));
-    for (int q = threadIdx.x; q < M2; q += blockDim.x) {
+    for (int q = tid; q < M2; q += NT) {
         const int m = q / M + 1, p = q % M + 1;
         Sm[q] = norm * sin(M_PI * (double)(m * p) / (double)(M + 1));
     }
-    if (threadIdx.x < M) lam[threadIdx.x] = 2.0 - 2.0 * cos(M_PI * (double)(threadIdx.x + 1) / (double)(M + 1));
-    if (threadIdx.x >= 1 && threadIdx.x <= M) {
-        const int r = threadIdx.x;
+    if (tid < M) lam[tid] = 2.0 - 2.0 * cos(M_PI * (double)(tid + 1) / (double)(M + 1));
+    if (tid >= 1 && tid <= M) {
+        const int r = tid;
         const double em = (double)key[KEY_HDR + r - 1], ep = (double)key[KEY_HDR + r];
         cr[r] = 2.0 * (em + ep);
         ar[r] = 4.0 * em;
         br[r] = 4.0 * ep;
     }
-    __syncthreads();
+    sync();
     // local frame: w = s, (u, v) the other two axes ascending
     const int ua = s == 0 ? 1 : 0, va = s == 2 ? 1 : 2;
     const int c0 = n / 2;
@@ -2219,17 +2337,26 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
         src[1][lax] += 1;
         src[2][lax] -= 1;
     }
-    // tridiagonal solves, one (m, l) mode pair per thread
+    // tridiagonal solves, one (m, l) mode pair per thread; the elimination
+    // coefficients live in the thread's private memory in the build kernel
+    // and in global build space in the walker (whose registers stay free)
+    double th_local[NT == TB_THREADS ? 64 : 1];
+    double* cvals;
+    if constexpr (NT == TB_THREADS)
+        cvals = th_local;
+    else
+        cvals = W.thomas + (size_t)tid * 64;
+    double* dvals = cvals + 32;
     for (int sidx = 0; sidx < nsrc; ++sidx) {
         const int p0 = src[sidx][0], q0 = src[sidx][1], r0 = src[sidx][2];
-        for (int ml = threadIdx.x; ml < M2; ml += blockDim.x) {
+        for (int ml = tid; ml < M2; ml += NT) {
             const int m = ml / M, l = ml % M;  // 0-based modes
             const double lm = lam[m] + lam[l];
             const double rhs0 = Sm[m * M + (p0 - 1)] * Sm[l * M + (q0 - 1)];
             double* col = zh + (size_t)sidx * M * M2 + ml;  // stride M2 over r
             // Thomas algorithm: forward elimination, then back substitution
-            double dvals[32], cvals[32];
             double cprev = 0.0, dprev = 0.0;
+            #pragma unroll 1
             for (int r = 1; r <= M; ++r) {
                 const double diag = cr[r] * lm + ar[r] + br[r];
                 const double sub = r > 1 ? -ar[r] : 0.0;
@@ -2242,6 +2369,7 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
             }
             double xnext = dvals[M];
             col[(size_t)(M - 1) * M2] = xnext;
+            #pragma unroll 1
             for (int r = M - 1; r >= 1; --r) {
                 const double xr = dvals[r] - cvals[r] * xnext;
                 col[(size_t)(r - 1) * M2] = xr;
@@ -2249,7 +2377,7 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
             }
         }
     }
-    __syncthreads();
+    sync();
     // exit probabilities on the six faces, in global hit-index order
     for (int sidx = 0; sidx < nsrc; ++sidx) {
         const double* Z = zh + (size_t)sidx * M * M2;  // Z[(r-1)*M2 + m*M + l]
@@ -2260,16 +2388,18 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
             const double link = side ? br[M] : ar[1];
             const double* Zr = Z + (size_t)(r - 1) * M2;
             // Y[m][q] = sum_l Z[m][l] S[l][q]
-            for (int e = threadIdx.x; e < M2; e += blockDim.x) {
+            for (int e = tid; e < M2; e += NT) {
                 const int m = e / M, qq = e % M;
                 double acc = 0.0;
+                #pragma unroll 1
                 for (int l = 0; l < M; ++l) acc += Zr[m * M + l] * Sm[l * M + qq];
                 tmp[e] = acc;
             }
-            __syncthreads();
-            for (int e = threadIdx.x; e < M2; e += blockDim.x) {
+            sync();
+            for (int e = tid; e < M2; e += NT) {
                 const int p = e / M, qq = e % M;  // 0-based local coords p-1, q-1
                 double acc = 0.0;
+                #pragma unroll 1
                 for (int m = 0; m < M; ++m) acc += Sm[m * M + p] * tmp[m * M + qq];
                 int g[3];
                 g[ua] = p + 1;
@@ -2279,7 +2409,7 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
                 const int oa = s == 0 ? 1 : 0, ob = s == 2 ? 1 : 2;
                 P[f * M2 + (g[ob] - 1) * M + (g[oa] - 1)] = link * acc;
             }
-            __syncthreads();
+            sync();
         }
         // u faces (p = 1 or M) and v faces (q = 1 or M)
         for (int which = 0; which < 4; ++which) {
@@ -2288,20 +2418,23 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
             const int fixed = side ? M - 1 : 0;  // 0-based
             // X[l][r] = sum_m S[m][fixed] Z[r][m][l]  (u faces)
             // X[m][r] = sum_l S[l][fixed] Z[r][m][l]  (v faces)
-            for (int e = threadIdx.x; e < M2; e += blockDim.x) {
+            for (int e = tid; e < M2; e += NT) {
                 const int j = e / M, r = e % M;
                 const double* Zr = Z + (size_t)r * M2;
                 double acc = 0.0;
                 if (ufaces)
+                    #pragma unroll 1
                     for (int m = 0; m < M; ++m) acc += Sm[m * M + fixed] * Zr[m * M + j];
                 else
+                    #pragma unroll 1
                     for (int l = 0; l < M; ++l) acc += Sm[l * M + fixed] * Zr[j * M + l];
                 tmp[e] = acc;
             }
-            __syncthreads();
-            for (int e = threadIdx.x; e < M2; e += blockDim.x) {
+            sync();
+            for (int e = tid; e < M2; e += NT) {
                 const int other = e / M, r = e % M;  // other: q (u faces) or p (v faces), 0-based
                 double acc = 0.0;
+                #pragma unroll 1
                 for (int j = 0; j < M; ++j) acc += Sm[j * M + other] * tmp[j * M + r];
                 int g[3];
                 const int fa = ufaces ? ua : va;
@@ -2317,10 +2450,10 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
                 const int oa = fa == 0 ? 1 : 0, ob = fa == 2 ? 1 : 2;
                 P[f * M2 + (g[ob] - 1) * M + (g[oa] - 1)] = cr[r + 1] * acc;
             }
-            __syncthreads();
+            sync();
         }
     }
-    __syncthreads();
+    sync();
     // weights -> CDF (one thread: sequential prefix sum in hit-index order)
     uint32_t* tab = C.data + (size_t)idx * C.tab_words;
     if (kind == 1) {
@@ -2337,29 +2470,27 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
         const double* Pc = Pout;
         const double* Pp = Pout + nb;
         const double* Pm = Pout + 2 * nb;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        for (int b = tid; b < nb; b += NT) {
             const double w = 0.5 * (Gp * (Pc[b] - Pp[b]) + Gm * (Pm[b] - Pc[b]));
             Pout[3 * nb + b] = w;  // stored after the three rows (workspace sized for it)
         }
-        __syncthreads();
-        for (int q = threadIdx.x; q < (nb + 31) / 32; q += blockDim.x) {
+        sync();
+        for (int q = tid; q < (nb + 31) / 32; q += NT) {
             uint32_t bits = 0;
             for (int k = 0; k < 32 && q * 32 + k < nb; ++k)
                 if (Pout[3 * nb + q * 32 + k] > 0.0) bits |= 1u << k;
             tab[TAB_CDF + nb + q] = bits;
         }
     }
-    // weights -> CDF in hit-index order: each thread sums a contiguous
-    // chunk, one thread scans the chunk sums, every thread then writes its
-    // chunk's thresholds ceil(cum / total * 2^32) (the last equals 2^32
+    // weights -> CDF in hit-index order: each of TB_THREADS chunks is summed
+    // by one thread, one thread scans the chunk sums, every chunk then
+    // writes its thresholds ceil(cum / total * 2^32) (the last equals 2^32
     // exactly: the chunk sums are formed in the same order)
     const double* wv = kind == 1 ? Pout + 3 * nb : Pout;
     const bool absw = kind == 1;
-    __shared__ double csum[TB_THREADS];
-    __shared__ int clast[TB_THREADS];
     const int chunk = (nb + TB_THREADS - 1) / TB_THREADS;
-    const int b0 = threadIdx.x * chunk, b1 = min(nb, b0 + chunk);
-    {
+    for (int ch = tid; ch < TB_THREADS; ch += NT) {
+        const int b0 = ch * chunk, b1 = min(nb, b0 + chunk);
         double sloc = 0.0;
         int last = -1;
         for (int b = b0; b < b1; ++b) {
@@ -2367,28 +2498,27 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
             sloc += v;
             if (v > 0.0) last = b;
         }
-        csum[threadIdx.x] = sloc;
-        clast[threadIdx.x] = last;
+        W.csum[ch] = sloc;
+        W.clast[ch] = last;
     }
-    __syncthreads();
-    __shared__ double total_sh;
-    __shared__ int last_sh;
-    if (threadIdx.x == 0) {
+    sync();
+    if (tid == 0) {
         double run = 0.0;
         int last = 0;
         for (int t = 0; t < TB_THREADS; ++t) {
-            const double c = csum[t];
-            csum[t] = run;  // exclusive prefix
+            const double c = W.csum[t];
+            W.csum[t] = run;  // exclusive prefix
             run += c;
-            if (clast[t] >= 0) last = clast[t];
+            if (W.clast[t] >= 0) last = W.clast[t];
         }
-        total_sh = run;
-        last_sh = last;
+        *W.total = run;
+        *W.last = last;
     }
-    __syncthreads();
-    {
-        const double tot = total_sh;
-        const double off = csum[threadIdx.x];
+    sync();
+    const double tot = *W.total;
+    for (int ch = tid; ch < TB_THREADS; ch += NT) {
+        const int b0 = ch * chunk, b1 = min(nb, b0 + chunk);
+        const double off = W.csum[ch];
         double loc = 0.0;
         for (int b = b0; b < b1; ++b) {
             loc += absw ? fabs(wv[b]) : wv[b];
@@ -2396,13 +2526,13 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
             tab[TAB_CDF + b] = cv >= 4294967295.0 ? 0xffffffffu : (uint32_t)cv;
         }
     }
-    if (threadIdx.x == 0) {
-        tab[0] = (uint32_t)last_sh;
-        tab[1] = kind == 1 ? __float_as_uint((float)total_sh) : 0u;
+    if (tid == 0) {
+        tab[0] = (uint32_t)*W.last;
+        tab[1] = kind == 1 ? __float_as_uint((float)tot) : 0u;
     }
-    __syncthreads();
+    sync();
     // guide[g] = first b with CDF[b] > g * 2^GUIDE_SHIFT (CDF nondecreasing)
-    for (int g = threadIdx.x; g <= (1 << GUIDE_BITS); g += TB_THREADS) {
+    for (int g = tid; g <= (1 << GUIDE_BITS); g += NT) {
         const unsigned long long thr = (unsigned long long)g << GUIDE_SHIFT;
         uint32_t lo = 0, hi = (uint32_t)nb;
         while (lo < hi) {
@@ -2414,10 +2544,121 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
         }
         tab[TAB_GUIDE + g] = lo;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    sync();
+    if (tid == 0) {
         __threadfence();
-        C.ready[idx] = 1u;
+        __hip_atomic_store(C.ready + idx, ready_value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// doubles of global build space per table besides the mode columns: the
+// arrays BuildSpace keeps in LDS for the build kernel, and the elimination
+// coefficients of 64 threads
+constexpr size_t BUILD_SMALL = 31 * 31 * 2 + 32 + 33 * 3 + TB_THREADS * 2 + 4 + 64 * 64;
+
+__global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
+    if (B.dev_count && (B.ctr->dev_stop || blockIdx.x >= *B.dev_count)) return;
+    const uint32_t idx = B.list[blockIdx.x];
+    if (B.dev_count) {
+        // the cache's queue itself: every thread has read the entry, which
+        // is then reset for the keys of the next launch
+        __syncthreads();
+        if (threadIdx.x == 0) B.cache.pending[blockIdx.x] = NO_INDEX;
+    }
+    if (idx >= B.cache.capacity) return;  // taken by a builder wave, or a key that found the cache full
+    __shared__ double Sm[31 * 31];
+    __shared__ double lam[32];
+    __shared__ double cr[33], ar[33], br[33];
+    __shared__ double tmp[31 * 31];
+    __shared__ double csum[TB_THREADS];
+    __shared__ int clast[TB_THREADS];
+    __shared__ double total_sh;
+    __shared__ int last_sh;
+    BuildSpace W;
+    W.zh = B.work + (size_t)blockIdx.x * B.work_stride;
+    W.Sm = Sm;
+    W.lam = lam;
+    W.cr = cr;
+    W.ar = ar;
+    W.br = br;
+    W.tmp = tmp;
+    W.csum = csum;
+    W.clast = clast;
+    W.total = &total_sh;
+    W.last = &last_sh;
+    W.thomas = nullptr;
+    build_table_body<TB_THREADS>(B.cache, idx, (int)threadIdx.x, W, [] { __syncthreads(); }, 1u);
+}
+
+// Builder waves of a walker launch (its first `builders` blocks): they take
+// the keys that walker lanes queue (the cache's pending list, in order,
+// claimed through K->build_next), build each table in their own global
+// build space with all 64 lanes and mark it ready with the launch's epoch;
+// they stop once every walker wave has finished and the queue is empty.
+// Phases of a build are separated by agent-scope fences (the lanes exchange
+// data through global memory).  A consumed queue entry is reset to
+// NO_INDEX; an entry whose writer does not show up is left for the builds
+// between launches.
+__device__ void builder_wave(const CacheDev& C, Counters* K, uint32_t walker_blocks, double* space, uint32_t epoch,
+                             int lane) {
+    BuildSpace W;
+    W.Sm = space;
+    W.lam = W.Sm + 31 * 31;
+    W.cr = W.lam + 32;
+    W.ar = W.cr + 33;
+    W.br = W.ar + 33;
+    W.tmp = W.br + 33;
+    W.csum = W.tmp + 31 * 31;
+    W.clast = reinterpret_cast<int*>(W.csum + TB_THREADS);
+    W.total = W.csum + 2 * TB_THREADS;
+    W.last = reinterpret_cast<int*>(W.total + 2);
+    W.thomas = W.total + 4;
+    W.zh = space + BUILD_SMALL;
+    for (;;) {
+        uint32_t ci = NO_INDEX;
+        int stop = 0;
+        if (lane == 0) {
+            for (;;) {
+                const uint32_t np = __hip_atomic_load(C.n_pending, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t bn = __hip_atomic_load(&K->build_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (bn < np) {
+                    if (atomicCAS(&K->build_next, bn, bn + 1u) == bn) {
+                        ci = bn;
+                        break;
+                    }
+                    continue;
+                }
+                if (__hip_atomic_load(&K->walkers_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= walker_blocks) {
+                    // every key queued in this launch was queued before its
+                    // wave finished: one more look at the queue
+                    if (__hip_atomic_load(C.n_pending, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <= bn) {
+                        stop = 1;
+                        break;
+                    }
+                    continue;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        stop = __shfl(stop, 0);
+        if (stop) return;
+        ci = __shfl(ci, 0);
+        uint32_t idx = NO_INDEX;
+        if (lane == 0) {
+            // the lane that took slot ci writes it right after taking it
+            for (int it = 0; it < (1 << 20); ++it) {
+                idx = __hip_atomic_load(C.pending + ci, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (idx != NO_INDEX) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (idx != NO_INDEX)
+                __hip_atomic_store(C.pending + ci, NO_INDEX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        idx = __shfl(idx, 0);
+        if (idx >= C.capacity) continue;
+        __threadfence();
+        build_table_body<64>(C, idx, lane, W, [] { __threadfence(); }, epoch);
+        if (lane == 0) atomicAdd(&K->walker_builds, 1u);
     }
 }
 
@@ -2425,14 +2666,21 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
 // Between walker launches.  The next launch resumes the walks the last one
 // parked, from the queue it wrote, with the queue state reset.
 // -------------------------------------------------------------------------
-__device__ __forceinline__ void prep_resume(Counters& K, uint32_t park_cap) {
+__device__ __forceinline__ void prep_resume(Counters& K, uint32_t park_cap, unsigned long long total) {
     K.resume_count = min(K.park_count, park_cap);
+    K.launch_idle = K.resume_count == 0u && K.walk_next >= total ? 1u : 0u;
     K.resume_side ^= 1u;
     K.park_count = 0u;
     K.resume_next = 0ull;
+    // the build queue was emptied before this kernel: its builder waves
+    // start from entry 0
+    K.build_next = 0u;
+    K.walkers_done = 0u;
 }
 
-__global__ void resume_prep_kernel(Counters* K, uint32_t park_cap) { prep_resume(*K, park_cap); }
+__global__ void resume_prep_kernel(Counters* K, uint32_t park_cap, unsigned long long total) {
+    prep_resume(*K, park_cap, total);
+}
 
 // A device-driven round (no host decision between launches): the tables
 // queued by the earlier launches were built by the kernel before this one,
@@ -2440,20 +2688,23 @@ __global__ void resume_prep_kernel(Counters* K, uint32_t park_cap) { prep_resume
 // resume.  More queued tables than that build covers hand everything over
 // to the host: the rest of the round does nothing and the parked walks stay
 // where they are.
-__global__ void device_round_prep_kernel(Counters* K, CacheDev C, uint32_t build_max, uint32_t park_cap) {
+__global__ void device_round_prep_kernel(Counters* K, CacheDev C, uint32_t build_max, uint32_t park_cap,
+                                         unsigned long long total) {
     if (K->dev_stop) return;
     const uint32_t np = *C.n_pending;
     if (np > build_max) {
         K->dev_stop = 1u;
         K->need_first = 0u;
         K->resume_count = 0u;
+        K->launch_idle = 1u;
         return;
     }
     *C.n_pending = 0u;
-    K->tables_built += np;
+    // entries taken by the last launch's builder waves are counted there
+    K->tables_built += np > K->build_next ? np - K->build_next : 0u;
     K->need_first = K->first_missing;
     K->first_missing = 0u;
-    prep_resume(*K, park_cap);
+    prep_resume(*K, park_cap, total);
 }
 
 // -------------------------------------------------------------------------
@@ -2766,19 +3017,8 @@ __device__ __forceinline__ void mean_se(double s1, double s2, double n, double* 
 __device__ __forceinline__ void stage_column(const float4* __restrict__ partial, int blocks, int K, int j,
                                              float4* col) {
     const int nb = min(blocks, DECIDE_MAX_BLOCKS);
-    for (int b0 = 0; b0 < nb; b0 += 64 * 4) {
-        float4 v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int b = b0 + u * 64 + (int)threadIdx.x;
-            if (b < nb) v[u] = partial[(size_t)b * K + j];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int b = b0 + u * 64 + (int)threadIdx.x;
-            if (b < nb) col[b] = v[u];
-        }
-    }
+#pragma unroll 4
+    for (int b = (int)threadIdx.x; b < nb; b += 64) col[b] = partial[(size_t)b * K + j];
     __syncthreads();
 }
 
@@ -2804,18 +3044,24 @@ __global__ void __launch_bounds__(64) decide_kernel(const float4* __restrict__ p
         double s1 = acc[master], s2 = acc[K + master];
         int to_ck = per_ck;
         for (int b0 = 0; b0 < blocks && !met; b0 += 8) {
-            // eight partials loaded ahead, added one at a time
-            float4 pv[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int b = b0 + u;
-                pv[u] = b >= blocks ? make_float4(0.f, 0.f, 0.f, 0.f)
-                                    : (b < DECIDE_MAX_BLOCKS ? pm[b] : partial[(size_t)b * K + master]);
-            }
-            for (int u = 0; u < 8 && b0 + u < blocks; ++u) {
-                const int b = b0 + u;
-                s1 += (double)pv[u].x + (double)pv[u].y;
-                s2 += (double)pv[u].z + (double)pv[u].w;
+            // eight partials loaded ahead (registers), added one at a time
+            float4 p0, p1, p2, p3, p4, p5, p6, p7;
+            auto ld = [&](int b) {
+                return b >= blocks ? make_float4(0.f, 0.f, 0.f, 0.f)
+                                   : (b < DECIDE_MAX_BLOCKS ? pm[b] : partial[(size_t)b * K + master]);
+            };
+            p0 = ld(b0);
+            p1 = ld(b0 + 1);
+            p2 = ld(b0 + 2);
+            p3 = ld(b0 + 3);
+            p4 = ld(b0 + 4);
+            p5 = ld(b0 + 5);
+            p6 = ld(b0 + 6);
+            p7 = ld(b0 + 7);
+            auto add = [&](const float4& p, int b) {
+                if (met || b >= blocks) return;
+                s1 += (double)p.x + (double)p.y;
+                s2 += (double)p.z + (double)p.w;
                 if (--to_ck == 0 || b + 1 == blocks) {
                     to_ck = per_ck;
                     const unsigned long long w = min((unsigned long long)(b + 1) * RED_CHUNK, count);
@@ -2824,10 +3070,17 @@ __global__ void __launch_bounds__(64) decide_kernel(const float4* __restrict__ p
                     if (m != 0.0 && 3.0 * se / fabs(m) <= target) {
                         chosen = b + 1;
                         met = 1;
-                        break;
                     }
                 }
-            }
+            };
+            add(p0, b0);
+            add(p1, b0 + 1);
+            add(p2, b0 + 2);
+            add(p3, b0 + 3);
+            add(p4, b0 + 4);
+            add(p5, b0 + 5);
+            add(p6, b0 + 6);
+            add(p7, b0 + 7);
         }
     } else if (threadIdx.x != 0) {
         return;
@@ -2849,21 +3102,26 @@ __global__ void __launch_bounds__(64) finish_seq_kernel(const float4* __restrict
     if (threadIdx.x != 0) return;
     double s1 = acc[j], s2 = acc[K + j];
     for (int b0 = 0; b0 < nb; b0 += 8) {
-        // eight partials loaded ahead, added one at a time
-        float4 pv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int b = b0 + u;
-            pv[u] = b >= nb ? make_float4(0.f, 0.f, 0.f, 0.f)
-                            : (b < DECIDE_MAX_BLOCKS ? col[b] : partial[(size_t)b * K + j]);
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (b0 + u < nb) {
-                s1 += (double)pv[u].x + (double)pv[u].y;
-                s2 += (double)pv[u].z + (double)pv[u].w;
-            }
-        }
+        // eight partials loaded ahead (registers), added one at a time
+        auto ld = [&](int b) {
+            return b >= nb ? make_float4(0.f, 0.f, 0.f, 0.f)
+                           : (b < DECIDE_MAX_BLOCKS ? col[b] : partial[(size_t)b * K + j]);
+        };
+        const float4 p0 = ld(b0), p1 = ld(b0 + 1), p2 = ld(b0 + 2), p3 = ld(b0 + 3), p4 = ld(b0 + 4),
+                     p5 = ld(b0 + 5), p6 = ld(b0 + 6), p7 = ld(b0 + 7);
+        auto add = [&](const float4& p, int b) {
+            if (b >= nb) return;
+            s1 += (double)p.x + (double)p.y;
+            s2 += (double)p.z + (double)p.w;
+        };
+        add(p0, b0);
+        add(p1, b0 + 1);
+        add(p2, b0 + 2);
+        add(p3, b0 + 3);
+        add(p4, b0 + 4);
+        add(p5, b0 + 5);
+        add(p6, b0 + 6);
+        add(p7, b0 + 7);
     }
     acc[j] = s1;
     acc[K + j] = s2;
@@ -2998,6 +3256,24 @@ struct Cache {
     std::mutex mu;
     uint32_t uniform_index = NO_INDEX;  // valid until the cache is emptied
     uint64_t flushes = 0;               // times the full cache was emptied
+    // walker launches number their in-launch table builds 2, 3, ... (ready
+    // words of tables built elsewhere are 1)
+    std::atomic<uint32_t> epoch{1};
+    uint32_t next_epoch() {
+        uint32_t e = ++epoch;
+        while (e < 2) e = ++epoch;
+        return e;
+    }
+    // Empties the cache (with its lock held and no FRW work in flight).
+    void clear() {
+        MW_HIP(hipMemset(d.slot, 0, 8ull * ((size_t)d.slot_mask + 1)));
+        MW_HIP(hipMemset(d.ready, 0, 4ull * d.capacity));
+        MW_HIP(hipMemset(d.n_tables, 0, 4));
+        MW_HIP(hipMemset(d.n_pending, 0, 4));
+        MW_HIP(hipMemset(d.pending, 0xff, 4ull * d.capacity));
+        MW_HIP(hipDeviceSynchronize());
+        uniform_index = NO_INDEX;
+    }
 };
 
 std::mutex g_cache_mu;
@@ -3050,6 +3326,7 @@ Cache& get_cache(int n) {
         MW_HIP(hipMemset(c->d.slot, 0, b_hash));
         MW_HIP(hipMemset(c->d.ready, 0, b_ready));
         MW_HIP(hipMemset(misc, 0, b_misc));
+        MW_HIP(hipMemset(c->d.pending, 0xff, b_pend));  // empty queue entries hold NO_INDEX
         MW_HIP(hipDeviceSynchronize());
         slot = std::move(c);
     }
@@ -3368,6 +3645,8 @@ LaunchGeom launch_geom(int n) {
 // queued tables one such round builds.
 constexpr int DEVICE_ROUNDS = 2;
 constexpr uint32_t DEV_BUILD_MAX = 128;
+// builder waves per walker launch (tables built during the launch)
+constexpr uint32_t WALKER_BUILDERS = 8;
 
 struct Runner {
     int n, hybrid;
@@ -3387,9 +3666,16 @@ struct Runner {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
     size_t ev_used = 0;
     uint64_t misses = 0, launches = 0;
-    uint32_t built_seen = 0;  // device-round table builds already counted in misses
+    uint32_t built_seen = 0;   // device-round table builds already counted in misses
+    uint32_t wbuilt_seen = 0;  // walker table builds already counted
+    uint64_t walker_builds = 0;
     double walker_ms = 0.0;
     double* dev_work = nullptr;  // workspace of the device-round table builds
+    // builder waves of each walker launch and their build spaces (none:
+    // MWALK_WALKER_BUILDS=0)
+    double* wb_space = nullptr;
+    uint32_t wb_builders = 0;
+    unsigned long long wb_stride = 0;
     // stream of this runner's launches and copies (nullptr: the legacy
     // default stream); table builds and cache flushes always run on the
     // default stream with the device otherwise idle
@@ -3416,6 +3702,7 @@ struct Runner {
             o += (b + 255) / 256 * 256;
             return r;
         };
+        wb_builders = env_size("MWALK_WALKER_BUILDS", 1) ? WALKER_BUILDERS : 0u;
         // counters and segment list adjacent: one copy sets both per run
         const size_t o_ctr = sz(sizeof(Counters)), o_sg = sz(sizeof(Segment) * (size_t)seg_cap), o_st = sz(16);
         const size_t o_p0 = sz(sizeof(Parked) * (size_t)park_cap), o_p1 = sz(sizeof(Parked) * (size_t)park_cap);
@@ -3442,6 +3729,7 @@ struct Runner {
             (void)hipEventDestroy(e.second);
         }
         dev_free(dev_work);
+        dev_free(wb_space);
         dev_free(mem);
     }
 
@@ -3481,6 +3769,7 @@ struct Runner {
             MW_HIP(hipGetLastError());
         }
         MW_HIP(hipDeviceSynchronize());
+        MW_HIP(hipMemset(cache->d.pending, 0xff, 4ull * npend));  // entries read: NO_INDEX again
         MW_HIP(hipMemset(cache->d.n_pending, 0, 4));
         misses += valid.size();
         return valid.size();
@@ -3514,13 +3803,8 @@ struct Runner {
     void flush_cache() {
         MW_REQUIRE(++flushes <= 4096, MW_ELIMIT,
                    "SGF table cache emptied 4096 times in one call (raise MWALK_TABLE_CAP)");
-        const CacheDev& d = cache->d;
-        MW_HIP(hipMemset(d.slot, 0, 8ull * ((size_t)d.slot_mask + 1)));
-        MW_HIP(hipMemset(d.ready, 0, 4ull * d.capacity));
-        MW_HIP(hipMemset(d.n_tables, 0, 4));
-        MW_HIP(hipMemset(d.n_pending, 0, 4));
-        MW_HIP(hipDeviceSynchronize());
-        cache->uniform_index = uniform_index = NO_INDEX;
+        cache->clear();
+        uniform_index = NO_INDEX;
         ++cache->flushes;
         ensure_uniform_table();
     }
@@ -3584,6 +3868,7 @@ struct Runner {
         memcpy(staging.data() + off, segs.data(), sizeof(Segment) * segs.size());
         MW_HIP(hipMemcpyAsync(ctr, staging.data(), staging.size(), hipMemcpyHostToDevice, stream));
         MW_HIP(hipStreamSynchronize(stream));  // the staging buffer goes out of scope
+        built_seen = wbuilt_seen = 0;          // the counters restart at zero
         return total;
     }
 
@@ -3599,6 +3884,9 @@ struct Runner {
         ev_used = 0;
         misses += h.tables_built - built_seen;
         built_seen = h.tables_built;
+        misses += h.walker_builds - wbuilt_seen;
+        walker_builds += h.walker_builds - wbuilt_seen;
+        wbuilt_seen = h.walker_builds;
         return h;
     }
 
@@ -3641,6 +3929,15 @@ struct Runner {
         W.park[0] = park[0];
         W.park[1] = park[1];
         W.park_cap = park_cap;
+        if (wb_builders && !wb_space) {
+            const uint32_t M = n - 1;
+            wb_stride = (BUILD_SMALL + (unsigned long long)3 * M * M * M + 4ull * 6 * M * M + 31) / 32 * 32;
+            wb_space = (double*)dev_alloc(sizeof(double) * wb_stride * wb_builders);
+        }
+        W.builders = wb_builders;
+        W.epoch = cache->next_epoch();
+        W.build_space = wb_space;
+        W.build_stride = wb_stride;
         W.ctr = ctr;
         W.lane_stride = g.lane_stride;
         W.uniform_index = uniform_index;
@@ -3649,6 +3946,8 @@ struct Runner {
         // one-wave blocks: the grid sets the resident waves per CU
         const int blocks = waves_per_cu > 0 ? std::min(g.blocks, g.cus * waves_per_cu) : g.blocks;
         const int blocks_e = waves_per_cu > 0 ? std::min(g.blocks_e, g.cus * waves_per_cu) : g.blocks_e;
+        // the builder waves are part of the grid (none in MicroWalk-E launches)
+        W.builders = expand_m > 0 ? 0u : std::min<uint32_t>(W.builders, (uint32_t)(blocks / 8));
         if (ev_used == evs.size()) {
             hipEvent_t a = nullptr, b = nullptr;
             MW_HIP(hipEventCreate(&a));
@@ -3697,7 +3996,7 @@ struct Runner {
         if (!dev_work) dev_work = (double*)dev_alloc(sizeof(double) * stride * DEV_BUILD_MAX);
         BuildArgs Ba{cache->d, cache->d.pending, 0u, dev_work, stride, cache->d.n_pending, ctr};
         build_tables_kernel<<<DEV_BUILD_MAX, TB_THREADS, 0, stream>>>(Ba);
-        device_round_prep_kernel<<<1, 1, 0, stream>>>(ctr, cache->d, DEV_BUILD_MAX, park_cap);
+        device_round_prep_kernel<<<1, 1, 0, stream>>>(ctr, cache->d, DEV_BUILD_MAX, park_cap, cur_total);
         MW_HIP(hipGetLastError());
         launch_first(cur_segs, &cur_s0, cur_total, 1, nullptr, true);
         launch_walker();
@@ -3712,7 +4011,6 @@ struct Runner {
         cur_single = segs.size() == 1;
         if (cur_single) cur_s0 = *s0;
         cur_total = upload(segs, s0);
-        built_seen = 0;
         launch_first(cur_segs, &cur_s0, cur_total, 0, nullptr);
         launch_walker();
         for (int r = 0; r < DEVICE_ROUNDS; ++r) device_round();
@@ -3738,7 +4036,7 @@ struct Runner {
             if (h.park_count == 0 && h.walk_next >= cur_total) return h;
             MW_REQUIRE(local < 100000, MW_ELIMIT, "walker relaunch limit reached");
             // the parked walks resume; the walk counter is kept
-            resume_prep_kernel<<<1, 1, 0, stream>>>(ctr, park_cap);
+            resume_prep_kernel<<<1, 1, 0, stream>>>(ctr, park_cap, cur_total);
             launch_walker();
             h = read_counters();
         }
@@ -3789,6 +4087,16 @@ struct Runner {
 
 }  // namespace
 
+extern "C" mw_status mw_table_cache_clear(int32_t n_cells) {
+    return guarded([&] {
+        MW_REQUIRE(n_cells >= 4 && n_cells <= 32 && n_cells % 2 == 0, MW_EINVAL,
+                   "table lattice size must be even, 4..32");
+        Cache& c = get_cache(n_cells);
+        std::lock_guard<std::mutex> lock(c.mu);
+        c.clear();
+    });
+}
+
 extern "C" mw_status mw_sgf_table(int32_t n_cells, int32_t kind, int32_t axis, int32_t normal_axis,
                                   const uint32_t* plane_codes, uint32_t* cdf, uint32_t* sign_bits, float* kh) {
     return guarded([&] {
@@ -3837,7 +4145,7 @@ constexpr size_t GAUSS_MAX_PATCHES = 1 << 22;
 
 // frw_extract: walks between two checks of the stopping rule (default), most
 // walks per launch, and the first launch of an extraction with no size hint
-constexpr uint64_t FRW_CHECKPOINT = 1u << 18;
+constexpr uint64_t FRW_CHECKPOINT = 1u << 16;
 constexpr uint64_t FRW_LAUNCH_CAP = 1u << 22;
 constexpr uint64_t FRW_FIRST_LAUNCH = 1u << 20;
 
@@ -4391,11 +4699,13 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         }
         const uint64_t launch_cap = std::min<uint64_t>(walk_budget, std::max<uint64_t>(ck, FRW_LAUNCH_CAP / ck * ck));
         // first launch: the walks the last extraction of this structure,
-        // master and rule needed, plus one checkpoint (performance only)
+        // master and rule needed, plus 6 % (at least one checkpoint) for the
+        // spread between seeds (performance only)
         uint64_t next = launch_cap;
         if (target_mode) {
             const uint64_t hint = st->walk_hint(master, ck, opt.target_rel_3sigma);
-            next = hint ? hint + ck : std::max<uint64_t>(ck, FRW_FIRST_LAUNCH / ck * ck);
+            next = hint ? (hint + std::max<uint64_t>(hint / 16, 1) + ck - 1) / ck * ck
+                        : std::max<uint64_t>(ck, FRW_FIRST_LAUNCH / ck * ck);
         }
         const bool own_scores = !(score_net && score_w);
         Extraction X(*st, master, opt.abs_tol_rel, launch_cap, own_scores);
@@ -4439,6 +4749,7 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
             stats->walks = X.done;
             stats->walks_launched = X.launched;
             stats->cache_miss = R.misses;
+            stats->tables_built_in_launch = R.walker_builds;
             stats->launches = R.launches;
             stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
             stats->walker_seconds = R.walker_ms * 1e-3;
