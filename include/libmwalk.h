@@ -276,8 +276,8 @@ typedef struct {
                                  default 1e-6                               */
     uint64_t first_walk;      /* id of the first walk (resume point)         */
     uint64_t batch_walks;     /* walks between checks of the target (a
-                                 multiple of 4096 after rounding up);
-                                 0 = 65536 for frw_extract                 */
+                                 multiple of 65536 after rounding up for
+                                 frw_extract); 0 = 65536 for frw_extract    */
     double gauss_is;          /* sampling of the Gaussian-surface point.  0
                                  (default): uniform by area, weight factor
                                  |G|.  > 0: importance sampling over G (the
@@ -324,9 +324,6 @@ typedef struct {
                                  after the checkpoint where the target was
                                  met (not in the row); the counters above
                                  count the work of all of them               */
-    uint64_t tables_built_in_launch; /* frw_extract: SGF tables built by the
-                                 walker launches' builder waves while walks
-                                 waited for them (part of cache_miss)       */
 } frw_stats;
 
 /* ------------------------------------------------------------------------
@@ -338,16 +335,16 @@ typedef struct {
  * divided by the number of walks (fF); cap_row[n_nets] is the env column.
  * stderr_row[j] is the standard error of cap_row[j].  Runs walk_budget walks,
  * or, when options->target_rel_3sigma > 0, stops at the first checkpoint
- * (every options->batch_walks walks, rounded up to a multiple of 4096;
- * default 65536) where 3 SE(C_mm) / |C_mm| <= target, and the row holds
- * exactly the walks up to that checkpoint.  The walks are run in launches of
+ * (every options->batch_walks walks, rounded up to a multiple of 65536;
+ * default 65536, at most 2^27) where 3 SE(C_mm) / |C_mm| <= target, and
+ * the row holds exactly the walks up to that checkpoint.  The walks are run in launches of
  * several checkpoints, sized from the walk count the last such call on this
  * structure, master and rule needed; walks after the stopping checkpoint are
  * dropped (stats->walks_launched counts them).  Walk scores are summed per
- * net in fp32 with compensated (Kahan) sums per block of 4096 walks and in
- * fp64 across blocks, in walk order, so a row is the same for any split
- * into launches: a target-mode row equals the fixed-budget row of the same
- * number of walks.
+ * net in fp32 with compensated (Kahan) sums per block of 4096 walks, in
+ * fp64 over each group of 16 blocks and then over the groups in walk order,
+ * so a row is the same for any split into launches: a target-mode row
+ * equals the fixed-budget row of the same number of walks.
  * score_net/score_w (device, walk_budget entries each, or NULL): per-walk net
  * index (n_nets for env) and fp32 weight, indexed by walk - first_walk;
  * entries from stats->walks on are unspecified.

@@ -282,8 +282,7 @@ class frw_stats(ctypes.Structure):
                 ("launches", ctypes.c_uint64), ("seconds", ctypes.c_double),
                 ("walker_seconds", ctypes.c_double), ("gauss_g", ctypes.c_double),
                 ("gauss_area", ctypes.c_double), ("gauss_faces", ctypes.c_uint64),
-                ("cube_halved", ctypes.c_uint64), ("walks_launched", ctypes.c_uint64),
-                ("tables_built_in_launch", ctypes.c_uint64)]
+                ("cube_halved", ctypes.c_uint64), ("walks_launched", ctypes.c_uint64)]
 
     def as_dict(self):
         return {"walks": self.walks, "hops": self.hops, "micro_steps": self.micro_steps,
@@ -292,8 +291,7 @@ class frw_stats(ctypes.Structure):
                 "hop_cap": self.hop_cap, "launches": self.launches, "seconds": self.seconds,
                 "walker_seconds": self.walker_seconds, "gauss_g": self.gauss_g,
                 "gauss_area": self.gauss_area, "gauss_faces": self.gauss_faces,
-                "cube_halved": self.cube_halved, "walks_launched": self.walks_launched,
-                "tables_built_in_launch": self.tables_built_in_launch}
+                "cube_halved": self.cube_halved, "walks_launched": self.walks_launched}
 
 
 def make_desc(st):

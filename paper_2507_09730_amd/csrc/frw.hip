@@ -140,9 +140,6 @@ struct Counters {
     // device-driven rounds: tables they built, 1 once they handed over to
     // the host, 1 when their first-transition launch has walks to redo
     uint32_t tables_built, dev_stop, need_first;
-    // builder waves of a walker launch: tables built, next queue entry,
-    // walker waves finished
-    uint32_t walker_builds, build_next, walkers_done;
     // set between launches: the next walker launch has no walk to resume
     // and no fresh walk left (every block of it ends at once)
     uint32_t launch_idle;
@@ -190,14 +187,6 @@ struct WalkArgs {
     uint32_t uniform_index; // table of the uniform cube
     int32_t expand_m;       // MicroWalk-E: expanded half-size n d / (2 m) (EXP kernels)
     int32_t plain;          // 1: every walk makes one transition per launch, then parks
-    // blocks [0, builders) are builder waves: they build the tables that
-    // walker lanes queue, each in its own global build space (build_stride
-    // doubles), marked ready with epoch (>= 2, unique per launch); lanes
-    // that need such a table wait for it (bounded) instead of parking
-    uint32_t builders;
-    uint32_t epoch;
-    double* build_space;
-    unsigned long long build_stride;
     // single-segment launches: a copy of the structure header, read through
     // the kernel-argument segment (uniform scalar loads) instead of memory
     // that the kernel also writes
@@ -956,16 +945,11 @@ __device__ uint32_t key_hash(uint32_t words, KeyF key) {
 
 // hash: key_hash of the key (computed by the caller).  On a hit, *glo and
 // *ghi receive the guide pair of word u's bucket in the table (loaded with the
-// key comparison).  A new key is queued for building (pending list).  A
-// table is ready when its ready word is nonzero, except that a walker launch
-// (epoch > 0) does not take tables built during itself (ready word = its
-// epoch: compute units may hold stale cache lines of them) other than `own`,
-// one its lane waited for.  LOOKUP_PARK leaves the table index in
-// *out_index (NO_INDEX while another lane is still adding the key).
+// key comparison).  A new key is queued for building (pending list); a
+// table is ready when its ready word is nonzero.
 template <class KeyF>
 __device__ __forceinline__ int lookup_or_insert(const CacheDev& C, KeyF key, uint32_t hash, uint32_t* out_index,
-                                               uint32_t u = 0, uint32_t* glo = nullptr, uint32_t* ghi = nullptr,
-                                               uint32_t epoch = 0, uint32_t own = NO_INDEX) {
+                                               uint32_t u = 0, uint32_t* glo = nullptr, uint32_t* ghi = nullptr) {
     const uint32_t words = C.key_words;
     uint32_t h = hash;
     if (h == 0u) h = 1u;
@@ -989,18 +973,14 @@ __device__ __forceinline__ int lookup_or_insert(const CacheDev& C, KeyF key, uin
                 __threadfence();
                 __hip_atomic_store(&C.slot[slot], hh | idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t pos = atomicAdd(C.n_pending, 1u);
-                __hip_atomic_store(C.pending + pos, idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                *out_index = idx;
+                C.pending[pos] = idx;
                 return LOOKUP_PARK;
             }
             cur = old;
         }
         if ((cur & SLOT_HASH_MASK) == hh) {
             const uint32_t idx = (uint32_t)cur;
-            if (idx == NO_INDEX) {
-                *out_index = NO_INDEX;
-                return LOOKUP_PARK;
-            }
+            if (idx == NO_INDEX) return LOOKUP_PARK;
             if (idx == FULL_INDEX) return LOOKUP_FULL;
             const uint32_t rdy = __hip_atomic_load(gpw(C.ready) + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             uint32_t g0 = 0, g1 = 0;
@@ -1024,10 +1004,7 @@ __device__ __forceinline__ int lookup_or_insert(const CacheDev& C, KeyF key, uin
                 same &= v.w == (q + 3 < words ? key(q + 3) : 0u);
             }
             if (same) {
-                if (!rdy || (rdy == epoch && idx != own)) {
-                    *out_index = idx;
-                    return LOOKUP_PARK;
-                }
+                if (!rdy) return LOOKUP_PARK;
                 *out_index = idx;
                 if (glo) {
                     *glo = g0;
@@ -1716,14 +1693,7 @@ __device__ __forceinline__ int mw_block_e16(MwState& M, MwStateE& Q, LaneCube L,
 // the loop below, the others take table transitions, and the wave switches
 // between the two while at least half of its working lanes walk.
 // -------------------------------------------------------------------------
-// builder waves of a walker launch (defined with the table builds)
-__device__ void builder_wave(const CacheDev& C, Counters* K, uint32_t walker_blocks, double* space, uint32_t epoch,
-                             int lane);
-
-// PH_WAIT: the lane's next transition needs a table that the launch's
-// builder waves are building; it waits (bounded) and then makes it
-enum Phase : int { PH_IDLE = 0, PH_NEED = 1, PH_MW = 2, PH_EXHAUSTED = 3, PH_PARK = 4, PH_WAIT = 5 };
-constexpr uint32_t WAIT_TICKS = 200000;  // 2 ms of the 100 MHz wall clock
+enum Phase : int { PH_IDLE = 0, PH_NEED = 1, PH_MW = 2, PH_EXHAUSTED = 3, PH_PARK = 4 };
 
 // Consecutive indices handed to the lanes of a wave from a global counter,
 // claimed CLAIM_CHUNK at a time: one device-scope atomic per chunk instead of
@@ -1781,18 +1751,8 @@ frw_walk_kernel(WalkArgs A) {
     const int n = A.n;
     const int lane = threadIdx.x & 63;
     // a launch with no parked walk to resume and no fresh walk left (a
-    // device-driven round after a run that finished) ends at once; the flag
-    // is fixed for the whole launch, so builder and walker waves agree
+    // device-driven round after a run that finished) ends at once
     if (A.ctr->launch_idle) return;
-    if constexpr (!EXP) {
-        // MicroWalk-E launches have no builder waves (their registers are
-        // spent on the expanded cubes): their lanes park on missing tables
-        if (blockIdx.x < A.builders) {
-            builder_wave(A.cache, A.ctr, gridDim.x - A.builders, A.build_space + (size_t)blockIdx.x * A.build_stride,
-                         A.epoch, lane);
-            return;
-        }
-    }
     uint32_t* my = lds + threadIdx.x * A.lane_stride;
     const LaneCube L = lane_cube(my, n);
     const LaneExp E = lane_exp(my, n);  // used by EXP kernels only
@@ -1836,34 +1796,8 @@ frw_walk_kernel(WalkArgs A) {
     MwState M{};
     MwStateE Q{};
     int env_net = 0;
-    // table this lane waits for (PH_WAIT), and after the wait the one built
-    // in this launch that the lane may take
-    uint32_t wait_idx = NO_INDEX;
-    uint32_t wait_t0 = 0;  // low word of the wall clock when the wait began
 
     for (;;) {
-        // ---- lanes waiting for a table that a builder wave is building:
-        // ready now (the transition is made again, after this compute
-        // unit's L1 lines are dropped so that the new table is read from
-        // L2), or parked after 2 ms ----
-        {
-            const uint64_t bw = __ballot(phase == PH_WAIT);
-            if (bw) {
-                bool got = false;
-                if (phase == PH_WAIT) {
-                    const uint32_t rdy =
-                        __hip_atomic_load(gpw(A.cache.ready) + wait_idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (rdy) {
-                        phase = PH_NEED;
-                        got = true;
-                    } else if ((uint32_t)wall_clock64() - wait_t0 > WAIT_TICKS) {
-                        phase = PH_PARK;
-                    }
-                }
-                if (__any(got)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                if (__ballot(phase != PH_WAIT && phase != PH_EXHAUSTED) == 0ull) __builtin_amdgcn_s_sleep(4);
-            }
-        }
         // ---- walks that park for the next launch: in the plain form after
         // each transition, and fresh walks whose first transition is still
         // missing (t = 0); one queue slot range claimed per wave ----
@@ -1958,13 +1892,13 @@ frw_walk_kernel(WalkArgs A) {
             }
         }
         // (a lane about to park keeps the loop going: the next pass parks it)
-        if (!__any(phase == PH_NEED || phase == PH_MW || phase == PH_PARK || phase == PH_WAIT)) break;
+        if (!__any(phase == PH_NEED || phase == PH_MW || phase == PH_PARK)) break;
 
         // ---- one transition for lanes that need one ----
         if (phase == PH_NEED) {
             const GAS Segment& SG = gp(A.segs)[sg];
             auto& S = walk_struct<MULTI>(A, SG);
-            bool park = false, done = false, wait_me = false;
+            bool park = false, done = false;
             int net = S.n_nets;
             float3 c;
             float R;
@@ -2061,17 +1995,9 @@ frw_walk_kernel(WalkArgs A) {
                                     return q == 1 ? (uint32_t)n
                                                   : (q == 2 ? (uint32_t)sax : (q < KEY_HDR ? 0u : L.bz[q - KEY_HDR]));
                                 },
-                                hsh, &idx, r.x, &glo, &ghi, A.epoch, wait_idx);
+                                hsh, &idx, r.x, &glo, &ghi);
                         }
-                        if (res == LOOKUP_PARK && A.builders > 0 && idx != NO_INDEX) {
-                            // the table is being built in this launch: the
-                            // lane waits for it, then makes this transition
-                            // again
-                            wait_idx = idx;
-                            wait_me = true;
-                            --c_hops;
-                            --c_cls[I.cls];
-                        } else if (res != LOOKUP_HIT) {
+                        if (res != LOOKUP_HIT) {
                             if (res == LOOKUP_FULL) err |= ERR_TABLE_CAP;
                             park = true;
                             --c_hops;
@@ -2142,9 +2068,6 @@ frw_walk_kernel(WalkArgs A) {
                 gpw(SG.score_net)[k] = net;
                 gpw(SG.score_w)[k] = omega;
                 phase = PH_IDLE;
-            } else if (wait_me) {
-                phase = PH_WAIT;
-                wait_t0 = (uint32_t)wall_clock64();
             } else if (park) {
                 const uint32_t slot = atomicAdd(&K.park_count, 1u);
                 if (slot < A.park_cap) {
@@ -2246,9 +2169,6 @@ frw_walk_kernel(WalkArgs A) {
         if (c_halved) atomicAdd(&K.halved, c_halved);
         if (err) atomicOr(&K.err, err);
     }
-    // every key this wave queued is visible before the builders see it done
-    __threadfence();
-    if (lane == 0) atomicAdd(&K.walkers_done, 1u);
 }
 
 // -------------------------------------------------------------------------
@@ -2274,10 +2194,9 @@ struct BuildArgs {
     const Counters* ctr;
 };
 
-// Storage of one table build besides the per-source mode columns: the
-// sine basis, eigenvalues, plane coefficients, a matrix product buffer and
-// the CDF chunk sums (in LDS for the build kernel, in global scratch for a
-// build inside the walker).
+// Storage of one table build: the per-source mode columns (global work
+// space), and in LDS the sine basis, eigenvalues, plane coefficients, a
+// matrix product buffer and the CDF chunk sums.
 struct BuildSpace {
     double* zh;    // [src][r][m][l] mode columns, then [src][nb] exit rows (3 M^3 + 4 nb doubles)
     double* Sm;    // 31 x 31
@@ -2290,13 +2209,12 @@ struct BuildSpace {
     int* clast;    // TB_THREADS
     double* total;
     int* last;
-    double* thomas;  // groups of 64 threads: 2 x 32 doubles per thread (elimination coefficients)
 };
 
 // Exact SGF table idx of the cache, built by a group of NT threads (thread
 // tid) that call sync() between phases.  Every value is computed by one
-// thread in a fixed order and the CDF is cut into TB_THREADS chunks whatever
-// NT is, so the table is the same bit for bit for any group size.  The
+// thread in a fixed order and the CDF is cut into TB_THREADS chunks, so the
+// table does not depend on how the work is spread over the threads.  The
 // table's ready word receives ready_value.
 template <int NT, class Sync>
 __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const BuildSpace& W, Sync sync,
@@ -2337,16 +2255,8 @@ __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const
         src[1][lax] += 1;
         src[2][lax] -= 1;
     }
-    // tridiagonal solves, one (m, l) mode pair per thread; the elimination
-    // coefficients live in the thread's private memory in the build kernel
-    // and in global build space in the walker (whose registers stay free)
-    double th_local[NT == TB_THREADS ? 64 : 1];
-    double* cvals;
-    if constexpr (NT == TB_THREADS)
-        cvals = th_local;
-    else
-        cvals = W.thomas + (size_t)tid * 64;
-    double* dvals = cvals + 32;
+    // tridiagonal solves, one (m, l) mode pair per thread
+    double cvals[32], dvals[32];
     for (int sidx = 0; sidx < nsrc; ++sidx) {
         const int p0 = src[sidx][0], q0 = src[sidx][1], r0 = src[sidx][2];
         for (int ml = tid; ml < M2; ml += NT) {
@@ -2551,21 +2461,10 @@ __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const
     }
 }
 
-// doubles of global build space per table besides the mode columns: the
-// arrays BuildSpace keeps in LDS for the build kernel, and the elimination
-// coefficients of 64 threads
-constexpr size_t BUILD_SMALL = 31 * 31 * 2 + 32 + 33 * 3 + TB_THREADS * 2 + 4 + 64 * 64;
-
 __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
     if (B.dev_count && (B.ctr->dev_stop || blockIdx.x >= *B.dev_count)) return;
     const uint32_t idx = B.list[blockIdx.x];
-    if (B.dev_count) {
-        // the cache's queue itself: every thread has read the entry, which
-        // is then reset for the keys of the next launch
-        __syncthreads();
-        if (threadIdx.x == 0) B.cache.pending[blockIdx.x] = NO_INDEX;
-    }
-    if (idx >= B.cache.capacity) return;  // taken by a builder wave, or a key that found the cache full
+    if (idx >= B.cache.capacity) return;  // a queue entry of a full cache
     __shared__ double Sm[31 * 31];
     __shared__ double lam[32];
     __shared__ double cr[33], ar[33], br[33];
@@ -2586,80 +2485,7 @@ __global__ void __launch_bounds__(TB_THREADS) build_tables_kernel(BuildArgs B) {
     W.clast = clast;
     W.total = &total_sh;
     W.last = &last_sh;
-    W.thomas = nullptr;
     build_table_body<TB_THREADS>(B.cache, idx, (int)threadIdx.x, W, [] { __syncthreads(); }, 1u);
-}
-
-// Builder waves of a walker launch (its first `builders` blocks): they take
-// the keys that walker lanes queue (the cache's pending list, in order,
-// claimed through K->build_next), build each table in their own global
-// build space with all 64 lanes and mark it ready with the launch's epoch;
-// they stop once every walker wave has finished and the queue is empty.
-// Phases of a build are separated by agent-scope fences (the lanes exchange
-// data through global memory).  A consumed queue entry is reset to
-// NO_INDEX; an entry whose writer does not show up is left for the builds
-// between launches.
-__device__ void builder_wave(const CacheDev& C, Counters* K, uint32_t walker_blocks, double* space, uint32_t epoch,
-                             int lane) {
-    BuildSpace W;
-    W.Sm = space;
-    W.lam = W.Sm + 31 * 31;
-    W.cr = W.lam + 32;
-    W.ar = W.cr + 33;
-    W.br = W.ar + 33;
-    W.tmp = W.br + 33;
-    W.csum = W.tmp + 31 * 31;
-    W.clast = reinterpret_cast<int*>(W.csum + TB_THREADS);
-    W.total = W.csum + 2 * TB_THREADS;
-    W.last = reinterpret_cast<int*>(W.total + 2);
-    W.thomas = W.total + 4;
-    W.zh = space + BUILD_SMALL;
-    for (;;) {
-        uint32_t ci = NO_INDEX;
-        int stop = 0;
-        if (lane == 0) {
-            for (;;) {
-                const uint32_t np = __hip_atomic_load(C.n_pending, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t bn = __hip_atomic_load(&K->build_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (bn < np) {
-                    if (atomicCAS(&K->build_next, bn, bn + 1u) == bn) {
-                        ci = bn;
-                        break;
-                    }
-                    continue;
-                }
-                if (__hip_atomic_load(&K->walkers_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= walker_blocks) {
-                    // every key queued in this launch was queued before its
-                    // wave finished: one more look at the queue
-                    if (__hip_atomic_load(C.n_pending, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <= bn) {
-                        stop = 1;
-                        break;
-                    }
-                    continue;
-                }
-                __builtin_amdgcn_s_sleep(8);
-            }
-        }
-        stop = __shfl(stop, 0);
-        if (stop) return;
-        ci = __shfl(ci, 0);
-        uint32_t idx = NO_INDEX;
-        if (lane == 0) {
-            // the lane that took slot ci writes it right after taking it
-            for (int it = 0; it < (1 << 20); ++it) {
-                idx = __hip_atomic_load(C.pending + ci, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (idx != NO_INDEX) break;
-                __builtin_amdgcn_s_sleep(1);
-            }
-            if (idx != NO_INDEX)
-                __hip_atomic_store(C.pending + ci, NO_INDEX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        idx = __shfl(idx, 0);
-        if (idx >= C.capacity) continue;
-        __threadfence();
-        build_table_body<64>(C, idx, lane, W, [] { __threadfence(); }, epoch);
-        if (lane == 0) atomicAdd(&K->walker_builds, 1u);
-    }
 }
 
 // -------------------------------------------------------------------------
@@ -2672,10 +2498,6 @@ __device__ __forceinline__ void prep_resume(Counters& K, uint32_t park_cap, unsi
     K.resume_side ^= 1u;
     K.park_count = 0u;
     K.resume_next = 0ull;
-    // the build queue was emptied before this kernel: its builder waves
-    // start from entry 0
-    K.build_next = 0u;
-    K.walkers_done = 0u;
 }
 
 __global__ void resume_prep_kernel(Counters* K, uint32_t park_cap, unsigned long long total) {
@@ -2700,8 +2522,7 @@ __global__ void device_round_prep_kernel(Counters* K, CacheDev C, uint32_t build
         return;
     }
     *C.n_pending = 0u;
-    // entries taken by the last launch's builder waves are counted there
-    K->tables_built += np > K->build_next ? np - K->build_next : 0u;
+    K->tables_built += np;
     K->need_first = K->first_missing;
     K->first_missing = 0u;
     prep_resume(*K, park_cap, total);
@@ -2989,13 +2810,14 @@ __global__ void finish_multi_kernel(const RedSeg* __restrict__ segs) {
     }
 }
 
-// Binary64 sums of a launch's block partials, in walk order, and the
-// stopping rule of Alg. 1 (walk until the estimate of C_mm is accurate
-// enough).  acc[2*K]: running sums (S1, S2) per net over the walks before
-// the launch; every block's partial is added to them one block at a time
-// in walk order, so the sums do not depend on how the walks were split into
-// launches.  Checkpoints fall every `per_ck` blocks of the launch (launches
-// start on a checkpoint); the first checkpoint where 3 SE(C_mm) / |C_mm| <=
+// Binary64 sums of a launch's block partials and the stopping rule of
+// Alg. 1 (walk until the estimate of C_mm is accurate enough).  The blocks
+// of 4096 walks form groups of SUM_GROUP; a group's partials are added in
+// block order from zero, and the group sums are added in order to acc[2*K],
+// the running sums (S1, S2) per net of the walks before the launch.
+// Launches start on a group boundary, so the sums do not depend on how the
+// walks were split into launches.  Checkpoints fall every `per_ck` blocks
+// (a multiple of SUM_GROUP); the first one where 3 SE(C_mm) / |C_mm| <=
 // target ends the extraction, and the blocks after it are not added.
 struct Choice {
     int32_t blocks;  // blocks added (-1: the gate was closed, nothing added)
@@ -3003,7 +2825,8 @@ struct Choice {
     unsigned long long walks;
 };
 
-constexpr int DECIDE_MAX_BLOCKS = 4096;  // master partials staged in LDS
+constexpr int SUM_GROUP = 16;            // blocks per group (65536 walks)
+constexpr int DECIDE_MAX_GROUPS = 4096;  // groups per launch (group sums in LDS)
 
 __device__ __forceinline__ void mean_se(double s1, double s2, double n, double* m, double* se) {
     const double mm = s1 / n;
@@ -3012,23 +2835,38 @@ __device__ __forceinline__ void mean_se(double s1, double s2, double n, double* 
     *se = sqrt(var > 0.0 ? var : 0.0);
 }
 
-// A net's partials of blocks [0, blocks) staged in LDS by one wave (the
-// first DECIDE_MAX_BLOCKS of them; later ones are read in place).
-__device__ __forceinline__ void stage_column(const float4* __restrict__ partial, int blocks, int K, int j,
-                                             float4* col) {
-    const int nb = min(blocks, DECIDE_MAX_BLOCKS);
-#pragma unroll 4
-    for (int b = (int)threadIdx.x; b < nb; b += 64) col[b] = partial[(size_t)b * K + j];
+// Group sums of net j over blocks [0, blocks): one lane per group, each
+// group's partials loaded at once and added in block order.
+__device__ __forceinline__ void group_sums(const float4* __restrict__ partial, int blocks, int K, int j, double* g1,
+                                           double* g2) {
+    const int ng = (blocks + SUM_GROUP - 1) / SUM_GROUP;
+    for (int g = (int)threadIdx.x; g < ng; g += 64) {
+        const int b0 = g * SUM_GROUP;
+        float4 p[SUM_GROUP];
+#pragma unroll
+        for (int u = 0; u < SUM_GROUP; ++u)
+            p[u] = b0 + u < blocks ? partial[(size_t)(b0 + u) * K + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+        for (int u = 0; u < SUM_GROUP; ++u) {
+            if (b0 + u < blocks) {
+                a1 += (double)p[u].x + (double)p[u].y;
+                a2 += (double)p[u].z + (double)p[u].w;
+            }
+        }
+        g1[g] = a1;
+        g2[g] = a2;
+    }
     __syncthreads();
 }
 
-// One wave: the master's partials go to LDS, then lane 0 adds them in order
-// and tests each checkpoint.  target <= 0: every block is added.
+// One wave: the master's group sums, then lane 0 adds them in order and
+// tests each checkpoint.  target <= 0: every block is added.
 __global__ void __launch_bounds__(64) decide_kernel(const float4* __restrict__ partial, int blocks, int K, int master,
                                                     int per_ck, const double* __restrict__ acc, double n_before,
                                                     unsigned long long count, double target, const Counters* gate,
                                                     unsigned long long gate_total, Choice* out) {
-    __shared__ float4 pm[DECIDE_MAX_BLOCKS];
+    __shared__ double g1[DECIDE_MAX_GROUPS], g2[DECIDE_MAX_GROUPS];
     if (gate_closed(gate, gate_total)) {
         if (threadIdx.x == 0) {
             out->blocks = -1;
@@ -3039,48 +2877,26 @@ __global__ void __launch_bounds__(64) decide_kernel(const float4* __restrict__ p
     }
     int chosen = blocks, met = 0;
     if (target > 0.0) {
-        stage_column(partial, blocks, K, master, pm);
+        group_sums(partial, blocks, K, master, g1, g2);
         if (threadIdx.x != 0) return;
+        const int ng = (blocks + SUM_GROUP - 1) / SUM_GROUP, ck_groups = per_ck / SUM_GROUP;
         double s1 = acc[master], s2 = acc[K + master];
-        int to_ck = per_ck;
-        for (int b0 = 0; b0 < blocks && !met; b0 += 8) {
-            // eight partials loaded ahead (registers), added one at a time
-            float4 p0, p1, p2, p3, p4, p5, p6, p7;
-            auto ld = [&](int b) {
-                return b >= blocks ? make_float4(0.f, 0.f, 0.f, 0.f)
-                                   : (b < DECIDE_MAX_BLOCKS ? pm[b] : partial[(size_t)b * K + master]);
-            };
-            p0 = ld(b0);
-            p1 = ld(b0 + 1);
-            p2 = ld(b0 + 2);
-            p3 = ld(b0 + 3);
-            p4 = ld(b0 + 4);
-            p5 = ld(b0 + 5);
-            p6 = ld(b0 + 6);
-            p7 = ld(b0 + 7);
-            auto add = [&](const float4& p, int b) {
-                if (met || b >= blocks) return;
-                s1 += (double)p.x + (double)p.y;
-                s2 += (double)p.z + (double)p.w;
-                if (--to_ck == 0 || b + 1 == blocks) {
-                    to_ck = per_ck;
-                    const unsigned long long w = min((unsigned long long)(b + 1) * RED_CHUNK, count);
-                    double m, se;
-                    mean_se(s1, s2, n_before + (double)w, &m, &se);
-                    if (m != 0.0 && 3.0 * se / fabs(m) <= target) {
-                        chosen = b + 1;
-                        met = 1;
-                    }
+        int to_ck = ck_groups;
+        for (int g = 0; g < ng; ++g) {
+            s1 += g1[g];
+            s2 += g2[g];
+            if (--to_ck == 0 || g + 1 == ng) {
+                to_ck = ck_groups;
+                const int nb = min((g + 1) * SUM_GROUP, blocks);
+                const unsigned long long w = min((unsigned long long)nb * RED_CHUNK, count);
+                double m, se;
+                mean_se(s1, s2, n_before + (double)w, &m, &se);
+                if (m != 0.0 && 3.0 * se / fabs(m) <= target) {
+                    chosen = nb;
+                    met = 1;
+                    break;
                 }
-            };
-            add(p0, b0);
-            add(p1, b0 + 1);
-            add(p2, b0 + 2);
-            add(p3, b0 + 3);
-            add(p4, b0 + 4);
-            add(p5, b0 + 5);
-            add(p6, b0 + 6);
-            add(p7, b0 + 7);
+            }
         }
     } else if (threadIdx.x != 0) {
         return;
@@ -3090,38 +2906,21 @@ __global__ void __launch_bounds__(64) decide_kernel(const float4* __restrict__ p
     out->walks = min((unsigned long long)chosen * RED_CHUNK, count);
 }
 
-// One wave per net: the chosen blocks' partials staged in LDS, added in
-// order by lane 0, then the row entry and its standard error.
+// One wave per net: the group sums of the chosen blocks added in order by
+// lane 0, then the row entry and its standard error.
 __global__ void __launch_bounds__(64) finish_seq_kernel(const float4* __restrict__ partial, int K, double* acc,
                                                         double n_before, const Choice* choice, double* result) {
-    __shared__ float4 col[DECIDE_MAX_BLOCKS];
+    __shared__ double g1[DECIDE_MAX_GROUPS], g2[DECIDE_MAX_GROUPS];
     const int j = blockIdx.x;
     const int nb = choice->blocks;
     if (nb < 0) return;
-    stage_column(partial, nb, K, j, col);
+    group_sums(partial, nb, K, j, g1, g2);
     if (threadIdx.x != 0) return;
+    const int ng = (nb + SUM_GROUP - 1) / SUM_GROUP;
     double s1 = acc[j], s2 = acc[K + j];
-    for (int b0 = 0; b0 < nb; b0 += 8) {
-        // eight partials loaded ahead (registers), added one at a time
-        auto ld = [&](int b) {
-            return b >= nb ? make_float4(0.f, 0.f, 0.f, 0.f)
-                           : (b < DECIDE_MAX_BLOCKS ? col[b] : partial[(size_t)b * K + j]);
-        };
-        const float4 p0 = ld(b0), p1 = ld(b0 + 1), p2 = ld(b0 + 2), p3 = ld(b0 + 3), p4 = ld(b0 + 4),
-                     p5 = ld(b0 + 5), p6 = ld(b0 + 6), p7 = ld(b0 + 7);
-        auto add = [&](const float4& p, int b) {
-            if (b >= nb) return;
-            s1 += (double)p.x + (double)p.y;
-            s2 += (double)p.z + (double)p.w;
-        };
-        add(p0, b0);
-        add(p1, b0 + 1);
-        add(p2, b0 + 2);
-        add(p3, b0 + 3);
-        add(p4, b0 + 4);
-        add(p5, b0 + 5);
-        add(p6, b0 + 6);
-        add(p7, b0 + 7);
+    for (int g = 0; g < ng; ++g) {
+        s1 += g1[g];
+        s2 += g2[g];
     }
     acc[j] = s1;
     acc[K + j] = s2;
@@ -3256,14 +3055,6 @@ struct Cache {
     std::mutex mu;
     uint32_t uniform_index = NO_INDEX;  // valid until the cache is emptied
     uint64_t flushes = 0;               // times the full cache was emptied
-    // walker launches number their in-launch table builds 2, 3, ... (ready
-    // words of tables built elsewhere are 1)
-    std::atomic<uint32_t> epoch{1};
-    uint32_t next_epoch() {
-        uint32_t e = ++epoch;
-        while (e < 2) e = ++epoch;
-        return e;
-    }
     // Empties the cache (with its lock held and no FRW work in flight).
     void clear() {
         MW_HIP(hipMemset(d.slot, 0, 8ull * ((size_t)d.slot_mask + 1)));
@@ -3645,8 +3436,7 @@ LaunchGeom launch_geom(int n) {
 // queued tables one such round builds.
 constexpr int DEVICE_ROUNDS = 2;
 constexpr uint32_t DEV_BUILD_MAX = 128;
-// builder waves per walker launch (tables built during the launch)
-constexpr uint32_t WALKER_BUILDERS = 8;
+
 
 struct Runner {
     int n, hybrid;
@@ -3666,16 +3456,10 @@ struct Runner {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
     size_t ev_used = 0;
     uint64_t misses = 0, launches = 0;
-    uint32_t built_seen = 0;   // device-round table builds already counted in misses
-    uint32_t wbuilt_seen = 0;  // walker table builds already counted
-    uint64_t walker_builds = 0;
+    uint32_t built_seen = 0;  // device-round table builds already counted in misses
     double walker_ms = 0.0;
     double* dev_work = nullptr;  // workspace of the device-round table builds
-    // builder waves of each walker launch and their build spaces (none:
-    // MWALK_WALKER_BUILDS=0)
-    double* wb_space = nullptr;
-    uint32_t wb_builders = 0;
-    unsigned long long wb_stride = 0;
+
     // stream of this runner's launches and copies (nullptr: the legacy
     // default stream); table builds and cache flushes always run on the
     // default stream with the device otherwise idle
@@ -3702,7 +3486,6 @@ struct Runner {
             o += (b + 255) / 256 * 256;
             return r;
         };
-        wb_builders = env_size("MWALK_WALKER_BUILDS", 1) ? WALKER_BUILDERS : 0u;
         // counters and segment list adjacent: one copy sets both per run
         const size_t o_ctr = sz(sizeof(Counters)), o_sg = sz(sizeof(Segment) * (size_t)seg_cap), o_st = sz(16);
         const size_t o_p0 = sz(sizeof(Parked) * (size_t)park_cap), o_p1 = sz(sizeof(Parked) * (size_t)park_cap);
@@ -3729,7 +3512,6 @@ struct Runner {
             (void)hipEventDestroy(e.second);
         }
         dev_free(dev_work);
-        dev_free(wb_space);
         dev_free(mem);
     }
 
@@ -3769,7 +3551,6 @@ struct Runner {
             MW_HIP(hipGetLastError());
         }
         MW_HIP(hipDeviceSynchronize());
-        MW_HIP(hipMemset(cache->d.pending, 0xff, 4ull * npend));  // entries read: NO_INDEX again
         MW_HIP(hipMemset(cache->d.n_pending, 0, 4));
         misses += valid.size();
         return valid.size();
@@ -3868,7 +3649,7 @@ struct Runner {
         memcpy(staging.data() + off, segs.data(), sizeof(Segment) * segs.size());
         MW_HIP(hipMemcpyAsync(ctr, staging.data(), staging.size(), hipMemcpyHostToDevice, stream));
         MW_HIP(hipStreamSynchronize(stream));  // the staging buffer goes out of scope
-        built_seen = wbuilt_seen = 0;          // the counters restart at zero
+        built_seen = 0;                        // the counters restart at zero
         return total;
     }
 
@@ -3884,9 +3665,7 @@ struct Runner {
         ev_used = 0;
         misses += h.tables_built - built_seen;
         built_seen = h.tables_built;
-        misses += h.walker_builds - wbuilt_seen;
-        walker_builds += h.walker_builds - wbuilt_seen;
-        wbuilt_seen = h.walker_builds;
+
         return h;
     }
 
@@ -3929,15 +3708,6 @@ struct Runner {
         W.park[0] = park[0];
         W.park[1] = park[1];
         W.park_cap = park_cap;
-        if (wb_builders && !wb_space) {
-            const uint32_t M = n - 1;
-            wb_stride = (BUILD_SMALL + (unsigned long long)3 * M * M * M + 4ull * 6 * M * M + 31) / 32 * 32;
-            wb_space = (double*)dev_alloc(sizeof(double) * wb_stride * wb_builders);
-        }
-        W.builders = wb_builders;
-        W.epoch = cache->next_epoch();
-        W.build_space = wb_space;
-        W.build_stride = wb_stride;
         W.ctr = ctr;
         W.lane_stride = g.lane_stride;
         W.uniform_index = uniform_index;
@@ -3946,8 +3716,6 @@ struct Runner {
         // one-wave blocks: the grid sets the resident waves per CU
         const int blocks = waves_per_cu > 0 ? std::min(g.blocks, g.cus * waves_per_cu) : g.blocks;
         const int blocks_e = waves_per_cu > 0 ? std::min(g.blocks_e, g.cus * waves_per_cu) : g.blocks_e;
-        // the builder waves are part of the grid (none in MicroWalk-E launches)
-        W.builders = expand_m > 0 ? 0u : std::min<uint32_t>(W.builders, (uint32_t)(blocks / 8));
         if (ev_used == evs.size()) {
             hipEvent_t a = nullptr, b = nullptr;
             MW_HIP(hipEventCreate(&a));
@@ -4146,7 +3914,8 @@ constexpr size_t GAUSS_MAX_PATCHES = 1 << 22;
 // frw_extract: walks between two checks of the stopping rule (default), most
 // walks per launch, and the first launch of an extraction with no size hint
 constexpr uint64_t FRW_CHECKPOINT = 1u << 16;
-constexpr uint64_t FRW_LAUNCH_CAP = 1u << 22;
+constexpr uint64_t FRW_LAUNCH_CAP = 1ull << 26;         // fixed budget
+constexpr uint64_t FRW_TARGET_LAUNCH_CAP = 1ull << 23;  // with a target (buffers sized for it)
 constexpr uint64_t FRW_FIRST_LAUNCH = 1u << 20;
 
 struct GaussHost {
@@ -4689,15 +4458,18 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         const int n = opt.n_cells;
         const bool target_mode = opt.target_rel_3sigma > 0;
         // the stopping rule's checkpoints: every ck walks, a whole number of
-        // reduction blocks; a launch walks a whole number of checkpoints (or
-        // reduction blocks without a target) and the binary64 sums run in
-        // walk order, so the result does not depend on the launch sizes
-        uint64_t ck = RED_CHUNK;
+        // 65536-walk groups of the binary64 sums; a launch walks a whole
+        // number of checkpoints (or groups without a target), so the result
+        // does not depend on the launch sizes
+        const uint64_t group = (uint64_t)SUM_GROUP * RED_CHUNK;
+        uint64_t ck = group;
         if (target_mode) {
             ck = opt.batch_walks ? opt.batch_walks : FRW_CHECKPOINT;
-            ck = (ck + RED_CHUNK - 1) / RED_CHUNK * RED_CHUNK;
+            ck = (ck + group - 1) / group * group;
+            MW_REQUIRE(ck <= ((uint64_t)DECIDE_MAX_GROUPS * group) / 2, MW_EINVAL, "batch_walks above 2^27");
         }
-        const uint64_t launch_cap = std::min<uint64_t>(walk_budget, std::max<uint64_t>(ck, FRW_LAUNCH_CAP / ck * ck));
+        const uint64_t cap_mode = target_mode ? FRW_TARGET_LAUNCH_CAP : FRW_LAUNCH_CAP;
+        const uint64_t launch_cap = std::min<uint64_t>(walk_budget, std::max<uint64_t>(ck, cap_mode / ck * ck));
         // first launch: the walks the last extraction of this structure,
         // master and rule needed, plus 6 % (at least one checkpoint) for the
         // spread between seeds (performance only)
@@ -4749,7 +4521,6 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
             stats->walks = X.done;
             stats->walks_launched = X.launched;
             stats->cache_miss = R.misses;
-            stats->tables_built_in_launch = R.walker_builds;
             stats->launches = R.launches;
             stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
             stats->walker_seconds = R.walker_ms * 1e-3;
