@@ -308,7 +308,8 @@ typedef struct {
     uint64_t launches;        /* walker-kernel launches                      */
     double seconds;           /* wall time of the call                      */
     double walker_seconds;    /* summed duration of the walker-kernel launches
-                                 (HIP events on the launch stream)          */
+                                 (HIP events on the launch stream, also
+                                 inside a replayed launch graph)            */
     double gauss_g;           /* frw_extract: growth g of the master's
                                  Gaussian surface (um); 0 for the matrix    */
     double gauss_area;        /* frw_extract: its area (um^2); 0 for the
@@ -348,6 +349,12 @@ typedef struct {
  * score_net/score_w (device, walk_budget entries each, or NULL): per-walk net
  * index (n_nets for env) and fp32 weight, indexed by walk - first_walk;
  * entries from stats->walks on are unspecified.
+ * The structure keeps the call's device buffers (per master and options, at
+ * most four sets, each sized for the largest launch: 2^23 walks with a
+ * target, up to 2^26 without) for later calls, with HIP graphs of the usual
+ * launch that later calls replay (set MWALK_FRW_GRAPHS=0 for eager
+ * launches; results are the same); mw_structure_destroy frees them.  Calls
+ * on one structure from several threads are safe.
  * stats may be NULL.  Synchronous: returns after the result is on the host.
  * Transition cubes are the largest conductor-free cubes, halved while they
  * touch more than MW_MAX_REGIONS dielectric boxes; MW_ELIMIT if more than

@@ -3129,6 +3129,11 @@ Cache& get_cache(int n) {
 
 using namespace mw;
 
+namespace {
+struct ExtractCtx;
+void delete_ctx(ExtractCtx* c);
+}  // namespace
+
 struct mw_structure {
     int device = 0;
     size_t bytes = 0;  // device memory held (arrays, grid index)
@@ -3150,6 +3155,11 @@ struct mw_structure {
         std::lock_guard<std::mutex> g(hint_mu);
         hints[{master, ck, target}] = walks;
     }
+    // frw_extract's buffers and launch graphs kept between calls, one per
+    // (master, options) in use; guarded by ctx_mu
+    std::mutex ctx_mu;
+    std::vector<ExtractCtx*> ctxs;
+    uint64_t ctx_clock = 0;
 };
 
 static void validate_desc(const mw_structure_desc* D) {
@@ -3386,6 +3396,8 @@ extern "C" mw_status mw_structure_destroy(mw_structure* s) {
     return guarded([&] {
         if (!s) return;
         (void)hipDeviceSynchronize();
+        for (ExtractCtx* c : s->ctxs) delete_ctx(c);
+        s->ctxs.clear();
         dev_free((void*)s->h.gc_list);
         dev_free(s->mem);
         delete s;
@@ -3434,7 +3446,7 @@ LaunchGeom launch_geom(int n) {
 // Device-driven rounds enqueued after a run's first walker launch (table
 // builds and resumes without a host decision in between), and the most
 // queued tables one such round builds.
-constexpr int DEVICE_ROUNDS = 2;
+constexpr int DEVICE_ROUNDS = 3;
 constexpr uint32_t DEV_BUILD_MAX = 128;
 
 
@@ -3453,6 +3465,7 @@ struct Runner {
     Parked* park[2];
     Segment* dsegs;
     // HIP event pairs around the walker launches not yet counted in walker_ms
+    // (recorded as external events, so that a captured graph records them)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
     size_t ev_used = 0;
     uint64_t misses = 0, launches = 0;
@@ -3653,16 +3666,51 @@ struct Runner {
         return total;
     }
 
-    Counters read_counters() {
-        Counters h{};
-        MW_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, stream));
-        MW_HIP(hipStreamSynchronize(stream));
+    // The upload of a single-segment run (zeroed counters, then the segment)
+    // as host bytes, for a copy that a graph replays.
+    size_t staging_bytes(size_t nseg) const { return (size_t)((char*)dsegs - (char*)ctr) + sizeof(Segment) * nseg; }
+    void fill_staging(const Segment& sg, char* buf) const {
+        const size_t off = (char*)dsegs - (char*)ctr;
+        memset(buf, 0, off);
+        memcpy(buf + off, &sg, sizeof sg);
+    }
+
+    // start() of a single-segment run whose upload is already in pinned host
+    // memory: nothing waits, so the calls can be captured in a graph.
+    void start_from(const Segment& sg, const StructDev* s0, const char* pinned) {
+        cur_segs = {sg};
+        cur_single = true;
+        cur_s0 = *s0;
+        cur_total = sg.count;
+        MW_HIP(hipMemcpyAsync(ctr, pinned, staging_bytes(1), hipMemcpyHostToDevice, stream));
+        built_seen = 0;
+        launch_first(cur_segs, &cur_s0, cur_total, 0, nullptr);
+        launch_walker();
+        for (int r = 0; r < DEVICE_ROUNDS; ++r) device_round();
+    }
+
+    // Per-call statistics start from zero (a runner kept between calls).
+    void reset_stats() {
+        misses = launches = 0;
+        walker_ms = 0.0;
+        flushes = 0;
+    }
+
+    // Adds the durations of the walker launches recorded since the last look.
+    void account_events() {
         for (size_t i = 0; i < ev_used; ++i) {
             float ms = 0.f;
             MW_HIP(hipEventElapsedTime(&ms, evs[i].first, evs[i].second));
             walker_ms += ms;
         }
         ev_used = 0;
+    }
+
+    Counters read_counters() {
+        Counters h{};
+        MW_HIP(hipMemcpyAsync(&h, ctr, sizeof h, hipMemcpyDeviceToHost, stream));
+        MW_HIP(hipStreamSynchronize(stream));
+        account_events();
         misses += h.tables_built - built_seen;
         built_seen = h.tables_built;
 
@@ -3725,9 +3773,8 @@ struct Runner {
             }
             evs.push_back({a, b});
         }
-        hipEvent_t ev0 = evs[ev_used].first, ev1 = evs[ev_used].second;
-        ++ev_used;
-        MW_HIP(hipEventRecord(ev0, stream));
+        const std::pair<hipEvent_t, hipEvent_t> ev = evs[ev_used++];
+        MW_HIP(hipEventRecordWithFlags(ev.first, stream, hipEventRecordExternal));
         if (expand_m > 0) {
             W.lane_stride = g.lane_stride_e;
             W.expand_m = expand_m;
@@ -3751,17 +3798,23 @@ struct Runner {
                 frw_walk_kernel<false, false><<<blocks, WALK_THREADS, g.lds, stream>>>(W);
         }
         MW_HIP(hipGetLastError());
-        MW_HIP(hipEventRecord(ev1, stream));
+        MW_HIP(hipEventRecordWithFlags(ev.second, stream, hipEventRecordExternal));
         ++launches;
     }
 
     // One device-driven round, enqueued without waiting: build the queued
     // tables, redo first transitions that missed one, resume the parked
     // walks.  A round with nothing to do costs a few empty launches.
-    void device_round() {
+    size_t dev_work_stride() const {
         const uint32_t M = n - 1;
-        const size_t stride = (size_t)3 * M * M * M + (size_t)4 * 6 * M * M + 64;
-        if (!dev_work) dev_work = (double*)dev_alloc(sizeof(double) * stride * DEV_BUILD_MAX);
+        return (size_t)3 * M * M * M + (size_t)4 * 6 * M * M + 64;
+    }
+    void prepare_device_rounds() {
+        if (!dev_work) dev_work = (double*)dev_alloc(sizeof(double) * dev_work_stride() * DEV_BUILD_MAX);
+    }
+    void device_round() {
+        const size_t stride = dev_work_stride();
+        prepare_device_rounds();
         BuildArgs Ba{cache->d, cache->d.pending, 0u, dev_work, stride, cache->d.n_pending, ctr};
         build_tables_kernel<<<DEV_BUILD_MAX, TB_THREADS, 0, stream>>>(Ba);
         device_round_prep_kernel<<<1, 1, 0, stream>>>(ctr, cache->d, DEV_BUILD_MAX, park_cap, cur_total);
@@ -4222,49 +4275,271 @@ struct Extraction {
         return s;
     }
 
-    // One launch of walks [done, done + sg.count) (done is a checkpoint)
-    // with a single wait in the usual case: the walks, then the reduction,
-    // the stopping rule and the binary64 sums, all gated on the walker's
-    // counters, and one copy of the row and the choice.  When a walk parked
-    // or a first transition missed its table the gate drops all three; the
-    // launch's walks are then completed and the same kernels run ungated.
-    // Returns the walker counters; *met tells whether the target was met.
-    Counters run_launch(Runner& R, const Segment& sg, int per_ck, double target, bool* met) {
+    // bytes of a launch's result copy: the row and its standard errors, then
+    // the choice of the stopping rule
+    size_t out_bytes() const { return sizeof(double) * 2 * K + sizeof(Choice); }
+
+    // The reduction, the stopping rule and the binary64 sums of a launch's
+    // scores (gated on the walker's counters, or not when gate is null), and
+    // the copy of the result to out (host).  Nothing waits.
+    void enqueue_tail(Runner& R, const Segment& sg, int per_ck, double target, const Counters* gate, char* out) {
         const int rb = (int)((sg.count + RED_CHUNK - 1) / RED_CHUNK);
-        const size_t out_bytes = sizeof(double) * 2 * K + sizeof(Choice);
-        std::vector<char> out(out_bytes);
-        auto tail = [&](const Counters* gate) {
-            reduce_scores_kernel<<<rb, RED_THREADS, 0, R.stream>>>(sg.score_net, sg.score_w, sg.count, K, partial,
-                                                                    gate, sg.count);
-            decide_kernel<<<1, 64, 0, R.stream>>>(partial, rb, K, master, per_ck, acc, (double)done, sg.count, target,
-                                                  gate, sg.count, choice);
-            finish_seq_kernel<<<K, 64, 0, R.stream>>>(partial, K, acc, (double)done, choice, result);
-            MW_HIP(hipGetLastError());
-            MW_HIP(hipMemcpyAsync(out.data(), result, out_bytes, hipMemcpyDeviceToHost, R.stream));
-        };
-        R.start({sg}, &hS);
-        tail(R.ctr);
-        Counters h = R.read_counters();  // waits for the stream
+        reduce_scores_kernel<<<rb, RED_THREADS, 0, R.stream>>>(sg.score_net, sg.score_w, sg.count, K, partial, gate,
+                                                                sg.count);
+        decide_kernel<<<1, 64, 0, R.stream>>>(partial, rb, K, master, per_ck, acc, (double)done, sg.count, target,
+                                              gate, sg.count, choice);
+        finish_seq_kernel<<<K, 64, 0, R.stream>>>(partial, K, acc, (double)done, choice, result);
+        MW_HIP(hipGetLastError());
+        MW_HIP(hipMemcpyAsync(out, result, out_bytes(), hipMemcpyDeviceToHost, R.stream));
+    }
+
+    // After the gated tail of a launch has run (counters h, result copy in
+    // out): when the gate was closed the launch's walks are completed and the
+    // tail runs again ungated; then the sums move on.
+    Counters complete(Runner& R, const Segment& sg, int per_ck, double target, Counters h, char* out, bool* met) {
         Choice c;
-        memcpy(&c, out.data() + sizeof(double) * 2 * K, sizeof c);
+        memcpy(&c, out + sizeof(double) * 2 * K, sizeof c);
         if (c.blocks < 0) {
             h = R.finish_from(h);
-            tail(nullptr);
+            enqueue_tail(R, sg, per_ck, target, nullptr, out);
             MW_HIP(hipStreamSynchronize(R.stream));
-            memcpy(&c, out.data() + sizeof(double) * 2 * K, sizeof c);
+            memcpy(&c, out + sizeof(double) * 2 * K, sizeof c);
         } else {
             R.check_errors(h);
         }
         MW_REQUIRE(c.blocks >= 0 && c.walks <= sg.count, MW_EDEVICE, "stopping rule returned no choice");
         done += c.walks;
         launched += sg.count;
-        memcpy(res.data(), out.data(), sizeof(double) * 2 * K);
+        memcpy(res.data(), out, sizeof(double) * 2 * K);
         *met = c.met != 0;
         return h;
     }
 
+    // One launch of walks [done, done + sg.count) (done is a checkpoint)
+    // with a single wait in the usual case: the walks, then the gated
+    // reduction, stopping rule and binary64 sums, and one copy of the row and
+    // the choice.  Returns the walker counters; *met tells whether the
+    // target was met.
+    Counters run_launch(Runner& R, const Segment& sg, int per_ck, double target, bool* met) {
+        std::vector<char> out(out_bytes());
+        R.start({sg}, &hS);
+        enqueue_tail(R, sg, per_ck, target, R.ctr, out.data());
+        const Counters h = R.read_counters();  // waits for the stream
+        return complete(R, sg, per_ck, target, h, out.data(), met);
+    }
+
+    // A kept extraction starts again from zero walks.
+    void reset(hipStream_t stream) {
+        done = launched = 0;
+        res.assign(2 * K, 0.0);
+        MW_HIP(hipMemsetAsync(acc, 0, sizeof(double) * 2 * K, stream));
+    }
+
     bool converged(double target) const {
         return target > 0 && res[master] != 0.0 && 3.0 * res[K + master] / std::fabs(res[master]) <= target;
+    }
+};
+
+// frw_extract's buffers kept with the structure between calls: the
+// extraction's device arrays, the runner's queues and events, a stream of
+// their own, and HIP graphs of the usual launch (upload, first transitions,
+// walker, device-driven rounds, gated reduction, stopping rule, sums and the
+// copies back), replayed when a call's launch has the same shape.  Replays
+// run the same kernels with the same arguments as the eager launch, so
+// results do not depend on which ran.  A graph holds no memset node.
+struct ExtractCtx {
+    // what the buffers depend on
+    int master = 0, n = 0, hybrid = 0, expand_m = 0, plain = 0;
+    double abs_tol_rel = 0.0, gauss_is = 0.0;
+    uint64_t chunk = 0;
+    bool own_scores = true;
+    bool busy = false;
+    uint64_t last_use = 0;
+    std::unique_ptr<Extraction> X;
+    std::unique_ptr<Runner> R;
+    hipStream_t stream = nullptr;
+    char* host_in = nullptr;   // pinned: the upload of a launch
+    char* host_out = nullptr;  // pinned: the result copy, then the counters
+    bool graphs_ok = true;
+    struct Graph {
+        uint64_t done, count;
+        int per_ck;
+        double target;
+        uint32_t uniform_index;
+        int waves_per_cu;
+        hipGraphExec_t exec;
+        uint64_t launches;
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> events;  // around its walker launches
+    };
+    std::vector<Graph> graphs;
+
+    ~ExtractCtx() {
+        for (Graph& g : graphs) {
+            (void)hipGraphExecDestroy(g.exec);
+            destroy_events(g.events);
+        }
+        if (host_in) (void)hipHostFree(host_in);
+        if (host_out) (void)hipHostFree(host_out);
+        R.reset();
+        X.reset();
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+
+    static void destroy_events(std::vector<std::pair<hipEvent_t, hipEvent_t>>& ev) {
+        for (auto& e : ev) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        ev.clear();
+    }
+
+    size_t out_counters_offset() const { return (X->out_bytes() + 255) / 256 * 256; }
+
+    // A graph of the launch of sg, captured on first use of its shape.
+    Graph* graph_for(const Segment& sg, int per_ck, double target) {
+        for (Graph& g : graphs)
+            if (g.done == X->done && g.count == sg.count && g.per_ck == per_ck && g.target == target &&
+                g.uniform_index == R->uniform_index && g.waves_per_cu == R->waves_per_cu)
+                return &g;
+        if (graphs.size() >= 8) return nullptr;
+        Graph g{X->done, sg.count, per_ck, target, R->uniform_index, R->waves_per_cu, nullptr, 0, {}};
+        R->account_events();  // the pool's pairs are free again
+        const uint64_t l0 = R->launches;
+        hipGraph_t graph = nullptr;
+        R->prepare_device_rounds();  // no allocation inside the capture
+        MW_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
+        bool captured = true;
+        try {
+            R->start_from(sg, &X->hS, host_in);
+            X->enqueue_tail(*R, sg, per_ck, target, R->ctr, host_out);
+            MW_HIP(hipMemcpyAsync(host_out + out_counters_offset(), R->ctr, sizeof(Counters), hipMemcpyDeviceToHost,
+                                  stream));
+        } catch (...) {
+            captured = false;
+        }
+        const hipError_t ee = hipStreamEndCapture(stream, &graph);
+        g.launches = R->launches - l0;
+        // the event pairs recorded in the graph belong to it from now on
+        g.events.assign(R->evs.begin(), R->evs.begin() + R->ev_used);
+        R->evs.erase(R->evs.begin(), R->evs.begin() + R->ev_used);
+        R->ev_used = 0;
+        R->launches = l0;
+        hipGraphExec_t exec = nullptr;
+        if (captured && ee == hipSuccess && graph && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            g.exec = exec;
+            graphs.push_back(std::move(g));
+            return &graphs.back();
+        }
+        // capture not possible here: eager launches from now on
+        if (graph) (void)hipGraphDestroy(graph);
+        destroy_events(g.events);
+        (void)hipGetLastError();
+        graphs_ok = false;
+        return nullptr;
+    }
+
+    // One launch as Extraction::run_launch, replayed from a graph when the
+    // segment uses the extraction's own buffers.
+    Counters run_launch(const Segment& sg, int per_ck, double target, bool* met) {
+        if (!graphs_ok || !own_scores || !env_size("MWALK_FRW_GRAPHS", 1))
+            return X->run_launch(*R, sg, per_ck, target, met);
+        R->fill_staging(sg, host_in);
+        Graph* g = graph_for(sg, per_ck, target);
+        if (!g) return X->run_launch(*R, sg, per_ck, target, met);
+        MW_HIP(hipGraphLaunch(g->exec, stream));
+        MW_HIP(hipStreamSynchronize(stream));
+        R->launches += g->launches;
+        for (auto& e : g->events) {
+            float ms = 0.f;
+            MW_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+            R->walker_ms += ms;
+        }
+        // the runner's view of the run, as start() leaves it
+        R->cur_segs = {sg};
+        R->cur_single = true;
+        R->cur_s0 = X->hS;
+        R->cur_total = sg.count;
+        Counters h;
+        memcpy(&h, host_out + out_counters_offset(), sizeof h);
+        R->misses += h.tables_built;
+        R->built_seen = h.tables_built;
+        return X->complete(*R, sg, per_ck, target, h, host_out, met);
+    }
+};
+
+void delete_ctx(ExtractCtx* c) { delete c; }
+
+// The context of a call (created when no idle one matches; at most four
+// are kept per structure, the least recently used idle one making room).
+struct CtxLease {
+    mw_structure* st;
+    ExtractCtx* c = nullptr;
+    bool kept = true;
+    CtxLease(mw_structure* st_, int master, const frw_options& opt, int expand_m, uint64_t chunk, bool own)
+        : st(st_) {
+        {
+            std::lock_guard<std::mutex> g(st->ctx_mu);
+            for (ExtractCtx* x : st->ctxs)
+                if (!x->busy && x->master == master && x->n == opt.n_cells && x->hybrid == opt.hybrid &&
+                    x->expand_m == expand_m && x->plain == opt.plain && x->abs_tol_rel == opt.abs_tol_rel &&
+                    x->gauss_is == opt.gauss_is && x->chunk == chunk && x->own_scores == own) {
+                    c = x;
+                    break;
+                }
+            if (c) {
+                c->busy = true;
+                c->last_use = ++st->ctx_clock;
+                return;
+            }
+        }
+        auto x = std::make_unique<ExtractCtx>();
+        x->master = master;
+        x->n = opt.n_cells;
+        x->hybrid = opt.hybrid;
+        x->expand_m = expand_m;
+        x->plain = opt.plain;
+        x->abs_tol_rel = opt.abs_tol_rel;
+        x->gauss_is = opt.gauss_is;
+        x->chunk = chunk;
+        x->own_scores = own;
+        MW_HIP(hipStreamCreateWithFlags(&x->stream, hipStreamNonBlocking));
+        x->X = std::make_unique<Extraction>(*st, master, opt.abs_tol_rel, chunk, own);
+        x->R = std::make_unique<Runner>(opt.n_cells, opt.hybrid, chunk, 1);
+        x->R->stream = x->stream;
+        x->R->expand_m = expand_m;
+        x->R->plain = opt.plain;
+        MW_HIP(hipHostMalloc((void**)&x->host_in, x->R->staging_bytes(1), 0));
+        MW_HIP(hipHostMalloc((void**)&x->host_out, x->out_counters_offset() + sizeof(Counters), 0));
+        if (opt.gauss_is > 0) x->X->importance(*x->R, opt.gauss_is * x->X->gauss_g);
+        x->busy = true;
+        std::lock_guard<std::mutex> g(st->ctx_mu);
+        x->last_use = ++st->ctx_clock;
+        if (st->ctxs.size() >= 4) {
+            size_t victim = st->ctxs.size();
+            for (size_t i = 0; i < st->ctxs.size(); ++i)
+                if (!st->ctxs[i]->busy && (victim == st->ctxs.size() || st->ctxs[i]->last_use < st->ctxs[victim]->last_use))
+                    victim = i;
+            if (victim < st->ctxs.size()) {
+                delete st->ctxs[victim];
+                st->ctxs.erase(st->ctxs.begin() + victim);
+            }
+        }
+        if (st->ctxs.size() < 4)
+            st->ctxs.push_back(x.get());
+        else
+            kept = false;  // every kept context is in use: this one lives for the call
+        c = x.release();
+    }
+    ~CtxLease() {
+        if (!c) return;
+        if (!kept) {
+            delete c;
+            return;
+        }
+        std::lock_guard<std::mutex> g(st->ctx_mu);
+        c->busy = false;
     }
 };
 
@@ -4480,12 +4755,14 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
                         : std::max<uint64_t>(ck, FRW_FIRST_LAUNCH / ck * ck);
         }
         const bool own_scores = !(score_net && score_w);
-        Extraction X(*st, master, opt.abs_tol_rel, launch_cap, own_scores);
-        Runner R(n, opt.hybrid, launch_cap, 1);
-        R.expand_m = expand_m_of(opt);
-        R.plain = opt.plain;
+        // buffers kept with the structure for this master and these options
+        CtxLease lease(st, master, opt, expand_m_of(opt), launch_cap, own_scores);
+        ExtractCtx& ctx = *lease.c;
+        Extraction& X = *ctx.X;
+        Runner& R = *ctx.R;
+        X.reset(R.stream);
+        R.reset_stats();
         (void)frw_tuned_waves(n, R.expand_m, &R.waves_per_cu);
-        if (opt.gauss_is > 0) X.importance(R, opt.gauss_is * X.gauss_g);
         frw_stats acc{};
         bool met = false;
         while (X.done < walk_budget && !met) {
@@ -4496,7 +4773,7 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
                 std::lock_guard<std::mutex> lock(R.cache->mu);
                 R.flushes = 0;
                 R.ensure_uniform_table();
-                add_counters(acc, X.run_launch(R, sgm, (int)(ck / RED_CHUNK), opt.target_rel_3sigma, &met));
+                add_counters(acc, ctx.run_launch(sgm, (int)(ck / RED_CHUNK), opt.target_rel_3sigma, &met));
             }
             if (!met && target_mode) {
                 // the walks still needed, predicted from the estimate so far

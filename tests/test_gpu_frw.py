@@ -215,6 +215,34 @@ def test_scores_independent_of_cache_state_and_resume(mw):
     assert torch.equal(torch.cat([c1["w"], c2["w"]]), a["w"])
 
 
+@pytest.mark.parametrize("target", [0.0, 0.02])
+def test_graph_replays_equal_eager(mw, monkeypatch, target):
+    """A structure keeps frw_extract's buffers between calls, and the usual
+    launch is captured in a HIP graph on first use and replayed afterwards:
+    replay after replay, with eager work of other extractions between them,
+    the rows equal those of eager launches (MWALK_FRW_GRAPHS=0) bit for
+    bit."""
+    st = W.c2_structure()
+    h = mw.StructureHandle(st)
+    kw = dict(target_rel_3sigma=target, batch_walks=65536) if target else {}
+    for k in range(4):
+        g = mw.frw_extract(h, 0, 400000, seed=70 + k, **kw)
+        monkeypatch.setenv("MWALK_FRW_GRAPHS", "0")
+        e = mw.frw_extract(h, 0, 400000, seed=70 + k, **kw)
+        monkeypatch.delenv("MWALK_FRW_GRAPHS")
+        mw.frw_extract(h, 1, 100000, seed=5)  # other work between the replays
+        print(k, g["stats"]["walks"], g["stats"]["launches"], g["stats"]["walker_seconds"],
+              e["stats"]["walker_seconds"])
+        assert np.array_equal(g["row"], e["row"]) and np.array_equal(g["se"], e["se"])
+        assert g["stats"]["walks"] == e["stats"]["walks"]
+        if not target:
+            # (with a target the launch sizes follow the last call's count)
+            for key in ("walks_launched", "hops", "micro_steps", "launches"):
+                assert g["stats"][key] == e["stats"][key], key
+        assert g["stats"]["walker_seconds"] > 0
+    h.close()
+
+
 @pytest.mark.parametrize("expand", [0, 5])
 def test_plain_form_equals_persistent(mw, expand):
     """The plain form (one walker launch per transition round, survivors
