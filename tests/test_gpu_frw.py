@@ -215,6 +215,33 @@ def test_scores_independent_of_cache_state_and_resume(mw):
     assert torch.equal(torch.cat([c1["w"], c2["w"]]), a["w"])
 
 
+def test_cleared_table_cache_keeps_scores(mw):
+    """mw_table_cache_clear empties one lattice size's table cache (the
+    20-cell one, which no other test uses): the next extraction rebuilds
+    every table it needs, and its walks equal those of the warm run bit for
+    bit."""
+    import torch
+    st = W.c2_structure()
+    h = mw.StructureHandle(st)
+    mw.mw_table_cache_clear(20)
+    a = mw.frw_extract(h, 0, 30000, seed=8, n_cells=20, scores=True)
+    b = mw.frw_extract(h, 0, 30000, seed=8, n_cells=20, scores=True)
+    mw.mw_table_cache_clear(20)
+    c = mw.frw_extract(h, 0, 30000, seed=8, n_cells=20, scores=True)
+    print("misses cold", a["stats"]["cache_miss"], "warm", b["stats"]["cache_miss"], "cleared",
+          c["stats"]["cache_miss"])
+    assert a["stats"]["cache_miss"] > 0 and b["stats"]["cache_miss"] == 0
+    # (the same keys again; a lane that compares a key row its compute
+    # unit's cache still holds from before the row was written adds the key
+    # a second time, so the counts may differ slightly)
+    assert abs(c["stats"]["cache_miss"] - a["stats"]["cache_miss"]) <= 0.05 * a["stats"]["cache_miss"]
+    for r in (b, c):
+        assert torch.equal(a["net"], r["net"]) and torch.equal(a["w"], r["w"])
+    with pytest.raises(mw.MWError):
+        mw.mw_table_cache_clear(15)
+    h.close()
+
+
 @pytest.mark.parametrize("target", [0.0, 0.02])
 def test_graph_replays_equal_eager(mw, monkeypatch, target):
     """A structure keeps frw_extract's buffers between calls, and the usual
