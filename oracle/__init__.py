@@ -132,29 +132,56 @@ def sgf_vertex(codes, src=None):
     return P, et.value
 
 
-def hop_table(plane_codes, axis):
-    """Exit distribution (6 M^2, hit-index order) from the centre of a cube
-    stratified along `axis` with the given plane codes (Sec. III-C, Eq. 8)."""
-    seq = np.ascontiguousarray(plane_codes, dtype=np.uint64)
+def _plane_seq(planes, lattice):
+    if lattice == 1:
+        # cell lattice: the planes' permittivities, passed as float bits
+        return np.ascontiguousarray(np.asarray(planes, dtype=np.float32).view(np.uint32), dtype=np.uint64)
+    return np.ascontiguousarray(planes, dtype=np.uint64)
+
+
+def sgf_cell(eps, src=None):
+    """Exact exit distribution (6 N^2, hit-index order) and E(tau) on the
+    cell-centred lattice (Sec. III-A, Eq. 6 codes) of an (N, N, N) [k, j, i]
+    permittivity grid, N odd, from cell src (default the centre)."""
+    e = np.ascontiguousarray(eps, dtype=np.float32)
+    N = e.shape[0]
+    if src is None:
+        src = ((N - 1) // 2,) * 3
+    s = np.asarray(src, dtype=np.int32)
+    P = np.zeros(6 * N * N)
+    et = ctypes.c_double(0)
+    rc = lib().mwo_sgf_cell(_p(e), I32(N), _p(s), _p(P), ctypes.byref(et))
+    if rc:
+        raise RuntimeError("cell sgf solve failed (%d)" % rc)
+    return P, et.value
+
+
+def hop_table(plane_codes, axis, lattice=0):
+    """Exit distribution (hit-index order) from the centre of a cube
+    stratified along `axis` (Sec. III-C, Eq. 8): 6 M^2 entries of the vertex
+    lattice from its plane codes, or with lattice=1, 6 N^2 entries of the
+    cell-centred lattice from its plane permittivities."""
+    seq = _plane_seq(plane_codes, lattice)
     n = int(seq.size)
-    P = np.zeros(6 * (n - 1) ** 2)
-    rc = lib().mwo_hop_table(I32(n), I32(axis), _p(seq), _p(P))
+    P = np.zeros(6 * (n - 1) ** 2 if lattice == 0 else 6 * n * n)
+    rc = lib().mwo_hop_table(I32(lattice), I32(n), I32(axis), _p(seq), _p(P))
     if rc:
         raise ValueError("hop table failed (%d)" % rc)
     return P
 
 
-def first_table(plane_codes, axis, normal_axis):
+def first_table(plane_codes, axis, normal_axis, lattice=0):
     """First-transition ingredients of a stratified cube: exit distributions
     from the centre c and from c +- e_normal, and the link conductances G+, G-
-    of c along the normal (eps units)."""
-    seq = np.ascontiguousarray(plane_codes, dtype=np.uint64)
+    of c along the normal (eps units).  lattice=1: the cell-centred lattice,
+    planes given by their permittivities."""
+    seq = _plane_seq(plane_codes, lattice)
     n = int(seq.size)
-    nb = 6 * (n - 1) ** 2
+    nb = 6 * (n - 1) ** 2 if lattice == 0 else 6 * n * n
     Pc, Pp, Pm = np.zeros(nb), np.zeros(nb), np.zeros(nb)
     gp, gm = ctypes.c_double(0), ctypes.c_double(0)
-    rc = lib().mwo_first_table(I32(n), I32(axis), I32(normal_axis), _p(seq), _p(Pc), _p(Pp), _p(Pm),
-                               ctypes.byref(gp), ctypes.byref(gm))
+    rc = lib().mwo_first_table(I32(lattice), I32(n), I32(axis), I32(normal_axis), _p(seq), _p(Pc), _p(Pp),
+                               _p(Pm), ctypes.byref(gp), ctypes.byref(gm))
     if rc:
         raise ValueError("first table failed (%d)" % rc)
     return Pc, Pp, Pm, gp.value, gm.value
@@ -221,7 +248,8 @@ STAT_KEYS = ("walks", "hops", "micro_steps", "cls_uniform", "cls_stratified", "c
 
 
 def frw_extract(st, master, n_walks, seed=0, first_walk=0, n_cells=16, hybrid=1,
-                abs_tol_rel=1e-6, threads=1, scores=False, expand=1.0, kernel_limits=False, gauss_is=0.0):
+                abs_tol_rel=1e-6, threads=1, scores=False, expand=1.0, kernel_limits=False, gauss_is=0.0,
+                lattice=0):
     """Alg. 1: capacitance row (fF, last entry env) and standard errors.
     expand > 1: MicroWalk-E transitions with that expansion factor.
     gauss_is > 0: importance sampling of the Gaussian-surface point over
@@ -231,7 +259,9 @@ def frw_extract(st, master, n_walks, seed=0, first_walk=0, n_cells=16, hybrid=1,
     MicroWalk-E rule when expand > 1).  kernel_limits=True reproduces the GPU
     kernel's capacity rule instead (a cube is halved while more than 16
     dielectric boxes, or for MicroWalk-E 7 conductors, touch it); it exists
-    only so that single walks can be compared with the kernel's one by one."""
+    only so that single walks can be compared with the kernel's one by one.
+    lattice=1: every cube on the cell-centred lattice of Sec. III-A (n_cells
+    odd; walks start in the centre cell and leave through panel centres)."""
     args, keep = _structure_args(st)
     K = st.n_nets + 1
     row = np.zeros(K)
@@ -241,7 +271,7 @@ def frw_extract(st, master, n_walks, seed=0, first_walk=0, n_cells=16, hybrid=1,
     stats = np.zeros(13, dtype=np.uint64)
     rc = lib().mwo_frw_extract(*args, I32(master), U64(n_walks), U64(first_walk), U64(seed),
                                I32(n_cells), I32(hybrid), DBL(abs_tol_rel), DBL(expand),
-                               I32(1 if kernel_limits else 0), DBL(gauss_is), I32(threads),
+                               I32(1 if kernel_limits else 0), DBL(gauss_is), I32(lattice), I32(threads),
                                _p(row), _p(se), _p(nets), _p(w), _p(stats))
     if rc:
         raise RuntimeError("oracle frw_extract failed (%d)" % rc)

@@ -389,6 +389,150 @@ bool sgf_vertex(const VertexSystem& S, const int src[3], std::vector<double>& P,
 }
 
 // ---------------------------------------------------------------------------
+// Exact discrete SGF of the cell-centred lattice (Sec. III-A; Eqs. 7-8, 11).
+//
+// The Eq. (6) codes of a node are normalised by its own permittivity, so the
+// code of a link seen from its two ends differs and G is not symmetric.  The
+// chain of Alg. 3 is still Q_II = D^-1 G_II; the source row of
+// (I - Q_II)^-1 Q_IB is P_b = sum_v y_v G_vb with (D - G_II)^T y = e_src,
+// and E(tau) = sum_v y_v D_v.  The solve is Jacobi-preconditioned BiCGSTAB
+// (van der Vorst) to a relative residual of 1e-14, checked on the true
+// residual and restarted from the current iterate when the recursive one
+// has drifted.
+// ---------------------------------------------------------------------------
+struct CellSystem {
+    int N;
+    std::vector<uint64_t> g;  // 6 per node: Eq. (6) codes, 2^24 towards a boundary panel
+    std::vector<double> D;
+};
+
+CellSystem build_cell_system(const std::vector<float>& eps, int N) {
+    CellSystem S;
+    S.N = N;
+    const size_t NI = (size_t)N * N * N;
+    S.g.resize(NI * 6);
+    S.D.resize(NI);
+    auto EPS = [&](int x, int y, int z) { return eps[((size_t)z * N + y) * N + x]; };
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                const size_t v = ((size_t)k * N + j) * N + i;
+                uint64_t sum = 0;
+                for (int d = 0; d < 6; ++d) {
+                    const int q[3] = {i + DIR[d][0], j + DIR[d][1], k + DIR[d][2]};
+                    const bool inside = q[0] >= 0 && q[0] < N && q[1] >= 0 && q[1] < N && q[2] >= 0 && q[2] < N;
+                    const uint64_t c = inside ? cell_link_code(EPS(q[0], q[1], q[2]), EPS(i, j, k)) : (1ull << 24);
+                    S.g[v * 6 + d] = c;
+                    sum += c;
+                }
+                S.D[v] = (double)sum;
+            }
+    return S;
+}
+
+// y = (D - G_II)^T x
+void apply_cell_t(const CellSystem& S, const std::vector<double>& x, std::vector<double>& y) {
+    const int N = S.N;
+    y.assign(x.size(), 0.0);
+    for (size_t v = 0; v < x.size(); ++v) y[v] = S.D[v] * x[v];
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                const size_t v = ((size_t)k * N + j) * N + i;
+                for (int d = 0; d < 6; ++d) {
+                    const int q[3] = {i + DIR[d][0], j + DIR[d][1], k + DIR[d][2]};
+                    if (q[0] < 0 || q[0] >= N || q[1] < 0 || q[1] >= N || q[2] < 0 || q[2] >= N) continue;
+                    y[((size_t)q[2] * N + q[1]) * N + q[0]] -= (double)S.g[v * 6 + d] * x[v];
+                }
+            }
+}
+
+static double norm2(const std::vector<double>& a) {
+    double s = 0;
+    for (double v : a) s += v * v;
+    return std::sqrt(s);
+}
+static double dotp(const std::vector<double>& a, const std::vector<double>& b) {
+    double s = 0;
+    for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
+    return s;
+}
+
+bool solve_cell_t(const CellSystem& S, const std::vector<double>& b, std::vector<double>& x) {
+    const size_t NI = S.D.size();
+    x.assign(NI, 0.0);
+    const double bn = norm2(b);
+    if (bn == 0) return true;
+    std::vector<double> r(NI), rh(NI), p(NI), v(NI), s(NI), t(NI), y(NI), z(NI), ax(NI);
+    for (int restart = 0; restart < 8; ++restart) {
+        apply_cell_t(S, x, ax);
+        for (size_t i = 0; i < NI; ++i) r[i] = b[i] - ax[i];
+        if (norm2(r) <= 1e-14 * bn) return true;
+        rh = r;
+        std::fill(p.begin(), p.end(), 0.0);
+        std::fill(v.begin(), v.end(), 0.0);
+        double rho = 1, alpha = 1, omega = 1;
+        for (int it = 0; it < 20000; ++it) {
+            const double rho1 = dotp(rh, r);
+            if (rho1 == 0) break;
+            const double beta = (rho1 / rho) * (alpha / omega);
+            for (size_t i = 0; i < NI; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+            for (size_t i = 0; i < NI; ++i) y[i] = p[i] / S.D[i];
+            apply_cell_t(S, y, v);
+            alpha = rho1 / dotp(rh, v);
+            for (size_t i = 0; i < NI; ++i) {
+                s[i] = r[i] - alpha * v[i];
+                x[i] += alpha * y[i];
+            }
+            if (norm2(s) <= 1e-14 * bn) break;
+            for (size_t i = 0; i < NI; ++i) z[i] = s[i] / S.D[i];
+            apply_cell_t(S, z, t);
+            omega = dotp(t, s) / dotp(t, t);
+            for (size_t i = 0; i < NI; ++i) {
+                x[i] += omega * z[i];
+                r[i] = s[i] - omega * t[i];
+            }
+            rho = rho1;
+            if (norm2(r) <= 1e-14 * bn || omega == 0) break;
+        }
+    }
+    apply_cell_t(S, x, ax);
+    for (size_t i = 0; i < NI; ++i) r[i] = b[i] - ax[i];
+    return norm2(r) <= 1e-14 * bn;
+}
+
+// Hit index of boundary panel (axis ax, side, in-face coordinates a, b) of
+// the cell lattice, as microwalk_cell numbers them.
+int cell_hit_index(int N, int ax, int side, int a, int b) { return (2 * ax + side) * N * N + b * N + a; }
+
+// Exit distribution P (6 N^2 entries, hit-index order) and E(tau) from the
+// node (voxel) src.
+bool sgf_cell(const CellSystem& S, const int src[3], std::vector<double>& P, double* etau) {
+    const int N = S.N;
+    std::vector<double> b(S.D.size(), 0.0), y;
+    b[((size_t)src[2] * N + src[1]) * N + src[0]] = 1.0;
+    if (!solve_cell_t(S, b, y)) return false;
+    P.assign((size_t)6 * N * N, 0.0);
+    double et = 0;
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                const size_t v = ((size_t)k * N + j) * N + i;
+                et += y[v] * S.D[v];
+                for (int d = 0; d < 6; ++d) {
+                    const int q[3] = {i + DIR[d][0], j + DIR[d][1], k + DIR[d][2]};
+                    const int ax = d / 2;
+                    if (q[ax] >= 0 && q[ax] < N) continue;
+                    const int a = ax == 0 ? q[1] : q[0];
+                    const int bb = ax == 2 ? q[1] : q[2];
+                    P[cell_hit_index(N, ax, q[ax] >= N ? 1 : 0, a, bb)] += y[v] * (double)S.g[v * 6 + d];
+                }
+            }
+    if (etau) *etau = et;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
 // Geometry (Alg. 1 input) and voxelisation of transition cubes.
 // ---------------------------------------------------------------------------
 struct Box {
@@ -574,6 +718,7 @@ struct Cube {
     int n;
     double c[3], R, h;
     std::vector<uint64_t> e;  // vertex cell codes
+    std::vector<float> ep;    // cell permittivities (the cell lattice's Eq. 6 uses them)
     int cls;                  // 0 uniform, 1 stratified, 2 non-stratified
     int axis;                 // stratification axis (0..2) when cls <= 1
     uint8_t full[3];          // per axis: every present region spans all cells
@@ -594,6 +739,7 @@ void build_cube(const Structure& S, const double c[3], double R, int n, Cube& C)
     C.R = R;
     C.h = 2 * R / n;
     C.e.assign((size_t)n * n * n, 0);
+    C.ep.assign((size_t)n * n * n, 0.f);
     std::vector<double> f[3];
     for (int a = 0; a < 3; ++a) {
         f[a].resize(n);
@@ -603,7 +749,9 @@ void build_cube(const Structure& S, const double c[3], double R, int n, Cube& C)
         for (int j = 0; j < n; ++j)
             for (int i = 0; i < n; ++i) {
                 double p[3] = {f[0][i], f[1][j], f[2][k]};
-                C.e[((size_t)k * n + j) * n + i] = vertex_cell_code(eps_at(S, p));
+                const float ev = eps_at(S, p);
+                C.e[((size_t)k * n + j) * n + i] = vertex_cell_code(ev);
+                C.ep[((size_t)k * n + j) * n + i] = ev;
             }
     // per-region per-axis membership counts
     bool full_axis[3] = {true, true, true};
@@ -752,6 +900,68 @@ std::vector<uint64_t> homogenised_codes(const Cube& C, int a) {
     return seq;
 }
 
+// Cell lattice: a plane is described by its permittivity (the float's bit
+// pattern), since Eq. (6) combines permittivities, not codes.
+uint64_t float_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return u;
+}
+float bits_float(uint64_t b) {
+    const uint32_t u = (uint32_t)b;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+std::vector<uint64_t> plane_eps(const Cube& C, int s) {
+    int n = C.n;
+    std::vector<uint64_t> seq(n);
+    for (int p = 0; p < n; ++p) {
+        int q[3] = {0, 0, 0};
+        q[s] = p;
+        seq[p] = float_bits(C.ep[((size_t)q[2] * n + q[1]) * n + q[0]]);
+    }
+    return seq;
+}
+
+// Homogenised first cube on the cell lattice: each plane normal to a takes
+// the mean permittivity of its n^2 cells, rounded to float.  The binary64 sum
+// is exact in any order (at most 2^10 cells of permittivity in [1e-3, 1e3]).
+std::vector<uint64_t> homogenised_eps(const Cube& C, int a) {
+    int n = C.n;
+    std::vector<uint64_t> seq(n);
+    for (int p = 0; p < n; ++p) {
+        double sum = 0;
+        for (int u = 0; u < n; ++u)
+            for (int v = 0; v < n; ++v) {
+                int q[3];
+                q[a] = p;
+                q[(a + 1) % 3] = u;
+                q[(a + 2) % 3] = v;
+                sum += (double)C.ep[((size_t)q[2] * n + q[1]) * n + q[0]];
+            }
+        seq[p] = float_bits((float)(sum / (double)(n * n)));
+    }
+    return seq;
+}
+
+std::vector<float> expand_layers_eps(const std::vector<uint64_t>& seq, int s, int n) {
+    std::vector<float> e((size_t)n * n * n);
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                int q[3] = {i, j, k};
+                e[((size_t)k * n + j) * n + i] = bits_float(seq[q[s]]);
+            }
+    return e;
+}
+
+// Face conductance of the link between two cells of the cell lattice, in
+// permittivity units: the series (harmonic) combination over its two halves,
+// the conductance behind Eq. (6).
+double cell_face_eps(float a, float b) { return 2.0 * (double)a * (double)b / ((double)a + (double)b); }
+
 std::vector<uint64_t> expand_layers(const std::vector<uint64_t>& seq, int s, int n) {
     std::vector<uint64_t> e((size_t)n * n * n);
     for (int k = 0; k < n; ++k)
@@ -785,8 +995,9 @@ struct TableCache {
     std::atomic<uint64_t> misses{0};
 };
 
-std::shared_ptr<HopTable> hop_table(TableCache& TC, int n, int s, const std::vector<uint64_t>& seq) {
+std::shared_ptr<HopTable> hop_table(TableCache& TC, int lattice, int n, int s, const std::vector<uint64_t>& seq) {
     std::vector<uint64_t> key;
+    key.push_back((uint64_t)lattice);
     key.push_back((uint64_t)n);
     key.push_back((uint64_t)s);
     key.insert(key.end(), seq.begin(), seq.end());
@@ -795,19 +1006,28 @@ std::shared_ptr<HopTable> hop_table(TableCache& TC, int n, int s, const std::vec
         auto it = TC.hop.find(key);
         if (it != TC.hop.end()) return it->second;
     }
-    auto e = expand_layers(seq, s, n);
-    VertexSystem VS = build_vertex_system(e, n);
     auto T = std::make_shared<HopTable>();
-    int src[3] = {n / 2, n / 2, n / 2};
-    if (!sgf_vertex(VS, src, T->P, nullptr)) return nullptr;
+    if (lattice == 1) {
+        // cell lattice: the walk starts in the centre cell
+        const CellSystem CS = build_cell_system(expand_layers_eps(seq, s, n), n);
+        int src[3] = {(n - 1) / 2, (n - 1) / 2, (n - 1) / 2};
+        if (!sgf_cell(CS, src, T->P, nullptr)) return nullptr;
+    } else {
+        auto e = expand_layers(seq, s, n);
+        VertexSystem VS = build_vertex_system(e, n);
+        int src[3] = {n / 2, n / 2, n / 2};
+        if (!sgf_vertex(VS, src, T->P, nullptr)) return nullptr;
+    }
     TC.misses++;
     std::lock_guard<std::mutex> g(TC.mu);
     TC.hop[key] = T;
     return T;
 }
 
-std::shared_ptr<FirstTable> first_table(TableCache& TC, int n, int s, int a, const std::vector<uint64_t>& seq) {
+std::shared_ptr<FirstTable> first_table(TableCache& TC, int lattice, int n, int s, int a,
+                                        const std::vector<uint64_t>& seq) {
     std::vector<uint64_t> key;
+    key.push_back((uint64_t)lattice);
     key.push_back((uint64_t)n);
     key.push_back((uint64_t)s);
     key.push_back((uint64_t)a);
@@ -817,9 +1037,30 @@ std::shared_ptr<FirstTable> first_table(TableCache& TC, int n, int s, int a, con
         auto it = TC.first.find(key);
         if (it != TC.first.end()) return it->second;
     }
+    auto T = std::make_shared<FirstTable>();
+    if (lattice == 1) {
+        // cell lattice: sources at the centre cell and its two neighbours
+        // along a; G+-, the face conductances between them
+        const std::vector<float> ep = expand_layers_eps(seq, s, n);
+        const CellSystem CS = build_cell_system(ep, n);
+        const int h0 = (n - 1) / 2;
+        int c[3] = {h0, h0, h0};
+        int cp[3] = {h0, h0, h0}, cm[3] = {h0, h0, h0};
+        cp[a] += 1;
+        cm[a] -= 1;
+        if (!sgf_cell(CS, c, T->Pc, nullptr)) return nullptr;
+        if (!sgf_cell(CS, cp, T->Pp, nullptr)) return nullptr;
+        if (!sgf_cell(CS, cm, T->Pm, nullptr)) return nullptr;
+        auto at = [&](const int q[3]) { return ep[((size_t)q[2] * n + q[1]) * n + q[0]]; };
+        T->Gp = cell_face_eps(at(c), at(cp));
+        T->Gm = cell_face_eps(at(c), at(cm));
+        TC.misses++;
+        std::lock_guard<std::mutex> g(TC.mu);
+        TC.first[key] = T;
+        return T;
+    }
     auto e = expand_layers(seq, s, n);
     VertexSystem VS = build_vertex_system(e, n);
-    auto T = std::make_shared<FirstTable>();
     int c[3] = {n / 2, n / 2, n / 2};
     int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
     cp[a] += 1;
@@ -995,7 +1236,26 @@ struct FrwParams {
     uint64_t seed;
     double expand = 1.0;  // MicroWalk-E expansion factor (1: plain MicroWalk)
     bool kernel_limits = false;  // reproduce the GPU kernel's cube halving (tests only)
+    int lattice = 0;             // 0 vertex lattice, 1 cell-centred lattice (n odd)
 };
+
+// Exit point of hit index b of cube C: a boundary node of the vertex
+// lattice, or the centre of a boundary panel of the cell lattice.
+void exit_point(const Cube& C, int lattice, int b, double x[3]) {
+    const int n = C.n;
+    if (lattice == 1) {
+        const int f = b / (n * n), rem = b % (n * n);
+        const int ax = f / 2, side = f % 2;
+        const int o0 = ax == 0 ? 1 : 0, o1 = ax == 2 ? 1 : 2;
+        x[ax] = C.c[ax] + (side ? C.R : -C.R);
+        x[o0] = C.c[o0] - C.R + (rem % n + 0.5) * C.h;
+        x[o1] = C.c[o1] - C.R + (rem / n + 0.5) * C.h;
+        return;
+    }
+    int node[3];
+    vertex_node_of_hit(n, b, node);
+    for (int q = 0; q < 3; ++q) x[q] = C.c[q] - C.R + node[q] * C.h;
+}
 
 // FirstTransition(r) kernel: the first cube centred at r on face F of G (it
 // touches the master), its branch (Fig. 4 reading), and the flux weights
@@ -1011,25 +1271,26 @@ double first_weights(const Structure& S, const Gauss& G, const GFace& F, const d
     build_cube(S, r, R, n, C);
     int branch, s;
     std::vector<uint64_t> seq;
+    const bool cell = P.lattice == 1;
     if (C.cls == 0) {
         branch = 0;
         s = a;
-        seq = plane_codes(C, a);
+        seq = cell ? plane_eps(C, a) : plane_codes(C, a);
     } else if (stratified_along(C, a)) {
         branch = 1;
         s = a;
-        seq = plane_codes(C, a);
+        seq = cell ? plane_eps(C, a) : plane_codes(C, a);
     } else if (C.cls == 1) {
         branch = 2;
         s = C.axis;
-        seq = plane_codes(C, s);
+        seq = cell ? plane_eps(C, s) : plane_codes(C, s);
     } else {
         branch = 3;
         s = a;
-        seq = homogenised_codes(C, a);
+        seq = cell ? homogenised_eps(C, a) : homogenised_codes(C, a);
     }
     *branch_out = branch;
-    auto FT = first_table(TC, n, s, a, seq);
+    auto FT = first_table(TC, P.lattice, n, s, a, seq);
     if (!FT) return -1.0;
     // flux stencil along the outward normal
     const std::vector<double>& Pout = F.side ? FT->Pp : FT->Pm;
@@ -1128,12 +1389,11 @@ bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P
     for (size_t b = 0; b < w.size(); ++b) aw[b] = std::fabs(w[b]);
     int b = sample_index(aw, K, rng_word(P.seed, 0, walk, PURPOSE_FIRST, 0));
     double omega = EPS0 * factor * K * (w[b] > 0 ? 1.0 : -1.0);
-    int node[3];
-    vertex_node_of_hit(n, b, node);
     // The walker's position is folded back into the window at symmetry
     // walls: by mirror symmetry the folded point has the same potential.
-    double x[3];
-    for (int q = 0; q < 3; ++q) x[q] = fold(S, q, C.c[q] - C.R + node[q] * C.h);
+    double x[3], xe[3];
+    exit_point(C, P.lattice, b, xe);
+    for (int q = 0; q < 3; ++q) x[q] = fold(S, q, xe[q]);
 
     // Transition loop.
     for (uint32_t t = 1;; ++t) {
@@ -1158,7 +1418,8 @@ bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P
         st.hop_class[C.cls]++;
         int hb;
         if (P.hybrid && C.cls <= 1) {
-            auto HT = hop_table(TC, n, C.axis, plane_codes(C, C.axis));
+            auto HT = hop_table(TC, P.lattice, n, C.axis,
+                                P.lattice == 1 ? plane_eps(C, C.axis) : plane_codes(C, C.axis));
             if (!HT) return false;
             hb = sample_index(HT->P, 1.0, rng_word(P.seed, t, walk, PURPOSE_TABLE, 0));
         } else if (P.expand > 1.0) {
@@ -1180,6 +1441,12 @@ bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P
                 return true;
             }
             if (hb < 0) return false;
+        } else if (P.lattice == 1) {
+            // Alg. 3 on the cell-centred lattice from the centre cell
+            int32_t steps = 0;
+            hb = microwalk_cell(C.ep.data(), n, P.seed, t, walk, &steps);
+            st.micro_steps += (uint64_t)steps;
+            if (hb < 0) return false;
         } else {
             int start[3] = {n / 2, n / 2, n / 2};
             int32_t steps = 0;
@@ -1187,8 +1454,8 @@ bool frw_walk(const Structure& S, const Gauss& G, int master, const FrwParams& P
             st.micro_steps += (uint64_t)steps;
             if (hb < 0) return false;
         }
-        vertex_node_of_hit(n, hb, node);
-        for (int q = 0; q < 3; ++q) x[q] = fold(S, q, C.c[q] - C.R + node[q] * C.h);
+        exit_point(C, P.lattice, hb, xe);
+        for (int q = 0; q < 3; ++q) x[q] = fold(S, q, xe[q]);
     }
 }
 
@@ -1334,6 +1601,18 @@ int mwo_sgf_vertex(const uint64_t* codes, int n, const int32_t* src, double* P, 
     return 0;
 }
 
+// Exact exit distribution and E(tau) of the cell-centred lattice (N odd)
+// from cell src, given the N^3 cell permittivities.
+int mwo_sgf_cell(const float* eps, int N, const int32_t* src, double* P, double* etau) {
+    if (N < 1 || N % 2 == 0) return -1;
+    const CellSystem CS = build_cell_system(std::vector<float>(eps, eps + (size_t)N * N * N), N);
+    std::vector<double> Pv;
+    int s[3] = {src[0], src[1], src[2]};
+    if (!sgf_cell(CS, s, Pv, etau)) return -2;
+    std::copy(Pv.begin(), Pv.end(), P);
+    return 0;
+}
+
 // Voxelisation + classification of one transition cube of a structure.
 // out_codes: n^3 vertex cell codes; out_cls: [class, axis].
 int mwo_build_cube(const double* cond, int n_cond, int n_nets, const double* diel, int n_diel,
@@ -1379,10 +1658,13 @@ int mwo_microwalk_e_cube(const double* cond, int n_cond, int n_nets, const doubl
 // Transition tables of a stratified cube (plane codes seq[n] along axis s),
 // as the walks use them (Sec. III-C; the exact discrete SGF, Eq. 8).
 // Hop table: exit distribution P (6 M^2) from the centre node.
-int mwo_hop_table(int n, int s, const uint64_t* seq, double* P) {
-    if (n < 2 || n % 2 || s < 0 || s > 2) return -1;
+// lattice 1: the cell-centred lattice (n odd, 6 n^2 entries from the centre
+// cell); seq then holds the planes' permittivities as float bit patterns.
+int mwo_hop_table(int lattice, int n, int s, const uint64_t* seq, double* P) {
+    if (lattice != 0 && lattice != 1) return -1;
+    if (n < 2 || (lattice == 0 ? n % 2 != 0 : n % 2 == 0) || s < 0 || s > 2) return -1;
     TableCache TC;
-    auto T = hop_table(TC, n, s, std::vector<uint64_t>(seq, seq + n));
+    auto T = hop_table(TC, lattice, n, s, std::vector<uint64_t>(seq, seq + n));
     if (!T) return -2;
     std::copy(T->P.begin(), T->P.end(), P);
     return 0;
@@ -1390,11 +1672,12 @@ int mwo_hop_table(int n, int s, const uint64_t* seq, double* P) {
 
 // First-transition table for normal axis a: exit distributions from the
 // centre c and from c +- e_a, and the link conductances G+, G- of c along a.
-int mwo_first_table(int n, int s, int a, const uint64_t* seq, double* Pc, double* Pp, double* Pm, double* Gp,
-                    double* Gm) {
-    if (n < 4 || n % 2 || s < 0 || s > 2 || a < 0 || a > 2) return -1;
+int mwo_first_table(int lattice, int n, int s, int a, const uint64_t* seq, double* Pc, double* Pp, double* Pm,
+                    double* Gp, double* Gm) {
+    if (lattice != 0 && lattice != 1) return -1;
+    if (n < 3 || (lattice == 0 ? n % 2 != 0 : n % 2 == 0) || s < 0 || s > 2 || a < 0 || a > 2) return -1;
     TableCache TC;
-    auto T = first_table(TC, n, s, a, std::vector<uint64_t>(seq, seq + n));
+    auto T = first_table(TC, lattice, n, s, a, std::vector<uint64_t>(seq, seq + n));
     if (!T) return -2;
     std::copy(T->Pc.begin(), T->Pc.end(), Pc);
     std::copy(T->Pp.begin(), T->Pp.end(), Pp);
@@ -1446,15 +1729,19 @@ int mwo_gauss(const double* cond, int n_cond, int n_nets, const double* win, con
 int mwo_frw_extract(const double* cond, int n_cond, int n_nets, const double* diel, int n_diel,
                     const double* layer_z0, const double* layer_eps, int n_layers, const double* win,
                     const int32_t* bc, int master, uint64_t n_walks, uint64_t first_walk, uint64_t seed, int n,
-                    int hybrid, double abs_tol_rel, double expand, int kernel_limits, double gauss_is, int threads,
-                    double* row, double* se, int32_t* score_net, double* score_w, uint64_t* stats) {
-    if (n < 4 || n % 2 || n_walks < 2) return -1;
+                    int hybrid, double abs_tol_rel, double expand, int kernel_limits, double gauss_is, int lattice,
+                    int threads, double* row, double* se, int32_t* score_net, double* score_w, uint64_t* stats) {
+    if (n_walks < 2 || (lattice != 0 && lattice != 1)) return -1;
+    // vertex lattice: n even (a centre node); cell lattice: n odd (a centre
+    // cell), plain MicroWalk only
+    if (lattice == 0 ? (n < 4 || n % 2 != 0) : (n < 3 || n % 2 == 0 || expand > 1.0)) return -1;
     Structure S = make_structure(cond, n_cond, n_nets, diel, n_diel, layer_z0, layer_eps, n_layers, win, bc);
     Gauss G;
     if (!build_gauss(S, master, G)) return -2;
     double diag = 0;
     for (int a = 0; a < 3; ++a) diag += (S.whi[a] - S.wlo[a]) * (S.whi[a] - S.wlo[a]);
-    FrwParams P{n, hybrid, abs_tol_rel * std::sqrt(diag), seed, expand < 1.0 ? 1.0 : expand, kernel_limits != 0};
+    FrwParams P{n, hybrid, abs_tol_rel * std::sqrt(diag), seed, expand < 1.0 ? 1.0 : expand, kernel_limits != 0,
+                lattice};
     TableCache TC;
     // importance sampling over G: patches of edge at most gauss_is x g
     if (gauss_is > 0 && !build_patches(S, G, gauss_is * G.g, P, TC)) return -4;

@@ -75,9 +75,10 @@ def vertex_exit_distribution(links, n, src=None):
     return np.asarray(P).ravel(), float(x.sum())
 
 
-def cell_exit_distribution(links, N):
+def cell_exit_distribution(links, N, src=None):
     """Same solve on the cell-centred lattice of Sec. III-A (Eq. 6 codes),
-    nodes (k*N+j)*N+i, hit index f*N^2 + b*N + a."""
+    nodes (k*N+j)*N+i, hit index f*N^2 + b*N + a; src (i, j, k) defaults to
+    the centre cell."""
     NI = N ** 3
     links = np.asarray(links, dtype=np.float64)
     p = links / links.sum(axis=1, keepdims=True)
@@ -104,9 +105,10 @@ def cell_exit_distribution(links, N):
     Q = sp.csr_matrix((vals, (rows, cols)), shape=(NI, NI))
     QB = sp.csr_matrix((bval, (brow, bcol)), shape=(NI, 6 * N * N))
     A = sp.identity(NI, format="csc") - Q.tocsc()
-    c = (N - 1) // 2
+    if src is None:
+        src = ((N - 1) // 2,) * 3
     e = np.zeros(NI)
-    e[(c * N + c) * N + c] = 1.0
+    e[(src[2] * N + src[1]) * N + src[0]] = 1.0
     x = spla.spsolve(A.T.tocsc(), e)
     return np.asarray(QB.T @ x).ravel(), float(x.sum())
 
