@@ -167,6 +167,37 @@ def c2_figures(mw, W, steps=20, walks=1000000, n_cells=16):
     return out, rows, ses
 
 
+def cell_lattice(mw, W, steps=10, walks=1000000, n_cells=15):
+    """Crossing wires (4 nets), 1e6 walks per extraction on the cell-centred
+    lattice of Sec. III-A (15^3-cell cubes, nodes at the voxel centres)."""
+    st = W.c2_structure()
+    h = mw.StructureHandle(st)
+    kw = dict(n_cells=n_cells, lattice=mw.MW_LATTICE_CELL)
+    mw.frw_extract(h, 0, walks, seed=9000, **kw)
+    rows, ses = [], []
+    wsum = ssum = wk = hops = 0
+    t0 = time.perf_counter()
+    for k in range(steps):
+        r = mw.frw_extract(h, 0, walks, seed=k, **kw)
+        s = r["stats"]
+        wsum += s["walks"]
+        ssum += s["micro_steps"]
+        hops += s["hops"]
+        wk += s["walker_seconds"]
+        rows.append(r["row"])
+        ses.append(r["se"])
+    dt = time.perf_counter() - t0
+    h.close()
+    out = {"workload": "crossing wires 2x2x1 um, 4 nets, master 0, cell-centred lattice, %d^3-cell cubes, "
+                       "%d walks per extraction" % (n_cells, walks),
+           "ms_per_extraction": dt / steps * 1e3, "walks_per_s": wsum / dt, "micro_steps_per_s": ssum / dt,
+           "walker_ms_per_extraction": wk / steps * 1e3, "hops_per_walk": hops / wsum,
+           "micro_steps_per_walk": ssum / wsum,
+           "C_mm": float(np.mean([r[0] for r in rows])),
+           "rel_3sigma_Cmm": float(np.mean([3 * e[0] / r[0] for r, e in zip(rows, ses)]))}
+    return out, rows, ses
+
+
 def batched_vs_plain(mw, W, reps=5):
     """4096-cube batched MicroWalk workload: autotuned graph replay of one
     persistent launch vs one launch per cube, same walks and seed."""
@@ -464,6 +495,8 @@ def main():
         _progress("c4 plain vs persistent")
         out["c2"], extras_rows["c2_rows"], extras_rows["c2_ses"] = c2_figures(mw, W)
         _progress("c2")
+        out["cell_lattice"], extras_rows["cell_rows"], extras_rows["cell_ses"] = cell_lattice(mw, W)
+        _progress("cell lattice")
         out["c1"] = c1_single_cube(mw, W)
         out["batched"] = batched_vs_plain(mw, W)
         _progress("c1, batched")
@@ -486,6 +519,9 @@ def main():
             out["c1"]["oracle"] = cpu_baseline_c1(W)
             r2 = oracle.frw_extract(W.c2_structure(), 0, 200000, seed=7, threads=_cores())
             out["c2"]["oracle_agreement"] = agreement(extras_rows["c2_rows"], extras_rows["c2_ses"], r2)
+            r3 = oracle.frw_extract(W.c2_structure(), 0, 100000, seed=7, threads=_cores(), n_cells=15, lattice=1)
+            out["cell_lattice"]["oracle_agreement"] = agreement(extras_rows["cell_rows"], extras_rows["cell_ses"],
+                                                                r3)
     print(json.dumps(out))
 
 

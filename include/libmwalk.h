@@ -245,7 +245,9 @@ mw_status mw_structure_create(const mw_structure_desc* desc, mw_structure** out)
 mw_status mw_structure_destroy(mw_structure* s);
 
 typedef struct {
-    int32_t n_cells;          /* cube lattice size (even, 4..32); default 16  */
+    int32_t n_cells;          /* cube lattice size: even, 4..32, on the vertex
+                                 lattice (default 16); odd, 3..31, on the cell
+                                 lattice (default 15)                       */
     int32_t hybrid;           /* 1 (default): stratified non-first cubes use
                                  the exact SGF table, the rest MicroWalk
                                  (Sec. III-C); 0: every non-first cube uses
@@ -292,6 +294,21 @@ typedef struct {
                                  is Q area_p / q_p.  The estimator keeps its
                                  expectation; its variance drops where K
                                  varies over G.  0 or in [0.05, 64].       */
+    int32_t lattice;          /* MW_LATTICE_VERTEX (0, default): nodes at the
+                                 cell corners; the walk starts at the centre
+                                 node and leaves through a boundary node.
+                                 MW_LATTICE_CELL (1): Sec. III-A as written,
+                                 nodes at the voxel centres with the Eq. (6)
+                                 coefficients; the walk starts in the centre
+                                 cell and leaves through the centre of a
+                                 boundary panel.  Stratified tables and
+                                 first-transition weights use the same
+                                 lattice (the face permittivity of a link
+                                 between two cells is their series value
+                                 2 e1 e2 / (e1 + e2)); homogenised first cubes
+                                 take each plane's mean permittivity.  The
+                                 cell lattice needs an odd n_cells and plain
+                                 MicroWalk (expand <= 1).                   */
 } frw_options;
 
 typedef struct {
@@ -379,7 +396,8 @@ mw_status frw_autotune(mw_structure* s, int32_t master, uint64_t walks, uint64_t
 
 /* ------------------------------------------------------------------------
  * mw_table_cache_clear — empties the transition-table cache of lattice size
- * n_cells (even, 4..32) on the current device; later calls rebuild the
+ * n_cells (even 4..32: vertex lattice; odd 3..31: cell lattice) on the
+ * current device; later calls rebuild the
  * tables they need (the tables are pure functions of their keys, so no
  * result changes).  Must not run while an extraction or server uses that
  * cache.  MW_EINVAL for a bad size.  Synchronous.                          */
@@ -410,6 +428,12 @@ mw_status mw_table_cache_clear(int32_t n_cells);
  * kh         host, 1 float or NULL: kind 1, sum_b |w_b| (the first-transition
  *            weight is eps0 |G| kh / h times the sign); kind 0: 0.
  * n_cells even in 4..32; codes in [66, 65536000] (eps in [1e-3, 1e3]).
+ * Cell-centred lattice (Sec. III-A, frw_options.lattice = 1): n_cells odd in
+ *   3..31, plane_codes[p] the bit pattern of the plane's float permittivity
+ *   (in [1e-3, 1e3]), M = n, the walk starts in the centre cell, b is the
+ *   panel index f*n^2 + b1*n + a (as mw_transition's cell lattice), and G+-
+ *   are the series permittivities 2 e_c e_+- / (e_c + e_+-) of the centre
+ *   cell and its neighbours along the normal.
  * MW_ELIMIT when the cache is full.  Synchronous.                          */
 mw_status mw_sgf_table(int32_t n_cells, int32_t kind, int32_t axis, int32_t normal_axis,
                        const uint32_t* plane_codes, uint32_t* cdf, uint32_t* sign_bits, float* kh);

@@ -271,7 +271,7 @@ class frw_options(ctypes.Structure):
                 ("expand", ctypes.c_int32), ("plain", ctypes.c_int32),
                 ("target_rel_3sigma", ctypes.c_double), ("abs_tol_rel", ctypes.c_double),
                 ("first_walk", ctypes.c_uint64), ("batch_walks", ctypes.c_uint64),
-                ("gauss_is", ctypes.c_double)]
+                ("gauss_is", ctypes.c_double), ("lattice", ctypes.c_int32)]
 
 
 class frw_stats(ctypes.Structure):
@@ -348,10 +348,11 @@ def mw_structure_destroy(handle):
 
 def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
                 target_rel_3sigma=0.0, abs_tol_rel=1e-6, first_walk=0, batch_walks=0,
-                scores=False, device="cuda", expand=0, plain=0, gauss_is=0.0):
+                scores=False, device="cuda", expand=0, plain=0, gauss_is=0.0, lattice=MW_LATTICE_VERTEX):
     """Alg. 1: one capacitance row (fF, last entry = grounded enclosure) and
     its standard errors.  With scores=True also returns the per-walk net and
-    fp32 weight (CUDA tensors)."""
+    fp32 weight (CUDA tensors).  lattice=MW_LATTICE_CELL: cubes on the
+    cell-centred lattice (odd n_cells)."""
     import torch
     if not isinstance(structure, StructureHandle):
         structure = StructureHandle(structure)
@@ -360,7 +361,7 @@ def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
     se = (ctypes.c_double * K)()
     stats = frw_stats()
     opt = frw_options(n_cells, hybrid, expand, plain, target_rel_3sigma, abs_tol_rel, first_walk,
-                      batch_walks, gauss_is)
+                      batch_walks, gauss_is, lattice)
     net = w = None
     if scores:
         net = torch.empty(walk_budget, dtype=torch.int32, device=device)
@@ -393,14 +394,19 @@ def mw_table_cache_clear(n_cells):
     _check(_lib.mw_table_cache_clear(I32(n_cells)))
 
 
-def mw_sgf_table(plane_codes, axis, kind=0, normal_axis=0):
+def mw_sgf_table(plane_codes, axis, kind=0, normal_axis=0, lattice=MW_LATTICE_VERTEX):
     """One transition table of the device cache (built if missing): the
     stratified cube's plane codes along `axis`; kind 0 hop table, kind 1
     first-transition table for `normal_axis`.  Returns {"cdf": uint32[6 M^2],
-    "sign": bool[6 M^2] (kind 1), "kh": float (kind 1)}."""
-    codes = np.ascontiguousarray(plane_codes, dtype=np.uint32)
+    "sign": bool[6 M^2] (kind 1), "kh": float (kind 1)}.  With
+    lattice=MW_LATTICE_CELL the planes are given by their permittivities
+    (odd count) and M = n."""
+    if lattice == MW_LATTICE_CELL:
+        codes = np.ascontiguousarray(np.asarray(plane_codes, dtype=np.float32).view(np.uint32))
+    else:
+        codes = np.ascontiguousarray(plane_codes, dtype=np.uint32)
     n = int(codes.size)
-    nb = 6 * (n - 1) ** 2
+    nb = 6 * (n - 1) ** 2 if lattice == MW_LATTICE_VERTEX else 6 * n * n
     cdf = np.zeros(nb, dtype=np.uint32)
     bits = np.zeros((nb + 31) // 32, dtype=np.uint32)
     kh = ctypes.c_float(0)
@@ -412,7 +418,7 @@ def mw_sgf_table(plane_codes, axis, kind=0, normal_axis=0):
 
 def frw_extract_matrix(structure, walks_per_master, seed=0, masters=None, n_cells=16, hybrid=1,
                        target_rel_3sigma=0.0, abs_tol_rel=1e-6, first_walk=0, batch_walks=0, expand=0,
-                       plain=0, gauss_is=0.0):
+                       plain=0, gauss_is=0.0, lattice=MW_LATTICE_VERTEX):
     """Capacitance-matrix rows for several masters (default: every net) in
     shared rounds.  Returns {"cap": (M, K) rows, "se": (M, K), "sym": (M, M)
     symmetrised block, "masters": list, "stats": dict}; master i uses seed + i."""
@@ -428,7 +434,7 @@ def frw_extract_matrix(structure, walks_per_master, seed=0, masters=None, n_cell
     sym = np.zeros((M, M))
     stats = frw_stats()
     opt = frw_options(n_cells, hybrid, expand, plain, target_rel_3sigma, abs_tol_rel, first_walk, batch_walks,
-                      gauss_is)
+                      gauss_is, lattice)
     _check(_lib.frw_extract_matrix(structure.handle, I32(M), _vp(m), U64(walks_per_master), U64(seed),
                                    ctypes.byref(opt), _vp(cap), _vp(se), _vp(sym), ctypes.byref(stats)))
     return {"cap": cap, "se": se, "sym": sym, "masters": [int(x) for x in m], "stats": stats.as_dict()}
@@ -459,8 +465,9 @@ class Server:
     """Request loop over the device (mw_server_*): submit structures, poll rows."""
 
     def __init__(self, hbm_budget_bytes, n_cells=16, hybrid=1, target_rel_3sigma=0.0,
-                 abs_tol_rel=1e-6, expand=0, plain=0, gauss_is=0.0):
-        opt = frw_options(n_cells, hybrid, expand, plain, target_rel_3sigma, abs_tol_rel, 0, 0, gauss_is)
+                 abs_tol_rel=1e-6, expand=0, plain=0, gauss_is=0.0, lattice=MW_LATTICE_VERTEX):
+        opt = frw_options(n_cells, hybrid, expand, plain, target_rel_3sigma, abs_tol_rel, 0, 0, gauss_is,
+                          lattice)
         h = ctypes.c_void_p()
         _check(_lib.mw_server_create(ctypes.c_size_t(int(hbm_budget_bytes)), ctypes.byref(opt),
                                      ctypes.byref(h)))

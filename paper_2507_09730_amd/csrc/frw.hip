@@ -67,6 +67,7 @@ struct StructDev {
     const float4* diel_hi;  // xyz hi, w = vertex cell code (bits)
     const float* layer_z0;
     const uint32_t* layer_code;
+    const uint32_t* layer_eps;  // layer permittivities as float bits (cell lattice)
     float wlo[3], whi[3];
     int32_t bc[6];
     // uniform grid
@@ -488,21 +489,26 @@ __device__ __forceinline__ void layer_walk(Z z0, C lcode, int nl, float zlo, flo
 // gd_off[cell + 1]) read ahead by the caller (ordinary cubes only).
 // marked: only the list entries b + i for the set bits i of marks are
 // visited (the boxes exp_fit found touching this cube).
-template <class SR>
+// CELL: a cube of the cell-centred lattice (n odd): the region codes are the
+// permittivities (float bits) and the mask rows lie n + 1 apart, so that
+// every axis starts on a dword (the extra row past the last cell repeats the
+// last cell's mask and is never read as a cell).
+template <bool CELL = false, class SR>
 __device__ __forceinline__ CubeInfo build_cube(SR& S, int cell, float3 c, float R, int n, LaneCube L,
                                               bool expanded = false, const uint32_t* lt = nullptr,
                                               const uint2* dr = nullptr, bool marked = false,
                                               unsigned long long marks = 0ull) {
     CubeInfo info{};
+    const int ns = CELL ? n + 1 : n;  // mask row stride (even)
     const float h = 2.f * R / (float)n;
     const float lo0[3] = {c.x - R, c.y - R, c.z - R};
-    LAS uint32_t* mask32 = reinterpret_cast<LAS uint32_t*>(L.mask);  // 3n is even
-    for (int q = 0; q < 3 * n / 2; ++q) mask32[q] = 0u;
+    LAS uint32_t* mask32 = reinterpret_cast<LAS uint32_t*>(L.mask);  // 3 ns is even
+    for (int q = 0; q < 3 * ns / 2; ++q) mask32[q] = 0u;
     // background layer of every z cell: layer(k) = #{q >= 1 : z_k >= z0[q]}
     // for the cell centre z_k (layer_z0 ascends)
     int lmin, lmax;
     const GAS float* z0 = gp(S.layer_z0);
-    const GAS uint32_t* lcode = gp(S.layer_code);
+    const GAS uint32_t* lcode = gp(CELL ? S.layer_eps : S.layer_code);
     const bool zfold = (S.bc[4] == MW_BC_NEUMANN && lo0[2] < S.wlo[2]) ||
                        (S.bc[5] == MW_BC_NEUMANN && lo0[2] + 2.f * R > S.whi[2]);
     if (!zfold && lt) {
@@ -553,7 +559,7 @@ __device__ __forceinline__ CubeInfo build_cube(SR& S, int cell, float3 c, float 
             return false;
         }
         const uint16_t bit = (uint16_t)(1u << nbits);
-        L.codes[MAX_REGIONS - 1 - nbits] = __float_as_uint(bhi.w);
+        L.codes[MAX_REGIONS - 1 - nbits] = __float_as_uint(CELL ? blo.w : bhi.w);
         ++nbits;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -565,15 +571,15 @@ __device__ __forceinline__ CubeInfo build_cube(SR& S, int cell, float3 c, float 
                 const float f1 = fminf(fmaxf((bh[a] - lo0[a]) * inv_h - 0.5f, -1.f), (float)n + 1.f);
                 const int i0 = max((int)ceilf(f0), 0), i1 = min((int)ceilf(f1), n);
                 if (i0 < i1) {
-                    toggle16(L.mask, a * n + i0, bit);
-                    if (i1 < n) toggle16(L.mask, a * n + i1, bit);
+                    toggle16(L.mask, a * ns + i0, bit);
+                    if (i1 < n) toggle16(L.mask, a * ns + i1, bit);
                 }
             } else {
                 bool prev = false;
                 for (int i = 0; i < n; ++i) {
                     const float x = fold(S, a, lo0[a] + ((float)i + 0.5f) * h);
                     const bool in = x >= bl[a] && x < bh[a];
-                    if (in != prev) toggle16(L.mask, a * n + i, bit);
+                    if (in != prev) toggle16(L.mask, a * ns + i, bit);
                     prev = in;
                 }
             }
@@ -587,16 +593,16 @@ __device__ __forceinline__ CubeInfo build_cube(SR& S, int cell, float3 c, float 
     // toggles -> masks (prefix xor along each axis); aggregate masks:
     // present boxes and boxes spanning all cells per axis
     uint32_t O[3];
-    // two cells per dword (n is even, so every axis starts on a dword)
+    // two cells per dword (ns is even, so every axis starts on a dword)
     auto prefix = [&](int a, int i, uint32_t w, uint32_t& m, uint32_t& A, uint32_t& Oa) {
         const uint32_t m0 = m ^ (w & 0xffffu);
         const uint32_t m1 = m0 ^ (w >> 16);
-        mask32[a * (n / 2) + i] = m0 | (m1 << 16);
+        mask32[a * (ns / 2) + i] = m0 | (m1 << 16);
         A &= m0 & m1;
         Oa |= m0 | m1;
         m = m1;
     };
-    if (n == 16) {
+    if (ns == 16) {
         // all 24 dwords are read before any is written back: one LDS round
         // trip instead of one per dword
         uint32_t w[24];
@@ -614,7 +620,7 @@ __device__ __forceinline__ CubeInfo build_cube(SR& S, int cell, float3 c, float 
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             uint32_t A = 0xffffu, Oa = 0, m = 0;
-            for (int i = 0; i < n / 2; ++i) prefix(a, i, mask32[a * (n / 2) + i], m, A, Oa);
+            for (int i = 0; i < ns / 2; ++i) prefix(a, i, mask32[a * (ns / 2) + i], m, A, Oa);
             info.A[a] = A;
             O[a] = Oa;
         }
@@ -842,9 +848,63 @@ __device__ __forceinline__ bool stratified_along(const CubeInfo& I, int s) {
     return f1 && f2;
 }
 
-// Code of plane p normal to s of a cube stratified along s.
-__device__ __forceinline__ uint32_t plane_code(LaneCube L, const CubeInfo& I, int n, int s, int p) {
-    return cell_code(L, L.mask[s * n + p] & I.present, L.bz[s == 2 ? p : 0]);
+// Code of plane p normal to s of a cube stratified along s (ns: the mask
+// row stride; the permittivity bits on the cell lattice).
+__device__ __forceinline__ uint32_t plane_code(LaneCube L, const CubeInfo& I, int ns, int s, int p) {
+    return cell_code(L, L.mask[s * ns + p] & I.present, L.bz[s == 2 ? p : 0]);
+}
+
+// Cell lattice (n odd, mask rows ns = n + 1 apart): mean permittivity of
+// each plane normal to a, rounded to float, written as float bits to
+// out[0..n).  Cells are summed by runs of equal masks (and background) in
+// binary64; every partial sum is exact (at most 2^10 cells of permittivity
+// in [1e-3, 1e3] times run lengths below 2^5), so the result does not depend
+// on the order.
+__device__ void plane_mean_eps(LaneCube L, int n, int a, LAS uint32_t* out) {
+    const int ns = n + 1;
+    const int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
+    uint32_t ubnd = 1u, vbnd = 1u;
+    {
+        uint32_t pu = L.mask[u * ns], pv = L.mask[v * ns], pb = a == 2 ? 0u : L.bz[0];
+        for (int i = 1; i < n; ++i) {
+            const uint32_t cu = L.mask[u * ns + i], cv = L.mask[v * ns + i], cb = a == 2 ? 0u : L.bz[i];
+            ubnd |= (cu != pu ? 1u : 0u) << i;
+            vbnd |= (cv != pv || cb != pb ? 1u : 0u) << i;
+            pu = cu;
+            pv = cv;
+            pb = cb;
+        }
+    }
+    const double area = (double)(n * n);
+    uint32_t prev_ma = 0xffffffffu, prev_b = 0, prev = 0;
+    for (int p = 0; p < n; ++p) {
+        const uint32_t ma = L.mask[a * ns + p];
+        const uint32_t bp = a == 2 ? L.bz[p] : 0u;
+        if (ma == prev_ma && bp == prev_b) {
+            out[p] = prev;
+            continue;
+        }
+        double sum = 0.0;
+        for (uint32_t ur = ubnd; ur;) {
+            const int i = __builtin_ctz(ur);
+            ur &= ur - 1u;
+            const int li = (ur ? __builtin_ctz(ur) : n) - i;
+            const uint32_t mau = ma & L.mask[u * ns + i];
+            double row = 0.0;
+            for (uint32_t vr = vbnd; vr;) {
+                const int j = __builtin_ctz(vr);
+                vr &= vr - 1u;
+                const int lj = (vr ? __builtin_ctz(vr) : n) - j;
+                const uint32_t bv = a == 2 ? bp : L.bz[j];
+                row += (double)lj * (double)__uint_as_float(cell_code(L, mau & L.mask[v * ns + j], bv));
+            }
+            sum += (double)li * row;
+        }
+        prev_ma = ma;
+        prev_b = bp;
+        prev = __float_as_uint((float)(sum / area));
+        out[p] = prev;
+    }
 }
 
 // Mean codes of the planes normal to a (rounded half to even) written to
@@ -1057,6 +1117,28 @@ __device__ __forceinline__ void node_of_hit(int n, int b, int node[3]) {
     node[2] = ax == 2 ? face : bb;
 }
 
+// Where a cell-lattice walk leaves cube (c, R): cell coordinates (i, j, k)
+// with one of them -1 or n name the boundary panel, whose centre is returned.
+__device__ __forceinline__ float3 cell_exit_point(float3 c, float R, float h, int n, int i, int j, int k) {
+    auto coord = [&](float cc, int q) {
+        return q < 0 ? cc - R : (q >= n ? cc + R : cc - R + ((float)q + 0.5f) * h);
+    };
+    return make_float3(coord(c.x, i), coord(c.y, j), coord(c.z, k));
+}
+
+// Cell coordinates (one of them -1 or n) of boundary panel b of the cell
+// lattice, hit index (2 ax + side) n^2 + b1 n + a1 with (a1, b1) the panel's
+// cells along the two other axes in ascending order.
+__device__ __forceinline__ void cell_panel_of_hit(int n, int b, int* i, int* j, int* k) {
+    const int f = b / (n * n), rem = b - f * n * n;
+    const int b1 = rem / n, a1 = rem - b1 * n;
+    const int ax = f >> 1, side = f & 1;
+    const int out = side ? n : -1;
+    *i = ax == 0 ? out : a1;
+    *j = ax == 1 ? out : (ax == 0 ? a1 : b1);
+    *k = ax == 2 ? out : b1;
+}
+
 // Looks up (or queues) the table of the key in key[0 .. C.key_words);
 // out[0] = status, out[1] = table index.
 __global__ void key_table_kernel(CacheDev C, const uint32_t* key, uint32_t* out) {
@@ -1069,11 +1151,17 @@ __global__ void key_table_kernel(CacheDev C, const uint32_t* key, uint32_t* out)
 }
 
 // Looks up (or queues) the hop table of the uniform cube; out[0] = status,
-// out[1] = table index.
+// out[1] = table index.  Its exit distribution does not depend on the
+// permittivity: the key holds code 1 (vertex lattice) or permittivity 1
+// (cell lattice, odd n) in every plane.
 __global__ void uniform_table_kernel(CacheDev C, int n, uint32_t* out) {
     if (threadIdx.x || blockIdx.x) return;
     uint32_t idx = NO_INDEX;
-    auto key = [&](uint32_t q) { return q == 1 ? (uint32_t)n : (q == 2 ? 2u : (q < KEY_HDR ? 0u : 1u)); };
+    const bool cell = (n & 1) != 0;
+    auto key = [&](uint32_t q) {
+        if (q == 0) return cell ? 2u : 0u;
+        return q == 1 ? (uint32_t)n : (q == 2 ? 2u : (q < KEY_HDR ? 0u : (cell ? 0x3f800000u : 1u)));
+    };
     const int res = lookup_or_insert(C, key, key_hash(C.key_words, key), &idx);
     out[0] = (uint32_t)res;
     out[1] = idx;
@@ -1088,14 +1176,16 @@ __global__ void uniform_table_kernel(CacheDev C, int n, uint32_t* out) {
 // -------------------------------------------------------------------------
 __device__ __forceinline__ float sel3(float3 v, int a) { return a == 0 ? v.x : (a == 1 ? v.y : v.z); }
 
-template <bool MULTI>
+// CELL: cubes of the cell-centred lattice (n odd).
+template <bool MULTI, bool CELL = false>
 __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
     extern __shared__ uint32_t lds[];
     if (A.dev_round && A.ctr->need_first == 0u) return;
     const int n = A.n;
+    const int ns = CELL ? n + 1 : n;  // mask row stride
     uint32_t* my = lds + threadIdx.x * A.lane_stride;
-    const LaneCube L = lane_cube(my, n);
-    LAS uint32_t* kbuf = L.bz + n;
+    const LaneCube L = lane_cube(my, ns);
+    LAS uint32_t* kbuf = L.bz + ns;
     unsigned long long c_br[4] = {0, 0, 0, 0}, c_halved = 0;
     uint32_t err = 0, missing = 0;
     // one structure per launch: its layer table goes to LDS once
@@ -1105,8 +1195,8 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         if (A.S0.n_layers <= LAYER_LDS) {
             if (threadIdx.x < 2 * LAYER_LDS) {
                 const int q = min((int)(threadIdx.x % LAYER_LDS), A.S0.n_layers - 1);
-                lt_lds[threadIdx.x] =
-                    threadIdx.x < LAYER_LDS ? __float_as_uint(gp(A.S0.layer_z0)[q]) : gp(A.S0.layer_code)[q];
+                lt_lds[threadIdx.x] = threadIdx.x < LAYER_LDS ? __float_as_uint(gp(A.S0.layer_z0)[q])
+                                                              : gp(CELL ? A.S0.layer_eps : A.S0.layer_code)[q];
             }
             lt = lt_lds;
         }
@@ -1178,11 +1268,11 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         float R = fminf(query_dist(S, c, cell, &who), G.g);
         // FirstTransition: cube touching the master (Sec. III-C, Fig. 4
         // branches; homogenised along the normal when not stratified)
-        CubeInfo I = build_cube(S, cell, c, R, n, L, false, lt, &drange);
+        CubeInfo I = build_cube<CELL>(S, cell, c, R, n, L, false, lt, &drange);
         const bool halved = I.overflow;
         for (int it = 0; it < 40 && I.overflow; ++it) {
             R *= 0.5f;  // capacity rule: halve while more than 16 boxes touch
-            I = build_cube(S, cell, c, R, n, L, false, lt, &drange);
+            I = build_cube<CELL>(S, cell, c, R, n, L, false, lt, &drange);
         }
         if (I.overflow) {
             err |= ERR_REGIONS;
@@ -1205,14 +1295,18 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
             br = 3;
             sax = a_norm;
         }
-        kbuf[0] = 1u;  // first-transition table
+        kbuf[0] = CELL ? 3u : 1u;  // first-transition table (of the cell lattice)
         kbuf[1] = (uint32_t)n;
         kbuf[2] = (uint32_t)sax;
         kbuf[3] = (uint32_t)a_norm;
-        if (br == 3)
-            plane_mean_codes(L, n, a_norm, kbuf + KEY_HDR);
-        else
-            for (int p = 0; p < n; ++p) kbuf[KEY_HDR + p] = plane_code(L, I, n, sax, p);
+        if (br == 3) {
+            if (CELL)
+                plane_mean_eps(L, n, a_norm, kbuf + KEY_HDR);
+            else
+                plane_mean_codes(L, n, a_norm, kbuf + KEY_HDR);
+        } else {
+            for (int p = 0; p < n; ++p) kbuf[KEY_HDR + p] = plane_code(L, I, ns, sax, p);
+        }
         uint32_t idx, glo = 0, ghi = 0;
         const Rand4 r2 = philox10(0u, 0u, (uint32_t)walk, ctr_hi(walk, PURPOSE_FIRST), SG.k0, SG.k1);
         auto key = [&](uint32_t q) { return kbuf[q]; };
@@ -1238,9 +1332,16 @@ __global__ void __launch_bounds__(FRW_THREADS) first_kernel(FirstArgs A) {
         float sgn = sb ? 1.f : -1.f;
         if (!side) sgn = -sgn;
         const float omega = EPS0 * factor * (Kh / h) * sgn;
-        int nd[3];
-        node_of_hit(n, b, nd);
-        const float3 x = make_float3(c.x - R + (float)nd[0] * h, c.y - R + (float)nd[1] * h, c.z - R + (float)nd[2] * h);
+        float3 x;
+        if (CELL) {
+            int ci, cj, ck;
+            cell_panel_of_hit(n, b, &ci, &cj, &ck);
+            x = cell_exit_point(c, R, h, n, ci, cj, ck);
+        } else {
+            int nd[3];
+            node_of_hit(n, b, nd);
+            x = make_float3(c.x - R + (float)nd[0] * h, c.y - R + (float)nd[1] * h, c.z - R + (float)nd[2] * h);
+        }
         const float3 xf = fold3(S, x);
         stf4(SG.first_state + k, make_float4(xf.x, xf.y, xf.z, omega));
         gpw(SG.first_done)[k] = 1u;
@@ -1405,6 +1506,71 @@ __device__ __forceinline__ bool mw_block(MwState& M, LaneCube L, int n, const Ra
             M.mz1 = ax == 2 ? hi : M.mz1;
             M.bz0 = ax == 2 ? zlo : M.bz0;
             M.bz1 = ax == 2 ? zhi : M.bz1;
+        }
+    }
+    return alive;
+}
+
+// -------------------------------------------------------------------------
+// MicroWalk on the cell-centred lattice of Sec. III-A (nodes at the voxel
+// centres; n odd, mask rows ns = n + 1 apart).  The walk stands on cell
+// (ni, nj, nk) and starts in the centre cell.  The Eq. (6) coefficient
+// towards a neighbour cell is eps_nb / (eps_nb + eps_v), kept as
+// rint(. * 2^24) of a binary64 division (exactly 2^23 for equal
+// permittivities), and 2^24 towards a boundary panel; the walk leaves the
+// cube at the centre of that panel.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t cell_eps_at(LaneCube L, int ns, int i, int j, int k) {
+    return cell_code(L, (uint32_t)L.mask[i] & L.mask[ns + j] & L.mask[2 * ns + k], L.bz[k]);
+}
+
+__device__ __forceinline__ uint32_t eq6_code(uint32_t nb, uint32_t v) {
+    if (nb == v) return 1u << 23;
+    const double e = (double)__uint_as_float(nb), ev = (double)__uint_as_float(v);
+    return (uint32_t)rint(e / (e + ev) * 16777216.0);
+}
+
+__device__ __forceinline__ void mw_begin_cell(MwState& M, int n) {
+    M.ni = M.nj = M.nk = (n - 1) / 2;
+    M.s = 0;
+}
+
+// Up to four steps with the four words of one Philox block; false once the
+// walk has left the cube (one coordinate is then -1 or n).
+__device__ __forceinline__ bool mw_block_cell(MwState& M, LaneCube L, int n, const Rand4& r) {
+    const int ns = n + 1;
+    const uint32_t us[4] = {r.x, r.y, r.z, r.w};
+    constexpr uint32_t PANEL = 1u << 24;
+    bool alive = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (alive) {
+            const int i = M.ni, j = M.nj, k = M.nk;
+            // neighbour indices clamped into the cube: a link out of it goes
+            // to a boundary panel whatever the read returns
+            const int im = max(i - 1, 0), ip = min(i + 1, n - 1);
+            const int jm = max(j - 1, 0), jp = min(j + 1, n - 1);
+            const int km = max(k - 1, 0), kp = min(k + 1, n - 1);
+            const uint32_t ev = cell_eps_at(L, ns, i, j, k);
+            const uint32_t g0 = i > 0 ? eq6_code(cell_eps_at(L, ns, im, j, k), ev) : PANEL;
+            const uint32_t g1 = i < n - 1 ? eq6_code(cell_eps_at(L, ns, ip, j, k), ev) : PANEL;
+            const uint32_t g2 = j > 0 ? eq6_code(cell_eps_at(L, ns, i, jm, k), ev) : PANEL;
+            const uint32_t g3 = j < n - 1 ? eq6_code(cell_eps_at(L, ns, i, jp, k), ev) : PANEL;
+            const uint32_t g4 = k > 0 ? eq6_code(cell_eps_at(L, ns, i, j, km), ev) : PANEL;
+            const uint32_t g5 = k < n - 1 ? eq6_code(cell_eps_at(L, ns, i, j, kp), ev) : PANEL;
+            // prefix sums (at most 6 * 2^24) and the move #{k < 5 : xq >= S_k}
+            const uint32_t S0 = g0, S1 = S0 + g1, S2 = S1 + g2, S3 = S2 + g3, S4 = S3 + g4, S5 = S4 + g5;
+            const uint32_t xq = __umulhi(us[q], S5);
+            const uint32_t d = (uint32_t)(xq >= S0) + (uint32_t)(xq >= S1) + (uint32_t)(xq >= S2) +
+                               (uint32_t)(xq >= S3) + (uint32_t)(xq >= S4);
+            const int ax = (int)(d >> 1);
+            const int dir = (d & 1u) ? 1 : -1;
+            ++M.s;
+            M.ni += ax == 0 ? dir : 0;
+            M.nj += ax == 1 ? dir : 0;
+            M.nk += ax == 2 ? dir : 0;
+            const int cnew = ax == 0 ? M.ni : (ax == 1 ? M.nj : M.nk);
+            alive = cnew >= 0 && cnew < n;
         }
     }
     return alive;
@@ -1742,19 +1908,22 @@ __device__ __forceinline__ decltype(auto) walk_struct(const WalkArgs& A, const G
 
 // EXP: MicroWalk hops use expanded cubes (MicroWalk-E).
 // N16: ordinary MicroWalk reads cell codes as cell_code16 (n <= 16).
-template <bool MULTI, bool EXP, bool N16 = false>
+// CELL: every cube on the cell-centred lattice (n odd; plain MicroWalk).
+template <bool MULTI, bool EXP, bool N16 = false, bool CELL = false>
 // three resident waves per SIMD (at most 168 VGPRs) for the plain MicroWalk
 // kernels, whose LDS allows 11 waves per compute unit; two for MicroWalk-E
 __global__ void __launch_bounds__(WALK_THREADS) __attribute__((amdgpu_waves_per_eu(EXP ? 2 : 3)))
 frw_walk_kernel(WalkArgs A) {
+    static_assert(!(CELL && (EXP || N16)), "the cell lattice runs plain MicroWalk steps of its own");
     extern __shared__ uint32_t lds[];
     const int n = A.n;
+    const int ns = CELL ? n + 1 : n;  // mask row stride
     const int lane = threadIdx.x & 63;
     // a launch with no parked walk to resume and no fresh walk left (a
     // device-driven round after a run that finished) ends at once
     if (A.ctr->launch_idle) return;
     uint32_t* my = lds + threadIdx.x * A.lane_stride;
-    const LaneCube L = lane_cube(my, n);
+    const LaneCube L = lane_cube(my, ns);
     const LaneExp E = lane_exp(my, n);  // used by EXP kernels only
 
     Counters& K = *A.ctr;
@@ -1768,7 +1937,8 @@ frw_walk_kernel(WalkArgs A) {
         if (S0.n_layers <= LAYER_LDS) {
             if (threadIdx.x < 2 * LAYER_LDS) {
                 const int q = min((int)(threadIdx.x % LAYER_LDS), S0.n_layers - 1);
-                lt_lds[threadIdx.x] = threadIdx.x < LAYER_LDS ? __float_as_uint(gp(S0.layer_z0)[q]) : gp(S0.layer_code)[q];
+                lt_lds[threadIdx.x] = threadIdx.x < LAYER_LDS ? __float_as_uint(gp(S0.layer_z0)[q])
+                                                              : gp(CELL ? S0.layer_eps : S0.layer_code)[q];
             }
             lt = lt_lds;
         }
@@ -1923,11 +2093,11 @@ frw_walk_kernel(WalkArgs A) {
                 }
             }
             if (!done) {
-                CubeInfo I = build_cube(S, cell, c, R, n, L, false, lt, &drange);
+                CubeInfo I = build_cube<CELL>(S, cell, c, R, n, L, false, lt, &drange);
                 const bool halved = I.overflow;
                 for (int it = 0; it < 40 && I.overflow; ++it) {
                     R *= 0.5f;  // capacity rule: halve while more than 16 boxes touch
-                    I = build_cube(S, cell, c, R, n, L, false, lt, &drange);
+                    I = build_cube<CELL>(S, cell, c, R, n, L, false, lt, &drange);
                 }
                 if (I.overflow) {
                     // more than 16 boxes overlap at this point: the call fails
@@ -1941,8 +2111,9 @@ frw_walk_kernel(WalkArgs A) {
                     ++c_cls[I.cls];
                     if (A.hybrid && I.cls <= 1) {
                         const int sax = I.axis;
-                        // hop table key: (0, n, axis, 0, plane codes); every
-                        // uniform cube shares one table
+                        // hop table key: (0, n, axis, 0, plane codes), or
+                        // (2, n, axis, 0, plane permittivities) on the cell
+                        // lattice; every uniform cube shares one table
                         uint32_t idx = A.uniform_index;
                         int res = LOOKUP_HIT;
                         const Rand4 r = philox10(0u, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_TABLE), wk0, wk1);
@@ -1952,12 +2123,12 @@ frw_walk_kernel(WalkArgs A) {
                             // codes (the cube is not used after this hop),
                             // hashed as they are formed
                             uint32_t hsh = KEY_HASH_SEED;
-                            hsh = key_hash_step(hsh, 0u);
+                            hsh = key_hash_step(hsh, CELL ? 2u : 0u);
                             hsh = key_hash_step(hsh, (uint32_t)n);
                             hsh = key_hash_step(hsh, (uint32_t)sax);
                             hsh = key_hash_step(hsh, 0u);
                             const uint32_t b0 = L.bz[0];
-                            if (n == 16) {
+                            if (!CELL && n == 16) {
                                 // eight planes at a time: their mask words,
                                 // background codes and box codes each in one
                                 // LDS round trip
@@ -1983,7 +2154,7 @@ frw_walk_kernel(WalkArgs A) {
 #pragma unroll 4
                                 for (int p = 0; p < n; ++p) {
                                     const uint32_t pc =
-                                        cell_code(L, L.mask[sax * n + p] & I.present, sax == 2 ? L.bz[p] : b0);
+                                        cell_code(L, L.mask[sax * ns + p] & I.present, sax == 2 ? L.bz[p] : b0);
                                     L.bz[p] = pc;
                                     hsh = key_hash_step(hsh, pc);
                                 }
@@ -1992,6 +2163,7 @@ frw_walk_kernel(WalkArgs A) {
                             res = lookup_or_insert(
                                 A.cache,
                                 [&](uint32_t q) {
+                                    if (CELL && q == 0) return 2u;
                                     return q == 1 ? (uint32_t)n
                                                   : (q == 2 ? (uint32_t)sax : (q < KEY_HDR ? 0u : L.bz[q - KEY_HDR]));
                                 },
@@ -2011,10 +2183,16 @@ frw_walk_kernel(WalkArgs A) {
                                 ghi = tab[TAB_GUIDE + (r.x >> GUIDE_SHIFT) + 1];
                             }
                             const int b = table_sample_guided(tab, A.cache.nb, r.x, glo, ghi);
-                            int nd[3];
-                            node_of_hit(n, b, nd);
-                            x = make_float3(c.x - R + (float)nd[0] * h, c.y - R + (float)nd[1] * h,
-                                            c.z - R + (float)nd[2] * h);
+                            if (CELL) {
+                                int ci, cj, ck;
+                                cell_panel_of_hit(n, b, &ci, &cj, &ck);
+                                x = cell_exit_point(c, R, h, n, ci, cj, ck);
+                            } else {
+                                int nd[3];
+                                node_of_hit(n, b, nd);
+                                x = make_float3(c.x - R + (float)nd[0] * h, c.y - R + (float)nd[1] * h,
+                                                c.z - R + (float)nd[2] * h);
+                            }
                             pos = fold3(S, x);
                             ++t;
                             if (A.plain) phase = PH_PARK;
@@ -2052,6 +2230,9 @@ frw_walk_kernel(WalkArgs A) {
                             else
                                 mw_begin(M, L, n);
                             mw_begin_e(M, Q, E, n);
+                        } else if (CELL) {
+                            c_halved += halved ? 1ull : 0ull;
+                            mw_begin_cell(M, n);
                         } else if (N16) {
                             c_halved += halved ? 1ull : 0ull;
                             mw_begin16(M, L, n);
@@ -2109,7 +2290,10 @@ frw_walk_kernel(WalkArgs A) {
                     const Rand4 r0 = philox10(b0, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), wk0, wk1);
                     const Rand4 r1 = philox10(b0 + 1, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), wk0, wk1);
                     bool in;
-                    if (N16) {
+                    if (CELL) {
+                        in = mw_block_cell(M, L, n, r0);
+                        if (in) in = mw_block_cell(M, L, n, r1);
+                    } else if (N16) {
                         in = mw_block16(M, L, n, r0);
                         if (in) in = mw_block16(M, L, n, r1);
                     } else {
@@ -2137,8 +2321,9 @@ frw_walk_kernel(WalkArgs A) {
                 } else if (!alive) {
                     c_steps += M.s;
                     const float h = 2.f * mR / (float)n;
-                    const float3 xx = make_float3(mc.x - mR + (float)M.ni * h, mc.y - mR + (float)M.nj * h,
-                                                  mc.z - mR + (float)M.nk * h);
+                    const float3 xx = CELL ? cell_exit_point(mc, mR, h, n, M.ni, M.nj, M.nk)
+                                           : make_float3(mc.x - mR + (float)M.ni * h, mc.y - mR + (float)M.nj * h,
+                                                         mc.z - mR + (float)M.nk * h);
                     pos = fold3(walk_struct<MULTI>(A, SG), xx);
                     ++t;
                     phase = A.plain ? PH_PARK : PH_NEED;
@@ -2221,7 +2406,14 @@ __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const
                                  uint32_t ready_value) {
     const uint32_t* key = C.keys + (size_t)idx * C.key_stride;
     const int kind = (int)key[0], n = (int)key[1], s = (int)key[2], anorm = (int)key[3];
-    const int M = n - 1, M2 = M * M, nb = 6 * M2;
+    // kind: bit 0 first transition, bit 1 cell-centred lattice.  Vertex
+    // lattice: M = n - 1 interior nodes per axis, Dirichlet sine basis.  Cell
+    // lattice (n odd): M = n cells per axis; the boundary panel sits half a
+    // cell away, which doubles the last in-plane link and makes the in-plane
+    // operator the one the DST-II basis sin(pi (m + 1) (p + 1/2) / n)
+    // diagonalises (eigenvalues 2 - 2 cos(pi (m + 1) / n)).
+    const bool first = (kind & 1) != 0, cellk = (kind & 2) != 0;
+    const int M = cellk ? n : n - 1, M2 = M * M, nb = 6 * M2;
     double* Sm = W.Sm;
     double* lam = W.lam;
     double* cr = W.cr;
@@ -2230,27 +2422,56 @@ __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const
     double* tmp = W.tmp;
     double* zh = W.zh;
     double* Pout = zh + (size_t)3 * M * M2;  // [src][nb]
-    const double norm = sqrt(2.0 / (double)(M + 1));
-    for (int q = tid; q < M2; q += NT) {
-        const int m = q / M + 1, p = q % M + 1;
-        Sm[q] = norm * sin(M_PI * (double)(m * p) / (double)(M + 1));
-    }
-    if (tid < M) lam[tid] = 2.0 - 2.0 * cos(M_PI * (double)(tid + 1) / (double)(M + 1));
-    if (tid >= 1 && tid <= M) {
-        const int r = tid;
-        const double em = (double)key[KEY_HDR + r - 1], ep = (double)key[KEY_HDR + r];
-        cr[r] = 2.0 * (em + ep);
-        ar[r] = 4.0 * em;
-        br[r] = 4.0 * ep;
+    if (!cellk) {
+        const double norm = sqrt(2.0 / (double)(M + 1));
+        for (int q = tid; q < M2; q += NT) {
+            const int m = q / M + 1, p = q % M + 1;
+            Sm[q] = norm * sin(M_PI * (double)(m * p) / (double)(M + 1));
+        }
+        if (tid < M) lam[tid] = 2.0 - 2.0 * cos(M_PI * (double)(tid + 1) / (double)(M + 1));
+        if (tid >= 1 && tid <= M) {
+            const int r = tid;
+            const double em = (double)key[KEY_HDR + r - 1], ep = (double)key[KEY_HDR + r];
+            cr[r] = 2.0 * (em + ep);
+            ar[r] = 4.0 * em;
+            br[r] = 4.0 * ep;
+        }
+    } else {
+        // Sm[mode * M + cell]; the last mode is normalised by sqrt(1 / n)
+        for (int q = tid; q < M2; q += NT) {
+            const int m = q / M, p = q % M;
+            const double norm = sqrt((m == M - 1 ? 1.0 : 2.0) / (double)M);
+            Sm[q] = norm * sin(M_PI * (double)(m + 1) * ((double)p + 0.5) / (double)M);
+        }
+        if (tid < M) lam[tid] = 2.0 - 2.0 * cos(M_PI * (double)(tid + 1) / (double)M);
+        if (tid >= 1 && tid <= M) {
+            // plane r (1-based): in-plane links 2^23 (equal permittivities),
+            // Eq. (6) codes to the planes below and above, 2^24 to a panel
+            const int r = tid;
+            const double ev = (double)__uint_as_float(key[KEY_HDR + r - 1]);
+            cr[r] = 8388608.0;
+            if (r == 1) {
+                ar[r] = 16777216.0;
+            } else {
+                const double e = (double)__uint_as_float(key[KEY_HDR + r - 2]);
+                ar[r] = key[KEY_HDR + r - 2] == key[KEY_HDR + r - 1] ? 8388608.0 : rint(e / (e + ev) * 16777216.0);
+            }
+            if (r == M) {
+                br[r] = 16777216.0;
+            } else {
+                const double e = (double)__uint_as_float(key[KEY_HDR + r]);
+                br[r] = key[KEY_HDR + r] == key[KEY_HDR + r - 1] ? 8388608.0 : rint(e / (e + ev) * 16777216.0);
+            }
+        }
     }
     sync();
     // local frame: w = s, (u, v) the other two axes ascending
     const int ua = s == 0 ? 1 : 0, va = s == 2 ? 1 : 2;
-    const int c0 = n / 2;
+    const int c0 = cellk ? (n - 1) / 2 + 1 : n / 2;  // centre node or cell, 1-based
     int src[3][3];
-    int nsrc = kind == 1 ? 3 : 1;
+    int nsrc = first ? 3 : 1;
     for (int q = 0; q < 3; ++q) src[q][0] = src[q][1] = src[q][2] = c0;  // (p, q, r) local
-    if (kind == 1) {
+    if (first) {
         const int lax = anorm == s ? 2 : (anorm == ua ? 0 : 1);
         src[1][lax] += 1;
         src[2][lax] -= 1;
@@ -2264,13 +2485,16 @@ __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const
             const double lm = lam[m] + lam[l];
             const double rhs0 = Sm[m * M + (p0 - 1)] * Sm[l * M + (q0 - 1)];
             double* col = zh + (size_t)sidx * M * M2 + ml;  // stride M2 over r
-            // Thomas algorithm: forward elimination, then back substitution
+            // Thomas algorithm: forward elimination, then back substitution.
+            // The cell lattice's codes are not symmetric: its row of
+            // (D - G)^-1 solves the transposed system, whose off-diagonals
+            // are the neighbours' codes towards plane r.
             double cprev = 0.0, dprev = 0.0;
             #pragma unroll 1
             for (int r = 1; r <= M; ++r) {
                 const double diag = cr[r] * lm + ar[r] + br[r];
-                const double sub = r > 1 ? -ar[r] : 0.0;
-                const double sup = r < M ? -br[r] : 0.0;
+                const double sub = r > 1 ? -(cellk ? br[r - 1] : ar[r]) : 0.0;
+                const double sup = r < M ? -(cellk ? ar[r + 1] : br[r]) : 0.0;
                 const double den = diag - sub * cprev;
                 cvals[r] = sup / den;
                 dvals[r] = ((r == r0 ? rhs0 : 0.0) - sub * dprev) / den;
@@ -2289,6 +2513,9 @@ __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const
     }
     sync();
     // exit probabilities on the six faces, in global hit-index order
+    // (coordinates of boundary nodes 1..M on the vertex lattice, of the
+    // cells next to a panel 0..M-1 on the cell lattice)
+    const int o1 = cellk ? 0 : 1;
     for (int sidx = 0; sidx < nsrc; ++sidx) {
         const double* Z = zh + (size_t)sidx * M * M2;  // Z[(r-1)*M2 + m*M + l]
         double* P = Pout + (size_t)sidx * nb;
@@ -2312,12 +2539,12 @@ __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const
                 #pragma unroll 1
                 for (int m = 0; m < M; ++m) acc += Sm[m * M + p] * tmp[m * M + qq];
                 int g[3];
-                g[ua] = p + 1;
-                g[va] = qq + 1;
+                g[ua] = p + o1;
+                g[va] = qq + o1;
                 g[s] = side ? n : 0;
                 const int f = 2 * s + side;
                 const int oa = s == 0 ? 1 : 0, ob = s == 2 ? 1 : 2;
-                P[f * M2 + (g[ob] - 1) * M + (g[oa] - 1)] = link * acc;
+                P[f * M2 + (g[ob] - o1) * M + (g[oa] - o1)] = link * acc;
             }
             sync();
         }
@@ -2348,17 +2575,19 @@ __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const
                 for (int j = 0; j < M; ++j) acc += Sm[j * M + other] * tmp[j * M + r];
                 int g[3];
                 const int fa = ufaces ? ua : va;
-                g[s] = r + 1;
+                g[s] = r + o1;
                 if (ufaces) {
                     g[ua] = side ? n : 0;
-                    g[va] = other + 1;
+                    g[va] = other + o1;
                 } else {
                     g[va] = side ? n : 0;
-                    g[ua] = other + 1;
+                    g[ua] = other + o1;
                 }
                 const int f = 2 * fa + side;
                 const int oa = fa == 0 ? 1 : 0, ob = fa == 2 ? 1 : 2;
-                P[f * M2 + (g[ob] - 1) * M + (g[oa] - 1)] = cr[r + 1] * acc;
+                // the in-plane link into a panel: 2^24 on the cell lattice
+                const double link = cellk ? 2.0 * cr[r + 1] : cr[r + 1];
+                P[f * M2 + (g[ob] - o1) * M + (g[oa] - o1)] = link * acc;
             }
             sync();
         }
@@ -2366,16 +2595,31 @@ __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const
     sync();
     // weights -> CDF (one thread: sequential prefix sum in hit-index order)
     uint32_t* tab = C.data + (size_t)idx * C.tab_words;
-    if (kind == 1) {
+    if (first) {
         // flux kernel of the first transition along +anorm (Sec. II-A weight):
-        // w_b = [G+ (P^c - P^+) + G- (P^- - P^c)] / 2, in units of 1/h
+        // w_b = [G+ (P^c - P^+) + G- (P^- - P^c)] / 2, in units of 1/h, with
+        // G+- the permittivity of the links from the centre along +-anorm
+        // (cell lattice: the series combination of the two half cells)
         double Gp, Gm;
-        const double e0 = (double)key[KEY_HDR + c0 - 1], e1 = (double)key[KEY_HDR + c0];
-        if (anorm == s) {
-            Gp = e1 / 65536.0;
-            Gm = e0 / 65536.0;
+        if (cellk) {
+            const int cc = c0 - 1;  // centre plane, 0-based
+            const double ec = (double)__uint_as_float(key[KEY_HDR + cc]);
+            if (anorm == s) {
+                const double ep = (double)__uint_as_float(key[KEY_HDR + cc + 1]);
+                const double em = (double)__uint_as_float(key[KEY_HDR + cc - 1]);
+                Gp = 2.0 * ec * ep / (ec + ep);
+                Gm = 2.0 * ec * em / (ec + em);
+            } else {
+                Gp = Gm = ec;
+            }
         } else {
-            Gp = Gm = (e0 + e1) / (2.0 * 65536.0);
+            const double e0 = (double)key[KEY_HDR + c0 - 1], e1 = (double)key[KEY_HDR + c0];
+            if (anorm == s) {
+                Gp = e1 / 65536.0;
+                Gm = e0 / 65536.0;
+            } else {
+                Gp = Gm = (e0 + e1) / (2.0 * 65536.0);
+            }
         }
         const double* Pc = Pout;
         const double* Pp = Pout + nb;
@@ -2396,8 +2640,8 @@ __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const
     // by one thread, one thread scans the chunk sums, every chunk then
     // writes its thresholds ceil(cum / total * 2^32) (the last equals 2^32
     // exactly: the chunk sums are formed in the same order)
-    const double* wv = kind == 1 ? Pout + 3 * nb : Pout;
-    const bool absw = kind == 1;
+    const double* wv = first ? Pout + 3 * nb : Pout;
+    const bool absw = first;
     const int chunk = (nb + TB_THREADS - 1) / TB_THREADS;
     for (int ch = tid; ch < TB_THREADS; ch += NT) {
         const int b0 = ch * chunk, b1 = min(nb, b0 + chunk);
@@ -2438,7 +2682,7 @@ __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const
     }
     if (tid == 0) {
         tab[0] = (uint32_t)*W.last;
-        tab[1] = kind == 1 ? __float_as_uint((float)tot) : 0u;
+        tab[1] = first ? __float_as_uint((float)tot) : 0u;
     }
     sync();
     // guide[g] = first b with CDF[b] > g * 2^GUIDE_SHIFT (CDF nondecreasing)
@@ -3070,6 +3314,10 @@ struct Cache {
 std::mutex g_cache_mu;
 std::map<std::pair<int, int>, std::unique_ptr<Cache>> g_caches;
 
+// Boundary entries per face side of a table: interior nodes per axis on the
+// vertex lattice (n even), cells per axis on the cell lattice (n odd).
+uint32_t table_m(int n) { return (n & 1) ? (uint32_t)n : (uint32_t)(n - 1); }
+
 size_t env_size(const char* name, size_t dflt) {
     const char* v = getenv(name);
     return v ? (size_t)strtoull(v, nullptr, 10) : dflt;
@@ -3082,7 +3330,7 @@ Cache& get_cache(int n) {
     auto& slot = g_caches[{dev, n}];
     if (!slot) {
         auto c = std::make_unique<Cache>();
-        const uint32_t M = n - 1;
+        const uint32_t M = table_m(n);
         const uint32_t nb = 6 * M * M;
         const uint32_t cap = (uint32_t)env_size("MWALK_TABLE_CAP", 65536);
         uint32_t nslots = 1;
@@ -3261,8 +3509,11 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
             dhi[i] = make_float4(b.hi[0], b.hi[1], b.hi[2], cw);
         }
         std::vector<float> z0(D->layer_z0, D->layer_z0 + nl);
-        std::vector<uint32_t> lcode(nl);
-        for (int l = 0; l < nl; ++l) lcode[l] = (uint32_t)std::nearbyint((double)D->layer_eps[l] * 65536.0);
+        std::vector<uint32_t> lcode(nl), leps(nl);
+        for (int l = 0; l < nl; ++l) {
+            lcode[l] = (uint32_t)std::nearbyint((double)D->layer_eps[l] * 65536.0);
+            std::memcpy(&leps[l], &D->layer_eps[l], 4);
+        }
         // one allocation: arrays, then grid offsets/counts (lists sized after counting)
         size_t o = 0;
         auto sz = [&](size_t b) {
@@ -3271,7 +3522,7 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
             return r;
         };
         const size_t o_clo = sz(16 * nc), o_chi = sz(16 * nc), o_dlo = sz(16 * dlo.size()), o_dhi = sz(16 * dhi.size());
-        const size_t o_z0 = sz(4 * nl), o_lc = sz(4 * nl);
+        const size_t o_z0 = sz(4 * nl), o_lc = sz(4 * nl), o_le = sz(4 * nl);
         const size_t o_cc = sz(4 * ncells), o_dc = sz(4 * ncells), o_coff = sz(4 * (ncells + 1)),
                      o_doff = sz(4 * (ncells + 1));
         const size_t o_ecc = sz(4 * ncells), o_edc = sz(4 * ncells), o_eoff = sz(4 * (ncells + 1)),
@@ -3291,6 +3542,7 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
         MW_HIP(hipMemcpyAsync(m + o_dhi, dhi.data(), 16 * dhi.size(), hipMemcpyHostToDevice, ss));
         MW_HIP(hipMemcpyAsync(m + o_z0, z0.data(), 4 * nl, hipMemcpyHostToDevice, ss));
         MW_HIP(hipMemcpyAsync(m + o_lc, lcode.data(), 4 * nl, hipMemcpyHostToDevice, ss));
+        MW_HIP(hipMemcpyAsync(m + o_le, leps.data(), 4 * nl, hipMemcpyHostToDevice, ss));
         StructDev& S = st->h;
         S.n_cond = nc;
         S.n_nets = D->n_nets;
@@ -3302,6 +3554,7 @@ extern "C" mw_status mw_structure_create(const mw_structure_desc* D, mw_structur
         S.diel_hi = (const float4*)(m + o_dhi);
         S.layer_z0 = (const float*)(m + o_z0);
         S.layer_code = (const uint32_t*)(m + o_lc);
+        S.layer_eps = (const uint32_t*)(m + o_le);
         double diag = 0;
         for (int a = 0; a < 3; ++a) {
             S.wlo[a] = D->win_lo[a];
@@ -3423,8 +3676,10 @@ LaunchGeom launch_geom(int n) {
     g.cus = cus;
     // LDS per lane: axis masks + region codes (+ a key buffer for first
     // transitions); odd dword strides spread lanes over the banks
-    g.lane_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * n + 3) / 4) | 1u;
-    g.first_stride = (uint32_t)((6 * n + 4 * MAX_REGIONS + 4 * n + 4 * (KEY_HDR + n) + 3) / 4) | 1u;
+    // (cell lattice, odd n: mask rows n + 1 apart)
+    const int ns = n + (n & 1);
+    g.lane_stride = (uint32_t)((6 * ns + 4 * MAX_REGIONS + 4 * ns + 3) / 4) | 1u;
+    g.first_stride = (uint32_t)((6 * ns + 4 * MAX_REGIONS + 4 * ns + 4 * (KEY_HDR + n) + 3) / 4) | 1u;
     // (+ the walker's LDS copy of the layer table)
     g.lds = (size_t)g.lane_stride * 4 * WALK_THREADS + 4 * 2 * LAYER_LDS;
     g.first_lds = (size_t)g.first_stride * 4 * FRW_THREADS + 4 * 2 * LAYER_LDS;
@@ -3518,6 +3773,10 @@ struct Runner {
         set_lds(frw_walk_kernel<true, true, true>, g.lds_e);
         set_lds(first_kernel<false>, g.first_lds);
         set_lds(first_kernel<true>, g.first_lds);
+        set_lds(frw_walk_kernel<false, false, false, true>, g.lds);
+        set_lds(frw_walk_kernel<true, false, false, true>, g.lds);
+        set_lds(first_kernel<false, true>, g.first_lds);
+        set_lds(first_kernel<true, true>, g.first_lds);
     }
     ~Runner() {
         for (auto& e : evs) {
@@ -3539,7 +3798,7 @@ struct Runner {
         std::vector<uint32_t> valid;
         for (uint32_t v : list)
             if (v < cache->d.capacity) valid.push_back(v);
-        const uint32_t M = n - 1;
+        const uint32_t M = table_m(n);
         const size_t stride = (size_t)3 * M * M * M + (size_t)4 * 6 * M * M + 64;
         const uint32_t chunk = 512;
         double* work = (double*)dev_alloc(sizeof(double) * stride * std::min<size_t>(chunk, valid.size()));
@@ -3735,10 +3994,17 @@ struct Runner {
         F.dev_round = dev_round ? 1 : 0;
         if (round > 0 && !dev_round) MW_HIP(hipMemsetAsync(&ctr->first_missing, 0, 4, stream));
         const int fblocks = (int)std::min<uint64_t>((total + FRW_THREADS - 1) / FRW_THREADS, (uint64_t)g.first_blocks);
-        if (segs.size() == 1)
+        // odd n: the cell-centred lattice
+        if (n & 1) {
+            if (segs.size() == 1)
+                first_kernel<false, true><<<fblocks, FRW_THREADS, g.first_lds, stream>>>(F);
+            else
+                first_kernel<true, true><<<fblocks, FRW_THREADS, g.first_lds, stream>>>(F);
+        } else if (segs.size() == 1) {
             first_kernel<false><<<fblocks, FRW_THREADS, g.first_lds, stream>>>(F);
-        else
+        } else {
             first_kernel<true><<<fblocks, FRW_THREADS, g.first_lds, stream>>>(F);
+        }
         MW_HIP(hipGetLastError());
     }
 
@@ -3786,6 +4052,12 @@ struct Runner {
                 frw_walk_kernel<false, true, true><<<blocks_e, WALK_THREADS, g.lds_e, stream>>>(W);
             else
                 frw_walk_kernel<false, true><<<blocks_e, WALK_THREADS, g.lds_e, stream>>>(W);
+        } else if (n & 1) {
+            // the cell-centred lattice
+            if (multi)
+                frw_walk_kernel<true, false, false, true><<<blocks, WALK_THREADS, g.lds, stream>>>(W);
+            else
+                frw_walk_kernel<false, false, false, true><<<blocks, WALK_THREADS, g.lds, stream>>>(W);
         } else if (multi) {
             if (n <= 16)
                 frw_walk_kernel<true, false, true><<<blocks, WALK_THREADS, g.lds, stream>>>(W);
@@ -3806,7 +4078,7 @@ struct Runner {
     // tables, redo first transitions that missed one, resume the parked
     // walks.  A round with nothing to do costs a few empty launches.
     size_t dev_work_stride() const {
-        const uint32_t M = n - 1;
+        const uint32_t M = table_m(n);
         return (size_t)3 * M * M * M + (size_t)4 * 6 * M * M + 64;
     }
     void prepare_device_rounds() {
@@ -3910,8 +4182,8 @@ struct Runner {
 
 extern "C" mw_status mw_table_cache_clear(int32_t n_cells) {
     return guarded([&] {
-        MW_REQUIRE(n_cells >= 4 && n_cells <= 32 && n_cells % 2 == 0, MW_EINVAL,
-                   "table lattice size must be even, 4..32");
+        MW_REQUIRE(n_cells >= 3 && n_cells <= 32, MW_EINVAL,
+                   "table lattice size must be 4..32 (even, vertex lattice) or 3..31 (odd, cell lattice)");
         Cache& c = get_cache(n_cells);
         std::lock_guard<std::mutex> lock(c.mu);
         c.clear();
@@ -3921,18 +4193,26 @@ extern "C" mw_status mw_table_cache_clear(int32_t n_cells) {
 extern "C" mw_status mw_sgf_table(int32_t n_cells, int32_t kind, int32_t axis, int32_t normal_axis,
                                   const uint32_t* plane_codes, uint32_t* cdf, uint32_t* sign_bits, float* kh) {
     return guarded([&] {
-        MW_REQUIRE(n_cells >= 4 && n_cells <= 32 && n_cells % 2 == 0, MW_EINVAL,
-                   "table lattice size must be even, 4..32");
+        MW_REQUIRE(n_cells >= 3 && n_cells <= 32, MW_EINVAL,
+                   "table lattice size must be 4..32 (even, vertex lattice) or 3..31 (odd, cell lattice)");
         MW_REQUIRE(kind == 0 || kind == 1, MW_EINVAL, "kind must be 0 (hop) or 1 (first transition)");
+        const bool cell = (n_cells & 1) != 0;
         MW_REQUIRE(axis >= 0 && axis < 3, MW_EINVAL, "axis must be 0, 1 or 2");
         MW_REQUIRE(kind == 0 || (normal_axis >= 0 && normal_axis < 3), MW_EINVAL, "normal axis must be 0, 1 or 2");
         MW_REQUIRE(plane_codes && cdf, MW_EINVAL, "null plane codes or CDF buffer");
         const int n = n_cells;
-        for (int p = 0; p < n; ++p)
-            MW_REQUIRE(plane_codes[p] >= 66u && plane_codes[p] <= 65536000u, MW_EINVAL,
-                       "plane code outside rint(eps * 2^16) for eps in [1e-3, 1e3]");
+        for (int p = 0; p < n; ++p) {
+            if (cell) {
+                float e;
+                std::memcpy(&e, &plane_codes[p], 4);
+                MW_REQUIRE(e >= 1e-3f && e <= 1e3f, MW_EINVAL, "plane permittivity outside [1e-3, 1e3]");
+            } else {
+                MW_REQUIRE(plane_codes[p] >= 66u && plane_codes[p] <= 65536000u, MW_EINVAL,
+                           "plane code outside rint(eps * 2^16) for eps in [1e-3, 1e3]");
+            }
+        }
         std::vector<uint32_t> key(KEY_HDR + n);
-        key[0] = (uint32_t)kind;
+        key[0] = (uint32_t)kind + (cell ? 2u : 0u);
         key[1] = (uint32_t)n;
         key[2] = (uint32_t)axis;
         key[3] = kind == 1 ? (uint32_t)normal_axis : 0u;
@@ -3940,7 +4220,7 @@ extern "C" mw_status mw_sgf_table(int32_t n_cells, int32_t kind, int32_t axis, i
         Runner R(n, 1, 0, 1);
         std::vector<uint32_t> tab;
         R.fetch_table(key, tab);
-        const uint32_t nb = 6u * (n - 1) * (n - 1);
+        const uint32_t nb = 6u * table_m(n) * table_m(n);
         memcpy(cdf, tab.data() + TAB_CDF, 4ull * nb);
         if (sign_bits) memcpy(sign_bits, tab.data() + TAB_CDF + nb, 4ull * ((nb + 31) / 32));
         if (kh) memcpy(kh, tab.data() + 1, 4);
@@ -4549,9 +4829,18 @@ frw_options normalised_options(const frw_options* options) {
     opt.hybrid = 1;
     opt.abs_tol_rel = 1e-6;
     if (options) opt = *options;
-    if (opt.n_cells == 0) opt.n_cells = 16;
-    MW_REQUIRE(opt.n_cells >= 4 && opt.n_cells <= 32 && opt.n_cells % 2 == 0, MW_EINVAL,
-               "n_cells must be even in [4, 32]");
+    MW_REQUIRE(opt.lattice == MW_LATTICE_VERTEX || opt.lattice == MW_LATTICE_CELL, MW_EINVAL,
+               "unknown lattice %d", opt.lattice);
+    if (opt.n_cells == 0) opt.n_cells = opt.lattice == MW_LATTICE_CELL ? 15 : 16;
+    // the kernels tell the lattices apart by the parity of n
+    if (opt.lattice == MW_LATTICE_VERTEX)
+        MW_REQUIRE(opt.n_cells >= 4 && opt.n_cells <= 32 && opt.n_cells % 2 == 0, MW_EINVAL,
+                   "vertex lattice: n_cells must be even in [4, 32]");
+    else
+        MW_REQUIRE(opt.n_cells >= 3 && opt.n_cells <= 31 && opt.n_cells % 2 == 1, MW_EINVAL,
+                   "cell lattice: n_cells must be odd in [3, 31]");
+    MW_REQUIRE(opt.lattice == MW_LATTICE_VERTEX || opt.expand <= 1, MW_EINVAL,
+               "MicroWalk-E (expand > 1) runs on the vertex lattice only");
     if (opt.abs_tol_rel <= 0) opt.abs_tol_rel = 1e-6;
     MW_REQUIRE(opt.plain == 0 || opt.plain == 1, MW_EINVAL, "plain must be 0 or 1");
     MW_REQUIRE(opt.gauss_is == 0 || (opt.gauss_is >= 0.05 && opt.gauss_is <= 64), MW_EINVAL,

@@ -238,7 +238,7 @@ def test_cleared_table_cache_keeps_scores(mw):
     for r in (b, c):
         assert torch.equal(a["net"], r["net"]) and torch.equal(a["w"], r["w"])
     with pytest.raises(mw.MWError):
-        mw.mw_table_cache_clear(15)
+        mw.mw_table_cache_clear(33)
     h.close()
 
 
