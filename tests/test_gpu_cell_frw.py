@@ -11,7 +11,9 @@ MW_LATTICE_CELL) through the C ABI, against the CPU oracle.
 * Rows: closed forms on plates; C2 rows against the oracle's in combined
   standard errors (Bonferroni over the entries compared together).
 * The shared-round kernels (capacitance matrix, serving) on the cell lattice
-  give the single extraction's walks and rows.
+  give the single extraction's walks and rows; the plain form and split runs
+  give its walks bit for bit; importance sampling over G (patch weights from
+  the cell-lattice first kernel) matches the oracle walk by walk.
 """
 import os
 
@@ -184,3 +186,41 @@ def test_cell_lattice_options_are_checked(mw):
         with pytest.raises(mw.MWError) as e:
             mw.frw_extract(st, 0, 1000, **kw)
         assert e.value.status == mw.MW_EINVAL
+
+
+@pytest.mark.parametrize("name", ["highk", "c2"])
+def test_cell_gauss_importance_walks_match_oracle(mw, oracle_lib, name):
+    """Importance sampling over G on the cell lattice: the patch weights come
+    from the first-transition kernel evaluated by the cell-lattice first
+    kernel (fp32) and by the oracle (fp64); walks agree one by one except
+    where a draw falls within rounding of a patch boundary.  The first cube's
+    centre cell is centred on the evaluated point, so a patch centre lying
+    exactly on a dielectric face would put a cell centre on that face, where
+    the fp32 and fp64 half-open tests may differ (either cube is valid); the
+    patch edge 0.7 g keeps the centres off the faces of both structures (with
+    1.0 g the middle patch of the high-k plates sits on the column's face)."""
+    st = W.parallel_plates("columns_highk") if name == "highk" else W.c2_structure()
+    g = mw.frw_extract(st, 0, 20000, seed=78, scores=True, gauss_is=0.7, n_cells=15, lattice=mw.MW_LATTICE_CELL)
+    o = oracle_lib.frw_extract(st, 0, 20000, seed=78, threads=_threads(), scores=True, gauss_is=0.7,
+                               n_cells=15, lattice=1, kernel_limits=True)
+    same_net, same_walk = _agreement(g, o)
+    print(name, "cell lattice, importance sampling: same net", same_net, "same net and weight", same_walk)
+    assert same_walk >= 0.995
+
+
+def test_cell_plain_form_and_resume_are_bit_identical(mw):
+    """The plain form (one walker launch per transition round) and a run
+    split at walk 12345 give the persistent run's walks bit for bit."""
+    import torch
+    st = W.c2_structure()
+    h = mw.StructureHandle(st)
+    kw = dict(n_cells=15, lattice=mw.MW_LATTICE_CELL, scores=True)
+    a = mw.frw_extract(h, 0, 30000, seed=12, **kw)
+    p = mw.frw_extract(h, 0, 30000, seed=12, plain=1, **kw)
+    b1 = mw.frw_extract(h, 0, 12345, seed=12, **kw)
+    b2 = mw.frw_extract(h, 0, 30000 - 12345, seed=12, first_walk=12345, **kw)
+    assert p["stats"]["launches"] > a["stats"]["launches"]
+    assert torch.equal(a["net"], p["net"]) and torch.equal(a["w"], p["w"])
+    assert torch.equal(a["net"], torch.cat([b1["net"], b2["net"]]))
+    assert torch.equal(a["w"], torch.cat([b1["w"], b2["w"]]))
+    h.close()

@@ -588,3 +588,27 @@ def test_microwalk_e_options(mw):
     a = mw.frw_extract(st, 0, 20000, seed=3, scores=True)
     b = mw.frw_extract(st, 0, 20000, seed=3, scores=True, expand=1)
     assert torch.equal(a["net"], b["net"]) and torch.equal(a["w"], b["w"])
+
+
+@pytest.mark.parametrize("walks,n_cells,lattice", [(2, 16, 0), (63, 16, 0), (4097, 16, 0), (65537, 16, 0),
+                                                   (3001, 4, 0), (1500, 32, 0), (3001, 3, 1), (65537, 15, 1)])
+def test_ragged_budgets_and_extreme_cube_sizes(mw, oracle_lib, walks, n_cells, lattice):
+    """The smallest budget (2 walks), counts that end inside a wave, a
+    4096-walk reduction block and a 65536-walk summation group, and the
+    smallest and largest cubes of both lattices: walks equal the oracle's one
+    by one and the row is the mean of the scores."""
+    st = W.c2_structure()
+    g = mw.frw_extract(st, 0, walks, seed=61, scores=True, n_cells=n_cells, lattice=lattice)
+    o = oracle_lib.frw_extract(st, 0, walks, seed=61, threads=_threads(), scores=True, n_cells=n_cells,
+                               lattice=lattice, kernel_limits=True)
+    assert g["stats"]["walks"] == walks and len(g["net"]) == walks
+    same_net, same_walk = _walk_agreement(g, o["net"], o["w"])
+    print(walks, n_cells, lattice, "same net", same_net, "same net and weight", same_walk)
+    assert same_walk >= (0.995 if walks > 1000 else 1.0 - 1.0 / walks)
+    K = len(g["row"])
+    w = g["w"].double().cpu().numpy()
+    s = np.bincount(g["net"].cpu().numpy(), weights=w, minlength=K) / walks
+    assert np.allclose(s, g["row"], rtol=1e-5, atol=1e-7 * np.abs(g["row"]).max())
+    with pytest.raises(mw.MWError) as e:
+        mw.frw_extract(st, 0, 1, n_cells=n_cells, lattice=lattice)
+    assert e.value.status == mw.MW_EINVAL
