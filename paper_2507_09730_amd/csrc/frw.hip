@@ -1576,6 +1576,94 @@ __device__ __forceinline__ bool mw_block_cell(MwState& M, LaneCube L, int n, con
     return alive;
 }
 
+// n <= 15: the prepared masks (as for cell_code16, with the z rows' own
+// background bits) of the rows i-1, i, i+1 of each axis are kept in
+// registers, indices clamped into the cube, so that every cell read is one
+// LDS load and a move reloads one row.  The six Eq. (6) codes need a
+// binary64 division only at a cell whose neighbours differ from it.
+struct CellRows {
+    uint32_t x0, x1, x2, y0, y1, y2, z0, z1, z2;
+};
+
+__device__ __forceinline__ void mw_begin_cell16(MwState& M, CellRows& C, LaneCube L, int n) {
+    const int ns = n + 1, c = (n - 1) / 2;
+    M.ni = M.nj = M.nk = c;
+    M.s = 0;
+    C.x0 = prep_xy(L.mask[c - 1]);
+    C.x1 = prep_xy(L.mask[c]);
+    C.x2 = prep_xy(L.mask[c + 1]);
+    C.y0 = prep_xy(L.mask[ns + c - 1]);
+    C.y1 = prep_xy(L.mask[ns + c]);
+    C.y2 = prep_xy(L.mask[ns + c + 1]);
+    C.z0 = prep_z(L.mask[2 * ns + c - 1], c - 1);
+    C.z1 = prep_z(L.mask[2 * ns + c], c);
+    C.z2 = prep_z(L.mask[2 * ns + c + 1], c + 1);
+}
+
+__device__ __forceinline__ bool mw_block_cell16(MwState& M, CellRows& C, LaneCube L, int n, const Rand4& r) {
+    const int ns = n + 1;
+    const uint32_t us[4] = {r.x, r.y, r.z, r.w};
+    constexpr uint32_t PANEL = 1u << 24, HALF = 1u << 23;
+    bool alive = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (alive) {
+            const int i = M.ni, j = M.nj, k = M.nk;
+            const uint32_t ev = cell_code16(L, C.x1 & C.y1 & C.z1);
+            const uint32_t e0 = cell_code16(L, C.x0 & C.y1 & C.z1), e1 = cell_code16(L, C.x2 & C.y1 & C.z1);
+            const uint32_t e2 = cell_code16(L, C.x1 & C.y0 & C.z1), e3 = cell_code16(L, C.x1 & C.y2 & C.z1);
+            const uint32_t e4 = cell_code16(L, C.x1 & C.y1 & C.z0), e5 = cell_code16(L, C.x1 & C.y1 & C.z2);
+            uint32_t g0 = HALF, g1 = HALF, g2 = HALF, g3 = HALF, g4 = HALF, g5 = HALF;
+            if ((e0 != ev) | (e1 != ev) | (e2 != ev) | (e3 != ev) | (e4 != ev) | (e5 != ev)) {
+                g0 = eq6_code(e0, ev);
+                g1 = eq6_code(e1, ev);
+                g2 = eq6_code(e2, ev);
+                g3 = eq6_code(e3, ev);
+                g4 = eq6_code(e4, ev);
+                g5 = eq6_code(e5, ev);
+            }
+            // links out of the cube go to boundary panels (the clamped rows'
+            // reads above are then ignored)
+            g0 = i > 0 ? g0 : PANEL;
+            g1 = i < n - 1 ? g1 : PANEL;
+            g2 = j > 0 ? g2 : PANEL;
+            g3 = j < n - 1 ? g3 : PANEL;
+            g4 = k > 0 ? g4 : PANEL;
+            g5 = k < n - 1 ? g5 : PANEL;
+            const uint32_t S0 = g0, S1 = S0 + g1, S2 = S1 + g2, S3 = S2 + g3, S4 = S3 + g4, S5 = S4 + g5;
+            const uint32_t xq = __umulhi(us[q], S5);
+            const uint32_t d = (uint32_t)(xq >= S0) + (uint32_t)(xq >= S1) + (uint32_t)(xq >= S2) +
+                               (uint32_t)(xq >= S3) + (uint32_t)(xq >= S4);
+            const int ax = (int)(d >> 1);
+            const bool up = (d & 1u) != 0;
+            const int dir = up ? 1 : -1;
+            ++M.s;
+            M.ni += ax == 0 ? dir : 0;
+            M.nj += ax == 1 ? dir : 0;
+            M.nk += ax == 2 ? dir : 0;
+            const int cnew = ax == 0 ? M.ni : (ax == 1 ? M.nj : M.nk);
+            alive = cnew >= 0 && cnew < n;
+            // the row that enters the window along ax (clamped; a walk that
+            // left is not stepped again)
+            const int rr = min(max(cnew + dir, 0), n - 1);
+            const uint32_t raw = L.mask[ax * ns + rr];
+            const uint32_t v = ax == 2 ? prep_z(raw, rr) : prep_xy(raw);
+            // rows (r0, r1, r2) of the move's axis become (r1, r2, v) going
+            // up and (v, r0, r1) going down (selects: no branch on the axis)
+            auto shift = [&](bool on, uint32_t& r0, uint32_t& r1, uint32_t& r2) {
+                const uint32_t a0 = r0, a1 = r1, a2 = r2;
+                r0 = on ? (up ? a1 : v) : a0;
+                r1 = on ? (up ? a2 : a0) : a1;
+                r2 = on ? (up ? v : a1) : a2;
+            };
+            shift(ax == 0, C.x0, C.x1, C.x2);
+            shift(ax == 1, C.y0, C.y1, C.y2);
+            shift(ax == 2, C.z0, C.z1, C.z2);
+        }
+    }
+    return alive;
+}
+
 // MicroWalk-E steps: node masks of the current node and its two neighbours
 // per axis, kept in registers.
 struct MwStateE {
@@ -1907,14 +1995,15 @@ __device__ __forceinline__ decltype(auto) walk_struct(const WalkArgs& A, const G
 }
 
 // EXP: MicroWalk hops use expanded cubes (MicroWalk-E).
-// N16: ordinary MicroWalk reads cell codes as cell_code16 (n <= 16).
+// N16: ordinary MicroWalk reads cell codes as cell_code16 (n <= 16; on
+// the cell lattice n <= 15, with the row masks in registers).
 // CELL: every cube on the cell-centred lattice (n odd; plain MicroWalk).
 template <bool MULTI, bool EXP, bool N16 = false, bool CELL = false>
 // three resident waves per SIMD (at most 168 VGPRs) for the plain MicroWalk
 // kernels, whose LDS allows 11 waves per compute unit; two for MicroWalk-E
 __global__ void __launch_bounds__(WALK_THREADS) __attribute__((amdgpu_waves_per_eu(EXP ? 2 : 3)))
 frw_walk_kernel(WalkArgs A) {
-    static_assert(!(CELL && (EXP || N16)), "the cell lattice runs plain MicroWalk steps of its own");
+    static_assert(!(CELL && EXP), "the cell lattice runs plain MicroWalk steps of its own");
     extern __shared__ uint32_t lds[];
     const int n = A.n;
     const int ns = CELL ? n + 1 : n;  // mask row stride
@@ -1965,6 +2054,7 @@ frw_walk_kernel(WalkArgs A) {
     float mR = 0.f;
     MwState M{};
     MwStateE Q{};
+    CellRows CR{};  // CELL && N16 kernels only
     int env_net = 0;
 
     for (;;) {
@@ -2232,7 +2322,10 @@ frw_walk_kernel(WalkArgs A) {
                             mw_begin_e(M, Q, E, n);
                         } else if (CELL) {
                             c_halved += halved ? 1ull : 0ull;
-                            mw_begin_cell(M, n);
+                            if (N16)
+                                mw_begin_cell16(M, CR, L, n);
+                            else
+                                mw_begin_cell(M, n);
                         } else if (N16) {
                             c_halved += halved ? 1ull : 0ull;
                             mw_begin16(M, L, n);
@@ -2290,7 +2383,10 @@ frw_walk_kernel(WalkArgs A) {
                     const Rand4 r0 = philox10(b0, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), wk0, wk1);
                     const Rand4 r1 = philox10(b0 + 1, t, (uint32_t)walk, ctr_hi(walk, PURPOSE_MICROWALK), wk0, wk1);
                     bool in;
-                    if (CELL) {
+                    if (CELL && N16) {
+                        in = mw_block_cell16(M, CR, L, n, r0);
+                        if (in) in = mw_block_cell16(M, CR, L, n, r1);
+                    } else if (CELL) {
                         in = mw_block_cell(M, L, n, r0);
                         if (in) in = mw_block_cell(M, L, n, r1);
                     } else if (N16) {
@@ -3775,6 +3871,8 @@ struct Runner {
         set_lds(first_kernel<true>, g.first_lds);
         set_lds(frw_walk_kernel<false, false, false, true>, g.lds);
         set_lds(frw_walk_kernel<true, false, false, true>, g.lds);
+        set_lds(frw_walk_kernel<false, false, true, true>, g.lds);
+        set_lds(frw_walk_kernel<true, false, true, true>, g.lds);
         set_lds(first_kernel<false, true>, g.first_lds);
         set_lds(first_kernel<true, true>, g.first_lds);
     }
@@ -4053,9 +4151,13 @@ struct Runner {
             else
                 frw_walk_kernel<false, true><<<blocks_e, WALK_THREADS, g.lds_e, stream>>>(W);
         } else if (n & 1) {
-            // the cell-centred lattice
-            if (multi)
+            // the cell-centred lattice (register row masks up to 15 cells)
+            if (multi && n <= 15)
+                frw_walk_kernel<true, false, true, true><<<blocks, WALK_THREADS, g.lds, stream>>>(W);
+            else if (multi)
                 frw_walk_kernel<true, false, false, true><<<blocks, WALK_THREADS, g.lds, stream>>>(W);
+            else if (n <= 15)
+                frw_walk_kernel<false, false, true, true><<<blocks, WALK_THREADS, g.lds, stream>>>(W);
             else
                 frw_walk_kernel<false, false, false, true><<<blocks, WALK_THREADS, g.lds, stream>>>(W);
         } else if (multi) {

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from _stats import z_crit
 
 
 def _z(a, b, sa, sb):
@@ -78,8 +79,9 @@ def test_c2_hybrid_equals_all_microwalk(oracle_lib, c2_rows):
     r_mw = oracle_lib.frw_extract(st, 0, 60000, seed=99, threads=8, hybrid=0)
     r_hy = c2_rows[0]
     assert r_mw["stats"]["cls_stratified"] + r_mw["stats"]["cls_uniform"] > 0
-    for j in range(len(r_hy["row"])):
-        assert _z(r_hy["row"][j], r_mw["row"][j], r_hy["se"][j], r_mw["se"][j]) < 3.5
+    K = len(r_hy["row"])
+    for j in range(K):
+        assert _z(r_hy["row"][j], r_mw["row"][j], r_hy["se"][j], r_mw["se"][j]) < z_crit(K)
 
 
 def test_resume_is_bit_identical(oracle_lib):
