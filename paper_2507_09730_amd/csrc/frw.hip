@@ -18,6 +18,11 @@
 // while at least half of the working lanes do; the others take their next
 // hop meanwhile.
 //
+// Cubes of an odd lattice size n use the cell-centred lattice of Sec. III-A
+// (nodes at the voxel centres, Eq. (6) coefficients from the cells'
+// permittivities, exits at panel centres) with the same cube description;
+// even n use the vertex lattice described above.
+//
 // Stratified cubes (every region present in the cube spans whole planes
 // normal to one axis) are sampled from cached exact SGF tables of the same
 // lattice.  A missing table parks the walk in a queue; the table is built by
