@@ -108,8 +108,12 @@ def agreement(rows, ses, r_or):
     o_row, o_se = np.asarray(r_or["row"]), np.asarray(r_or["se"])
     both = (np.abs(g_row) > 4 * g_se) & (np.abs(o_row) > 4 * o_se)
     z = np.abs(g_row - o_row)[both] / np.hypot(g_se, o_se)[both]
+    # E|X| of a zero-mean normal is sqrt(2 / pi) sigma: the Err_avg that the
+    # two samples' standard errors alone would give
+    noise = float(np.sqrt(2 / np.pi) * np.hypot(g_se, o_se)[:-1].sum() / np.abs(o_row[:-1]).sum())
     return {"entries_compared": int(both.sum()), "max_z": float(z.max()) if z.size else None,
-            "mean_z2": float(np.mean(z ** 2)) if z.size else None, "err_avg": err_avg(g_row, o_row)}
+            "mean_z2": float(np.mean(z ** 2)) if z.size else None, "err_avg": err_avg(g_row, o_row),
+            "err_avg_noise": noise}
 
 
 def c1_single_cube(mw, W, reps=20):
