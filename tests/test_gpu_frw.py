@@ -612,3 +612,46 @@ def test_ragged_budgets_and_extreme_cube_sizes(mw, oracle_lib, walks, n_cells, l
     with pytest.raises(mw.MWError) as e:
         mw.frw_extract(st, 0, 1, n_cells=n_cells, lattice=lattice)
     assert e.value.status == mw.MW_EINVAL
+
+
+def test_concurrent_extractions_equal_sequential(mw):
+    """frw_extract from several host threads on one structure (the binding
+    releases the GIL during the call): masters, lattice sizes, both lattices,
+    a target and the plain form at once, twice over; every call returns the
+    walks and row of the same call made alone, bit for bit."""
+    import threading
+    import torch
+    st = W.c2_structure()
+    h = mw.StructureHandle(st)
+    jobs = [dict(master=0, seed=71), dict(master=1, seed=72), dict(master=0, seed=73, n_cells=12),
+            dict(master=2, seed=74, target_rel_3sigma=0.05), dict(master=0, seed=75, n_cells=15, lattice=1),
+            dict(master=3, seed=76, plain=1)]
+
+    def run(j):
+        j = dict(j)
+        m = j.pop("master")
+        return mw.frw_extract(h, m, 40000, scores=True, **j)
+
+    alone = [run(j) for j in jobs]
+    for rep in range(2):
+        out, errs = [None] * len(jobs), []
+
+        def worker(i):
+            try:
+                out[i] = run(jobs[i])
+            except Exception as e:  # reported below
+                errs.append(repr(e))
+
+        th = [threading.Thread(target=worker, args=(i,)) for i in range(len(jobs))]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join(timeout=120)
+        assert not errs, errs
+        assert all(t.is_alive() is False for t in th)
+        for a, b in zip(alone, out):
+            n = int(a["stats"]["walks"])
+            assert int(b["stats"]["walks"]) == n
+            assert torch.equal(a["net"][:n], b["net"][:n]) and torch.equal(a["w"][:n], b["w"][:n])
+            assert np.array_equal(a["row"], b["row"]) and np.array_equal(a["se"], b["se"])
+    h.close()
