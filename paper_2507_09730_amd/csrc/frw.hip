@@ -1020,8 +1020,15 @@ __device__ __forceinline__ int lookup_or_insert(const CacheDev& C, KeyF key, uin
     if (h == 0u) h = 1u;
     const unsigned long long hh = (unsigned long long)h << 32;
     uint32_t slot = (h * 0x9E3779B1u) & C.slot_mask;
+    // The slot and ready words are read at workgroup scope (through the
+    // compute unit's cache): a stale empty slot only sends the lane to the
+    // CAS, which returns the current word; a stale "being inserted" slot
+    // parks the walk, as the current word would (tables are built between
+    // launches); ready words do not change during a launch, and each launch
+    // starts with the compute units' caches invalidated.
     for (uint32_t probe = 0; probe <= C.slot_mask; ++probe) {
-        unsigned long long cur = __hip_atomic_load(gpw(C.slot) + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long cur =
+            __hip_atomic_load(gpw(C.slot) + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (cur == 0ull) {
             const unsigned long long old = atomicCAS(&C.slot[slot], 0ull, hh | NO_INDEX);
             if (old == 0ull) {
@@ -1047,7 +1054,8 @@ __device__ __forceinline__ int lookup_or_insert(const CacheDev& C, KeyF key, uin
             const uint32_t idx = (uint32_t)cur;
             if (idx == NO_INDEX) return LOOKUP_PARK;
             if (idx == FULL_INDEX) return LOOKUP_FULL;
-            const uint32_t rdy = __hip_atomic_load(gpw(C.ready) + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t rdy =
+                __hip_atomic_load(gpw(C.ready) + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             uint32_t g0 = 0, g1 = 0;
             if (glo) {
                 // the table's guide pair, read with the key (unused unless
