@@ -5150,12 +5150,13 @@ extern "C" mw_status frw_extract(mw_structure* st, int32_t master, uint64_t walk
         const uint64_t cap_mode = target_mode ? FRW_TARGET_LAUNCH_CAP : FRW_LAUNCH_CAP;
         const uint64_t launch_cap = std::min<uint64_t>(walk_budget, std::max<uint64_t>(ck, cap_mode / ck * ck));
         // first launch: the walks the last extraction of this structure,
-        // master and rule needed, plus 6 % (at least one checkpoint) for the
-        // spread between seeds (performance only)
+        // master and rule needed, plus one checkpoint (1/64 of them when that
+        // is more) for the spread between seeds; a shortfall costs one more
+        // launch, never a different result
         uint64_t next = launch_cap;
         if (target_mode) {
             const uint64_t hint = st->walk_hint(master, ck, opt.target_rel_3sigma);
-            next = hint ? (hint + std::max<uint64_t>(hint / 16, 1) + ck - 1) / ck * ck
+            next = hint ? (hint + std::max<uint64_t>(hint / 64, ck) + ck - 1) / ck * ck
                         : std::max<uint64_t>(ck, FRW_FIRST_LAUNCH / ck * ck);
         }
         const bool own_scores = !(score_net && score_w);
