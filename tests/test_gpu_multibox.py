@@ -100,3 +100,18 @@ def test_multibox_microwalk_e_runs(mw):
     print("mw-e multibox", row, se, r["stats"]["hops"] / r["stats"]["walks"])
     assert row[0] > 0 and (row[1:] <= 0).all()
     assert abs(row.sum()) < 4 * np.sqrt((se ** 2).sum()) + 0.02 * row[0]
+
+
+def test_c2_multibox_cell_lattice_matches_oracle(mw, oracle_lib):
+    """A multi-box master on the cell-centred lattice (15-cell cubes):
+    Gaussian surface of the union, first transitions and walks on that
+    lattice, rows against the oracle's."""
+    st = W.c2_multibox_structure(False)
+    r_gpu = mw.frw_extract(st, 0, 1000000, seed=33, n_cells=15, lattice=mw.MW_LATTICE_CELL)
+    r_or = oracle_lib.frw_extract(st, 0, 30000, seed=34, threads=_threads(), n_cells=15, lattice=1)
+    K = len(r_gpu["row"])
+    zs = np.array([_z(r_gpu["row"][j], r_or["row"][j], r_gpu["se"][j], r_or["se"][j])
+                   if (r_gpu["se"][j] > 0 or r_or["se"][j] > 0) else 0.0 for j in range(K)])
+    print("cell lattice gpu", r_gpu["row"], r_gpu["se"], "oracle", r_or["row"], r_or["se"], "z", zs)
+    assert zs.max() < z_crit(K)
+    assert r_gpu["row"][0] > 0 and (r_gpu["row"][1:] <= 0).all()
