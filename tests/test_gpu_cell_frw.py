@@ -100,22 +100,38 @@ def _agreement(g, o):
     return float(same.mean()), float((same & (rel <= W_REL)).mean())
 
 
-@pytest.mark.parametrize("name,hybrid,n_cells", [("plates", 1, 15), ("checker", 1, 15), ("c2", 1, 15),
-                                                 ("c2", 0, 15), ("c2", 1, 7), ("c2", 1, 31)])
-def test_cell_walks_match_oracle_one_by_one(mw, oracle_lib, name, hybrid, n_cells):
+@pytest.mark.parametrize("name,hybrid,n_cells,floor", [
+    ("plates", 1, 15, 0.999), ("checker", 1, 15, 0.999), ("stack", 1, 15, 0.999), ("c2", 1, 15, 0.999),
+    ("c2", 0, 15, 0.999), ("c2", 1, 7, 0.999), ("c2", 1, 31, 0.999), ("c4", 1, 15, 0.99)])
+def test_cell_walks_match_oracle_one_by_one(mw, oracle_lib, name, hybrid, n_cells, floor):
+    """The twelve-layer stack reads its background layers from global memory
+    (more layers than the LDS copy holds).  Its layer faces are shifted by
+    12.3 nm here: in the plain stack the Gaussian surface and some cell
+    centres of every first cube lie exactly on layer faces, where the fp32
+    and binary64 half-open tests may choose different layers (either cube is
+    valid; walk-by-walk comparisons need points off the faces).  The large
+    interconnect window has cubes that the kernel's capacity rule halves,
+    which the oracle follows here (kernel_limits)."""
+    def stack():
+        st = W.parallel_plates("stack")
+        st.layer_z0[1:] += np.float32(0.0123)
+        return st
+
     st = {"plates": lambda: W.parallel_plates("columns"), "checker": lambda: W.parallel_plates("checkerboard"),
-          "c2": W.c2_structure}[name]()
-    N = 20000 if n_cells <= 15 else 4000
-    g = mw.frw_extract(st, 0, N, seed=31, scores=True, hybrid=hybrid, n_cells=n_cells,
+          "stack": stack, "c2": W.c2_structure, "c4": W.c4_structure}[name]()
+    m = st.meta["master"] if name == "c4" else 0
+    N = 3000 if name == "c4" else (20000 if n_cells <= 15 else 4000)
+    g = mw.frw_extract(st, m, N, seed=31, scores=True, hybrid=hybrid, n_cells=n_cells,
                        lattice=mw.MW_LATTICE_CELL)
-    o = oracle_lib.frw_extract(st, 0, N, seed=31, threads=_threads(), scores=True, hybrid=hybrid,
+    o = oracle_lib.frw_extract(st, m, N, seed=31, threads=_threads(), scores=True, hybrid=hybrid,
                                n_cells=n_cells, lattice=1, kernel_limits=True)
     same_net, same_walk = _agreement(g, o)
     print(name, hybrid, n_cells, "same net", same_net, "same net and weight", same_walk, g["stats"])
-    assert g["stats"]["cube_halved"] == 0
+    if name != "c4":
+        assert g["stats"]["cube_halved"] == 0
     if hybrid == 0:
         assert g["stats"]["micro_steps"] > 0
-    assert same_walk >= 0.999
+    assert same_walk >= floor
 
 
 @pytest.mark.parametrize("variant", ["uniform", "columns", "checkerboard"])
