@@ -2637,7 +2637,9 @@ __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const
             for (int e = tid; e < M2; e += NT) {
                 const int m = e / M, qq = e % M;
                 double acc = 0.0;
-                #pragma unroll 1
+                // unrolled so that the global loads of Z issue together (the
+                // sum keeps its order)
+                #pragma unroll 8
                 for (int l = 0; l < M; ++l) acc += Zr[m * M + l] * Sm[l * M + qq];
                 tmp[e] = acc;
             }
@@ -2669,10 +2671,10 @@ __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const
                 const double* Zr = Z + (size_t)r * M2;
                 double acc = 0.0;
                 if (ufaces)
-                    #pragma unroll 1
+                    #pragma unroll 8
                     for (int m = 0; m < M; ++m) acc += Sm[m * M + fixed] * Zr[m * M + j];
                 else
-                    #pragma unroll 1
+                    #pragma unroll 8
                     for (int l = 0; l < M; ++l) acc += Sm[l * M + fixed] * Zr[j * M + l];
                 tmp[e] = acc;
             }
@@ -2794,18 +2796,21 @@ __device__ void build_table_body(const CacheDev& C, uint32_t idx, int tid, const
         tab[1] = first ? __float_as_uint((float)tot) : 0u;
     }
     sync();
-    // guide[g] = first b with CDF[b] > g * 2^GUIDE_SHIFT (CDF nondecreasing)
-    for (int g = tid; g <= (1 << GUIDE_BITS); g += NT) {
-        const unsigned long long thr = (unsigned long long)g << GUIDE_SHIFT;
-        uint32_t lo = 0, hi = (uint32_t)nb;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if ((unsigned long long)tab[TAB_CDF + mid] <= thr)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        tab[TAB_GUIDE + g] = lo;
+    // guide[g] = first b with CDF[b] > g * 2^GUIDE_SHIFT (CDF nondecreasing):
+    // entry b is the answer exactly for CDF[b-1] <= g 2^GUIDE_SHIFT < CDF[b]
+    // (CDF[-1] = 0), and nb for g 2^GUIDE_SHIFT >= CDF[nb-1]; each entry
+    // writes its own range of g (two loads per entry instead of a bisection
+    // per g)
+    const unsigned long long gstep = 1ull << GUIDE_SHIFT;
+    for (int b = tid; b < nb; b += NT) {
+        const unsigned long long lo = b ? tab[TAB_CDF + b - 1] : 0ull, hi = tab[TAB_CDF + b];
+        const int g0 = (int)((lo + gstep - 1) >> GUIDE_SHIFT), g1 = (int)((hi + gstep - 1) >> GUIDE_SHIFT);
+        for (int g = g0; g < g1; ++g) tab[TAB_GUIDE + g] = (uint32_t)b;
+    }
+    {
+        const unsigned long long last = tab[TAB_CDF + nb - 1];
+        for (int g = (int)((last + gstep - 1) >> GUIDE_SHIFT) + tid; g <= (1 << GUIDE_BITS); g += NT)
+            tab[TAB_GUIDE + g] = (uint32_t)nb;
     }
     sync();
     if (tid == 0) {
