@@ -7,6 +7,10 @@
 // table with the GPU library; it is built from this file alone with
 // `g++ -O2 -ffp-contract=off -shared -fPIC`.
 //
+// Both node placements are implemented for FRW: the vertex lattice (nodes at
+// cell corners, the default) and the cell-centred lattice of Sec. III-A
+// (nodes at voxel centres, Eq. (6) coefficients, lattice = 1).
+//
 // Arithmetic is binary64 except where the method is specified in integers
 // (cell and link codes, thresholds, Philox words).  Each function names the
 // passage of the paper it follows; readings of points the paper leaves open
