@@ -433,6 +433,32 @@ def test_c4_matches_oracle(mw, oracle_lib):
 
 
 
+def test_c4_headline_sampled_walks_match_oracle(mw, oracle_lib):
+    """The headline configuration as the bench times it (the large window
+    walked to 3 SE / |C_mm| <= 1 %, one launch of several checkpoints
+    replayed from a HIP graph after warm-up calls): five runs of 200 walks
+    spread over the kept walks, recomputed by the oracle from their walk
+    indices, equal the GPU's walks one by one; the stopping checkpoint
+    meets the target."""
+    st = W.c4_structure()
+    m = st.meta["master"]
+    h = mw.StructureHandle(st)
+    for k in range(2):
+        mw.frw_extract(h, m, 100000000, seed=60 + k, target_rel_3sigma=0.01)
+    g = mw.frw_extract(h, m, 100000000, seed=7, target_rel_3sigma=0.01, scores=True)
+    n = int(g["stats"]["walks"])
+    assert n % 65536 == 0 and 3 * g["se"][m] / g["row"][m] <= 0.01
+    agree = []
+    for f in np.linspace(0, n - 200, 5).astype(np.int64):
+        o = oracle_lib.frw_extract(st, m, 200, seed=7, first_walk=int(f), threads=_threads(), scores=True,
+                                   kernel_limits=True)
+        part = {"net": g["net"][f:f + 200], "w": g["w"][f:f + 200]}
+        agree.append(_walk_agreement(part, o["net"], o["w"])[1])
+    print("walks", n, "per-run agreement", agree)
+    assert min(agree) >= 0.98 and np.mean(agree) >= 0.99
+    h.close()
+
+
 def test_matrix_rows_equal_single_extractions(mw):
     """frw_extract_matrix: every row equals frw_extract of that master with
     key seed + i (same walks, fp32 summation order aside); the matrix obeys
