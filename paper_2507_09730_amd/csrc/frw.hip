@@ -1533,60 +1533,10 @@ __device__ __forceinline__ bool mw_block(MwState& M, LaneCube L, int n, const Ra
 // permittivities), and 2^24 towards a boundary panel; the walk leaves the
 // cube at the centre of that panel.
 // -------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t cell_eps_at(LaneCube L, int ns, int i, int j, int k) {
-    return cell_code(L, (uint32_t)L.mask[i] & L.mask[ns + j] & L.mask[2 * ns + k], L.bz[k]);
-}
-
 __device__ __forceinline__ uint32_t eq6_code(uint32_t nb, uint32_t v) {
     if (nb == v) return 1u << 23;
     const double e = (double)__uint_as_float(nb), ev = (double)__uint_as_float(v);
     return (uint32_t)rint(e / (e + ev) * 16777216.0);
-}
-
-__device__ __forceinline__ void mw_begin_cell(MwState& M, int n) {
-    M.ni = M.nj = M.nk = (n - 1) / 2;
-    M.s = 0;
-}
-
-// Up to four steps with the four words of one Philox block; false once the
-// walk has left the cube (one coordinate is then -1 or n).
-__device__ __forceinline__ bool mw_block_cell(MwState& M, LaneCube L, int n, const Rand4& r) {
-    const int ns = n + 1;
-    const uint32_t us[4] = {r.x, r.y, r.z, r.w};
-    constexpr uint32_t PANEL = 1u << 24;
-    bool alive = true;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        if (alive) {
-            const int i = M.ni, j = M.nj, k = M.nk;
-            // neighbour indices clamped into the cube: a link out of it goes
-            // to a boundary panel whatever the read returns
-            const int im = max(i - 1, 0), ip = min(i + 1, n - 1);
-            const int jm = max(j - 1, 0), jp = min(j + 1, n - 1);
-            const int km = max(k - 1, 0), kp = min(k + 1, n - 1);
-            const uint32_t ev = cell_eps_at(L, ns, i, j, k);
-            const uint32_t g0 = i > 0 ? eq6_code(cell_eps_at(L, ns, im, j, k), ev) : PANEL;
-            const uint32_t g1 = i < n - 1 ? eq6_code(cell_eps_at(L, ns, ip, j, k), ev) : PANEL;
-            const uint32_t g2 = j > 0 ? eq6_code(cell_eps_at(L, ns, i, jm, k), ev) : PANEL;
-            const uint32_t g3 = j < n - 1 ? eq6_code(cell_eps_at(L, ns, i, jp, k), ev) : PANEL;
-            const uint32_t g4 = k > 0 ? eq6_code(cell_eps_at(L, ns, i, j, km), ev) : PANEL;
-            const uint32_t g5 = k < n - 1 ? eq6_code(cell_eps_at(L, ns, i, j, kp), ev) : PANEL;
-            // prefix sums (at most 6 * 2^24) and the move #{k < 5 : xq >= S_k}
-            const uint32_t S0 = g0, S1 = S0 + g1, S2 = S1 + g2, S3 = S2 + g3, S4 = S3 + g4, S5 = S4 + g5;
-            const uint32_t xq = __umulhi(us[q], S5);
-            const uint32_t d = (uint32_t)(xq >= S0) + (uint32_t)(xq >= S1) + (uint32_t)(xq >= S2) +
-                               (uint32_t)(xq >= S3) + (uint32_t)(xq >= S4);
-            const int ax = (int)(d >> 1);
-            const int dir = (d & 1u) ? 1 : -1;
-            ++M.s;
-            M.ni += ax == 0 ? dir : 0;
-            M.nj += ax == 1 ? dir : 0;
-            M.nk += ax == 2 ? dir : 0;
-            const int cnew = ax == 0 ? M.ni : (ax == 1 ? M.nj : M.nk);
-            alive = cnew >= 0 && cnew < n;
-        }
-    }
-    return alive;
 }
 
 // n <= 15: the prepared masks (as for cell_code16, with the z rows' own
@@ -1596,6 +1546,7 @@ __device__ __forceinline__ bool mw_block_cell(MwState& M, LaneCube L, int n, con
 // binary64 division only at a cell whose neighbours differ from it.
 struct CellRows {
     uint32_t x0, x1, x2, y0, y1, y2, z0, z1, z2;
+    uint32_t b0, b1, b2;  // n > 15: background codes of z rows k-1, k, k+1
 };
 
 __device__ __forceinline__ void mw_begin_cell16(MwState& M, CellRows& C, LaneCube L, int n) {
@@ -1672,6 +1623,86 @@ __device__ __forceinline__ bool mw_block_cell16(MwState& M, CellRows& C, LaneCub
             shift(ax == 0, C.x0, C.x1, C.x2);
             shift(ax == 1, C.y0, C.y1, C.y2);
             shift(ax == 2, C.z0, C.z1, C.z2);
+        }
+    }
+    return alive;
+}
+
+// n > 15 (up to 31): the same steps with the rows' plain masks and the z
+// rows' background codes in registers; a cell read is one LDS load of the
+// top box's code and a select of the background code.
+__device__ __forceinline__ void mw_begin_cell(MwState& M, CellRows& C, LaneCube L, int n) {
+    const int ns = n + 1, c = (n - 1) / 2;
+    M.ni = M.nj = M.nk = c;
+    M.s = 0;
+    C.x0 = L.mask[c - 1];
+    C.x1 = L.mask[c];
+    C.x2 = L.mask[c + 1];
+    C.y0 = L.mask[ns + c - 1];
+    C.y1 = L.mask[ns + c];
+    C.y2 = L.mask[ns + c + 1];
+    C.z0 = L.mask[2 * ns + c - 1];
+    C.z1 = L.mask[2 * ns + c];
+    C.z2 = L.mask[2 * ns + c + 1];
+    C.b0 = L.bz[c - 1];
+    C.b1 = L.bz[c];
+    C.b2 = L.bz[c + 1];
+}
+
+__device__ __forceinline__ bool mw_block_cell(MwState& M, CellRows& C, LaneCube L, int n, const Rand4& r) {
+    const int ns = n + 1;
+    const uint32_t us[4] = {r.x, r.y, r.z, r.w};
+    constexpr uint32_t PANEL = 1u << 24, HALF = 1u << 23;
+    bool alive = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (alive) {
+            const int i = M.ni, j = M.nj, k = M.nk;
+            const uint32_t ev = cell_code(L, C.x1 & C.y1 & C.z1, C.b1);
+            const uint32_t e0 = cell_code(L, C.x0 & C.y1 & C.z1, C.b1), e1 = cell_code(L, C.x2 & C.y1 & C.z1, C.b1);
+            const uint32_t e2 = cell_code(L, C.x1 & C.y0 & C.z1, C.b1), e3 = cell_code(L, C.x1 & C.y2 & C.z1, C.b1);
+            const uint32_t e4 = cell_code(L, C.x1 & C.y1 & C.z0, C.b0), e5 = cell_code(L, C.x1 & C.y1 & C.z2, C.b2);
+            uint32_t g0 = HALF, g1 = HALF, g2 = HALF, g3 = HALF, g4 = HALF, g5 = HALF;
+            if ((e0 != ev) | (e1 != ev) | (e2 != ev) | (e3 != ev) | (e4 != ev) | (e5 != ev)) {
+                g0 = eq6_code(e0, ev);
+                g1 = eq6_code(e1, ev);
+                g2 = eq6_code(e2, ev);
+                g3 = eq6_code(e3, ev);
+                g4 = eq6_code(e4, ev);
+                g5 = eq6_code(e5, ev);
+            }
+            g0 = i > 0 ? g0 : PANEL;
+            g1 = i < n - 1 ? g1 : PANEL;
+            g2 = j > 0 ? g2 : PANEL;
+            g3 = j < n - 1 ? g3 : PANEL;
+            g4 = k > 0 ? g4 : PANEL;
+            g5 = k < n - 1 ? g5 : PANEL;
+            const uint32_t S0 = g0, S1 = S0 + g1, S2 = S1 + g2, S3 = S2 + g3, S4 = S3 + g4, S5 = S4 + g5;
+            const uint32_t xq = __umulhi(us[q], S5);
+            const uint32_t d = (uint32_t)(xq >= S0) + (uint32_t)(xq >= S1) + (uint32_t)(xq >= S2) +
+                               (uint32_t)(xq >= S3) + (uint32_t)(xq >= S4);
+            const int ax = (int)(d >> 1);
+            const bool up = (d & 1u) != 0;
+            const int dir = up ? 1 : -1;
+            ++M.s;
+            M.ni += ax == 0 ? dir : 0;
+            M.nj += ax == 1 ? dir : 0;
+            M.nk += ax == 2 ? dir : 0;
+            const int cnew = ax == 0 ? M.ni : (ax == 1 ? M.nj : M.nk);
+            alive = cnew >= 0 && cnew < n;
+            const int rr = min(max(cnew + dir, 0), n - 1);
+            const uint32_t v = L.mask[ax * ns + rr];
+            const uint32_t vb = L.bz[rr];  // used for z moves only
+            auto shift = [&](bool on, uint32_t& r0, uint32_t& r1, uint32_t& r2, uint32_t nv) {
+                const uint32_t a0 = r0, a1 = r1, a2 = r2;
+                r0 = on ? (up ? a1 : nv) : a0;
+                r1 = on ? (up ? a2 : a0) : a1;
+                r2 = on ? (up ? nv : a1) : a2;
+            };
+            shift(ax == 0, C.x0, C.x1, C.x2, v);
+            shift(ax == 1, C.y0, C.y1, C.y2, v);
+            shift(ax == 2, C.z0, C.z1, C.z2, v);
+            shift(ax == 2, C.b0, C.b1, C.b2, vb);
         }
     }
     return alive;
@@ -2067,7 +2098,7 @@ frw_walk_kernel(WalkArgs A) {
     float mR = 0.f;
     MwState M{};
     MwStateE Q{};
-    CellRows CR{};  // CELL && N16 kernels only
+    CellRows CR{};  // CELL kernels only
     int env_net = 0;
 
     for (;;) {
@@ -2338,7 +2369,7 @@ frw_walk_kernel(WalkArgs A) {
                             if (N16)
                                 mw_begin_cell16(M, CR, L, n);
                             else
-                                mw_begin_cell(M, n);
+                                mw_begin_cell(M, CR, L, n);
                         } else if (N16) {
                             c_halved += halved ? 1ull : 0ull;
                             mw_begin16(M, L, n);
@@ -2400,8 +2431,8 @@ frw_walk_kernel(WalkArgs A) {
                         in = mw_block_cell16(M, CR, L, n, r0);
                         if (in) in = mw_block_cell16(M, CR, L, n, r1);
                     } else if (CELL) {
-                        in = mw_block_cell(M, L, n, r0);
-                        if (in) in = mw_block_cell(M, L, n, r1);
+                        in = mw_block_cell(M, CR, L, n, r0);
+                        if (in) in = mw_block_cell(M, CR, L, n, r1);
                     } else if (N16) {
                         in = mw_block16(M, L, n, r0);
                         if (in) in = mw_block16(M, L, n, r1);
