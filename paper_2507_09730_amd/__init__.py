@@ -377,12 +377,12 @@ def frw_extract(structure, master, walk_budget, seed=0, n_cells=16, hybrid=1,
 
 
 
-def frw_autotune(structure, master, walks, seed=0, n_cells=16, hybrid=1, expand=0):
+def frw_autotune(structure, master, walks, seed=0, n_cells=16, hybrid=1, expand=0, lattice=MW_LATTICE_VERTEX):
     """Tunes the FRW walker's resident waves per CU on this extraction and
     keeps the choice (returned) for later calls with the same lattice."""
     if not isinstance(structure, StructureHandle):
         structure = StructureHandle(structure)
-    opt = frw_options(n_cells, hybrid, expand, 0, 0.0, 1e-6, 0, 0, 0.0)
+    opt = frw_options(n_cells, hybrid, expand, 0, 0.0, 1e-6, 0, 0, 0.0, lattice)
     w = ctypes.c_int32(0)
     _check(_lib.frw_autotune(structure.handle, I32(master), U64(walks), U64(seed), ctypes.byref(opt),
                              ctypes.byref(w)))

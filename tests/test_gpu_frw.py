@@ -307,24 +307,27 @@ def test_full_table_cache_keeps_results(mw, oracle_lib, monkeypatch):
     assert same_walk >= 0.999
 
 
-def test_frw_autotune_keeps_results(mw, monkeypatch, tmp_path):
+@pytest.mark.parametrize("n_cells,lattice", [(14, 0), (13, 1)])
+def test_frw_autotune_keeps_results(mw, monkeypatch, tmp_path, n_cells, lattice):
     """The walker's launch geometry (resident waves per CU) is tuned on a
-    14-cell lattice (no other test uses it), kept in the tune cache file and
-    used by later extractions, whose walks stay bit-identical."""
+    lattice size no other test uses (14 cells, and 13 cells of the cell
+    lattice), kept in the tune cache file and used by later extractions,
+    whose walks stay bit-identical."""
     import json
     import torch
     cache = tmp_path / "tune.json"
     monkeypatch.setenv("MWALK_TUNE_CACHE", str(cache))
     st = W.c2_structure()
     h = mw.StructureHandle(st)
-    a = mw.frw_extract(h, 0, 30000, seed=4, n_cells=14, scores=True)
-    w = mw.frw_autotune(h, 0, 300000, n_cells=14)
-    b = mw.frw_extract(h, 0, 30000, seed=4, n_cells=14, scores=True)
+    kw = dict(n_cells=n_cells, lattice=lattice)
+    a = mw.frw_extract(h, 0, 30000, seed=4, scores=True, **kw)
+    w = mw.frw_autotune(h, 0, 300000, **kw)
+    b = mw.frw_extract(h, 0, 30000, seed=4, scores=True, **kw)
     print("tuned waves per CU", w)
     assert 4 <= w <= 16
     assert torch.equal(a["net"], b["net"]) and torch.equal(a["w"], b["w"])
     entries = next(iter(json.load(open(cache)).values()))
-    assert any(e["key"] == [-1, 14, 0] and e["tune"][1] == w for e in entries)
+    assert any(e["key"] == [-1, n_cells, 0] and e["tune"][1] == w for e in entries)
 
 
 def test_convergence_target(mw):
